@@ -1,0 +1,446 @@
+"""FP64 CPU oracle for the FMM-ForceAtlas2 / Kamada-Kawai layout method.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the HIP library (``paper_2403_03504_amd``) and does not import it.
+
+The heavy loops live in ``fa2_oracle.c`` (plain C, FP64, OpenMP over target
+nodes); this module holds the parts that are a few lines of NumPy.  Section
+references are to "Graph Visualization for Blockchain Data" (Dietl et al.).
+
+Readings taken where the paper is silent (each is a parameter):
+
+* repulsion is degree-weighted as in ForceAtlas2: ``kr (deg_i+1)(deg_j+1)/d``;
+  the mass of a node is ``deg + 1`` with ``deg`` = distinct neighbours;
+* attraction is linear and unweighted (sec. 3.2: proportional to distance);
+* gravity is "strong" and mass-weighted about the origin by default
+  (sec. 3.2: proportional to the distance to the centre);
+* swing and traction are the unweighted sums the paper prints (sec. 3.2);
+  the ForceAtlas2 variant (mass-weighted, traction halved) is ``swing_mode=1``;
+* the step size follows ForceAtlas2 (Jacomy et al. 2014), which the paper
+  defers to: ``s_G = tau * tra / swg`` capped to rise at most ``max_rise`` per
+  iteration, ``s_i = ks s_G / (1 + s_G sqrt(swg_i))`` capped at ``ksmax/|F_i|``.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fa2_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GRAV_STRONG_MASS, GRAV_FA2_CONST, GRAV_STRONG_UNIT = 0, 1, 2
+SWING_PAPER, SWING_FA2 = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part with gcc (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+                        "-ffp-contract=off", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.orc_repulsion_exact.argtypes = [i64, P, P, P, f64, i64, P, P, P]
+        L.orc_components.argtypes = [i64, P, P, P]
+        L.orc_components.restype = i64
+        L.orc_bfs_hops.argtypes = [i32, P, P, P]
+        L.orc_root.argtypes = [i64, P, P, ctypes.c_int, P]
+        L.orc_morton.argtypes = [i64, P, P, ctypes.c_int, P]
+        L.orc_sort_by_key.argtypes = [i64, P, P]
+        L.orc_tree.argtypes = [i64, P, ctypes.c_int, ctypes.c_int, i64, P]
+        L.orc_tree.restype = i64
+        L.orc_fmm_repulsion.argtypes = [i64, P, P, P, f64, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+        L.orc_fmm_repulsion.restype = ctypes.c_int
+        L.orc_fmm_lists.argtypes = [i64, P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P]
+        L.orc_fmm_lists.restype = i64
+        L.orc_kk_energy.argtypes = [i32, P, f64, P, P]
+        L.orc_kk_energy.restype = f64
+        L.orc_kk_steps.argtypes = [i32, P, f64, i32, P, P]
+        L.orc_num_threads.restype = ctypes.c_int
+        for nm in ("orc_op_m2m", "orc_op_m2l", "orc_op_l2l"):
+            getattr(L, nm).argtypes = [P, P, f64, f64, ctypes.c_int, P, P]
+        L.orc_op_p2m.argtypes = [i64, P, P, P, f64, f64, ctypes.c_int, P, P]
+        L.orc_op_l2p.argtypes = [P, P, f64, f64, ctypes.c_int, P]
+        L.orc_op_m2p.argtypes = [P, P, f64, f64, ctypes.c_int, P]
+        L.orc_op_p2l.argtypes = [f64, f64, f64, ctypes.c_int, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --- graph preparation (sec. 2 and sec. 4) -----------------------------------
+
+def build_csr(n: int, src, dst):
+    """Simple undirected graph in CSR: directions ignored, duplicate pairs and
+    self loops dropped, each row sorted ascending (sec. 4: components are
+    taken ignoring edge directions; an address may be both input and output of
+    one transaction, which is one adjacency).  Returns (row_ptr int64,
+    col int32, deg int32)."""
+    s = np.asarray(src, dtype=np.int64)
+    d = np.asarray(dst, dtype=np.int64)
+    if s.size and (s.min() < 0 or d.min() < 0 or s.max() >= n or d.max() >= n):
+        raise ValueError("edge endpoint out of range")
+    u = np.concatenate([s, d])
+    v = np.concatenate([d, s])
+    keep = u != v
+    pairs = np.unique(u[keep] * n + v[keep])
+    rows = pairs // n
+    cols = (pairs % n).astype(np.int32)
+    deg = np.bincount(rows, minlength=n).astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    return row_ptr, cols, deg
+
+
+def components(row_ptr, col):
+    """label[v] = smallest node id in v's component (sec. 4)."""
+    n = row_ptr.shape[0] - 1
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    lab = np.empty(n, dtype=np.int32)
+    k = lib().orc_components(n, _p(rp), _p(c), _p(lab))
+    return lab, int(k)
+
+
+# --- forces (sec. 3.2) --------------------------------------------------------
+
+def masses(deg) -> np.ndarray:
+    return np.asarray(deg, dtype=np.float64) + 1.0
+
+
+def repulsion_exact(x, y, m, kr: float = 1.0, targets=None):
+    """Exact pairwise repulsion kr m_i m_j (p_i - p_j)/|p_i - p_j|^2 (O(n^2))."""
+    x, y, m = _f64(x), _f64(y), _f64(m)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        nt, tp = t.shape[0], _p(t)
+    fx = np.empty(nt)
+    fy = np.empty(nt)
+    lib().orc_repulsion_exact(n, _p(x), _p(y), _p(m), float(kr), nt, tp, _p(fx), _p(fy))
+    return fx, fy
+
+
+def repulsion_fmm(x, y, m, kr: float = 1.0, p: int = 8, leaf_size: int = 64, bits: int = 16,
+                  with_stats: bool = False):
+    """The paper's FMM repulsion (sec. 3.2.1) in FP64."""
+    x, y, m = _f64(x), _f64(y), _f64(m)
+    n = x.shape[0]
+    fx = np.empty(n)
+    fy = np.empty(n)
+    st = np.zeros(12, dtype=np.int64)
+    rc = lib().orc_fmm_repulsion(n, _p(x), _p(y), _p(m), float(kr), int(p), int(leaf_size), int(bits),
+                                 _p(fx), _p(fy), _p(st))
+    if rc != 0:
+        raise ValueError("invalid FMM parameters")
+    if with_stats:
+        keys = ("cells", "leaves", "max_level", "near_pairs", "v_entries", "w_entries", "x_entries",
+                "coverage_min", "coverage_max", "u_entries", "w_entries2", "x_entries2")
+        return fx, fy, dict(zip(keys, (int(v) for v in st)))
+    return fx, fy
+
+
+def attraction(row_ptr, col, x, y, ka: float = 1.0):
+    """Linear attraction along every edge: F_a,i = ka sum_{j in N(i)} (p_j - p_i)."""
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    deg = np.diff(np.asarray(row_ptr, dtype=np.int64))
+    rows = np.repeat(np.arange(n), deg)
+    col = np.asarray(col, dtype=np.int64)
+    fx = np.bincount(rows, weights=x[col] - x[rows], minlength=n)
+    fy = np.bincount(rows, weights=y[col] - y[rows], minlength=n)
+    return ka * fx, ka * fy
+
+
+def gravity(x, y, m, kg: float = 1.0, mode: int = GRAV_STRONG_MASS):
+    """Gravity towards the origin, proportional to the distance (sec. 3.2)."""
+    x, y, m = _f64(x), _f64(y), _f64(m)
+    if mode == GRAV_STRONG_MASS:
+        return -kg * m * x, -kg * m * y
+    if mode == GRAV_STRONG_UNIT:
+        return -kg * x, -kg * y
+    if mode == GRAV_FA2_CONST:
+        r = np.hypot(x, y)
+        s = np.where(r > 0, -kg * m / np.where(r > 0, r, 1.0), 0.0)
+        return s * x, s * y
+    raise ValueError("unknown gravity mode")
+
+
+@dataclasses.dataclass
+class FA2Params:
+    kr: float = 1.0
+    kg: float = 1.0
+    ka: float = 1.0
+    gravity_mode: int = GRAV_STRONG_MASS
+    swing_mode: int = SWING_PAPER
+    tau: float = 1.0
+    ks: float = 0.1
+    ksmax: float = 10.0
+    max_rise: float = 0.5
+    repulsion: str = "exact"  # "exact" | "fmm"
+    p: int = 8
+    leaf_size: int = 64
+    bits: int = 16
+
+
+def forces(row_ptr, col, deg, x, y, prm: FA2Params = FA2Params()):
+    """(F_r, F_a, F_g) of every node, each an (fx, fy) pair."""
+    m = masses(deg)
+    if prm.repulsion == "fmm":
+        fr = repulsion_fmm(x, y, m, prm.kr, prm.p, prm.leaf_size, prm.bits)
+    else:
+        fr = repulsion_exact(x, y, m, prm.kr)
+    fa = attraction(row_ptr, col, x, y, prm.ka)
+    fg = gravity(x, y, m, prm.kg, prm.gravity_mode)
+    return fr, fa, fg
+
+
+def swing_traction(fx, fy, fpx, fpy, m, mode: int = SWING_PAPER):
+    """Per-node swing |F_t - F_{t-1}| and traction |F_t + F_{t-1}| and their
+    sums (sec. 3.2).  Returns (swg_i, tra_i, SWG, TRA)."""
+    fx, fy, fpx, fpy = _f64(fx), _f64(fy), _f64(fpx), _f64(fpy)
+    swg = np.hypot(fx - fpx, fy - fpy)
+    tra = np.hypot(fx + fpx, fy + fpy)
+    if mode == SWING_FA2:
+        w = _f64(m)
+        return swg, tra, float(np.sum(w * swg)), float(np.sum(w * tra) / 2.0)
+    return swg, tra, float(np.sum(swg)), float(np.sum(tra))
+
+
+def global_speed(SWG: float, TRA: float, s_prev: float, it: int, prm: FA2Params) -> float:
+    """s_G = tau TRA / SWG, at most (1 + max_rise) s_prev after the first
+    iteration; SWG = 0 gives 1 on the first iteration and the capped value
+    afterwards."""
+    if SWG > 0.0:
+        s = prm.tau * TRA / SWG
+        if it > 0:
+            s = min(s, (1.0 + prm.max_rise) * s_prev)
+        return s
+    return 1.0 if it == 0 else (1.0 + prm.max_rise) * s_prev
+
+
+def node_speed(swg_i, fx, fy, s_g: float, prm: FA2Params):
+    """s_i = ks s_G / (1 + s_G sqrt(swg_i)), capped at ksmax / |F_i|."""
+    s = prm.ks * s_g / (1.0 + s_g * np.sqrt(swg_i))
+    fn = np.hypot(_f64(fx), _f64(fy))
+    cap = np.where(fn > 0, prm.ksmax / np.where(fn > 0, fn, 1.0), np.inf)
+    return np.minimum(s, cap)
+
+
+def fa2_step(row_ptr, col, deg, x, y, fpx, fpy, s_prev: float, it: int, prm: FA2Params = FA2Params(),
+             given_forces=None):
+    """One ForceAtlas2 iteration (sec. 3.2): forces at the current positions,
+    swing and traction against the previous forces, global then per-node step
+    size, and the move p += s_i F_i.  With ``it == 0`` the previous forces are
+    taken as zero.  ``given_forces`` = (fx, fy) replaces the force evaluation
+    (to check the update given identical forces).  Returns a dict."""
+    m = masses(deg)
+    if given_forces is None:
+        fr, fa, fg = forces(row_ptr, col, deg, x, y, prm)
+        fx = fr[0] + fa[0] + fg[0]
+        fy = fr[1] + fa[1] + fg[1]
+    else:
+        fx, fy = _f64(given_forces[0]), _f64(given_forces[1])
+    if it == 0:
+        fpx = np.zeros_like(fx)
+        fpy = np.zeros_like(fy)
+    swg_i, tra_i, SWG, TRA = swing_traction(fx, fy, fpx, fpy, m, prm.swing_mode)
+    s_g = global_speed(SWG, TRA, s_prev, it, prm)
+    s_i = node_speed(swg_i, fx, fy, s_g, prm)
+    nx = _f64(x) + s_i * fx
+    ny = _f64(y) + s_i * fy
+    return dict(x=nx, y=ny, fx=fx, fy=fy, swg=SWG, tra=TRA, speed=s_g, s_i=s_i)
+
+
+# --- Morton order and quadtree (sec. 3.2.1) -----------------------------------
+
+def root_square(x, y, bits: int = 16):
+    x, y = _f64(x), _f64(y)
+    out = np.empty(4)
+    lib().orc_root(x.shape[0], _p(x), _p(y), int(bits), _p(out))
+    return out  # xmin, ymin, L, S
+
+
+def morton(x, y, bits: int = 16) -> np.ndarray:
+    x, y = _f64(x), _f64(y)
+    k = np.empty(x.shape[0], dtype=np.uint64)
+    lib().orc_morton(x.shape[0], _p(x), _p(y), int(bits), _p(k))
+    return k
+
+
+def sort_by_key(key) -> np.ndarray:
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    perm = np.empty(k.shape[0], dtype=np.int64)
+    lib().orc_sort_by_key(k.shape[0], _p(k), _p(perm))
+    return perm
+
+
+def tree(sorted_keys, bits: int = 16, leaf_size: int = 64) -> np.ndarray:
+    """Cells as an int32 array [ncell, 10]: level, ix, iy, begin, end, parent,
+    child0..3, in (level, Morton prefix) order."""
+    k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    cap = max(16, 4 * k.shape[0] + 16)
+    out = np.empty((cap, 10), dtype=np.int32)
+    c = lib().orc_tree(k.shape[0], _p(k), int(bits), int(leaf_size), cap, _p(out))
+    if c < 0:
+        raise RuntimeError("tree capacity")
+    return out[:c].copy()
+
+
+def fmm_lists(x, y, leaf_size: int = 64, bits: int = 16):
+    """Tree and the U/V/W/X lists of the FMM for these positions."""
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    caps = np.array([4 * n + 16, 64 * n + 64, 64 * n + 64, 64 * n + 64, 64 * n + 64], dtype=np.int64)
+    while True:
+        cells = np.empty((caps[0], 10), dtype=np.int32)
+        ptrs = np.empty(4 * (caps[0] + 1), dtype=np.int64)
+        U = np.empty(caps[1], dtype=np.int32)
+        V = np.empty(caps[2], dtype=np.int32)
+        W = np.empty(caps[3], dtype=np.int32)
+        X = np.empty(caps[4], dtype=np.int32)
+        lens = np.zeros(5, dtype=np.int64)
+        r = lib().orc_fmm_lists(n, _p(x), _p(y), int(leaf_size), int(bits), _p(caps), _p(cells), _p(ptrs),
+                                _p(U), _p(V), _p(W), _p(X), _p(lens))
+        if r >= 0:
+            break
+        caps = np.maximum(caps, lens + 16)
+    nc = int(lens[0])
+    pt = ptrs[:4 * (nc + 1)].reshape(4, nc + 1)
+    return dict(cells=cells[:nc].copy(), U=(pt[0].copy(), U[:lens[1]].copy()), V=(pt[1].copy(), V[:lens[2]].copy()),
+                W=(pt[2].copy(), W[:lens[3]].copy()), X=(pt[3].copy(), X[:lens[4]].copy()))
+
+
+# --- FMM operators, exposed for tests (complex as re/im FP64 arrays) ---------
+
+def _cz(p):
+    return np.zeros(p + 1), np.zeros(p + 1)
+
+
+def op_p2m(zx, zy, q, cx, cy, p):
+    zx, zy, q = _f64(zx), _f64(zy), _f64(q)
+    re, im = _cz(p)
+    lib().orc_op_p2m(zx.shape[0], _p(zx), _p(zy), _p(q), float(cx), float(cy), int(p), _p(re), _p(im))
+    return re + 1j * im
+
+
+def _op3(name, a, z0, p, acc=None):
+    are, aim = _f64(np.real(a)), _f64(np.imag(a))
+    if acc is None:
+        bre, bim = _cz(p)
+    else:
+        bre, bim = _f64(np.real(acc)).copy(), _f64(np.imag(acc)).copy()
+    getattr(lib(), name)(_p(are), _p(aim), float(np.real(z0)), float(np.imag(z0)), int(p), _p(bre), _p(bim))
+    return bre + 1j * bim
+
+
+def op_m2m(a, z0, p, acc=None):
+    return _op3("orc_op_m2m", a, z0, p, acc)
+
+
+def op_m2l(a, z0, p, acc=None):
+    return _op3("orc_op_m2l", a, z0, p, acc)
+
+
+def op_l2l(b, z0, p, acc=None):
+    return _op3("orc_op_l2l", b, z0, p, acc)
+
+
+def op_l2p(b, d, p):
+    bre, bim = _f64(np.real(b)), _f64(np.imag(b))
+    out = np.empty(2)
+    lib().orc_op_l2p(_p(bre), _p(bim), float(np.real(d)), float(np.imag(d)), int(p), _p(out))
+    return out[0] + 1j * out[1]
+
+
+def op_m2p(a, d, p):
+    are, aim = _f64(np.real(a)), _f64(np.imag(a))
+    out = np.empty(2)
+    lib().orc_op_m2p(_p(are), _p(aim), float(np.real(d)), float(np.imag(d)), int(p), _p(out))
+    return out[0] + 1j * out[1]
+
+
+def op_p2l(q, z0, p, acc=None):
+    if acc is None:
+        bre, bim = _cz(p)
+    else:
+        bre, bim = _f64(np.real(acc)).copy(), _f64(np.imag(acc)).copy()
+    lib().orc_op_p2l(float(q), float(np.real(z0)), float(np.imag(z0)), int(p), _p(bre), _p(bim))
+    return bre + 1j * bim
+
+
+# --- Kamada-Kawai (sec. 3.1) ---------------------------------------------------
+
+def hop_distances(row_ptr, col) -> np.ndarray:
+    """All-pairs hop distances of a graph with local ids (BFS per source)."""
+    n = row_ptr.shape[0] - 1
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    d = np.empty((n, n), dtype=np.int32)
+    lib().orc_bfs_hops(n, _p(rp), _p(c), _p(d))
+    return d
+
+
+def floyd_warshall(n: int, row_ptr, col) -> np.ndarray:
+    """The paper's all-pairs shortest path algorithm (sec. 3.1), unit weights;
+    used only to cross-check the breadth-first distances on tiny graphs."""
+    INF = np.iinfo(np.int64).max // 4
+    d = np.full((n, n), INF, dtype=np.int64)
+    np.fill_diagonal(d, 0)
+    for i in range(n):
+        for e in range(row_ptr[i], row_ptr[i + 1]):
+            d[i, col[e]] = 1
+    for k in range(n):
+        d = np.minimum(d, d[:, k:k + 1] + d[k:k + 1, :])
+    d[d >= INF] = -1
+    return d.astype(np.int32)
+
+
+def kk_energy(dist, x, y, l: float = 1.0) -> float:
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    x, y = _f64(x), _f64(y)
+    return float(lib().orc_kk_energy(d.shape[0], _p(d), float(l), _p(x), _p(y)))
+
+
+def kk_steps(dist, x, y, l: float = 1.0, steps: int = 1):
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    x, y = _f64(x).copy(), _f64(y).copy()
+    lib().orc_kk_steps(d.shape[0], _p(d), float(l), int(steps), _p(x), _p(y))
+    return x, y
+
+
+def rel_err(ax, ay, bx, by) -> float:
+    """Norm-wise relative error |a - b|_2 / |b|_2 over all components."""
+    num = np.sqrt(np.sum((_f64(ax) - _f64(bx)) ** 2 + (_f64(ay) - _f64(by)) ** 2))
+    den = np.sqrt(np.sum(_f64(bx) ** 2 + _f64(by) ** 2))
+    return float(num / den) if den > 0 else float(num)

@@ -1,0 +1,216 @@
+/*
+ * fa2lay.h -- C ABI of libfa2lay.so, an MI355X (gfx950) implementation of the
+ * graph layout method of "Graph Visualization for Blockchain Data"
+ * (Dietl, Gemuend, Oeltz, Thiele, Werner, 2024):
+ *
+ *   - split the graph into connected components, ignoring edge directions
+ *     (sec. 4);
+ *   - lay out small components with Kamada-Kawai on shortest-path (hop)
+ *     distances (sec. 3.1, sec. 4);
+ *   - lay out large components with ForceAtlas2, whose all-pairs repulsion is
+ *     evaluated by a 2D Fast Multipole Method over a quadtree (sec. 3.2,
+ *     sec. 3.2.1), with the swing/traction step-size control of sec. 3.2.
+ *
+ * Conventions (every entry point):
+ *   - Pointers are DEVICE pointers on the context's device, owned by the
+ *     caller, unless marked [host].  Arrays are dense, 0-based, and laid out
+ *     as stated.  The library never frees or retains a caller pointer.
+ *   - Work is enqueued on the context's stream (the stream passed to
+ *     fl_create / fl_set_stream).  A call returns before the work finishes
+ *     unless it returns a [host] value, in which case it synchronises the
+ *     stream first.
+ *   - The context owns its workspace (sort buffers, tree, lists, expansions)
+ *     and grows it on demand with hipMalloc; repeated calls at the same or
+ *     smaller sizes allocate nothing.
+ *   - Errors are returned as fl_status; nothing is thrown or aborted across
+ *     the ABI.  Arguments are validated on the host before any launch; a
+ *     failed call launches nothing.  fl_last_error() describes the last
+ *     failure of the context.  A context is not thread-safe: use one per
+ *     host thread and stream.
+ *   - Node ids are int32 in [0, n).  Positions are FP32, structure-of-arrays
+ *     (x[n], y[n]).
+ */
+#ifndef FA2LAY_H
+#define FA2LAY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FL_OK = 0,
+    FL_EINVAL = -1,       /* bad argument (null pointer, size, id out of range, parameter) */
+    FL_ENOMEM = -2,       /* device allocation failed or exceeds the context budget */
+    FL_EHIP = -3,         /* a HIP runtime call failed; see fl_last_error */
+    FL_ENONFINITE = -4,   /* a non-finite position was found */
+    FL_EBUSY = -5,        /* serving: no free slot / budget (try later) */
+    FL_ECANCELED = -6,    /* serving: job cancelled */
+    FL_EUNSUPPORTED = -7  /* valid but not supported by this build (e.g. expansion order) */
+} fl_status;
+
+typedef struct fl_ctx fl_ctx;
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a
+ * hipStream_t; NULL = the device's null stream).  *out receives the handle. */
+fl_status fl_create(fl_ctx **out, int device, void *stream);
+/* Release the context and its workspace (synchronises its stream). */
+void fl_destroy(fl_ctx *ctx);
+/* Text of the last error on this context; valid until the next call on it. */
+const char *fl_last_error(const fl_ctx *ctx);
+/* Switch the stream later calls enqueue on. */
+fl_status fl_set_stream(fl_ctx *ctx, void *stream);
+/* Block until the context's stream has drained. */
+fl_status fl_synchronize(fl_ctx *ctx);
+/* Bytes of device workspace the context holds. [host] */
+size_t fl_workspace_bytes(const fl_ctx *ctx);
+/* Library version string, e.g. "fa2lay 0.1 gfx950". [host] */
+const char *fl_version(void);
+
+/* ------------------------------------------------------------------------
+ * Graph preparation (sec. 2: bipartite address/transaction graph with input
+ * and output edges; sec. 4: components are taken ignoring edge directions).
+ * ------------------------------------------------------------------------ */
+
+/* Build the simple undirected graph of a directed edge list in CSR form:
+ * direction ignored, self loops and duplicate pairs dropped, each row sorted
+ * ascending.  deg[i] = number of distinct neighbours.
+ *   src, dst [m] int32 in [0, n);  row_ptr [n+1];  col_idx capacity 2m;
+ *   deg [n];  *nnz_out [host] = row_ptr[n].  Synchronises.
+ * Errors: FL_EINVAL for n < 1, m < 0, n*n >= 2^62 or an id outside [0, n)
+ * (checked on the device before any output is written). Bit-exact. */
+fl_status fl_build_csr(fl_ctx *ctx, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                       int32_t *row_ptr, int32_t *col_idx, int32_t *deg, int64_t *nnz_out);
+
+/* Connected components of a CSR graph (sec. 4): label[v] = the smallest node
+ * id of v's component.  *n_comp_out [host] = number of components.
+ * Synchronises.  Bit-exact. */
+fl_status fl_components(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        int32_t *label, int32_t *n_comp_out);
+
+/* ------------------------------------------------------------------------
+ * Quadtree hooks (sec. 3.2.1: a square covering all particles, divided into
+ * four while it holds more than leaf_size particles).  Exposed for testing.
+ * ------------------------------------------------------------------------ */
+
+/* Root square and Morton keys of the points (x[i], y[i]):
+ *   xmin, ymin = exact minima (FP64 of FP32 values), L = max(xmax-xmin,
+ *   ymax-ymin) (1 if 0), S = 2^bits / L (FP64, correctly rounded);
+ *   q = min(floor((x - xmin) * S), 2^bits - 1), same for y with ymin;
+ *   key = q_x bits in the even positions, q_y bits in the odd ones.
+ * key [n] uint32; root4 [4] double (xmin, ymin, L, S) may be NULL.
+ * bits in [1, 16]. */
+fl_status fl_morton(fl_ctx *ctx, int32_t n, const float *x, const float *y, int32_t bits, uint32_t *key,
+                    double *root4);
+
+/* Stable ascending sort of key[n] (uint32; only the low 2*bits bits are
+ * significant): key_out [n] sorted keys, perm [n] = source index of each
+ * output position (ties keep ascending index). */
+fl_status fl_sort_keys(fl_ctx *ctx, int32_t n, const uint32_t *key, int32_t bits, uint32_t *key_out,
+                       int32_t *perm);
+
+/* Build the adaptive quadtree of the points and copy it out.  cells
+ * [cap * 10] int32, one row per cell: level, ix, iy, begin, end, parent,
+ * child0..child3 (-1 = empty quadrant; child q covers (2ix + (q&1),
+ * 2iy + (q>>1))); [begin, end) indexes the Morton-sorted order.  Cells are
+ * in depth-first pre-order (sorted by (begin, level)).  A cell is a leaf iff
+ * it holds <= leaf_size points or sits at level `bits`.  *n_cells_out [host].
+ * Synchronises.  FL_EINVAL if cap is too small (n_cells_out still set). */
+fl_status fl_tree(fl_ctx *ctx, int32_t n, const float *x, const float *y, int32_t bits, int32_t leaf_size,
+                  int32_t *cells, int32_t cap, int32_t *n_cells_out);
+
+/* ------------------------------------------------------------------------
+ * ForceAtlas2 (sec. 3.2) with FMM repulsion (sec. 3.2.1)
+ * ------------------------------------------------------------------------ */
+
+enum { FL_GRAV_STRONG_MASS = 0, FL_GRAV_FA2_CONST = 1, FL_GRAV_STRONG_UNIT = 2 };
+enum { FL_SWING_PAPER = 0, FL_SWING_FA2 = 1 };
+enum { FL_REP_EXACT = 0, FL_REP_FMM = 1 };
+
+/* Forces (mass m_i = deg_i + 1):
+ *   repulsion  F_r,i = kr m_i sum_{j != i} m_j (p_i - p_j) / |p_i - p_j|^2
+ *              (coincident pairs contribute 0);
+ *   attraction F_a,i = ka sum_{j in N(i)} (p_j - p_i);
+ *   gravity    STRONG_MASS: -kg m_i p_i;  STRONG_UNIT: -kg p_i;
+ *              FA2_CONST: -kg m_i p_i / |p_i| (0 at the origin).
+ * Step (sec. 3.2): swg_i = |F_i - F'_i|, tra_i = |F_i + F'_i| with F' the
+ *   previous iteration's forces (0 on the first); SWING_PAPER: SWG = sum
+ *   swg_i, TRA = sum tra_i; SWING_FA2: SWG = sum m_i swg_i, TRA = sum
+ *   m_i tra_i / 2.  s_G = tau TRA / SWG, capped at (1 + max_rise) s_prev after
+ *   the first iteration (SWG = 0: 1 on the first, the cap afterwards);
+ *   s_i = ks s_G / (1 + s_G sqrt(swg_i)), capped at ksmax / |F_i|;
+ *   p_i += s_i F_i.  Sums, s_G and s_i are FP64. */
+typedef struct {
+    double kr, kg, ka;
+    int32_t gravity_mode;  /* FL_GRAV_* */
+    int32_t swing_mode;    /* FL_SWING_* */
+    double tau, ks, ksmax, max_rise;
+    int32_t repulsion;     /* FL_REP_EXACT (O(n^2)) or FL_REP_FMM */
+    int32_t p;             /* FMM expansion order: 4, 6, 8, 10, 12, 16 */
+    int32_t leaf_size;     /* FMM: a cell holding more points is divided (1..1024) */
+    int32_t morton_bits;   /* FMM: quadtree depth cap, 1..16 */
+} fl_fa2_params;
+
+/* Defaults: kr = kg = ka = 1, STRONG_MASS, SWING_PAPER, tau = 1, ks = 0.1,
+ * ksmax = 10, max_rise = 0.5, FMM, p = 8, leaf_size = 64, morton_bits = 16. */
+void fl_fa2_default_params(fl_fa2_params *prm);
+
+/* Caller-owned iteration state. fx_prev/fy_prev [n]: forces of the previous
+ * iteration (ignored when iter == 0), overwritten with this iteration's.
+ * scalars [4] double on the device: [0] s_G of the previous iteration
+ * (read when iter > 0), overwritten with this iteration's s_G; [1] SWG;
+ * [2] TRA of the last iteration.  iter [host] counts completed iterations
+ * and is advanced by the step/run calls. */
+typedef struct {
+    float *fx_prev;
+    float *fy_prev;
+    double *scalars;
+    int64_t iter;
+} fl_fa2_state;
+
+typedef struct {
+    double swg, tra, speed;
+} fl_step_stats;
+
+/* The three force terms at positions (x, y) of a CSR graph (deg [n] as from
+ * fl_build_csr; row_ptr/col_idx symmetric).  Any output pair may be NULL. */
+fl_status fl_fa2_forces(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        const int32_t *deg, const float *x, const float *y, const fl_fa2_params *prm,
+                        float *frx, float *fry, float *fax, float *fay, float *fgx, float *fgy);
+
+/* One iteration, in place on x, y and the state.  stats [host] may be NULL
+ * (if not, the call synchronises).  FL_ENONFINITE if a force or position is
+ * not finite (then x, y are left unmodified). */
+fl_status fl_fa2_step(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                      const int32_t *deg, float *x, float *y, fl_fa2_state *state, const fl_fa2_params *prm,
+                      fl_step_stats *stats);
+
+/* `iters` iterations with no host synchronisation inside the loop.
+ * per_iter [host, iters entries] may be NULL (if not, synchronises at the
+ * end).  Checks for non-finite values at the end of the run. */
+fl_status fl_fa2_run(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const int32_t *deg, float *x, float *y, fl_fa2_state *state, const fl_fa2_params *prm,
+                     int32_t iters, fl_step_stats *per_iter);
+
+/* Statistics of the last FMM evaluation on this context [host, synchronises]:
+ * out[0] cells, [1] leaves, [2] near-field (P2P) particle pairs, [3] M2L
+ * (V-list) entries, [4] W-list entries, [5] X-list entries, [6] deepest
+ * level, [7] U-list entries. */
+fl_status fl_fmm_stats(fl_ctx *ctx, int64_t *out8);
+
+/* Per-phase device timing (HIP events on the context's stream).  When
+ * enabled, fl_fa2_step/run record events around their phases; fl_get_timing
+ * returns the accumulated milliseconds and launch counts per phase
+ * (FL_NPHASE entries each) and clears them [host, synchronises]. */
+enum { FL_PH_TREE = 0, FL_PH_LISTS, FL_PH_UPWARD, FL_PH_M2L, FL_PH_EVAL, FL_PH_ATTRACT, FL_PH_UPDATE,
+       FL_PH_EXACT, FL_NPHASE };
+fl_status fl_set_timing(fl_ctx *ctx, int enable);
+fl_status fl_get_timing(fl_ctx *ctx, double *ms, int64_t *counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FA2LAY_H */

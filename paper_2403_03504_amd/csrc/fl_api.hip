@@ -1,0 +1,153 @@
+// Context management, error plumbing and per-phase timing of libfa2lay.
+#include "fl_common.h"
+
+#include <cstdio>
+
+namespace fl {
+
+PhaseTimer::PhaseTimer(fl_ctx *ctx, int phase) : c(ctx), ph(phase)
+{
+    if (!c->timing) return;
+    if (c->ev_free.empty()) {
+        hipEvent_t e;
+        FL_CHECK_HIP(hipEventCreate(&e));
+        c->ev_free.push_back(e);
+    }
+    a = c->ev_free.back();
+    c->ev_free.pop_back();
+    FL_CHECK_HIP(hipEventRecord(a, c->stream));
+}
+
+PhaseTimer::~PhaseTimer() noexcept(false)
+{
+    if (!a) return;
+    hipEvent_t b;
+    if (c->ev_free.empty()) {
+        if (hipEventCreate(&b) != hipSuccess) return;
+    } else {
+        b = c->ev_free.back();
+        c->ev_free.pop_back();
+    }
+    if (hipEventRecord(b, c->stream) != hipSuccess) return;
+    c->ev_pending.push_back({ph, {a, b}});
+    // bound the number of outstanding events: fold the oldest ones once the
+    // stream has passed them (this synchronises, so keep the window large)
+    if (c->ev_pending.size() > 4096) flush_timing(c);
+}
+
+void flush_timing(fl_ctx *c)
+{
+    for (auto &pe : c->ev_pending) {
+        FL_CHECK_HIP(hipEventSynchronize(pe.second.second));
+        float ms = 0.f;
+        FL_CHECK_HIP(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+        c->phase_ms[pe.first] += ms;
+        c->phase_cnt[pe.first] += 1;
+        c->ev_free.push_back(pe.second.first);
+        c->ev_free.push_back(pe.second.second);
+    }
+    c->ev_pending.clear();
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+const char *fl_version(void) { return "fa2lay 0.1 gfx950"; }
+
+fl_status fl_create(fl_ctx **out, int device, void *stream)
+{
+    if (!out) return FL_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FL_EINVAL;
+    fl_ctx *c = new (std::nothrow) fl_ctx();
+    if (!c) return FL_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return FL_EHIP;
+    }
+    if (hipMalloc(&c->d_stats, 16 * sizeof(int64_t)) != hipSuccess) {
+        delete c;
+        return FL_ENOMEM;
+    }
+    if (hipMemset(c->d_stats, 0, 16 * sizeof(int64_t)) != hipSuccess ||
+        hipHostMalloc(&c->host_stage, 4096, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(c->d_stats);
+        delete c;
+        return FL_EHIP;
+    }
+    *out = c;
+    return FL_OK;
+}
+
+void fl_destroy(fl_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    for (auto &pe : c->ev_pending) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    for (auto e : c->ev_free) (void)hipEventDestroy(e);
+    if (c->d_stats) (void)hipFree(c->d_stats);
+    if (c->host_stage) (void)hipHostFree(c->host_stage);
+    delete c;
+}
+
+const char *fl_last_error(const fl_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+fl_status fl_set_stream(fl_ctx *c, void *stream)
+{
+    FL_API_BEGIN(c)
+    c->stream = (hipStream_t)stream;
+    FL_API_END(c)
+}
+
+fl_status fl_synchronize(fl_ctx *c)
+{
+    FL_API_BEGIN(c)
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    FL_API_END(c)
+}
+
+size_t fl_workspace_bytes(const fl_ctx *c) { return c ? c->ws_bytes : 0; }
+
+fl_status fl_set_timing(fl_ctx *c, int enable)
+{
+    FL_API_BEGIN(c)
+    c->timing = enable != 0;
+    FL_API_END(c)
+}
+
+fl_status fl_get_timing(fl_ctx *c, double *ms, int64_t *counts)
+{
+    FL_API_BEGIN(c)
+    flush_timing(c);
+    for (int i = 0; i < FL_NPHASE; ++i) {
+        if (ms) ms[i] = c->phase_ms[i];
+        if (counts) counts[i] = c->phase_cnt[i];
+        c->phase_ms[i] = 0.0;
+        c->phase_cnt[i] = 0;
+    }
+    FL_API_END(c)
+}
+
+fl_status fl_fmm_stats(fl_ctx *c, int64_t *out8)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(out8 != nullptr, "fl_fmm_stats: null output");
+    FL_CHECK_HIP(hipMemcpyAsync(c->host_stage, c->d_stats, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    std::memcpy(out8, c->host_stage, 8 * sizeof(int64_t));
+    FL_API_END(c)
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+// Internal header of libfa2lay: context, workspace, error plumbing and the
+// wave64 device helpers shared by the kernels.  Written for gfx950 (CDNA4):
+// 64-lane wavefronts, 256-thread workgroups unless a kernel says otherwise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fa2lay.h"
+
+namespace fl {
+
+constexpr int WAVE = 64;
+
+struct Error : std::runtime_error {
+    fl_status code;
+    Error(fl_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define FL_CHECK_HIP(expr)                                                                          \
+    do {                                                                                            \
+        hipError_t _e = (expr);                                                                     \
+        if (_e != hipSuccess)                                                                       \
+            throw ::fl::Error(FL_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));          \
+    } while (0)
+
+#define FL_REQUIRE(cond, msg)                                                                       \
+    do {                                                                                            \
+        if (!(cond)) throw ::fl::Error(FL_EINVAL, msg);                                             \
+    } while (0)
+
+#define FL_LAUNCH_CHECK() FL_CHECK_HIP(hipGetLastError())
+
+// Entry points: validate, run, map exceptions to fl_status and the
+// context's last-error text.  Nothing is thrown across the C ABI.
+#define FL_API_BEGIN(c)                                                                             \
+    if (!(c)) return FL_EINVAL;                                                                     \
+    try {                                                                                           \
+        FL_CHECK_HIP(hipSetDevice((c)->device));
+
+#define FL_API_END(c)                                                                               \
+    }                                                                                               \
+    catch (const fl::Error &e) {                                                                    \
+        (c)->err = e.what();                                                                        \
+        return e.code;                                                                              \
+    }                                                                                               \
+    catch (const std::exception &e) {                                                               \
+        (c)->err = e.what();                                                                        \
+        return FL_EHIP;                                                                             \
+    }                                                                                               \
+    return FL_OK;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace fl
+
+struct fl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::map<std::string, fl::DevBuf> bufs;
+    size_t ws_bytes = 0;
+    // pinned host staging for small read-backs
+    void *host_stage = nullptr;
+    // timing
+    bool timing = false;
+    double phase_ms[FL_NPHASE] = {};
+    int64_t phase_cnt[FL_NPHASE] = {};
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    // statistics of the last FMM evaluation live in device memory
+    int64_t *d_stats = nullptr;  // [8]
+    uint32_t epoch = 0;          // hash-table epoch, advanced per tree build
+};
+
+namespace fl {
+
+// Grow-only named workspace buffer of at least `count` elements of T.
+// Growing synchronises the stream (the old buffer may still be in use).
+template <class T>
+T *ws(fl_ctx *c, const char *name, size_t count)
+{
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    DevBuf &b = c->bufs[name];
+    if (b.cap < bytes) {
+        if (b.p) {
+            FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+            FL_CHECK_HIP(hipFree(b.p));
+            c->ws_bytes -= b.cap;
+            b.p = nullptr;
+            b.cap = 0;
+        }
+        size_t nb = bytes + bytes / 8 + 256;
+        hipError_t e = hipMalloc(&b.p, nb);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(FL_ENOMEM, std::string("workspace allocation of ") + std::to_string(nb) + " bytes for " +
+                                       name + " failed");
+        }
+        b.cap = nb;
+        c->ws_bytes += nb;
+    }
+    return static_cast<T *>(b.p);
+}
+
+// Zero-filled on first allocation (kept for buffers whose contents must start
+// at zero and are kept clean by the kernels that use them).
+template <class T>
+T *ws_zeroed(fl_ctx *c, const char *name, size_t count)
+{
+    DevBuf &b = c->bufs[name];
+    size_t before = b.cap;
+    T *p = ws<T>(c, name, count);
+    if (b.cap != before) FL_CHECK_HIP(hipMemsetAsync(p, 0, b.cap, c->stream));
+    return p;
+}
+
+inline unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 1 << 20)
+{
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (unsigned)b;
+}
+
+// ---- timing helpers --------------------------------------------------------
+struct PhaseTimer {
+    fl_ctx *c;
+    int ph;
+    hipEvent_t a = nullptr;
+    PhaseTimer(fl_ctx *ctx, int phase);
+    ~PhaseTimer() noexcept(false);
+};
+void flush_timing(fl_ctx *c);
+
+// ---- device helpers --------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ float wave_min_f(float v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// Inclusive scan across the 64 lanes of a wave.
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        T t = __shfl_up(v, o, WAVE);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over a block of NT threads; returns the exclusive prefix and
+// the block total.  `lds` holds NT/64 elements.  Contains __syncthreads.
+template <class T, int NT>
+__device__ __forceinline__ T block_excl_scan(T v, T *lds, T &total)
+{
+    constexpr int NW = NT / WAVE;
+    int lane = lane_id(), w = threadIdx.x / WAVE;
+    T inc = wave_incl_scan(v);
+    if (lane == WAVE - 1) lds[w] = inc;
+    __syncthreads();
+    T wbase = T(0), tot = T(0);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        T s = lds[i];
+        if (i < w) wbase += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wbase + inc - v;
+}
+
+// Sum over a block of NT threads (deterministic order); result valid in all
+// threads.  `lds` holds NT/64 elements.
+template <class T, int NT>
+__device__ __forceinline__ T block_sum(T v, T *lds)
+{
+    constexpr int NW = NT / WAVE;
+    T s = wave_sum(v);
+    if (lane_id() == 0) lds[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    T tot = T(0);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) tot += lds[i];
+    __syncthreads();
+    return tot;
+}
+
+// ---- scans and sorts (fl_scan.hip) ----------------------------------------
+// Exclusive scan of in[0..n) into out[0..n]; out[n] = total.  n is a host
+// bound; when dn != nullptr the live length is *dn (<= n) and elements past it
+// read as zero.  Three launches.
+void scan_excl_i32(fl_ctx *c, const int32_t *in, int32_t *out, int64_t n, const int32_t *dn = nullptr);
+void scan_excl_i64(fl_ctx *c, const int64_t *in, int64_t *out, int64_t n, const int32_t *dn = nullptr);
+
+// Stable LSD radix sort of 32-bit keys with int32 payload over bits
+// [0, nbits).  Ping-pongs between (k, v) and (kt, vt); returns true when the
+// sorted result ended in (kt, vt).
+bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits);
+bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits);
+
+}  // namespace fl

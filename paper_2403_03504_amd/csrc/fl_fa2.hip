@@ -1,0 +1,442 @@
+// ForceAtlas2 iteration of the paper's sec. 3.2 on one GPU:
+//   repulsion  exact O(n^2) (LDS-tiled) or FMM (fl_fmm.hip)
+//   k_combine  linear CSR attraction (FP64 sums; rows longer than 32 are
+//              summed by the whole block), gravity, F = F_r + F_a + F_g,
+//              per-node swing |F - F'| and traction |F + F'| in FP64, block
+//              partial sums; the last block to finish adds the partials in a
+//              fixed order and sets the global speed s_G (no host round trip)
+//   k_update   per-node speed and move p += s_i F, F' <- F
+// There are no floating-point atomics: a run is bitwise reproducible.
+#include "fl_fmm.h"
+
+namespace fl {
+namespace {
+
+constexpr int NT = 256;
+constexpr int HEAVY = 32;
+
+struct StepConsts {
+    double ka, kg, tau, ks, ksmax, max_rise;
+    int gravity_mode, swing_mode;
+};
+
+// ---- exact repulsion ------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_rep_exact(int n, const float *__restrict__ x, const float *__restrict__ y,
+                                                  const int32_t *__restrict__ deg, float kr, float *__restrict__ frx,
+                                                  float *__restrict__ fry)
+{
+    __shared__ float4 tile[NT];
+    const int i = blockIdx.x * NT + threadIdx.x;
+    const float xi = i < n ? x[i] : 0.f, yi = i < n ? y[i] : 0.f;
+    double ax = 0.0, ay = 0.0;
+    for (int t0 = 0; t0 < n; t0 += NT) {
+        const int j = t0 + threadIdx.x;
+        tile[threadIdx.x] = j < n ? make_float4(x[j], y[j], (float)(deg[j] + 1), 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+        float sx = 0.f, sy = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < NT; ++k) {
+            const float4 s = tile[k];
+            const float dx = xi - s.x, dy = yi - s.y;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+            const float sm = s.z * __builtin_amdgcn_rcpf(r2);
+            sx = fmaf(sm, dx, sx);
+            sy = fmaf(sm, dy, sy);
+        }
+        ax += sx;
+        ay += sy;
+        __syncthreads();
+    }
+    if (i < n) {
+        const double km = (double)kr * (double)(deg[i] + 1);
+        frx[i] = (float)(km * ax);
+        fry[i] = (float)(km * ay);
+    }
+}
+
+// ---- attraction + gravity + combine + swing/traction ---------------------------
+__global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ col, const int32_t *__restrict__ deg,
+                                                const float *__restrict__ x, const float *__restrict__ y,
+                                                const float *__restrict__ frx, const float *__restrict__ fry,
+                                                StepConsts k, const float *__restrict__ fpx,
+                                                const float *__restrict__ fpy, int first, float *__restrict__ fx,
+                                                float *__restrict__ fy, float *__restrict__ fax,
+                                                float *__restrict__ fay, float *__restrict__ fgx,
+                                                float *__restrict__ fgy, double2 *__restrict__ part,
+                                                unsigned *__restrict__ ticket, double *__restrict__ scalars,
+                                                int32_t *__restrict__ flags, double *__restrict__ ring, int ring_it)
+{
+    __shared__ int hl[NT];
+    __shared__ double2 hres[NT];
+    __shared__ int nh;
+    __shared__ double lds[NT / WAVE];
+    __shared__ int is_last;
+    if (threadIdx.x == 0) nh = 0;
+    __syncthreads();
+    const int i = blockIdx.x * NT + threadIdx.x;
+    double ax = 0.0, ay = 0.0, xi = 0.0, yi = 0.0;
+    int slot = -1;
+    if (i < n) {
+        xi = x[i];
+        yi = y[i];
+        const int rb = row_ptr[i], re = row_ptr[i + 1];
+        if (re - rb <= HEAVY) {
+            for (int e = rb; e < re; ++e) {
+                const int j = col[e];
+                ax += (double)x[j] - xi;
+                ay += (double)y[j] - yi;
+            }
+        } else {
+            slot = atomicAdd(&nh, 1);
+            hl[slot] = i;
+        }
+    }
+    __syncthreads();
+    const int nheavy = nh;
+    for (int h = 0; h < nheavy; ++h) {
+        const int r = hl[h];
+        const int rb = row_ptr[r], re = row_ptr[r + 1];
+        const double rx = x[r], ry = y[r];
+        double sx = 0.0, sy = 0.0;
+        for (int e = rb + threadIdx.x; e < re; e += NT) {
+            const int j = col[e];
+            sx += (double)x[j] - rx;
+            sy += (double)y[j] - ry;
+        }
+        sx = block_sum<double, NT>(sx, lds);
+        sy = block_sum<double, NT>(sy, lds);
+        if (threadIdx.x == 0) hres[h] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if (slot >= 0) {
+        ax = hres[slot].x;
+        ay = hres[slot].y;
+    }
+    double wswg = 0.0, wtra = 0.0;
+    if (i < n) {
+        const double m = (double)(deg[i] + 1);
+        const double Fax = k.ka * ax, Fay = k.ka * ay;
+        double Fgx, Fgy;
+        if (k.gravity_mode == FL_GRAV_STRONG_UNIT) {
+            Fgx = -k.kg * xi;
+            Fgy = -k.kg * yi;
+        } else if (k.gravity_mode == FL_GRAV_FA2_CONST) {
+            const double r = sqrt(xi * xi + yi * yi);
+            const double s = r > 0.0 ? -k.kg * m / r : 0.0;
+            Fgx = s * xi;
+            Fgy = s * yi;
+        } else {
+            Fgx = -k.kg * m * xi;
+            Fgy = -k.kg * m * yi;
+        }
+        const double Frx = frx ? (double)frx[i] : 0.0, Fry = fry ? (double)fry[i] : 0.0;
+        const float Fx = (float)(Frx + Fax + Fgx), Fy = (float)(Fry + Fay + Fgy);
+        if (fx) {
+            fx[i] = Fx;
+            fy[i] = Fy;
+        }
+        if (fax) {
+            fax[i] = (float)Fax;
+            fay[i] = (float)Fay;
+        }
+        if (fgx) {
+            fgx[i] = (float)Fgx;
+            fgy[i] = (float)Fgy;
+        }
+        if (!isfinite(Fx) || !isfinite(Fy)) atomicOr(flags, 1);
+        if (part) {
+            const double px = first ? 0.0 : (double)fpx[i], py = first ? 0.0 : (double)fpy[i];
+            const double dxs = (double)Fx - px, dys = (double)Fy - py;
+            const double dxt = (double)Fx + px, dyt = (double)Fy + py;
+            const double w = (k.swing_mode == FL_SWING_FA2) ? m : 1.0;
+            wswg = w * sqrt(dxs * dxs + dys * dys);
+            wtra = w * sqrt(dxt * dxt + dyt * dyt);
+        }
+    }
+    if (!part) return;
+    wswg = block_sum<double, NT>(wswg, lds);
+    wtra = block_sum<double, NT>(wtra, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = make_double2(wswg, wtra);
+        __threadfence();
+        const unsigned t = atomicAdd(ticket, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    // fixed-order reduction of the block partials
+    double s0 = 0.0, s1 = 0.0;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += NT) {
+        const double2 v = part[b];
+        s0 += v.x;
+        s1 += v.y;
+    }
+    s0 = block_sum<double, NT>(s0, lds);
+    s1 = block_sum<double, NT>(s1, lds);
+    if (threadIdx.x == 0) {
+        const double SWG = s0;
+        const double TRA = (k.swing_mode == FL_SWING_FA2) ? s1 / 2.0 : s1;
+        const double sprev = scalars[0];
+        double sG;
+        if (SWG > 0.0) {
+            sG = k.tau * TRA / SWG;
+            if (!first) sG = fmin(sG, (1.0 + k.max_rise) * sprev);
+        } else {
+            sG = first ? 1.0 : (1.0 + k.max_rise) * sprev;
+        }
+        scalars[0] = sG;
+        scalars[1] = SWG;
+        scalars[2] = TRA;
+        if (ring) {
+            ring[3 * ring_it + 0] = SWG;
+            ring[3 * ring_it + 1] = TRA;
+            ring[3 * ring_it + 2] = sG;
+        }
+        *ticket = 0u;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_update(int n, float *__restrict__ x, float *__restrict__ y,
+                                               const float *__restrict__ fx, const float *__restrict__ fy,
+                                               float *__restrict__ fpx, float *__restrict__ fpy, int first,
+                                               const double *__restrict__ scalars, double ks, double ksmax,
+                                               int32_t *__restrict__ flags)
+{
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    if (*flags & 1) return;  // non-finite forces: leave the layout as it was
+    const double sG = scalars[0];
+    const float Fx = fx[i], Fy = fy[i];
+    const double px = first ? 0.0 : (double)fpx[i], py = first ? 0.0 : (double)fpy[i];
+    const double dx = (double)Fx - px, dy = (double)Fy - py;
+    const double swg = sqrt(dx * dx + dy * dy);
+    double s = ks * sG / (1.0 + sG * sqrt(swg));
+    const double fn = sqrt((double)Fx * Fx + (double)Fy * Fy);
+    if (fn > 0.0) s = fmin(s, ksmax / fn);
+    const float nx = (float)((double)x[i] + s * (double)Fx);
+    const float ny = (float)((double)y[i] + s * (double)Fy);
+    x[i] = nx;
+    y[i] = ny;
+    fpx[i] = Fx;
+    fpy[i] = Fy;
+    if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags, 2);
+}
+
+__global__ void k_validate_graph(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                 const int32_t *__restrict__ deg, int32_t *__restrict__ bad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == 0 && row_ptr[0] != 0) atomicOr(bad, 1);
+    if (i == n) return;
+    const int rb = row_ptr[i], re = row_ptr[i + 1];
+    if (re < rb) {
+        atomicOr(bad, 2);
+        return;
+    }
+    if (deg && deg[i] != re - rb) atomicOr(bad, 4);
+    for (int e = rb; e < re; ++e) {
+        const int j = col[e];
+        if (j < 0 || j >= n) {
+            atomicOr(bad, 8);
+            return;
+        }
+    }
+}
+
+__global__ void k_check_finite(int n, const float *__restrict__ x, const float *__restrict__ y,
+                               int32_t *__restrict__ flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (!isfinite(x[i]) || !isfinite(y[i]))) atomicOr(flags, 4);
+}
+
+}  // namespace
+
+struct GraphArgs {
+    int32_t n;
+    const int32_t *row_ptr, *col, *deg;
+};
+
+static void validate_params(const fl_fa2_params *p)
+{
+    FL_REQUIRE(p != nullptr, "null FA2 parameters");
+    FL_REQUIRE(std::isfinite(p->kr) && std::isfinite(p->kg) && std::isfinite(p->ka), "kr, kg, ka must be finite");
+    FL_REQUIRE(p->gravity_mode >= 0 && p->gravity_mode <= 2, "unknown gravity_mode");
+    FL_REQUIRE(p->swing_mode == FL_SWING_PAPER || p->swing_mode == FL_SWING_FA2, "unknown swing_mode");
+    FL_REQUIRE(p->tau > 0.0 && std::isfinite(p->tau), "tau must be > 0");
+    FL_REQUIRE(p->ks >= 0.0 && std::isfinite(p->ks), "ks must be >= 0");
+    FL_REQUIRE(p->ksmax > 0.0, "ksmax must be > 0");
+    FL_REQUIRE(p->max_rise >= 0.0 && std::isfinite(p->max_rise), "max_rise must be >= 0");
+    FL_REQUIRE(p->repulsion == FL_REP_EXACT || p->repulsion == FL_REP_FMM, "unknown repulsion mode");
+    if (p->repulsion == FL_REP_FMM) {
+        FL_REQUIRE(p->leaf_size >= 1 && p->leaf_size <= 1024, "leaf_size must be in [1, 1024]");
+        FL_REQUIRE(p->morton_bits >= 1 && p->morton_bits <= 16, "morton_bits must be in [1, 16]");
+        if (!fmm_order_supported(p->p))
+            throw Error(p->p >= 1 && p->p <= 20 ? FL_EUNSUPPORTED : FL_EINVAL,
+                        "FMM expansion order must be one of 4, 6, 8, 10, 12, 16");
+    }
+}
+
+static void validate_graph(fl_ctx *c, const GraphArgs &g)
+{
+    FL_REQUIRE(g.n >= 1, "need n >= 1");
+    FL_REQUIRE(g.row_ptr && g.col && g.deg, "null graph array");
+    int32_t *bad = ws<int32_t>(c, "fa2_bad", 1);
+    FL_CHECK_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), c->stream));
+    hipLaunchKernelGGL(k_validate_graph, dim3(grid_for((int64_t)g.n + 1, NT)), dim3(NT), 0, c->stream, g.n, g.row_ptr,
+                       g.col, g.deg, bad);
+    FL_LAUNCH_CHECK();
+    int32_t b = read_i32(c, bad);
+    if (b & 1) throw Error(FL_EINVAL, "row_ptr[0] must be 0");
+    if (b & 2) throw Error(FL_EINVAL, "row_ptr must be non-decreasing");
+    if (b & 4) throw Error(FL_EINVAL, "deg[i] must equal row_ptr[i+1] - row_ptr[i]");
+    if (b & 8) throw Error(FL_EINVAL, "column index outside [0, n)");
+}
+
+static void repulsion(fl_ctx *c, const GraphArgs &g, const float *x, const float *y, const fl_fa2_params *p,
+                      float *frx, float *fry)
+{
+    if (p->repulsion == FL_REP_EXACT) {
+        PhaseTimer pt(c, FL_PH_EXACT);
+        hipLaunchKernelGGL(k_rep_exact, dim3(grid_for(g.n, NT)), dim3(NT), 0, c->stream, g.n, x, y, g.deg,
+                           (float)p->kr, frx, fry);
+        FL_LAUNCH_CHECK();
+    } else {
+        fmm_repulsion(c, g.n, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, (float)p->kr, frx, fry);
+    }
+}
+
+static StepConsts consts(const fl_fa2_params *p)
+{
+    return StepConsts{p->ka, p->kg, p->tau, p->ks, p->ksmax, p->max_rise, p->gravity_mode, p->swing_mode};
+}
+
+// one iteration; flags must have been cleared by the caller
+static void iteration(fl_ctx *c, const GraphArgs &g, float *x, float *y, fl_fa2_state *st, const fl_fa2_params *p,
+                      int32_t *flags, double *ring, int ring_it)
+{
+    const int n = g.n;
+    float *frx = ws<float>(c, "fa2_frx", n);
+    float *fry = ws<float>(c, "fa2_fry", n);
+    float *fcx = ws<float>(c, "fa2_fcx", n);
+    float *fcy = ws<float>(c, "fa2_fcy", n);
+    const unsigned nb = grid_for(n, NT);
+    double2 *part = ws<double2>(c, "fa2_part", nb);
+    unsigned *ticket = ws_zeroed<unsigned>(c, "fa2_ticket", 4);
+    const int first = st->iter == 0 ? 1 : 0;
+    repulsion(c, g, x, y, p, frx, fry);
+    {
+        PhaseTimer pt(c, FL_PH_ATTRACT);
+        hipLaunchKernelGGL(k_combine, dim3(nb), dim3(NT), 0, c->stream, n, g.row_ptr, g.col, g.deg, x, y, frx, fry,
+                           consts(p), st->fx_prev, st->fy_prev, first, fcx, fcy, (float *)nullptr, (float *)nullptr,
+                           (float *)nullptr, (float *)nullptr, part, ticket, st->scalars, flags, ring, ring_it);
+        FL_LAUNCH_CHECK();
+    }
+    {
+        PhaseTimer pt(c, FL_PH_UPDATE);
+        hipLaunchKernelGGL(k_update, dim3(nb), dim3(NT), 0, c->stream, n, x, y, fcx, fcy, st->fx_prev, st->fy_prev,
+                           first, st->scalars, p->ks, p->ksmax, flags);
+        FL_LAUNCH_CHECK();
+    }
+    st->iter += 1;
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+void fl_fa2_default_params(fl_fa2_params *p)
+{
+    if (!p) return;
+    p->kr = 1.0;
+    p->kg = 1.0;
+    p->ka = 1.0;
+    p->gravity_mode = FL_GRAV_STRONG_MASS;
+    p->swing_mode = FL_SWING_PAPER;
+    p->tau = 1.0;
+    p->ks = 0.1;
+    p->ksmax = 10.0;
+    p->max_rise = 0.5;
+    p->repulsion = FL_REP_FMM;
+    p->p = 8;
+    p->leaf_size = 64;
+    p->morton_bits = 16;
+}
+
+fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                        const float *x, const float *y, const fl_fa2_params *prm, float *frx, float *fry, float *fax,
+                        float *fay, float *fgx, float *fgy)
+{
+    FL_API_BEGIN(c)
+    validate_params(prm);
+    FL_REQUIRE(x && y, "null positions");
+    FL_REQUIRE((!frx) == (!fry) && (!fax) == (!fay) && (!fgx) == (!fgy), "force outputs come in x/y pairs");
+    GraphArgs g{n, row_ptr, col_idx, deg};
+    validate_graph(c, g);
+    float *rx = frx ? frx : ws<float>(c, "fa2_frx", n);
+    float *ry = fry ? fry : ws<float>(c, "fa2_fry", n);
+    repulsion(c, g, x, y, prm, rx, ry);
+    if (fax || fgx) {
+        int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
+        hipLaunchKernelGGL(k_combine, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, row_ptr, col_idx, deg, x, y,
+                           (const float *)nullptr, (const float *)nullptr, consts(prm), (const float *)nullptr,
+                           (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
+                           (double2 *)nullptr, (unsigned *)nullptr, (double *)nullptr, flags, (double *)nullptr, 0);
+        FL_LAUNCH_CHECK();
+    }
+    FL_API_END(c)
+}
+
+static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                          float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, int32_t iters,
+                          fl_step_stats *per_iter, bool always_sync)
+{
+    FL_API_BEGIN(c)
+    validate_params(prm);
+    FL_REQUIRE(x && y && st && st->fx_prev && st->fy_prev && st->scalars, "null positions or state");
+    FL_REQUIRE(st->iter >= 0, "state iter must be >= 0");
+    FL_REQUIRE(iters >= 0, "iters must be >= 0");
+    GraphArgs g{n, row_ptr, col_idx, deg};
+    validate_graph(c, g);
+    int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
+    FL_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), c->stream));
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, x, y, flags);
+    FL_LAUNCH_CHECK();
+    if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
+    double *ring = per_iter ? ws<double>(c, "fa2_ring", 3 * (size_t)(iters > 0 ? iters : 1)) : nullptr;
+    for (int it = 0; it < iters; ++it) iteration(c, g, x, y, st, prm, flags, ring, it);
+    if (per_iter || always_sync) {
+        int32_t f = read_i32(c, flags);
+        if (per_iter && iters > 0) {
+            std::vector<double> h(3 * (size_t)iters);
+            FL_CHECK_HIP(hipMemcpyAsync(h.data(), ring, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+            FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+            for (int it = 0; it < iters; ++it) per_iter[it] = fl_step_stats{h[3 * it], h[3 * it + 1], h[3 * it + 2]};
+        }
+        if (prm->repulsion == FL_REP_FMM && tree_error_bits(c, true))
+            throw Error(FL_EHIP, "FMM capacity guard tripped (tree or list sizes)");
+        if (f & 1) throw Error(FL_ENONFINITE, "non-finite force");
+        if (f & 2) throw Error(FL_ENONFINITE, "non-finite position after the update");
+    }
+    FL_API_END(c)
+}
+
+fl_status fl_fa2_step(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                      float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, fl_step_stats *stats)
+{
+    return run_impl(c, n, row_ptr, col_idx, deg, x, y, st, prm, 1, stats, true);
+}
+
+fl_status fl_fa2_run(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                     float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, int32_t iters,
+                     fl_step_stats *per_iter)
+{
+    return run_impl(c, n, row_ptr, col_idx, deg, x, y, st, prm, iters, per_iter, true);
+}
+
+}  // extern "C"

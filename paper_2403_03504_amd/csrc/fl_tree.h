@@ -1,0 +1,156 @@
+// Quadtree, neighbour/interaction lists and expansion storage shared by the
+// FMM kernels.  Layout (all structure-of-arrays in HBM, sized by provable
+// capacities so no kernel can overflow and nothing is read back to the host
+// inside an iteration):
+//
+//   part[n]     float4 (x, y, mass, original index as int bits), Morton order
+//   skey[n]     uint32 Morton keys, sorted
+//   cells       depth-first pre-order (sorted by (begin, level)); per cell:
+//               level, ixy (ix | iy << 16), begin, end, parent, child (int4,
+//               -1 = empty quadrant), leafidx (-1 for internal cells)
+//   leaves      leaf_cell[nleaves] in Morton order (a leaf's index = the
+//               index of its first particle among the "cell-start" particles)
+//   hash        (level, ix, iy) -> cell id, open addressing, epoch-tagged
+//   lists       V (M2L) and X (P2L) per cell; U (P2P) and W (M2P) per leaf;
+//               offsets are packed int64 pairs (lo = first list, hi = second)
+//   M, Lp       outgoing / partial incoming expansions, (p+1) float2 per
+//               cell, scaled by the cell width (coefficient k of an outgoing
+//               expansion holds a_k / w^k, of an incoming one b_k * w^k)
+#pragma once
+
+#include "fl_common.h"
+
+namespace fl {
+
+struct TreeBufs {
+    int n = 0, bits = 16, leaf = 64;
+    int64_t cells_cap = 0, leaves_cap = 0, hash_cap = 0;
+    double *root = nullptr;      // [4] xmin, ymin, L, S
+    float4 *part = nullptr;      // [n]
+    uint32_t *skey = nullptr;    // [n]
+    int32_t *lvl = nullptr;      // [cells_cap]
+    uint32_t *ixy = nullptr;
+    int32_t *beg = nullptr, *end = nullptr, *par = nullptr, *leafidx = nullptr;
+    int4 *child = nullptr;
+    int32_t *leaf_cell = nullptr;  // [leaves_cap]
+    uint32_t *start_key = nullptr;
+    int32_t *start_pos = nullptr, *start_D = nullptr;
+    int32_t *counts = nullptr;     // [0] cells, [1] leaves, [2] max level, [3] error bits
+    uint64_t *hkey = nullptr;
+    int32_t *hval = nullptr;
+    uint32_t *epoch = nullptr;     // device epoch of the hash table
+    int64_t *off2 = nullptr;       // per particle (cells, starts) packed prefix
+    int32_t *pack = nullptr;       // per particle (D+1) | lambda << 8
+};
+
+struct ListBufs {
+    int64_t v_cap = 0, x_cap = 0, u_cap = 0, w_cap = 0;
+    int64_t *offVX = nullptr;  // [cells_cap + 1]
+    int64_t *offUW = nullptr;  // [leaves_cap + 1]
+    int32_t *V = nullptr, *X = nullptr, *U = nullptr, *W = nullptr;
+};
+
+// Device view used by the kernels.
+struct TreeView {
+    int n, bits, leaf;
+    const double *root;
+    const float4 *part;
+    const int32_t *lvl;
+    const uint32_t *ixy;
+    const int32_t *beg, *end, *par, *leafidx;
+    const int4 *child;
+    const int32_t *leaf_cell;
+    const int32_t *counts;
+    const uint64_t *hkey;
+    const int32_t *hval;
+    const uint32_t *epoch;
+    int64_t hash_cap;
+};
+
+inline TreeView view(const TreeBufs &t)
+{
+    return TreeView{t.n,   t.bits,      t.leaf,  t.root,   t.part,  t.lvl,  t.ixy,  t.beg,  t.end,
+                    t.par, t.leafidx,   t.child, t.leaf_cell, t.counts, t.hkey, t.hval, t.epoch, t.hash_cap};
+}
+
+// Capacities that no input can exceed (see the capacity notes in fl_tree.hip).
+int64_t cells_capacity(int64_t n, int leaf, int bits);
+
+// bbox -> Morton keys -> stable sort -> sorted particles -> tree.  mass may be
+// null (unit masses).  All on the context stream, no host synchronisation.
+void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *y, const int32_t *deg, int bits,
+                int leaf);
+void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L);
+// Sticky capacity-guard bits of the tree/list kernels (synchronises).
+int32_t tree_error_bits(fl_ctx *c, bool clear);
+
+void fill_i32(fl_ctx *c, int32_t *p, int64_t n, int32_t v);
+int32_t read_i32(fl_ctx *c, const int32_t *dp);
+int64_t read_i64(fl_ctx *c, const int64_t *dp);
+
+// ---- geometry helpers (device) ---------------------------------------------
+__device__ __forceinline__ int cell_ix(uint32_t v) { return (int)(v & 0xFFFFu); }
+__device__ __forceinline__ int cell_iy(uint32_t v) { return (int)(v >> 16); }
+
+__device__ __forceinline__ bool is_leaf4(int4 ch) { return ch.x < 0 && ch.y < 0 && ch.z < 0 && ch.w < 0; }
+
+// Closed squares of two distinct, non-nested cells touch.
+__device__ __forceinline__ bool cells_adjacent(int la, uint32_t a, int lb, uint32_t b)
+{
+    int L = la > lb ? la : lb;
+    int sa = 1 << (L - la), sb = 1 << (L - lb);
+    int ax0 = cell_ix(a) * sa, ay0 = cell_iy(a) * sa;
+    int bx0 = cell_ix(b) * sb, by0 = cell_iy(b) * sb;
+    return ax0 <= bx0 + sb && bx0 <= ax0 + sa && ay0 <= by0 + sb && by0 <= ay0 + sa;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z ^= z >> 33;
+    z *= 0xff51afd7ed558ccdull;
+    z ^= z >> 33;
+    z *= 0xc4ceb9fe1a85ec53ull;
+    z ^= z >> 33;
+    return z;
+}
+
+__device__ __forceinline__ uint64_t hash_key(int level, int ix, int iy)
+{
+    return ((uint64_t)level << 32) | ((uint64_t)(uint32_t)ix << 16) | (uint64_t)(uint32_t)iy;
+}
+
+__device__ __forceinline__ int64_t hash_size(int ncells, int64_t cap)
+{
+    int64_t h = 64;
+    while (h < 2 * (int64_t)ncells) h <<= 1;
+    return h < cap ? h : cap;
+}
+
+// cell id of region (level, ix, iy), or -1 if no cell of that exact region
+__device__ __forceinline__ int hash_find(const TreeView &t, int64_t H, uint64_t ep, int level, int ix, int iy)
+{
+    uint64_t k = hash_key(level, ix, iy) | (ep << 37);
+    int64_t h = (int64_t)(mix64(k & ((1ull << 37) - 1)) & (uint64_t)(H - 1));
+    for (int64_t probe = 0; probe < H; ++probe) {
+        uint64_t v = t.hkey[h];
+        if ((v >> 37) != ep) return -1;
+        if (v == k) return t.hval[h];
+        h = (h + 1) & (H - 1);
+    }
+    return -1;
+}
+
+// Deepest cell on the path to region (level, ix, iy): the region's own cell,
+// else the leaf that covers it; -1 when the region holds no particle.
+__device__ __forceinline__ int lookup_region(const TreeView &t, int64_t H, uint64_t ep, int level, int ix, int iy)
+{
+    for (int l = level; l >= 0; --l, ix >>= 1, iy >>= 1) {
+        int id = hash_find(t, H, ep, l, ix, iy);
+        if (id < 0) continue;
+        if (l == level) return id;
+        return is_leaf4(t.child[id]) ? id : -1;
+    }
+    return -1;
+}
+
+}  // namespace fl

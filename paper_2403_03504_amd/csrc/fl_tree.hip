@@ -1,0 +1,682 @@
+// Quadtree over the particles (paper sec. 3.2.1: a square covering all
+// particles, divided into four while it holds more than leaf_size of them)
+// and the neighbour / interaction lists of the FMM.
+//
+// Tree construction without per-level launches.  With K the sorted Morton
+// keys and cd(a, b) the number of leading base-4 digits two keys share:
+//   D(k)   = cd(K[k-1], K[k])            (k starts a new level-l region for l > D)
+//   W(j)   = cd(K[j], K[j+L])            (L = leaf_size)
+//   lam(k) = min(B, 1 + max_{j in [k-L, k]} W(j))
+// A level-l region holding particle k has more than L particles iff some
+// window of L+1 consecutive sorted particles containing k shares its level-l
+// prefix, i.e. iff l <= max W over the windows through k.  So lam(k) is the
+// level of the leaf holding k, and particle k begins exactly the cells of
+// levels D(k)+1 .. lam(k).  A prefix sum of max(0, lam - D) numbers every cell
+// in (begin, level) order, which is depth-first pre-order.  The windowed
+// maximum uses log2(L+1) doubling rounds in LDS.
+//
+// Capacity notes (no kernel can write past them):
+//   cells  <= 1 + 4 B floor(n / (L+1))  (a split cell holds > L particles and
+//            split cells of one level are disjoint), and <= 1 + B n;
+//   V(c)   <= 27 (same-level cells in the parent's 6x6 block minus c's 3x3);
+//   X(c)   <= 8 (one covering leaf per ring square of the parent);
+//   sum |W| = sum |X| (W and X are dual) <= 8 cells;
+//   sum |U| <= 17 leaves (a leaf touches at most 8 cells at least its size).
+#include "fl_tree.h"
+
+namespace fl {
+
+int64_t cells_capacity(int64_t n, int leaf, int bits)
+{
+    int64_t a = 1 + 4 * (int64_t)bits * (n / ((int64_t)leaf + 1));
+    int64_t b = 1 + (int64_t)bits * n;
+    int64_t c = a < b ? a : b;
+    return c < 1 ? 1 : c;
+}
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ uint32_t part1by1(uint32_t v)
+{
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact1by1(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+    v = (v | (v >> 4)) & 0x00FF00FFu;
+    v = (v | (v >> 8)) & 0x0000FFFFu;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t quantize(float v, double vmin, double S, int bits)
+{
+    double t = floor(__dmul_rn(__dsub_rn((double)v, vmin), S));
+    double top = (double)((1u << bits) - 1u);
+    if (!(t >= 0.0)) t = 0.0;  // also maps NaN to 0
+    if (t > top) t = top;
+    return (uint32_t)t;
+}
+
+// common leading base-4 digits of two keys of 2*bits bits
+__device__ __forceinline__ int common_digits(uint32_t a, uint32_t b, int bits)
+{
+    uint32_t x = a ^ b;
+    if (x == 0) return bits;
+    int lz = __clz((int)x) - (32 - 2 * bits);
+    return lz >> 1;
+}
+
+// ---- bbox + root square (last block finalises; deterministic) -------------
+constexpr int BB_BLOCKS = 256;
+
+__global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const float *__restrict__ y, int n,
+                                             float4 *__restrict__ partial, unsigned *__restrict__ ticket,
+                                             double *__restrict__ root, int bits, uint32_t *__restrict__ epoch)
+{
+    __shared__ float4 red[NT / WAVE];
+    __shared__ int is_last;
+    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        float a = x[i], b = y[i];
+        mnx = fminf(mnx, a);
+        mxx = fmaxf(mxx, a);
+        mny = fminf(mny, b);
+        mxy = fmaxf(mxy, b);
+    }
+    mnx = wave_min_f(mnx);
+    mxx = wave_max_f(mxx);
+    mny = wave_min_f(mny);
+    mxy = wave_max_f(mxy);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = make_float4(mnx, mxx, mny, mxy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float4 r = red[0];
+        for (int w = 1; w < NT / WAVE; ++w) {
+            r.x = fminf(r.x, red[w].x);
+            r.y = fmaxf(r.y, red[w].y);
+            r.z = fminf(r.z, red[w].z);
+            r.w = fmaxf(r.w, red[w].w);
+        }
+        partial[blockIdx.x] = r;
+        __threadfence();
+        unsigned t = atomicAdd(ticket, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    if (threadIdx.x == 0) {
+        float4 r = partial[0];
+        for (unsigned b = 1; b < gridDim.x; ++b) {
+            float4 q = partial[b];
+            r.x = fminf(r.x, q.x);
+            r.y = fmaxf(r.y, q.y);
+            r.z = fminf(r.z, q.z);
+            r.w = fmaxf(r.w, q.w);
+        }
+        double x0 = r.x, x1 = r.y, y0 = r.z, y1 = r.w;
+        double L = (x1 - x0) > (y1 - y0) ? (x1 - x0) : (y1 - y0);
+        if (!(L > 0.0)) L = 1.0;
+        if (!isfinite(x0)) x0 = 0.0;
+        if (!isfinite(y0)) y0 = 0.0;
+        if (!isfinite(L)) L = 1.0;
+        root[0] = x0;
+        root[1] = y0;
+        root[2] = L;
+        root[3] = __ddiv_rn(ldexp(1.0, bits), L);
+        uint32_t e = *epoch + 1u;
+        if (e >= (1u << 27) || e == 0u) e = 1u;
+        *epoch = e;
+        *ticket = 0u;
+    }
+}
+
+__global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, int n,
+                         const double *__restrict__ root, int bits, uint32_t *__restrict__ key,
+                         int32_t *__restrict__ idx)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x0 = root[0], y0 = root[1], S = root[3];
+    uint32_t qx = quantize(x[i], x0, S, bits), qy = quantize(y[i], y0, S, bits);
+    key[i] = part1by1(qx) | (part1by1(qy) << 1);
+    if (idx) idx[i] = i;
+}
+
+__global__ void k_gather(const float *__restrict__ x, const float *__restrict__ y, const int32_t *__restrict__ deg,
+                         const int32_t *__restrict__ perm, int n, float4 *__restrict__ part)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int i = perm[k];
+    float m = deg ? (float)(deg[i] + 1) : 1.0f;
+    part[k] = make_float4(x[i], y[i], m, __int_as_float(i));
+}
+
+// ---- tree: levels per particle ----------------------------------------------
+constexpr int T1_TB = 1024;
+constexpr int T1_MAXL = 1024;  // largest leaf size supported
+constexpr int T1_LEN = T1_TB + T1_MAXL;
+constexpr int T1_PER = T1_LEN / NT;
+
+__global__ __launch_bounds__(NT) void k_tree_levels(const uint32_t *__restrict__ K, int n, int bits, int L,
+                                                    int32_t *__restrict__ pack, int64_t *__restrict__ cnt2)
+{
+    __shared__ int A[T1_LEN];
+    const int t0 = blockIdx.x * T1_TB;
+    const int base = t0 - L;
+    const int len = T1_TB + L;
+    for (int i = threadIdx.x; i < len; i += NT) {
+        int j = base + i;
+        A[i] = (j >= 0 && j + L < n) ? common_digits(K[j], K[j + L], bits) : -1;
+    }
+    const int w = L + 1;
+    int s = 1;
+    while (2 * s <= w) s <<= 1;
+    for (int h = 1; h < s; h <<= 1) {
+        int v[T1_PER];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < T1_PER; ++r) {
+            int i = threadIdx.x + r * NT;
+            int a = -1;
+            if (i < len) {
+                a = A[i];
+                if (i + h < len) a = max(a, A[i + h]);
+            }
+            v[r] = a;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < T1_PER; ++r) {
+            int i = threadIdx.x + r * NT;
+            if (i < len) A[i] = v[r];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < T1_TB; t += NT) {
+        int k = t0 + t;
+        if (k >= n) break;
+        int mx = max(A[t], A[t + w - s]);
+        int lam = min(bits, 1 + mx);
+        int D = (k == 0) ? -1 : common_digits(K[k - 1], K[k], bits);
+        int c = lam - D;
+        if (c < 0) c = 0;
+        pack[k] = (D + 1) | (lam << 8);
+        cnt2[k] = (int64_t)c | ((int64_t)(c > 0 ? 1 : 0) << 32);
+    }
+}
+
+__device__ __forceinline__ uint32_t region_prefix(uint32_t key, int level, int bits)
+{
+    return level == 0 ? 0u : (key >> (2 * (bits - level)));
+}
+
+__global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, const int32_t *__restrict__ pack,
+                             const int64_t *__restrict__ off2, TreeBufs t)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int pk = pack[k];
+    int D = (pk & 0xFF) - 1, lam = pk >> 8;
+    if (lam - D <= 0) return;
+    int64_t o = off2[k];
+    int cid0 = (int)(o & 0xFFFFFFFFll), li = (int)(o >> 32);
+    int64_t tot = off2[n];
+    int ncells = (int)(tot & 0xFFFFFFFFll), nleaves = (int)(tot >> 32);
+    if (ncells > t.cells_cap || nleaves > t.leaves_cap) {
+        // cannot happen (see the capacity notes); refuse rather than overrun
+        if (k == 0) {
+            t.counts[0] = 0;
+            t.counts[1] = 0;
+            t.counts[3] = 1;
+        }
+        return;
+    }
+    uint32_t key = K[k];
+    t.start_pos[li] = k;
+    t.start_key[li] = key;
+    t.start_D[li] = D;
+    t.leaf_cell[li] = cid0 + (lam - D - 1);
+    if (k == 0) {
+        t.counts[0] = ncells;
+        t.counts[1] = nleaves;
+    }
+    atomicMax(&t.counts[2], lam);
+    const int64_t H = hash_size(ncells, t.hash_cap);
+    const uint64_t ep = *t.epoch;
+    for (int l = D + 1; l <= lam; ++l) {
+        int id = cid0 + (l - D - 1);
+        uint32_t pre = region_prefix(key, l, bits);
+        int ix = (int)compact1by1(pre), iy = (int)compact1by1(pre >> 1);
+        t.lvl[id] = l;
+        t.ixy[id] = (uint32_t)ix | ((uint32_t)iy << 16);
+        t.beg[id] = k;
+        t.child[id] = make_int4(-1, -1, -1, -1);
+        t.leafidx[id] = (l == lam) ? li : -1;
+        t.par[id] = (l == 0) ? -1 : (l - 1 > D ? id - 1 : -2);
+        // insert (l, ix, iy) -> id
+        uint64_t hk = hash_key(l, ix, iy);
+        uint64_t kk = hk | (ep << 37);
+        int64_t h = (int64_t)(mix64(hk) & (uint64_t)(H - 1));
+        for (int64_t probe = 0; probe < H; ++probe) {
+            uint64_t old = t.hkey[h];
+            if ((old >> 37) == ep) {
+                h = (h + 1) & (H - 1);
+                continue;
+            }
+            unsigned long long prev = atomicCAS((unsigned long long *)&t.hkey[h], (unsigned long long)old,
+                                                (unsigned long long)kk);
+            if (prev == old) {
+                t.hval[h] = id;
+                break;
+            }
+            --probe;  // lost the slot to another insert: look at it again
+        }
+    }
+}
+
+__device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int n, uint64_t v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((uint64_t)a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, const int64_t *__restrict__ off2,
+                             TreeBufs t)
+{
+    int id = blockIdx.x * blockDim.x + threadIdx.x;
+    int ncells = t.counts[0];
+    if (id >= ncells) return;
+    int nleaves = t.counts[1];
+    int l = t.lvl[id];
+    if (l == 0) {
+        t.end[id] = n;
+        return;
+    }
+    int k = t.beg[id];
+    uint32_t pre = region_prefix(K[k], l, bits);
+    int sh = 2 * (bits - l);
+    uint64_t T = ((uint64_t)pre + 1ull) << sh;
+    int j = lower_bound_u32(t.start_key, nleaves, T);
+    t.end[id] = j < nleaves ? t.start_pos[j] : n;
+    int p = t.par[id];
+    if (p == -2) {
+        uint64_t Tp = (uint64_t)(pre >> 2) << (sh + 2);
+        int jp = lower_bound_u32(t.start_key, nleaves, Tp);
+        if (jp >= nleaves) {
+            atomicOr(&t.counts[3], 2);
+            return;
+        }
+        int bp = t.start_pos[jp];
+        int Dp = t.start_D[jp];
+        int cid0 = (int)(off2[bp] & 0xFFFFFFFFll);
+        p = cid0 + (l - 1 - Dp - 1);
+        t.par[id] = p;
+    }
+    if (p < 0 || p >= ncells) {
+        atomicOr(&t.counts[3], 2);
+        return;
+    }
+    reinterpret_cast<int *>(&t.child[p])[pre & 3u] = id;
+}
+
+// ---- lists ------------------------------------------------------------------
+struct CountSink {
+    int nV = 0, nX = 0, nU = 0, nW = 0;
+    __device__ void V(int) { ++nV; }
+    __device__ void X(int) { ++nX; }
+    __device__ void U(int) { ++nU; }
+    __device__ void W(int) { ++nW; }
+};
+
+struct FillSink {
+    int32_t *pV, *pX, *pU, *pW;
+    int nV = 0, nX = 0, nU = 0, nW = 0;
+    __device__ void V(int s) { pV[nV++] = s; }
+    __device__ void X(int s) { pX[nX++] = s; }
+    __device__ void U(int s) { pU[nU++] = s; }
+    __device__ void W(int s) { pW[nW++] = s; }
+};
+
+template <class Sink>
+__device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c, Sink &sk)
+{
+    const int l = t.lvl[c];
+    const uint32_t cxy = t.ixy[c];
+    const int cx = cell_ix(cxy), cy = cell_iy(cxy);
+    // V and X: the parent's ring (interacting cells)
+    if (l >= 2) {
+        const int pl = l - 1, px = cx >> 1, py = cy >> 1, pside = 1 << pl;
+        int seen[8];
+        int ns = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                int rx = px + dx, ry = py + dy;
+                if (rx < 0 || ry < 0 || rx >= pside || ry >= pside) continue;
+                int N = lookup_region(t, H, ep, pl, rx, ry);
+                if (N < 0) continue;
+                int4 ch = t.child[N];
+                if (!is_leaf4(ch)) {
+                    // N is the same-level neighbour of the parent, subdivided
+                    int cc[4] = {ch.x, ch.y, ch.z, ch.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int s = cc[q];
+                        if (s >= 0 && !cells_adjacent(l, t.ixy[s], l, cxy)) sk.V(s);
+                    }
+                } else {
+                    bool dup = false;
+                    for (int i = 0; i < ns; ++i) dup |= (seen[i] == N);
+                    if (!dup && !cells_adjacent(t.lvl[N], t.ixy[N], l, cxy)) {
+                        seen[ns++] = N;
+                        sk.X(N);
+                    }
+                }
+            }
+    }
+    // U and W for leaves: neighbours and the far parts of subdivided ones
+    if (is_leaf4(t.child[c])) {
+        sk.U(c);
+        const int side = 1 << l;
+        int seen[8];
+        int ns = 0;
+        int stack[64];
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                int rx = cx + dx, ry = cy + dy;
+                if (rx < 0 || ry < 0 || rx >= side || ry >= side) continue;
+                int N = lookup_region(t, H, ep, l, rx, ry);
+                if (N < 0) continue;
+                int4 ch = t.child[N];
+                if (is_leaf4(ch)) {
+                    bool dup = false;
+                    for (int i = 0; i < ns; ++i) dup |= (seen[i] == N);
+                    if (!dup) {
+                        seen[ns++] = N;
+                        sk.U(N);
+                    }
+                    continue;
+                }
+                int sp = 0;
+                stack[sp++] = N;
+                while (sp > 0) {
+                    int d = stack[--sp];
+                    int4 dc = t.child[d];
+                    int cc[4] = {dc.x, dc.y, dc.z, dc.w};
+                    for (int q = 0; q < 4; ++q) {
+                        int s = cc[q];
+                        if (s < 0) continue;
+                        if (cells_adjacent(t.lvl[s], t.ixy[s], l, cxy)) {
+                            if (is_leaf4(t.child[s])) sk.U(s);
+                            else if (sp < 64) stack[sp++] = s;
+                        } else {
+                            sk.W(s);
+                        }
+                    }
+                }
+            }
+    }
+}
+
+__global__ void k_lists_count(TreeView t, int64_t *__restrict__ cntVX, int64_t *__restrict__ cntUW)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= t.counts[0]) return;
+    const int64_t H = hash_size(t.counts[0], t.hash_cap);
+    const uint64_t ep = *t.epoch;
+    CountSink sk;
+    enumerate_lists(t, H, ep, c, sk);
+    cntVX[c] = (int64_t)sk.nV | ((int64_t)sk.nX << 32);
+    int li = t.leafidx[c];
+    if (li >= 0) cntUW[li] = (int64_t)sk.nU | ((int64_t)sk.nW << 32);
+}
+
+__global__ void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX, const int64_t *__restrict__ offUW,
+                             int32_t *__restrict__ V, int32_t *__restrict__ X, int32_t *__restrict__ U,
+                             int32_t *__restrict__ W, unsigned long long *__restrict__ near_pairs, int64_t cap,
+                             int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap, int64_t w_cap,
+                             int32_t *__restrict__ err)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long pairs = 0;
+    const int64_t tvx = offVX[cap], tuw = offUW[lcap];
+    const bool fits = (tvx & 0xFFFFFFFFll) <= v_cap && (tvx >> 32) <= x_cap && (tuw & 0xFFFFFFFFll) <= u_cap &&
+                      (tuw >> 32) <= w_cap;
+    if (!fits && c == 0) atomicOr(err, 4);
+    if (fits && c < t.counts[0]) {
+        const int64_t H = hash_size(t.counts[0], t.hash_cap);
+        const uint64_t ep = *t.epoch;
+        int64_t o = offVX[c];
+        int li = t.leafidx[c];
+        int64_t ou = li >= 0 ? offUW[li] : 0;
+        FillSink sk{V + (o & 0xFFFFFFFFll), X + (o >> 32), U + (ou & 0xFFFFFFFFll), W + (ou >> 32)};
+        enumerate_lists(t, H, ep, c, sk);
+        if (li >= 0) {
+            int64_t src = 0;
+            for (int i = 0; i < sk.nU; ++i) src += t.end[sk.pU[i]] - t.beg[sk.pU[i]];
+            pairs = (unsigned long long)src * (unsigned long long)(t.end[c] - t.beg[c]);
+        }
+    }
+    pairs = wave_sum(pairs);
+    if (lane_id() == 0 && pairs) atomicAdd(near_pairs, pairs);
+}
+
+__global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t *__restrict__ totVX,
+                              const int64_t *__restrict__ totUW, int64_t *__restrict__ st)
+{
+    st[0] = counts[0];
+    st[1] = counts[1];
+    st[3] = *totVX & 0xFFFFFFFFll;
+    st[5] = *totVX >> 32;
+    st[7] = *totUW & 0xFFFFFFFFll;
+    st[4] = *totUW >> 32;
+    st[6] = counts[2];
+}
+
+__global__ void k_export_cells(TreeView t, int32_t *__restrict__ out, int cap)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= t.counts[0] || c >= cap) return;
+    int32_t *o = out + 10 * (int64_t)c;
+    uint32_t v = t.ixy[c];
+    int4 ch = t.child[c];
+    o[0] = t.lvl[c];
+    o[1] = cell_ix(v);
+    o[2] = cell_iy(v);
+    o[3] = t.beg[c];
+    o[4] = t.end[c];
+    o[5] = t.par[c];
+    o[6] = ch.x;
+    o[7] = ch.y;
+    o[8] = ch.z;
+    o[9] = ch.w;
+}
+
+}  // namespace
+
+void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *y, const int32_t *deg, int bits,
+                int leaf)
+{
+    t.n = n;
+    t.bits = bits;
+    t.leaf = leaf;
+    t.cells_cap = cells_capacity(n, leaf, bits);
+    t.leaves_cap = t.cells_cap < n ? t.cells_cap : n;
+    int64_t hc = 64;
+    while (hc < 2 * t.cells_cap) hc <<= 1;
+    t.hash_cap = hc;
+    const int64_t cap = t.cells_cap, lcap = t.leaves_cap;
+
+    t.root = ws<double>(c, "t_root", 4);
+    float4 *bpart = ws<float4>(c, "t_bbox_part", BB_BLOCKS);
+    unsigned *ticket = ws_zeroed<unsigned>(c, "t_ticket", 4);
+    t.epoch = ws_zeroed<uint32_t>(c, "t_epoch", 4);
+    uint32_t *k0 = ws<uint32_t>(c, "t_key0", n);
+    uint32_t *k1 = ws<uint32_t>(c, "t_key1", n);
+    int32_t *i0 = ws<int32_t>(c, "t_idx0", n);
+    int32_t *i1 = ws<int32_t>(c, "t_idx1", n);
+    t.part = ws<float4>(c, "t_part", n);
+    t.lvl = ws<int32_t>(c, "t_lvl", cap);
+    t.ixy = ws<uint32_t>(c, "t_ixy", cap);
+    t.beg = ws<int32_t>(c, "t_beg", cap);
+    t.end = ws<int32_t>(c, "t_end", cap);
+    t.par = ws<int32_t>(c, "t_par", cap);
+    t.leafidx = ws<int32_t>(c, "t_leafidx", cap);
+    t.child = ws<int4>(c, "t_child", cap);
+    t.leaf_cell = ws<int32_t>(c, "t_leafcell", lcap);
+    t.start_key = ws<uint32_t>(c, "t_skey_start", lcap);
+    t.start_pos = ws<int32_t>(c, "t_spos", lcap);
+    t.start_D = ws<int32_t>(c, "t_sD", lcap);
+    t.counts = ws_zeroed<int32_t>(c, "t_counts", 4);
+    t.hkey = ws_zeroed<uint64_t>(c, "t_hkey", hc);
+    t.hval = ws<int32_t>(c, "t_hval", hc);
+    t.pack = ws<int32_t>(c, "t_pack", n);
+    int64_t *cnt2 = ws<int64_t>(c, "t_cnt2", n);
+    t.off2 = ws<int64_t>(c, "t_off2", (size_t)n + 1);
+
+    int nb = (int)grid_for(n, NT, BB_BLOCKS);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(NT), 0, c->stream, x, y, n, bpart, ticket, t.root, bits, t.epoch);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, t.root, bits, k0, i0);
+    FL_LAUNCH_CHECK();
+    bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits);
+    uint32_t *sk = alt ? k1 : k0;
+    int32_t *perm = alt ? i1 : i0;
+    t.skey = sk;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, deg, perm, n, t.part);
+    FL_CHECK_HIP(hipMemsetAsync(t.counts, 0, 3 * sizeof(int32_t), c->stream));  // [3] (error bits) is sticky
+    hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, sk, n, bits, leaf, t.pack,
+                       cnt2);
+    FL_LAUNCH_CHECK();
+    scan_excl_i64(c, cnt2, t.off2, n);
+    hipLaunchKernelGGL(k_tree_cells, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, sk, n, bits, t.pack, t.off2, t);
+    hipLaunchKernelGGL(k_tree_links, dim3(grid_for(cap, NT)), dim3(NT), 0, c->stream, sk, n, bits, t.off2, t);
+    FL_LAUNCH_CHECK();
+}
+
+void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
+{
+    const int64_t cap = t.cells_cap, lcap = t.leaves_cap;
+    L.v_cap = 27 * cap;
+    L.x_cap = 8 * cap;
+    L.w_cap = 8 * cap;
+    L.u_cap = 17 * lcap;
+    int64_t *cntVX = ws<int64_t>(c, "l_cntVX", cap);
+    int64_t *cntUW = ws<int64_t>(c, "l_cntUW", lcap);
+    L.offVX = ws<int64_t>(c, "l_offVX", cap + 1);
+    L.offUW = ws<int64_t>(c, "l_offUW", lcap + 1);
+    L.V = ws<int32_t>(c, "l_V", L.v_cap);
+    L.X = ws<int32_t>(c, "l_X", L.x_cap);
+    L.U = ws<int32_t>(c, "l_U", L.u_cap);
+    L.W = ws<int32_t>(c, "l_W", L.w_cap);
+    TreeView tv = view(t);
+    hipLaunchKernelGGL(k_lists_count, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, cntVX, cntUW);
+    FL_LAUNCH_CHECK();
+    scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
+    scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
+    FL_CHECK_HIP(hipMemsetAsync(c->d_stats + 2, 0, sizeof(int64_t), c->stream));
+    hipLaunchKernelGGL(k_lists_fill, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, L.offVX, L.offUW, L.V,
+                       L.X, L.U, L.W, (unsigned long long *)(c->d_stats + 2), cap, lcap, L.v_cap, L.x_cap, L.u_cap,
+                       L.w_cap, t.counts + 3);
+    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, L.offVX + cap, L.offUW + lcap,
+                       c->d_stats);
+    FL_LAUNCH_CHECK();
+}
+
+int32_t tree_error_bits(fl_ctx *c, bool clear)
+{
+    int32_t *counts = ws_zeroed<int32_t>(c, "t_counts", 4);
+    int32_t v = read_i32(c, counts + 3);
+    if (clear) FL_CHECK_HIP(hipMemsetAsync(counts + 3, 0, sizeof(int32_t), c->stream));
+    return v;
+}
+
+void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits, uint32_t *key, double *root_out)
+{
+    double *root = root_out ? root_out : ws<double>(c, "t_root", 4);
+    float4 *bpart = ws<float4>(c, "t_bbox_part", BB_BLOCKS);
+    unsigned *ticket = ws_zeroed<unsigned>(c, "t_ticket", 4);
+    uint32_t *epoch = ws_zeroed<uint32_t>(c, "t_epoch", 4);
+    int nb = (int)grid_for(n, NT, BB_BLOCKS);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(NT), 0, c->stream, x, y, n, bpart, ticket, root, bits, epoch);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, root, bits, key,
+                       (int32_t *)nullptr);
+    FL_LAUNCH_CHECK();
+}
+
+__global__ void k_iota(int32_t *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+fl_status fl_morton(fl_ctx *c, int32_t n, const float *x, const float *y, int32_t bits, uint32_t *key, double *root4)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(n >= 1 && x && y && key, "fl_morton: need n >= 1 and non-null arrays");
+    FL_REQUIRE(bits >= 1 && bits <= 16, "fl_morton: bits must be in [1, 16]");
+    morton_keys(c, n, x, y, bits, key, root4);
+    FL_API_END(c)
+}
+
+fl_status fl_sort_keys(fl_ctx *c, int32_t n, const uint32_t *key, int32_t bits, uint32_t *key_out, int32_t *perm)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(n >= 1 && key && key_out && perm, "fl_sort_keys: need n >= 1 and non-null arrays");
+    FL_REQUIRE(bits >= 1 && bits <= 16, "fl_sort_keys: bits must be in [1, 16]");
+    uint32_t *kt = ws<uint32_t>(c, "sk_kt", n);
+    int32_t *vt = ws<int32_t>(c, "sk_vt", n);
+    FL_CHECK_HIP(hipMemcpyAsync(key_out, key, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, perm, n);
+    FL_LAUNCH_CHECK();
+    bool alt = radix_sort_u32(c, key_out, perm, kt, vt, n, 2 * bits);
+    if (alt) {
+        FL_CHECK_HIP(hipMemcpyAsync(key_out, kt, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+        FL_CHECK_HIP(hipMemcpyAsync(perm, vt, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    FL_API_END(c)
+}
+
+fl_status fl_tree(fl_ctx *c, int32_t n, const float *x, const float *y, int32_t bits, int32_t leaf_size,
+                  int32_t *cells, int32_t cap, int32_t *n_cells_out)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(n >= 1 && x && y && cells && cap >= 0, "fl_tree: need n >= 1 and non-null arrays");
+    FL_REQUIRE(bits >= 1 && bits <= 16, "fl_tree: bits must be in [1, 16]");
+    FL_REQUIRE(leaf_size >= 1 && leaf_size <= 1024, "fl_tree: leaf_size must be in [1, 1024]");
+    TreeBufs t;
+    build_tree(c, t, n, x, y, nullptr, bits, leaf_size);
+    TreeView tv = view(t);
+    hipLaunchKernelGGL(k_export_cells, dim3(grid_for(t.cells_cap, 256)), dim3(256), 0, c->stream, tv, cells, cap);
+    FL_LAUNCH_CHECK();
+    int32_t nc = read_i32(c, t.counts);
+    if (tree_error_bits(c, true)) throw Error(FL_EHIP, "fl_tree: capacity guard tripped");
+    if (n_cells_out) *n_cells_out = nc;
+    FL_REQUIRE(nc <= cap, "fl_tree: output capacity too small");
+    FL_API_END(c)
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+"""Thin Python binding of libfa2lay.so (the C ABI in include/fa2lay.h).
+
+Argument marshalling only: every step of the layout runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.  There is
+no CPU fallback: importing this module raises if the library is not built, and
+every call raises ``FlError`` on a non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfa2lay.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2403_03504_amd.build` "
+                      "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENONFINITE, FL_EBUSY, FL_ECANCELED, FL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+GRAV_STRONG_MASS, GRAV_FA2_CONST, GRAV_STRONG_UNIT = 0, 1, 2
+SWING_PAPER, SWING_FA2 = 0, 1
+REP_EXACT, REP_FMM = 0, 1
+PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact")
+
+EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
+            "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
+            "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_run", "fl_fmm_stats",
+            "fl_set_timing", "fl_get_timing")
+
+
+class FlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class FA2Params(ctypes.Structure):
+    _fields_ = [("kr", ctypes.c_double), ("kg", ctypes.c_double), ("ka", ctypes.c_double),
+                ("gravity_mode", ctypes.c_int32), ("swing_mode", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("ks", ctypes.c_double), ("ksmax", ctypes.c_double),
+                ("max_rise", ctypes.c_double), ("repulsion", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("morton_bits", ctypes.c_int32)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("fx_prev", ctypes.c_void_p), ("fy_prev", ctypes.c_void_p), ("scalars", ctypes.c_void_p),
+                ("iter", ctypes.c_int64)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("swg", ctypes.c_double), ("tra", ctypes.c_double), ("speed", ctypes.c_double)]
+
+
+P = ctypes.c_void_p
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+_sig = {
+    "fl_create": ([ctypes.POINTER(P), ctypes.c_int, P], _i32),
+    "fl_destroy": ([P], None),
+    "fl_last_error": ([P], ctypes.c_char_p),
+    "fl_set_stream": ([P, P], _i32),
+    "fl_synchronize": ([P], _i32),
+    "fl_workspace_bytes": ([P], ctypes.c_size_t),
+    "fl_version": ([], ctypes.c_char_p),
+    "fl_build_csr": ([P, _i32, _i64, P, P, P, P, P, ctypes.POINTER(_i64)], _i32),
+    "fl_components": ([P, _i32, P, P, P, ctypes.POINTER(_i32)], _i32),
+    "fl_morton": ([P, _i32, P, P, _i32, P, P], _i32),
+    "fl_sort_keys": ([P, _i32, P, _i32, P, P], _i32),
+    "fl_tree": ([P, _i32, P, P, _i32, _i32, P, _i32, ctypes.POINTER(_i32)], _i32),
+    "fl_fa2_default_params": ([ctypes.POINTER(FA2Params)], None),
+    "fl_fa2_forces": ([P, _i32, P, P, P, P, P, ctypes.POINTER(FA2Params), P, P, P, P, P, P], _i32),
+    "fl_fa2_step": ([P, _i32, P, P, P, P, P, ctypes.POINTER(_State), ctypes.POINTER(FA2Params),
+                     ctypes.POINTER(StepStats)], _i32),
+    "fl_fa2_run": ([P, _i32, P, P, P, P, P, ctypes.POINTER(_State), ctypes.POINTER(FA2Params), _i32,
+                    ctypes.POINTER(StepStats)], _i32),
+    "fl_fmm_stats": ([P, ctypes.POINTER(_i64)], _i32),
+    "fl_set_timing": ([P, ctypes.c_int], _i32),
+    "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def version() -> str:
+    return _lib.fl_version().decode()
+
+
+def default_params(**kw) -> FA2Params:
+    p = FA2Params()
+    _lib.fl_fa2_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t: torch.Tensor | None, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class FA2State:
+    """Caller-owned iteration state (previous forces, device scalars, count)."""
+    fx_prev: torch.Tensor
+    fy_prev: torch.Tensor
+    scalars: torch.Tensor  # float64 [4]: s_G, SWG, TRA
+    iter: int = 0
+
+    @staticmethod
+    def zeros(n: int, device) -> "FA2State":
+        return FA2State(torch.zeros(n, dtype=torch.float32, device=device),
+                        torch.zeros(n, dtype=torch.float32, device=device),
+                        torch.zeros(4, dtype=torch.float64, device=device), 0)
+
+    def _c(self) -> _State:
+        return _State(self.fx_prev.data_ptr(), self.fy_prev.data_ptr(), self.scalars.data_ptr(), self.iter)
+
+
+class Graph:
+    """A CSR graph on the device (int32 row_ptr, col_idx, deg)."""
+
+    def __init__(self, n: int, row_ptr: torch.Tensor, col: torch.Tensor, deg: torch.Tensor):
+        self.n, self.row_ptr, self.col, self.deg = n, row_ptr, col, deg
+
+
+class Context:
+    """An fl_ctx bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._h = P()
+        self._check(_lib.fl_create(ctypes.byref(self._h), device, P(stream.cuda_stream)), "fl_create")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != FL_OK:
+            msg = _lib.fl_last_error(self._h).decode() if self._h else what
+            raise FlError(st, f"{what}: {msg}")
+
+    def set_stream(self, stream):
+        self._check(_lib.fl_set_stream(self._h, P(stream.cuda_stream)), "fl_set_stream")
+
+    def synchronize(self):
+        self._check(_lib.fl_synchronize(self._h), "fl_synchronize")
+
+    def workspace_bytes(self) -> int:
+        return int(_lib.fl_workspace_bytes(self._h))
+
+    # graph preparation ----------------------------------------------------
+    def build_csr(self, n: int, src: torch.Tensor, dst: torch.Tensor) -> Graph:
+        m = int(src.numel())
+        row_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(max(2 * m, 1), dtype=torch.int32, device=self.device)
+        deg = torch.empty(n, dtype=torch.int32, device=self.device)
+        nnz = _i64()
+        self._check(_lib.fl_build_csr(self._h, n, m, _ptr(src, torch.int32), _ptr(dst, torch.int32), _ptr(row_ptr),
+                                      _ptr(col), _ptr(deg), ctypes.byref(nnz)), "fl_build_csr")
+        return Graph(n, row_ptr, col[:max(nnz.value, 1)].contiguous() if nnz.value else col, deg)
+
+    def components(self, g: Graph):
+        label = torch.empty(g.n, dtype=torch.int32, device=self.device)
+        k = _i32()
+        self._check(_lib.fl_components(self._h, g.n, _ptr(g.row_ptr, torch.int32), _ptr(g.col, torch.int32),
+                                       _ptr(label), ctypes.byref(k)), "fl_components")
+        return label, int(k.value)
+
+    # quadtree hooks ----------------------------------------------------------
+    def morton(self, x: torch.Tensor, y: torch.Tensor, bits: int = 16):
+        n = x.numel()
+        key = torch.empty(n, dtype=torch.int32, device=self.device)  # uint32 bit patterns
+        root = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._check(_lib.fl_morton(self._h, n, _ptr(x, torch.float32), _ptr(y, torch.float32), bits, _ptr(key),
+                                   _ptr(root)), "fl_morton")
+        return key, root
+
+    def sort_keys(self, key: torch.Tensor, bits: int = 16):
+        n = key.numel()
+        out = torch.empty_like(key)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(_lib.fl_sort_keys(self._h, n, _ptr(key, torch.int32), bits, _ptr(out), _ptr(perm)),
+                    "fl_sort_keys")
+        return out, perm
+
+    def tree(self, x: torch.Tensor, y: torch.Tensor, bits: int = 16, leaf_size: int = 64, cap: int | None = None):
+        n = x.numel()
+        cap = cap if cap is not None else 4 * n + 16
+        cells = torch.empty(cap * 10, dtype=torch.int32, device=self.device)
+        nc = _i32()
+        self._check(_lib.fl_tree(self._h, n, _ptr(x, torch.float32), _ptr(y, torch.float32), bits, leaf_size,
+                                 _ptr(cells), cap, ctypes.byref(nc)), "fl_tree")
+        return cells[:10 * nc.value].view(nc.value, 10)
+
+    # ForceAtlas2 -------------------------------------------------------------
+    def fa2_forces(self, g: Graph, x: torch.Tensor, y: torch.Tensor, params: FA2Params, components=True):
+        n = g.n
+        out = {k: torch.empty(n, dtype=torch.float32, device=self.device) for k in ("frx", "fry")}
+        if components:
+            for k in ("fax", "fay", "fgx", "fgy"):
+                out[k] = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._check(_lib.fl_fa2_forces(self._h, n, _ptr(g.row_ptr, torch.int32), _ptr(g.col, torch.int32),
+                                       _ptr(g.deg, torch.int32), _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                       ctypes.byref(params), _ptr(out["frx"]), _ptr(out["fry"]),
+                                       _ptr(out.get("fax")), _ptr(out.get("fay")), _ptr(out.get("fgx")),
+                                       _ptr(out.get("fgy"))), "fl_fa2_forces")
+        return out
+
+    def fa2_step(self, g: Graph, x: torch.Tensor, y: torch.Tensor, state: FA2State, params: FA2Params,
+                 stats: bool = True):
+        cs = state._c()
+        st = StepStats()
+        self._check(_lib.fl_fa2_step(self._h, g.n, _ptr(g.row_ptr, torch.int32), _ptr(g.col, torch.int32),
+                                     _ptr(g.deg, torch.int32), _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                     ctypes.byref(cs), ctypes.byref(params), ctypes.byref(st) if stats else None),
+                    "fl_fa2_step")
+        state.iter = int(cs.iter)
+        return (st.swg, st.tra, st.speed) if stats else None
+
+    def fa2_run(self, g: Graph, x: torch.Tensor, y: torch.Tensor, state: FA2State, params: FA2Params, iters: int,
+                stats: bool = False):
+        cs = state._c()
+        arr = (StepStats * max(iters, 1))() if stats else None
+        self._check(_lib.fl_fa2_run(self._h, g.n, _ptr(g.row_ptr, torch.int32), _ptr(g.col, torch.int32),
+                                    _ptr(g.deg, torch.int32), _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                    ctypes.byref(cs), ctypes.byref(params), iters, arr), "fl_fa2_run")
+        state.iter = int(cs.iter)
+        if stats:
+            return [(a.swg, a.tra, a.speed) for a in arr[:iters]]
+        return None
+
+    def fmm_stats(self) -> dict:
+        out = (_i64 * 8)()
+        self._check(_lib.fl_fmm_stats(self._h, out), "fl_fmm_stats")
+        keys = ("cells", "leaves", "near_pairs", "v_entries", "w_entries", "x_entries", "max_level", "u_entries")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def set_timing(self, enable: bool):
+        self._check(_lib.fl_set_timing(self._h, 1 if enable else 0), "fl_set_timing")
+
+    def get_timing(self):
+        ms = (ctypes.c_double * len(PHASES))()
+        cnt = (_i64 * len(PHASES))()
+        self._check(_lib.fl_get_timing(self._h, ms, cnt), "fl_get_timing")
+        return {p: (ms[i], int(cnt[i])) for i, p in enumerate(PHASES)}

@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the FMM-ForceAtlas2 iteration on one MI355X.
+
+Workload: a synthetic bitcoin-like bipartite transaction graph of 2,000,000
+nodes (40 % transactions, Zipf(2) input/output counts capped at 20, 500 hub
+addresses of degree 5k-20k, re-attached into one component), positions
+uniform in a square, FP32.  A step is one full ForceAtlas2 iteration:
+Morton sort, quadtree, lists, FMM repulsion (P2M, M2M, M2L/P2L, L2L,
+L2P/M2P/P2P), CSR attraction, gravity, FP64 swing/traction sums, speed and
+update.  The metric is node-updates/s = nodes x iterations / wall time.
+
+Also reported (same JSON line): GPU exact-direct repulsion at the same size
+(the equal-accuracy comparator), the FMM's relative force error on a sampled
+node subset against the FP64 exact sum, the roofline of the dominant kernel
+(P2P/L2P/M2P evaluation, FP32 ALU) measured with HIP events over the timed
+region, and the FP64 CPU oracle's throughput on the same workload.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FA2 node-updates/s at 2M nodes (FMM vs direct, ≤1e-3 err); p50/p99 latency"
+FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9  # 78.6 TFLOP/s: FP32 FMA, packed FP32 disabled in this build
+FP32_PUBLISHED = 157.3e12                   # published FP32 vector peak (needs packed FP32)
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nodes", type=int, default=2_000_000)
+    ap.add_argument("--hubs", type=int, default=500)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--direct-steps", type=int, default=1, help="exact-direct comparator iterations (0: skip)")
+    ap.add_argument("--sample", type=int, default=1000, help="nodes in the force-error sample (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "multi-GPU sharding is a design note only", file=sys.stderr)
+        return 2
+
+    import numpy as np
+
+    from paper_2403_03504_amd import workloads as w
+
+    t = time.perf_counter()
+    g = w.giant_2m(args.seed, args.nodes, args.hubs)
+    log(f"generated {g.n} nodes / {g.m} edge records in {time.perf_counter() - t:.1f}s")
+
+    import torch
+
+    from paper_2403_03504_amd import fa2lay as fl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    ctx = fl.Context(0)
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(g.src).to(dev)
+    dst = torch.from_numpy(g.dst).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    G = ctx.build_csr(g.n, src, dst)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    nnz = int(G.row_ptr[-1].item())
+    log(f"CSR built on GPU: nnz {nnz} in {setup_s * 1e3:.1f} ms")
+
+    prm = fl.default_params(repulsion=fl.REP_FMM, p=args.p, leaf_size=args.leaf)
+    x = torch.from_numpy(g.x).to(dev)
+    y = torch.from_numpy(g.y).to(dev)
+    st = fl.FA2State.zeros(g.n, dev)
+    ctx.fa2_run(G, x, y, st, prm, args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} iterations done")
+
+    # ---- timed region ------------------------------------------------------
+    ctx.fmm_stats(reset=True)
+    ctx.get_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fa2_run(G, x, y, st, prm, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    wall = t1 - t0
+    value = g.n * args.steps / wall
+    phases = ctx.get_timing()
+    fst = ctx.fmm_stats()
+    log(f"timed {args.steps} iterations: {wall * 1e3 / args.steps:.3f} ms/iter, {value:.4g} node-updates/s")
+    log("phases (ms/iter): " + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f}" for k, v in phases.items() if v[1]))
+
+    # roofline of the dominant kernel: P2P + L2P + M2P evaluation (FP32 ALU)
+    evals = max(fst["evaluations"], 1)
+    pairs_per_launch = fst["total_near_pairs"] / evals
+    eval_ms = phases["eval"][0] / max(phases["eval"][1], 1)
+    # 11 FLOP per near-field pair (2 sub, 3 for r^2, 1 reciprocal, 1 mul,
+    # 4 for the two multiply-adds); L2P: Horner of degree p-1 in complex
+    # arithmetic, 8 FLOP per term, per particle
+    eval_flop = 11.0 * pairs_per_launch + 8.0 * args.p * g.n
+    achieved = eval_flop / (eval_ms * 1e-3)
+    attract_ms = phases["attract"][0] / max(phases["attract"][1], 1)
+    attract_bytes = 40.0 * g.n + 4.0 * nnz  # compulsory bytes of the attraction/combine pass
+    roofline = {"kernel": "k_eval (P2P+L2P+M2P)", "bound": "alu", "achieved": achieved / 1e12,
+                "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
+                "frac_of_published_157": achieved / FP32_PUBLISHED, "traffic": None,
+                "flop_per_launch": eval_flop, "near_pairs_per_launch": pairs_per_launch,
+                "launch_ms": eval_ms,
+                "attraction": {"achieved_GBps": attract_bytes / (attract_ms * 1e-3) / 1e9,
+                               "bytes_per_launch": attract_bytes, "launch_ms": attract_ms,
+                               "frac_hbm": attract_bytes / (attract_ms * 1e-3) / HBM_PEAK}}
+
+    result = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": f"bipartite Zipf transaction graph, {g.n} nodes, {args.hubs} hubs, "
+                                     f"{nnz // 2} edges; FMM p={args.p}, leaf<={args.leaf}",
+                         "nodes": g.n, "edges": nnz // 2, "p": args.p, "leaf_size": args.leaf,
+                         "fp64": "swing/traction sums, speeds, bounding square"},
+              "roofline": roofline,
+              "phases_ms_per_iter": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]},
+              "fmm": {k: fst[k] for k in ("cells", "leaves", "max_level", "near_pairs", "v_entries",
+                                         "w_entries", "x_entries")},
+              "setup_ms": setup_s * 1e3}
+
+    # ---- accuracy on a sample, and the exact-direct comparator --------------
+    from oracle import oracle as orc
+    xs = x.detach().cpu().numpy()
+    ys = y.detach().cpu().numpy()
+    deg = G.deg.cpu().numpy()
+    out_fmm = ctx.fa2_forces(G, x, y, prm, components=False)
+    prm_d = fl.default_params(repulsion=fl.REP_EXACT)
+    torch.cuda.synchronize()
+    td = time.perf_counter()
+    out_dir = ctx.fa2_forces(G, x, y, prm_d, components=False)
+    torch.cuda.synchronize()
+    direct_rep_s = time.perf_counter() - td
+    if args.sample > 0:
+        rng = np.random.default_rng(12345)
+        tg = np.sort(rng.choice(g.n, size=min(args.sample, g.n), replace=False))
+        ex, ey = orc.repulsion_exact(xs, ys, deg + 1.0, targets=tg)
+        fmx, fmy = out_fmm["frx"].cpu().numpy()[tg], out_fmm["fry"].cpu().numpy()[tg]
+        dmx, dmy = out_dir["frx"].cpu().numpy()[tg], out_dir["fry"].cpu().numpy()[tg]
+        result["accuracy"] = {"sample_nodes": int(tg.size), "positions": f"after {args.warmup + args.steps} iterations",
+                              "fmm_rel_err": orc.rel_err(fmx, fmy, ex, ey),
+                              "direct_rel_err": orc.rel_err(dmx, dmy, ex, ey),
+                              "reference": "FP64 exact sum over all nodes (oracle)"}
+        log(f"repulsion error on {tg.size} nodes: FMM {result['accuracy']['fmm_rel_err']:.2e}, "
+            f"direct {result['accuracy']['direct_rel_err']:.2e}")
+    if args.direct_steps > 0:
+        xd, yd = x.clone(), y.clone()
+        sd = fl.FA2State(st.fx_prev.clone(), st.fy_prev.clone(), st.scalars.clone(), st.iter)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        ctx.fa2_run(G, xd, yd, sd, prm_d, args.direct_steps)
+        torch.cuda.synchronize()
+        dwall = time.perf_counter() - td
+        dv = g.n * args.direct_steps / dwall
+        result["direct"] = {"node_updates_per_s": dv, "ms_per_step": dwall * 1e3 / args.direct_steps,
+                            "steps": args.direct_steps, "fmm_speedup": value / dv,
+                            "pairs_per_s": g.n * (g.n - 1) * args.direct_steps / dwall,
+                            "repulsion_only_s": direct_rep_s}
+        log(f"exact-direct: {dwall * 1e3 / args.direct_steps:.1f} ms/iter, FMM speedup {value / dv:.1f}x")
+
+    # ---- CPU oracle baseline: one full FA2 iteration, FMM repulsion, FP64 ----
+    if not args.no_cpu:
+        rp, col, deg_o = orc.build_csr(g.n, g.src, g.dst)
+        oprm = orc.FA2Params(repulsion="fmm", p=args.p, leaf_size=args.leaf)
+        tc = time.perf_counter()
+        orc.fa2_step(rp, col, deg_o, g.x, g.y, np.zeros(g.n), np.zeros(g.n), 0.0, 0, oprm)
+        cs = time.perf_counter() - tc
+        result["cpu_baseline"] = {"value": g.n / cs, "unit": "node-updates/s", "cores": orc.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"one full FA2 iteration of the same {g.n}-node graph (FP64 FMM "
+                                            f"repulsion p={args.p}, leaf<={args.leaf}), {cs:.1f} s"}
+        log(f"cpu oracle: {cs:.1f}s per iteration on {orc.num_threads()} threads")
+    ctx.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -194,11 +194,14 @@ fl_status fl_fa2_run(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32
                      const int32_t *deg, float *x, float *y, fl_fa2_state *state, const fl_fa2_params *prm,
                      int32_t iters, fl_step_stats *per_iter);
 
-/* Statistics of the last FMM evaluation on this context [host, synchronises]:
- * out[0] cells, [1] leaves, [2] near-field (P2P) particle pairs, [3] M2L
- * (V-list) entries, [4] W-list entries, [5] X-list entries, [6] deepest
- * level, [7] U-list entries. */
-fl_status fl_fmm_stats(fl_ctx *ctx, int64_t *out8);
+/* Statistics of the FMM evaluations on this context [host, synchronises]:
+ * last evaluation: out[0] cells, [1] leaves, [2] near-field (P2P) particle
+ * pairs, [3] M2L (V-list) entries, [4] W-list entries, [5] X-list entries,
+ * [6] deepest level, [7] U-list entries; totals since the last reset:
+ * [8] near-field pairs, [9] M2L entries, [10] evaluations, [11] particles
+ * evaluated.  reset != 0 zeroes the totals after reading them. */
+enum { FL_NSTATS = 12 };
+fl_status fl_fmm_stats(fl_ctx *ctx, int64_t *out, int reset);
 
 /* Per-phase device timing (HIP events on the context's stream).  When
  * enabled, fl_fa2_step/run record events around their phases; fl_get_timing

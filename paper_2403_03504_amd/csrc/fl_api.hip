@@ -1,5 +1,5 @@
 // Context management, error plumbing and per-phase timing of libfa2lay.
-#include "fl_common.h"
+#include "fl_tree.h"
 
 #include <cstdio>
 
@@ -140,13 +140,16 @@ fl_status fl_get_timing(fl_ctx *c, double *ms, int64_t *counts)
     FL_API_END(c)
 }
 
-fl_status fl_fmm_stats(fl_ctx *c, int64_t *out8)
+fl_status fl_fmm_stats(fl_ctx *c, int64_t *out, int reset)
 {
     FL_API_BEGIN(c)
-    FL_REQUIRE(out8 != nullptr, "fl_fmm_stats: null output");
-    FL_CHECK_HIP(hipMemcpyAsync(c->host_stage, c->d_stats, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    FL_REQUIRE(out != nullptr, "fl_fmm_stats: null output");
+    tree_max_level(c);
+    FL_CHECK_HIP(hipMemcpyAsync(c->host_stage, c->d_stats, FL_NSTATS * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                c->stream));
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));
-    std::memcpy(out8, c->host_stage, 8 * sizeof(int64_t));
+    std::memcpy(out, c->host_stage, FL_NSTATS * sizeof(int64_t));
+    if (reset) FL_CHECK_HIP(hipMemsetAsync(c->d_stats + 8, 0, 4 * sizeof(int64_t), c->stream));
     FL_API_END(c)
 }
 

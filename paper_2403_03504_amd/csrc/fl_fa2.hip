@@ -1,7 +1,8 @@
 // ForceAtlas2 iteration of the paper's sec. 3.2 on one GPU:
 //   repulsion  exact O(n^2) (LDS-tiled) or FMM (fl_fmm.hip)
-//   k_combine  linear CSR attraction (FP64 sums; rows longer than 32 are
-//              summed by the whole block), gravity, F = F_r + F_a + F_g,
+//   k_combine  linear CSR attraction (FP64 sums; rows longer than 32 entries
+//              are cut into 256-entry chunks summed by one wave each and
+//              added in chunk order), gravity, F = F_r + F_a + F_g,
 //              per-node swing |F - F'| and traction |F + F'| in FP64, block
 //              partial sums; the last block to finish adds the partials in a
 //              fixed order and sets the global speed s_G (no host round trip)
@@ -14,6 +15,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int HEAVY = 32;
+constexpr int COMBINE_BLOCKS = 1024;  // fixed grid: one ticket atomic per block
 
 struct StepConsts {
     double ka, kg, tau, ks, ksmax, max_rise;
@@ -54,10 +56,62 @@ __global__ __launch_bounds__(NT) void k_rep_exact(int n, const float *__restrict
     }
 }
 
+// ---- attraction plan: rows longer than HEAVY are cut into CHUNK-entry pieces,
+// each summed by one wave; the owning row adds its pieces in order ---------------
+constexpr int CHUNK = 256;
+
+__global__ void k_chunk_count(int n, const int32_t *__restrict__ row_ptr, int32_t *__restrict__ nch)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int d = row_ptr[i + 1] - row_ptr[i];
+    nch[i] = d > HEAVY ? (d + CHUNK - 1) / CHUNK : 0;
+}
+
+__global__ void k_chunk_fill(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ choff,
+                             int2 *__restrict__ chunks)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int rb = row_ptr[i], re = row_ptr[i + 1];
+    for (int c = choff[i], e = rb; c < choff[i + 1]; ++c, e += CHUNK) chunks[c] = make_int2(i, e);
+}
+
+__global__ void k_pack_xy(const float *__restrict__ x, const float *__restrict__ y, int n, float2 *__restrict__ xy)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) xy[i] = make_float2(x[i], y[i]);
+}
+
+__global__ __launch_bounds__(NT) void k_attract_chunks(const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col, const float2 *__restrict__ xy,
+                                                       const int2 *__restrict__ chunks,
+                                                       const int32_t *__restrict__ nchunks, double2 *__restrict__ csum)
+{
+    const int nc = *nchunks;
+    const int lane = lane_id();
+    for (int c = blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE; c < nc; c += gridDim.x * (NT / WAVE)) {
+        const int2 ch = chunks[c];
+        const int r = ch.x;
+        const int e1 = min(ch.y + CHUNK, row_ptr[r + 1]);
+        const float2 pr = xy[r];
+        const double rx = pr.x, ry = pr.y;
+        double sx = 0.0, sy = 0.0;
+        for (int e = ch.y + lane; e < e1; e += WAVE) {
+            const float2 pj = xy[col[e]];
+            sx += (double)pj.x - rx;
+            sy += (double)pj.y - ry;
+        }
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        if (lane == 0) csum[c] = make_double2(sx, sy);
+    }
+}
+
 // ---- attraction + gravity + combine + swing/traction ---------------------------
 __global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const int32_t *__restrict__ deg,
-                                                const float *__restrict__ x, const float *__restrict__ y,
+                                                const float2 *__restrict__ xy,
                                                 const float *__restrict__ frx, const float *__restrict__ fry,
                                                 StepConsts k, const float *__restrict__ fpx,
                                                 const float *__restrict__ fpy, int first, float *__restrict__ fx,
@@ -65,56 +119,43 @@ __global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict
                                                 float *__restrict__ fay, float *__restrict__ fgx,
                                                 float *__restrict__ fgy, double2 *__restrict__ part,
                                                 unsigned *__restrict__ ticket, double *__restrict__ scalars,
-                                                int32_t *__restrict__ flags, double *__restrict__ ring, int ring_it)
+                                                int32_t *__restrict__ flags, double *__restrict__ ring, int ring_it,
+                                                const int32_t *__restrict__ choff, const double2 *__restrict__ csum)
 {
-    __shared__ int hl[NT];
-    __shared__ double2 hres[NT];
-    __shared__ int nh;
     __shared__ double lds[NT / WAVE];
     __shared__ int is_last;
-    if (threadIdx.x == 0) nh = 0;
-    __syncthreads();
-    const int i = blockIdx.x * NT + threadIdx.x;
-    double ax = 0.0, ay = 0.0, xi = 0.0, yi = 0.0;
-    int slot = -1;
-    if (i < n) {
-        xi = x[i];
-        yi = y[i];
+    double wswg = 0.0, wtra = 0.0;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        double ax = 0.0, ay = 0.0;
+        const float2 pi = xy[i];
+        const double xi = pi.x, yi = pi.y;
         const int rb = row_ptr[i], re = row_ptr[i + 1];
         if (re - rb <= HEAVY) {
-            for (int e = rb; e < re; ++e) {
-                const int j = col[e];
-                ax += (double)x[j] - xi;
-                ay += (double)y[j] - yi;
+            int e = rb;
+            for (; e + 4 <= re; e += 4) {  // four gathers in flight
+                const int j0 = col[e], j1 = col[e + 1], j2 = col[e + 2], j3 = col[e + 3];
+                const float2 p0 = xy[j0], p1 = xy[j1], p2 = xy[j2], p3 = xy[j3];
+                ax += (double)p0.x - xi;
+                ay += (double)p0.y - yi;
+                ax += (double)p1.x - xi;
+                ay += (double)p1.y - yi;
+                ax += (double)p2.x - xi;
+                ay += (double)p2.y - yi;
+                ax += (double)p3.x - xi;
+                ay += (double)p3.y - yi;
+            }
+            for (; e < re; ++e) {
+                const float2 pj = xy[col[e]];
+                ax += (double)pj.x - xi;
+                ay += (double)pj.y - yi;
             }
         } else {
-            slot = atomicAdd(&nh, 1);
-            hl[slot] = i;
+            for (int c = choff[i]; c < choff[i + 1]; ++c) {
+                const double2 v = csum[c];
+                ax += v.x;
+                ay += v.y;
+            }
         }
-    }
-    __syncthreads();
-    const int nheavy = nh;
-    for (int h = 0; h < nheavy; ++h) {
-        const int r = hl[h];
-        const int rb = row_ptr[r], re = row_ptr[r + 1];
-        const double rx = x[r], ry = y[r];
-        double sx = 0.0, sy = 0.0;
-        for (int e = rb + threadIdx.x; e < re; e += NT) {
-            const int j = col[e];
-            sx += (double)x[j] - rx;
-            sy += (double)y[j] - ry;
-        }
-        sx = block_sum<double, NT>(sx, lds);
-        sy = block_sum<double, NT>(sy, lds);
-        if (threadIdx.x == 0) hres[h] = make_double2(sx, sy);
-    }
-    __syncthreads();
-    if (slot >= 0) {
-        ax = hres[slot].x;
-        ay = hres[slot].y;
-    }
-    double wswg = 0.0, wtra = 0.0;
-    if (i < n) {
         const double m = (double)(deg[i] + 1);
         const double Fax = k.ka * ax, Fay = k.ka * ay;
         double Fgx, Fgy;
@@ -150,8 +191,8 @@ __global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict
             const double dxs = (double)Fx - px, dys = (double)Fy - py;
             const double dxt = (double)Fx + px, dyt = (double)Fy + py;
             const double w = (k.swing_mode == FL_SWING_FA2) ? m : 1.0;
-            wswg = w * sqrt(dxs * dxs + dys * dys);
-            wtra = w * sqrt(dxt * dxt + dyt * dyt);
+            wswg += w * sqrt(dxs * dxs + dys * dys);
+            wtra += w * sqrt(dxt * dxt + dyt * dyt);
         }
     }
     if (!part) return;
@@ -224,20 +265,23 @@ __global__ __launch_bounds__(NT) void k_update(int n, float *__restrict__ x, flo
     if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags, 2);
 }
 
-__global__ void k_validate_graph(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                 const int32_t *__restrict__ deg, int32_t *__restrict__ bad)
+__global__ void k_validate_rows(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
+                                int32_t *__restrict__ bad)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
     if (i == 0 && row_ptr[0] != 0) atomicOr(bad, 1);
     if (i == n) return;
     const int rb = row_ptr[i], re = row_ptr[i + 1];
-    if (re < rb) {
-        atomicOr(bad, 2);
-        return;
-    }
-    if (deg && deg[i] != re - rb) atomicOr(bad, 4);
-    for (int e = rb; e < re; ++e) {
+    if (re < rb) atomicOr(bad, 2);
+    else if (deg && deg[i] != re - rb) atomicOr(bad, 4);
+}
+
+__global__ void k_validate_cols(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                int32_t *__restrict__ bad)
+{
+    const int nnz = row_ptr[n];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) {
         const int j = col[e];
         if (j < 0 || j >= n) {
             atomicOr(bad, 8);
@@ -286,14 +330,57 @@ static void validate_graph(fl_ctx *c, const GraphArgs &g)
     FL_REQUIRE(g.row_ptr && g.col && g.deg, "null graph array");
     int32_t *bad = ws<int32_t>(c, "fa2_bad", 1);
     FL_CHECK_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), c->stream));
-    hipLaunchKernelGGL(k_validate_graph, dim3(grid_for((int64_t)g.n + 1, NT)), dim3(NT), 0, c->stream, g.n, g.row_ptr,
-                       g.col, g.deg, bad);
+    hipLaunchKernelGGL(k_validate_rows, dim3(grid_for((int64_t)g.n + 1, NT)), dim3(NT), 0, c->stream, g.n, g.row_ptr,
+                       g.deg, bad);
     FL_LAUNCH_CHECK();
     int32_t b = read_i32(c, bad);
+    if (b == 0) {
+        hipLaunchKernelGGL(k_validate_cols, dim3(2048), dim3(NT), 0, c->stream, g.n, g.row_ptr, g.col, bad);
+        FL_LAUNCH_CHECK();
+        b = read_i32(c, bad);
+    }
     if (b & 1) throw Error(FL_EINVAL, "row_ptr[0] must be 0");
     if (b & 2) throw Error(FL_EINVAL, "row_ptr must be non-decreasing");
     if (b & 4) throw Error(FL_EINVAL, "deg[i] must equal row_ptr[i+1] - row_ptr[i]");
     if (b & 8) throw Error(FL_EINVAL, "column index outside [0, n)");
+}
+
+struct AttractPlan {
+    int32_t *choff = nullptr;   // [n+1] first chunk of each row (heavy rows only)
+    int2 *chunks = nullptr;     // (row, first entry)
+    double2 *csum = nullptr;    // per-chunk sums
+    int64_t cap = 0;
+};
+
+// Chunks of the rows longer than HEAVY; depends on the graph only.
+static AttractPlan attract_plan(fl_ctx *c, const GraphArgs &g)
+{
+    AttractPlan a;
+    const int n = g.n;
+    int32_t nnz = read_i32(c, g.row_ptr + n);
+    a.cap = nnz / (HEAVY + 1) + nnz / CHUNK + 2;
+    int32_t *nch = ws<int32_t>(c, "at_nch", n);
+    a.choff = ws<int32_t>(c, "at_choff", (size_t)n + 1);
+    a.chunks = ws<int2>(c, "at_chunks", a.cap);
+    a.csum = ws<double2>(c, "at_csum", a.cap);
+    hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, g.row_ptr, nch);
+    FL_LAUNCH_CHECK();
+    scan_excl_i32(c, nch, a.choff, n);
+    hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, g.row_ptr, a.choff, a.chunks);
+    FL_LAUNCH_CHECK();
+    return a;
+}
+
+// positions interleaved (x, y) so each neighbour is one 8-byte gather
+static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const AttractPlan &a, const float *x,
+                                    const float *y)
+{
+    float2 *xy = ws<float2>(c, "at_xy", g.n);
+    hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, c->stream, x, y, g.n, xy);
+    hipLaunchKernelGGL(k_attract_chunks, dim3(1024), dim3(NT), 0, c->stream, g.row_ptr, g.col, (const float2 *)xy,
+                       a.chunks, a.choff + g.n, a.csum);
+    FL_LAUNCH_CHECK();
+    return xy;
 }
 
 static void repulsion(fl_ctx *c, const GraphArgs &g, const float *x, const float *y, const fl_fa2_params *p,
@@ -315,8 +402,8 @@ static StepConsts consts(const fl_fa2_params *p)
 }
 
 // one iteration; flags must have been cleared by the caller
-static void iteration(fl_ctx *c, const GraphArgs &g, float *x, float *y, fl_fa2_state *st, const fl_fa2_params *p,
-                      int32_t *flags, double *ring, int ring_it)
+static void iteration(fl_ctx *c, const GraphArgs &g, const AttractPlan &ap, float *x, float *y, fl_fa2_state *st,
+                      const fl_fa2_params *p, int32_t *flags, double *ring, int ring_it)
 {
     const int n = g.n;
     float *frx = ws<float>(c, "fa2_frx", n);
@@ -324,15 +411,18 @@ static void iteration(fl_ctx *c, const GraphArgs &g, float *x, float *y, fl_fa2_
     float *fcx = ws<float>(c, "fa2_fcx", n);
     float *fcy = ws<float>(c, "fa2_fcy", n);
     const unsigned nb = grid_for(n, NT);
-    double2 *part = ws<double2>(c, "fa2_part", nb);
+    const unsigned nbc = grid_for(n, NT, COMBINE_BLOCKS);
+    double2 *part = ws<double2>(c, "fa2_part", nbc);
     unsigned *ticket = ws_zeroed<unsigned>(c, "fa2_ticket", 4);
     const int first = st->iter == 0 ? 1 : 0;
     repulsion(c, g, x, y, p, frx, fry);
     {
         PhaseTimer pt(c, FL_PH_ATTRACT);
-        hipLaunchKernelGGL(k_combine, dim3(nb), dim3(NT), 0, c->stream, n, g.row_ptr, g.col, g.deg, x, y, frx, fry,
+        const float2 *xy = attract_chunks(c, g, ap, x, y);
+        hipLaunchKernelGGL(k_combine, dim3(nbc), dim3(NT), 0, c->stream, n, g.row_ptr, g.col, g.deg, xy, frx, fry,
                            consts(p), st->fx_prev, st->fy_prev, first, fcx, fcy, (float *)nullptr, (float *)nullptr,
-                           (float *)nullptr, (float *)nullptr, part, ticket, st->scalars, flags, ring, ring_it);
+                           (float *)nullptr, (float *)nullptr, part, ticket, st->scalars, flags, ring, ring_it,
+                           ap.choff, ap.csum);
         FL_LAUNCH_CHECK();
     }
     {
@@ -383,10 +473,14 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
     repulsion(c, g, x, y, prm, rx, ry);
     if (fax || fgx) {
         int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
-        hipLaunchKernelGGL(k_combine, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, row_ptr, col_idx, deg, x, y,
+        AttractPlan ap = attract_plan(c, g);
+        const float2 *xy = attract_chunks(c, g, ap, x, y);
+        hipLaunchKernelGGL(k_combine, dim3(grid_for(n, NT, COMBINE_BLOCKS)), dim3(NT), 0, c->stream, n, row_ptr,
+                           col_idx, deg, xy,
                            (const float *)nullptr, (const float *)nullptr, consts(prm), (const float *)nullptr,
                            (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
-                           (double2 *)nullptr, (unsigned *)nullptr, (double *)nullptr, flags, (double *)nullptr, 0);
+                           (double2 *)nullptr, (unsigned *)nullptr, (double *)nullptr, flags, (double *)nullptr, 0,
+                           ap.choff, ap.csum);
         FL_LAUNCH_CHECK();
     }
     FL_API_END(c)
@@ -409,7 +503,8 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
     FL_LAUNCH_CHECK();
     if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
     double *ring = per_iter ? ws<double>(c, "fa2_ring", 3 * (size_t)(iters > 0 ? iters : 1)) : nullptr;
-    for (int it = 0; it < iters; ++it) iteration(c, g, x, y, st, prm, flags, ring, it);
+    AttractPlan ap = attract_plan(c, g);
+    for (int it = 0; it < iters; ++it) iteration(c, g, ap, x, y, st, prm, flags, ring, it);
     if (per_iter || always_sync) {
         int32_t f = read_i32(c, flags);
         if (per_iter && iters > 0) {

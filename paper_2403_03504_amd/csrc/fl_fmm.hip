@@ -7,22 +7,23 @@
 // overflow for any order or extent: outgoing coefficient k holds a_k / w^k
 // (|.| <= Q 0.71^k / k), incoming coefficient l holds b_l w^l.
 //
-//   k_upward  leaves: outgoing expansion from the particles (P2M); then each
-//             thread climbs while it is the last child to finish, shifting
-//             the four children's expansions to the parent centre (M2M).  The
-//             arrival counters reset themselves; nobody waits for anybody.
+//   k_p2m     leaves: outgoing expansion from the particles (P2M).
+//   k_m2m     one launch per level, deepest first: each cell shifts its
+//             children's expansions to its centre and adds them (M2M).
 //   k_m2l     every cell: interacting cells' outgoing expansions converted to
 //             an incoming one (M2L, V list) plus particles of coarser
-//             separated leaves (P2L, X list).
+//             separated leaves (P2L, X list); one lane per source cell.
 //   k_l2l     every leaf: incoming expansions of the leaf and all its
 //             ancestors shifted to the leaf centre.  Shifts compose exactly,
 //             so this is the paper's parent-to-child recursion unrolled along
 //             each leaf's ancestor chain (one launch instead of one per level).
 //   k_eval    one wave per leaf: far field from the incoming expansion (L2P),
 //             W-list outgoing expansions at the particles (M2P), and the
-//             direct near field over the U list (P2P).  Lanes are split into
-//             groups that stride over the sources so small leaves still fill
-//             the wave; groups are combined with xor shuffles (fixed order).
+//             direct near field over the U list (P2P).  Lanes hold targets;
+//             sources are read at wave-uniform addresses (scalar loads, SGPR
+//             operands: no per-lane memory traffic in the pair loop).  Leaves
+//             of at most 32 targets run two half-waves on alternate sources,
+//             combined with one xor shuffle (fixed order).
 #include "fl_fmm.h"
 
 namespace fl {
@@ -67,143 +68,204 @@ __device__ __forceinline__ float2 rel(float x, float y, const CellGeo &g)
 }
 
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(256) void k_upward(TreeView t, float2 *__restrict__ M, int32_t *arrive)
+// Lanes of one wave exchanging data through LDS: make every lane's LDS writes
+// visible to the other lanes of the wave (no block barrier: the waves of a
+// block work on different leaves and must not wait for each other).
+__device__ __forceinline__ void wave_lds_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int P>
+struct P2MLds {
+    float2 buf[4][P + 1][WAVE + 1];  // per-wave P2M contributions, transposed (padded rows)
+};
+
+// k_p2m: one wave per leaf.  Each lane takes particles of the leaf and writes
+// its P+1 terms (Q contribution and -q u^k / k) to LDS; lane k then sums
+// column k in lane order.
+template <int P>
+__global__ __launch_bounds__(256) void k_p2m(TreeView t, const float4 *__restrict__ part,
+                                             const int32_t *__restrict__ leaf_cell, float2 *__restrict__ M)
+{
+    __shared__ P2MLds<P> sh;
     const int nleaves = t.counts[1];
-    for (int li = blockIdx.x * blockDim.x + threadIdx.x; li < nleaves; li += gridDim.x * blockDim.x) {
-        const int c = t.leaf_cell[li];
+    const int lane = lane_id();
+    const int w = threadIdx.x / WAVE;
+    const int wpb = blockDim.x / WAVE;
+    for (int li = blockIdx.x * wpb + w; li < nleaves; li += gridDim.x * wpb) {
+        const int c = leaf_cell[li];
         const CellGeo g = geo(t, c);
-        float2 a[P + 1];
-#pragma unroll
-        for (int k = 0; k <= P; ++k) a[k] = make_float2(0.f, 0.f);
+        const double inv_w = 1.0 / g.w;
         const int b = t.beg[c], e = t.end[c];
-        for (int j = b; j < e; ++j) {
-            const float4 p = t.part[j];
-            const float2 u = rel(p.x, p.y, g);
-            a[0].x += p.z;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int t0 = b; t0 < e; t0 += WAVE) {
+            const int j = t0 + lane;
+            float q = 0.f;
+            float2 u = make_float2(0.f, 0.f);
+            if (j < e) {
+                const float4 p = part[j];
+                q = p.z;
+                u = make_float2((float)(((double)p.x - g.cx) * inv_w), (float)(((double)p.y - g.cy) * inv_w));
+            }
+            sh.buf[w][0][lane] = make_float2(q, 0.f);
             float2 pw = u;
 #pragma unroll
             for (int k = 1; k <= P; ++k) {
-                const float s = p.z / (float)k;
-                a[k].x -= s * pw.x;
-                a[k].y -= s * pw.y;
+                sh.buf[w][k][lane] = cscale(pw, -q / (float)k);
                 pw = cmul(pw, u);
+            }
+            wave_lds_sync();
+            if (lane <= P) {
+#pragma unroll 8
+                for (int i = 0; i < WAVE; ++i) acc = cadd(acc, sh.buf[w][lane][i]);
+            }
+            wave_lds_sync();
+        }
+        if (lane <= P) M[(int64_t)c * (P + 1) + lane] = acc;
+    }
+}
+
+// k_m2m: the cells of one level shift their children's outgoing expansions
+// to their own centre and add them (child centre at (+-1/4, +-1/4) parent
+// widths, child width 1/2), with the constant operator of each quadrant:
+//   A_l = sum_k T_q[l][k] A^q_k,  T_q[0][0] = 1,  T_q[l][0] = -z^l / l,
+//   T_q[l][k] = 2^-k z^(l-k) C(l-1, k-1) (1 <= k <= l).
+// One launch per level, deepest first: the kernel boundary orders the levels.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2m(TreeView t, int level, float2 *__restrict__ M)
+{
+    __shared__ float2 T[4][P + 1][P + 1];
+    const int ncells = t.counts[0];
+    if (level >= t.bits || ncells <= 1) return;
+    for (int idx = threadIdx.x; idx < 4 * (P + 1) * (P + 1); idx += blockDim.x) {
+        const int q = idx / ((P + 1) * (P + 1)), l = (idx / (P + 1)) % (P + 1), k = idx % (P + 1);
+        const float2 z = make_float2((q & 1) ? 0.25f : -0.25f, (q >> 1) ? 0.25f : -0.25f);
+        float2 v = make_float2(0.f, 0.f);
+        if (l == 0) {
+            v = make_float2(k == 0 ? 1.f : 0.f, 0.f);
+        } else if (k == 0) {
+            float2 zl = make_float2(1.f, 0.f);
+            for (int i = 0; i < l; ++i) zl = cmul(zl, z);
+            v = cscale(zl, -1.0f / (float)l);
+        } else if (k <= l) {
+            float2 zl = make_float2(1.f, 0.f);
+            for (int i = 0; i < l - k; ++i) zl = cmul(zl, z);
+            float b = 1.0f;  // C(l-1, k-1)
+            for (int i = 1; i <= k - 1; ++i) b = b * (float)(l - k + i) / (float)i;
+            v = cscale(zl, ldexpf(b, -k));
+        }
+        T[q][l][k] = v;
+    }
+    __syncthreads();
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x) {
+        if (t.lvl[c] != level) continue;
+        const int4 ch = t.child[c];
+        if (is_leaf4(ch)) continue;
+        float2 B[P + 1];
+#pragma unroll
+        for (int l = 0; l <= P; ++l) B[l] = make_float2(0.f, 0.f);
+        const int cc[4] = {ch.x, ch.y, ch.z, ch.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cid = cc[q];
+            if (cid < 0) continue;
+            float2 A[P + 1];
+            const float2 *Mq = M + (int64_t)cid * (P + 1);
+#pragma unroll
+            for (int k = 0; k <= P; ++k) A[k] = Mq[k];
+#pragma unroll
+            for (int l = 0; l <= P; ++l) {
+#pragma unroll
+                for (int k = 0; k <= l; ++k) {
+                    const float2 tq = T[q][l][k];
+                    B[l].x += tq.x * A[k].x - tq.y * A[k].y;
+                    B[l].y += tq.x * A[k].y + tq.y * A[k].x;
+                }
             }
         }
         float2 *Mc = M + (int64_t)c * (P + 1);
 #pragma unroll
-        for (int k = 0; k <= P; ++k) Mc[k] = a[k];
-
-        // climb: shift the children of each completed parent (M2M)
-        int cur = c;
-        while (true) {
-            const int par = t.par[cur];
-            if (par < 0) break;
-            const int4 ch = t.child[par];
-            const int nch = (ch.x >= 0) + (ch.y >= 0) + (ch.z >= 0) + (ch.w >= 0);
-            __threadfence();
-            const int old = atomicAdd(&arrive[par], 1);
-            if (old != nch - 1) break;
-            __threadfence();
-            arrive[par] = 0;
-            float2 bsum[P + 1];
-#pragma unroll
-            for (int l = 0; l <= P; ++l) bsum[l] = make_float2(0.f, 0.f);
-            const int cc[4] = {ch.x, ch.y, ch.z, ch.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int cid = cc[q];
-                if (cid < 0) continue;
-                // child centre relative to the parent centre, in parent widths
-                const float2 z = make_float2((q & 1) ? 0.25f : -0.25f, (q >> 1) ? 0.25f : -0.25f);
-                float2 A[P + 1];
-                const float2 *Mq = M + (int64_t)cid * (P + 1);
-#pragma unroll
-                for (int k = 0; k <= P; ++k) A[k] = Mq[k];
-                float2 zp[P + 1];
-                zp[0] = make_float2(1.f, 0.f);
-#pragma unroll
-                for (int k = 1; k <= P; ++k) zp[k] = cmul(zp[k - 1], z);
-                const float Q = A[0].x;
-                bsum[0].x += Q;
-#pragma unroll
-                for (int l = 1; l <= P; ++l) {
-                    float2 s = cscale(zp[l], -Q / (float)l);
-                    float half = 1.0f;
-#pragma unroll
-                    for (int k = 1; k <= l; ++k) {
-                        half *= 0.5f;
-                        const float2 tz = cmul(A[k], zp[l - k]);
-                        const float f = half * binomf(l - 1, k - 1);
-                        s.x += f * tz.x;
-                        s.y += f * tz.y;
-                    }
-                    bsum[l] = cadd(bsum[l], s);
-                }
-            }
-            float2 *Mp = M + (int64_t)par * (P + 1);
-#pragma unroll
-            for (int l = 0; l <= P; ++l) Mp[l] = bsum[l];
-            cur = par;
-        }
+        for (int l = 0; l <= P; ++l) Mc[l] = B[l];
     }
 }
 
 // ---------------------------------------------------------------------------
+// k_m2l: two target cells per wave (one per half-wave).  Lane j of a half
+// converts source V[j] of its cell (a V list holds at most 27 cells) with the
+// whole M2L of Greengard & Rokhlin's Lemma 2.4 in scaled form, rho = w / z0:
+//   B_l += rho^l [ -Q/l + sum_k C(l+k-1, k-1) (-rho)^k A_k ],
+// and the half's lanes are summed by an xor butterfly (fixed order).  The X
+// list (P2L: particles of coarser separated leaves) is spread over the same
+// lanes, particle by particle, before the butterfly.
 template <int P>
-__global__ __launch_bounds__(256) void k_m2l(TreeView t, const float2 *__restrict__ M,
-                                             const int64_t *__restrict__ offVX, const int32_t *__restrict__ V,
-                                             const int32_t *__restrict__ X, float2 *__restrict__ Lp)
+__global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restrict__ part,
+                                             const float2 *__restrict__ M, const int64_t *__restrict__ offVX,
+                                             const int32_t *__restrict__ V, const int32_t *__restrict__ X,
+                                             float2 *__restrict__ Lp)
 {
     const int ncells = t.counts[0];
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x) {
+    const int lane = lane_id();
+    const int half = lane >> 5, j = lane & 31;
+    const int wpb = blockDim.x / WAVE;
+    for (int c0 = 2 * (blockIdx.x * wpb + (int)threadIdx.x / WAVE); c0 < ncells; c0 += 2 * gridDim.x * wpb) {
+        const int c = c0 + half;
+        const bool live = c < ncells;
         float2 B[P + 1];
 #pragma unroll
         for (int l = 0; l <= P; ++l) B[l] = make_float2(0.f, 0.f);
-        const int64_t o0 = offVX[c], o1 = offVX[c + 1];
-        const int v0 = (int)(o0 & 0xFFFFFFFFll), v1 = (int)(o1 & 0xFFFFFFFFll);
-        const int x0 = (int)(o0 >> 32), x1 = (int)(o1 >> 32);
-        const uint32_t cxy = t.ixy[c];
-        const int cx = cell_ix(cxy), cy = cell_iy(cxy);
-        for (int e = v0; e < v1; ++e) {
-            const int s = V[e];
-            const uint32_t sxy = t.ixy[s];
-            // same level: source centre - target centre = w (dx + i dy)
-            const float dx = (float)(cell_ix(sxy) - cx), dy = (float)(cell_iy(sxy) - cy);
-            const float2 rho = crecip(make_float2(dx, dy));  // w / z0
-            const float2 mr = make_float2(-rho.x, -rho.y);
-            const float2 *Ms = M + (int64_t)s * (P + 1);
-            const float Q = Ms[0].x;
-            float2 ap[P + 1];
-            float2 pw = mr;
-#pragma unroll
-            for (int k = 1; k <= P; ++k) {
-                ap[k] = cmul(pw, Ms[k]);
-                pw = cmul(pw, mr);
-            }
-            float2 rl = rho;
-#pragma unroll
-            for (int l = 1; l <= P; ++l) {
-                float2 in = make_float2(-Q / (float)l, 0.f);
+        int x0 = 0, x1 = 0;
+        if (live) {
+            const int64_t o0 = offVX[c], o1 = offVX[c + 1];
+            const int v0 = (int)(o0 & 0xFFFFFFFFll), v1 = (int)(o1 & 0xFFFFFFFFll);
+            x0 = (int)(o0 >> 32);
+            x1 = (int)(o1 >> 32);
+            const uint32_t cxy = t.ixy[c];
+            for (int ei = v0 + j; ei < v1; ei += 32) {
+                const int s = V[ei];
+                const uint32_t sxy = t.ixy[s];
+                // same level: source centre - target centre = w (dx + i dy)
+                const float dx = (float)(cell_ix(sxy) - cell_ix(cxy)), dy = (float)(cell_iy(sxy) - cell_iy(cxy));
+                const float2 rho = crecip(make_float2(dx, dy));
+                const float2 mr = make_float2(-rho.x, -rho.y);
+                const float2 *Ms = M + (int64_t)s * (P + 1);
+                const float Q = Ms[0].x;
+                float2 ap[P + 1];
+                float2 pw = mr;
 #pragma unroll
                 for (int k = 1; k <= P; ++k) {
-                    const float bc = binomf(l + k - 1, k - 1);
-                    in.x += bc * ap[k].x;
-                    in.y += bc * ap[k].y;
+                    ap[k] = cmul(pw, Ms[k]);
+                    pw = cmul(pw, mr);
                 }
-                B[l] = cadd(B[l], cmul(rl, in));
-                rl = cmul(rl, rho);
+                float2 rl = rho;
+#pragma unroll
+                for (int l = 1; l <= P; ++l) {
+                    float2 in = make_float2(-Q / (float)l, 0.f);
+#pragma unroll
+                    for (int k = 1; k <= P; ++k) {
+                        const float bc = binomf(l + k - 1, k - 1);
+                        in.x += bc * ap[k].x;
+                        in.y += bc * ap[k].y;
+                    }
+                    B[l] = cadd(B[l], cmul(rl, in));
+                    rl = cmul(rl, rho);
+                }
             }
         }
-        if (x1 > x0) {
+        const bool anyx = __ballot(live && x1 > x0) != 0;
+        if (anyx && live && x1 > x0) {
             const CellGeo g = geo(t, c);
+            const double inv_w = 1.0 / g.w;
             for (int e = x0; e < x1; ++e) {
                 const int s = X[e];
                 const int sb = t.beg[s], se = t.end[s];
-                for (int j = sb; j < se; ++j) {
-                    const float4 p = t.part[j];
-                    const float2 rho = crecip(rel(p.x, p.y, g));  // w / (z_j - z_c)
+                for (int jj = sb + j; jj < se; jj += 32) {
+                    const float4 p = part[jj];
+                    const float2 zn = make_float2((float)(((double)p.x - g.cx) * inv_w),
+                                                  (float)(((double)p.y - g.cy) * inv_w));
+                    const float2 rho = crecip(zn);  // w / (z_j - z_c)
                     float2 pw = rho;
 #pragma unroll
                     for (int l = 1; l <= P; ++l) {
@@ -215,9 +277,20 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float2 *__restric
                 }
             }
         }
-        float2 *Lc = Lp + (int64_t)c * (P + 1);
 #pragma unroll
-        for (int l = 0; l <= P; ++l) Lc[l] = B[l];
+        for (int o = 16; o > 0; o >>= 1) {
+#pragma unroll
+            for (int l = 1; l <= P; ++l) {
+                B[l].x += __shfl_xor(B[l].x, o, WAVE);
+                B[l].y += __shfl_xor(B[l].y, o, WAVE);
+            }
+        }
+        if (live) {
+            float2 *Lc = Lp + (int64_t)c * (P + 1);
+#pragma unroll
+            for (int l = 0; l <= P; ++l)
+                if (j == l) Lc[l] = B[l];
+        }
     }
 }
 
@@ -265,62 +338,84 @@ __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restric
 }
 
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(256) void k_eval(TreeView t, const float2 *__restrict__ M,
-                                              const float2 *__restrict__ Lleaf, const int64_t *__restrict__ offUW,
-                                              const int32_t *__restrict__ U, const int32_t *__restrict__ W, float kr,
-                                              float *__restrict__ frx, float *__restrict__ fry)
-{
-    const int nleaves = t.counts[1];
-    const int lane = lane_id();
-    const int waves_total = gridDim.x * (blockDim.x / WAVE);
-    for (int li = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; li < nleaves; li += waves_total) {
-        const int c = t.leaf_cell[li];
-        const int b = t.beg[c], e = t.end[c];
-        const int64_t ou0 = offUW[li], ou1 = offUW[li + 1];
-        const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = (int)(ou1 & 0xFFFFFFFFll);
-        const int w0 = (int)(ou0 >> 32), w1 = (int)(ou1 >> 32);
-        const CellGeo g = geo(t, c);
-        const float2 *Lc = Lleaf + (int64_t)li * (P + 1);
-        for (int t0 = b; t0 < e; t0 += WAVE) {
-            const int ntc = min(WAVE, e - t0);
-            const int lg = ntc <= 4 ? 2 : ntc <= 8 ? 3 : ntc <= 16 ? 4 : ntc <= 32 ? 5 : 6;
-            const int tp = 1 << lg;
-            const int G = WAVE >> lg;
-            const int ti = lane & (tp - 1), grp = lane >> lg;
-            const bool valid = ti < ntc;
-            const float4 me = t.part[t0 + (valid ? ti : 0)];
-            float fx = 0.f, fy = 0.f;
-            for (int ue = u0; ue < u1; ++ue) {
-                const int s = U[ue];
-                const int sb = t.beg[s], se = t.end[s];
-                int j = sb + grp;
-                for (; j + 3 * G < se; j += 4 * G) {
-                    const float4 s0 = t.part[j], s1 = t.part[j + G], s2 = t.part[j + 2 * G], s3 = t.part[j + 3 * G];
-#define FL_P2P_PAIR(S)                                                                                              \
+// near-field pair: source (sx, sy, sm) at a wave-uniform address, so the
+// compiler keeps it in scalar registers and the VALU reads it directly
+#define FL_P2P_PAIR(SX, SY, SM)                                                                                     \
     {                                                                                                               \
-        const float dx = me.x - S.x, dy = me.y - S.y;                                                               \
+        const float dx = me.x - (SX), dy = me.y - (SY);                                                             \
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));                                                        \
-        const float sm = S.z * __builtin_amdgcn_rcpf(r2);                                                           \
+        const float sm = (SM) * __builtin_amdgcn_rcpf(r2);                                                          \
         fx = fmaf(sm, dx, fx);                                                                                      \
         fy = fmaf(sm, dy, fy);                                                                                      \
     }
-                    FL_P2P_PAIR(s0)
-                    FL_P2P_PAIR(s1)
-                    FL_P2P_PAIR(s2)
-                    FL_P2P_PAIR(s3)
+
+template <int P>
+__global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restrict__ part,
+                                              const float2 *__restrict__ M, const float2 *__restrict__ Lleaf,
+                                              const int64_t *__restrict__ offUW, const int32_t *__restrict__ U,
+                                              const int32_t *__restrict__ W, const int32_t *__restrict__ cbeg,
+                                              const int32_t *__restrict__ cend, const int32_t *__restrict__ leaf_cell,
+                                              float kr, float *__restrict__ frx, float *__restrict__ fry)
+{
+    const int nleaves = t.counts[1];
+    const int lane = lane_id();
+    const int wpb = blockDim.x / WAVE;
+    const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
+    for (int li = first; li < nleaves; li += gridDim.x * wpb) {
+        const int c = leaf_cell[li];
+        const int b = cbeg[c], e = cend[c];
+        const int64_t ou0 = offUW[li], ou1 = offUW[li + 1];
+        const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = (int)(ou1 & 0xFFFFFFFFll);
+        const int w0 = (int)(ou0 >> 32), w1 = (int)(ou1 >> 32);
+        for (int t0 = b; t0 < e; t0 += WAVE) {
+            const int ntc = min(WAVE, e - t0);
+            // small leaves: the two half-waves take alternate sources
+            const bool split = ntc <= WAVE / 2;
+            const int ti = split ? (lane & (WAVE / 2 - 1)) : lane;
+            const int half = split ? (lane >> 5) : 0;
+            const bool valid = ti < ntc;
+            const float4 me = part[t0 + (valid ? ti : 0)];
+            float fx = 0.f, fy = 0.f;
+            for (int ue = u0; ue < u1; ++ue) {
+                const int s = U[ue];
+                const int sb = cbeg[s], se = cend[s];
+                int j = sb;
+                if (!split) {
+                    for (; j + 4 <= se; j += 4) {
+                        const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
+                        FL_P2P_PAIR(s0.x, s0.y, s0.z)
+                        FL_P2P_PAIR(s1.x, s1.y, s1.z)
+                        FL_P2P_PAIR(s2.x, s2.y, s2.z)
+                        FL_P2P_PAIR(s3.x, s3.y, s3.z)
+                    }
+                    for (; j < se; ++j) {
+                        const float4 s0 = part[j];
+                        FL_P2P_PAIR(s0.x, s0.y, s0.z)
+                    }
+                } else {
+                    for (; j + 4 <= se; j += 4) {
+                        const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
+                        FL_P2P_PAIR(half ? s1.x : s0.x, half ? s1.y : s0.y, half ? s1.z : s0.z)
+                        FL_P2P_PAIR(half ? s3.x : s2.x, half ? s3.y : s2.y, half ? s3.z : s2.z)
+                    }
+                    for (; j + 2 <= se; j += 2) {
+                        const float4 s0 = part[j], s1 = part[j + 1];
+                        FL_P2P_PAIR(half ? s1.x : s0.x, half ? s1.y : s0.y, half ? s1.z : s0.z)
+                    }
+                    if (j < se) {
+                        const float4 s0 = part[j];
+                        const float m0 = half ? 0.f : s0.z;  // odd tail: lower half only
+                        FL_P2P_PAIR(s0.x, s0.y, m0)
+                    }
                 }
-                for (; j < se; j += G) {
-                    const float4 s0 = t.part[j];
-                    FL_P2P_PAIR(s0)
-                }
-#undef FL_P2P_PAIR
             }
-            for (int o = tp; o < WAVE; o <<= 1) {
-                fx += __shfl_xor(fx, o, WAVE);
-                fy += __shfl_xor(fy, o, WAVE);
+            if (split) {
+                fx += __shfl_xor(fx, WAVE / 2, WAVE);
+                fy += __shfl_xor(fy, WAVE / 2, WAVE);
             }
-            if (grp == 0 && valid) {
+            if (half == 0 && valid) {
+                const CellGeo g = geo(t, c);
+                const float2 *Lc = Lleaf + (int64_t)li * (P + 1);
                 // far field: incoming expansion of the leaf (Horner in the scaled variable)
                 const float2 v = rel(me.x, me.y, g);
                 float2 acc = cscale(Lc[P], (float)P);
@@ -354,6 +449,7 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float2 *__restri
         }
     }
 }
+#undef FL_P2P_PAIR
 
 template <int P>
 void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float *frx, float *fry)
@@ -362,25 +458,30 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
     float2 *M = ws<float2>(c, "f_M", (size_t)cap * (P + 1));
     float2 *Lp = ws<float2>(c, "f_Lp", (size_t)cap * (P + 1));
     float2 *Ll = ws<float2>(c, "f_Lleaf", (size_t)lcap * (P + 1));
-    int32_t *arrive = ws_zeroed<int32_t>(c, "f_arrive", cap);
     TreeView tv = view(t);
     const unsigned gl = grid_for(lcap, 256, 2048);
     const unsigned gc = grid_for(cap, 256, 2048);
     {
         PhaseTimer pt(c, FL_PH_UPWARD);
-        hipLaunchKernelGGL(k_upward<P>, dim3(gl), dim3(256), 0, c->stream, tv, M, arrive);
+        hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(lcap, 4, 2048)), dim3(256), 0, c->stream, tv,
+                           (const float4 *)t.part, (const int32_t *)t.leaf_cell, M);
+        for (int lev = t.bits - 1; lev >= 0; --lev)
+            hipLaunchKernelGGL(k_m2m<P>, dim3(grid_for(cap, 256, 512)), dim3(256), 0, c->stream, tv, lev, M);
         FL_LAUNCH_CHECK();
     }
     {
         PhaseTimer pt(c, FL_PH_M2L);
-        hipLaunchKernelGGL(k_m2l<P>, dim3(gc), dim3(256), 0, c->stream, tv, M, L.offVX, L.V, L.X, Lp);
+        hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(cap, 8, 2048)), dim3(256), 0, c->stream, tv,
+                           (const float4 *)t.part, M, L.offVX, L.V, L.X, Lp);
         hipLaunchKernelGGL(k_l2l<P>, dim3(gl), dim3(256), 0, c->stream, tv, Lp, Ll);
         FL_LAUNCH_CHECK();
     }
     {
         PhaseTimer pt(c, FL_PH_EVAL);
         const unsigned ge = grid_for(lcap, 4, 2048);  // 4 waves per block
-        hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, M, Ll, L.offUW, L.U, L.W, kr, frx, fry);
+        hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, M, Ll, L.offUW,
+                           L.U, L.W, (const int32_t *)t.beg, (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr,
+                           frx, fry);
         FL_LAUNCH_CHECK();
     }
 }

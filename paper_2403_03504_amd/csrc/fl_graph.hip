@@ -39,16 +39,37 @@ __global__ void k_csr_flags(const uint64_t *__restrict__ keys, int64_t len, uint
     flag[i] = (k != sent && (i == 0 || keys[i - 1] != k)) ? 1 : 0;
 }
 
-__global__ void k_csr_fill(const uint64_t *__restrict__ keys, const int32_t *__restrict__ flag,
-                           const int32_t *__restrict__ pos, int64_t len, int64_t n, int32_t *__restrict__ col,
-                           int32_t *__restrict__ deg)
+__global__ void k_csr_compact(const uint64_t *__restrict__ keys, const int32_t *__restrict__ flag,
+                              const int32_t *__restrict__ pos, int64_t len, int64_t n, int32_t *__restrict__ col,
+                              uint64_t *__restrict__ ukeys)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= len || !flag[i]) return;
     uint64_t k = keys[i];
-    int64_t u = (int64_t)(k / (uint64_t)n), v = (int64_t)(k % (uint64_t)n);
-    col[pos[i]] = (int32_t)v;
-    atomicAdd(&deg[u], 1);
+    col[pos[i]] = (int32_t)(k % (uint64_t)n);
+    ukeys[pos[i]] = k;
+}
+
+// row_ptr[u] = number of distinct pairs with row < u (binary search over the
+// sorted distinct keys); no atomics, so hub rows cost nothing extra
+__global__ void k_csr_rows(const uint64_t *__restrict__ ukeys, const int32_t *__restrict__ nnz_p, int64_t n,
+                           int32_t *__restrict__ row_ptr, int32_t *__restrict__ deg)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    const int64_t nnz = nnz_p ? *nnz_p : 0;
+    auto lb = [&](uint64_t v) {
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (ukeys[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    int64_t a = lb((uint64_t)u * (uint64_t)n);
+    row_ptr[u] = (int32_t)a;
+    if (u < n) deg[u] = (int32_t)(lb((uint64_t)(u + 1) * (uint64_t)n) - a);
 }
 
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
@@ -146,7 +167,8 @@ int64_t build_csr(fl_ctx *c, int32_t n, int64_t m, const int32_t *src, const int
     int64_t len = 2 * m;
     int32_t *bad = ws<int32_t>(c, "csr_bad", 1);
     FL_CHECK_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), c->stream));
-    fill_i32(c, deg, n, 0);
+    const int32_t *nnz_p = nullptr;
+    const uint64_t *ukeys = nullptr;
     if (m > 0) {
         uint64_t *keys = ws<uint64_t>(c, "csr_keys", (size_t)len);
         uint64_t *tmp = ws<uint64_t>(c, "csr_keys_tmp", (size_t)len);
@@ -162,11 +184,16 @@ int64_t build_csr(fl_ctx *c, int32_t n, int64_t m, const int32_t *src, const int
         int32_t *pos = ws<int32_t>(c, "csr_pos", (size_t)len + 1);
         hipLaunchKernelGGL(k_csr_flags, dim3(grid_for(len, 256)), dim3(256), 0, c->stream, sk, len, sent, flag);
         scan_excl_i32(c, flag, pos, len);
-        hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(len, 256)), dim3(256), 0, c->stream, sk, flag, pos, len,
-                           (int64_t)n, col, deg);
+        uint64_t *uk = alt ? keys : tmp;  // the free ping-pong buffer
+        hipLaunchKernelGGL(k_csr_compact, dim3(grid_for(len, 256)), dim3(256), 0, c->stream, sk, flag, pos, len,
+                           (int64_t)n, col, uk);
         FL_LAUNCH_CHECK();
+        nnz_p = pos + len;
+        ukeys = uk;
     }
-    scan_excl_i32(c, deg, row_ptr, n);
+    hipLaunchKernelGGL(k_csr_rows, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, c->stream, ukeys, nnz_p,
+                       (int64_t)n, row_ptr, deg);
+    FL_LAUNCH_CHECK();
     return (int64_t)read_i32(c, row_ptr + n);
 }
 

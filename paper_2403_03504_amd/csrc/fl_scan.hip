@@ -127,6 +127,9 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Stable scatter of one pass.  Each wave ranks its 1024 keys step by step
+// (ballot masks of equal digits), the block then places its 4096 keys in LDS
+// in digit order and writes every digit's run contiguously (coalesced).
 template <class K, bool HasVal>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin,
                                                        K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
@@ -134,6 +137,10 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
 {
     __shared__ int wcnt[RS_NW][RS_BINS];
     __shared__ int gbase[RS_BINS];
+    __shared__ int lstart[RS_BINS];
+    __shared__ int scan_tmp[RS_NT / WAVE];
+    __shared__ K skey[RS_TILE];
+    __shared__ int32_t sval[HasVal ? RS_TILE : 1];
     const int lane = lane_id(), w = threadIdx.x / WAVE;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&wcnt[0][0])[i] = 0;
     gbase[threadIdx.x] = hscan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
@@ -171,7 +178,8 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
         if (d >= 0 && lane == leader) wcnt[w][d] = b0 + cnt;
     }
     __syncthreads();
-    // per digit: exclusive prefix over the waves of this block
+    // per digit: exclusive prefix over the waves, and the digit's start in
+    // the block's digit-sorted order
     {
         int t = threadIdx.x, run = 0;
 #pragma unroll
@@ -180,15 +188,28 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
             wcnt[ww][t] = run;
             run += cnum;
         }
+        int tot;
+        int ex = block_excl_scan<int, RS_NT>(run, scan_tmp, tot);
+        lstart[t] = ex;
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < RS_STEPS; ++s) {
         const int d = dig[s];
         if (d < 0) continue;
-        int64_t pos = (int64_t)gbase[d] + wcnt[w][d] + off[s];
-        kout[pos] = key[s];
-        if (HasVal) vout[pos] = val[s];
+        const int lp = lstart[d] + wcnt[w][d] + off[s];
+        skey[lp] = key[s];
+        if (HasVal) sval[lp] = val[s];
+    }
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int live = (int)((n - tile0) < RS_TILE ? (n - tile0) : RS_TILE);
+    for (int i = threadIdx.x; i < live; i += RS_NT) {
+        const K k2 = skey[i];
+        const int d = (int)((k2 >> shift) & (RS_BINS - 1));
+        const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
+        kout[pos] = k2;
+        if (HasVal) vout[pos] = sval[i];
     }
 }
 

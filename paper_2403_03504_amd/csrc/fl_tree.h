@@ -81,6 +81,8 @@ int64_t cells_capacity(int64_t n, int leaf, int bits);
 void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *y, const int32_t *deg, int bits,
                 int leaf);
 void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L);
+// Deepest level of the last tree into the statistics block.
+void tree_max_level(fl_ctx *c);
 // Sticky capacity-guard bits of the tree/list kernels (synchronises).
 int32_t tree_error_bits(fl_ctx *c, bool clear);
 

@@ -115,14 +115,22 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
     __syncthreads();
     if (!is_last) return;
     __threadfence();
+    {
+        float4 q = threadIdx.x < gridDim.x ? partial[threadIdx.x] : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        q.x = wave_min_f(q.x);
+        q.y = wave_max_f(q.y);
+        q.z = wave_min_f(q.z);
+        q.w = wave_max_f(q.w);
+        if (lane_id() == 0) red[threadIdx.x / WAVE] = q;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        float4 r = partial[0];
-        for (unsigned b = 1; b < gridDim.x; ++b) {
-            float4 q = partial[b];
-            r.x = fminf(r.x, q.x);
-            r.y = fmaxf(r.y, q.y);
-            r.z = fminf(r.z, q.z);
-            r.w = fmaxf(r.w, q.w);
+        float4 r = red[0];
+        for (int w = 1; w < NT / WAVE; ++w) {
+            r.x = fminf(r.x, red[w].x);
+            r.y = fmaxf(r.y, red[w].y);
+            r.z = fminf(r.z, red[w].z);
+            r.w = fmaxf(r.w, red[w].w);
         }
         double x0 = r.x, x1 = r.y, y0 = r.z, y1 = r.w;
         double L = (x1 - x0) > (y1 - y0) ? (x1 - x0) : (y1 - y0);
@@ -153,14 +161,23 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
     if (idx) idx[i] = i;
 }
 
-__global__ void k_gather(const float *__restrict__ x, const float *__restrict__ y, const int32_t *__restrict__ deg,
-                         const int32_t *__restrict__ perm, int n, float4 *__restrict__ part)
+// (x, y, mass, index) of every node in one 16-byte record, so the Morton
+// gather and the CSR attraction fetch a node with a single access
+__global__ void k_pack(const float *__restrict__ x, const float *__restrict__ y, const int32_t *__restrict__ deg,
+                       int n, float4 *__restrict__ xym)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float m = deg ? (float)(deg[i] + 1) : 1.0f;
+    xym[i] = make_float4(x[i], y[i], m, __int_as_float(i));
+}
+
+__global__ void k_gather(const float4 *__restrict__ xym, const int32_t *__restrict__ perm, int n,
+                         float4 *__restrict__ part)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    int i = perm[k];
-    float m = deg ? (float)(deg[i] + 1) : 1.0f;
-    part[k] = make_float4(x[i], y[i], m, __int_as_float(i));
+    part[k] = xym[perm[k]];
 }
 
 // ---- tree: levels per particle ----------------------------------------------
@@ -252,7 +269,6 @@ __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, co
         t.counts[0] = ncells;
         t.counts[1] = nleaves;
     }
-    atomicMax(&t.counts[2], lam);
     const int64_t H = hash_size(ncells, t.hash_cap);
     const uint64_t ep = *t.epoch;
     for (int l = D + 1; l <= lam; ++l) {
@@ -354,6 +370,28 @@ struct FillSink {
     __device__ void W(int s) { pW[nW++] = s; }
 };
 
+// A coarse leaf N can cover several squares of a cell's ring; it is listed
+// once, at the first ring square (in scan order) that it covers.  Squares of
+// the ring at level l around (cx, cy), scanned dy-major from (-1, -1).
+__device__ __forceinline__ bool ring_seen_before(const TreeView &t, int N, int l, int cx, int cy, int side, int dx,
+                                                 int dy)
+{
+    const int ln = t.lvl[N];
+    if (ln >= l) return false;  // same-level cells cover one square only
+    const int sh = l - ln;
+    const uint32_t nxy = t.ixy[N];
+    const int nx = cell_ix(nxy), ny = cell_iy(nxy);
+    for (int ey = -1; ey <= dy; ++ey)
+        for (int ex = -1; ex <= 1; ++ex) {
+            if (ey == dy && ex >= dx) return false;
+            if (!ex && !ey) continue;
+            const int rx = cx + ex, ry = cy + ey;
+            if (rx < 0 || ry < 0 || rx >= side || ry >= side) continue;
+            if ((rx >> sh) == nx && (ry >> sh) == ny) return true;
+        }
+    return false;
+}
+
 template <class Sink>
 __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c, Sink &sk)
 {
@@ -363,8 +401,6 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
     // V and X: the parent's ring (interacting cells)
     if (l >= 2) {
         const int pl = l - 1, px = cx >> 1, py = cy >> 1, pside = 1 << pl;
-        int seen[8];
-        int ns = 0;
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 if (!dx && !dy) continue;
@@ -381,13 +417,9 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
                         int s = cc[q];
                         if (s >= 0 && !cells_adjacent(l, t.ixy[s], l, cxy)) sk.V(s);
                     }
-                } else {
-                    bool dup = false;
-                    for (int i = 0; i < ns; ++i) dup |= (seen[i] == N);
-                    if (!dup && !cells_adjacent(t.lvl[N], t.ixy[N], l, cxy)) {
-                        seen[ns++] = N;
-                        sk.X(N);
-                    }
+                } else if (!ring_seen_before(t, N, pl, px, py, pside, dx, dy) &&
+                           !cells_adjacent(t.lvl[N], t.ixy[N], l, cxy)) {
+                    sk.X(N);
                 }
             }
     }
@@ -395,8 +427,6 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
     if (is_leaf4(t.child[c])) {
         sk.U(c);
         const int side = 1 << l;
-        int seen[8];
-        int ns = 0;
         int stack[64];
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
@@ -407,12 +437,7 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
                 if (N < 0) continue;
                 int4 ch = t.child[N];
                 if (is_leaf4(ch)) {
-                    bool dup = false;
-                    for (int i = 0; i < ns; ++i) dup |= (seen[i] == N);
-                    if (!dup) {
-                        seen[ns++] = N;
-                        sk.U(N);
-                    }
+                    if (!ring_seen_before(t, N, l, cx, cy, side, dx, dy)) sk.U(N);
                     continue;
                 }
                 int sp = 0;
@@ -480,7 +505,7 @@ __global__ void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX, cons
 }
 
 __global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t *__restrict__ totVX,
-                              const int64_t *__restrict__ totUW, int64_t *__restrict__ st)
+                              const int64_t *__restrict__ totUW, int64_t *__restrict__ st, int n)
 {
     st[0] = counts[0];
     st[1] = counts[1];
@@ -488,7 +513,10 @@ __global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t 
     st[5] = *totVX >> 32;
     st[7] = *totUW & 0xFFFFFFFFll;
     st[4] = *totUW >> 32;
-    st[6] = counts[2];
+    st[8] += st[2];
+    st[9] += st[3];
+    st[10] += 1;
+    st[11] += n;
 }
 
 __global__ void k_export_cells(TreeView t, int32_t *__restrict__ out, int cap)
@@ -560,7 +588,9 @@ void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *
     uint32_t *sk = alt ? k1 : k0;
     int32_t *perm = alt ? i1 : i0;
     t.skey = sk;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, deg, perm, n, t.part);
+    float4 *xym = ws<float4>(c, "t_xym", n);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, deg, n, xym);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float4 *)xym, perm, n, t.part);
     FL_CHECK_HIP(hipMemsetAsync(t.counts, 0, 3 * sizeof(int32_t), c->stream));  // [3] (error bits) is sticky
     hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, sk, n, bits, leaf, t.pack,
                        cnt2);
@@ -596,6 +626,29 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
                        L.X, L.U, L.W, (unsigned long long *)(c->d_stats + 2), cap, lcap, L.v_cap, L.x_cap, L.u_cap,
                        L.w_cap, t.counts + 3);
     hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, L.offVX + cap, L.offUW + lcap,
+                       c->d_stats, t.n);
+    FL_LAUNCH_CHECK();
+}
+
+__global__ void k_max_level(const int32_t *__restrict__ counts, const int32_t *__restrict__ lvl,
+                            int64_t *__restrict__ st)
+{
+    __shared__ int lds[4];
+    int m = 0;
+    for (int i = threadIdx.x; i < counts[0]; i += blockDim.x) m = max(m, lvl[i]);
+    m = wave_max_i(m);
+    if (lane_id() == 0) lds[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) st[6] = max(max(lds[0], lds[1]), max(lds[2], lds[3]));
+}
+
+// deepest level of the last tree into the statistics block (for fl_fmm_stats)
+void tree_max_level(fl_ctx *c)
+{
+    auto it = c->bufs.find("t_lvl");
+    if (it == c->bufs.end() || !it->second.p) return;
+    int32_t *counts = ws_zeroed<int32_t>(c, "t_counts", 4);
+    hipLaunchKernelGGL(k_max_level, dim3(1), dim3(256), 0, c->stream, counts, (const int32_t *)it->second.p,
                        c->d_stats);
     FL_LAUNCH_CHECK();
 }

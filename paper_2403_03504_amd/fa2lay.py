@@ -78,7 +78,7 @@ _sig = {
                      ctypes.POINTER(StepStats)], _i32),
     "fl_fa2_run": ([P, _i32, P, P, P, P, P, ctypes.POINTER(_State), ctypes.POINTER(FA2Params), _i32,
                     ctypes.POINTER(StepStats)], _i32),
-    "fl_fmm_stats": ([P, ctypes.POINTER(_i64)], _i32),
+    "fl_fmm_stats": ([P, ctypes.POINTER(_i64), ctypes.c_int], _i32),
     "fl_set_timing": ([P, ctypes.c_int], _i32),
     "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
 }
@@ -255,10 +255,11 @@ class Context:
             return [(a.swg, a.tra, a.speed) for a in arr[:iters]]
         return None
 
-    def fmm_stats(self) -> dict:
-        out = (_i64 * 8)()
-        self._check(_lib.fl_fmm_stats(self._h, out), "fl_fmm_stats")
-        keys = ("cells", "leaves", "near_pairs", "v_entries", "w_entries", "x_entries", "max_level", "u_entries")
+    def fmm_stats(self, reset: bool = False) -> dict:
+        out = (_i64 * 12)()
+        self._check(_lib.fl_fmm_stats(self._h, out, 1 if reset else 0), "fl_fmm_stats")
+        keys = ("cells", "leaves", "near_pairs", "v_entries", "w_entries", "x_entries", "max_level", "u_entries",
+                "total_near_pairs", "total_v_entries", "evaluations", "total_particles")
         return dict(zip(keys, (int(v) for v in out)))
 
     def set_timing(self, enable: bool):

@@ -38,10 +38,29 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel: str = "k_eval<8>", profile: str = "fa2_fmm_giant2m_p8.md"):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    if the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", profile)
+    src = os.path.join(ROOT, "paper_2403_03504_amd", "csrc", "fl_fmm.hip")
+    try:
+        text = open(path).read()
+        want = re.search(r"fl_fmm.hip\)\[:16\] = ([0-9a-f]{16})", text).group(1)
+        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if want != have:
+            return None
+        row = re.search(r"\| `" + re.escape(kernel) + r"` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.]+) \|", text)
+        return float(row.group(1)) * 1e6 if row else None
+    except (OSError, AttributeError):
+        return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nodes", type=int, default=2_000_000)
     ap.add_argument("--hubs", type=int, default=500)
@@ -51,6 +70,8 @@ def main() -> int:
     ap.add_argument("--direct-steps", type=int, default=1, help="exact-direct comparator iterations (0: skip)")
     ap.add_argument("--sample", type=int, default=1000, help="nodes in the force-error sample (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="finish with a device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,7 +145,8 @@ def main() -> int:
     attract_bytes = 40.0 * g.n + 4.0 * nnz  # compulsory bytes of the attraction/combine pass
     roofline = {"kernel": "k_eval (P2P+L2P+M2P)", "bound": "alu", "achieved": achieved / 1e12,
                 "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
-                "frac_of_published_157": achieved / FP32_PUBLISHED, "traffic": None,
+                "frac_of_published_157": achieved / FP32_PUBLISHED,
+                "traffic": profiled_traffic(f"k_eval<{args.p}>") if args.p == 8 else None,
                 "flop_per_launch": eval_flop, "near_pairs_per_launch": pairs_per_launch,
                 "launch_ms": eval_ms,
                 "attraction": {"achieved_GBps": attract_bytes / (attract_ms * 1e-3) / 1e9,
@@ -149,14 +171,15 @@ def main() -> int:
     xs = x.detach().cpu().numpy()
     ys = y.detach().cpu().numpy()
     deg = G.deg.cpu().numpy()
-    out_fmm = ctx.fa2_forces(G, x, y, prm, components=False)
     prm_d = fl.default_params(repulsion=fl.REP_EXACT)
-    torch.cuda.synchronize()
-    td = time.perf_counter()
-    out_dir = ctx.fa2_forces(G, x, y, prm_d, components=False)
-    torch.cuda.synchronize()
-    direct_rep_s = time.perf_counter() - td
+    direct_rep_s = None
     if args.sample > 0:
+        out_fmm = ctx.fa2_forces(G, x, y, prm, components=False)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        out_dir = ctx.fa2_forces(G, x, y, prm_d, components=False)
+        torch.cuda.synchronize()
+        direct_rep_s = time.perf_counter() - td
         rng = np.random.default_rng(12345)
         tg = np.sort(rng.choice(g.n, size=min(args.sample, g.n), replace=False))
         ex, ey = orc.repulsion_exact(xs, ys, deg + 1.0, targets=tg)
@@ -195,6 +218,16 @@ def main() -> int:
                                   "sample": f"one full FA2 iteration of the same {g.n}-node graph (FP64 FMM "
                                             f"repulsion p={args.p}, leaf<={args.leaf}), {cs:.1f} s"}
         log(f"cpu oracle: {cs:.1f}s per iteration on {orc.num_threads()} threads")
+    if args.copy_calib_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale that turns the counters of the kernels above into bytes
+        nbytes = args.copy_calib_mb << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = nbytes
     ctx.close()
     print(json.dumps(result), flush=True)
     return 0

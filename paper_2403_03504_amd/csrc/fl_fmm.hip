@@ -8,8 +8,10 @@
 // (|.| <= Q 0.71^k / k), incoming coefficient l holds b_l w^l.
 //
 //   k_p2m     leaves: outgoing expansion from the particles (P2M).
-//   k_m2m     one launch per level, deepest first: each cell shifts its
-//             children's expansions to its centre and adds them (M2M).
+//   k_m2m_*   each internal cell shifts its children's expansions to its
+//             centre and adds them (M2M), deepest level first: one workgroup
+//             per level-4 subtree (levels ordered by workgroup barriers),
+//             then one workgroup for the levels above.
 //   k_m2l     every cell: interacting cells' outgoing expansions converted to
 //             an incoming one (M2L, V list) plus particles of coarser
 //             separated leaves (P2L, X list); one lane per source cell.
@@ -22,8 +24,8 @@
 //             direct near field over the U list (P2P).  Lanes hold targets;
 //             sources are read at wave-uniform addresses (scalar loads, SGPR
 //             operands: no per-lane memory traffic in the pair loop).  Leaves
-//             of at most 32 targets run two half-waves on alternate sources,
-//             combined with one xor shuffle (fixed order).
+//             of at most 32 (16) targets run 2 (4) lane groups on interleaved
+//             sources, combined with xor shuffles (fixed order).
 #include "fl_fmm.h"
 
 namespace fl {
@@ -128,67 +130,133 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const float4 *__restric
     }
 }
 
-// k_m2m: the cells of one level shift their children's outgoing expansions
-// to their own centre and add them (child centre at (+-1/4, +-1/4) parent
-// widths, child width 1/2), with the constant operator of each quadrant:
+// Child-to-parent shift of outgoing expansions (M2M, Greengard & Rokhlin
+// Lemma 2.3) in scaled form: child centre at (+-1/4, +-1/4) parent widths,
+// child width 1/2, so each quadrant has a constant operator
 //   A_l = sum_k T_q[l][k] A^q_k,  T_q[0][0] = 1,  T_q[l][0] = -z^l / l,
 //   T_q[l][k] = 2^-k z^(l-k) C(l-1, k-1) (1 <= k <= l).
-// One launch per level, deepest first: the kernel boundary orders the levels.
 template <int P>
-__global__ __launch_bounds__(256) void k_m2m(TreeView t, int level, float2 *__restrict__ M)
+__global__ void k_m2m_table(float2 *__restrict__ T)
 {
-    __shared__ float2 T[4][P + 1][P + 1];
-    const int ncells = t.counts[0];
-    if (level >= t.bits || ncells <= 1) return;
     for (int idx = threadIdx.x; idx < 4 * (P + 1) * (P + 1); idx += blockDim.x) {
         const int q = idx / ((P + 1) * (P + 1)), l = (idx / (P + 1)) % (P + 1), k = idx % (P + 1);
-        const float2 z = make_float2((q & 1) ? 0.25f : -0.25f, (q >> 1) ? 0.25f : -0.25f);
-        float2 v = make_float2(0.f, 0.f);
+        const double zx = (q & 1) ? 0.25 : -0.25, zy = (q >> 1) ? 0.25 : -0.25;
+        double vx = 0.0, vy = 0.0;
         if (l == 0) {
-            v = make_float2(k == 0 ? 1.f : 0.f, 0.f);
-        } else if (k == 0) {
-            float2 zl = make_float2(1.f, 0.f);
-            for (int i = 0; i < l; ++i) zl = cmul(zl, z);
-            v = cscale(zl, -1.0f / (float)l);
+            vx = k == 0 ? 1.0 : 0.0;
         } else if (k <= l) {
-            float2 zl = make_float2(1.f, 0.f);
-            for (int i = 0; i < l - k; ++i) zl = cmul(zl, z);
-            float b = 1.0f;  // C(l-1, k-1)
-            for (int i = 1; i <= k - 1; ++i) b = b * (float)(l - k + i) / (float)i;
-            v = cscale(zl, ldexpf(b, -k));
+            double px = 1.0, py = 0.0;  // z^(l-k)
+            for (int i = 0; i < l - k; ++i) {
+                const double nx = px * zx - py * zy, ny = px * zy + py * zx;
+                px = nx;
+                py = ny;
+            }
+            double f;
+            if (k == 0) {
+                f = -1.0 / (double)l;
+            } else {
+                f = ldexp(1.0, -k);
+                for (int i = 1; i <= k - 1; ++i) f = f * (double)(l - k + i) / (double)i;
+            }
+            vx = f * px;
+            vy = f * py;
         }
-        T[q][l][k] = v;
+        T[idx] = make_float2((float)vx, (float)vy);
     }
-    __syncthreads();
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x) {
-        if (t.lvl[c] != level) continue;
-        const int4 ch = t.child[c];
-        if (is_leaf4(ch)) continue;
-        float2 B[P + 1];
+}
+
+template <int P>
+__device__ __forceinline__ void m2m_cell(const TreeView &t, const float2 *__restrict__ T, float2 *M, int c)
+{
+    const int4 ch = t.child[c];
+    float2 B[P + 1];
 #pragma unroll
-        for (int l = 0; l <= P; ++l) B[l] = make_float2(0.f, 0.f);
-        const int cc[4] = {ch.x, ch.y, ch.z, ch.w};
+    for (int l = 0; l <= P; ++l) B[l] = make_float2(0.f, 0.f);
+    const int cc[4] = {ch.x, ch.y, ch.z, ch.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int cid = cc[q];
-            if (cid < 0) continue;
-            float2 A[P + 1];
-            const float2 *Mq = M + (int64_t)cid * (P + 1);
+    for (int q = 0; q < 4; ++q) {
+        const int cid = cc[q];
+        if (cid < 0) continue;
+        float2 A[P + 1];
+        const float2 *Mq = M + (int64_t)cid * (P + 1);
 #pragma unroll
-            for (int k = 0; k <= P; ++k) A[k] = Mq[k];
+        for (int k = 0; k <= P; ++k) A[k] = Mq[k];
+        const float2 *Tq = T + q * (P + 1) * (P + 1);
 #pragma unroll
-            for (int l = 0; l <= P; ++l) {
+        for (int l = 0; l <= P; ++l) {
 #pragma unroll
-                for (int k = 0; k <= l; ++k) {
-                    const float2 tq = T[q][l][k];
-                    B[l].x += tq.x * A[k].x - tq.y * A[k].y;
-                    B[l].y += tq.x * A[k].y + tq.y * A[k].x;
-                }
+            for (int k = 0; k <= l; ++k) {
+                const float2 tq = Tq[l * (P + 1) + k];
+                B[l].x += tq.x * A[k].x - tq.y * A[k].y;
+                B[l].y += tq.x * A[k].y + tq.y * A[k].x;
             }
         }
-        float2 *Mc = M + (int64_t)c * (P + 1);
+    }
+    float2 *Mc = M + (int64_t)c * (P + 1);
 #pragma unroll
-        for (int l = 0; l <= P; ++l) Mc[l] = B[l];
+    for (int l = 0; l <= P; ++l) Mc[l] = B[l];
+}
+
+// first cell id whose first particle is >= v (cells are sorted by begin)
+__device__ __forceinline__ int first_cell_at(const TreeView &t, int ncells, int v)
+{
+    int lo = 0, hi = ncells;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (t.beg[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int M2M_CUT = 4;  // subtrees rooted at level 4: 256 workgroups
+
+// k_m2m_sub: workgroup r owns the subtree of the level-4 square r (a
+// contiguous range of the pre-order); its internal cells are shifted level by
+// level, deepest first, with a workgroup barrier between levels.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2m_sub(TreeView t, const float2 *__restrict__ T, float2 *M)
+{
+    const int ncells = t.counts[0];
+    const int r = blockIdx.x;
+    const int side = 1 << M2M_CUT;
+    if (ncells <= 1 || M2M_CUT >= t.bits) return;
+    const int64_t H = hash_size(ncells, t.hash_cap);
+    const uint64_t ep = *t.epoch;
+    const int root = hash_find(t, H, ep, M2M_CUT, r % side, r / side);
+    if (root < 0 || is_leaf4(t.child[root])) return;
+    const int c0 = root, c1 = first_cell_at(t, ncells, t.end[root]);
+    int maxl = M2M_CUT;
+    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) maxl = max(maxl, t.lvl[c]);
+    __shared__ int sm[4];
+    maxl = wave_max_i(maxl);
+    if (lane_id() == 0) sm[threadIdx.x / WAVE] = maxl;
+    __syncthreads();
+    maxl = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
+    for (int lev = maxl - 1; lev >= M2M_CUT; --lev) {
+        for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x)
+            if (t.lvl[c] == lev && !is_leaf4(t.child[c])) m2m_cell<P>(t, T, M, c);
+        __syncthreads();
+    }
+}
+
+// k_m2m_top: the internal cells above level 4 (at most 85 squares, found by
+// their (level, ix, iy) key), one workgroup.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2m_top(TreeView t, const float2 *__restrict__ T, float2 *M)
+{
+    const int ncells = t.counts[0];
+    if (ncells <= 1) return;
+    const int64_t H = hash_size(ncells, t.hash_cap);
+    const uint64_t ep = *t.epoch;
+    const int top = min(M2M_CUT, t.bits) - 1;
+    for (int lev = top; lev >= 0; --lev) {
+        const int side = 1 << lev;
+        for (int r = threadIdx.x; r < side * side; r += blockDim.x) {
+            const int c = hash_find(t, H, ep, lev, r % side, r / side);
+            if (c >= 0 && !is_leaf4(t.child[c])) m2m_cell<P>(t, T, M, c);
+        }
+        __syncthreads();
     }
 }
 
@@ -352,10 +420,11 @@ __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restric
 template <int P>
 __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restrict__ part,
                                               const float2 *__restrict__ M, const float2 *__restrict__ Lleaf,
-                                              const int64_t *__restrict__ offUW, const int32_t *__restrict__ U,
-                                              const int32_t *__restrict__ W, const int32_t *__restrict__ cbeg,
-                                              const int32_t *__restrict__ cend, const int32_t *__restrict__ leaf_cell,
-                                              float kr, float *__restrict__ frx, float *__restrict__ fry)
+                                              const int64_t *__restrict__ offUW, const int2 *__restrict__ U,
+                                              const int32_t *__restrict__ nU, const int32_t *__restrict__ W,
+                                              const int32_t *__restrict__ cbeg, const int32_t *__restrict__ cend,
+                                              const int32_t *__restrict__ leaf_cell, float kr,
+                                              float *__restrict__ frx, float *__restrict__ fry)
 {
     const int nleaves = t.counts[1];
     const int lane = lane_id();
@@ -365,22 +434,22 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
         const int c = leaf_cell[li];
         const int b = cbeg[c], e = cend[c];
         const int64_t ou0 = offUW[li], ou1 = offUW[li + 1];
-        const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = (int)(ou1 & 0xFFFFFFFFll);
+        const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = u0 + nU[li];
         const int w0 = (int)(ou0 >> 32), w1 = (int)(ou1 >> 32);
         for (int t0 = b; t0 < e; t0 += WAVE) {
             const int ntc = min(WAVE, e - t0);
-            // small leaves: the two half-waves take alternate sources
-            const bool split = ntc <= WAVE / 2;
-            const int ti = split ? (lane & (WAVE / 2 - 1)) : lane;
-            const int half = split ? (lane >> 5) : 0;
+            // small leaves: G lane groups take interleaved sources
+            const int lg = ntc <= WAVE / 4 ? 2 : ntc <= WAVE / 2 ? 1 : 0;
+            const int ti = lane & ((WAVE >> lg) - 1);
+            const int grp = lane >> (6 - lg);
             const bool valid = ti < ntc;
             const float4 me = part[t0 + (valid ? ti : 0)];
             float fx = 0.f, fy = 0.f;
             for (int ue = u0; ue < u1; ++ue) {
-                const int s = U[ue];
-                const int sb = cbeg[s], se = cend[s];
+                const int2 rg = U[ue];
+                const int sb = rg.x, se = rg.y;
                 int j = sb;
-                if (!split) {
+                if (lg == 0) {
                     for (; j + 4 <= se; j += 4) {
                         const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
                         FL_P2P_PAIR(s0.x, s0.y, s0.z)
@@ -392,42 +461,56 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                         const float4 s0 = part[j];
                         FL_P2P_PAIR(s0.x, s0.y, s0.z)
                     }
-                } else {
+                } else if (lg == 1) {
+                    const bool hi = grp != 0;
                     for (; j + 4 <= se; j += 4) {
                         const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
-                        FL_P2P_PAIR(half ? s1.x : s0.x, half ? s1.y : s0.y, half ? s1.z : s0.z)
-                        FL_P2P_PAIR(half ? s3.x : s2.x, half ? s3.y : s2.y, half ? s3.z : s2.z)
+                        FL_P2P_PAIR(hi ? s1.x : s0.x, hi ? s1.y : s0.y, hi ? s1.z : s0.z)
+                        FL_P2P_PAIR(hi ? s3.x : s2.x, hi ? s3.y : s2.y, hi ? s3.z : s2.z)
                     }
                     for (; j + 2 <= se; j += 2) {
                         const float4 s0 = part[j], s1 = part[j + 1];
-                        FL_P2P_PAIR(half ? s1.x : s0.x, half ? s1.y : s0.y, half ? s1.z : s0.z)
+                        FL_P2P_PAIR(hi ? s1.x : s0.x, hi ? s1.y : s0.y, hi ? s1.z : s0.z)
                     }
                     if (j < se) {
                         const float4 s0 = part[j];
-                        const float m0 = half ? 0.f : s0.z;  // odd tail: lower half only
-                        FL_P2P_PAIR(s0.x, s0.y, m0)
+                        FL_P2P_PAIR(s0.x, s0.y, hi ? 0.f : s0.z)  // odd tail: lower half only
+                    }
+                } else {
+                    // four groups: each lane loads its own source (tiny leaves only)
+                    for (; j < se; j += 4) {
+                        const int jj = j + grp;
+                        const float4 s0 = part[jj < se ? jj : j];
+                        FL_P2P_PAIR(s0.x, s0.y, jj < se ? s0.z : 0.f)
                     }
                 }
             }
-            if (split) {
+            if (lg >= 2) {
+                fx += __shfl_xor(fx, WAVE / 4, WAVE);
+                fy += __shfl_xor(fy, WAVE / 4, WAVE);
+            }
+            if (lg >= 1) {
                 fx += __shfl_xor(fx, WAVE / 2, WAVE);
                 fy += __shfl_xor(fy, WAVE / 2, WAVE);
             }
-            if (half == 0 && valid) {
+            if (grp == 0 && valid) {
                 const CellGeo g = geo(t, c);
+                const double inv_w = 1.0 / g.w;
                 const float2 *Lc = Lleaf + (int64_t)li * (P + 1);
                 // far field: incoming expansion of the leaf (Horner in the scaled variable)
-                const float2 v = rel(me.x, me.y, g);
+                const float2 v = make_float2((float)(((double)me.x - g.cx) * inv_w),
+                                             (float)(((double)me.y - g.cy) * inv_w));
                 float2 acc = cscale(Lc[P], (float)P);
 #pragma unroll
                 for (int l = P - 1; l >= 1; --l) acc = cadd(cmul(acc, v), cscale(Lc[l], (float)l));
-                const float invw = (float)(1.0 / g.w);
-                float2 dphi = cscale(acc, invw);
+                float2 dphi = cscale(acc, (float)inv_w);
                 // W list: outgoing expansions of small separated cells at the particle
                 for (int we = w0; we < w1; ++we) {
                     const int s = W[we];
                     const CellGeo gs = geo(t, s);
-                    const float2 tt = crecip(rel(me.x, me.y, gs));  // w_s / (z - z_s)
+                    const double inv_ws = 1.0 / gs.w;
+                    const float2 tt = crecip(make_float2((float)(((double)me.x - gs.cx) * inv_ws),
+                                                         (float)(((double)me.y - gs.cy) * inv_ws)));
                     const float2 *Ms = M + (int64_t)s * (P + 1);
                     float2 sum = make_float2(Ms[0].x, 0.f);
                     float2 pw = tt;
@@ -438,7 +521,7 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                         sum.y -= (float)k * tk.y;
                         pw = cmul(pw, tt);
                     }
-                    dphi = cadd(dphi, cscale(cmul(tt, sum), (float)(1.0 / gs.w)));
+                    dphi = cadd(dphi, cscale(cmul(tt, sum), (float)inv_ws));
                 }
                 // F = kr m_i (conj(phi'_far) + near field)
                 const float km = kr * me.z;
@@ -463,10 +546,15 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
     const unsigned gc = grid_for(cap, 256, 2048);
     {
         PhaseTimer pt(c, FL_PH_UPWARD);
+        std::string tn = "f_m2m_T" + std::to_string(P);
+        auto it = c->bufs.find(tn);
+        const bool fresh = it == c->bufs.end() || !it->second.p;
+        float2 *T = ws<float2>(c, tn.c_str(), 4 * (P + 1) * (P + 1));
+        if (fresh) hipLaunchKernelGGL(k_m2m_table<P>, dim3(1), dim3(256), 0, c->stream, T);
         hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(lcap, 4, 2048)), dim3(256), 0, c->stream, tv,
                            (const float4 *)t.part, (const int32_t *)t.leaf_cell, M);
-        for (int lev = t.bits - 1; lev >= 0; --lev)
-            hipLaunchKernelGGL(k_m2m<P>, dim3(grid_for(cap, 256, 512)), dim3(256), 0, c->stream, tv, lev, M);
+        hipLaunchKernelGGL(k_m2m_sub<P>, dim3(1 << (2 * M2M_CUT)), dim3(256), 0, c->stream, tv, (const float2 *)T, M);
+        hipLaunchKernelGGL(k_m2m_top<P>, dim3(1), dim3(256), 0, c->stream, tv, (const float2 *)T, M);
         FL_LAUNCH_CHECK();
     }
     {
@@ -480,8 +568,8 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
         PhaseTimer pt(c, FL_PH_EVAL);
         const unsigned ge = grid_for(lcap, 4, 2048);  // 4 waves per block
         hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, M, Ll, L.offUW,
-                           L.U, L.W, (const int32_t *)t.beg, (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr,
-                           frx, fry);
+                           (const int2 *)L.U, (const int32_t *)L.nU, L.W, (const int32_t *)t.beg,
+                           (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr, frx, fry);
         FL_LAUNCH_CHECK();
     }
 }

@@ -12,7 +12,9 @@
 //               index of its first particle among the "cell-start" particles)
 //   hash        (level, ix, iy) -> cell id, open addressing, epoch-tagged
 //   lists       V (M2L) and X (P2L) per cell; U (P2P) and W (M2P) per leaf;
-//               offsets are packed int64 pairs (lo = first list, hi = second)
+//               offsets are packed int64 pairs (lo = first list, hi = second);
+//               U is stored as the leaves' particle ranges, sorted and with
+//               touching ranges merged (a leaf's 3x3 block is a few Morton runs)
 //   M, Lp       outgoing / partial incoming expansions, (p+1) float2 per
 //               cell, scaled by the cell width (coefficient k of an outgoing
 //               expansion holds a_k / w^k, of an incoming one b_k * w^k)
@@ -47,7 +49,9 @@ struct ListBufs {
     int64_t v_cap = 0, x_cap = 0, u_cap = 0, w_cap = 0;
     int64_t *offVX = nullptr;  // [cells_cap + 1]
     int64_t *offUW = nullptr;  // [leaves_cap + 1]
-    int32_t *V = nullptr, *X = nullptr, *U = nullptr, *W = nullptr;
+    int32_t *V = nullptr, *X = nullptr, *W = nullptr;
+    int2 *U = nullptr;         // near-field particle ranges [begin, end), sorted and merged
+    int32_t *nU = nullptr;     // [leaves_cap] merged range count of each leaf
 };
 
 // Device view used by the kernels.

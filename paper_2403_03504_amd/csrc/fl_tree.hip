@@ -362,11 +362,14 @@ struct CountSink {
 };
 
 struct FillSink {
-    int32_t *pV, *pX, *pU, *pW;
+    int32_t *pV, *pX;
+    int2 *pU;
+    int32_t *pW;
+    const int32_t *beg, *end;
     int nV = 0, nX = 0, nU = 0, nW = 0;
     __device__ void V(int s) { pV[nV++] = s; }
     __device__ void X(int s) { pX[nX++] = s; }
-    __device__ void U(int s) { pU[nU++] = s; }
+    __device__ void U(int s) { pU[nU++] = make_int2(beg[s], end[s]); }
     __device__ void W(int s) { pW[nW++] = s; }
 };
 
@@ -475,8 +478,9 @@ __global__ void k_lists_count(TreeView t, int64_t *__restrict__ cntVX, int64_t *
 }
 
 __global__ void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX, const int64_t *__restrict__ offUW,
-                             int32_t *__restrict__ V, int32_t *__restrict__ X, int32_t *__restrict__ U,
-                             int32_t *__restrict__ W, unsigned long long *__restrict__ near_pairs, int64_t cap,
+                             int32_t *__restrict__ V, int32_t *__restrict__ X, int2 *__restrict__ U,
+                             int32_t *__restrict__ nU, int32_t *__restrict__ W,
+                             unsigned long long *__restrict__ near_pairs, int64_t cap,
                              int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap, int64_t w_cap,
                              int32_t *__restrict__ err)
 {
@@ -492,11 +496,29 @@ __global__ void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX, cons
         int64_t o = offVX[c];
         int li = t.leafidx[c];
         int64_t ou = li >= 0 ? offUW[li] : 0;
-        FillSink sk{V + (o & 0xFFFFFFFFll), X + (o >> 32), U + (ou & 0xFFFFFFFFll), W + (ou >> 32)};
+        FillSink sk{V + (o & 0xFFFFFFFFll), X + (o >> 32), U + (ou & 0xFFFFFFFFll), W + (ou >> 32), t.beg, t.end};
         enumerate_lists(t, H, ep, c, sk);
         if (li >= 0) {
+            // sort the near-field ranges by start and merge touching ones
+            int2 *r = sk.pU;
+            const int k = sk.nU;
+            for (int a = 1; a < k; ++a) {
+                const int2 v = r[a];
+                int b = a - 1;
+                while (b >= 0 && r[b].x > v.x) {
+                    r[b + 1] = r[b];
+                    --b;
+                }
+                r[b + 1] = v;
+            }
+            int m = 0;
             int64_t src = 0;
-            for (int i = 0; i < sk.nU; ++i) src += t.end[sk.pU[i]] - t.beg[sk.pU[i]];
+            for (int a = 0; a < k; ++a) {
+                src += r[a].y - r[a].x;
+                if (m > 0 && r[m - 1].y == r[a].x) r[m - 1].y = r[a].y;
+                else r[m++] = r[a];
+            }
+            nU[li] = m;
             pairs = (unsigned long long)src * (unsigned long long)(t.end[c] - t.beg[c]);
         }
     }
@@ -614,7 +636,8 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
     L.offUW = ws<int64_t>(c, "l_offUW", lcap + 1);
     L.V = ws<int32_t>(c, "l_V", L.v_cap);
     L.X = ws<int32_t>(c, "l_X", L.x_cap);
-    L.U = ws<int32_t>(c, "l_U", L.u_cap);
+    L.U = ws<int2>(c, "l_U", L.u_cap);
+    L.nU = ws<int32_t>(c, "l_nU", lcap);
     L.W = ws<int32_t>(c, "l_W", L.w_cap);
     TreeView tv = view(t);
     hipLaunchKernelGGL(k_lists_count, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, cntVX, cntUW);
@@ -623,7 +646,7 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
     scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
     FL_CHECK_HIP(hipMemsetAsync(c->d_stats + 2, 0, sizeof(int64_t), c->stream));
     hipLaunchKernelGGL(k_lists_fill, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, L.offVX, L.offUW, L.V,
-                       L.X, L.U, L.W, (unsigned long long *)(c->d_stats + 2), cap, lcap, L.v_cap, L.x_cap, L.u_cap,
+                       L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2), cap, lcap, L.v_cap, L.x_cap, L.u_cap,
                        L.w_cap, t.counts + 3);
     hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, L.offVX + cap, L.offUW + lcap,
                        c->d_stats, t.n);

@@ -203,6 +203,63 @@ fl_status fl_fa2_run(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32
 enum { FL_NSTATS = 12 };
 fl_status fl_fmm_stats(fl_ctx *ctx, int64_t *out, int reset);
 
+/* ------------------------------------------------------------------------
+ * Kamada-Kawai for small components (sec. 3.1): hop distances d_ij by
+ * breadth-first search (exact for unit weights, equal to the Floyd-Warshall
+ * distances the paper names), then localized stress majorization of the
+ * energy  E = sum_{i<j} d_ij^-2 (|p_i - p_j| - l d_ij)^2: every node of a
+ * component moves together from the previous positions to
+ *   p_i' = sum_{j!=i} w_ij (p_j + l d_ij u_ij) / sum_{j!=i} w_ij,
+ * w_ij = d_ij^-2, u_ij = (p_i - p_j)/|p_i - p_j| (0 when they coincide).
+ * Components are given as node ranges: comp_offsets [host, n_comp+1]
+ * increasing, component k = nodes [comp_offsets[k], comp_offsets[k+1]), each
+ * of 1..256 nodes, with no edge leaving its range.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double l;       /* rescaling constant: desired length per hop (> 0) */
+    int32_t steps;  /* majorization steps */
+} fl_kk_params;
+
+/* Defaults: l = 1, steps = 200. */
+void fl_kk_default_params(fl_kk_params *prm);
+
+/* Hop distances of every component: dist [sum n_k^2] int32, component k's
+ * n_k x n_k row-major matrix of local ids starting at dist_offsets[k] =
+ * sum_{k'<k} n_k'^2 (written to dist_offsets [host, n_comp+1] if not NULL).
+ * Synchronises.  FL_EINVAL if an edge leaves its component or a component is
+ * not connected.  Bit-exact. */
+fl_status fl_hop_distances(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
+                           const int32_t *col_idx, int32_t *dist, int64_t *dist_offsets);
+
+/* prm->steps majorization steps of every component, in place on x, y, given
+ * the distances of fl_hop_distances.  One persistent launch: components are
+ * packed into batches of at most 256 nodes, one workgroup each.
+ * Synchronises. */
+fl_status fl_kk_steps(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *dist, float *x,
+                      float *y, const fl_kk_params *prm);
+
+/* fl_hop_distances then fl_kk_steps, distances in the context workspace. */
+fl_status fl_kk_layout(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
+                       const int32_t *col_idx, float *x, float *y, const fl_kk_params *prm);
+
+/* ------------------------------------------------------------------------
+ * The whole method (sec. 4): connected components of the CSR graph; single
+ * nodes to the origin; components of 2..kk_max_nodes nodes by Kamada-Kawai;
+ * larger ones by fa2_iters ForceAtlas2 iterations each (FMM repulsion when
+ * fa2->repulsion is FL_REP_FMM and the component has >= fmm_min_nodes nodes,
+ * exact otherwise).  x, y in place, caller's node order.  Components are laid
+ * out independently, each about its own centre.  Synchronises.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_comp, n_single, n_kk, n_fa2;
+    int64_t kk_nodes, fa2_nodes;
+    double ms_setup, ms_kk, ms_fa2;
+} fl_layout_stats;
+
+fl_status fl_layout(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                    float *x, float *y, const fl_fa2_params *fa2, int32_t fa2_iters, const fl_kk_params *kk,
+                    int32_t kk_max_nodes, int32_t fmm_min_nodes, fl_layout_stats *stats);
+
 /* Per-phase device timing (HIP events on the context's stream).  When
  * enabled, fl_fa2_step/run record events around their phases; fl_get_timing
  * returns the accumulated milliseconds and launch counts per phase

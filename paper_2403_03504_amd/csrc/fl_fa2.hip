@@ -434,6 +434,23 @@ static void iteration(fl_ctx *c, const GraphArgs &g, const AttractPlan &ap, floa
     st->iter += 1;
 }
 
+// Iterations on a validated graph; no host synchronisation (used by the
+// layout pipeline and the server).  flags must be a zeroed device int.
+void fa2_run_internal(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg, float *x,
+                      float *y, fl_fa2_state *st, const fl_fa2_params *prm, int iters, int32_t *flags)
+{
+    GraphArgs g{n, row_ptr, col, deg};
+    AttractPlan ap = attract_plan(c, g);
+    for (int it = 0; it < iters; ++it) iteration(c, g, ap, x, y, st, prm, flags, nullptr, 0);
+}
+
+void fa2_validate(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg,
+                  const fl_fa2_params *prm)
+{
+    validate_params(prm);
+    validate_graph(c, GraphArgs{n, row_ptr, col, deg});
+}
+
 }  // namespace fl
 
 using namespace fl;

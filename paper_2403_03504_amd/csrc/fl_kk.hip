@@ -1,0 +1,306 @@
+// Kamada-Kawai for the small components (paper sec. 3.1, sec. 4).
+//
+//   k_kk_bfs    hop distances d_ij of one component (<= 256 nodes) per
+//               workgroup: breadth-first search from every source at once.
+//               Each node keeps bitsets over sources (visited, frontier) in
+//               LDS; one level is next(v) = OR_{u in N(v)} frontier(u) minus
+//               visited(v), and every source bit newly set in next(v) is the
+//               distance d+1 of (source, v).  Unit weights, so this equals the
+//               paper's Floyd-Warshall distances (exact integers).
+//   k_kk_steps  localized stress majorization of the energy
+//               E = sum_{i<j} d_ij^-2 (|p_i - p_j| - l d_ij)^2, all nodes of a
+//               component updated together from the previous positions:
+//                 p_i' = sum_{j!=i} w_ij (p_j + l d_ij u_ij) / sum_{j!=i} w_ij,
+//               w_ij = d_ij^-2, u_ij the unit vector from p_j to p_i (0 if the
+//               two coincide).  One workgroup runs every step for a batch of
+//               components (at most 256 nodes in total, one thread per node),
+//               with positions and the batch's distances (uint8) in LDS.
+#include "fl_common.h"
+#include "fl_tree.h"
+
+namespace fl {
+namespace {
+
+constexpr int KK_MAX = 256;
+constexpr int KK_WORDS = KK_MAX / 32;
+
+__global__ __launch_bounds__(256) void k_kk_bfs(const int32_t *__restrict__ comp_off, const int32_t *__restrict__ ids,
+                                                const int64_t *__restrict__ dist_off,
+                                                const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                int32_t *__restrict__ dist, int32_t *__restrict__ err)
+{
+    __shared__ uint32_t vis[KK_MAX][KK_WORDS];
+    __shared__ uint32_t fr[KK_MAX][KK_WORDS];
+    __shared__ uint32_t nx[KK_MAX][KK_WORDS];
+    __shared__ int any;
+    const int c = ids[blockIdx.x];
+    const int cb = comp_off[c], n = comp_off[c + 1] - cb;
+    int32_t *D = dist + dist_off[blockIdx.x];
+    const int nw = (n + 31) / 32;
+    for (int i = threadIdx.x; i < n * nw; i += blockDim.x) {
+        const int v = i / nw, w = i % nw;
+        const uint32_t self = (v / 32 == w) ? (1u << (v % 32)) : 0u;
+        vis[v][w] = self;
+        fr[v][w] = self;
+    }
+    for (int v = threadIdx.x; v < n; v += blockDim.x) D[(int64_t)v * n + v] = 0;
+    __syncthreads();
+    for (int d = 0; d < n; ++d) {
+        if (threadIdx.x == 0) any = 0;
+        for (int i = threadIdx.x; i < n * nw; i += blockDim.x) {
+            const int v = i / nw, w = i % nw;
+            uint32_t acc = 0;
+            for (int e = row_ptr[cb + v]; e < row_ptr[cb + v + 1]; ++e) {
+                const int u = col[e] - cb;
+                if (u < 0 || u >= n) {
+                    atomicOr(err, 1);  // edge leaves the component
+                    continue;
+                }
+                acc |= fr[u][w];
+            }
+            nx[v][w] = acc & ~vis[v][w];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n * nw; i += blockDim.x) {
+            const int v = i / nw, w = i % nw;
+            uint32_t m = nx[v][w];
+            fr[v][w] = m;
+            vis[v][w] |= m;
+            if (m) any = 1;
+            while (m) {
+                const int b = __ffs((int)m) - 1;
+                m &= m - 1;
+                D[(int64_t)(w * 32 + b) * n + v] = d + 1;
+            }
+        }
+        __syncthreads();
+        if (!any) break;
+        __syncthreads();
+    }
+    // a pair never reached means the "component" was not connected
+    for (int i = threadIdx.x; i < n * nw; i += blockDim.x) {
+        const int v = i / nw, w = i % nw;
+        const int lim = min(32, n - w * 32);
+        const uint32_t full = lim == 32 ? 0xFFFFFFFFu : ((1u << lim) - 1u);
+        if ((vis[v][w] & full) != full) atomicOr(err, 2);
+    }
+}
+
+struct KKBatch {
+    int32_t c0, c1;  // components [c0, c1) of the full list: consecutive node ranges
+    int32_t k0;      // index of c0 in the subset (for the distance offsets)
+    int32_t pad;
+};
+
+__global__ __launch_bounds__(256) void k_kk_steps(const KKBatch *__restrict__ batches,
+                                                  const int32_t *__restrict__ comp_off,
+                                                  const int64_t *__restrict__ dist_off,
+                                                  const int32_t *__restrict__ dist, float *__restrict__ x,
+                                                  float *__restrict__ y, float l, int steps)
+{
+    __shared__ float2 pos[KK_MAX];
+    __shared__ uint8_t D8[KK_MAX * KK_MAX];
+    __shared__ int cstart[KK_MAX + 1];  // batch-local node offsets of the components
+    __shared__ int dbase[KK_MAX];       // batch-local distance offsets
+    const KKBatch bt = batches[blockIdx.x];
+    const int ncomp = bt.c1 - bt.c0;
+    const int nb = comp_off[bt.c0];
+    const int nnodes = comp_off[bt.c1] - nb;
+    if (threadIdx.x == 0) {
+        int s = 0, db = 0;
+        for (int k = 0; k < ncomp; ++k) {
+            const int nk = comp_off[bt.c0 + k + 1] - comp_off[bt.c0 + k];
+            cstart[k] = s;
+            dbase[k] = db;
+            s += nk;
+            db += nk * nk;
+        }
+        cstart[ncomp] = s;
+    }
+    __syncthreads();
+    // stage distances as bytes (components of <= 256 nodes have d <= 255)
+    for (int k = 0; k < ncomp; ++k) {
+        const int nk = cstart[k + 1] - cstart[k];
+        const int32_t *Dk = dist + dist_off[bt.k0 + k];
+        for (int i = threadIdx.x; i < nk * nk; i += blockDim.x) D8[dbase[k] + i] = (uint8_t)Dk[i];
+    }
+    const int t = threadIdx.x;
+    int k = 0;
+    if (t < nnodes) {
+        while (cstart[k + 1] <= t) ++k;
+        pos[t] = make_float2(x[nb + t], y[nb + t]);
+    }
+    __syncthreads();
+    const int s0 = t < nnodes ? cstart[k] : 0;
+    const int nk = t < nnodes ? cstart[k + 1] - s0 : 0;
+    const int li = t - s0;
+    const uint8_t *Drow = D8 + (t < nnodes ? dbase[k] + li * nk : 0);
+    for (int st = 0; st < steps; ++st) {
+        float2 np = make_float2(0.f, 0.f);
+        if (t < nnodes) {
+            const float2 pi = pos[t];
+            float sw = 0.f, ax = 0.f, ay = 0.f;
+            for (int j = 0; j < nk; ++j) {
+                if (j == li) continue;
+                const float2 pj = pos[s0 + j];
+                const float d = (float)Drow[j];
+                const float w = 1.0f / (d * d);
+                const float dx = pi.x - pj.x, dy = pi.y - pj.y;
+                const float r2 = dx * dx + dy * dy;
+                const float rinv = r2 > 0.f ? rsqrtf(r2) : 0.f;
+                const float ld = l * d * w;  // w l d
+                sw += w;
+                ax += w * pj.x + ld * dx * rinv;
+                ay += w * pj.y + ld * dy * rinv;
+            }
+            np = sw > 0.f ? make_float2(ax / sw, ay / sw) : pi;
+        }
+        __syncthreads();
+        if (t < nnodes) pos[t] = np;
+        __syncthreads();
+    }
+    if (t < nnodes) {
+        x[nb + t] = pos[t].x;
+        y[nb + t] = pos[t].y;
+    }
+}
+
+}  // namespace
+
+// Components taken by Kamada-Kawai: `ids` (ascending) index the full offset
+// list.  Batches join runs of consecutive ids (adjacent node ranges) up to
+// KK_MAX nodes; dist_off[k] = sum of n^2 over ids[0..k).
+struct KKPlan {
+    std::vector<int32_t> ids;
+    std::vector<int64_t> doff;
+    std::vector<KKBatch> batches;
+    int32_t *d_off = nullptr, *d_ids = nullptr;
+    int64_t *d_doff = nullptr;
+    KKBatch *d_batches = nullptr;
+};
+
+static KKPlan kk_plan(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids)
+{
+    KKPlan p;
+    p.ids = ids;
+    const int m = (int)ids.size();
+    p.doff.resize(m + 1);
+    p.doff[0] = 0;
+    for (int k = 0; k < m; ++k) {
+        const int cid = ids[k];
+        FL_REQUIRE(cid >= 0 && cid < n_all && (k == 0 || cid > ids[k - 1]), "component ids must be ascending");
+        const int64_t nk = off[cid + 1] - off[cid];
+        FL_REQUIRE(nk >= 1, "component offsets must be increasing");
+        FL_REQUIRE(nk <= KK_MAX, "Kamada-Kawai components are limited to 256 nodes");
+        p.doff[k + 1] = p.doff[k] + nk * nk;
+    }
+    int k = 0;
+    while (k < m) {
+        int e = k, tot = 0;
+        while (e < m && (e == k || ids[e] == ids[e - 1] + 1) && tot + (off[ids[e] + 1] - off[ids[e]]) <= KK_MAX) {
+            tot += off[ids[e] + 1] - off[ids[e]];
+            ++e;
+        }
+        p.batches.push_back(KKBatch{ids[k], ids[e - 1] + 1, k, 0});
+        k = e;
+    }
+    p.d_off = ws<int32_t>(c, "kk_off", n_all + 1);
+    p.d_ids = ws<int32_t>(c, "kk_ids", m > 0 ? m : 1);
+    p.d_doff = ws<int64_t>(c, "kk_doff", m + 1);
+    p.d_batches = ws<KKBatch>(c, "kk_batches", p.batches.size() + 1);
+    FL_CHECK_HIP(hipMemcpyAsync(p.d_off, off, sizeof(int32_t) * (n_all + 1), hipMemcpyHostToDevice, c->stream));
+    if (m > 0) FL_CHECK_HIP(hipMemcpyAsync(p.d_ids, p.ids.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c->stream));
+    FL_CHECK_HIP(hipMemcpyAsync(p.d_doff, p.doff.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, c->stream));
+    if (!p.batches.empty())
+        FL_CHECK_HIP(hipMemcpyAsync(p.d_batches, p.batches.data(), sizeof(KKBatch) * p.batches.size(),
+                                    hipMemcpyHostToDevice, c->stream));
+    return p;
+}
+
+static void kk_bfs(fl_ctx *c, const KKPlan &p, const int32_t *row_ptr, const int32_t *col, int32_t *dist)
+{
+    if (p.ids.empty()) return;
+    int32_t *err = ws<int32_t>(c, "kk_err", 1);
+    FL_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
+    hipLaunchKernelGGL(k_kk_bfs, dim3((unsigned)p.ids.size()), dim3(256), 0, c->stream, p.d_off, p.d_ids, p.d_doff,
+                       row_ptr, col, dist, err);
+    FL_LAUNCH_CHECK();
+    int32_t e = read_i32(c, err);  // also keeps the plan's host vectors alive until the copies are done
+    if (e & 1) throw Error(FL_EINVAL, "an edge leaves its component's id range");
+    if (e & 2) throw Error(FL_EINVAL, "a component is not connected");
+}
+
+static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float *x, float *y, double l, int steps)
+{
+    if (p.batches.empty()) return;
+    hipLaunchKernelGGL(k_kk_steps, dim3((unsigned)p.batches.size()), dim3(256), 0, c->stream, p.d_batches, p.d_off,
+                       p.d_doff, dist, x, y, (float)l, steps);
+    FL_LAUNCH_CHECK();
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));  // host plan vectors outlive the async copies
+}
+
+// Kamada-Kawai for the components `ids` of a graph whose components are the
+// node ranges [off[k], off[k+1]); distances in the context workspace.
+void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,
+                      const int32_t *row_ptr, const int32_t *col, float *x, float *y, double l, int steps)
+{
+    if (ids.empty()) return;
+    KKPlan p = kk_plan(c, n_all, off, ids);
+    int32_t *dist = ws<int32_t>(c, "kk_dist", p.doff.back() > 0 ? p.doff.back() : 1);
+    kk_bfs(c, p, row_ptr, col, dist);
+    kk_run_steps(c, p, dist, x, y, l, steps);
+}
+
+static std::vector<int32_t> iota_ids(int n)
+{
+    std::vector<int32_t> v(n);
+    for (int i = 0; i < n; ++i) v[i] = i;
+    return v;
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+void fl_kk_default_params(fl_kk_params *p)
+{
+    if (!p) return;
+    p->l = 1.0;
+    p->steps = 200;
+}
+
+fl_status fl_hop_distances(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
+                           const int32_t *col_idx, int32_t *dist, int64_t *dist_offsets)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(n_comp >= 1 && comp_offsets && row_ptr && col_idx && dist, "fl_hop_distances: bad arguments");
+    KKPlan p = kk_plan(c, n_comp, comp_offsets, iota_ids(n_comp));
+    kk_bfs(c, p, row_ptr, col_idx, dist);
+    if (dist_offsets) std::memcpy(dist_offsets, p.doff.data(), sizeof(int64_t) * (n_comp + 1));
+    FL_API_END(c)
+}
+
+fl_status fl_kk_steps(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, const int32_t *dist, float *x, float *y,
+                      const fl_kk_params *prm)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(n_comp >= 1 && comp_offsets && dist && x && y && prm, "fl_kk_steps: bad arguments");
+    FL_REQUIRE(prm->l > 0.0 && std::isfinite(prm->l) && prm->steps >= 0, "fl_kk_steps: need l > 0, steps >= 0");
+    KKPlan p = kk_plan(c, n_comp, comp_offsets, iota_ids(n_comp));
+    kk_run_steps(c, p, dist, x, y, prm->l, prm->steps);
+    FL_API_END(c)
+}
+
+fl_status fl_kk_layout(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
+                       const int32_t *col_idx, float *x, float *y, const fl_kk_params *prm)
+{
+    FL_API_BEGIN(c)
+    FL_REQUIRE(n_comp >= 1 && comp_offsets && row_ptr && col_idx && x && y && prm, "fl_kk_layout: bad arguments");
+    FL_REQUIRE(prm->l > 0.0 && std::isfinite(prm->l) && prm->steps >= 0, "fl_kk_layout: need l > 0, steps >= 0");
+    kk_layout_subset(c, n_comp, comp_offsets, iota_ids(n_comp), row_ptr, col_idx, x, y, prm->l, prm->steps);
+    FL_API_END(c)
+}
+
+}  // extern "C"

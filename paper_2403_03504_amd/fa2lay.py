@@ -31,7 +31,8 @@ PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact"
 EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
             "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_run", "fl_fmm_stats",
-            "fl_set_timing", "fl_get_timing")
+            "fl_set_timing", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances", "fl_kk_steps",
+            "fl_kk_layout", "fl_layout")
 
 
 class FlError(RuntimeError):
@@ -51,6 +52,16 @@ class FA2Params(ctypes.Structure):
 class _State(ctypes.Structure):
     _fields_ = [("fx_prev", ctypes.c_void_p), ("fy_prev", ctypes.c_void_p), ("scalars", ctypes.c_void_p),
                 ("iter", ctypes.c_int64)]
+
+
+class KKParams(ctypes.Structure):
+    _fields_ = [("l", ctypes.c_double), ("steps", ctypes.c_int32)]
+
+
+class LayoutStats(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int32), ("n_single", ctypes.c_int32), ("n_kk", ctypes.c_int32),
+                ("n_fa2", ctypes.c_int32), ("kk_nodes", ctypes.c_int64), ("fa2_nodes", ctypes.c_int64),
+                ("ms_setup", ctypes.c_double), ("ms_kk", ctypes.c_double), ("ms_fa2", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):
@@ -80,6 +91,12 @@ _sig = {
                     ctypes.POINTER(StepStats)], _i32),
     "fl_fmm_stats": ([P, ctypes.POINTER(_i64), ctypes.c_int], _i32),
     "fl_set_timing": ([P, ctypes.c_int], _i32),
+    "fl_kk_default_params": ([ctypes.POINTER(KKParams)], None),
+    "fl_hop_distances": ([P, _i32, P, P, P, P, P], _i32),
+    "fl_kk_steps": ([P, _i32, P, P, P, P, ctypes.POINTER(KKParams)], _i32),
+    "fl_kk_layout": ([P, _i32, P, P, P, P, P, ctypes.POINTER(KKParams)], _i32),
+    "fl_layout": ([P, _i32, P, P, P, P, P, ctypes.POINTER(FA2Params), _i32, ctypes.POINTER(KKParams), _i32, _i32,
+                   ctypes.POINTER(LayoutStats)], _i32),
     "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
 }
 for _name, (_args, _res) in _sig.items():
@@ -100,6 +117,22 @@ def default_params(**kw) -> FA2Params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def kk_params(**kw) -> KKParams:
+    p = KKParams()
+    _lib.fl_kk_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _host_i32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _ptr(t: torch.Tensor | None, dtype=None):
@@ -254,6 +287,39 @@ class Context:
         if stats:
             return [(a.swg, a.tra, a.speed) for a in arr[:iters]]
         return None
+
+    # Kamada-Kawai (components given as node ranges, host offsets) ----------
+    def hop_distances(self, g: Graph, comp_offsets):
+        import numpy as np
+        off, offp = _host_i32(comp_offsets)
+        sizes = np.diff(off.astype(np.int64))
+        dist = torch.empty(int(np.sum(sizes * sizes)), dtype=torch.int32, device=self.device)
+        doff = np.zeros(off.shape[0], dtype=np.int64)
+        self._check(_lib.fl_hop_distances(self._h, off.shape[0] - 1, offp, _ptr(g.row_ptr, torch.int32),
+                                          _ptr(g.col, torch.int32), _ptr(dist),
+                                          doff.ctypes.data_as(ctypes.c_void_p)), "fl_hop_distances")
+        return dist, doff
+
+    def kk_steps(self, comp_offsets, dist: torch.Tensor, x: torch.Tensor, y: torch.Tensor, params: KKParams):
+        off, offp = _host_i32(comp_offsets)
+        self._check(_lib.fl_kk_steps(self._h, off.shape[0] - 1, offp, _ptr(dist, torch.int32),
+                                     _ptr(x, torch.float32), _ptr(y, torch.float32), ctypes.byref(params)),
+                    "fl_kk_steps")
+
+    def kk_layout(self, g: Graph, comp_offsets, x: torch.Tensor, y: torch.Tensor, params: KKParams):
+        off, offp = _host_i32(comp_offsets)
+        self._check(_lib.fl_kk_layout(self._h, off.shape[0] - 1, offp, _ptr(g.row_ptr, torch.int32),
+                                      _ptr(g.col, torch.int32), _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                      ctypes.byref(params)), "fl_kk_layout")
+
+    def layout(self, g: Graph, x: torch.Tensor, y: torch.Tensor, fa2: FA2Params, fa2_iters: int,
+               kk: KKParams, kk_max_nodes: int = 256, fmm_min_nodes: int = 4096) -> dict:
+        st = LayoutStats()
+        self._check(_lib.fl_layout(self._h, g.n, _ptr(g.row_ptr, torch.int32), _ptr(g.col, torch.int32),
+                                   _ptr(g.deg, torch.int32), _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                   ctypes.byref(fa2), fa2_iters, ctypes.byref(kk), kk_max_nodes, fmm_min_nodes,
+                                   ctypes.byref(st)), "fl_layout")
+        return {k: getattr(st, k) for k, _ in LayoutStats._fields_}
 
     def fmm_stats(self, reset: bool = False) -> dict:
         out = (_i64 * 12)()

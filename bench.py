@@ -57,6 +57,57 @@ def profiled_traffic(kernel: str = "k_eval<8>", profile: str = "fa2_fmm_giant2m_
         return None
 
 
+def serving(args, fl, w, np) -> dict:
+    """Layout jobs arriving as a Poisson stream, n ~ round(exp(U(ln 100,
+    ln 1e6))) bipartite graphs (40 % transactions, n/4000 hubs), each laid out
+    with `serving_iters` iterations; once with continuous batching (several
+    slots, admission by memory budget) and once one job at a time."""
+    import math
+    import threading
+    rng = np.random.Generator(np.random.PCG64(5))
+    J = args.serving_jobs
+    sizes = np.round(np.exp(rng.uniform(math.log(100), math.log(1e6), size=J))).astype(np.int64)
+    gaps = rng.exponential(1.0 / args.serving_rate, size=J)
+    t = time.perf_counter()
+    jobs = [w.scaled(5_000_000 + i, int(n)) for i, n in enumerate(sizes)]
+    log(f"serving: generated {J} jobs ({int(sizes.sum())} nodes) in {time.perf_counter() - t:.1f}s")
+    prm = fl.default_params(p=args.p, leaf_size=args.leaf)
+    out = {"jobs": J, "rate_per_s": args.serving_rate, "iters": args.serving_iters,
+           "nodes_total": int(sizes.sum()), "sizes": "log-uniform 100..1e6", "budget_GiB": 32}
+
+    def run(slots):
+        srv = fl.Server(0, budget_bytes=32 << 30, slots=slots)
+        ids = []
+
+        def feeder():
+            for g, dt in zip(jobs, gaps):
+                time.sleep(dt)
+                ids.append(srv.submit(g.n, g.src, g.dst, g.x, g.y, args.serving_iters, prm))
+
+        th = threading.Thread(target=feeder)
+        t0 = time.perf_counter()
+        th.start()
+        th.join()
+        times = []
+        for i in ids:
+            assert srv.wait(i, 600.0) == fl.JOB_DONE
+            times.append(srv.result(i)[2])
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([td - ta for ta, ts, td in times]) * 1e3
+        span = max(td for _, _, td in times) - min(ta for ta, _, _ in times)
+        return {"slots": slots, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "node_updates_per_s": float(sizes.sum()) * args.serving_iters / span,
+                "wall_s": wall}
+
+    out["batched"] = run(args.serving_slots)
+    log(f"serving ({args.serving_slots} slots): p50 {out['batched']['p50_ms']:.1f} ms, "
+        f"p99 {out['batched']['p99_ms']:.1f} ms, {out['batched']['node_updates_per_s']:.3g} node-updates/s")
+    out["one_at_a_time"] = run(1)
+    log(f"serving (1 slot): p50 {out['one_at_a_time']['p50_ms']:.1f} ms, p99 {out['one_at_a_time']['p99_ms']:.1f} ms")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +121,10 @@ def main() -> int:
     ap.add_argument("--direct-steps", type=int, default=1, help="exact-direct comparator iterations (0: skip)")
     ap.add_argument("--sample", type=int, default=1000, help="nodes in the force-error sample (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serving-jobs", type=int, default=100, help="jobs in the serving run (0: skip)")
+    ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrival rate, jobs/s")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-iters", type=int, default=200)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="finish with a device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -218,6 +273,10 @@ def main() -> int:
                                   "sample": f"one full FA2 iteration of the same {g.n}-node graph (FP64 FMM "
                                             f"repulsion p={args.p}, leaf<={args.leaf}), {cs:.1f} s"}
         log(f"cpu oracle: {cs:.1f}s per iteration on {orc.num_threads()} threads")
+    if args.serving_jobs > 0:
+        ctx.close()
+        result["serving"] = serving(args, fl, w, np)
+        ctx = fl.Context(0)
     if args.copy_calib_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
         # the scale that turns the counters of the kernels above into bytes

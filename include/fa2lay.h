@@ -260,6 +260,59 @@ fl_status fl_layout(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_
                     float *x, float *y, const fl_fa2_params *fa2, int32_t fa2_iters, const fl_kk_params *kk,
                     int32_t kk_max_nodes, int32_t fmm_min_nodes, fl_layout_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Layout server: continuous batching of layout jobs on one GPU.  Jobs are
+ * copied at submission and queued FIFO; `max_slots` workers (one HIP stream
+ * and context each) admit the head of the queue whenever the estimated device
+ * bytes of the running jobs plus its own fit `mem_budget_bytes`, so jobs that
+ * arrive while others run start as soon as a slot and memory free up, and
+ * their kernels overlap on the device.  A job runs fl_build_csr + fl_layout
+ * (kk_max_nodes 256, fmm_min_nodes 4096) and its positions come back to host
+ * memory.  Results do not depend on the other jobs in flight.  All server
+ * calls are thread-safe.  Times are seconds since the server was created.
+ * ------------------------------------------------------------------------ */
+typedef struct fl_server fl_server;
+enum { FL_JOB_QUEUED = 0, FL_JOB_RUNNING = 1, FL_JOB_DONE = 2, FL_JOB_FAILED = 3, FL_JOB_CANCELED = 4 };
+
+typedef struct {
+    int32_t n;                /* nodes */
+    int64_t m;                /* directed edge records */
+    const int32_t *src, *dst; /* [host, m] */
+    const float *x0, *y0;     /* [host, n] initial positions */
+    int32_t iters;            /* ForceAtlas2 iterations per large component */
+    fl_fa2_params params;
+} fl_job;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, canceled, queued, running;
+    int64_t bytes_in_use, peak_bytes, node_updates;
+} fl_server_stats;
+
+fl_status fl_server_create(fl_server **out, int device, size_t mem_budget_bytes, int32_t max_slots);
+/* Test hook: a server whose workers sleep ns_per_node_update * n * iters
+ * nanoseconds instead of using the GPU (results = initial positions). */
+fl_status fl_server_create_fake(fl_server **out, size_t mem_budget_bytes, int32_t max_slots,
+                                double ns_per_node_update);
+/* Copies the job's arrays; never waits for the GPU.  FL_ENOMEM if the job
+ * alone exceeds the budget, FL_EINVAL for a malformed job. */
+fl_status fl_server_submit(fl_server *srv, const fl_job *job, uint64_t *job_id);
+fl_status fl_server_poll(fl_server *srv, uint64_t job_id, int32_t *state);
+/* Block until the job is done, failed or cancelled (timeout_s < 0: no limit;
+ * FL_EBUSY on timeout). */
+fl_status fl_server_wait(fl_server *srv, uint64_t job_id, double timeout_s, int32_t *state);
+/* Positions [host, n each; either may be NULL] and times3 [host, 3]:
+ * arrival, start, completion.  FL_EBUSY while queued/running, FL_EHIP if the
+ * job failed (fl_server_last_error has its message), FL_ECANCELED. */
+fl_status fl_server_result(fl_server *srv, uint64_t job_id, float *x_host, float *y_host, double *times3);
+/* Forget a finished job and free its host results. */
+fl_status fl_server_release(fl_server *srv, uint64_t job_id);
+/* Cancel a queued job (FL_EBUSY once it runs). */
+fl_status fl_server_cancel(fl_server *srv, uint64_t job_id);
+fl_status fl_server_stats_get(fl_server *srv, fl_server_stats *out);
+const char *fl_server_last_error(const fl_server *srv);
+/* Cancels queued jobs, waits for running ones, frees everything. */
+void fl_server_destroy(fl_server *srv);
+
 /* Per-phase device timing (HIP events on the context's stream).  When
  * enabled, fl_fa2_step/run record events around their phases; fl_get_timing
  * returns the accumulated milliseconds and launch counts per phase

@@ -32,7 +32,10 @@ EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_syn
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
             "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_run", "fl_fmm_stats",
             "fl_set_timing", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances", "fl_kk_steps",
-            "fl_kk_layout", "fl_layout")
+            "fl_kk_layout", "fl_layout", "fl_server_create", "fl_server_create_fake", "fl_server_submit",
+            "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release", "fl_server_cancel",
+            "fl_server_stats_get", "fl_server_last_error", "fl_server_destroy")
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELED = 0, 1, 2, 3, 4
 
 
 class FlError(RuntimeError):
@@ -62,6 +65,17 @@ class LayoutStats(ctypes.Structure):
     _fields_ = [("n_comp", ctypes.c_int32), ("n_single", ctypes.c_int32), ("n_kk", ctypes.c_int32),
                 ("n_fa2", ctypes.c_int32), ("kk_nodes", ctypes.c_int64), ("fa2_nodes", ctypes.c_int64),
                 ("ms_setup", ctypes.c_double), ("ms_kk", ctypes.c_double), ("ms_fa2", ctypes.c_double)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p), ("y0", ctypes.c_void_p), ("iters", ctypes.c_int32),
+                ("params", FA2Params)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "failed", "canceled", "queued",
+                                               "running", "bytes_in_use", "peak_bytes", "node_updates")]
 
 
 class StepStats(ctypes.Structure):
@@ -99,6 +113,20 @@ _sig = {
                    ctypes.POINTER(LayoutStats)], _i32),
     "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
 }
+_U64 = ctypes.c_uint64
+_sig.update({
+    "fl_server_create": ([ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, _i32], _i32),
+    "fl_server_create_fake": ([ctypes.POINTER(P), ctypes.c_size_t, _i32, ctypes.c_double], _i32),
+    "fl_server_submit": ([P, ctypes.POINTER(_Job), ctypes.POINTER(_U64)], _i32),
+    "fl_server_poll": ([P, _U64, ctypes.POINTER(_i32)], _i32),
+    "fl_server_wait": ([P, _U64, ctypes.c_double, ctypes.POINTER(_i32)], _i32),
+    "fl_server_result": ([P, _U64, P, P, P], _i32),
+    "fl_server_release": ([P, _U64], _i32),
+    "fl_server_cancel": ([P, _U64], _i32),
+    "fl_server_stats_get": ([P, ctypes.POINTER(ServerStats)], _i32),
+    "fl_server_last_error": ([P], ctypes.c_char_p),
+    "fl_server_destroy": ([P], None),
+})
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -336,3 +364,79 @@ class Context:
         cnt = (_i64 * len(PHASES))()
         self._check(_lib.fl_get_timing(self._h, ms, cnt), "fl_get_timing")
         return {p: (ms[i], int(cnt[i])) for i, p in enumerate(PHASES)}
+
+
+class Server:
+    """Continuous-batching layout server (fl_server_*).  Jobs are host arrays;
+    results come back as host numpy arrays with arrival/start/done times."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 32 << 30, slots: int = 4,
+                 fake_ns_per_update: float = 0.0):
+        self._h = P()
+        if fake_ns_per_update > 0:
+            st = _lib.fl_server_create_fake(ctypes.byref(self._h), budget_bytes, slots, fake_ns_per_update)
+        else:
+            st = _lib.fl_server_create(ctypes.byref(self._h), device, budget_bytes, slots)
+        if st != FL_OK:
+            raise FlError(st, "fl_server_create failed")
+        self._keep = {}
+
+    def _check(self, st: int, what: str):
+        if st != FL_OK:
+            raise FlError(st, f"{what}: {_lib.fl_server_last_error(self._h).decode()}")
+
+    def submit(self, n: int, src, dst, x0, y0, iters: int, params: FA2Params) -> int:
+        import numpy as np
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        x0 = np.ascontiguousarray(x0, dtype=np.float32)
+        y0 = np.ascontiguousarray(y0, dtype=np.float32)
+        j = _Job(n, src.shape[0], src.ctypes.data, dst.ctypes.data, x0.ctypes.data, y0.ctypes.data, iters, params)
+        jid = _U64()
+        self._check(_lib.fl_server_submit(self._h, ctypes.byref(j), ctypes.byref(jid)), "fl_server_submit")
+        self._keep[jid.value] = n
+        return int(jid.value)
+
+    def poll(self, jid: int) -> int:
+        s = _i32()
+        self._check(_lib.fl_server_poll(self._h, jid, ctypes.byref(s)), "fl_server_poll")
+        return int(s.value)
+
+    def wait(self, jid: int, timeout: float = -1.0) -> int:
+        s = _i32()
+        st = _lib.fl_server_wait(self._h, jid, timeout, ctypes.byref(s))
+        if st not in (FL_OK, FL_EBUSY):
+            self._check(st, "fl_server_wait")
+        return int(s.value)
+
+    def result(self, jid: int, release: bool = True):
+        import numpy as np
+        n = self._keep[jid]
+        x = np.empty(n, np.float32)
+        y = np.empty(n, np.float32)
+        t = np.zeros(3)
+        st = _lib.fl_server_result(self._h, jid, x.ctypes.data, y.ctypes.data, t.ctypes.data)
+        self._check(st, "fl_server_result")
+        if release:
+            _lib.fl_server_release(self._h, jid)
+            self._keep.pop(jid, None)
+        return x, y, tuple(t)
+
+    def cancel(self, jid: int):
+        self._check(_lib.fl_server_cancel(self._h, jid), "fl_server_cancel")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        self._check(_lib.fl_server_stats_get(self._h, ctypes.byref(s)), "fl_server_stats_get")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fl_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

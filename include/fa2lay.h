@@ -189,7 +189,11 @@ fl_status fl_fa2_step(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int3
 
 /* `iters` iterations with no host synchronisation inside the loop.
  * per_iter [host, iters entries] may be NULL (if not, synchronises at the
- * end).  Checks for non-finite values at the end of the run. */
+ * end).  Checks for non-finite values at the end of the run.  When per_iter
+ * is NULL, timing is off, graphs are on (fl_set_graphs) and iters >= 4, the
+ * first iteration runs eagerly and one more is captured into a HIP graph on
+ * the context's private streams and replayed; the results are bitwise those
+ * of eager iterations.  The call returns after the work is done. */
 fl_status fl_fa2_run(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                      const int32_t *deg, float *x, float *y, fl_fa2_state *state, const fl_fa2_params *prm,
                      int32_t iters, fl_step_stats *per_iter);
@@ -248,7 +252,11 @@ fl_status fl_kk_layout(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets,
  * larger ones by fa2_iters ForceAtlas2 iterations each (FMM repulsion when
  * fa2->repulsion is FL_REP_FMM and the component has >= fmm_min_nodes nodes,
  * exact otherwise).  x, y in place, caller's node order.  Components are laid
- * out independently, each about its own centre.  Synchronises.
+ * out independently, each about its own centre.  The ForceAtlas2 components
+ * run concurrently: they are dealt, largest first, to up to 8 branch streams
+ * owned by the context, and one HIP graph holding an iteration of every
+ * component is replayed (results bitwise those of each component run alone
+ * by fl_fa2_run).  Synchronises.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t n_comp, n_single, n_kk, n_fa2;
@@ -320,6 +328,9 @@ void fl_server_destroy(fl_server *srv);
 enum { FL_PH_TREE = 0, FL_PH_LISTS, FL_PH_UPWARD, FL_PH_M2L, FL_PH_EVAL, FL_PH_ATTRACT, FL_PH_UPDATE,
        FL_PH_EXACT, FL_NPHASE };
 fl_status fl_set_timing(fl_ctx *ctx, int enable);
+/* Graph replay of fl_fa2_run (on by default); 0 runs every iteration as
+ * eager launches (the same results, bitwise). */
+fl_status fl_set_graphs(fl_ctx *ctx, int enable);
 fl_status fl_get_timing(fl_ctx *ctx, double *ms, int64_t *counts);
 
 #ifdef __cplusplus

@@ -49,6 +49,28 @@ void flush_timing(fl_ctx *c)
     c->ev_pending.clear();
 }
 
+hipStream_t aux_stream(fl_ctx *c, int i)
+{
+    if (!c->aux[i]) FL_CHECK_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
+    return c->aux[i];
+}
+
+fl_ctx *sub_ctx(fl_ctx *c, size_t b)
+{
+    while (c->sub.size() <= b) {
+        hipStream_t s = nullptr;
+        FL_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        fl_ctx *sc = nullptr;
+        if (fl_create(&sc, c->device, s) != FL_OK) {
+            (void)hipStreamDestroy(s);
+            throw Error(FL_EHIP, "branch context creation failed");
+        }
+        sc->own_stream = true;
+        c->sub.push_back(sc);
+    }
+    return c->sub[b];
+}
+
 }  // namespace fl
 
 using namespace fl;
@@ -90,6 +112,13 @@ void fl_destroy(fl_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    for (auto *s : c->sub) fl_destroy(s);
+    for (auto s : c->aux)
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (auto &kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto &pe : c->ev_pending) {
@@ -124,6 +153,13 @@ fl_status fl_set_timing(fl_ctx *c, int enable)
 {
     FL_API_BEGIN(c)
     c->timing = enable != 0;
+    FL_API_END(c)
+}
+
+fl_status fl_set_graphs(fl_ctx *c, int enable)
+{
+    FL_API_BEGIN(c)
+    c->use_graphs = enable != 0;
     FL_API_END(c)
 }
 

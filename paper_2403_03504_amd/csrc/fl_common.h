@@ -80,6 +80,12 @@ struct fl_ctx {
     // statistics of the last FMM evaluation live in device memory
     int64_t *d_stats = nullptr;  // [8]
     uint32_t epoch = 0;          // hash-table epoch, advanced per tree build
+    bool use_graphs = true;      // fl_fa2_run replays a captured iteration
+    // private streams (created on first use, destroyed with the context) and
+    // branch contexts for concurrent runs of independent systems
+    hipStream_t aux[2] = {nullptr, nullptr};
+    std::vector<fl_ctx *> sub;
+    bool own_stream = false;     // a branch context destroys its stream
 };
 
 namespace fl {
@@ -124,6 +130,11 @@ T *ws_zeroed(fl_ctx *c, const char *name, size_t count)
     if (b.cap != before) FL_CHECK_HIP(hipMemsetAsync(p, 0, b.cap, c->stream));
     return p;
 }
+
+// Private stream i (0 or 1) of the context, created on first use.
+hipStream_t aux_stream(fl_ctx *c, int i);
+// Branch context b (with its own stream), created on first use.
+fl_ctx *sub_ctx(fl_ctx *c, size_t b);
 
 inline unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 1 << 20)
 {

@@ -8,6 +8,10 @@
 //              fixed order and sets the global speed s_G (no host round trip)
 //   k_update   per-node speed and move p += s_i F, F' <- F
 // There are no floating-point atomics: a run is bitwise reproducible.
+#include <algorithm>
+#include <vector>
+
+#include "fl_fa2.h"
 #include "fl_fmm.h"
 
 namespace fl {
@@ -348,21 +352,24 @@ static void validate_graph(fl_ctx *c, const GraphArgs &g)
 struct AttractPlan {
     int32_t *choff = nullptr;   // [n+1] first chunk of each row (heavy rows only)
     int2 *chunks = nullptr;     // (row, first entry)
-    double2 *csum = nullptr;    // per-chunk sums
-    int64_t cap = 0;
+    int64_t cap = 0;            // chunk capacity; per-chunk sums live in workspace "at_csum"
 };
 
-// Chunks of the rows longer than HEAVY; depends on the graph only.
-static AttractPlan attract_plan(fl_ctx *c, const GraphArgs &g)
+static int64_t attract_cap(int64_t nnz) { return nnz / (HEAVY + 1) + nnz / CHUNK + 2; }
+
+// Chunks of the rows longer than HEAVY; depends on the graph only.  The plan
+// goes to the given arrays (choff [n+1], chunks [attract_cap(nnz)]) or, when
+// they are null, to the context's workspace.
+static AttractPlan attract_plan(fl_ctx *c, const GraphArgs &g, int32_t *choff = nullptr, int2 *chunks = nullptr,
+                                int64_t nnz = -1)
 {
     AttractPlan a;
     const int n = g.n;
-    int32_t nnz = read_i32(c, g.row_ptr + n);
-    a.cap = nnz / (HEAVY + 1) + nnz / CHUNK + 2;
+    if (nnz < 0) nnz = read_i32(c, g.row_ptr + n);
+    a.cap = attract_cap(nnz);
     int32_t *nch = ws<int32_t>(c, "at_nch", n);
-    a.choff = ws<int32_t>(c, "at_choff", (size_t)n + 1);
-    a.chunks = ws<int2>(c, "at_chunks", a.cap);
-    a.csum = ws<double2>(c, "at_csum", a.cap);
+    a.choff = choff ? choff : ws<int32_t>(c, "at_choff", (size_t)n + 1);
+    a.chunks = chunks ? chunks : ws<int2>(c, "at_chunks", a.cap);
     hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, g.row_ptr, nch);
     FL_LAUNCH_CHECK();
     scan_excl_i32(c, nch, a.choff, n);
@@ -373,12 +380,12 @@ static AttractPlan attract_plan(fl_ctx *c, const GraphArgs &g)
 
 // positions interleaved (x, y) so each neighbour is one 8-byte gather
 static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const AttractPlan &a, const float *x,
-                                    const float *y)
+                                    const float *y, double2 *csum)
 {
     float2 *xy = ws<float2>(c, "at_xy", g.n);
     hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, c->stream, x, y, g.n, xy);
     hipLaunchKernelGGL(k_attract_chunks, dim3(1024), dim3(NT), 0, c->stream, g.row_ptr, g.col, (const float2 *)xy,
-                       a.chunks, a.choff + g.n, a.csum);
+                       a.chunks, a.choff + g.n, csum);
     FL_LAUNCH_CHECK();
     return xy;
 }
@@ -418,11 +425,12 @@ static void iteration(fl_ctx *c, const GraphArgs &g, const AttractPlan &ap, floa
     repulsion(c, g, x, y, p, frx, fry);
     {
         PhaseTimer pt(c, FL_PH_ATTRACT);
-        const float2 *xy = attract_chunks(c, g, ap, x, y);
+        double2 *csum = ws<double2>(c, "at_csum", ap.cap);
+        const float2 *xy = attract_chunks(c, g, ap, x, y, csum);
         hipLaunchKernelGGL(k_combine, dim3(nbc), dim3(NT), 0, c->stream, n, g.row_ptr, g.col, g.deg, xy, frx, fry,
                            consts(p), st->fx_prev, st->fy_prev, first, fcx, fcy, (float *)nullptr, (float *)nullptr,
                            (float *)nullptr, (float *)nullptr, part, ticket, st->scalars, flags, ring, ring_it,
-                           ap.choff, ap.csum);
+                           ap.choff, (const double2 *)csum);
         FL_LAUNCH_CHECK();
     }
     {
@@ -434,14 +442,178 @@ static void iteration(fl_ctx *c, const GraphArgs &g, const AttractPlan &ap, floa
     st->iter += 1;
 }
 
-// Iterations on a validated graph; no host synchronisation (used by the
-// layout pipeline and the server).  flags must be a zeroed device int.
-void fa2_run_internal(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg, float *x,
-                      float *y, fl_fa2_state *st, const fl_fa2_params *prm, int iters, int32_t *flags)
+// ---- graph replay ------------------------------------------------------------
+// An iteration is a fixed sequence of launches whose sizes depend only on n
+// and the parameters (every data-dependent count stays on the device), so
+// after one eager iteration (which sizes the workspace and makes F_prev
+// valid) one more is captured on private streams and the graph is replayed.
+// Captured iterations are bitwise the same as eager ones.
+constexpr int GRAPH_MIN_ITERS = 4;
+constexpr size_t MANY_BRANCHES = 8;
+
+namespace {
+
+struct CompRun {
+    fl_ctx *c;  // context (and stream) of the branch the system runs on
+    GraphArgs g;
+    AttractPlan ap;
+    float *x, *y;
+    fl_fa2_state st;
+    fl_fa2_params prm;
+};
+
+static void destroy_graph(hipGraph_t g, hipGraphExec_t e)
 {
-    GraphArgs g{n, row_ptr, col, deg};
-    AttractPlan ap = attract_plan(c, g);
-    for (int it = 0; it < iters; ++it) iteration(c, g, ap, x, y, st, prm, flags, nullptr, 0);
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+}
+
+// Iterations of independent systems grouped in branches (the systems of one
+// branch share its context and run one after the other): one eager iteration
+// of every system, then one graph holding one iteration of every system, a
+// parallel path per branch, replayed iters-1 times on `main`.  On return all
+// work is enqueued; `main` is ordered after every branch stream.
+static void run_graph(hipStream_t main, std::vector<std::vector<CompRun>> &branches, int32_t *flags, int iters)
+{
+    for (auto &br : branches)
+        for (auto &r : br) iteration(r.c, r.g, r.ap, r.x, r.y, &r.st, &r.prm, flags, nullptr, 0);
+    std::vector<hipEvent_t> ev(branches.size() + 1, nullptr);
+    auto free_events = [&] {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    try {
+        for (auto &e : ev) FL_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        hipEvent_t fork = ev.back();
+        // main waits for the eager iterations (run on the branch streams)
+        for (size_t k = 0; k < branches.size(); ++k) {
+            FL_CHECK_HIP(hipEventRecord(ev[k], branches[k][0].c->stream));
+            FL_CHECK_HIP(hipStreamWaitEvent(main, ev[k], 0));
+        }
+        if (iters > 1) {
+            FL_CHECK_HIP(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
+            try {
+                FL_CHECK_HIP(hipEventRecord(fork, main));
+                for (size_t k = 0; k < branches.size(); ++k) {
+                    hipStream_t bs = branches[k][0].c->stream;
+                    FL_CHECK_HIP(hipStreamWaitEvent(bs, fork, 0));
+                    for (auto &r : branches[k]) {
+                        const int64_t it0 = r.st.iter;
+                        iteration(r.c, r.g, r.ap, r.x, r.y, &r.st, &r.prm, flags, nullptr, 0);
+                        r.st.iter = it0;  // recorded, not run
+                    }
+                    FL_CHECK_HIP(hipEventRecord(ev[k], bs));
+                    FL_CHECK_HIP(hipStreamWaitEvent(main, ev[k], 0));
+                }
+            } catch (...) {
+                hipGraph_t g2 = nullptr;
+                (void)hipStreamEndCapture(main, &g2);
+                destroy_graph(g2, nullptr);
+                throw;
+            }
+            FL_CHECK_HIP(hipStreamEndCapture(main, &graph));
+            FL_CHECK_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            for (int it = 1; it < iters; ++it) FL_CHECK_HIP(hipGraphLaunch(exec, main));
+            for (auto &br : branches)
+                for (auto &r : br) r.st.iter += iters - 1;
+        }
+        // later work on a branch stream comes after the replays
+        FL_CHECK_HIP(hipEventRecord(fork, main));
+        for (auto &br : branches) FL_CHECK_HIP(hipStreamWaitEvent(br[0].c->stream, fork, 0));
+        FL_CHECK_HIP(hipStreamSynchronize(main));
+    } catch (...) {
+        (void)hipStreamSynchronize(main);
+        destroy_graph(graph, exec);
+        free_events();
+        throw;
+    }
+    destroy_graph(graph, exec);
+    free_events();
+}
+
+}  // namespace
+
+// Independent systems (the large components of a layout), each `iters`
+// iterations from a zero state, concurrently.  Systems are dealt to at most
+// MANY_BRANCHES branches, largest first, each to the branch with the least
+// work so far; a branch has its own context and stream, and its systems run
+// one after the other on it.  Per-system state (F', scalars, attraction
+// chunks) sits in one slab of the caller's workspace.
+void fa2_run_many(fl_ctx *c, const std::vector<FA2System> &sys, const fl_fa2_params *prm, int iters,
+                  int32_t fmm_min_nodes, int32_t *flags)
+{
+    if (sys.empty() || iters <= 0) return;
+    const size_t ns = sys.size();
+    const size_t nbr = std::min<size_t>(ns, MANY_BRANCHES);
+    std::vector<size_t> order(ns);
+    for (size_t k = 0; k < ns; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return sys[a].n > sys[b].n; });
+    // slab offsets
+    std::vector<int64_t> o_node(ns), o_rp(ns), o_ch(ns);
+    int64_t t_node = 0, t_rp = 0, t_ch = 0;
+    for (size_t k = 0; k < ns; ++k) {
+        o_node[k] = t_node;
+        o_rp[k] = t_rp;
+        o_ch[k] = t_ch;
+        t_node += sys[k].n;
+        t_rp += (int64_t)sys[k].n + 1;
+        t_ch += attract_cap(sys[k].nnz);
+    }
+    float *fp = ws<float>(c, "many_fp", 2 * (size_t)t_node);
+    double *sc = ws<double>(c, "many_sc", 4 * ns);
+    int32_t *choff = ws<int32_t>(c, "many_choff", (size_t)t_rp);
+    int2 *chunks = ws<int2>(c, "many_chunks", (size_t)t_ch);
+
+    hipStream_t main = aux_stream(c, 1);
+    std::vector<fl_ctx *> ctxs(nbr);
+    hipEvent_t ready = nullptr;
+    FL_CHECK_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    try {
+        FL_CHECK_HIP(hipEventRecord(ready, c->stream));  // inputs were prepared on the caller's stream
+        for (size_t b = 0; b < nbr; ++b) {
+            ctxs[b] = sub_ctx(c, b);
+            ctxs[b]->timing = false;
+            FL_CHECK_HIP(hipStreamWaitEvent(ctxs[b]->stream, ready, 0));
+        }
+        std::vector<std::vector<CompRun>> branches(nbr);
+        std::vector<double> load(nbr, 0.0);
+        for (size_t k : order) {
+            const size_t b = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            const FA2System &s = sys[k];
+            CompRun r;
+            r.c = ctxs[b];
+            r.g = GraphArgs{s.n, s.row_ptr, s.col, s.deg};
+            r.ap = attract_plan(r.c, r.g, choff + o_rp[k], chunks + o_ch[k], s.nnz);
+            r.x = s.x;
+            r.y = s.y;
+            r.st = fl_fa2_state{fp + 2 * o_node[k], fp + 2 * o_node[k] + s.n, sc + 4 * k, 0};
+            r.prm = *prm;
+            const bool exact = r.prm.repulsion == FL_REP_FMM && s.n < fmm_min_nodes;
+            if (exact) r.prm.repulsion = FL_REP_EXACT;
+            // rough cost of an iteration: exact repulsion is quadratic, the
+            // FMM path a fixed launch-bound part plus a linear one
+            load[b] += exact ? 1e-9 * (double)s.n * s.n + 20.0 : 1e-3 * s.n + 100.0;
+            branches[b].push_back(r);
+        }
+        run_graph(main, branches, flags, iters);
+        FL_CHECK_HIP(hipEventRecord(ready, main));
+        FL_CHECK_HIP(hipStreamWaitEvent(c->stream, ready, 0));
+        for (auto &br : branches) {
+            bool fmm = false;
+            for (auto &r : br) fmm = fmm || r.prm.repulsion == FL_REP_FMM;
+            if (fmm && tree_error_bits(br[0].c, true))
+                throw Error(FL_EHIP, "FMM capacity guard tripped (tree or list sizes)");
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(main);
+        for (auto *cc : ctxs)
+            if (cc) (void)hipStreamSynchronize(cc->stream);
+        (void)hipEventDestroy(ready);
+        throw;
+    }
+    (void)hipEventDestroy(ready);
 }
 
 void fa2_validate(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg,
@@ -491,13 +663,14 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
     if (fax || fgx) {
         int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
         AttractPlan ap = attract_plan(c, g);
-        const float2 *xy = attract_chunks(c, g, ap, x, y);
+        double2 *csum = ws<double2>(c, "at_csum", ap.cap);
+        const float2 *xy = attract_chunks(c, g, ap, x, y, csum);
         hipLaunchKernelGGL(k_combine, dim3(grid_for(n, NT, COMBINE_BLOCKS)), dim3(NT), 0, c->stream, n, row_ptr,
                            col_idx, deg, xy,
                            (const float *)nullptr, (const float *)nullptr, consts(prm), (const float *)nullptr,
                            (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
                            (double2 *)nullptr, (unsigned *)nullptr, (double *)nullptr, flags, (double *)nullptr, 0,
-                           ap.choff, ap.csum);
+                           ap.choff, (const double2 *)csum);
         FL_LAUNCH_CHECK();
     }
     FL_API_END(c)
@@ -521,7 +694,34 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
     if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
     double *ring = per_iter ? ws<double>(c, "fa2_ring", 3 * (size_t)(iters > 0 ? iters : 1)) : nullptr;
     AttractPlan ap = attract_plan(c, g);
-    for (int it = 0; it < iters; ++it) iteration(c, g, ap, x, y, st, prm, flags, ring, it);
+    if (!ring && !c->timing && iters >= GRAPH_MIN_ITERS && c->use_graphs) {
+        // the caller's stream may be the null stream, which cannot be
+        // captured: run on private streams ordered after it and before
+        // anything enqueued on it later
+        hipStream_t user = c->stream;
+        hipEvent_t e = nullptr;
+        FL_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        try {
+            hipStream_t bs = aux_stream(c, 0), main = aux_stream(c, 1);
+            FL_CHECK_HIP(hipEventRecord(e, user));
+            FL_CHECK_HIP(hipStreamWaitEvent(bs, e, 0));
+            c->stream = bs;
+            std::vector<std::vector<CompRun>> br{{CompRun{c, g, ap, x, y, *st, *prm}}};
+            run_graph(main, br, flags, iters);
+            c->stream = user;
+            FL_CHECK_HIP(hipEventRecord(e, main));
+            FL_CHECK_HIP(hipStreamWaitEvent(user, e, 0));
+            st->iter = br[0][0].st.iter;
+        } catch (...) {
+            if (c->stream != user) (void)hipStreamSynchronize(c->stream);
+            c->stream = user;
+            (void)hipEventDestroy(e);
+            throw;
+        }
+        (void)hipEventDestroy(e);
+    } else {
+        for (int it = 0; it < iters; ++it) iteration(c, g, ap, x, y, st, prm, flags, ring, it);
+    }
     if (per_iter || always_sync) {
         int32_t f = read_i32(c, flags);
         if (per_iter && iters > 0) {

@@ -76,6 +76,14 @@ __global__ void k_local_csr(const int32_t *__restrict__ nrow_ptr, const int32_t 
         lcol[e] = ncol[base + e] - cb;
 }
 
+// first CSR entry of each component (k in [0, ncomp]: the last is nnz)
+__global__ void k_comp_rp(const int32_t *__restrict__ off, int ncomp, const int32_t *__restrict__ nrow_ptr,
+                          int32_t *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k <= ncomp) out[k] = nrow_ptr[off[k]];
+}
+
 __global__ void k_zero_pos(float *__restrict__ xs, float *__restrict__ ys, const int32_t *__restrict__ idx, int m)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,8 +144,13 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
     int32_t *ncol = ws<int32_t>(c, "lay_col", nnz > 0 ? nnz : 1);
     hipLaunchKernelGGL(k_permute_cols, dim3(g), dim3(256), 0, c->stream, perm, inv, n, row_ptr, col, nrow_ptr, ncol);
     FL_LAUNCH_CHECK();
-    std::vector<int32_t> off(ncomp + 1);
+    int32_t *d_crp = ws<int32_t>(c, "lay_crp", (size_t)ncomp + 1);
+    hipLaunchKernelGGL(k_comp_rp, dim3(grid_for((int64_t)ncomp + 1, 256)), dim3(256), 0, c->stream,
+                       (const int32_t *)d_off, ncomp, (const int32_t *)nrow_ptr, d_crp);
+    FL_LAUNCH_CHECK();
+    std::vector<int32_t> off(ncomp + 1), crp(ncomp + 1);
     FL_CHECK_HIP(hipMemcpyAsync(off.data(), d_off, sizeof(int32_t) * (ncomp + 1), hipMemcpyDeviceToHost, c->stream));
+    FL_CHECK_HIP(hipMemcpyAsync(crp.data(), d_crp, sizeof(int32_t) * (ncomp + 1), hipMemcpyDeviceToHost, c->stream));
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));
 
     std::vector<int32_t> kk_ids, fa2_ids, single_nodes;
@@ -169,23 +182,22 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
     auto t2 = std::chrono::steady_clock::now();
     int32_t *flags = ws<int32_t>(c, "lay_flags", 1);
     FL_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), c->stream));
-    int maxc = 0;
-    for (int k : fa2_ids) maxc = std::max(maxc, off[k + 1] - off[k]);
     if (!fa2_ids.empty()) {
-        int32_t *lrp = ws<int32_t>(c, "lay_lrp", (size_t)maxc + 1);
+        // a local CSR per component, side by side: component j of the list
+        // keeps rows [cb + j, cb + j + nc] and its own column range
+        int32_t *lrp = ws<int32_t>(c, "lay_lrp", (size_t)n + fa2_ids.size() + 1);
         int32_t *lcol = ws<int32_t>(c, "lay_lcol", nnz > 0 ? nnz : 1);
-        float *fpx = ws<float>(c, "lay_fpx", maxc), *fpy = ws<float>(c, "lay_fpy", maxc);
-        double *sc = ws<double>(c, "lay_sc", 4);
-        for (int k : fa2_ids) {
+        std::vector<FA2System> sys;
+        for (size_t j = 0; j < fa2_ids.size(); ++j) {
+            const int k = fa2_ids[j];
             const int cb = off[k], nc = off[k + 1] - off[k];
+            int32_t *rp = lrp + cb + j, *cl = lcol + crp[k];
             hipLaunchKernelGGL(k_local_csr, dim3(grid_for(nc + 1, 256, 1024)), dim3(256), 0, c->stream,
-                               (const int32_t *)nrow_ptr, (const int32_t *)ncol, cb, nc, lrp, lcol);
+                               (const int32_t *)nrow_ptr, (const int32_t *)ncol, cb, nc, rp, cl);
             FL_LAUNCH_CHECK();
-            fl_fa2_params p = *fa2;
-            if (p.repulsion == FL_REP_FMM && nc < fmm_min_nodes) p.repulsion = FL_REP_EXACT;
-            fl_fa2_state st{fpx, fpy, sc, 0};
-            fa2_run_internal(c, nc, lrp, lcol, ndeg + cb, xs + cb, ys + cb, &st, &p, fa2_iters, flags);
+            sys.push_back(FA2System{nc, (int64_t)crp[k + 1] - crp[k], rp, cl, ndeg + cb, xs + cb, ys + cb});
         }
+        fa2_run_many(c, sys, fa2, fa2_iters, fmm_min_nodes, flags);
     }
     hipLaunchKernelGGL(k_unpermute_pos, dim3(g), dim3(256), 0, c->stream, perm, n, (const float *)xs,
                        (const float *)ys, x, y);

@@ -541,6 +541,12 @@ __global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t 
     st[11] += n;
 }
 
+__global__ void k_zero_i64(int64_t *__restrict__ p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 __global__ void k_export_cells(TreeView t, int32_t *__restrict__ out, int cap)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -613,7 +619,7 @@ void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *
     float4 *xym = ws<float4>(c, "t_xym", n);
     hipLaunchKernelGGL(k_pack, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, deg, n, xym);
     hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float4 *)xym, perm, n, t.part);
-    FL_CHECK_HIP(hipMemsetAsync(t.counts, 0, 3 * sizeof(int32_t), c->stream));  // [3] (error bits) is sticky
+    fill_i32(c, t.counts, 3, 0);  // [3] (error bits) is sticky; a kernel, not a memset, so graphs replay it
     hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, sk, n, bits, leaf, t.pack,
                        cnt2);
     FL_LAUNCH_CHECK();
@@ -644,7 +650,7 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
     FL_LAUNCH_CHECK();
     scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
     scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
-    FL_CHECK_HIP(hipMemsetAsync(c->d_stats + 2, 0, sizeof(int64_t), c->stream));
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, c->d_stats + 2, 1);
     hipLaunchKernelGGL(k_lists_fill, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, L.offVX, L.offUW, L.V,
                        L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2), cap, lcap, L.v_cap, L.x_cap, L.u_cap,
                        L.w_cap, t.counts + 3);

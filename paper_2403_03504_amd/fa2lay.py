@@ -31,7 +31,7 @@ PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact"
 EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
             "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_run", "fl_fmm_stats",
-            "fl_set_timing", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances", "fl_kk_steps",
+            "fl_set_timing", "fl_set_graphs", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances", "fl_kk_steps",
             "fl_kk_layout", "fl_layout", "fl_server_create", "fl_server_create_fake", "fl_server_submit",
             "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release", "fl_server_cancel",
             "fl_server_stats_get", "fl_server_last_error", "fl_server_destroy")
@@ -105,6 +105,7 @@ _sig = {
                     ctypes.POINTER(StepStats)], _i32),
     "fl_fmm_stats": ([P, ctypes.POINTER(_i64), ctypes.c_int], _i32),
     "fl_set_timing": ([P, ctypes.c_int], _i32),
+    "fl_set_graphs": ([P, ctypes.c_int], _i32),
     "fl_kk_default_params": ([ctypes.POINTER(KKParams)], None),
     "fl_hop_distances": ([P, _i32, P, P, P, P, P], _i32),
     "fl_kk_steps": ([P, _i32, P, P, P, P, ctypes.POINTER(KKParams)], _i32),
@@ -358,6 +359,9 @@ class Context:
 
     def set_timing(self, enable: bool):
         self._check(_lib.fl_set_timing(self._h, 1 if enable else 0), "fl_set_timing")
+
+    def set_graphs(self, enable: bool):
+        self._check(_lib.fl_set_graphs(self._h, 1 if enable else 0), "fl_set_graphs")
 
     def get_timing(self):
         ms = (ctypes.c_double * len(PHASES))()

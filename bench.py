@@ -108,6 +108,138 @@ def serving(args, fl, w, np) -> dict:
     return out
 
 
+def batched(args, fl, w, np, torch) -> dict:
+    """Many uneven components through one fl_layout call: power-law small
+    components (sizes 3..200) laid out by Kamada-Kawai and a few large ones
+    (log-uniform 5k..50k nodes) by ForceAtlas2; concurrent replayed graphs,
+    then the same call with every component run eagerly one after the other."""
+    t = time.perf_counter()
+    g, offs = w.batched_components(3, args.batched_small, args.batched_large)
+    sizes = np.diff(offs)
+    log(f"batched: generated {sizes.size} components ({g.n} nodes) in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda", 0)
+    ctx = fl.Context(0)
+    G = ctx.build_csr(g.n, torch.from_numpy(g.src).to(dev), torch.from_numpy(g.dst).to(dev))
+    fa2 = fl.default_params(repulsion=fl.REP_FMM, p=args.p, leaf_size=args.leaf)
+    kk = fl.kk_params(steps=args.batched_kk_steps)
+    small = sizes[sizes <= 256]
+    kk_pairs = float(np.sum(small * (small - 1))) * args.batched_kk_steps
+    large = sizes[sizes > 256]
+    out = {"components": int(sizes.size), "nodes": int(g.n), "kk_components": int(small.size),
+           "fa2_components": int(large.size), "fa2_sizes": [int(v) for v in sorted(large)],
+           "kk_steps": args.batched_kk_steps, "fa2_iters": args.batched_fa2_iters,
+           "fmm_min_nodes": 4096}
+    for mode in ("concurrent_graphs", "sequential_eager"):
+        ctx.set_graphs(mode == "concurrent_graphs")
+        best = None
+        for _ in range(2):  # the first call sizes the workspaces
+            x = torch.from_numpy(g.x).to(dev)
+            y = torch.from_numpy(g.y).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.layout(G, x, y, fa2, args.batched_fa2_iters, kk, kk_max_nodes=256, fmm_min_nodes=4096)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if best is None or wall < best[0]:
+                best = (wall, st)
+        wall, st = best
+        r = {"wall_ms": wall * 1e3, "setup_ms": st["ms_setup"], "kk_ms": st["ms_kk"], "fa2_ms": st["ms_fa2"],
+             "kk_pair_updates_per_s": kk_pairs / (st["ms_kk"] * 1e-3),
+             "fa2_node_updates_per_s": st["fa2_nodes"] * args.batched_fa2_iters / (st["ms_fa2"] * 1e-3)}
+        out[mode] = r
+        log(f"batched ({mode}): wall {r['wall_ms']:.1f} ms, KK {r['kk_ms']:.1f} ms "
+            f"({r['kk_pair_updates_per_s']:.3g} pair-updates/s), FA2 {r['fa2_ms']:.1f} ms "
+            f"({r['fa2_node_updates_per_s']:.3g} node-updates/s)")
+    ctx.set_graphs(True)
+    ctx.close()
+    return out
+
+
+def precision_study(args, ctx, G, g, fl, orc, np, torch) -> dict:
+    """Expansion order p in {4, 8, 12} on the full graph: each p runs its own
+    trajectory from the initial positions; at iterations t in {0, 1, 100,
+    last} the FMM repulsion and the GPU exact-direct repulsion are compared
+    with the FP64 exact sum over all nodes on a fixed random sample of
+    targets."""
+    dev = torch.device("cuda", 0)
+    deg = G.deg.cpu().numpy()
+    rng = np.random.default_rng(4)
+    tg = np.sort(rng.choice(g.n, size=min(args.precision_sample, g.n), replace=False))
+    last = args.precision_iters - 1
+    marks = sorted({0, 1, min(100, last), last})
+    prm_d = fl.default_params(repulsion=fl.REP_EXACT)
+    out = {"sample_nodes": int(tg.size), "iterations": args.precision_iters, "checkpoints": marks,
+           "leaf_size": args.leaf, "reference": "FP64 exact sum over all nodes (oracle) on the sample",
+           "orders": {}}
+    for p in (4, 8, 12):
+        prm = fl.default_params(repulsion=fl.REP_FMM, p=p, leaf_size=args.leaf)
+        x = torch.from_numpy(g.x).to(dev)
+        y = torch.from_numpy(g.y).to(dev)
+        st = fl.FA2State.zeros(g.n, dev)
+        rows, t_run, n_run = [], 0.0, 0
+        for t in marks:
+            k = t - st.iter
+            if k > 0:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.fa2_run(G, x, y, st, prm, k)
+                torch.cuda.synchronize()
+                t_run += time.perf_counter() - t0
+                n_run += k
+            of = ctx.fa2_forces(G, x, y, prm, components=False)
+            od = ctx.fa2_forces(G, x, y, prm_d, components=False)
+            xs, ys = x.cpu().numpy(), y.cpu().numpy()
+            ex, ey = orc.repulsion_exact(xs, ys, deg + 1.0, targets=tg)
+            e_f = orc.rel_err(of["frx"].cpu().numpy()[tg], of["fry"].cpu().numpy()[tg], ex, ey)
+            e_d = orc.rel_err(od["frx"].cpu().numpy()[tg], od["fry"].cpu().numpy()[tg], ex, ey)
+            rows.append({"t": t, "fmm_rel_err": e_f, "direct_rel_err": e_d})
+        ms = t_run * 1e3 / max(n_run, 1)
+        out["orders"][str(p)] = {"errors": rows, "ms_per_step": ms, "node_updates_per_s": g.n / (ms * 1e-3),
+                                 "max_fmm_rel_err": max(r["fmm_rel_err"] for r in rows)}
+        log(f"precision p={p}: {ms:.3f} ms/iter, FMM error " +
+            ", ".join(f"t={r['t']} {r['fmm_rel_err']:.2e}" for r in rows) +
+            f" (direct {max(r['direct_rel_err'] for r in rows):.2e})")
+    return out
+
+
+def tuned_run(args, G, g, fl, np, torch) -> dict:
+    """fl_autotune on the full graph's points (a random order, so that each
+    size is a uniform subsample) for the error bound, then the timed
+    iterations again with FL_REP_AUTO."""
+    dev = torch.device("cuda", 0)
+    ctx = fl.Context(0)
+    order = torch.from_numpy(np.random.default_rng(7).permutation(g.n)).to(dev)
+    xs = torch.from_numpy(g.x).to(dev)[order].contiguous()
+    ys = torch.from_numpy(g.y).to(dev)[order].contiguous()
+    ds = G.deg[order].contiguous()
+    sizes = [s for s in (1024, 4096, 16384, 65536, 262144, 1048576) if s < g.n] + [g.n]
+    t0 = time.perf_counter()
+    table, samples = ctx.autotune(xs, ys, ds, sizes, max_rel_err=args.tune_err, reps=3)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune ({tune_s:.1f} s): crossover {table['fmm_min_nodes']}, (p, leaf) per size " +
+        ", ".join(f"{s}: ({p}, {l})" for s, p, l in zip(sizes, table["p"], table["leaf_size"])))
+    prm = fl.default_params(repulsion=fl.REP_AUTO)
+    x = torch.from_numpy(g.x).to(dev)
+    y = torch.from_numpy(g.y).to(dev)
+    st = fl.FA2State.zeros(g.n, dev)
+    ctx.fa2_run(G, x, y, st, prm, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fa2_run(G, x, y, st, prm, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    k = len(sizes) - 1
+    pick = [q for q in samples if q["size"] == g.n and q["p"] == table["p"][k] and q["leaf_size"] == table["leaf_size"][k]]
+    out = {"max_rel_err": args.tune_err, "sizes": sizes, "table": table, "tune_s": tune_s,
+           "measurements": len(samples), "ms_per_step": wall * 1e3 / args.steps,
+           "node_updates_per_s": g.n * args.steps / wall,
+           "full_size_choice": {"p": table["p"][k], "leaf_size": table["leaf_size"][k],
+                                "rel_err_vs_gpu_exact": pick[0]["rel_err"] if pick else None}}
+    log(f"tuned run: {out['ms_per_step']:.3f} ms/iter, {out['node_updates_per_s']:.4g} node-updates/s")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +259,15 @@ def main() -> int:
     ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrival rate, jobs/s")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-iters", type=int, default=200)
+    ap.add_argument("--tune-err", type=float, default=1e-3,
+                    help="error bound of the autotuned run (0: skip)")
+    ap.add_argument("--precision-sample", type=int, default=500,
+                    help="sample nodes of the p = 4/8/12 precision study (0: skip)")
+    ap.add_argument("--precision-iters", type=int, default=300)
+    ap.add_argument("--batched-small", type=int, default=10_000, help="small components in the batched run (0: skip)")
+    ap.add_argument("--batched-large", type=int, default=20)
+    ap.add_argument("--batched-kk-steps", type=int, default=200)
+    ap.add_argument("--batched-fa2-iters", type=int, default=200)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="finish with a device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -287,6 +428,12 @@ def main() -> int:
                                   "sample": f"one full FA2 iteration of the same {g.n}-node graph (FP64 FMM "
                                             f"repulsion p={args.p}, leaf<={args.leaf}), {cs:.1f} s"}
         log(f"cpu oracle: {cs:.1f}s per iteration on {orc.num_threads()} threads")
+    if args.tune_err > 0:
+        result["autotuned"] = tuned_run(args, G, g, fl, np, torch)
+    if args.precision_sample > 0:
+        result["precision"] = precision_study(args, ctx, G, g, fl, orc, np, torch)
+    if args.batched_small > 0:
+        result["batched"] = batched(args, fl, w, np, torch)
     if args.serving_jobs > 0:
         ctx.close()
         result["serving"] = serving(args, fl, w, np)

@@ -127,7 +127,10 @@ fl_status fl_tree(fl_ctx *ctx, int32_t n, const float *x, const float *y, int32_
 
 enum { FL_GRAV_STRONG_MASS = 0, FL_GRAV_FA2_CONST = 1, FL_GRAV_STRONG_UNIT = 2 };
 enum { FL_SWING_PAPER = 0, FL_SWING_FA2 = 1 };
-enum { FL_REP_EXACT = 0, FL_REP_FMM = 1 };
+/* FL_REP_AUTO: per system of n nodes, the context's tuning table decides
+ * (exact below its crossover, else FMM with the p and leaf_size of n's size
+ * bucket; see fl_autotune). */
+enum { FL_REP_EXACT = 0, FL_REP_FMM = 1, FL_REP_AUTO = 2 };
 
 /* Forces (mass m_i = deg_i + 1):
  *   repulsion  F_r,i = kr m_i sum_{j != i} m_j (p_i - p_j) / |p_i - p_j|^2
@@ -147,7 +150,7 @@ typedef struct {
     int32_t gravity_mode;  /* FL_GRAV_* */
     int32_t swing_mode;    /* FL_SWING_* */
     double tau, ks, ksmax, max_rise;
-    int32_t repulsion;     /* FL_REP_EXACT (O(n^2)) or FL_REP_FMM */
+    int32_t repulsion;     /* FL_REP_EXACT (O(n^2)), FL_REP_FMM or FL_REP_AUTO */
     int32_t p;             /* FMM expansion order: 4, 6, 8, 10, 12, 16 */
     int32_t leaf_size;     /* FMM: a cell holding more points is divided (1..1024) */
     int32_t morton_bits;   /* FMM: quadtree depth cap, 1..16 */
@@ -251,12 +254,14 @@ fl_status fl_kk_layout(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets,
  * nodes to the origin; components of 2..kk_max_nodes nodes by Kamada-Kawai;
  * larger ones by fa2_iters ForceAtlas2 iterations each (FMM repulsion when
  * fa2->repulsion is FL_REP_FMM and the component has >= fmm_min_nodes nodes,
- * exact otherwise).  x, y in place, caller's node order.  Components are laid
+ * exact otherwise; with FL_REP_AUTO the context's tuning table decides per
+ * component and fmm_min_nodes is not used).  x, y in place, caller's node order.  Components are laid
  * out independently, each about its own centre.  The ForceAtlas2 components
  * run concurrently: they are dealt, largest first, to up to 8 branch streams
  * owned by the context, and one HIP graph holding an iteration of every
  * component is replayed (results bitwise those of each component run alone
- * by fl_fa2_run).  Synchronises.
+ * by fl_fa2_run).  With graphs off (fl_set_graphs) the components run one
+ * after the other as eager launches on the context's stream.  Synchronises.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t n_comp, n_single, n_kk, n_fa2;
@@ -267,6 +272,55 @@ typedef struct {
 fl_status fl_layout(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
                     float *x, float *y, const fl_fa2_params *fa2, int32_t fa2_iters, const fl_kk_params *kk,
                     int32_t kk_max_nodes, int32_t fmm_min_nodes, fl_layout_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Autotuning (project addition; the paper fixes no FMM parameters).
+ * The table maps a system size to exact or FMM repulsion and the FMM's
+ * expansion order p and leaf size; FL_REP_AUTO reads it.
+ * ------------------------------------------------------------------------ */
+enum { FL_TUNE_MAX_BUCKETS = 16 };
+typedef struct {
+    int32_t fmm_min_nodes;  /* exact repulsion below this size, FMM from it */
+    int32_t n_buckets;      /* 1..FL_TUNE_MAX_BUCKETS */
+    int32_t bucket_max[FL_TUNE_MAX_BUCKETS]; /* bucket b: sizes <= bucket_max[b], ascending (the last
+                                                bucket also takes every larger size) */
+    int32_t p[FL_TUNE_MAX_BUCKETS];          /* expansion order per bucket (4, 6, 8, 10, 12, 16) */
+    int32_t leaf_size[FL_TUNE_MAX_BUCKETS];  /* leaf size per bucket (1..1024) */
+    double max_rel_err;     /* error bound the table was tuned for (0: not tuned) */
+} fl_tuning;
+
+/* The table a new context starts with: fmm_min_nodes 4096, one bucket with
+ * p = 8, leaf_size = 64, max_rel_err 0. */
+void fl_default_tuning(fl_tuning *out);
+/* Copy a table into the context (NULL: the default); FL_EINVAL if malformed. */
+fl_status fl_set_tuning(fl_ctx *ctx, const fl_tuning *tuning);
+fl_status fl_get_tuning(fl_ctx *ctx, fl_tuning *out);
+
+/* One measurement of fl_autotune: p = 0 is the exact repulsion. */
+typedef struct {
+    int32_t size, p, leaf_size, feasible;
+    double ms;       /* median over the repetitions (tree, lists and passes for FMM) */
+    double rel_err;  /* |F - F_exact|_2 / |F_exact|_2 over all nodes of the prefix */
+} fl_tune_sample;
+
+/* Measure and build a tuning table; the table is also installed in the
+ * context.  For each size s of sizes [host, ascending, 1..16 entries, each
+ * in [2, n]], the first s points of x, y, deg [device, n] (pass them in
+ * random order, so that a prefix is a uniform subsample; deg gives the
+ * masses) are evaluated by the exact repulsion and by the FMM for every
+ * p in {4, 6, 8, 10, 12, 16} and leaf_size in {16, 24, 32, 48, 64, 96, 128},
+ * `reps` timed repetitions each (HIP events on the context's stream).  At
+ * each size the fastest FMM configuration whose error against the exact
+ * forces is <= max_rel_err is chosen (the most accurate one if none is);
+ * the crossover is the geometric mean of the largest size at which exact
+ * repulsion is faster and the next one (sizes[0] if the FMM wins at every
+ * size, past the last size if it wins at none).  max_rel_err in [1e-6, 1]
+ * (the exact reference itself is good to about 1e-7); reps in [1, 20].
+ * samples [host, samples_cap entries] may be NULL; n_samples [host] gets the
+ * number of measurements.  Synchronises. */
+fl_status fl_autotune(fl_ctx *ctx, int32_t n, const float *x, const float *y, const int32_t *deg, int32_t n_sizes,
+                      const int32_t *sizes, double max_rel_err, int32_t reps, fl_tuning *out,
+                      fl_tune_sample *samples, int32_t samples_cap, int32_t *n_samples);
 
 /* ------------------------------------------------------------------------
  * Layout server: continuous batching of layout jobs on one GPU.  Jobs are
@@ -297,6 +351,9 @@ typedef struct {
 } fl_server_stats;
 
 fl_status fl_server_create(fl_server **out, int device, size_t mem_budget_bytes, int32_t max_slots);
+/* Tuning table (see fl_autotune) for jobs admitted from now on whose
+ * params.repulsion is FL_REP_AUTO; NULL restores the default. */
+fl_status fl_server_set_tuning(fl_server *srv, const fl_tuning *tuning);
 /* Test hook: a server whose workers sleep ns_per_node_update * n * iters
  * nanoseconds instead of using the GPU (results = initial positions). */
 fl_status fl_server_create_fake(fl_server **out, size_t mem_budget_bytes, int32_t max_slots,
@@ -328,8 +385,9 @@ void fl_server_destroy(fl_server *srv);
 enum { FL_PH_TREE = 0, FL_PH_LISTS, FL_PH_UPWARD, FL_PH_M2L, FL_PH_EVAL, FL_PH_ATTRACT, FL_PH_UPDATE,
        FL_PH_EXACT, FL_NPHASE };
 fl_status fl_set_timing(fl_ctx *ctx, int enable);
-/* Graph replay of fl_fa2_run (on by default); 0 runs every iteration as
- * eager launches (the same results, bitwise). */
+/* Graph replay of fl_fa2_run and concurrent components in fl_layout (on by
+ * default); 0 runs every iteration as eager launches on the context's stream
+ * (the same results, bitwise). */
 fl_status fl_set_graphs(fl_ctx *ctx, int enable);
 fl_status fl_get_timing(fl_ctx *ctx, double *ms, int64_t *counts);
 

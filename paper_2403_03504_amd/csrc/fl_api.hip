@@ -89,6 +89,7 @@ fl_status fl_create(fl_ctx **out, int device, void *stream)
     if (!c) return FL_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    fl_default_tuning(&c->tuning);
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return FL_EHIP;

@@ -81,6 +81,7 @@ struct fl_ctx {
     int64_t *d_stats = nullptr;  // [8]
     uint32_t epoch = 0;          // hash-table epoch, advanced per tree build
     bool use_graphs = true;      // fl_fa2_run replays a captured iteration
+    fl_tuning tuning{};          // read by FL_REP_AUTO (set in fl_create)
     // private streams (created on first use, destroyed with the context) and
     // branch contexts for concurrent runs of independent systems
     hipStream_t aux[2] = {nullptr, nullptr};
@@ -130,6 +131,12 @@ T *ws_zeroed(fl_ctx *c, const char *name, size_t count)
     if (b.cap != before) FL_CHECK_HIP(hipMemsetAsync(p, 0, b.cap, c->stream));
     return p;
 }
+
+// Parameters with FL_REP_AUTO replaced by the choice of `t` for a system of
+// n nodes (other modes are returned unchanged).
+fl_fa2_params resolve_repulsion(const fl_tuning &t, int64_t n, const fl_fa2_params &p);
+// Throws FL_EINVAL unless t is a well-formed table.
+void check_tuning(const fl_tuning &t);
 
 // Private stream i (0 or 1) of the context, created on first use.
 hipStream_t aux_stream(fl_ctx *c, int i);

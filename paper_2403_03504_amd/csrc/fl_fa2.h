@@ -12,6 +12,10 @@ namespace fl {
 void fa2_validate(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg,
                   const fl_fa2_params *prm);
 
+// Exact O(n^2) repulsion of n points with masses deg + 1 (no validation).
+void exact_repulsion(fl_ctx *c, int32_t n, const float *x, const float *y, const int32_t *deg, float kr, float *frx,
+                     float *fry);
+
 // An independent system for fa2_run_many (device arrays; ids local to it).
 struct FA2System {
     int32_t n;

@@ -318,7 +318,8 @@ static void validate_params(const fl_fa2_params *p)
     FL_REQUIRE(p->ks >= 0.0 && std::isfinite(p->ks), "ks must be >= 0");
     FL_REQUIRE(p->ksmax > 0.0, "ksmax must be > 0");
     FL_REQUIRE(p->max_rise >= 0.0 && std::isfinite(p->max_rise), "max_rise must be >= 0");
-    FL_REQUIRE(p->repulsion == FL_REP_EXACT || p->repulsion == FL_REP_FMM, "unknown repulsion mode");
+    FL_REQUIRE(p->repulsion == FL_REP_EXACT || p->repulsion == FL_REP_FMM || p->repulsion == FL_REP_AUTO,
+               "unknown repulsion mode");
     if (p->repulsion == FL_REP_FMM) {
         FL_REQUIRE(p->leaf_size >= 1 && p->leaf_size <= 1024, "leaf_size must be in [1, 1024]");
         FL_REQUIRE(p->morton_bits >= 1 && p->morton_bits <= 16, "morton_bits must be in [1, 16]");
@@ -566,6 +567,21 @@ void fa2_run_many(fl_ctx *c, const std::vector<FA2System> &sys, const fl_fa2_par
     int32_t *choff = ws<int32_t>(c, "many_choff", (size_t)t_rp);
     int2 *chunks = ws<int2>(c, "many_chunks", (size_t)t_ch);
 
+    if (!c->use_graphs) {
+        // one system after the other, eager launches on the caller's stream
+        for (size_t k : order) {
+            const FA2System &s = sys[k];
+            GraphArgs g{s.n, s.row_ptr, s.col, s.deg};
+            AttractPlan ap = attract_plan(c, g, choff + o_rp[k], chunks + o_ch[k], s.nnz);
+            fl_fa2_state st{fp + 2 * o_node[k], fp + 2 * o_node[k] + s.n, sc + 4 * k, 0};
+            fl_fa2_params p = resolve_repulsion(c->tuning, s.n, *prm);
+            if (prm->repulsion == FL_REP_FMM && s.n < fmm_min_nodes) p.repulsion = FL_REP_EXACT;
+            for (int it = 0; it < iters; ++it) iteration(c, g, ap, s.x, s.y, &st, &p, flags, nullptr, 0);
+        }
+        if (prm->repulsion != FL_REP_EXACT && tree_error_bits(c, true))
+            throw Error(FL_EHIP, "FMM capacity guard tripped (tree or list sizes)");
+        return;
+    }
     hipStream_t main = aux_stream(c, 1);
     std::vector<fl_ctx *> ctxs(nbr);
     hipEvent_t ready = nullptr;
@@ -589,9 +605,9 @@ void fa2_run_many(fl_ctx *c, const std::vector<FA2System> &sys, const fl_fa2_par
             r.x = s.x;
             r.y = s.y;
             r.st = fl_fa2_state{fp + 2 * o_node[k], fp + 2 * o_node[k] + s.n, sc + 4 * k, 0};
-            r.prm = *prm;
-            const bool exact = r.prm.repulsion == FL_REP_FMM && s.n < fmm_min_nodes;
-            if (exact) r.prm.repulsion = FL_REP_EXACT;
+            r.prm = resolve_repulsion(c->tuning, s.n, *prm);
+            if (prm->repulsion == FL_REP_FMM && s.n < fmm_min_nodes) r.prm.repulsion = FL_REP_EXACT;
+            const bool exact = r.prm.repulsion == FL_REP_EXACT;
             // rough cost of an iteration: exact repulsion is quadratic, the
             // FMM path a fixed launch-bound part plus a linear one
             load[b] += exact ? 1e-9 * (double)s.n * s.n + 20.0 : 1e-3 * s.n + 100.0;
@@ -614,6 +630,13 @@ void fa2_run_many(fl_ctx *c, const std::vector<FA2System> &sys, const fl_fa2_par
         throw;
     }
     (void)hipEventDestroy(ready);
+}
+
+void exact_repulsion(fl_ctx *c, int32_t n, const float *x, const float *y, const int32_t *deg, float kr, float *frx,
+                     float *fry)
+{
+    hipLaunchKernelGGL(k_rep_exact, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, x, y, deg, kr, frx, fry);
+    FL_LAUNCH_CHECK();
 }
 
 void fa2_validate(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg,
@@ -652,6 +675,9 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
                         float *fay, float *fgx, float *fgy)
 {
     FL_API_BEGIN(c)
+    FL_REQUIRE(prm != nullptr, "null FA2 parameters");
+    const fl_fa2_params rp = resolve_repulsion(c->tuning, n, *prm);
+    prm = &rp;
     validate_params(prm);
     FL_REQUIRE(x && y, "null positions");
     FL_REQUIRE((!frx) == (!fry) && (!fax) == (!fay) && (!fgx) == (!fgy), "force outputs come in x/y pairs");
@@ -681,6 +707,9 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
                           fl_step_stats *per_iter, bool always_sync)
 {
     FL_API_BEGIN(c)
+    FL_REQUIRE(prm != nullptr, "null FA2 parameters");
+    const fl_fa2_params rp = resolve_repulsion(c->tuning, n, *prm);
+    prm = &rp;
     validate_params(prm);
     FL_REQUIRE(x && y && st && st->fx_prev && st->fy_prev && st->scalars, "null positions or state");
     FL_REQUIRE(st->iter >= 0, "state iter must be >= 0");

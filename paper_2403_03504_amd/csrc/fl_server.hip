@@ -37,6 +37,7 @@ struct Job {
     std::vector<float> x, y;
     int32_t iters = 0;
     fl_fa2_params prm{};
+    fl_tuning tuning{};  // the server's table when the job was admitted
     int32_t state = FL_JOB_QUEUED;
     double t_arrive = 0, t_start = 0, t_done = 0;
     size_t bytes = 0;
@@ -66,6 +67,7 @@ struct fl_server {
     std::vector<std::thread> workers;
     std::chrono::steady_clock::time_point origin = std::chrono::steady_clock::now();
     fl_server_stats st{};
+    fl_tuning tuning{};
     std::string err;
 
     double now() const
@@ -116,7 +118,9 @@ void run_on_gpu(fl_ctx *ctx, hipStream_t s, DevArrays &d, Job &j)
     FL_CHECK_HIP(hipMemcpyAsync(d.x, j.x.data(), 4 * (size_t)j.n, hipMemcpyHostToDevice, s));
     FL_CHECK_HIP(hipMemcpyAsync(d.y, j.y.data(), 4 * (size_t)j.n, hipMemcpyHostToDevice, s));
     int64_t nnz = 0;
-    fl_status rc = fl_build_csr(ctx, j.n, j.m, d.src, d.dst, d.rp, d.col, d.deg, &nnz);
+    fl_status rc = fl_set_tuning(ctx, &j.tuning);
+    if (rc != FL_OK) throw fl::Error(rc, fl_last_error(ctx));
+    rc = fl_build_csr(ctx, j.n, j.m, d.src, d.dst, d.rp, d.col, d.deg, &nnz);
     if (rc != FL_OK) throw fl::Error(rc, fl_last_error(ctx));
     fl_kk_params kk;
     fl_kk_default_params(&kk);
@@ -153,6 +157,7 @@ void worker(fl_server *sv)
             sv->queue.pop_front();
             j->state = FL_JOB_RUNNING;
             j->t_start = sv->now();
+            j->tuning = sv->tuning;
             sv->in_use += j->bytes;
             sv->peak = std::max(sv->peak, sv->in_use);
             sv->st.admitted++;
@@ -211,6 +216,7 @@ fl_status server_create(fl_server **out, int device, size_t budget, int32_t slot
     if (!sv) return FL_ENOMEM;
     sv->device = device;
     sv->budget = budget;
+    fl_default_tuning(&sv->tuning);
     sv->slots = slots;
     sv->fake_ns = fake_ns;
     for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv);
@@ -331,6 +337,24 @@ fl_status fl_server_release(fl_server *sv, uint64_t id)
     if (it == sv->jobs.end()) return FL_EINVAL;
     if (it->second->state == FL_JOB_QUEUED || it->second->state == FL_JOB_RUNNING) return FL_EBUSY;
     sv->jobs.erase(it);
+    return FL_OK;
+}
+
+fl_status fl_server_set_tuning(fl_server *sv, const fl_tuning *tuning)
+{
+    if (!sv) return FL_EINVAL;
+    fl_tuning t;
+    if (tuning) t = *tuning;
+    else fl_default_tuning(&t);
+    try {
+        fl::check_tuning(t);
+    } catch (const fl::Error &e) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->err = e.what();
+        return e.code;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->tuning = t;
     return FL_OK;
 }
 

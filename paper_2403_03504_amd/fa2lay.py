@@ -25,16 +25,18 @@ _lib = ctypes.CDLL(LIB_PATH)
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENONFINITE, FL_EBUSY, FL_ECANCELED, FL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 GRAV_STRONG_MASS, GRAV_FA2_CONST, GRAV_STRONG_UNIT = 0, 1, 2
 SWING_PAPER, SWING_FA2 = 0, 1
-REP_EXACT, REP_FMM = 0, 1
+REP_EXACT, REP_FMM, REP_AUTO = 0, 1, 2
+TUNE_MAX_BUCKETS = 16
 PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact")
 
 EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
             "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_run", "fl_fmm_stats",
-            "fl_set_timing", "fl_set_graphs", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances", "fl_kk_steps",
-            "fl_kk_layout", "fl_layout", "fl_server_create", "fl_server_create_fake", "fl_server_submit",
-            "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release", "fl_server_cancel",
-            "fl_server_stats_get", "fl_server_last_error", "fl_server_destroy")
+            "fl_set_timing", "fl_set_graphs", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances",
+            "fl_kk_steps", "fl_kk_layout", "fl_layout", "fl_server_create", "fl_server_create_fake",
+            "fl_server_submit", "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release",
+            "fl_server_cancel", "fl_server_stats_get", "fl_server_last_error", "fl_server_destroy",
+            "fl_default_tuning", "fl_set_tuning", "fl_get_tuning", "fl_autotune", "fl_server_set_tuning")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELED = 0, 1, 2, 3, 4
 
 
@@ -78,6 +80,33 @@ class ServerStats(ctypes.Structure):
                                                "running", "bytes_in_use", "peak_bytes", "node_updates")]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("fmm_min_nodes", ctypes.c_int32), ("n_buckets", ctypes.c_int32),
+                ("bucket_max", ctypes.c_int32 * TUNE_MAX_BUCKETS), ("p", ctypes.c_int32 * TUNE_MAX_BUCKETS),
+                ("leaf_size", ctypes.c_int32 * TUNE_MAX_BUCKETS), ("max_rel_err", ctypes.c_double)]
+
+    def to_dict(self) -> dict:
+        nb = self.n_buckets
+        return {"fmm_min_nodes": self.fmm_min_nodes, "bucket_max": list(self.bucket_max[:nb]),
+                "p": list(self.p[:nb]), "leaf_size": list(self.leaf_size[:nb]), "max_rel_err": self.max_rel_err}
+
+    @staticmethod
+    def from_dict(d: dict) -> "Tuning":
+        t = Tuning()
+        nb = len(d["p"])
+        if not (len(d["bucket_max"]) == len(d["leaf_size"]) == nb):
+            raise ValueError("tuning: bucket_max, p and leaf_size differ in length")
+        t.fmm_min_nodes, t.n_buckets, t.max_rel_err = int(d["fmm_min_nodes"]), nb, float(d.get("max_rel_err", 0.0))
+        for i in range(nb):
+            t.bucket_max[i], t.p[i], t.leaf_size[i] = int(d["bucket_max"][i]), int(d["p"][i]), int(d["leaf_size"][i])
+        return t
+
+
+class TuneSample(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("p", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("feasible", ctypes.c_int32), ("ms", ctypes.c_double), ("rel_err", ctypes.c_double)]
+
+
 class StepStats(ctypes.Structure):
     _fields_ = [("swg", ctypes.c_double), ("tra", ctypes.c_double), ("speed", ctypes.c_double)]
 
@@ -113,6 +142,11 @@ _sig = {
     "fl_layout": ([P, _i32, P, P, P, P, P, ctypes.POINTER(FA2Params), _i32, ctypes.POINTER(KKParams), _i32, _i32,
                    ctypes.POINTER(LayoutStats)], _i32),
     "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
+    "fl_default_tuning": ([ctypes.POINTER(Tuning)], None),
+    "fl_set_tuning": ([P, ctypes.POINTER(Tuning)], _i32),
+    "fl_get_tuning": ([P, ctypes.POINTER(Tuning)], _i32),
+    "fl_autotune": ([P, _i32, P, P, P, _i32, P, ctypes.c_double, _i32, ctypes.POINTER(Tuning),
+                     ctypes.POINTER(TuneSample), _i32, ctypes.POINTER(_i32)], _i32),
 }
 _U64 = ctypes.c_uint64
 _sig.update({
@@ -127,6 +161,7 @@ _sig.update({
     "fl_server_stats_get": ([P, ctypes.POINTER(ServerStats)], _i32),
     "fl_server_last_error": ([P], ctypes.c_char_p),
     "fl_server_destroy": ([P], None),
+    "fl_server_set_tuning": ([P, ctypes.POINTER(Tuning)], _i32),
 })
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -146,6 +181,12 @@ def default_params(**kw) -> FA2Params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def default_tuning() -> dict:
+    t = Tuning()
+    _lib.fl_default_tuning(ctypes.byref(t))
+    return t.to_dict()
 
 
 def kk_params(**kw) -> KKParams:
@@ -363,6 +404,30 @@ class Context:
     def set_graphs(self, enable: bool):
         self._check(_lib.fl_set_graphs(self._h, 1 if enable else 0), "fl_set_graphs")
 
+    def set_tuning(self, tuning: dict | None):
+        t = Tuning.from_dict(tuning) if tuning is not None else None
+        self._check(_lib.fl_set_tuning(self._h, ctypes.byref(t) if t is not None else None), "fl_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(_lib.fl_get_tuning(self._h, ctypes.byref(t)), "fl_get_tuning")
+        return t.to_dict()
+
+    def autotune(self, x: torch.Tensor, y: torch.Tensor, deg: torch.Tensor, sizes, max_rel_err: float = 1e-3,
+                 reps: int = 3):
+        """fl_autotune: returns (tuning dict, list of measurement dicts); the
+        table is also installed in this context."""
+        sz, szp = _host_i32(sizes)
+        cap = len(sz) * 64
+        arr = (TuneSample * cap)()
+        ns = _i32()
+        t = Tuning()
+        self._check(_lib.fl_autotune(self._h, x.shape[0], _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                     _ptr(deg, torch.int32), len(sz), szp, max_rel_err, reps, ctypes.byref(t), arr,
+                                     cap, ctypes.byref(ns)), "fl_autotune")
+        samples = [{k: getattr(arr[i], k) for k, _ in TuneSample._fields_} for i in range(min(ns.value, cap))]
+        return t.to_dict(), samples
+
     def get_timing(self):
         ms = (ctypes.c_double * len(PHASES))()
         cnt = (_i64 * len(PHASES))()
@@ -428,6 +493,11 @@ class Server:
 
     def cancel(self, jid: int):
         self._check(_lib.fl_server_cancel(self._h, jid), "fl_server_cancel")
+
+    def set_tuning(self, tuning: dict | None):
+        t = Tuning.from_dict(tuning) if tuning is not None else None
+        self._check(_lib.fl_server_set_tuning(self._h, ctypes.byref(t) if t is not None else None),
+                    "fl_server_set_tuning")
 
     def stats(self) -> dict:
         s = ServerStats()

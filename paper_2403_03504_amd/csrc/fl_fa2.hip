@@ -470,68 +470,61 @@ static void destroy_graph(hipGraph_t g, hipGraphExec_t e)
 }
 
 // Iterations of independent systems grouped in branches (the systems of one
-// branch share its context and run one after the other): one eager iteration
-// of every system, then one graph holding one iteration of every system, a
-// parallel path per branch, replayed iters-1 times on `main`.  On return all
-// work is enqueued; `main` is ordered after every branch stream.
+// branch share its context and run one after the other on its stream): one
+// eager iteration of every system, then per branch one graph holding one
+// iteration of its systems, captured on and replayed iters-1 times on the
+// branch's own stream, so that branches run on separate hardware queues.
+// On return all work is enqueued and `main` is ordered after every branch.
 static void run_graph(hipStream_t main, std::vector<std::vector<CompRun>> &branches, int32_t *flags, int iters)
 {
     for (auto &br : branches)
         for (auto &r : br) iteration(r.c, r.g, r.ap, r.x, r.y, &r.st, &r.prm, flags, nullptr, 0);
-    std::vector<hipEvent_t> ev(branches.size() + 1, nullptr);
-    auto free_events = [&] {
+    const size_t nb = branches.size();
+    std::vector<hipGraph_t> graphs(nb, nullptr);
+    std::vector<hipGraphExec_t> execs(nb, nullptr);
+    std::vector<hipEvent_t> ev(nb, nullptr);
+    auto release = [&] {
+        for (size_t b = 0; b < nb; ++b) destroy_graph(graphs[b], execs[b]);
         for (auto e : ev)
             if (e) (void)hipEventDestroy(e);
     };
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
     try {
-        for (auto &e : ev) FL_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        hipEvent_t fork = ev.back();
-        // main waits for the eager iterations (run on the branch streams)
-        for (size_t k = 0; k < branches.size(); ++k) {
-            FL_CHECK_HIP(hipEventRecord(ev[k], branches[k][0].c->stream));
-            FL_CHECK_HIP(hipStreamWaitEvent(main, ev[k], 0));
-        }
         if (iters > 1) {
-            FL_CHECK_HIP(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
-            try {
-                FL_CHECK_HIP(hipEventRecord(fork, main));
-                for (size_t k = 0; k < branches.size(); ++k) {
-                    hipStream_t bs = branches[k][0].c->stream;
-                    FL_CHECK_HIP(hipStreamWaitEvent(bs, fork, 0));
-                    for (auto &r : branches[k]) {
+            for (size_t b = 0; b < nb; ++b) {
+                hipStream_t bs = branches[b][0].c->stream;
+                FL_CHECK_HIP(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+                try {
+                    for (auto &r : branches[b]) {
                         const int64_t it0 = r.st.iter;
                         iteration(r.c, r.g, r.ap, r.x, r.y, &r.st, &r.prm, flags, nullptr, 0);
                         r.st.iter = it0;  // recorded, not run
                     }
-                    FL_CHECK_HIP(hipEventRecord(ev[k], bs));
-                    FL_CHECK_HIP(hipStreamWaitEvent(main, ev[k], 0));
+                } catch (...) {
+                    hipGraph_t g2 = nullptr;
+                    (void)hipStreamEndCapture(bs, &g2);
+                    destroy_graph(g2, nullptr);
+                    throw;
                 }
-            } catch (...) {
-                hipGraph_t g2 = nullptr;
-                (void)hipStreamEndCapture(main, &g2);
-                destroy_graph(g2, nullptr);
-                throw;
+                FL_CHECK_HIP(hipStreamEndCapture(bs, &graphs[b]));
+                FL_CHECK_HIP(hipGraphInstantiate(&execs[b], graphs[b], nullptr, nullptr, 0));
             }
-            FL_CHECK_HIP(hipStreamEndCapture(main, &graph));
-            FL_CHECK_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-            for (int it = 1; it < iters; ++it) FL_CHECK_HIP(hipGraphLaunch(exec, main));
+            for (int it = 1; it < iters; ++it)
+                for (size_t b = 0; b < nb; ++b) FL_CHECK_HIP(hipGraphLaunch(execs[b], branches[b][0].c->stream));
             for (auto &br : branches)
                 for (auto &r : br) r.st.iter += iters - 1;
         }
-        // later work on a branch stream comes after the replays
-        FL_CHECK_HIP(hipEventRecord(fork, main));
-        for (auto &br : branches) FL_CHECK_HIP(hipStreamWaitEvent(br[0].c->stream, fork, 0));
+        for (size_t b = 0; b < nb; ++b) {
+            FL_CHECK_HIP(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+            FL_CHECK_HIP(hipEventRecord(ev[b], branches[b][0].c->stream));
+            FL_CHECK_HIP(hipStreamWaitEvent(main, ev[b], 0));
+        }
         FL_CHECK_HIP(hipStreamSynchronize(main));
     } catch (...) {
-        (void)hipStreamSynchronize(main);
-        destroy_graph(graph, exec);
-        free_events();
+        for (auto &br : branches) (void)hipStreamSynchronize(br[0].c->stream);
+        release();
         throw;
     }
-    destroy_graph(graph, exec);
-    free_events();
+    release();
 }
 
 }  // namespace

@@ -87,6 +87,8 @@ struct fl_ctx {
     hipStream_t aux[2] = {nullptr, nullptr};
     std::vector<fl_ctx *> sub;
     bool own_stream = false;     // a branch context destroys its stream
+    int32_t seg1_n = -1;         // n of the cached one-system descriptor
+    int tree_cbits = 0;          // system-id width of the hash keys last inserted
 };
 
 namespace fl {
@@ -256,5 +258,6 @@ void scan_excl_i64(fl_ctx *c, const int64_t *in, int64_t *out, int64_t n, const 
 // sorted result ended in (kt, vt).
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits);
 bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits);
+bool radix_sort_u64v(fl_ctx *c, uint64_t *k, int32_t *v, uint64_t *kt, int32_t *vt, int64_t n, int nbits);
 
 }  // namespace fl

@@ -4,7 +4,7 @@
 
 #include <vector>
 
-#include "fl_common.h"
+#include "fl_tree.h"
 
 namespace fl {
 
@@ -12,24 +12,27 @@ namespace fl {
 void fa2_validate(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg,
                   const fl_fa2_params *prm);
 
-// Exact O(n^2) repulsion of n points with masses deg + 1 (no validation).
-void exact_repulsion(fl_ctx *c, int32_t n, const float *x, const float *y, const int32_t *deg, float kr, float *frx,
-                     float *fry);
+// Exact O(n^2) repulsion within every system of `sg`, masses deg + 1 (no
+// validation).
+void exact_repulsion(fl_ctx *c, const Segs &sg, const float *x, const float *y, const int32_t *deg, float kr,
+                     float *frx, float *fry);
 
-// An independent system for fa2_run_many (device arrays; ids local to it).
-struct FA2System {
-    int32_t n;
-    int64_t nnz;  // row_ptr[n], known on the host
+// A batch of independent systems sharing one set of parameters: system k owns
+// nodes [coff[k], coff[k+1]) of the arrays, whose CSR ids are local to the
+// batch.  prm.repulsion is FL_REP_EXACT or FL_REP_FMM.
+struct FA2Batch {
+    std::vector<int32_t> coff;  // host, K + 1 entries
+    int64_t nnz;                // row_ptr[n], known on the host
     const int32_t *row_ptr, *col, *deg;
     float *x, *y;
+    fl_fa2_params prm;
 };
-// `iters` iterations of every system from a zero state, concurrently: the
-// systems are dealt to up to 8 branch contexts (own streams), one captured
-// graph holds one iteration of all of them and is replayed iters-1 times.
-// Ordered after earlier, and before later, work on the context's stream;
-// throws if an FMM capacity guard tripped.
-void fa2_run_many(fl_ctx *c, const std::vector<FA2System> &sys, const fl_fa2_params *prm, int iters,
-                  int32_t fmm_min_nodes, int32_t *flags);
+// `iters` iterations of every batch from a zero state.  With graphs on, each
+// batch runs on its own branch context (own stream) as one replayed graph,
+// concurrently with the others; otherwise one after the other, eagerly, on
+// the context's stream.  Ordered after earlier, and before later, work on the
+// context's stream; throws if an FMM capacity guard tripped.
+void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &b, int iters, int32_t *flags);
 
 int32_t components(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t *label);
 void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,

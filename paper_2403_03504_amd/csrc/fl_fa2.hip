@@ -19,7 +19,6 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int HEAVY = 32;
-constexpr int COMBINE_BLOCKS = 1024;  // fixed grid: one ticket atomic per block
 
 struct StepConsts {
     double ka, kg, tau, ks, ksmax, max_rise;
@@ -27,17 +26,30 @@ struct StepConsts {
 };
 
 // ---- exact repulsion ------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_rep_exact(int n, const float *__restrict__ x, const float *__restrict__ y,
+// Block b takes targets [tile + 256 (b % 8), +256) of system tile b / 8; every
+// target sums its own system's sources in 256-source tiles counted from the
+// system's first node (FP32 within a tile, FP64 across tiles), so a system's
+// forces do not depend on the other systems of the batch.
+constexpr int EXACT_SUB = SEG_TILE / NT;
+
+__global__ __launch_bounds__(NT) void k_rep_exact(Segs sg, const float *__restrict__ x, const float *__restrict__ y,
                                                   const int32_t *__restrict__ deg, float kr, float *__restrict__ frx,
                                                   float *__restrict__ fry)
 {
     __shared__ float4 tile[NT];
-    const int i = blockIdx.x * NT + threadIdx.x;
-    const float xi = i < n ? x[i] : 0.f, yi = i < n ? y[i] : 0.f;
+    const int2 tl = sg.tiles[blockIdx.x / EXACT_SUB];
+    const int comp = tl.x;
+    const int cb = sg.coff[comp], ce = sg.coff[comp + 1];
+    const int t0 = tl.y + (int)(blockIdx.x % EXACT_SUB) * NT;
+    const int tend = min(tl.y + SEG_TILE, ce);
+    if (t0 >= tend) return;  // the whole block
+    const int i = t0 + threadIdx.x;
+    const bool live = i < tend;
+    const float xi = live ? x[i] : 0.f, yi = live ? y[i] : 0.f;
     double ax = 0.0, ay = 0.0;
-    for (int t0 = 0; t0 < n; t0 += NT) {
-        const int j = t0 + threadIdx.x;
-        tile[threadIdx.x] = j < n ? make_float4(x[j], y[j], (float)(deg[j] + 1), 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int s0 = cb; s0 < ce; s0 += NT) {
+        const int j = s0 + threadIdx.x;
+        tile[threadIdx.x] = j < ce ? make_float4(x[j], y[j], (float)(deg[j] + 1), 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         float sx = 0.f, sy = 0.f;
 #pragma unroll 8
@@ -53,7 +65,7 @@ __global__ __launch_bounds__(NT) void k_rep_exact(int n, const float *__restrict
         ay += sy;
         __syncthreads();
     }
-    if (i < n) {
+    if (live) {
         const double km = (double)kr * (double)(deg[i] + 1);
         frx[i] = (float)(km * ax);
         fry[i] = (float)(km * ay);
@@ -113,7 +125,11 @@ __global__ __launch_bounds__(NT) void k_attract_chunks(const int32_t *__restrict
 }
 
 // ---- attraction + gravity + combine + swing/traction ---------------------------
-__global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict__ row_ptr,
+// One block per system tile.  Per-tile FP64 partial sums of swing and
+// traction; the last tile of a system to finish adds its system's partials in
+// tile order (fixed, so runs are bitwise reproducible and a system's result
+// does not depend on the batch) and sets that system's global speed.
+__global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const int32_t *__restrict__ deg,
                                                 const float2 *__restrict__ xy,
                                                 const float *__restrict__ frx, const float *__restrict__ fry,
@@ -122,14 +138,17 @@ __global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict
                                                 float *__restrict__ fy, float *__restrict__ fax,
                                                 float *__restrict__ fay, float *__restrict__ fgx,
                                                 float *__restrict__ fgy, double2 *__restrict__ part,
-                                                unsigned *__restrict__ ticket, double *__restrict__ scalars,
+                                                unsigned *__restrict__ cticket, double *__restrict__ scalars,
                                                 int32_t *__restrict__ flags, double *__restrict__ ring, int ring_it,
                                                 const int32_t *__restrict__ choff, const double2 *__restrict__ csum)
 {
     __shared__ double lds[NT / WAVE];
     __shared__ int is_last;
+    const int2 tl = sg.tiles[blockIdx.x];
+    const int comp = tl.x;
+    const int b1 = min(tl.y + SEG_TILE, sg.coff[comp + 1]);
     double wswg = 0.0, wtra = 0.0;
-    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    for (int i = tl.y + threadIdx.x; i < b1; i += NT) {
         double ax = 0.0, ay = 0.0;
         const float2 pi = xy[i];
         const double xi = pi.x, yi = pi.y;
@@ -202,28 +221,30 @@ __global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict
     if (!part) return;
     wswg = block_sum<double, NT>(wswg, lds);
     wtra = block_sum<double, NT>(wtra, lds);
+    const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
     if (threadIdx.x == 0) {
         part[blockIdx.x] = make_double2(wswg, wtra);
         __threadfence();
-        const unsigned t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
+        const unsigned t = atomicAdd(&cticket[comp], 1u);
+        is_last = (t == (unsigned)(nt - 1));
     }
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    // fixed-order reduction of the block partials
+    // fixed-order reduction of the system's tile partials
     double s0 = 0.0, s1 = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += NT) {
-        const double2 v = part[b];
+    for (int b = threadIdx.x; b < nt; b += NT) {
+        const double2 v = part[t0 + b];
         s0 += v.x;
         s1 += v.y;
     }
     s0 = block_sum<double, NT>(s0, lds);
     s1 = block_sum<double, NT>(s1, lds);
     if (threadIdx.x == 0) {
+        double *sc = scalars + 4 * (int64_t)comp;
         const double SWG = s0;
         const double TRA = (k.swing_mode == FL_SWING_FA2) ? s1 / 2.0 : s1;
-        const double sprev = scalars[0];
+        const double sprev = sc[0];
         double sG;
         if (SWG > 0.0) {
             sG = k.tau * TRA / SWG;
@@ -231,42 +252,45 @@ __global__ __launch_bounds__(NT) void k_combine(int n, const int32_t *__restrict
         } else {
             sG = first ? 1.0 : (1.0 + k.max_rise) * sprev;
         }
-        scalars[0] = sG;
-        scalars[1] = SWG;
-        scalars[2] = TRA;
+        sc[0] = sG;
+        sc[1] = SWG;
+        sc[2] = TRA;
         if (ring) {
             ring[3 * ring_it + 0] = SWG;
             ring[3 * ring_it + 1] = TRA;
             ring[3 * ring_it + 2] = sG;
         }
-        *ticket = 0u;
+        cticket[comp] = 0u;
     }
 }
 
-__global__ __launch_bounds__(NT) void k_update(int n, float *__restrict__ x, float *__restrict__ y,
+__global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, float *__restrict__ y,
                                                const float *__restrict__ fx, const float *__restrict__ fy,
                                                float *__restrict__ fpx, float *__restrict__ fpy, int first,
                                                const double *__restrict__ scalars, double ks, double ksmax,
                                                int32_t *__restrict__ flags)
 {
-    const int i = blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
     if (*flags & 1) return;  // non-finite forces: leave the layout as it was
-    const double sG = scalars[0];
-    const float Fx = fx[i], Fy = fy[i];
-    const double px = first ? 0.0 : (double)fpx[i], py = first ? 0.0 : (double)fpy[i];
-    const double dx = (double)Fx - px, dy = (double)Fy - py;
-    const double swg = sqrt(dx * dx + dy * dy);
-    double s = ks * sG / (1.0 + sG * sqrt(swg));
-    const double fn = sqrt((double)Fx * Fx + (double)Fy * Fy);
-    if (fn > 0.0) s = fmin(s, ksmax / fn);
-    const float nx = (float)((double)x[i] + s * (double)Fx);
-    const float ny = (float)((double)y[i] + s * (double)Fy);
-    x[i] = nx;
-    y[i] = ny;
-    fpx[i] = Fx;
-    fpy[i] = Fy;
-    if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags, 2);
+    const int2 tl = sg.tiles[blockIdx.x];
+    const int comp = tl.x;
+    const int b1 = min(tl.y + SEG_TILE, sg.coff[comp + 1]);
+    const double sG = scalars[4 * (int64_t)comp];
+    for (int i = tl.y + threadIdx.x; i < b1; i += NT) {
+        const float Fx = fx[i], Fy = fy[i];
+        const double px = first ? 0.0 : (double)fpx[i], py = first ? 0.0 : (double)fpy[i];
+        const double dx = (double)Fx - px, dy = (double)Fy - py;
+        const double swg = sqrt(dx * dx + dy * dy);
+        double s = ks * sG / (1.0 + sG * sqrt(swg));
+        const double fn = sqrt((double)Fx * Fx + (double)Fy * Fy);
+        if (fn > 0.0) s = fmin(s, ksmax / fn);
+        const float nx = (float)((double)x[i] + s * (double)Fx);
+        const float ny = (float)((double)y[i] + s * (double)Fy);
+        x[i] = nx;
+        y[i] = ny;
+        fpx[i] = Fx;
+        fpy[i] = Fy;
+        if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags, 2);
+    }
 }
 
 __global__ void k_validate_rows(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
@@ -391,16 +415,16 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
     return xy;
 }
 
-static void repulsion(fl_ctx *c, const GraphArgs &g, const float *x, const float *y, const fl_fa2_params *p,
-                      float *frx, float *fry)
+static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float *x, const float *y,
+                      const fl_fa2_params *p, float *frx, float *fry)
 {
     if (p->repulsion == FL_REP_EXACT) {
         PhaseTimer pt(c, FL_PH_EXACT);
-        hipLaunchKernelGGL(k_rep_exact, dim3(grid_for(g.n, NT)), dim3(NT), 0, c->stream, g.n, x, y, g.deg,
+        hipLaunchKernelGGL(k_rep_exact, dim3(sg.ntiles * EXACT_SUB), dim3(NT), 0, c->stream, sg, x, y, g.deg,
                            (float)p->kr, frx, fry);
         FL_LAUNCH_CHECK();
     } else {
-        fmm_repulsion(c, g.n, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, (float)p->kr, frx, fry);
+        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, (float)p->kr, frx, fry);
     }
 }
 
@@ -409,53 +433,13 @@ static StepConsts consts(const fl_fa2_params *p)
     return StepConsts{p->ka, p->kg, p->tau, p->ks, p->ksmax, p->max_rise, p->gravity_mode, p->swing_mode};
 }
 
-// one iteration; flags must have been cleared by the caller
-static void iteration(fl_ctx *c, const GraphArgs &g, const AttractPlan &ap, float *x, float *y, fl_fa2_state *st,
-                      const fl_fa2_params *p, int32_t *flags, double *ring, int ring_it)
-{
-    const int n = g.n;
-    float *frx = ws<float>(c, "fa2_frx", n);
-    float *fry = ws<float>(c, "fa2_fry", n);
-    float *fcx = ws<float>(c, "fa2_fcx", n);
-    float *fcy = ws<float>(c, "fa2_fcy", n);
-    const unsigned nb = grid_for(n, NT);
-    const unsigned nbc = grid_for(n, NT, COMBINE_BLOCKS);
-    double2 *part = ws<double2>(c, "fa2_part", nbc);
-    unsigned *ticket = ws_zeroed<unsigned>(c, "fa2_ticket", 4);
-    const int first = st->iter == 0 ? 1 : 0;
-    repulsion(c, g, x, y, p, frx, fry);
-    {
-        PhaseTimer pt(c, FL_PH_ATTRACT);
-        double2 *csum = ws<double2>(c, "at_csum", ap.cap);
-        const float2 *xy = attract_chunks(c, g, ap, x, y, csum);
-        hipLaunchKernelGGL(k_combine, dim3(nbc), dim3(NT), 0, c->stream, n, g.row_ptr, g.col, g.deg, xy, frx, fry,
-                           consts(p), st->fx_prev, st->fy_prev, first, fcx, fcy, (float *)nullptr, (float *)nullptr,
-                           (float *)nullptr, (float *)nullptr, part, ticket, st->scalars, flags, ring, ring_it,
-                           ap.choff, (const double2 *)csum);
-        FL_LAUNCH_CHECK();
-    }
-    {
-        PhaseTimer pt(c, FL_PH_UPDATE);
-        hipLaunchKernelGGL(k_update, dim3(nb), dim3(NT), 0, c->stream, n, x, y, fcx, fcy, st->fx_prev, st->fy_prev,
-                           first, st->scalars, p->ks, p->ksmax, flags);
-        FL_LAUNCH_CHECK();
-    }
-    st->iter += 1;
-}
-
-// ---- graph replay ------------------------------------------------------------
-// An iteration is a fixed sequence of launches whose sizes depend only on n
-// and the parameters (every data-dependent count stays on the device), so
-// after one eager iteration (which sizes the workspace and makes F_prev
-// valid) one more is captured on private streams and the graph is replayed.
-// Captured iterations are bitwise the same as eager ones.
-constexpr int GRAPH_MIN_ITERS = 4;
-constexpr size_t MANY_BRANCHES = 8;
-
 namespace {
 
-struct CompRun {
-    fl_ctx *c;  // context (and stream) of the branch the system runs on
+// A batch of K independent systems sharing parameters (K = 1: one graph).
+// The state's scalars hold 4 doubles per system.
+struct Sys {
+    fl_ctx *c;  // context (and stream) the batch runs on
+    Segs sg;
     GraphArgs g;
     AttractPlan ap;
     float *x, *y;
@@ -463,64 +447,102 @@ struct CompRun {
     fl_fa2_params prm;
 };
 
+// one iteration; flags must have been cleared by the caller
+static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
+{
+    fl_ctx *c = b.c;
+    const int n = b.g.n;
+    float *frx = ws<float>(c, "fa2_frx", n);
+    float *fry = ws<float>(c, "fa2_fry", n);
+    float *fcx = ws<float>(c, "fa2_fcx", n);
+    float *fcy = ws<float>(c, "fa2_fcy", n);
+    double2 *part = ws<double2>(c, "fa2_part", (size_t)b.sg.ntiles);
+    unsigned *cticket = ws_zeroed<unsigned>(c, "fa2_cticket", (size_t)b.sg.K);
+    const int first = b.st.iter == 0 ? 1 : 0;
+    repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, frx, fry);
+    {
+        PhaseTimer pt(c, FL_PH_ATTRACT);
+        double2 *csum = ws<double2>(c, "at_csum", b.ap.cap);
+        const float2 *xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum);
+        hipLaunchKernelGGL(k_combine, dim3(b.sg.ntiles), dim3(NT), 0, c->stream, b.sg, b.g.row_ptr, b.g.col,
+                           b.g.deg, xy, (const float *)frx, (const float *)fry, consts(&b.prm),
+                           (const float *)b.st.fx_prev, (const float *)b.st.fy_prev, first, fcx, fcy,
+                           (float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, part, cticket,
+                           b.st.scalars, flags, ring, ring_it, (const int32_t *)b.ap.choff, (const double2 *)csum);
+        FL_LAUNCH_CHECK();
+    }
+    {
+        PhaseTimer pt(c, FL_PH_UPDATE);
+        hipLaunchKernelGGL(k_update, dim3(b.sg.ntiles), dim3(NT), 0, c->stream, b.sg, b.x, b.y,
+                           (const float *)fcx, (const float *)fcy, b.st.fx_prev, b.st.fy_prev, first,
+                           (const double *)b.st.scalars, b.prm.ks, b.prm.ksmax, flags);
+        FL_LAUNCH_CHECK();
+    }
+    b.st.iter += 1;
+}
+
+// ---- graph replay ------------------------------------------------------------
+// An iteration is a fixed sequence of launches whose sizes depend only on the
+// systems and the parameters (every data-dependent count stays on the
+// device), so after one eager iteration (which sizes the workspace and makes
+// F' valid) one more is captured and the graph is replayed.  Captured
+// iterations are bitwise the same as eager ones.
+constexpr int GRAPH_MIN_ITERS = 4;
+
 static void destroy_graph(hipGraph_t g, hipGraphExec_t e)
 {
     if (e) (void)hipGraphExecDestroy(e);
     if (g) (void)hipGraphDestroy(g);
 }
 
-// Iterations of independent systems grouped in branches (the systems of one
-// branch share its context and run one after the other on its stream): one
-// eager iteration of every system, then per branch one graph holding one
-// iteration of its systems, captured on and replayed iters-1 times on the
-// branch's own stream, so that branches run on separate hardware queues.
-// On return all work is enqueued and `main` is ordered after every branch.
-static void run_graph(hipStream_t main, std::vector<std::vector<CompRun>> &branches, int32_t *flags, int iters)
+// Iterations of batches, each on its own context and stream: one eager
+// iteration of every batch, then per batch one graph holding one iteration,
+// captured on and replayed iters-1 times on the batch's stream, so that
+// batches run on separate hardware queues.  On return all work is enqueued
+// and `main` is ordered after every batch.
+static void run_graph(hipStream_t main, std::vector<Sys> &bs, int32_t *flags, int iters)
 {
-    for (auto &br : branches)
-        for (auto &r : br) iteration(r.c, r.g, r.ap, r.x, r.y, &r.st, &r.prm, flags, nullptr, 0);
-    const size_t nb = branches.size();
+    for (auto &b : bs) iteration(b, flags, nullptr, 0);
+    const size_t nb = bs.size();
     std::vector<hipGraph_t> graphs(nb, nullptr);
     std::vector<hipGraphExec_t> execs(nb, nullptr);
     std::vector<hipEvent_t> ev(nb, nullptr);
     auto release = [&] {
-        for (size_t b = 0; b < nb; ++b) destroy_graph(graphs[b], execs[b]);
+        for (size_t k = 0; k < nb; ++k) destroy_graph(graphs[k], execs[k]);
         for (auto e : ev)
             if (e) (void)hipEventDestroy(e);
     };
     try {
         if (iters > 1) {
-            for (size_t b = 0; b < nb; ++b) {
-                hipStream_t bs = branches[b][0].c->stream;
-                FL_CHECK_HIP(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+            for (size_t k = 0; k < nb; ++k) {
+                hipStream_t s = bs[k].c->stream;
+                FL_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                const int64_t it0 = bs[k].st.iter;
                 try {
-                    for (auto &r : branches[b]) {
-                        const int64_t it0 = r.st.iter;
-                        iteration(r.c, r.g, r.ap, r.x, r.y, &r.st, &r.prm, flags, nullptr, 0);
-                        r.st.iter = it0;  // recorded, not run
-                    }
+                    iteration(bs[k], flags, nullptr, 0);
                 } catch (...) {
                     hipGraph_t g2 = nullptr;
-                    (void)hipStreamEndCapture(bs, &g2);
+                    (void)hipStreamEndCapture(s, &g2);
                     destroy_graph(g2, nullptr);
+                    bs[k].st.iter = it0;
                     throw;
                 }
-                FL_CHECK_HIP(hipStreamEndCapture(bs, &graphs[b]));
-                FL_CHECK_HIP(hipGraphInstantiate(&execs[b], graphs[b], nullptr, nullptr, 0));
+                bs[k].st.iter = it0;  // recorded, not run
+                FL_CHECK_HIP(hipStreamEndCapture(s, &graphs[k]));
+                FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
             }
             for (int it = 1; it < iters; ++it)
-                for (size_t b = 0; b < nb; ++b) FL_CHECK_HIP(hipGraphLaunch(execs[b], branches[b][0].c->stream));
-            for (auto &br : branches)
-                for (auto &r : br) r.st.iter += iters - 1;
+                for (size_t k = 0; k < nb; ++k) FL_CHECK_HIP(hipGraphLaunch(execs[k], bs[k].c->stream));
+            for (auto &b : bs) b.st.iter += iters - 1;
         }
-        for (size_t b = 0; b < nb; ++b) {
-            FL_CHECK_HIP(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
-            FL_CHECK_HIP(hipEventRecord(ev[b], branches[b][0].c->stream));
-            FL_CHECK_HIP(hipStreamWaitEvent(main, ev[b], 0));
+        for (size_t k = 0; k < nb; ++k) {
+            FL_CHECK_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+            FL_CHECK_HIP(hipEventRecord(ev[k], bs[k].c->stream));
+            FL_CHECK_HIP(hipStreamWaitEvent(main, ev[k], 0));
         }
         FL_CHECK_HIP(hipStreamSynchronize(main));
     } catch (...) {
-        for (auto &br : branches) (void)hipStreamSynchronize(br[0].c->stream);
+        for (auto &b : bs) (void)hipStreamSynchronize(b.c->stream);
         release();
         throw;
     }
@@ -529,106 +551,69 @@ static void run_graph(hipStream_t main, std::vector<std::vector<CompRun>> &branc
 
 }  // namespace
 
-// Independent systems (the large components of a layout), each `iters`
-// iterations from a zero state, concurrently.  Systems are dealt to at most
-// MANY_BRANCHES branches, largest first, each to the branch with the least
-// work so far; a branch has its own context and stream, and its systems run
-// one after the other on it.  Per-system state (F', scalars, attraction
-// chunks) sits in one slab of the caller's workspace.
-void fa2_run_many(fl_ctx *c, const std::vector<FA2System> &sys, const fl_fa2_params *prm, int iters,
-                  int32_t fmm_min_nodes, int32_t *flags)
+// Batches of independent systems (the large components of a layout), each
+// `iters` iterations from a zero state.  Batch k runs on branch context k
+// (own stream and workspace: tree, lists, state, attraction plan), all of
+// its systems in the same launches; with graphs on, the batches' replayed
+// graphs run concurrently, otherwise the batches run one after the other as
+// eager launches on the caller's stream.
+void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &in, int iters, int32_t *flags)
 {
-    if (sys.empty() || iters <= 0) return;
-    const size_t ns = sys.size();
-    const size_t nbr = std::min<size_t>(ns, MANY_BRANCHES);
-    std::vector<size_t> order(ns);
-    for (size_t k = 0; k < ns; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return sys[a].n > sys[b].n; });
-    // slab offsets
-    std::vector<int64_t> o_node(ns), o_rp(ns), o_ch(ns);
-    int64_t t_node = 0, t_rp = 0, t_ch = 0;
-    for (size_t k = 0; k < ns; ++k) {
-        o_node[k] = t_node;
-        o_rp[k] = t_rp;
-        o_ch[k] = t_ch;
-        t_node += sys[k].n;
-        t_rp += (int64_t)sys[k].n + 1;
-        t_ch += attract_cap(sys[k].nnz);
-    }
-    float *fp = ws<float>(c, "many_fp", 2 * (size_t)t_node);
-    double *sc = ws<double>(c, "many_sc", 4 * ns);
-    int32_t *choff = ws<int32_t>(c, "many_choff", (size_t)t_rp);
-    int2 *chunks = ws<int2>(c, "many_chunks", (size_t)t_ch);
-
-    if (!c->use_graphs) {
-        // one system after the other, eager launches on the caller's stream
-        for (size_t k : order) {
-            const FA2System &s = sys[k];
-            GraphArgs g{s.n, s.row_ptr, s.col, s.deg};
-            AttractPlan ap = attract_plan(c, g, choff + o_rp[k], chunks + o_ch[k], s.nnz);
-            fl_fa2_state st{fp + 2 * o_node[k], fp + 2 * o_node[k] + s.n, sc + 4 * k, 0};
-            fl_fa2_params p = resolve_repulsion(c->tuning, s.n, *prm);
-            if (prm->repulsion == FL_REP_FMM && s.n < fmm_min_nodes) p.repulsion = FL_REP_EXACT;
-            for (int it = 0; it < iters; ++it) iteration(c, g, ap, s.x, s.y, &st, &p, flags, nullptr, 0);
-        }
-        if (prm->repulsion != FL_REP_EXACT && tree_error_bits(c, true))
-            throw Error(FL_EHIP, "FMM capacity guard tripped (tree or list sizes)");
-        return;
-    }
-    hipStream_t main = aux_stream(c, 1);
-    std::vector<fl_ctx *> ctxs(nbr);
+    if (in.empty() || iters <= 0) return;
+    const bool graphs = c->use_graphs;
     hipEvent_t ready = nullptr;
     FL_CHECK_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    std::vector<Sys> bs;
     try {
         FL_CHECK_HIP(hipEventRecord(ready, c->stream));  // inputs were prepared on the caller's stream
-        for (size_t b = 0; b < nbr; ++b) {
-            ctxs[b] = sub_ctx(c, b);
-            ctxs[b]->timing = false;
-            FL_CHECK_HIP(hipStreamWaitEvent(ctxs[b]->stream, ready, 0));
+        for (size_t k = 0; k < in.size(); ++k) {
+            const FA2Batch &B = in[k];
+            fl_ctx *bc = graphs ? sub_ctx(c, k) : c;
+            if (graphs) {
+                bc->timing = false;
+                FL_CHECK_HIP(hipStreamWaitEvent(bc->stream, ready, 0));
+            }
+            const std::string tag = "bt" + std::to_string(graphs ? 0 : k);
+            Sys b;
+            b.c = bc;
+            b.sg = make_segs(bc, B.coff, tag.c_str());
+            const int n = b.sg.n;
+            b.g = GraphArgs{n, B.row_ptr, B.col, B.deg};
+            int32_t *choff = ws<int32_t>(bc, (tag + "_choff").c_str(), (size_t)n + 1);
+            int2 *chunks = ws<int2>(bc, (tag + "_chunks").c_str(), (size_t)attract_cap(B.nnz));
+            b.ap = attract_plan(bc, b.g, choff, chunks, B.nnz);
+            b.x = B.x;
+            b.y = B.y;
+            b.st = fl_fa2_state{ws<float>(bc, (tag + "_fpx").c_str(), n), ws<float>(bc, (tag + "_fpy").c_str(), n),
+                                ws<double>(bc, (tag + "_sc").c_str(), 4 * (size_t)b.sg.K), 0};
+            b.prm = B.prm;
+            bs.push_back(b);
         }
-        std::vector<std::vector<CompRun>> branches(nbr);
-        std::vector<double> load(nbr, 0.0);
-        for (size_t k : order) {
-            const size_t b = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
-            const FA2System &s = sys[k];
-            CompRun r;
-            r.c = ctxs[b];
-            r.g = GraphArgs{s.n, s.row_ptr, s.col, s.deg};
-            r.ap = attract_plan(r.c, r.g, choff + o_rp[k], chunks + o_ch[k], s.nnz);
-            r.x = s.x;
-            r.y = s.y;
-            r.st = fl_fa2_state{fp + 2 * o_node[k], fp + 2 * o_node[k] + s.n, sc + 4 * k, 0};
-            r.prm = resolve_repulsion(c->tuning, s.n, *prm);
-            if (prm->repulsion == FL_REP_FMM && s.n < fmm_min_nodes) r.prm.repulsion = FL_REP_EXACT;
-            const bool exact = r.prm.repulsion == FL_REP_EXACT;
-            // rough cost of an iteration: exact repulsion is quadratic, the
-            // FMM path a fixed launch-bound part plus a linear one
-            load[b] += exact ? 1e-9 * (double)s.n * s.n + 20.0 : 1e-3 * s.n + 100.0;
-            branches[b].push_back(r);
+        if (graphs) {
+            hipStream_t main = aux_stream(c, 1);
+            run_graph(main, bs, flags, iters);
+            FL_CHECK_HIP(hipEventRecord(ready, main));
+            FL_CHECK_HIP(hipStreamWaitEvent(c->stream, ready, 0));
+        } else {
+            for (auto &b : bs)
+                for (int it = 0; it < iters; ++it) iteration(b, flags, nullptr, 0);
         }
-        run_graph(main, branches, flags, iters);
-        FL_CHECK_HIP(hipEventRecord(ready, main));
-        FL_CHECK_HIP(hipStreamWaitEvent(c->stream, ready, 0));
-        for (auto &br : branches) {
-            bool fmm = false;
-            for (auto &r : br) fmm = fmm || r.prm.repulsion == FL_REP_FMM;
-            if (fmm && tree_error_bits(br[0].c, true))
+        for (auto &b : bs)
+            if (b.prm.repulsion != FL_REP_EXACT && tree_error_bits(b.c, true))
                 throw Error(FL_EHIP, "FMM capacity guard tripped (tree or list sizes)");
-        }
     } catch (...) {
-        (void)hipStreamSynchronize(main);
-        for (auto *cc : ctxs)
-            if (cc) (void)hipStreamSynchronize(cc->stream);
+        if (graphs)
+            for (auto &b : bs) (void)hipStreamSynchronize(b.c->stream);
         (void)hipEventDestroy(ready);
         throw;
     }
     (void)hipEventDestroy(ready);
 }
 
-void exact_repulsion(fl_ctx *c, int32_t n, const float *x, const float *y, const int32_t *deg, float kr, float *frx,
-                     float *fry)
+void exact_repulsion(fl_ctx *c, const Segs &sg, const float *x, const float *y, const int32_t *deg, float kr,
+                     float *frx, float *fry)
 {
-    hipLaunchKernelGGL(k_rep_exact, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, x, y, deg, kr, frx, fry);
+    hipLaunchKernelGGL(k_rep_exact, dim3(sg.ntiles * EXACT_SUB), dim3(NT), 0, c->stream, sg, x, y, deg, kr, frx, fry);
     FL_LAUNCH_CHECK();
 }
 
@@ -676,16 +661,16 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
     FL_REQUIRE((!frx) == (!fry) && (!fax) == (!fay) && (!fgx) == (!fgy), "force outputs come in x/y pairs");
     GraphArgs g{n, row_ptr, col_idx, deg};
     validate_graph(c, g);
+    const Segs sg = segs_single(c, n);
     float *rx = frx ? frx : ws<float>(c, "fa2_frx", n);
     float *ry = fry ? fry : ws<float>(c, "fa2_fry", n);
-    repulsion(c, g, x, y, prm, rx, ry);
+    repulsion(c, sg, g, x, y, prm, rx, ry);
     if (fax || fgx) {
         int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
         AttractPlan ap = attract_plan(c, g);
         double2 *csum = ws<double2>(c, "at_csum", ap.cap);
         const float2 *xy = attract_chunks(c, g, ap, x, y, csum);
-        hipLaunchKernelGGL(k_combine, dim3(grid_for(n, NT, COMBINE_BLOCKS)), dim3(NT), 0, c->stream, n, row_ptr,
-                           col_idx, deg, xy,
+        hipLaunchKernelGGL(k_combine, dim3(sg.ntiles), dim3(NT), 0, c->stream, sg, row_ptr, col_idx, deg, xy,
                            (const float *)nullptr, (const float *)nullptr, consts(prm), (const float *)nullptr,
                            (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
                            (double2 *)nullptr, (unsigned *)nullptr, (double *)nullptr, flags, (double *)nullptr, 0,
@@ -715,7 +700,7 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
     FL_LAUNCH_CHECK();
     if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
     double *ring = per_iter ? ws<double>(c, "fa2_ring", 3 * (size_t)(iters > 0 ? iters : 1)) : nullptr;
-    AttractPlan ap = attract_plan(c, g);
+    Sys b{c, segs_single(c, n), g, attract_plan(c, g), x, y, *st, *prm};
     if (!ring && !c->timing && iters >= GRAPH_MIN_ITERS && c->use_graphs) {
         // the caller's stream may be the null stream, which cannot be
         // captured: run on private streams ordered after it and before
@@ -728,12 +713,12 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
             FL_CHECK_HIP(hipEventRecord(e, user));
             FL_CHECK_HIP(hipStreamWaitEvent(bs, e, 0));
             c->stream = bs;
-            std::vector<std::vector<CompRun>> br{{CompRun{c, g, ap, x, y, *st, *prm}}};
-            run_graph(main, br, flags, iters);
+            std::vector<Sys> one{b};
+            run_graph(main, one, flags, iters);
             c->stream = user;
             FL_CHECK_HIP(hipEventRecord(e, main));
             FL_CHECK_HIP(hipStreamWaitEvent(user, e, 0));
-            st->iter = br[0][0].st.iter;
+            st->iter = one[0].st.iter;
         } catch (...) {
             if (c->stream != user) (void)hipStreamSynchronize(c->stream);
             c->stream = user;
@@ -742,7 +727,8 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
         }
         (void)hipEventDestroy(e);
     } else {
-        for (int it = 0; it < iters; ++it) iteration(c, g, ap, x, y, st, prm, flags, ring, it);
+        for (int it = 0; it < iters; ++it) iteration(b, flags, ring, it);
+        st->iter = b.st.iter;
     }
     if (per_iter || always_sync) {
         int32_t f = read_i32(c, flags);

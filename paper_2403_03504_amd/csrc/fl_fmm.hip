@@ -26,6 +26,8 @@
 //             operands: no per-lane memory traffic in the pair loop).  Leaves
 //             of at most 32 (16) targets run 2 (4) lane groups on interleaved
 //             sources, combined with xor shuffles (fixed order).
+#include <algorithm>
+
 #include "fl_fmm.h"
 
 namespace fl {
@@ -57,7 +59,8 @@ struct CellGeo {
 
 __device__ __forceinline__ CellGeo geo(const TreeView &t, int c)
 {
-    const double x0 = t.root[0], y0 = t.root[1], L = t.root[2];
+    const double *rt = t.root + 4 * (int64_t)cell_comp(t, c);
+    const double x0 = rt[0], y0 = rt[1], L = rt[2];
     const int l = t.lvl[c];
     const uint32_t v = t.ixy[c];
     const double w = ldexp(L, -l);
@@ -211,37 +214,42 @@ __device__ __forceinline__ int first_cell_at(const TreeView &t, int ncells, int 
 
 constexpr int M2M_CUT = 4;  // subtrees rooted at level 4: 256 workgroups
 
-// k_m2m_sub: workgroup r owns the subtree of the level-4 square r (a
-// contiguous range of the pre-order); its internal cells are shifted level by
-// level, deepest first, with a workgroup barrier between levels.
+// k_m2m_sub: a workgroup owns the subtree of one level-4 square of one
+// system (a contiguous range of the pre-order) at a time; its internal cells
+// are shifted level by level, deepest first, with a workgroup barrier
+// between levels.  Subtree r is square r % 256 of system r / 256.
 template <int P>
 __global__ __launch_bounds__(256) void k_m2m_sub(TreeView t, const float2 *__restrict__ T, float2 *M)
 {
     const int ncells = t.counts[0];
-    const int r = blockIdx.x;
     const int side = 1 << M2M_CUT;
     if (ncells <= 1 || M2M_CUT >= t.bits) return;
     const int64_t H = hash_size(ncells, t.hash_cap);
     const uint64_t ep = *t.epoch;
-    const int root = hash_find(t, H, ep, M2M_CUT, r % side, r / side);
-    if (root < 0 || is_leaf4(t.child[root])) return;
-    const int c0 = root, c1 = first_cell_at(t, ncells, t.end[root]);
-    int maxl = M2M_CUT;
-    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) maxl = max(maxl, t.lvl[c]);
     __shared__ int sm[4];
-    maxl = wave_max_i(maxl);
-    if (lane_id() == 0) sm[threadIdx.x / WAVE] = maxl;
-    __syncthreads();
-    maxl = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
-    for (int lev = maxl - 1; lev >= M2M_CUT; --lev) {
-        for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x)
-            if (t.lvl[c] == lev && !is_leaf4(t.child[c])) m2m_cell<P>(t, T, M, c);
+    const int64_t nsub = (int64_t)t.K * side * side;
+    for (int64_t r = blockIdx.x; r < nsub; r += gridDim.x) {
+        const int comp = (int)(r >> (2 * M2M_CUT)), sq = (int)(r & (side * side - 1));
+        const int root = hash_find(t, H, ep, comp, M2M_CUT, sq % side, sq / side);
+        if (root < 0 || is_leaf4(t.child[root])) continue;  // uniform over the workgroup
+        const int c0 = root, c1 = first_cell_at(t, ncells, t.end[root]);
+        int maxl = M2M_CUT;
+        for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) maxl = max(maxl, t.lvl[c]);
+        maxl = wave_max_i(maxl);
+        if (lane_id() == 0) sm[threadIdx.x / WAVE] = maxl;
         __syncthreads();
+        maxl = max(max(sm[0], sm[1]), max(sm[2], sm[3]));
+        __syncthreads();
+        for (int lev = maxl - 1; lev >= M2M_CUT; --lev) {
+            for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x)
+                if (t.lvl[c] == lev && !is_leaf4(t.child[c])) m2m_cell<P>(t, T, M, c);
+            __syncthreads();
+        }
     }
 }
 
-// k_m2m_top: the internal cells above level 4 (at most 85 squares, found by
-// their (level, ix, iy) key), one workgroup.
+// k_m2m_top: the internal cells above level 4 (at most 85 squares per
+// system, found by their (system, level, ix, iy) key), a workgroup per system.
 template <int P>
 __global__ __launch_bounds__(256) void k_m2m_top(TreeView t, const float2 *__restrict__ T, float2 *M)
 {
@@ -250,13 +258,15 @@ __global__ __launch_bounds__(256) void k_m2m_top(TreeView t, const float2 *__res
     const int64_t H = hash_size(ncells, t.hash_cap);
     const uint64_t ep = *t.epoch;
     const int top = min(M2M_CUT, t.bits) - 1;
-    for (int lev = top; lev >= 0; --lev) {
-        const int side = 1 << lev;
-        for (int r = threadIdx.x; r < side * side; r += blockDim.x) {
-            const int c = hash_find(t, H, ep, lev, r % side, r / side);
-            if (c >= 0 && !is_leaf4(t.child[c])) m2m_cell<P>(t, T, M, c);
+    for (int comp = blockIdx.x; comp < t.K; comp += gridDim.x) {
+        for (int lev = top; lev >= 0; --lev) {
+            const int side = 1 << lev;
+            for (int r = threadIdx.x; r < side * side; r += blockDim.x) {
+                const int c = hash_find(t, H, ep, comp, lev, r % side, r / side);
+                if (c >= 0 && !is_leaf4(t.child[c])) m2m_cell<P>(t, T, M, c);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -553,8 +563,11 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
         if (fresh) hipLaunchKernelGGL(k_m2m_table<P>, dim3(1), dim3(256), 0, c->stream, T);
         hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(lcap, 4, 2048)), dim3(256), 0, c->stream, tv,
                            (const float4 *)t.part, (const int32_t *)t.leaf_cell, M);
-        hipLaunchKernelGGL(k_m2m_sub<P>, dim3(1 << (2 * M2M_CUT)), dim3(256), 0, c->stream, tv, (const float2 *)T, M);
-        hipLaunchKernelGGL(k_m2m_top<P>, dim3(1), dim3(256), 0, c->stream, tv, (const float2 *)T, M);
+        const int64_t nsub = (int64_t)t.s.K << (2 * M2M_CUT);
+        hipLaunchKernelGGL(k_m2m_sub<P>, dim3((unsigned)std::min<int64_t>(nsub, 2048)), dim3(256), 0, c->stream, tv,
+                           (const float2 *)T, M);
+        hipLaunchKernelGGL(k_m2m_top<P>, dim3((unsigned)std::min(t.s.K, 1024)), dim3(256), 0, c->stream, tv,
+                           (const float2 *)T, M);
         FL_LAUNCH_CHECK();
     }
     {
@@ -578,14 +591,14 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
 
 bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16; }
 
-void fmm_repulsion(fl_ctx *c, int32_t n, const float *x, const float *y, const int32_t *deg, int p, int leaf,
+void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
                    int bits, float kr, float *frx, float *fry)
 {
     TreeBufs t;
     ListBufs L;
     {
         PhaseTimer pt(c, FL_PH_TREE);
-        build_tree(c, t, n, x, y, deg, bits, leaf);
+        build_tree(c, t, s, x, y, deg, bits, leaf);
     }
     {
         PhaseTimer pt(c, FL_PH_LISTS);

@@ -3,12 +3,16 @@
 // Kamada-Kawai and those with many by ForceAtlas2 with FMM repulsion.
 //
 // Nodes are renumbered so that every component is a contiguous id range
-// (stable sort by component label, i.e. by smallest member id), the CSR is
-// permuted accordingly, the small components run through the batched
-// Kamada-Kawai kernels in one persistent launch, each large component runs
-// its own ForceAtlas2 iterations on a local CSR, and the positions are put
-// back in the caller's order.  Single nodes go to the origin.
+// (stable sort by component label, i.e. by smallest member id), and the
+// components are regrouped by method: the ForceAtlas2 components first, one
+// group per repulsion configuration (exact, or FMM with its p and leaf size),
+// then the Kamada-Kawai components, then single nodes (which go to the
+// origin).  The CSR is permuted accordingly.  The small components run
+// through the batched Kamada-Kawai kernels; every ForceAtlas2 group runs as
+// one batch, all its components in the same launches; positions go back in
+// the caller's order.
 #include <chrono>
+#include <map>
 
 #include "fl_fa2.h"
 #include "fl_tree.h"
@@ -76,20 +80,25 @@ __global__ void k_local_csr(const int32_t *__restrict__ nrow_ptr, const int32_t 
         lcol[e] = ncol[base + e] - cb;
 }
 
-// first CSR entry of each component (k in [0, ncomp]: the last is nnz)
-__global__ void k_comp_rp(const int32_t *__restrict__ off, int ncomp, const int32_t *__restrict__ nrow_ptr,
-                          int32_t *__restrict__ out)
+// New position of every node once the components are regrouped: the node
+// at label-sorted position r (component comp(r) = pos[r] + flag[r] - 1)
+// moves to newstart[comp] + (r - off[comp]).
+__global__ void k_regroup(const int32_t *__restrict__ perm, const int32_t *__restrict__ flag,
+                          const int32_t *__restrict__ pos, const int32_t *__restrict__ off,
+                          const int32_t *__restrict__ newstart, int n, int32_t *__restrict__ perm2)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k <= ncomp) out[k] = nrow_ptr[off[k]];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int k = pos[r] + flag[r] - 1;
+    perm2[newstart[k] + (r - off[k])] = perm[r];
 }
 
-__global__ void k_zero_pos(float *__restrict__ xs, float *__restrict__ ys, const int32_t *__restrict__ idx, int m)
+__global__ void k_zero_range(float *__restrict__ xs, float *__restrict__ ys, int b, int e)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    xs[idx[i]] = 0.f;
-    ys[idx[i]] = 0.f;
+    const int i = b + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= e) return;
+    xs[i] = 0.f;
+    ys[i] = 0.f;
 }
 
 __global__ void k_unpermute_pos(const int32_t *__restrict__ perm, int n, const float *__restrict__ xs,
@@ -135,72 +144,130 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
     hipLaunchKernelGGL(k_comp_flags, dim3(g), dim3(256), 0, c->stream, skey, n, flag);
     scan_excl_i32(c, flag, pos, n);
     hipLaunchKernelGGL(k_comp_offsets, dim3(g), dim3(256), 0, c->stream, flag, pos, n, d_off);
+    FL_LAUNCH_CHECK();
+    std::vector<int32_t> off(ncomp + 1);
+    FL_CHECK_HIP(hipMemcpyAsync(off.data(), d_off, sizeof(int32_t) * (ncomp + 1), hipMemcpyDeviceToHost, c->stream));
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+
+    // classify, then regroup: ForceAtlas2 groups (one per distinct resolved
+    // repulsion configuration) first, then the Kamada-Kawai components, then
+    // single nodes; label order within each class
+    struct Cfg {
+        int rep, p, leaf;
+        bool operator<(const Cfg &o) const
+        {
+            return rep != o.rep ? rep < o.rep : (p != o.p ? p < o.p : leaf < o.leaf);
+        }
+    };
+    std::map<Cfg, std::vector<int32_t>> groups;
+    std::map<Cfg, fl_fa2_params> group_prm;
+    std::vector<int32_t> kk_list, single_list;
+    int64_t kk_nodes = 0, fa2_nodes = 0;
+    int32_t n_fa2 = 0;
+    for (int k = 0; k < ncomp; ++k) {
+        const int sz = off[k + 1] - off[k];
+        if (sz == 1) {
+            single_list.push_back(k);
+        } else if (sz <= kk_max_nodes) {
+            kk_list.push_back(k);
+            kk_nodes += sz;
+        } else {
+            fl_fa2_params pr = resolve_repulsion(c->tuning, sz, *fa2);
+            if (fa2->repulsion == FL_REP_FMM && sz < fmm_min_nodes) pr.repulsion = FL_REP_EXACT;
+            const Cfg key = pr.repulsion == FL_REP_EXACT ? Cfg{FL_REP_EXACT, 0, 0}
+                                                          : Cfg{FL_REP_FMM, pr.p, pr.leaf_size};
+            groups[key].push_back(k);
+            group_prm[key] = pr;
+            fa2_nodes += sz;
+            ++n_fa2;
+        }
+    }
+    std::vector<int32_t> newstart(ncomp), neworder;
+    neworder.reserve(ncomp);
+    for (auto &kv : groups)
+        for (int32_t k : kv.second) neworder.push_back(k);
+    for (int32_t k : kk_list) neworder.push_back(k);
+    for (int32_t k : single_list) neworder.push_back(k);
+    std::vector<int32_t> newoff(ncomp + 1, 0);
+    for (int j = 0; j < ncomp; ++j) {
+        const int k = neworder[j];
+        newstart[k] = newoff[j];
+        newoff[j + 1] = newoff[j] + (off[k + 1] - off[k]);
+    }
+    int32_t *d_newstart = ws<int32_t>(c, "lay_newstart", (size_t)ncomp);
+    FL_CHECK_HIP(hipMemcpyAsync(d_newstart, newstart.data(), sizeof(int32_t) * ncomp, hipMemcpyHostToDevice,
+                                c->stream));
+    int32_t *perm2 = ws<int32_t>(c, "lay_perm2", n);
+    hipLaunchKernelGGL(k_regroup, dim3(g), dim3(256), 0, c->stream, perm, (const int32_t *)flag,
+                       (const int32_t *)pos, (const int32_t *)d_off, (const int32_t *)d_newstart, n, perm2);
+    FL_LAUNCH_CHECK();
+
     int32_t *inv = ws<int32_t>(c, "lay_inv", n), *ndeg = ws<int32_t>(c, "lay_ndeg", n);
     float *xs = ws<float>(c, "lay_xs", n), *ys = ws<float>(c, "lay_ys", n);
-    hipLaunchKernelGGL(k_permute_nodes, dim3(g), dim3(256), 0, c->stream, perm, n, deg, x, y, inv, ndeg, xs, ys);
+    hipLaunchKernelGGL(k_permute_nodes, dim3(g), dim3(256), 0, c->stream, (const int32_t *)perm2, n, deg, x, y, inv,
+                       ndeg, xs, ys);
     int32_t *nrow_ptr = ws<int32_t>(c, "lay_rp", (size_t)n + 1);
     scan_excl_i32(c, ndeg, nrow_ptr, n);
     const int32_t nnz = read_i32(c, row_ptr + n);
     int32_t *ncol = ws<int32_t>(c, "lay_col", nnz > 0 ? nnz : 1);
-    hipLaunchKernelGGL(k_permute_cols, dim3(g), dim3(256), 0, c->stream, perm, inv, n, row_ptr, col, nrow_ptr, ncol);
+    hipLaunchKernelGGL(k_permute_cols, dim3(g), dim3(256), 0, c->stream, (const int32_t *)perm2, inv, n, row_ptr,
+                       col, nrow_ptr, ncol);
     FL_LAUNCH_CHECK();
-    int32_t *d_crp = ws<int32_t>(c, "lay_crp", (size_t)ncomp + 1);
-    hipLaunchKernelGGL(k_comp_rp, dim3(grid_for((int64_t)ncomp + 1, 256)), dim3(256), 0, c->stream,
-                       (const int32_t *)d_off, ncomp, (const int32_t *)nrow_ptr, d_crp);
-    FL_LAUNCH_CHECK();
-    std::vector<int32_t> off(ncomp + 1), crp(ncomp + 1);
-    FL_CHECK_HIP(hipMemcpyAsync(off.data(), d_off, sizeof(int32_t) * (ncomp + 1), hipMemcpyDeviceToHost, c->stream));
-    FL_CHECK_HIP(hipMemcpyAsync(crp.data(), d_crp, sizeof(int32_t) * (ncomp + 1), hipMemcpyDeviceToHost, c->stream));
-    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
-
-    std::vector<int32_t> kk_ids, fa2_ids, single_nodes;
-    int64_t kk_nodes = 0, fa2_nodes = 0;
-    for (int k = 0; k < ncomp; ++k) {
-        const int sz = off[k + 1] - off[k];
-        if (sz == 1) single_nodes.push_back(off[k]);
-        else if (sz <= kk_max_nodes) {
-            kk_ids.push_back(k);
-            kk_nodes += sz;
-        } else {
-            fa2_ids.push_back(k);
-            fa2_nodes += sz;
-        }
-    }
     const double ms_setup = ms_since(t0);
+
     auto t1 = std::chrono::steady_clock::now();
-    if (!single_nodes.empty()) {
-        int32_t *d_single = ws<int32_t>(c, "lay_single", single_nodes.size());
-        FL_CHECK_HIP(hipMemcpyAsync(d_single, single_nodes.data(), sizeof(int32_t) * single_nodes.size(),
-                                    hipMemcpyHostToDevice, c->stream));
-        hipLaunchKernelGGL(k_zero_pos, dim3(grid_for((int64_t)single_nodes.size(), 256)), dim3(256), 0, c->stream, xs,
-                           ys, (const int32_t *)d_single, (int)single_nodes.size());
+    const int n_first_single = newoff[ncomp - (int)single_list.size()];  // single nodes come last
+    if (!single_list.empty()) {
+        hipLaunchKernelGGL(k_zero_range, dim3(grid_for(n - n_first_single, 256)), dim3(256), 0, c->stream, xs, ys,
+                           n_first_single, n);
         FL_LAUNCH_CHECK();
     }
-    kk_layout_subset(c, ncomp, off.data(), kk_ids, nrow_ptr, ncol, xs, ys, kk->l, kk->steps);
+    {
+        std::vector<int32_t> kk_ids;
+        const int first_kk = ncomp - (int)single_list.size() - (int)kk_list.size();
+        for (int j = 0; j < (int)kk_list.size(); ++j) kk_ids.push_back(first_kk + j);
+        kk_layout_subset(c, ncomp, newoff.data(), kk_ids, nrow_ptr, ncol, xs, ys, kk->l, kk->steps);
+    }
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));
     const double ms_kk = ms_since(t1);
+
     auto t2 = std::chrono::steady_clock::now();
     int32_t *flags = ws<int32_t>(c, "lay_flags", 1);
-    FL_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), c->stream));
-    if (!fa2_ids.empty()) {
-        // a local CSR per component, side by side: component j of the list
-        // keeps rows [cb + j, cb + j + nc] and its own column range
-        int32_t *lrp = ws<int32_t>(c, "lay_lrp", (size_t)n + fa2_ids.size() + 1);
+    fill_i32(c, flags, 1, 0);
+    if (!groups.empty()) {
+        // one local CSR per group (rows [gs, ge) of the regrouped CSR, ids
+        // shifted to the group), side by side: group j keeps rows
+        // [gs + j, ge + j] of lrp
+        int32_t *lrp = ws<int32_t>(c, "lay_lrp", (size_t)n + groups.size() + 1);
         int32_t *lcol = ws<int32_t>(c, "lay_lcol", nnz > 0 ? nnz : 1);
-        std::vector<FA2System> sys;
-        for (size_t j = 0; j < fa2_ids.size(); ++j) {
-            const int k = fa2_ids[j];
-            const int cb = off[k], nc = off[k + 1] - off[k];
-            int32_t *rp = lrp + cb + j, *cl = lcol + crp[k];
-            hipLaunchKernelGGL(k_local_csr, dim3(grid_for(nc + 1, 256, 1024)), dim3(256), 0, c->stream,
-                               (const int32_t *)nrow_ptr, (const int32_t *)ncol, cb, nc, rp, cl);
+        std::vector<FA2Batch> batches;
+        int j = 0, ci = 0;
+        for (auto &kv : groups) {
+            const int gs = newoff[ci], cnt = (int)kv.second.size();
+            const int ge = newoff[ci + cnt];
+            const int32_t e0 = read_i32(c, nrow_ptr + gs), e1 = read_i32(c, nrow_ptr + ge);
+            int32_t *rp = lrp + gs + j, *cl = lcol + e0;
+            hipLaunchKernelGGL(k_local_csr, dim3(grid_for((int64_t)(ge - gs) + 1, 256, 1024)), dim3(256), 0,
+                               c->stream, (const int32_t *)nrow_ptr, (const int32_t *)ncol, gs, ge - gs, rp, cl);
             FL_LAUNCH_CHECK();
-            sys.push_back(FA2System{nc, (int64_t)crp[k + 1] - crp[k], rp, cl, ndeg + cb, xs + cb, ys + cb});
+            FA2Batch b;
+            b.coff.resize(cnt + 1);
+            for (int q = 0; q <= cnt; ++q) b.coff[q] = newoff[ci + q] - gs;
+            b.nnz = (int64_t)e1 - e0;
+            b.row_ptr = rp;
+            b.col = cl;
+            b.deg = ndeg + gs;
+            b.x = xs + gs;
+            b.y = ys + gs;
+            b.prm = group_prm[kv.first];
+            batches.push_back(std::move(b));
+            ci += cnt;
+            ++j;
         }
-        fa2_run_many(c, sys, fa2, fa2_iters, fmm_min_nodes, flags);
+        fa2_run_batches(c, batches, fa2_iters, flags);
     }
-    hipLaunchKernelGGL(k_unpermute_pos, dim3(g), dim3(256), 0, c->stream, perm, n, (const float *)xs,
-                       (const float *)ys, x, y);
+    hipLaunchKernelGGL(k_unpermute_pos, dim3(g), dim3(256), 0, c->stream, (const int32_t *)perm2, n,
+                       (const float *)xs, (const float *)ys, x, y);
     FL_LAUNCH_CHECK();
     const int32_t f = read_i32(c, flags);
     const double ms_fa2 = ms_since(t2);
@@ -208,9 +275,9 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
     if (f & 2) throw Error(FL_ENONFINITE, "non-finite position in a ForceAtlas2 component");
     if (stats) {
         stats->n_comp = ncomp;
-        stats->n_single = (int32_t)single_nodes.size();
-        stats->n_kk = (int32_t)kk_ids.size();
-        stats->n_fa2 = (int32_t)fa2_ids.size();
+        stats->n_single = (int32_t)single_list.size();
+        stats->n_kk = (int32_t)kk_list.size();
+        stats->n_fa2 = n_fa2;
         stats->kk_nodes = kk_nodes;
         stats->fa2_nodes = fa2_nodes;
         stats->ms_setup = ms_setup;

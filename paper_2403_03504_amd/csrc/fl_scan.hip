@@ -259,4 +259,9 @@ bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits)
     return radix_sort<uint64_t, false>(c, k, nullptr, kt, nullptr, n, nbits, "u64");
 }
 
+bool radix_sort_u64v(fl_ctx *c, uint64_t *k, int32_t *v, uint64_t *kt, int32_t *vt, int64_t n, int nbits)
+{
+    return radix_sort<uint64_t, true>(c, k, v, kt, vt, n, nbits, "u64v");
+}
+
 }  // namespace fl

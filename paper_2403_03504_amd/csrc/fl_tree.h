@@ -3,6 +3,13 @@
 // capacities so no kernel can overflow and nothing is read back to the host
 // inside an iteration):
 //
+//   systems     K independent systems (components) handled together: system
+//               k owns nodes [coff[k], coff[k+1]); every system has its own
+//               root square and its own tree (a forest), and no list ever
+//               joins two systems.  Reductions run over tiles of SEG_TILE
+//               nodes that never straddle two systems, so a system's results
+//               do not depend on what else is in the batch.
+//
 //   part[n]     float4 (x, y, mass, original index as int bits), Morton order
 //   skey[n]     uint32 Morton keys, sorted
 //   cells       depth-first pre-order (sorted by (begin, level)); per cell:
@@ -10,7 +17,8 @@
 //               -1 = empty quadrant), leafidx (-1 for internal cells)
 //   leaves      leaf_cell[nleaves] in Morton order (a leaf's index = the
 //               index of its first particle among the "cell-start" particles)
-//   hash        (level, ix, iy) -> cell id, open addressing, epoch-tagged
+//   hash        (system, level, ix, iy) -> cell id, open addressing,
+//               epoch-tagged (cleared only when the epoch wraps)
 //   lists       V (M2L) and X (P2L) per cell; U (P2P) and W (M2P) per leaf;
 //               offsets are packed int64 pairs (lo = first list, hi = second);
 //               U is stored as the leaves' particle ranges, sorted and with
@@ -20,14 +28,37 @@
 //               expansion holds a_k / w^k, of an incoming one b_k * w^k)
 #pragma once
 
+#include <vector>
+
 #include "fl_common.h"
 
 namespace fl {
 
+constexpr int SEG_TILE = 2048;
+
+// K independent systems over n nodes (device arrays, see the layout notes).
+struct Segs {
+    int K = 1, n = 0;
+    const int32_t *coff = nullptr;      // [K+1] first node of each system
+    const int32_t *ncomp = nullptr;     // [n] system of each node; null when K == 1
+    const int2 *tiles = nullptr;        // [ntiles] (system, first node), SEG_TILE nodes at most
+    const int32_t *tile_off = nullptr;  // [K+1] first tile of each system
+    int ntiles = 0;
+    int cbits = 0;                      // bits of the system id in hash keys (0 when K == 1)
+};
+
+// One system of n nodes (device arrays cached per context).
+Segs segs_single(fl_ctx *c, int32_t n);
+// K systems with host offsets coff[0..K] (coff[0] = 0, strictly increasing);
+// uploads to workspace buffers named after `tag` and synchronises.
+Segs make_segs(fl_ctx *c, const std::vector<int32_t> &coff, const char *tag);
+
 struct TreeBufs {
     int n = 0, bits = 16, leaf = 64;
+    Segs s;
     int64_t cells_cap = 0, leaves_cap = 0, hash_cap = 0;
-    double *root = nullptr;      // [4] xmin, ymin, L, S
+    double *root = nullptr;      // [4 K] per system: xmin, ymin, L, S
+    int32_t *ccomp = nullptr;    // [cells_cap] system of each cell (null when K == 1)
     float4 *part = nullptr;      // [n]
     uint32_t *skey = nullptr;    // [n]
     int32_t *lvl = nullptr;      // [cells_cap]
@@ -35,7 +66,7 @@ struct TreeBufs {
     int32_t *beg = nullptr, *end = nullptr, *par = nullptr, *leafidx = nullptr;
     int4 *child = nullptr;
     int32_t *leaf_cell = nullptr;  // [leaves_cap]
-    uint32_t *start_key = nullptr;
+    uint64_t *start_key = nullptr;  // system << 32 | Morton key of each cell-start particle
     int32_t *start_pos = nullptr, *start_D = nullptr;
     int32_t *counts = nullptr;     // [0] cells, [1] leaves, [2] max level, [3] error bits
     uint64_t *hkey = nullptr;
@@ -56,7 +87,9 @@ struct ListBufs {
 
 // Device view used by the kernels.
 struct TreeView {
-    int n, bits, leaf;
+    int n, bits, leaf, K, cbits;
+    const int32_t *coff;
+    const int32_t *ccomp;
     const double *root;
     const float4 *part;
     const int32_t *lvl;
@@ -73,16 +106,19 @@ struct TreeView {
 
 inline TreeView view(const TreeBufs &t)
 {
-    return TreeView{t.n,   t.bits,      t.leaf,  t.root,   t.part,  t.lvl,  t.ixy,  t.beg,  t.end,
-                    t.par, t.leafidx,   t.child, t.leaf_cell, t.counts, t.hkey, t.hval, t.epoch, t.hash_cap};
+    return TreeView{t.n,        t.bits,     t.leaf,      t.s.K,    t.s.cbits, t.s.coff,  t.ccomp,
+                    t.root,     t.part,     t.lvl,       t.ixy,    t.beg,     t.end,     t.par,
+                    t.leafidx,  t.child,    t.leaf_cell, t.counts, t.hkey,    t.hval,    t.epoch,
+                    t.hash_cap};
 }
 
 // Capacities that no input can exceed (see the capacity notes in fl_tree.hip).
-int64_t cells_capacity(int64_t n, int leaf, int bits);
+int64_t cells_capacity(int64_t n, int leaf, int bits, int K = 1);
 
-// bbox -> Morton keys -> stable sort -> sorted particles -> tree.  mass may be
-// null (unit masses).  All on the context stream, no host synchronisation.
-void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *y, const int32_t *deg, int bits,
+// Per system: bbox -> Morton keys; then one stable sort by (system, key) ->
+// sorted particles -> forest.  deg may be null (unit masses).  All on the
+// context stream, no host synchronisation.
+void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
                 int leaf);
 void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L);
 // Deepest level of the last tree into the statistics block.
@@ -120,9 +156,16 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z;
 }
 
-__device__ __forceinline__ uint64_t hash_key(int level, int ix, int iy)
+__device__ __forceinline__ int cell_comp(const TreeView &t, int c) { return t.ccomp ? t.ccomp[c] : 0; }
+
+// key bits: iy [0,16) ix [16,32) level [32,37) system [37,37+cbits) epoch above
+constexpr int HASH_BASE_BITS = 37;
+constexpr int HASH_TAG_BITS = 27;  // system + epoch bits
+
+__device__ __forceinline__ uint64_t hash_key(int comp, int level, int ix, int iy)
 {
-    return ((uint64_t)level << 32) | ((uint64_t)(uint32_t)ix << 16) | (uint64_t)(uint32_t)iy;
+    return ((uint64_t)(uint32_t)comp << HASH_BASE_BITS) | ((uint64_t)level << 32) | ((uint64_t)(uint32_t)ix << 16) |
+           (uint64_t)(uint32_t)iy;
 }
 
 __device__ __forceinline__ int64_t hash_size(int ncells, int64_t cap)
@@ -132,26 +175,29 @@ __device__ __forceinline__ int64_t hash_size(int ncells, int64_t cap)
     return h < cap ? h : cap;
 }
 
-// cell id of region (level, ix, iy), or -1 if no cell of that exact region
-__device__ __forceinline__ int hash_find(const TreeView &t, int64_t H, uint64_t ep, int level, int ix, int iy)
+// cell id of region (comp, level, ix, iy), or -1 if no cell of that exact region
+__device__ __forceinline__ int hash_find(const TreeView &t, int64_t H, uint64_t ep, int comp, int level, int ix,
+                                         int iy)
 {
-    uint64_t k = hash_key(level, ix, iy) | (ep << 37);
-    int64_t h = (int64_t)(mix64(k & ((1ull << 37) - 1)) & (uint64_t)(H - 1));
+    const int sh = HASH_BASE_BITS + t.cbits;
+    uint64_t k = hash_key(comp, level, ix, iy) | (ep << sh);
+    int64_t h = (int64_t)(mix64(k & ((1ull << sh) - 1)) & (uint64_t)(H - 1));
     for (int64_t probe = 0; probe < H; ++probe) {
         uint64_t v = t.hkey[h];
-        if ((v >> 37) != ep) return -1;
+        if ((v >> sh) != ep) return -1;
         if (v == k) return t.hval[h];
         h = (h + 1) & (H - 1);
     }
     return -1;
 }
 
-// Deepest cell on the path to region (level, ix, iy): the region's own cell,
-// else the leaf that covers it; -1 when the region holds no particle.
-__device__ __forceinline__ int lookup_region(const TreeView &t, int64_t H, uint64_t ep, int level, int ix, int iy)
+// Deepest cell on the path to region (comp, level, ix, iy): the region's own
+// cell, else the leaf that covers it; -1 when the region holds no particle.
+__device__ __forceinline__ int lookup_region(const TreeView &t, int64_t H, uint64_t ep, int comp, int level, int ix,
+                                             int iy)
 {
     for (int l = level; l >= 0; --l, ix >>= 1, iy >>= 1) {
-        int id = hash_find(t, H, ep, l, ix, iy);
+        int id = hash_find(t, H, ep, comp, l, ix, iy);
         if (id < 0) continue;
         if (l == level) return id;
         return is_leaf4(t.child[id]) ? id : -1;

@@ -17,7 +17,8 @@
 //
 // Capacity notes (no kernel can write past them):
 //   cells  <= 1 + 4 B floor(n / (L+1))  (a split cell holds > L particles and
-//            split cells of one level are disjoint), and <= 1 + B n;
+//            split cells of one level are disjoint), and <= 1 + B n; a forest
+//            of K trees holds at most K + 4 B floor(n / (L+1)) and K + B n;
 //   V(c)   <= 27 (same-level cells in the parent's 6x6 block minus c's 3x3);
 //   X(c)   <= 8 (one covering leaf per ring square of the parent);
 //   sum |W| = sum |X| (W and X are dual) <= 8 cells;
@@ -26,10 +27,11 @@
 
 namespace fl {
 
-int64_t cells_capacity(int64_t n, int leaf, int bits)
+// A forest of K trees holds at most the sum of the per-tree bounds.
+int64_t cells_capacity(int64_t n, int leaf, int bits, int K)
 {
-    int64_t a = 1 + 4 * (int64_t)bits * (n / ((int64_t)leaf + 1));
-    int64_t b = 1 + (int64_t)bits * n;
+    int64_t a = (int64_t)K + 4 * (int64_t)bits * (n / ((int64_t)leaf + 1));
+    int64_t b = (int64_t)K + (int64_t)bits * n;
     int64_t c = a < b ? a : b;
     return c < 1 ? 1 : c;
 }
@@ -76,17 +78,24 @@ __device__ __forceinline__ int common_digits(uint32_t a, uint32_t b, int bits)
     return lz >> 1;
 }
 
-// ---- bbox + root square (last block finalises; deterministic) -------------
-constexpr int BB_BLOCKS = 256;
-
-__global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const float *__restrict__ y, int n,
-                                             float4 *__restrict__ partial, unsigned *__restrict__ ticket,
-                                             double *__restrict__ root, int bits, uint32_t *__restrict__ epoch)
+// ---- bbox + root square per system ------------------------------------------
+// One block per tile (tiles never straddle two systems).  The last tile of a
+// system to finish combines that system's tile extrema (min/max are exact, so
+// the order does not matter) into its root square; the last system to finish
+// advances the hash epoch.
+__global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const float *__restrict__ y, Segs sg,
+                                             float4 *__restrict__ partial, unsigned *__restrict__ cticket,
+                                             unsigned *__restrict__ gticket, double *__restrict__ root, int bits,
+                                             uint32_t *__restrict__ epoch)
 {
     __shared__ float4 red[NT / WAVE];
     __shared__ int is_last;
+    const int2 tl = sg.tiles[blockIdx.x];
+    const int comp = tl.x, b0 = tl.y;
+    const int cend = sg.coff[comp + 1];
+    const int b1 = min(b0 + SEG_TILE, cend);
     float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
-    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    for (int i = b0 + threadIdx.x; i < b1; i += NT) {
         float a = x[i], b = y[i];
         mnx = fminf(mnx, a);
         mxx = fmaxf(mxx, a);
@@ -99,6 +108,7 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
     mxy = wave_max_f(mxy);
     if (lane_id() == 0) red[threadIdx.x / WAVE] = make_float4(mnx, mxx, mny, mxy);
     __syncthreads();
+    const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
     if (threadIdx.x == 0) {
         float4 r = red[0];
         for (int w = 1; w < NT / WAVE; ++w) {
@@ -109,20 +119,26 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
         }
         partial[blockIdx.x] = r;
         __threadfence();
-        unsigned t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
+        unsigned t = atomicAdd(&cticket[comp], 1u);
+        is_last = (t == (unsigned)(nt - 1));
     }
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    {
-        float4 q = threadIdx.x < gridDim.x ? partial[threadIdx.x] : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-        q.x = wave_min_f(q.x);
-        q.y = wave_max_f(q.y);
-        q.z = wave_min_f(q.z);
-        q.w = wave_max_f(q.w);
-        if (lane_id() == 0) red[threadIdx.x / WAVE] = q;
+    float4 q = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    for (int j = threadIdx.x; j < nt; j += NT) {
+        const float4 v = partial[t0 + j];
+        q.x = fminf(q.x, v.x);
+        q.y = fmaxf(q.y, v.y);
+        q.z = fminf(q.z, v.z);
+        q.w = fmaxf(q.w, v.w);
     }
+    q.x = wave_min_f(q.x);
+    q.y = wave_max_f(q.y);
+    q.z = wave_min_f(q.z);
+    q.w = wave_max_f(q.w);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = q;
     __syncthreads();
     if (threadIdx.x == 0) {
         float4 r = red[0];
@@ -138,26 +154,45 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
         if (!isfinite(x0)) x0 = 0.0;
         if (!isfinite(y0)) y0 = 0.0;
         if (!isfinite(L)) L = 1.0;
-        root[0] = x0;
-        root[1] = y0;
-        root[2] = L;
-        root[3] = __ddiv_rn(ldexp(1.0, bits), L);
-        uint32_t e = *epoch + 1u;
-        if (e >= (1u << 27) || e == 0u) e = 1u;
-        *epoch = e;
-        *ticket = 0u;
+        double *rt = root + 4 * (int64_t)comp;
+        rt[0] = x0;
+        rt[1] = y0;
+        rt[2] = L;
+        rt[3] = __ddiv_rn(ldexp(1.0, bits), L);
+        cticket[comp] = 0u;
+        __threadfence();
+        const unsigned g = atomicAdd(gticket, 1u);
+        if (g == (unsigned)(sg.K - 1)) {
+            if (epoch) {
+                uint32_t e = *epoch + 1u;
+                if (e >= (1u << (HASH_TAG_BITS - sg.cbits)) || e == 0u) e = 1u;  // wrap: k_morton clears the table
+                *epoch = e;
+            }
+            *gticket = 0u;
+        }
     }
 }
 
+// Morton key of every node relative to its system's root square; with more
+// than one system also the sort key (system << 32 | key).  When the hash
+// epoch has just wrapped to 1 the table is cleared here (before any insert
+// of this build).
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, int n,
-                         const double *__restrict__ root, int bits, uint32_t *__restrict__ key,
-                         int32_t *__restrict__ idx)
+                         const int32_t *__restrict__ ncomp, const double *__restrict__ root, int bits,
+                         uint32_t *__restrict__ key, uint64_t *__restrict__ key64, int32_t *__restrict__ idx,
+                         const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hkey, int64_t hcap)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (hkey && epoch && *epoch == 1u)
+        for (int64_t h = i; h < hcap; h += (int64_t)gridDim.x * blockDim.x) hkey[h] = 0ull;
     if (i >= n) return;
-    double x0 = root[0], y0 = root[1], S = root[3];
+    const int comp = ncomp ? ncomp[i] : 0;
+    const double *rt = root + 4 * (int64_t)comp;
+    double x0 = rt[0], y0 = rt[1], S = rt[3];
     uint32_t qx = quantize(x[i], x0, S, bits), qy = quantize(y[i], y0, S, bits);
-    key[i] = part1by1(qx) | (part1by1(qy) << 1);
+    const uint32_t k = part1by1(qx) | (part1by1(qy) << 1);
+    if (key) key[i] = k;
+    if (key64) key64[i] = ((uint64_t)(uint32_t)comp << 32) | k;
     if (idx) idx[i] = i;
 }
 
@@ -172,12 +207,15 @@ __global__ void k_pack(const float *__restrict__ x, const float *__restrict__ y,
     xym[i] = make_float4(x[i], y[i], m, __int_as_float(i));
 }
 
+// sorted particles; with more than one system also the sorted Morton keys
+// (the low halves of the sorted (system, key) pairs)
 __global__ void k_gather(const float4 *__restrict__ xym, const int32_t *__restrict__ perm, int n,
-                         float4 *__restrict__ part)
+                         float4 *__restrict__ part, const uint64_t *__restrict__ skey64, uint32_t *__restrict__ skey)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     part[k] = xym[perm[k]];
+    if (skey64) skey[k] = (uint32_t)skey64[k];
 }
 
 // ---- tree: levels per particle ----------------------------------------------
@@ -186,8 +224,12 @@ constexpr int T1_MAXL = 1024;  // largest leaf size supported
 constexpr int T1_LEN = T1_TB + T1_MAXL;
 constexpr int T1_PER = T1_LEN / NT;
 
+// Sorted position k belongs to the system of node k (the sort keeps every
+// system's node range).  Two particles of different systems share no cell:
+// their common-prefix length is -1.
 __global__ __launch_bounds__(NT) void k_tree_levels(const uint32_t *__restrict__ K, int n, int bits, int L,
-                                                    int32_t *__restrict__ pack, int64_t *__restrict__ cnt2)
+                                                    const int32_t *__restrict__ ncomp, int32_t *__restrict__ pack,
+                                                    int64_t *__restrict__ cnt2)
 {
     __shared__ int A[T1_LEN];
     const int t0 = blockIdx.x * T1_TB;
@@ -195,7 +237,9 @@ __global__ __launch_bounds__(NT) void k_tree_levels(const uint32_t *__restrict__
     const int len = T1_TB + L;
     for (int i = threadIdx.x; i < len; i += NT) {
         int j = base + i;
-        A[i] = (j >= 0 && j + L < n) ? common_digits(K[j], K[j + L], bits) : -1;
+        int a = -1;
+        if (j >= 0 && j + L < n && (!ncomp || ncomp[j] == ncomp[j + L])) a = common_digits(K[j], K[j + L], bits);
+        A[i] = a;
     }
     const int w = L + 1;
     int s = 1;
@@ -226,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_tree_levels(const uint32_t *__restrict__
         if (k >= n) break;
         int mx = max(A[t], A[t + w - s]);
         int lam = min(bits, 1 + mx);
-        int D = (k == 0) ? -1 : common_digits(K[k - 1], K[k], bits);
+        int D = (k == 0 || (ncomp && ncomp[k - 1] != ncomp[k])) ? -1 : common_digits(K[k - 1], K[k], bits);
         int c = lam - D;
         if (c < 0) c = 0;
         pack[k] = (D + 1) | (lam << 8);
@@ -240,7 +284,8 @@ __device__ __forceinline__ uint32_t region_prefix(uint32_t key, int level, int b
 }
 
 __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, const int32_t *__restrict__ pack,
-                             const int64_t *__restrict__ off2, TreeBufs t)
+                             const int64_t *__restrict__ off2, const int32_t *__restrict__ ncomp, int cbits,
+                             TreeBufs t)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -261,8 +306,9 @@ __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, co
         return;
     }
     uint32_t key = K[k];
+    const int comp = ncomp ? ncomp[k] : 0;
     t.start_pos[li] = k;
-    t.start_key[li] = key;
+    t.start_key[li] = ((uint64_t)(uint32_t)comp << 32) | key;
     t.start_D[li] = D;
     t.leaf_cell[li] = cid0 + (lam - D - 1);
     if (k == 0) {
@@ -281,13 +327,15 @@ __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, co
         t.child[id] = make_int4(-1, -1, -1, -1);
         t.leafidx[id] = (l == lam) ? li : -1;
         t.par[id] = (l == 0) ? -1 : (l - 1 > D ? id - 1 : -2);
-        // insert (l, ix, iy) -> id
-        uint64_t hk = hash_key(l, ix, iy);
-        uint64_t kk = hk | (ep << 37);
+        if (t.ccomp) t.ccomp[id] = comp;
+        // insert (comp, l, ix, iy) -> id
+        const int sh = HASH_BASE_BITS + cbits;
+        uint64_t hk = hash_key(comp, l, ix, iy);
+        uint64_t kk = hk | (ep << sh);
         int64_t h = (int64_t)(mix64(hk) & (uint64_t)(H - 1));
         for (int64_t probe = 0; probe < H; ++probe) {
             uint64_t old = t.hkey[h];
-            if ((old >> 37) == ep) {
+            if ((old >> sh) == ep) {
                 h = (h + 1) & (H - 1);
                 continue;
             }
@@ -302,12 +350,12 @@ __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, co
     }
 }
 
-__device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int n, uint64_t v)
+__device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int n, uint64_t v)
 {
     int lo = 0, hi = n;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if ((uint64_t)a[mid] < v) lo = mid + 1;
+        if (a[mid] < v) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -321,20 +369,24 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
     if (id >= ncells) return;
     int nleaves = t.counts[1];
     int l = t.lvl[id];
+    const int comp = t.ccomp ? t.ccomp[id] : 0;
     if (l == 0) {
-        t.end[id] = n;
+        t.end[id] = t.s.K > 1 ? t.s.coff[comp + 1] : n;
         return;
     }
     int k = t.beg[id];
     uint32_t pre = region_prefix(K[k], l, bits);
     int sh = 2 * (bits - l);
-    uint64_t T = ((uint64_t)pre + 1ull) << sh;
-    int j = lower_bound_u32(t.start_key, nleaves, T);
+    // start keys carry the system above bit 32: the region's end is the first
+    // cell start past it in the same system, or the next system's first start
+    const uint64_t cs = (uint64_t)(uint32_t)comp << 32;
+    uint64_t T = cs + (((uint64_t)pre + 1ull) << sh);
+    int j = lower_bound_u64(t.start_key, nleaves, T);
     t.end[id] = j < nleaves ? t.start_pos[j] : n;
     int p = t.par[id];
     if (p == -2) {
-        uint64_t Tp = (uint64_t)(pre >> 2) << (sh + 2);
-        int jp = lower_bound_u32(t.start_key, nleaves, Tp);
+        uint64_t Tp = cs | ((uint64_t)(pre >> 2) << (sh + 2));
+        int jp = lower_bound_u64(t.start_key, nleaves, Tp);
         if (jp >= nleaves) {
             atomicOr(&t.counts[3], 2);
             return;
@@ -401,6 +453,7 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
     const int l = t.lvl[c];
     const uint32_t cxy = t.ixy[c];
     const int cx = cell_ix(cxy), cy = cell_iy(cxy);
+    const int comp = cell_comp(t, c);  // lists never leave the cell's system
     // V and X: the parent's ring (interacting cells)
     if (l >= 2) {
         const int pl = l - 1, px = cx >> 1, py = cy >> 1, pside = 1 << pl;
@@ -409,7 +462,7 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
                 if (!dx && !dy) continue;
                 int rx = px + dx, ry = py + dy;
                 if (rx < 0 || ry < 0 || rx >= pside || ry >= pside) continue;
-                int N = lookup_region(t, H, ep, pl, rx, ry);
+                int N = lookup_region(t, H, ep, comp, pl, rx, ry);
                 if (N < 0) continue;
                 int4 ch = t.child[N];
                 if (!is_leaf4(ch)) {
@@ -436,7 +489,7 @@ __device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c
                 if (!dx && !dy) continue;
                 int rx = cx + dx, ry = cy + dy;
                 if (rx < 0 || ry < 0 || rx >= side || ry >= side) continue;
-                int N = lookup_region(t, H, ep, l, rx, ry);
+                int N = lookup_region(t, H, ep, comp, l, rx, ry);
                 if (N < 0) continue;
                 int4 ch = t.child[N];
                 if (is_leaf4(ch)) {
@@ -566,30 +619,115 @@ __global__ void k_export_cells(TreeView t, int32_t *__restrict__ out, int cap)
     o[9] = ch.w;
 }
 
+__global__ void k_fill_ncomp(const int32_t *__restrict__ coff, int K, int n, int32_t *__restrict__ ncomp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = K;  // last system whose first node is <= i
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (coff[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    ncomp[i] = lo;
+}
+
 }  // namespace
 
-void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *y, const int32_t *deg, int bits,
-                int leaf)
+static Segs upload_segs(fl_ctx *c, const std::vector<int32_t> &coff, const std::string &tag)
 {
+    const int K = (int)coff.size() - 1;
+    FL_REQUIRE(K >= 1 && K <= (1 << 20), "between 1 and 2^20 systems per batch");
+    FL_REQUIRE(coff[0] == 0, "system offsets must start at 0");
+    std::vector<int2> tiles;
+    std::vector<int32_t> toff(K + 1);
+    for (int k = 0; k < K; ++k) {
+        FL_REQUIRE(coff[k + 1] > coff[k], "every system needs at least one node");
+        toff[k] = (int32_t)tiles.size();
+        for (int64_t b = coff[k]; b < coff[k + 1]; b += SEG_TILE) tiles.push_back(make_int2(k, (int)b));
+    }
+    toff[K] = (int32_t)tiles.size();
+    Segs sg;
+    sg.K = K;
+    sg.n = coff[K];
+    sg.ntiles = (int)tiles.size();
+    int cb = 0;
+    while ((1 << cb) < K) ++cb;
+    sg.cbits = cb;
+    int32_t *d_coff = ws<int32_t>(c, (tag + "_coff").c_str(), (size_t)K + 1);
+    int32_t *d_toff = ws<int32_t>(c, (tag + "_toff").c_str(), (size_t)K + 1);
+    int2 *d_tiles = ws<int2>(c, (tag + "_tiles").c_str(), tiles.size());
+    FL_CHECK_HIP(hipMemcpyAsync(d_coff, coff.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice, c->stream));
+    FL_CHECK_HIP(hipMemcpyAsync(d_toff, toff.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice, c->stream));
+    FL_CHECK_HIP(
+        hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, c->stream));
+    sg.coff = d_coff;
+    sg.tile_off = d_toff;
+    sg.tiles = d_tiles;
+    if (K > 1) {
+        int32_t *nc = ws<int32_t>(c, (tag + "_ncomp").c_str(), (size_t)sg.n);
+        hipLaunchKernelGGL(k_fill_ncomp, dim3(grid_for(sg.n, NT)), dim3(NT), 0, c->stream, (const int32_t *)d_coff, K,
+                           sg.n, nc);
+        FL_LAUNCH_CHECK();
+        sg.ncomp = nc;
+    }
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));  // the host vectors go out of scope
+    return sg;
+}
+
+Segs segs_single(fl_ctx *c, int32_t n)
+{
+    FL_REQUIRE(n >= 1, "need n >= 1");
+    if (c->seg1_n != n) {
+        c->seg1_n = -1;
+        upload_segs(c, std::vector<int32_t>{0, n}, "seg1");
+        c->seg1_n = n;
+    }
+    Segs sg;
+    sg.K = 1;
+    sg.n = n;
+    sg.ntiles = (n + SEG_TILE - 1) / SEG_TILE;
+    sg.coff = ws<int32_t>(c, "seg1_coff", 2);
+    sg.tile_off = ws<int32_t>(c, "seg1_toff", 2);
+    sg.tiles = ws<int2>(c, "seg1_tiles", (size_t)sg.ntiles);
+    return sg;
+}
+
+Segs make_segs(fl_ctx *c, const std::vector<int32_t> &coff, const char *tag) { return upload_segs(c, coff, tag); }
+
+namespace {
+
+void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg,
+                     int bits, int leaf)
+{
+    const int n = s.n;
     t.n = n;
+    t.s = s;
     t.bits = bits;
     t.leaf = leaf;
-    t.cells_cap = cells_capacity(n, leaf, bits);
+    t.cells_cap = cells_capacity(n, leaf, bits, s.K);
     t.leaves_cap = t.cells_cap < n ? t.cells_cap : n;
     int64_t hc = 64;
     while (hc < 2 * t.cells_cap) hc <<= 1;
     t.hash_cap = hc;
     const int64_t cap = t.cells_cap, lcap = t.leaves_cap;
 
-    t.root = ws<double>(c, "t_root", 4);
-    float4 *bpart = ws<float4>(c, "t_bbox_part", BB_BLOCKS);
-    unsigned *ticket = ws_zeroed<unsigned>(c, "t_ticket", 4);
+    t.root = ws<double>(c, "t_root", 4 * (size_t)s.K);
+    float4 *bpart = ws<float4>(c, "t_bbox_part", (size_t)s.ntiles);
+    unsigned *cticket = ws_zeroed<unsigned>(c, "t_cticket", (size_t)s.K);
+    unsigned *gticket = ws_zeroed<unsigned>(c, "t_gticket", 4);
     t.epoch = ws_zeroed<uint32_t>(c, "t_epoch", 4);
     uint32_t *k0 = ws<uint32_t>(c, "t_key0", n);
     uint32_t *k1 = ws<uint32_t>(c, "t_key1", n);
     int32_t *i0 = ws<int32_t>(c, "t_idx0", n);
     int32_t *i1 = ws<int32_t>(c, "t_idx1", n);
+    uint64_t *q0 = nullptr, *q1 = nullptr;
+    if (s.K > 1) {
+        q0 = ws<uint64_t>(c, "t_qkey0", n);
+        q1 = ws<uint64_t>(c, "t_qkey1", n);
+    }
     t.part = ws<float4>(c, "t_part", n);
+    t.ccomp = s.K > 1 ? ws<int32_t>(c, "t_ccomp", cap) : nullptr;
     t.lvl = ws<int32_t>(c, "t_lvl", cap);
     t.ixy = ws<uint32_t>(c, "t_ixy", cap);
     t.beg = ws<int32_t>(c, "t_beg", cap);
@@ -598,7 +736,7 @@ void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *
     t.leafidx = ws<int32_t>(c, "t_leafidx", cap);
     t.child = ws<int4>(c, "t_child", cap);
     t.leaf_cell = ws<int32_t>(c, "t_leafcell", lcap);
-    t.start_key = ws<uint32_t>(c, "t_skey_start", lcap);
+    t.start_key = ws<uint64_t>(c, "t_skey_start", lcap);
     t.start_pos = ws<int32_t>(c, "t_spos", lcap);
     t.start_D = ws<int32_t>(c, "t_sD", lcap);
     t.counts = ws_zeroed<int32_t>(c, "t_counts", 4);
@@ -607,26 +745,55 @@ void build_tree(fl_ctx *c, TreeBufs &t, int32_t n, const float *x, const float *
     t.pack = ws<int32_t>(c, "t_pack", n);
     int64_t *cnt2 = ws<int64_t>(c, "t_cnt2", n);
     t.off2 = ws<int64_t>(c, "t_off2", (size_t)n + 1);
+    if (c->tree_cbits != s.cbits) {
+        // the key layout changes: restart the epoch, so that this build
+        // clears the table before inserting
+        fill_i32(c, (int32_t *)t.epoch, 1, 0);
+        c->tree_cbits = s.cbits;
+    }
 
-    int nb = (int)grid_for(n, NT, BB_BLOCKS);
-    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(NT), 0, c->stream, x, y, n, bpart, ticket, t.root, bits, t.epoch);
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, t.root, bits, k0, i0);
+    hipLaunchKernelGGL(k_bbox, dim3(s.ntiles), dim3(NT), 0, c->stream, x, y, s, bpart, cticket, gticket, t.root, bits,
+                       t.epoch);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
+                       (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
+                       t.hkey, t.hash_cap);
     FL_LAUNCH_CHECK();
-    bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits);
-    uint32_t *sk = alt ? k1 : k0;
-    int32_t *perm = alt ? i1 : i0;
+    uint32_t *sk;
+    int32_t *perm;
+    const uint64_t *sq = nullptr;
+    if (s.K > 1) {
+        const bool alt = radix_sort_u64v(c, q0, i0, q1, i1, n, 32 + s.cbits);
+        sq = alt ? q1 : q0;
+        perm = alt ? i1 : i0;
+        sk = k0;  // written by k_gather
+    } else {
+        const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits);
+        sk = alt ? k1 : k0;
+        perm = alt ? i1 : i0;
+    }
     t.skey = sk;
     float4 *xym = ws<float4>(c, "t_xym", n);
     hipLaunchKernelGGL(k_pack, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, deg, n, xym);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float4 *)xym, perm, n, t.part);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float4 *)xym, perm, n, t.part,
+                       sq, sk);
     fill_i32(c, t.counts, 3, 0);  // [3] (error bits) is sticky; a kernel, not a memset, so graphs replay it
-    hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, sk, n, bits, leaf, t.pack,
-                       cnt2);
+    hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
+                       leaf, s.ncomp, t.pack, cnt2);
     FL_LAUNCH_CHECK();
     scan_excl_i64(c, cnt2, t.off2, n);
-    hipLaunchKernelGGL(k_tree_cells, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, sk, n, bits, t.pack, t.off2, t);
-    hipLaunchKernelGGL(k_tree_links, dim3(grid_for(cap, NT)), dim3(NT), 0, c->stream, sk, n, bits, t.off2, t);
+    hipLaunchKernelGGL(k_tree_cells, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
+                       (const int32_t *)t.pack, (const int64_t *)t.off2, s.ncomp, s.cbits, t);
+    hipLaunchKernelGGL(k_tree_links, dim3(grid_for(cap, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
+                       (const int64_t *)t.off2, t);
     FL_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
+                int leaf)
+{
+    build_tree_impl(c, t, s, x, y, deg, bits, leaf);
 }
 
 void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
@@ -692,14 +859,17 @@ int32_t tree_error_bits(fl_ctx *c, bool clear)
 
 void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits, uint32_t *key, double *root_out)
 {
+    const Segs sg = segs_single(c, n);
     double *root = root_out ? root_out : ws<double>(c, "t_root", 4);
-    float4 *bpart = ws<float4>(c, "t_bbox_part", BB_BLOCKS);
-    unsigned *ticket = ws_zeroed<unsigned>(c, "t_ticket", 4);
-    uint32_t *epoch = ws_zeroed<uint32_t>(c, "t_epoch", 4);
-    int nb = (int)grid_for(n, NT, BB_BLOCKS);
-    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(NT), 0, c->stream, x, y, n, bpart, ticket, root, bits, epoch);
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, root, bits, key,
-                       (int32_t *)nullptr);
+    float4 *bpart = ws<float4>(c, "t_bbox_part", (size_t)sg.ntiles);
+    unsigned *cticket = ws_zeroed<unsigned>(c, "t_cticket", 1);
+    unsigned *gticket = ws_zeroed<unsigned>(c, "t_gticket", 4);
+    // no tree is built: leave the hash epoch alone
+    hipLaunchKernelGGL(k_bbox, dim3(sg.ntiles), dim3(NT), 0, c->stream, x, y, sg, bpart, cticket, gticket, root, bits,
+                       (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, (const int32_t *)nullptr,
+                       (const double *)root, bits, key, (uint64_t *)nullptr, (int32_t *)nullptr,
+                       (const uint32_t *)nullptr, (uint64_t *)nullptr, (int64_t)0);
     FL_LAUNCH_CHECK();
 }
 
@@ -750,7 +920,7 @@ fl_status fl_tree(fl_ctx *c, int32_t n, const float *x, const float *y, int32_t 
     FL_REQUIRE(bits >= 1 && bits <= 16, "fl_tree: bits must be in [1, 16]");
     FL_REQUIRE(leaf_size >= 1 && leaf_size <= 1024, "fl_tree: leaf_size must be in [1, 1024]");
     TreeBufs t;
-    build_tree(c, t, n, x, y, nullptr, bits, leaf_size);
+    build_tree(c, t, segs_single(c, n), x, y, nullptr, bits, leaf_size);
     TreeView tv = view(t);
     hipLaunchKernelGGL(k_export_cells, dim3(grid_for(t.cells_cap, 256)), dim3(256), 0, c->stream, tv, cells, cap);
     FL_LAUNCH_CHECK();

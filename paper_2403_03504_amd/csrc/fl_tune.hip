@@ -139,14 +139,15 @@ static void autotune(fl_ctx *c, int32_t n, const float *x, const float *y, const
     t.max_rel_err = max_rel_err;
     for (int k = 0; k < n_sizes; ++k) {
         const int s = sizes[k];
-        t_exact[k] = time_median(c, reps, [&] { exact_repulsion(c, s, x, y, deg, 1.f, ex, ey); });
+        const Segs sg = segs_single(c, s);
+        t_exact[k] = time_median(c, reps, [&] { exact_repulsion(c, sg, x, y, deg, 1.f, ex, ey); });
         samples.push_back(fl_tune_sample{s, 0, 0, 1, t_exact[k], 0.0});
         double best = INFINITY, best_err = INFINITY, closest = INFINITY;
         int bp = 8, bl = 64, cp = 16, cl = 16;
         for (int p : TUNE_P) {
             for (int leaf : TUNE_LEAF) {
                 const double ms =
-                    time_median(c, reps, [&] { fmm_repulsion(c, s, x, y, deg, p, leaf, bits, 1.f, fx, fy); });
+                    time_median(c, reps, [&] { fmm_repulsion(c, sg, x, y, deg, p, leaf, bits, 1.f, fx, fy); });
                 if (tree_error_bits(c, true)) throw Error(FL_EHIP, "FMM capacity guard tripped while tuning");
                 const double e = rel_err(c, s, fx, fy, ex, ey);
                 const int ok = e <= max_rel_err ? 1 : 0;

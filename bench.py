@@ -230,11 +230,13 @@ def tuned_run(args, G, g, fl, np, torch) -> dict:
     wall = time.perf_counter() - t0
     ctx.close()
     k = len(sizes) - 1
-    pick = [q for q in samples if q["size"] == g.n and q["p"] == table["p"][k] and q["leaf_size"] == table["leaf_size"][k]]
+    pick = [q for q in samples if q["size"] == g.n and q["p"] == table["p"][k]
+            and q["leaf_size"] == table["leaf_size"][k] and q["list_lanes"] == table["list_lanes"][k]]
     out = {"max_rel_err": args.tune_err, "sizes": sizes, "table": table, "tune_s": tune_s,
            "measurements": len(samples), "ms_per_step": wall * 1e3 / args.steps,
            "node_updates_per_s": g.n * args.steps / wall,
            "full_size_choice": {"p": table["p"][k], "leaf_size": table["leaf_size"][k],
+                                "list_lanes": table["list_lanes"][k],
                                 "rel_err_vs_gpu_exact": pick[0]["rel_err"] if pick else None}}
     log(f"tuned run: {out['ms_per_step']:.3f} ms/iter, {out['node_updates_per_s']:.4g} node-updates/s")
     return out
@@ -250,6 +252,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--list-lanes", type=int, default=0, help="lanes per cell of the list kernels (0: by size)")
     ap.add_argument("--phase-steps", type=int, default=50,
                     help="iterations of the eager pass that times every phase with HIP events")
     ap.add_argument("--direct-steps", type=int, default=1, help="exact-direct comparator iterations (0: skip)")
@@ -305,7 +308,7 @@ def main() -> int:
     nnz = int(G.row_ptr[-1].item())
     log(f"CSR built on GPU: nnz {nnz} in {setup_s * 1e3:.1f} ms")
 
-    prm = fl.default_params(repulsion=fl.REP_FMM, p=args.p, leaf_size=args.leaf)
+    prm = fl.default_params(repulsion=fl.REP_FMM, p=args.p, leaf_size=args.leaf, list_lanes=args.list_lanes)
     x = torch.from_numpy(g.x).to(dev)
     y = torch.from_numpy(g.y).to(dev)
     st = fl.FA2State.zeros(g.n, dev)

@@ -154,10 +154,13 @@ typedef struct {
     int32_t p;             /* FMM expansion order: 4, 6, 8, 10, 12, 16 */
     int32_t leaf_size;     /* FMM: a cell holding more points is divided (1..1024) */
     int32_t morton_bits;   /* FMM: quadtree depth cap, 1..16 */
+    int32_t list_lanes;    /* FMM: lanes per cell that build the interaction lists, 1 or 8 (0: chosen
+                              by size); a launch shape only, the results are the same */
 } fl_fa2_params;
 
 /* Defaults: kr = kg = ka = 1, STRONG_MASS, SWING_PAPER, tau = 1, ks = 0.1,
- * ksmax = 10, max_rise = 0.5, FMM, p = 8, leaf_size = 64, morton_bits = 16. */
+ * ksmax = 10, max_rise = 0.5, FMM, p = 8, leaf_size = 64, morton_bits = 16,
+ * list_lanes = 0. */
 void fl_fa2_default_params(fl_fa2_params *prm);
 
 /* Caller-owned iteration state. fx_prev/fy_prev [n]: forces of the previous
@@ -286,11 +289,12 @@ typedef struct {
                                                 bucket also takes every larger size) */
     int32_t p[FL_TUNE_MAX_BUCKETS];          /* expansion order per bucket (4, 6, 8, 10, 12, 16) */
     int32_t leaf_size[FL_TUNE_MAX_BUCKETS];  /* leaf size per bucket (1..1024) */
+    int32_t list_lanes[FL_TUNE_MAX_BUCKETS]; /* lanes per cell of the list kernels (1 or 8; 0: by size) */
     double max_rel_err;     /* error bound the table was tuned for (0: not tuned) */
 } fl_tuning;
 
 /* The table a new context starts with: fmm_min_nodes 4096, one bucket with
- * p = 8, leaf_size = 64, max_rel_err 0. */
+ * p = 8, leaf_size = 64, list_lanes = 0, max_rel_err 0. */
 void fl_default_tuning(fl_tuning *out);
 /* Copy a table into the context (NULL: the default); FL_EINVAL if malformed. */
 fl_status fl_set_tuning(fl_ctx *ctx, const fl_tuning *tuning);
@@ -298,7 +302,7 @@ fl_status fl_get_tuning(fl_ctx *ctx, fl_tuning *out);
 
 /* One measurement of fl_autotune: p = 0 is the exact repulsion. */
 typedef struct {
-    int32_t size, p, leaf_size, feasible;
+    int32_t size, p, leaf_size, list_lanes, feasible;
     double ms;       /* median over the repetitions (tree, lists and passes for FMM) */
     double rel_err;  /* |F - F_exact|_2 / |F_exact|_2 over all nodes of the prefix */
 } fl_tune_sample;
@@ -308,8 +312,8 @@ typedef struct {
  * in [2, n]], the first s points of x, y, deg [device, n] (pass them in
  * random order, so that a prefix is a uniform subsample; deg gives the
  * masses) are evaluated by the exact repulsion and by the FMM for every
- * p in {4, 6, 8, 10, 12, 16} and leaf_size in {16, 24, 32, 48, 64, 96, 128},
- * `reps` timed repetitions each (HIP events on the context's stream).  At
+ * p in {4, 6, 8, 10, 12, 16}, leaf_size in {16, 24, 32, 48, 64, 96, 128}
+ * and list_lanes in {1, 8}, `reps` timed repetitions each (HIP events on the context's stream).  At
  * each size the fastest FMM configuration whose error against the exact
  * forces is <= max_rel_err is chosen (the most accurate one if none is);
  * the crossover is the geometric mean of the largest size at which exact

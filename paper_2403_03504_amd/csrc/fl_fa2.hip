@@ -347,6 +347,7 @@ static void validate_params(const fl_fa2_params *p)
     if (p->repulsion == FL_REP_FMM) {
         FL_REQUIRE(p->leaf_size >= 1 && p->leaf_size <= 1024, "leaf_size must be in [1, 1024]");
         FL_REQUIRE(p->morton_bits >= 1 && p->morton_bits <= 16, "morton_bits must be in [1, 16]");
+        FL_REQUIRE(p->list_lanes == 0 || p->list_lanes == 1 || p->list_lanes == 8, "list_lanes must be 0, 1 or 8");
         if (!fmm_order_supported(p->p))
             throw Error(p->p >= 1 && p->p <= 20 ? FL_EUNSUPPORTED : FL_EINVAL,
                         "FMM expansion order must be one of 4, 6, 8, 10, 12, 16");
@@ -424,7 +425,8 @@ static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float
                            (float)p->kr, frx, fry);
         FL_LAUNCH_CHECK();
     } else {
-        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, (float)p->kr, frx, fry);
+        const int lanes = p->list_lanes ? p->list_lanes : default_list_lanes(sg.n);
+        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, frx, fry);
     }
 }
 
@@ -646,6 +648,7 @@ void fl_fa2_default_params(fl_fa2_params *p)
     p->p = 8;
     p->leaf_size = 64;
     p->morton_bits = 16;
+    p->list_lanes = 0;
 }
 
 fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,

@@ -592,7 +592,7 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
 bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16; }
 
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, float kr, float *frx, float *fry)
+                   int bits, int lanes, float kr, float *frx, float *fry)
 {
     TreeBufs t;
     ListBufs L;
@@ -602,7 +602,7 @@ void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, con
     }
     {
         PhaseTimer pt(c, FL_PH_LISTS);
-        build_lists(c, t, L);
+        build_lists(c, t, L, lanes);
     }
     switch (p) {
     case 4: run_fmm_p<4>(c, t, L, kr, frx, fry); break;

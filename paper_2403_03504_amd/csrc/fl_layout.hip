@@ -174,6 +174,7 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
         } else {
             fl_fa2_params pr = resolve_repulsion(c->tuning, sz, *fa2);
             if (fa2->repulsion == FL_REP_FMM && sz < fmm_min_nodes) pr.repulsion = FL_REP_EXACT;
+            pr.list_lanes = fa2->list_lanes;  // a batch's launch shape follows the batch's size
             const Cfg key = pr.repulsion == FL_REP_EXACT ? Cfg{FL_REP_EXACT, 0, 0}
                                                           : Cfg{FL_REP_FMM, pr.p, pr.leaf_size};
             groups[key].push_back(k);

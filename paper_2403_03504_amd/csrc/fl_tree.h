@@ -120,7 +120,10 @@ int64_t cells_capacity(int64_t n, int leaf, int bits, int K = 1);
 // context stream, no host synchronisation.
 void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
                 int leaf);
-void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L);
+// lanes: lanes per cell of the list kernels, 1 or 8 (the same lists either way)
+void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes);
+// lanes per cell when the caller leaves the choice open (0)
+int default_list_lanes(int64_t n);
 // Deepest level of the last tree into the statistics block.
 void tree_max_level(fl_ctx *c);
 // Sticky capacity-guard bits of the tree/list kernels (synchronises).

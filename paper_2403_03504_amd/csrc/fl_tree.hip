@@ -447,114 +447,201 @@ __device__ __forceinline__ bool ring_seen_before(const TreeView &t, int N, int l
     return false;
 }
 
+// The lists of cell c are enumerated by LANES lanes (1 or 8): lane q takes
+// squares q, q + LANES, ... of the 3x3 ring (numbered dy-major from (-1, -1)
+// without the centre), the V and X entries coming from that square of the
+// parent's ring and the U and W entries from that square of c's own ring
+// (leaves only).  Concatenating the lanes' entries in lane order gives each
+// list in the order of one scan of the ring, whatever LANES is, so the lists
+// (and every result) do not depend on the launch shape.  One lane per cell
+// suits large trees (many cells, throughput-bound); eight suit small ones
+// (few cells, bound by the chains of dependent hash lookups).
+__device__ __forceinline__ void ring_square(int q, int &dx, int &dy)
+{
+    const int r = q < 4 ? q : q + 1;  // skip the centre (index 4 of the 3x3 block)
+    dx = r % 3 - 1;
+    dy = r / 3 - 1;
+}
+
 template <class Sink>
-__device__ void enumerate_lists(const TreeView &t, int64_t H, uint64_t ep, int c, Sink &sk)
+__device__ void vx_square(const TreeView &t, int64_t H, uint64_t ep, int c, int comp, int l, uint32_t cxy, int q,
+                          Sink &sk)
+{
+    if (l < 2) return;
+    int dx, dy;
+    ring_square(q, dx, dy);
+    const int pl = l - 1, px = cell_ix(cxy) >> 1, py = cell_iy(cxy) >> 1, pside = 1 << pl;
+    const int rx = px + dx, ry = py + dy;
+    if (rx < 0 || ry < 0 || rx >= pside || ry >= pside) return;
+    const int N = lookup_region(t, H, ep, comp, pl, rx, ry);
+    if (N < 0) return;
+    const int4 ch = t.child[N];
+    if (!is_leaf4(ch)) {
+        // N is the same-level neighbour of the parent, subdivided
+        const int cc[4] = {ch.x, ch.y, ch.z, ch.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int s = cc[k];
+            if (s >= 0 && !cells_adjacent(l, t.ixy[s], l, cxy)) sk.V(s);
+        }
+    } else if (!ring_seen_before(t, N, pl, px, py, pside, dx, dy) && !cells_adjacent(t.lvl[N], t.ixy[N], l, cxy)) {
+        sk.X(N);
+    }
+}
+
+template <class Sink>
+__device__ void uw_square(const TreeView &t, int64_t H, uint64_t ep, int comp, int l, uint32_t cxy, int q, Sink &sk)
+{
+    int dx, dy;
+    ring_square(q, dx, dy);
+    const int cx = cell_ix(cxy), cy = cell_iy(cxy), side = 1 << l;
+    const int rx = cx + dx, ry = cy + dy;
+    if (rx < 0 || ry < 0 || rx >= side || ry >= side) return;
+    const int N = lookup_region(t, H, ep, comp, l, rx, ry);
+    if (N < 0) return;
+    if (is_leaf4(t.child[N])) {
+        if (!ring_seen_before(t, N, l, cx, cy, side, dx, dy)) sk.U(N);
+        return;
+    }
+    int stack[64];
+    int sp = 0;
+    stack[sp++] = N;
+    while (sp > 0) {
+        const int d = stack[--sp];
+        const int4 dc = t.child[d];
+        const int cc[4] = {dc.x, dc.y, dc.z, dc.w};
+        for (int k = 0; k < 4; ++k) {
+            const int s = cc[k];
+            if (s < 0) continue;
+            if (cells_adjacent(t.lvl[s], t.ixy[s], l, cxy)) {
+                if (is_leaf4(t.child[s])) sk.U(s);
+                else if (sp < 64) stack[sp++] = s;
+            } else {
+                sk.W(s);
+            }
+        }
+    }
+}
+
+template <int LANES, class Sink>
+__device__ void enumerate_part(const TreeView &t, int64_t H, uint64_t ep, int c, int q, Sink &sk)
 {
     const int l = t.lvl[c];
     const uint32_t cxy = t.ixy[c];
-    const int cx = cell_ix(cxy), cy = cell_iy(cxy);
     const int comp = cell_comp(t, c);  // lists never leave the cell's system
-    // V and X: the parent's ring (interacting cells)
-    if (l >= 2) {
-        const int pl = l - 1, px = cx >> 1, py = cy >> 1, pside = 1 << pl;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy) continue;
-                int rx = px + dx, ry = py + dy;
-                if (rx < 0 || ry < 0 || rx >= pside || ry >= pside) continue;
-                int N = lookup_region(t, H, ep, comp, pl, rx, ry);
-                if (N < 0) continue;
-                int4 ch = t.child[N];
-                if (!is_leaf4(ch)) {
-                    // N is the same-level neighbour of the parent, subdivided
-                    int cc[4] = {ch.x, ch.y, ch.z, ch.w};
+    for (int s = q; s < 8; s += LANES) vx_square(t, H, ep, c, comp, l, cxy, s, sk);
+    if (!is_leaf4(t.child[c])) return;
+    for (int s = q; s < 8; s += LANES) uw_square(t, H, ep, comp, l, cxy, s, sk);
+}
+
+template <int LANES>
+__device__ __forceinline__ int group_sum(int v)
+{
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        int s = cc[q];
-                        if (s >= 0 && !cells_adjacent(l, t.ixy[s], l, cxy)) sk.V(s);
-                    }
-                } else if (!ring_seen_before(t, N, pl, px, py, pside, dx, dy) &&
-                           !cells_adjacent(t.lvl[N], t.ixy[N], l, cxy)) {
-                    sk.X(N);
-                }
-            }
-    }
-    // U and W for leaves: neighbours and the far parts of subdivided ones
-    if (is_leaf4(t.child[c])) {
-        sk.U(c);
-        const int side = 1 << l;
-        int stack[64];
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy) continue;
-                int rx = cx + dx, ry = cy + dy;
-                if (rx < 0 || ry < 0 || rx >= side || ry >= side) continue;
-                int N = lookup_region(t, H, ep, comp, l, rx, ry);
-                if (N < 0) continue;
-                int4 ch = t.child[N];
-                if (is_leaf4(ch)) {
-                    if (!ring_seen_before(t, N, l, cx, cy, side, dx, dy)) sk.U(N);
-                    continue;
-                }
-                int sp = 0;
-                stack[sp++] = N;
-                while (sp > 0) {
-                    int d = stack[--sp];
-                    int4 dc = t.child[d];
-                    int cc[4] = {dc.x, dc.y, dc.z, dc.w};
-                    for (int q = 0; q < 4; ++q) {
-                        int s = cc[q];
-                        if (s < 0) continue;
-                        if (cells_adjacent(t.lvl[s], t.ixy[s], l, cxy)) {
-                            if (is_leaf4(t.child[s])) sk.U(s);
-                            else if (sp < 64) stack[sp++] = s;
-                        } else {
-                            sk.W(s);
-                        }
-                    }
-                }
-            }
-    }
+    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
+    return v;
 }
 
-__global__ void k_lists_count(TreeView t, int64_t *__restrict__ cntVX, int64_t *__restrict__ cntUW)
+template <int LANES>
+__device__ __forceinline__ int group_excl(int v)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= t.counts[0]) return;
-    const int64_t H = hash_size(t.counts[0], t.hash_cap);
+    const int q = lane_id() & (LANES - 1);
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+        const int u = __shfl_up(inc, o, LANES);
+        if (q >= o) inc += u;
+    }
+    return inc - v;
+}
+
+// Grid-stride over cells, one LANES-lane group per cell; the trip count is
+// uniform over the wave (the shuffles need all lanes of a group).
+template <int LANES>
+__global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__restrict__ cntVX,
+                                                     int64_t *__restrict__ cntUW)
+{
+    const int ncells = t.counts[0];
+    const int64_t H = hash_size(ncells, t.hash_cap);
     const uint64_t ep = *t.epoch;
-    CountSink sk;
-    enumerate_lists(t, H, ep, c, sk);
-    cntVX[c] = (int64_t)sk.nV | ((int64_t)sk.nX << 32);
-    int li = t.leafidx[c];
-    if (li >= 0) cntUW[li] = (int64_t)sk.nU | ((int64_t)sk.nW << 32);
+    const int q = lane_id() & (LANES - 1);
+    const int gpw = WAVE / LANES;
+    const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int nw = gridDim.x * (blockDim.x / WAVE);
+    for (int c0 = wid * gpw; c0 < ncells; c0 += nw * gpw) {
+        const int c = c0 + lane_id() / LANES;
+        CountSink sk;
+        if (c < ncells) enumerate_part<LANES>(t, H, ep, c, q, sk);
+        const int nV = group_sum<LANES>(sk.nV), nX = group_sum<LANES>(sk.nX);
+        const int nU = group_sum<LANES>(sk.nU), nW = group_sum<LANES>(sk.nW);
+        if (c < ncells && q == 0) {
+            cntVX[c] = (int64_t)nV | ((int64_t)nX << 32);
+            const int li = t.leafidx[c];
+            if (li >= 0) cntUW[li] = (int64_t)(nU + 1) | ((int64_t)nW << 32);  // + the leaf itself
+        }
+    }
 }
 
-__global__ void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX, const int64_t *__restrict__ offUW,
-                             int32_t *__restrict__ V, int32_t *__restrict__ X, int2 *__restrict__ U,
-                             int32_t *__restrict__ nU, int32_t *__restrict__ W,
-                             unsigned long long *__restrict__ near_pairs, int64_t cap,
-                             int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap, int64_t w_cap,
-                             int32_t *__restrict__ err)
+template <int LANES>
+__global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX,
+                                                    const int64_t *__restrict__ offUW, int32_t *__restrict__ V,
+                                                    int32_t *__restrict__ X, int2 *__restrict__ U,
+                                                    int32_t *__restrict__ nU, int32_t *__restrict__ W,
+                                                    unsigned long long *__restrict__ near_pairs, int64_t cap,
+                                                    int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap,
+                                                    int64_t w_cap, int32_t *__restrict__ err)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long pairs = 0;
+    const int ncells = t.counts[0];
     const int64_t tvx = offVX[cap], tuw = offUW[lcap];
     const bool fits = (tvx & 0xFFFFFFFFll) <= v_cap && (tvx >> 32) <= x_cap && (tuw & 0xFFFFFFFFll) <= u_cap &&
                       (tuw >> 32) <= w_cap;
-    if (!fits && c == 0) atomicOr(err, 4);
-    if (fits && c < t.counts[0]) {
-        const int64_t H = hash_size(t.counts[0], t.hash_cap);
-        const uint64_t ep = *t.epoch;
-        int64_t o = offVX[c];
-        int li = t.leafidx[c];
-        int64_t ou = li >= 0 ? offUW[li] : 0;
-        FillSink sk{V + (o & 0xFFFFFFFFll), X + (o >> 32), U + (ou & 0xFFFFFFFFll), W + (ou >> 32), t.beg, t.end};
-        enumerate_lists(t, H, ep, c, sk);
-        if (li >= 0) {
+    if (!fits) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 4);
+        return;
+    }
+    const int64_t H = hash_size(ncells, t.hash_cap);
+    const uint64_t ep = *t.epoch;
+    const int q = lane_id() & (LANES - 1);
+    const int gpw = WAVE / LANES;
+    const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int nw = gridDim.x * (blockDim.x / WAVE);
+    unsigned long long pairs = 0;
+    for (int c0 = wid * gpw; c0 < ncells; c0 += nw * gpw) {
+        const int c = c0 + lane_id() / LANES;
+        const bool live = c < ncells;
+        int pV = 0, pX = 0, pU = 0, pW = 0, kU = 0;
+        if (LANES > 1) {  // each lane's offsets within its group's lists
+            CountSink cs;
+            if (live) enumerate_part<LANES>(t, H, ep, c, q, cs);
+            pV = group_excl<LANES>(cs.nV);
+            pX = group_excl<LANES>(cs.nX);
+            pU = group_excl<LANES>(cs.nU);
+            pW = group_excl<LANES>(cs.nW);
+        }
+        const int li = live ? t.leafidx[c] : -1;
+        int2 *u0 = nullptr;
+        if (live) {
+            const int64_t o = offVX[c];
+            const int64_t ou = li >= 0 ? offUW[li] : 0;
+            u0 = U + (ou & 0xFFFFFFFFll);
+            FillSink sk{V + (o & 0xFFFFFFFFll) + pV, X + (o >> 32) + pX, u0 + 1 + pU, W + (ou >> 32) + pW,
+                        t.beg, t.end};
+            enumerate_part<LANES>(t, H, ep, c, q, sk);
+            if (li >= 0 && q == 0) u0[0] = make_int2(t.beg[c], t.end[c]);
+            kU = sk.nU;
+        }
+        if (LANES > 1) {
+            kU = group_sum<LANES>(kU);
+            // the group's U entries were written by its lanes: make them
+            // visible to lane 0, which sorts and merges them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        if (live && li >= 0 && q == 0) {
             // sort the near-field ranges by start and merge touching ones
-            int2 *r = sk.pU;
-            const int k = sk.nU;
+            int2 *r = u0;
+            const int k = kU + 1;
             for (int a = 1; a < k; ++a) {
                 const int2 v = r[a];
                 int b = a - 1;
@@ -572,7 +659,7 @@ __global__ void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX, cons
                 else r[m++] = r[a];
             }
             nU[li] = m;
-            pairs = (unsigned long long)src * (unsigned long long)(t.end[c] - t.beg[c]);
+            pairs += (unsigned long long)src * (unsigned long long)(t.end[c] - t.beg[c]);
         }
     }
     pairs = wave_sum(pairs);
@@ -796,8 +883,13 @@ void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const flo
     build_tree_impl(c, t, s, x, y, deg, bits, leaf);
 }
 
-void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
+// eight lanes measured faster at every size tried (15k-node components up to
+// a 2M-node system); one lane per cell stays available to the tuner
+int default_list_lanes(int64_t) { return 8; }
+
+void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
 {
+    FL_REQUIRE(lanes == 1 || lanes == 8, "list building takes 1 or 8 lanes per cell");
     const int64_t cap = t.cells_cap, lcap = t.leaves_cap;
     L.v_cap = 27 * cap;
     L.x_cap = 8 * cap;
@@ -813,14 +905,19 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L)
     L.nU = ws<int32_t>(c, "l_nU", lcap);
     L.W = ws<int32_t>(c, "l_W", L.w_cap);
     TreeView tv = view(t);
-    hipLaunchKernelGGL(k_lists_count, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, cntVX, cntUW);
+    // grid-stride over the cells (their number is known on the device only)
+    const bool wide = lanes == 8;
+    const unsigned lg = grid_for(cap, wide ? 256 / 8 : 256, 4096);
+    if (wide) hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW);
+    else hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW);
     FL_LAUNCH_CHECK();
     scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
     scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, c->d_stats + 2, 1);
-    hipLaunchKernelGGL(k_lists_fill, dim3(grid_for(cap, 128)), dim3(128), 0, c->stream, tv, L.offVX, L.offUW, L.V,
-                       L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2), cap, lcap, L.v_cap, L.x_cap, L.u_cap,
-                       L.w_cap, t.counts + 3);
+    auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
+    hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
+                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2),
+                       cap, lcap, L.v_cap, L.x_cap, L.u_cap, L.w_cap, t.counts + 3);
     hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, L.offVX + cap, L.offUW + lcap,
                        c->d_stats, t.n);
     FL_LAUNCH_CHECK();

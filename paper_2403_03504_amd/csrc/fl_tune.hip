@@ -21,6 +21,7 @@ constexpr int ERR_BLOCKS = 512;
 constexpr int ERR_NT = 256;
 const int TUNE_P[] = {4, 6, 8, 10, 12, 16};
 const int TUNE_LEAF[] = {16, 24, 32, 48, 64, 96, 128};
+const int TUNE_LANES[] = {1, 8};
 
 // per-block partial sums of |a - b|^2 and |b|^2 in FP64
 __global__ __launch_bounds__(ERR_NT) void k_err_partial(int n, const float *__restrict__ ax,
@@ -96,6 +97,8 @@ void check_tuning(const fl_tuning &t)
     for (int b = 0; b < t.n_buckets; ++b) {
         FL_REQUIRE(fmm_order_supported(t.p[b]), "tuning: p must be one of 4, 6, 8, 10, 12, 16");
         FL_REQUIRE(t.leaf_size[b] >= 1 && t.leaf_size[b] <= 1024, "tuning: leaf_size must be in [1, 1024]");
+        FL_REQUIRE(t.list_lanes[b] == 0 || t.list_lanes[b] == 1 || t.list_lanes[b] == 8,
+                   "tuning: list_lanes must be 0, 1 or 8");
         FL_REQUIRE(t.bucket_max[b] >= 1, "tuning: bucket_max must be >= 1");
         FL_REQUIRE(b == 0 || t.bucket_max[b] > t.bucket_max[b - 1], "tuning: bucket_max must be ascending");
     }
@@ -115,6 +118,7 @@ fl_fa2_params resolve_repulsion(const fl_tuning &t, int64_t n, const fl_fa2_para
     r.repulsion = FL_REP_FMM;
     r.p = t.p[b];
     r.leaf_size = t.leaf_size[b];
+    if (p.list_lanes == 0) r.list_lanes = t.list_lanes[b];
     return r;
 }
 
@@ -141,39 +145,45 @@ static void autotune(fl_ctx *c, int32_t n, const float *x, const float *y, const
         const int s = sizes[k];
         const Segs sg = segs_single(c, s);
         t_exact[k] = time_median(c, reps, [&] { exact_repulsion(c, sg, x, y, deg, 1.f, ex, ey); });
-        samples.push_back(fl_tune_sample{s, 0, 0, 1, t_exact[k], 0.0});
-        double best = INFINITY, best_err = INFINITY, closest = INFINITY;
-        int bp = 8, bl = 64, cp = 16, cl = 16;
+        samples.push_back(fl_tune_sample{s, 0, 0, 0, 1, t_exact[k], 0.0});
+        double best = INFINITY, best_err = INFINITY, closest = INFINITY, closest_ms = INFINITY;
+        int bp = 8, bl = 64, bn = 1, cp = 16, cl = 16, cn = 1;
         for (int p : TUNE_P) {
             for (int leaf : TUNE_LEAF) {
-                const double ms =
-                    time_median(c, reps, [&] { fmm_repulsion(c, sg, x, y, deg, p, leaf, bits, 1.f, fx, fy); });
-                if (tree_error_bits(c, true)) throw Error(FL_EHIP, "FMM capacity guard tripped while tuning");
-                const double e = rel_err(c, s, fx, fy, ex, ey);
-                const int ok = e <= max_rel_err ? 1 : 0;
-                samples.push_back(fl_tune_sample{s, p, leaf, ok, ms, e});
-                if (ok && ms < best) {
-                    best = ms;
-                    best_err = e;
-                    bp = p;
-                    bl = leaf;
-                }
-                if (e < closest) {
-                    closest = e;
-                    cp = p;
-                    cl = leaf;
+                for (int lanes : TUNE_LANES) {
+                    const double ms = time_median(
+                        c, reps, [&] { fmm_repulsion(c, sg, x, y, deg, p, leaf, bits, lanes, 1.f, fx, fy); });
+                    if (tree_error_bits(c, true)) throw Error(FL_EHIP, "FMM capacity guard tripped while tuning");
+                    const double e = rel_err(c, s, fx, fy, ex, ey);
+                    const int ok = e <= max_rel_err ? 1 : 0;
+                    samples.push_back(fl_tune_sample{s, p, leaf, lanes, ok, ms, e});
+                    if (ok && ms < best) {
+                        best = ms;
+                        best_err = e;
+                        bp = p;
+                        bl = leaf;
+                        bn = lanes;
+                    }
+                    if (e < closest || (e == closest && ms < closest_ms)) {
+                        closest = e;
+                        closest_ms = ms;
+                        cp = p;
+                        cl = leaf;
+                        cn = lanes;
+                    }
                 }
             }
         }
         if (!std::isfinite(best_err)) {  // no configuration meets the bound: the most accurate one
             bp = cp;
             bl = cl;
-            for (const auto &sm : samples)
-                if (sm.size == s && sm.p == cp && sm.leaf_size == cl) best = sm.ms;
+            bn = cn;
+            best = closest_ms;
         }
         t_fmm[k] = best;
         t.p[k] = bp;
         t.leaf_size[k] = bl;
+        t.list_lanes[k] = bn;
         t.bucket_max[k] = k + 1 < n_sizes ? (int32_t)std::floor(std::sqrt((double)s * sizes[k + 1])) : INT32_MAX;
     }
     // crossover: the FMM is faster from size index k0 on
@@ -201,6 +211,7 @@ void fl_default_tuning(fl_tuning *out)
     out->bucket_max[0] = INT32_MAX;
     out->p[0] = 8;
     out->leaf_size[0] = 64;
+    out->list_lanes[0] = 0;
     out->max_rel_err = 0.0;
 }
 

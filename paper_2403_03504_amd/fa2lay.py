@@ -51,7 +51,7 @@ class FA2Params(ctypes.Structure):
                 ("gravity_mode", ctypes.c_int32), ("swing_mode", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("ks", ctypes.c_double), ("ksmax", ctypes.c_double),
                 ("max_rise", ctypes.c_double), ("repulsion", ctypes.c_int32), ("p", ctypes.c_int32),
-                ("leaf_size", ctypes.c_int32), ("morton_bits", ctypes.c_int32)]
+                ("leaf_size", ctypes.c_int32), ("morton_bits", ctypes.c_int32), ("list_lanes", ctypes.c_int32)]
 
 
 class _State(ctypes.Structure):
@@ -83,12 +83,14 @@ class ServerStats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("fmm_min_nodes", ctypes.c_int32), ("n_buckets", ctypes.c_int32),
                 ("bucket_max", ctypes.c_int32 * TUNE_MAX_BUCKETS), ("p", ctypes.c_int32 * TUNE_MAX_BUCKETS),
-                ("leaf_size", ctypes.c_int32 * TUNE_MAX_BUCKETS), ("max_rel_err", ctypes.c_double)]
+                ("leaf_size", ctypes.c_int32 * TUNE_MAX_BUCKETS), ("list_lanes", ctypes.c_int32 * TUNE_MAX_BUCKETS),
+                ("max_rel_err", ctypes.c_double)]
 
     def to_dict(self) -> dict:
         nb = self.n_buckets
         return {"fmm_min_nodes": self.fmm_min_nodes, "bucket_max": list(self.bucket_max[:nb]),
-                "p": list(self.p[:nb]), "leaf_size": list(self.leaf_size[:nb]), "max_rel_err": self.max_rel_err}
+                "p": list(self.p[:nb]), "leaf_size": list(self.leaf_size[:nb]),
+                "list_lanes": list(self.list_lanes[:nb]), "max_rel_err": self.max_rel_err}
 
     @staticmethod
     def from_dict(d: dict) -> "Tuning":
@@ -97,14 +99,19 @@ class Tuning(ctypes.Structure):
         if not (len(d["bucket_max"]) == len(d["leaf_size"]) == nb):
             raise ValueError("tuning: bucket_max, p and leaf_size differ in length")
         t.fmm_min_nodes, t.n_buckets, t.max_rel_err = int(d["fmm_min_nodes"]), nb, float(d.get("max_rel_err", 0.0))
+        lanes = d.get("list_lanes", [0] * nb)
+        if len(lanes) != nb:
+            raise ValueError("tuning: list_lanes differs in length")
         for i in range(nb):
             t.bucket_max[i], t.p[i], t.leaf_size[i] = int(d["bucket_max"][i]), int(d["p"][i]), int(d["leaf_size"][i])
+            t.list_lanes[i] = int(lanes[i])
         return t
 
 
 class TuneSample(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int32), ("p", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
-                ("feasible", ctypes.c_int32), ("ms", ctypes.c_double), ("rel_err", ctypes.c_double)]
+                ("list_lanes", ctypes.c_int32), ("feasible", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("rel_err", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):
@@ -418,7 +425,7 @@ class Context:
         """fl_autotune: returns (tuning dict, list of measurement dicts); the
         table is also installed in this context."""
         sz, szp = _host_i32(sizes)
-        cap = len(sz) * 64
+        cap = len(sz) * 128
         arr = (TuneSample * cap)()
         ns = _i32()
         t = Tuning()

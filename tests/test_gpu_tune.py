@@ -62,13 +62,13 @@ def test_autotune_meets_its_bound(ctx, fl, orc):
     _note("  table", table)
     assert ctx.get_tuning() == table
     assert len(table["p"]) == len(sizes) and table["bucket_max"][-1] == 2 ** 31 - 1
-    assert len(samples) == len(sizes) * (1 + 6 * 7)
+    assert len(samples) == len(sizes) * (1 + 6 * 7 * 2)
     assert all(np.isfinite(s["ms"]) and s["ms"] > 0 for s in samples)
     # the crossover follows from the measured times
     for k, s in enumerate(sizes):
         ex = [q for q in samples if q["size"] == s and q["p"] == 0][0]["ms"]
         pick = [q for q in samples if q["size"] == s and q["p"] == table["p"][k]
-                and q["leaf_size"] == table["leaf_size"][k]][0]
+                and q["leaf_size"] == table["leaf_size"][k] and q["list_lanes"] == table["list_lanes"][k]][0]
         assert pick["feasible"] == 1 and pick["rel_err"] <= bound
         faster = [q for q in samples if q["size"] == s and q["p"] > 0 and q["feasible"] and q["ms"] < pick["ms"]]
         assert not faster
@@ -76,7 +76,8 @@ def test_autotune_meets_its_bound(ctx, fl, orc):
             assert pick["ms"] < ex
     # independent check of each chosen configuration against the FP64 oracle
     for k, s in enumerate(sizes):
-        prm = fl.default_params(repulsion=fl.REP_FMM, p=table["p"][k], leaf_size=table["leaf_size"][k])
+        prm = fl.default_params(repulsion=fl.REP_FMM, p=table["p"][k], leaf_size=table["leaf_size"][k],
+                                list_lanes=table["list_lanes"][k])
         out = ctx.fa2_forces(mass_graph(fl, deg[:s]), dev(x[:s]), dev(y[:s]), prm, components=False)
         ex, ey = orc.repulsion_exact(x[:s], y[:s], deg[:s] + 1.0)
         err = orc.rel_err(host(out["frx"]), host(out["fry"]), ex, ey)
@@ -86,7 +87,7 @@ def test_autotune_meets_its_bound(ctx, fl, orc):
 
 
 TABLE = {"fmm_min_nodes": 3000, "bucket_max": [5000, 2 ** 31 - 1], "p": [4, 12], "leaf_size": [32, 96],
-         "max_rel_err": 1e-3}
+         "list_lanes": [8, 1], "max_rel_err": 1e-3}
 
 
 @pytest.mark.parametrize("n,expect", [(2000, None), (4000, (4, 32)), (9000, (12, 96))])

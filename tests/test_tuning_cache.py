@@ -53,9 +53,9 @@ def test_default_table_and_struct_roundtrip():
     from paper_2403_03504_amd import fa2lay as fl
     d = fl.default_tuning()
     assert d == {"fmm_min_nodes": 4096, "bucket_max": [2 ** 31 - 1], "p": [8], "leaf_size": [64],
-                 "max_rel_err": 0.0}
+                 "list_lanes": [0], "max_rel_err": 0.0}
     t = {"fmm_min_nodes": 100, "bucket_max": [10, 20, 30], "p": [4, 6, 16], "leaf_size": [1, 2, 3],
-         "max_rel_err": 0.5}
+         "list_lanes": [1, 8, 0], "max_rel_err": 0.5}
     assert fl.Tuning.from_dict(t).to_dict() == t
     with pytest.raises(ValueError):
         fl.Tuning.from_dict(dict(t, p=[4]))

@@ -15,7 +15,7 @@ void fa2_validate(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *c
 // Exact O(n^2) repulsion within every system of `sg`, masses deg + 1 (no
 // validation).
 void exact_repulsion(fl_ctx *c, const Segs &sg, const float *x, const float *y, const int32_t *deg, float kr,
-                     float *frx, float *fry);
+                     float2 *fr);
 
 // A batch of independent systems sharing one set of parameters: system k owns
 // nodes [coff[k], coff[k+1]) of the arrays, whose CSR ids are local to the

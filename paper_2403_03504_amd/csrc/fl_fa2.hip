@@ -33,8 +33,7 @@ struct StepConsts {
 constexpr int EXACT_SUB = SEG_TILE / NT;
 
 __global__ __launch_bounds__(NT) void k_rep_exact(Segs sg, const float *__restrict__ x, const float *__restrict__ y,
-                                                  const int32_t *__restrict__ deg, float kr, float *__restrict__ frx,
-                                                  float *__restrict__ fry)
+                                                  const int32_t *__restrict__ deg, float kr, float2 *__restrict__ fr)
 {
     __shared__ float4 tile[NT];
     const int2 tl = sg.tiles[blockIdx.x / EXACT_SUB];
@@ -67,8 +66,7 @@ __global__ __launch_bounds__(NT) void k_rep_exact(Segs sg, const float *__restri
     }
     if (live) {
         const double km = (double)kr * (double)(deg[i] + 1);
-        frx[i] = (float)(km * ax);
-        fry[i] = (float)(km * ay);
+        fr[i] = make_float2((float)(km * ax), (float)(km * ay));
     }
 }
 
@@ -125,25 +123,23 @@ __global__ __launch_bounds__(NT) void k_attract_chunks(const int32_t *__restrict
 }
 
 // ---- attraction + gravity + combine + swing/traction ---------------------------
-// One block per system tile.  Per-tile FP64 partial sums of swing and
-// traction; the last tile of a system to finish adds its system's partials in
-// tile order (fixed, so runs are bitwise reproducible and a system's result
-// does not depend on the batch) and sets that system's global speed.
+// One block per system tile: forces, and per-tile FP64 partial sums of swing
+// and traction.  k_speed then adds each system's tile partials in tile order
+// (fixed, so runs are bitwise reproducible and a system's result does not
+// depend on the batch) and sets that system's global speed.
 __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const int32_t *__restrict__ deg,
                                                 const float2 *__restrict__ xy,
-                                                const float *__restrict__ frx, const float *__restrict__ fry,
+                                                const float2 *__restrict__ fr,
                                                 StepConsts k, const float *__restrict__ fpx,
                                                 const float *__restrict__ fpy, int first, float *__restrict__ fx,
                                                 float *__restrict__ fy, float *__restrict__ fax,
                                                 float *__restrict__ fay, float *__restrict__ fgx,
                                                 float *__restrict__ fgy, double2 *__restrict__ part,
-                                                unsigned *__restrict__ cticket, double *__restrict__ scalars,
-                                                int32_t *__restrict__ flags, double *__restrict__ ring, int ring_it,
-                                                const int32_t *__restrict__ choff, const double2 *__restrict__ csum)
+                                                int32_t *__restrict__ flags, const int32_t *__restrict__ choff,
+                                                const double2 *__restrict__ csum)
 {
     __shared__ double lds[NT / WAVE];
-    __shared__ int is_last;
     const int2 tl = sg.tiles[blockIdx.x];
     const int comp = tl.x;
     const int b1 = min(tl.y + SEG_TILE, sg.coff[comp + 1]);
@@ -194,7 +190,8 @@ __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restri
             Fgx = -k.kg * m * xi;
             Fgy = -k.kg * m * yi;
         }
-        const double Frx = frx ? (double)frx[i] : 0.0, Fry = fry ? (double)fry[i] : 0.0;
+        const float2 fri = fr ? fr[i] : make_float2(0.f, 0.f);
+        const double Frx = fri.x, Fry = fri.y;
         const float Fx = (float)(Frx + Fax + Fgx), Fy = (float)(Fry + Fay + Fgy);
         if (fx) {
             fx[i] = Fx;
@@ -221,46 +218,46 @@ __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restri
     if (!part) return;
     wswg = block_sum<double, NT>(wswg, lds);
     wtra = block_sum<double, NT>(wtra, lds);
-    const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = make_double2(wswg, wtra);
-        __threadfence();
-        const unsigned t = atomicAdd(&cticket[comp], 1u);
-        is_last = (t == (unsigned)(nt - 1));
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    // fixed-order reduction of the system's tile partials
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < nt; b += NT) {
-        const double2 v = part[t0 + b];
-        s0 += v.x;
-        s1 += v.y;
-    }
-    s0 = block_sum<double, NT>(s0, lds);
-    s1 = block_sum<double, NT>(s1, lds);
-    if (threadIdx.x == 0) {
-        double *sc = scalars + 4 * (int64_t)comp;
-        const double SWG = s0;
-        const double TRA = (k.swing_mode == FL_SWING_FA2) ? s1 / 2.0 : s1;
-        const double sprev = sc[0];
-        double sG;
-        if (SWG > 0.0) {
-            sG = k.tau * TRA / SWG;
-            if (!first) sG = fmin(sG, (1.0 + k.max_rise) * sprev);
-        } else {
-            sG = first ? 1.0 : (1.0 + k.max_rise) * sprev;
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(wswg, wtra);
+}
+
+// Block k: systems k, k + gridDim.x, ...: SWG, TRA (fixed-order sums of the
+// tile partials) and the global speed.
+__global__ __launch_bounds__(NT) void k_speed(Segs sg, const double2 *__restrict__ part, StepConsts k, int first,
+                                              double *__restrict__ scalars, double *__restrict__ ring, int ring_it)
+{
+    __shared__ double lds[NT / WAVE];
+    for (int comp = blockIdx.x; comp < sg.K; comp += gridDim.x) {
+        const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
+        double s0 = 0.0, s1 = 0.0;
+        for (int b = threadIdx.x; b < nt; b += NT) {
+            const double2 v = part[t0 + b];
+            s0 += v.x;
+            s1 += v.y;
         }
-        sc[0] = sG;
-        sc[1] = SWG;
-        sc[2] = TRA;
-        if (ring) {
-            ring[3 * ring_it + 0] = SWG;
-            ring[3 * ring_it + 1] = TRA;
-            ring[3 * ring_it + 2] = sG;
+        s0 = block_sum<double, NT>(s0, lds);
+        s1 = block_sum<double, NT>(s1, lds);
+        if (threadIdx.x == 0) {
+            double *sc = scalars + 4 * (int64_t)comp;
+            const double SWG = s0;
+            const double TRA = (k.swing_mode == FL_SWING_FA2) ? s1 / 2.0 : s1;
+            const double sprev = sc[0];
+            double sG;
+            if (SWG > 0.0) {
+                sG = k.tau * TRA / SWG;
+                if (!first) sG = fmin(sG, (1.0 + k.max_rise) * sprev);
+            } else {
+                sG = first ? 1.0 : (1.0 + k.max_rise) * sprev;
+            }
+            sc[0] = sG;
+            sc[1] = SWG;
+            sc[2] = TRA;
+            if (ring) {
+                ring[3 * ring_it + 0] = SWG;
+                ring[3 * ring_it + 1] = TRA;
+                ring[3 * ring_it + 2] = sG;
+            }
         }
-        cticket[comp] = 0u;
     }
 }
 
@@ -291,6 +288,15 @@ __global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, f
         fpy[i] = Fy;
         if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags, 2);
     }
+}
+
+__global__ void k_split(const float2 *__restrict__ v, int n, float *__restrict__ a, float *__restrict__ b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 q = v[i];
+    a[i] = q.x;
+    b[i] = q.y;
 }
 
 __global__ void k_validate_rows(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ deg,
@@ -417,16 +423,16 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
 }
 
 static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float *x, const float *y,
-                      const fl_fa2_params *p, float *frx, float *fry)
+                      const fl_fa2_params *p, float2 *fr)
 {
     if (p->repulsion == FL_REP_EXACT) {
         PhaseTimer pt(c, FL_PH_EXACT);
         hipLaunchKernelGGL(k_rep_exact, dim3(sg.ntiles * EXACT_SUB), dim3(NT), 0, c->stream, sg, x, y, g.deg,
-                           (float)p->kr, frx, fry);
+                           (float)p->kr, fr);
         FL_LAUNCH_CHECK();
     } else {
         const int lanes = p->list_lanes ? p->list_lanes : default_list_lanes(sg.n);
-        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, frx, fry);
+        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, fr);
     }
 }
 
@@ -454,23 +460,23 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
 {
     fl_ctx *c = b.c;
     const int n = b.g.n;
-    float *frx = ws<float>(c, "fa2_frx", n);
-    float *fry = ws<float>(c, "fa2_fry", n);
+    float2 *fr = ws<float2>(c, "fa2_fr", n);
     float *fcx = ws<float>(c, "fa2_fcx", n);
     float *fcy = ws<float>(c, "fa2_fcy", n);
     double2 *part = ws<double2>(c, "fa2_part", (size_t)b.sg.ntiles);
-    unsigned *cticket = ws_zeroed<unsigned>(c, "fa2_cticket", (size_t)b.sg.K);
     const int first = b.st.iter == 0 ? 1 : 0;
-    repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, frx, fry);
+    repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
     {
         PhaseTimer pt(c, FL_PH_ATTRACT);
         double2 *csum = ws<double2>(c, "at_csum", b.ap.cap);
         const float2 *xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum);
         hipLaunchKernelGGL(k_combine, dim3(b.sg.ntiles), dim3(NT), 0, c->stream, b.sg, b.g.row_ptr, b.g.col,
-                           b.g.deg, xy, (const float *)frx, (const float *)fry, consts(&b.prm),
+                           b.g.deg, xy, (const float2 *)fr, consts(&b.prm),
                            (const float *)b.st.fx_prev, (const float *)b.st.fy_prev, first, fcx, fcy,
-                           (float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, part, cticket,
-                           b.st.scalars, flags, ring, ring_it, (const int32_t *)b.ap.choff, (const double2 *)csum);
+                           (float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, part, flags,
+                           (const int32_t *)b.ap.choff, (const double2 *)csum);
+        hipLaunchKernelGGL(k_speed, dim3(std::min(b.sg.K, 1024)), dim3(NT), 0, c->stream, b.sg,
+                           (const double2 *)part, consts(&b.prm), first, b.st.scalars, ring, ring_it);
         FL_LAUNCH_CHECK();
     }
     {
@@ -613,9 +619,9 @@ void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &in, int iters, int3
 }
 
 void exact_repulsion(fl_ctx *c, const Segs &sg, const float *x, const float *y, const int32_t *deg, float kr,
-                     float *frx, float *fry)
+                     float2 *fr)
 {
-    hipLaunchKernelGGL(k_rep_exact, dim3(sg.ntiles * EXACT_SUB), dim3(NT), 0, c->stream, sg, x, y, deg, kr, frx, fry);
+    hipLaunchKernelGGL(k_rep_exact, dim3(sg.ntiles * EXACT_SUB), dim3(NT), 0, c->stream, sg, x, y, deg, kr, fr);
     FL_LAUNCH_CHECK();
 }
 
@@ -665,19 +671,21 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
     GraphArgs g{n, row_ptr, col_idx, deg};
     validate_graph(c, g);
     const Segs sg = segs_single(c, n);
-    float *rx = frx ? frx : ws<float>(c, "fa2_frx", n);
-    float *ry = fry ? fry : ws<float>(c, "fa2_fry", n);
-    repulsion(c, sg, g, x, y, prm, rx, ry);
+    float2 *fr = ws<float2>(c, "fa2_fr", n);
+    repulsion(c, sg, g, x, y, prm, fr);
+    if (frx) {
+        hipLaunchKernelGGL(k_split, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float2 *)fr, n, frx, fry);
+        FL_LAUNCH_CHECK();
+    }
     if (fax || fgx) {
         int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
         AttractPlan ap = attract_plan(c, g);
         double2 *csum = ws<double2>(c, "at_csum", ap.cap);
         const float2 *xy = attract_chunks(c, g, ap, x, y, csum);
         hipLaunchKernelGGL(k_combine, dim3(sg.ntiles), dim3(NT), 0, c->stream, sg, row_ptr, col_idx, deg, xy,
-                           (const float *)nullptr, (const float *)nullptr, consts(prm), (const float *)nullptr,
+                           (const float2 *)nullptr, consts(prm), (const float *)nullptr,
                            (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
-                           (double2 *)nullptr, (unsigned *)nullptr, (double *)nullptr, flags, (double *)nullptr, 0,
-                           ap.choff, (const double2 *)csum);
+                           (double2 *)nullptr, flags, (const int32_t *)ap.choff, (const double2 *)csum);
         FL_LAUNCH_CHECK();
     }
     FL_API_END(c)

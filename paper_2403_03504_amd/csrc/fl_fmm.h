@@ -7,11 +7,11 @@ namespace fl {
 
 bool fmm_order_supported(int p);
 
-// F_r of every node in original order into frx/fry (FP32), on the context
-// stream, without host synchronisation.  deg supplies the masses deg + 1.
-// Every system of `s` is its own particle set: no force crosses systems.
-// lanes: lanes per cell of the list kernels (1 or 8).
+// F_r of every node in original order into fr (FP32 (x, y) pairs), on the
+// context stream, without host synchronisation.  deg supplies the masses
+// deg + 1.  Every system of `s` is its own particle set: no force crosses
+// systems.  lanes: lanes per cell of the list kernels (1 or 8).
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, int lanes, float kr, float *frx, float *fry);
+                   int bits, int lanes, float kr, float2 *fr);
 
 }  // namespace fl

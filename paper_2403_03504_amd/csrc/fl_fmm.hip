@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                                               const int32_t *__restrict__ nU, const int32_t *__restrict__ W,
                                               const int32_t *__restrict__ cbeg, const int32_t *__restrict__ cend,
                                               const int32_t *__restrict__ leaf_cell, float kr,
-                                              float *__restrict__ frx, float *__restrict__ fry)
+                                              float2 *__restrict__ fr)
 {
     const int nleaves = t.counts[1];
     const int lane = lane_id();
@@ -536,8 +536,7 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                 // F = kr m_i (conj(phi'_far) + near field)
                 const float km = kr * me.z;
                 const int orig = __float_as_int(me.w);
-                frx[orig] = km * (dphi.x + fx);
-                fry[orig] = km * (fy - dphi.y);
+                fr[orig] = make_float2(km * (dphi.x + fx), km * (fy - dphi.y));  // one 8-byte store per node
             }
         }
     }
@@ -545,7 +544,7 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
 #undef FL_P2P_PAIR
 
 template <int P>
-void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float *frx, float *fry)
+void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float2 *fr)
 {
     const int64_t cap = t.cells_cap, lcap = t.leaves_cap;
     float2 *M = ws<float2>(c, "f_M", (size_t)cap * (P + 1));
@@ -582,7 +581,7 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
         const unsigned ge = grid_for(lcap, 4, 2048);  // 4 waves per block
         hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, M, Ll, L.offUW,
                            (const int2 *)L.U, (const int32_t *)L.nU, L.W, (const int32_t *)t.beg,
-                           (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr, frx, fry);
+                           (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr, fr);
         FL_LAUNCH_CHECK();
     }
 }
@@ -592,7 +591,7 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float 
 bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16; }
 
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, int lanes, float kr, float *frx, float *fry)
+                   int bits, int lanes, float kr, float2 *fr)
 {
     TreeBufs t;
     ListBufs L;
@@ -605,12 +604,12 @@ void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, con
         build_lists(c, t, L, lanes);
     }
     switch (p) {
-    case 4: run_fmm_p<4>(c, t, L, kr, frx, fry); break;
-    case 6: run_fmm_p<6>(c, t, L, kr, frx, fry); break;
-    case 8: run_fmm_p<8>(c, t, L, kr, frx, fry); break;
-    case 10: run_fmm_p<10>(c, t, L, kr, frx, fry); break;
-    case 12: run_fmm_p<12>(c, t, L, kr, frx, fry); break;
-    case 16: run_fmm_p<16>(c, t, L, kr, frx, fry); break;
+    case 4: run_fmm_p<4>(c, t, L, kr, fr); break;
+    case 6: run_fmm_p<6>(c, t, L, kr, fr); break;
+    case 8: run_fmm_p<8>(c, t, L, kr, fr); break;
+    case 10: run_fmm_p<10>(c, t, L, kr, fr); break;
+    case 12: run_fmm_p<12>(c, t, L, kr, fr); break;
+    case 16: run_fmm_p<16>(c, t, L, kr, fr); break;
     default: throw Error(FL_EUNSUPPORTED, "FMM expansion order not built (use 4, 6, 8, 10, 12 or 16)");
     }
 }

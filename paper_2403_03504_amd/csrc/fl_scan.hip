@@ -1,7 +1,7 @@
 // Device-wide exclusive scans and a stable LSD radix sort, written for wave64.
 //
-// Scan: reduce tiles -> scan tile sums in one block -> rescan tiles with their
-// offsets.  Radix sort: per pass, a digit histogram per tile, a scan of the
+// Scan: reduce tiles -> rescan every tile with the sum of the tiles before it
+// (two launches; the tile sums are scanned first only when there are many).  Radix sort: per pass, a digit histogram per tile, a scan of the
 // digit-major histogram, and a stable scatter in which each wave ranks its
 // keys step by step with ballot-built "same digit" lane masks (no atomics in
 // the ranking, so the order of equal digits is the input order).
@@ -34,31 +34,46 @@ __global__ __launch_bounds__(SC_NT) void k_scan_reduce(const T *__restrict__ in,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// One block scans the tile sums in place (exclusive) and writes the total.
-template <class T>
-__global__ __launch_bounds__(SC_TOP_NT) void k_scan_top(T *__restrict__ part, int64_t ntiles, T *__restrict__ total)
-{
-    __shared__ T lds[SC_TOP_NT / WAVE];
-    T carry = T(0);
-    for (int64_t b = 0; b < ntiles; b += SC_TOP_NT) {
-        int64_t i = b + threadIdx.x;
-        T v = i < ntiles ? part[i] : T(0);
-        T tot;
-        T ex = block_excl_scan<T, SC_TOP_NT>(v, lds, tot);
-        if (i < ntiles) part[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *total = carry;
-}
+// Each block adds the sums of the tiles before it, then scans its own tile.
+// With few tiles (<= SC_DIRECT) a block adds the raw tile sums itself in a
+// fixed order; with more, they were scanned beforehand (part then holds the
+// exclusive prefixes and part[ntiles] the total).  Block 0 also writes the
+// total to out[live] and out[n].  Entries past `live` are only written inside
+// the last live tile.
+constexpr int64_t SC_DIRECT = 4096;
 
 template <class T>
 __global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T *__restrict__ out, int64_t n,
-                                                      const int32_t *__restrict__ dn, const T *__restrict__ part)
+                                                      const int32_t *__restrict__ dn, const T *__restrict__ part,
+                                                      int scanned)
 {
     __shared__ T lds[SC_NT / WAVE];
     int64_t live = dn ? (int64_t)*dn : n;
     if (live > n) live = n;
-    int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_IPT;
+    const int64_t tile0 = (int64_t)blockIdx.x * SC_TILE;
+    const int64_t nlive_tiles = (live + SC_TILE - 1) / SC_TILE;
+    if (blockIdx.x == 0) {
+        T tot = T(0);
+        if (scanned) {
+            tot = part[nlive_tiles];
+        } else {
+            for (int64_t b = threadIdx.x; b < nlive_tiles; b += SC_NT) tot += part[b];
+            tot = block_sum<T, SC_NT>(tot, lds);
+        }
+        if (threadIdx.x == 0) {
+            out[live] = tot;
+            out[n] = tot;
+        }
+    }
+    if (tile0 >= live) return;  // the whole block
+    T carry = T(0);
+    if (scanned) {
+        carry = part[blockIdx.x];
+    } else {
+        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SC_NT) carry += part[b];
+        carry = block_sum<T, SC_NT>(carry, lds);
+    }
+    const int64_t base = tile0 + (int64_t)threadIdx.x * SC_IPT;
     T v[SC_IPT];
     T s = T(0);
 #pragma unroll
@@ -69,7 +84,7 @@ __global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T
     }
     T tot;
     T ex = block_excl_scan<T, SC_NT>(s, lds, tot);
-    T run = part[blockIdx.x] + ex;
+    T run = carry + ex;
 #pragma unroll
     for (int i = 0; i < SC_IPT; ++i) {
         int64_t idx = base + i;
@@ -78,25 +93,23 @@ __global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T
     }
 }
 
-// out[n] = total (copied from the top-level result)
 template <class T>
-__global__ void k_scan_total(T *__restrict__ out, int64_t n, const T *__restrict__ total)
-{
-    out[n] = *total;
-}
-
-template <class T>
-void scan_excl(fl_ctx *c, const T *in, T *out, int64_t n, const int32_t *dn, const char *tag)
+void scan_excl(fl_ctx *c, const T *in, T *out, int64_t n, const int32_t *dn, const char *tag, int depth = 0)
 {
     int64_t ntiles = (n + SC_TILE - 1) / SC_TILE;
     if (ntiles < 1) ntiles = 1;
-    std::string nm = std::string("scan_part_") + tag;
+    std::string nm = std::string("scan_part_") + tag + std::to_string(depth);
     T *part = ws<T>(c, nm.c_str(), (size_t)ntiles + 1);
-    T *total = part + ntiles;
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)ntiles), dim3(SC_NT), 0, c->stream, in, n, dn, part);
-    hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(SC_TOP_NT), 0, c->stream, part, ntiles, total);
-    hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)ntiles), dim3(SC_NT), 0, c->stream, in, out, n, dn, part);
-    hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(1), 0, c->stream, out, n, total);
+    const bool scanned = ntiles > SC_DIRECT;
+    if (scanned) {  // exclusive prefixes of the tile sums, total at part[ntiles]
+        std::string nm2 = std::string("scan_pfx_") + tag + std::to_string(depth);
+        T *pfx = ws<T>(c, nm2.c_str(), (size_t)ntiles + 1);
+        scan_excl<T>(c, part, pfx, ntiles, nullptr, tag, depth + 1);
+        part = pfx;
+    }
+    hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)ntiles), dim3(SC_NT), 0, c->stream, in, out, n, dn,
+                       (const T *)part, scanned ? 1 : 0);
     FL_LAUNCH_CHECK();
 }
 

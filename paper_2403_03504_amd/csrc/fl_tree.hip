@@ -23,6 +23,8 @@
 //   X(c)   <= 8 (one covering leaf per ring square of the parent);
 //   sum |W| = sum |X| (W and X are dual) <= 8 cells;
 //   sum |U| <= 17 leaves (a leaf touches at most 8 cells at least its size).
+#include <algorithm>
+
 #include "fl_tree.h"
 
 namespace fl {
@@ -79,23 +81,18 @@ __device__ __forceinline__ int common_digits(uint32_t a, uint32_t b, int bits)
 }
 
 // ---- bbox + root square per system ------------------------------------------
-// One block per tile (tiles never straddle two systems).  The last tile of a
-// system to finish combines that system's tile extrema (min/max are exact, so
-// the order does not matter) into its root square; the last system to finish
-// advances the hash epoch.
+// k_bbox: the extrema of every tile (tiles never straddle two systems);
+// k_bbox_root: one block per system combines its tiles' extrema (min/max are
+// exact, so the order does not matter) into the system's root square.  Two
+// launches and no device-scope fences.
 __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const float *__restrict__ y, Segs sg,
-                                             float4 *__restrict__ partial, unsigned *__restrict__ cticket,
-                                             unsigned *__restrict__ gticket, double *__restrict__ root, int bits,
-                                             uint32_t *__restrict__ epoch)
+                                             float4 *__restrict__ partial)
 {
     __shared__ float4 red[NT / WAVE];
-    __shared__ int is_last;
     const int2 tl = sg.tiles[blockIdx.x];
-    const int comp = tl.x, b0 = tl.y;
-    const int cend = sg.coff[comp + 1];
-    const int b1 = min(b0 + SEG_TILE, cend);
+    const int b1 = min(tl.y + SEG_TILE, sg.coff[tl.x + 1]);
     float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
-    for (int i = b0 + threadIdx.x; i < b1; i += NT) {
+    for (int i = tl.y + threadIdx.x; i < b1; i += NT) {
         float a = x[i], b = y[i];
         mnx = fminf(mnx, a);
         mxx = fmaxf(mxx, a);
@@ -108,7 +105,6 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
     mxy = wave_max_f(mxy);
     if (lane_id() == 0) red[threadIdx.x / WAVE] = make_float4(mnx, mxx, mny, mxy);
     __syncthreads();
-    const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
     if (threadIdx.x == 0) {
         float4 r = red[0];
         for (int w = 1; w < NT / WAVE; ++w) {
@@ -118,58 +114,57 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
             r.w = fmaxf(r.w, red[w].w);
         }
         partial[blockIdx.x] = r;
-        __threadfence();
-        unsigned t = atomicAdd(&cticket[comp], 1u);
-        is_last = (t == (unsigned)(nt - 1));
     }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    float4 q = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-    for (int j = threadIdx.x; j < nt; j += NT) {
-        const float4 v = partial[t0 + j];
-        q.x = fminf(q.x, v.x);
-        q.y = fmaxf(q.y, v.y);
-        q.z = fminf(q.z, v.z);
-        q.w = fmaxf(q.w, v.w);
+}
+
+// Block k finishes the root squares of systems k, k + gridDim.x, ...; block 0
+// also advances the hash epoch (when there is a table).
+__global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restrict__ partial,
+                                                  double *__restrict__ root, int bits, uint32_t *__restrict__ epoch)
+{
+    __shared__ float4 red[NT / WAVE];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && epoch) {
+        uint32_t e = *epoch + 1u;
+        if (e >= (1u << (HASH_TAG_BITS - sg.cbits)) || e == 0u) e = 1u;  // wrap: k_morton clears the table
+        *epoch = e;
     }
-    q.x = wave_min_f(q.x);
-    q.y = wave_max_f(q.y);
-    q.z = wave_min_f(q.z);
-    q.w = wave_max_f(q.w);
-    __syncthreads();
-    if (lane_id() == 0) red[threadIdx.x / WAVE] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float4 r = red[0];
-        for (int w = 1; w < NT / WAVE; ++w) {
-            r.x = fminf(r.x, red[w].x);
-            r.y = fmaxf(r.y, red[w].y);
-            r.z = fminf(r.z, red[w].z);
-            r.w = fmaxf(r.w, red[w].w);
+    for (int comp = blockIdx.x; comp < sg.K; comp += gridDim.x) {
+        const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
+        float4 q = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        for (int j = threadIdx.x; j < nt; j += NT) {
+            const float4 v = partial[t0 + j];
+            q.x = fminf(q.x, v.x);
+            q.y = fmaxf(q.y, v.y);
+            q.z = fminf(q.z, v.z);
+            q.w = fmaxf(q.w, v.w);
         }
-        double x0 = r.x, x1 = r.y, y0 = r.z, y1 = r.w;
-        double L = (x1 - x0) > (y1 - y0) ? (x1 - x0) : (y1 - y0);
-        if (!(L > 0.0)) L = 1.0;
-        if (!isfinite(x0)) x0 = 0.0;
-        if (!isfinite(y0)) y0 = 0.0;
-        if (!isfinite(L)) L = 1.0;
-        double *rt = root + 4 * (int64_t)comp;
-        rt[0] = x0;
-        rt[1] = y0;
-        rt[2] = L;
-        rt[3] = __ddiv_rn(ldexp(1.0, bits), L);
-        cticket[comp] = 0u;
-        __threadfence();
-        const unsigned g = atomicAdd(gticket, 1u);
-        if (g == (unsigned)(sg.K - 1)) {
-            if (epoch) {
-                uint32_t e = *epoch + 1u;
-                if (e >= (1u << (HASH_TAG_BITS - sg.cbits)) || e == 0u) e = 1u;  // wrap: k_morton clears the table
-                *epoch = e;
+        q.x = wave_min_f(q.x);
+        q.y = wave_max_f(q.y);
+        q.z = wave_min_f(q.z);
+        q.w = wave_max_f(q.w);
+        if (lane_id() == 0) red[threadIdx.x / WAVE] = q;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float4 r = red[0];
+            for (int w = 1; w < NT / WAVE; ++w) {
+                r.x = fminf(r.x, red[w].x);
+                r.y = fmaxf(r.y, red[w].y);
+                r.z = fminf(r.z, red[w].z);
+                r.w = fmaxf(r.w, red[w].w);
             }
-            *gticket = 0u;
+            double x0 = r.x, x1 = r.y, y0 = r.z, y1 = r.w;
+            double L = (x1 - x0) > (y1 - y0) ? (x1 - x0) : (y1 - y0);
+            if (!(L > 0.0)) L = 1.0;
+            if (!isfinite(x0)) x0 = 0.0;
+            if (!isfinite(y0)) y0 = 0.0;
+            if (!isfinite(L)) L = 1.0;
+            double *rt = root + 4 * (int64_t)comp;
+            rt[0] = x0;
+            rt[1] = y0;
+            rt[2] = L;
+            rt[3] = __ddiv_rn(ldexp(1.0, bits), L);
         }
+        __syncthreads();
     }
 }
 
@@ -582,6 +577,34 @@ __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__rest
     }
 }
 
+// Near-field ranges of a leaf are sorted by start and touching ones merged.
+// Up to FILL_STAGE of them are gathered in LDS and sorted there by lane 0 of
+// the cell's group (a handful of LDS operations per range); larger lists
+// (rare: a coarse leaf beside many small ones) are sorted in place in global
+// memory.
+constexpr int FILL_STAGE = 48;
+
+__device__ __forceinline__ int sort_merge_ranges(int2 *r, int k, int64_t &src)
+{
+    for (int a = 1; a < k; ++a) {
+        const int2 v = r[a];
+        int b = a - 1;
+        while (b >= 0 && r[b].x > v.x) {
+            r[b + 1] = r[b];
+            --b;
+        }
+        r[b + 1] = v;
+    }
+    int m = 0;
+    src = 0;
+    for (int a = 0; a < k; ++a) {
+        src += r[a].y - r[a].x;
+        if (m > 0 && r[m - 1].y == r[a].x) r[m - 1].y = r[a].y;
+        else r[m++] = r[a];
+    }
+    return m;
+}
+
 template <int LANES>
 __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX,
                                                     const int64_t *__restrict__ offUW, int32_t *__restrict__ V,
@@ -591,8 +614,10 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                                                     int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap,
                                                     int64_t w_cap, int32_t *__restrict__ err)
 {
+    constexpr int STG = LANES > 1 ? FILL_STAGE : 1;  // one lane per cell: no staging
+    __shared__ int2 stage[256 / LANES][STG];
     const int ncells = t.counts[0];
-    const int64_t tvx = offVX[cap], tuw = offUW[lcap];
+    const int64_t tvx = offVX[ncells], tuw = offUW[t.counts[1]];
     const bool fits = (tvx & 0xFFFFFFFFll) <= v_cap && (tvx >> 32) <= x_cap && (tuw & 0xFFFFFFFFll) <= u_cap &&
                       (tuw >> 32) <= w_cap;
     if (!fits) {
@@ -605,11 +630,17 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
     const int gpw = WAVE / LANES;
     const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int nw = gridDim.x * (blockDim.x / WAVE);
+    int2 *st = stage[threadIdx.x / LANES];
     unsigned long long pairs = 0;
     for (int c0 = wid * gpw; c0 < ncells; c0 += nw * gpw) {
         const int c = c0 + lane_id() / LANES;
         const bool live = c < ncells;
-        int pV = 0, pX = 0, pU = 0, pW = 0, kU = 0;
+        const int li = live ? t.leafidx[c] : -1;
+        const int64_t ou = li >= 0 ? offUW[li] : 0;
+        int2 *u0 = U + (ou & 0xFFFFFFFFll);
+        // the leaf's range count, itself included (from the counting pass)
+        const int k = li >= 0 ? (int)((offUW[li + 1] - ou) & 0xFFFFFFFFll) : 0;
+        int pV = 0, pX = 0, pU = 0, pW = 0;
         if (LANES > 1) {  // each lane's offsets within its group's lists
             CountSink cs;
             if (live) enumerate_part<LANES>(t, H, ep, c, q, cs);
@@ -618,63 +649,50 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
             pU = group_excl<LANES>(cs.nU);
             pW = group_excl<LANES>(cs.nW);
         }
-        const int li = live ? t.leafidx[c] : -1;
-        int2 *u0 = nullptr;
+        const bool staged = LANES > 1 && li >= 0 && k <= STG;
         if (live) {
             const int64_t o = offVX[c];
-            const int64_t ou = li >= 0 ? offUW[li] : 0;
-            u0 = U + (ou & 0xFFFFFFFFll);
-            FillSink sk{V + (o & 0xFFFFFFFFll) + pV, X + (o >> 32) + pX, u0 + 1 + pU, W + (ou >> 32) + pW,
-                        t.beg, t.end};
+            FillSink sk{V + (o & 0xFFFFFFFFll) + pV, X + (o >> 32) + pX, (staged ? st : u0) + 1 + pU,
+                        W + (ou >> 32) + pW, t.beg, t.end};
             enumerate_part<LANES>(t, H, ep, c, q, sk);
-            if (li >= 0 && q == 0) u0[0] = make_int2(t.beg[c], t.end[c]);
-            kU = sk.nU;
+            if (li >= 0 && q == 0) (staged ? st : u0)[0] = make_int2(t.beg[c], t.end[c]);
         }
-        if (LANES > 1) {
-            kU = group_sum<LANES>(kU);
-            // the group's U entries were written by its lanes: make them
-            // visible to lane 0, which sorts and merges them
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-        if (live && li >= 0 && q == 0) {
-            // sort the near-field ranges by start and merge touching ones
-            int2 *r = u0;
-            const int k = kU + 1;
-            for (int a = 1; a < k; ++a) {
-                const int2 v = r[a];
-                int b = a - 1;
-                while (b >= 0 && r[b].x > v.x) {
-                    r[b + 1] = r[b];
-                    --b;
-                }
-                r[b + 1] = v;
-            }
-            int m = 0;
-            int64_t src = 0;
-            for (int a = 0; a < k; ++a) {
-                src += r[a].y - r[a].x;
-                if (m > 0 && r[m - 1].y == r[a].x) r[m - 1].y = r[a].y;
-                else r[m++] = r[a];
+        // the group's U entries were written by its lanes (LDS, or global
+        // memory for long lists): make them visible to lane 0
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (li >= 0 && q == 0) {
+            int64_t src;
+            int m;
+            if (staged) {
+                m = sort_merge_ranges(st, k, src);
+                for (int a = 0; a < m; ++a) u0[a] = st[a];
+            } else {
+                m = sort_merge_ranges(u0, k, src);
             }
             nU[li] = m;
             pairs += (unsigned long long)src * (unsigned long long)(t.end[c] - t.beg[c]);
         }
+        // lane 0 is done with the stage before the next cell's lanes write it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     pairs = wave_sum(pairs);
     if (lane_id() == 0 && pairs) atomicAdd(near_pairs, pairs);
 }
 
-__global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t *__restrict__ totVX,
-                              const int64_t *__restrict__ totUW, int64_t *__restrict__ st, int n)
+__global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t *__restrict__ offVX,
+                              const int64_t *__restrict__ offUW, int64_t *__restrict__ st, int n)
 {
+    const int64_t tvx = offVX[counts[0]], tuw = offUW[counts[1]];
     st[0] = counts[0];
     st[1] = counts[1];
-    st[3] = *totVX & 0xFFFFFFFFll;
-    st[5] = *totVX >> 32;
-    st[7] = *totUW & 0xFFFFFFFFll;
-    st[4] = *totUW >> 32;
+    st[3] = tvx & 0xFFFFFFFFll;
+    st[5] = tvx >> 32;
+    st[7] = tuw & 0xFFFFFFFFll;
+    st[4] = tuw >> 32;
     st[8] += st[2];
     st[9] += st[3];
     st[10] += 1;
@@ -801,8 +819,6 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
 
     t.root = ws<double>(c, "t_root", 4 * (size_t)s.K);
     float4 *bpart = ws<float4>(c, "t_bbox_part", (size_t)s.ntiles);
-    unsigned *cticket = ws_zeroed<unsigned>(c, "t_cticket", (size_t)s.K);
-    unsigned *gticket = ws_zeroed<unsigned>(c, "t_gticket", 4);
     t.epoch = ws_zeroed<uint32_t>(c, "t_epoch", 4);
     uint32_t *k0 = ws<uint32_t>(c, "t_key0", n);
     uint32_t *k1 = ws<uint32_t>(c, "t_key1", n);
@@ -839,8 +855,9 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
         c->tree_cbits = s.cbits;
     }
 
-    hipLaunchKernelGGL(k_bbox, dim3(s.ntiles), dim3(NT), 0, c->stream, x, y, s, bpart, cticket, gticket, t.root, bits,
-                       t.epoch);
+    hipLaunchKernelGGL(k_bbox, dim3(s.ntiles), dim3(NT), 0, c->stream, x, y, s, bpart);
+    hipLaunchKernelGGL(k_bbox_root, dim3(std::min(s.K, 1024)), dim3(NT), 0, c->stream, s, (const float4 *)bpart,
+                       t.root, bits, t.epoch);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
                        (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
                        t.hkey, t.hash_cap);
@@ -918,7 +935,8 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
                        (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2),
                        cap, lcap, L.v_cap, L.x_cap, L.u_cap, L.w_cap, t.counts + 3);
-    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, L.offVX + cap, L.offUW + lcap,
+    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, (const int64_t *)L.offVX,
+                       (const int64_t *)L.offUW,
                        c->d_stats, t.n);
     FL_LAUNCH_CHECK();
 }
@@ -959,10 +977,9 @@ void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits,
     const Segs sg = segs_single(c, n);
     double *root = root_out ? root_out : ws<double>(c, "t_root", 4);
     float4 *bpart = ws<float4>(c, "t_bbox_part", (size_t)sg.ntiles);
-    unsigned *cticket = ws_zeroed<unsigned>(c, "t_cticket", 1);
-    unsigned *gticket = ws_zeroed<unsigned>(c, "t_gticket", 4);
     // no tree is built: leave the hash epoch alone
-    hipLaunchKernelGGL(k_bbox, dim3(sg.ntiles), dim3(NT), 0, c->stream, x, y, sg, bpart, cticket, gticket, root, bits,
+    hipLaunchKernelGGL(k_bbox, dim3(sg.ntiles), dim3(NT), 0, c->stream, x, y, sg, bpart);
+    hipLaunchKernelGGL(k_bbox_root, dim3(1), dim3(NT), 0, c->stream, sg, (const float4 *)bpart, root, bits,
                        (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, (const int32_t *)nullptr,
                        (const double *)root, bits, key, (uint64_t *)nullptr, (int32_t *)nullptr,

@@ -24,15 +24,15 @@ const int TUNE_LEAF[] = {16, 24, 32, 48, 64, 96, 128};
 const int TUNE_LANES[] = {1, 8};
 
 // per-block partial sums of |a - b|^2 and |b|^2 in FP64
-__global__ __launch_bounds__(ERR_NT) void k_err_partial(int n, const float *__restrict__ ax,
-                                                         const float *__restrict__ ay, const float *__restrict__ bx,
-                                                         const float *__restrict__ by, double2 *__restrict__ part)
+__global__ __launch_bounds__(ERR_NT) void k_err_partial(int n, const float2 *__restrict__ a,
+                                                         const float2 *__restrict__ b, double2 *__restrict__ part)
 {
     __shared__ double lds[ERR_NT / WAVE];
     double d = 0.0, r = 0.0;
     for (int i = blockIdx.x * ERR_NT + threadIdx.x; i < n; i += gridDim.x * ERR_NT) {
-        const double ex = (double)bx[i], ey = (double)by[i];
-        const double dx = (double)ax[i] - ex, dy = (double)ay[i] - ey;
+        const float2 av = a[i], bv = b[i];
+        const double ex = (double)bv.x, ey = (double)bv.y;
+        const double dx = (double)av.x - ex, dy = (double)av.y - ey;
         d += dx * dx + dy * dy;
         r += ex * ex + ey * ey;
     }
@@ -41,10 +41,10 @@ __global__ __launch_bounds__(ERR_NT) void k_err_partial(int n, const float *__re
     if (threadIdx.x == 0) part[blockIdx.x] = make_double2(d, r);
 }
 
-double rel_err(fl_ctx *c, int n, const float *ax, const float *ay, const float *bx, const float *by)
+double rel_err(fl_ctx *c, int n, const float2 *a, const float2 *b)
 {
     double2 *part = ws<double2>(c, "tune_part", ERR_BLOCKS);
-    hipLaunchKernelGGL(k_err_partial, dim3(ERR_BLOCKS), dim3(ERR_NT), 0, c->stream, n, ax, ay, bx, by, part);
+    hipLaunchKernelGGL(k_err_partial, dim3(ERR_BLOCKS), dim3(ERR_NT), 0, c->stream, n, a, b, part);
     FL_LAUNCH_CHECK();
     std::vector<double2> h(ERR_BLOCKS);
     FL_CHECK_HIP(hipMemcpyAsync(h.data(), part, sizeof(double2) * ERR_BLOCKS, hipMemcpyDeviceToHost, c->stream));
@@ -134,8 +134,8 @@ static void autotune(fl_ctx *c, int32_t n, const float *x, const float *y, const
         FL_REQUIRE(sizes[k] >= 2 && sizes[k] <= n, "fl_autotune: sizes must be in [2, n]");
         FL_REQUIRE(k == 0 || sizes[k] > sizes[k - 1], "fl_autotune: sizes must be ascending");
     }
-    float *ex = ws<float>(c, "tune_ex", n), *ey = ws<float>(c, "tune_ey", n);
-    float *fx = ws<float>(c, "tune_fx", n), *fy = ws<float>(c, "tune_fy", n);
+    float2 *ex = ws<float2>(c, "tune_ex", n);
+    float2 *fx = ws<float2>(c, "tune_fx", n);
     const int bits = 16;
     std::vector<double> t_exact(n_sizes), t_fmm(n_sizes);
     fl_tuning t{};
@@ -144,7 +144,7 @@ static void autotune(fl_ctx *c, int32_t n, const float *x, const float *y, const
     for (int k = 0; k < n_sizes; ++k) {
         const int s = sizes[k];
         const Segs sg = segs_single(c, s);
-        t_exact[k] = time_median(c, reps, [&] { exact_repulsion(c, sg, x, y, deg, 1.f, ex, ey); });
+        t_exact[k] = time_median(c, reps, [&] { exact_repulsion(c, sg, x, y, deg, 1.f, ex); });
         samples.push_back(fl_tune_sample{s, 0, 0, 0, 1, t_exact[k], 0.0});
         double best = INFINITY, best_err = INFINITY, closest = INFINITY, closest_ms = INFINITY;
         int bp = 8, bl = 64, bn = 1, cp = 16, cl = 16, cn = 1;
@@ -152,9 +152,9 @@ static void autotune(fl_ctx *c, int32_t n, const float *x, const float *y, const
             for (int leaf : TUNE_LEAF) {
                 for (int lanes : TUNE_LANES) {
                     const double ms = time_median(
-                        c, reps, [&] { fmm_repulsion(c, sg, x, y, deg, p, leaf, bits, lanes, 1.f, fx, fy); });
+                        c, reps, [&] { fmm_repulsion(c, sg, x, y, deg, p, leaf, bits, lanes, 1.f, fx); });
                     if (tree_error_bits(c, true)) throw Error(FL_EHIP, "FMM capacity guard tripped while tuning");
-                    const double e = rel_err(c, s, fx, fy, ex, ey);
+                    const double e = rel_err(c, s, fx, ex);
                     const int ok = e <= max_rel_err ? 1 : 0;
                     samples.push_back(fl_tune_sample{s, p, leaf, lanes, ok, ms, e});
                     if (ok && ms < best) {

@@ -25,7 +25,13 @@
 //             sources are read at wave-uniform addresses (scalar loads, SGPR
 //             operands: no per-lane memory traffic in the pair loop).  Leaves
 //             of at most 32 (16) targets run 2 (4) lane groups on interleaved
-//             sources, combined with xor shuffles (fixed order).
+//             sources, staged 64 at a time in LDS and read there by each
+//             group (no per-pair selects); the groups are combined with xor
+//             shuffles (fixed order).
+//
+// Launch shapes: P2M, M2L and the evaluation launch about one wave per leaf
+// (or pair of cells) instead of a fixed stride of several per wave; the cost
+// per leaf varies a lot, and the dispatcher balances short waves better.
 #include <algorithm>
 
 #include "fl_fmm.h"
@@ -436,9 +442,11 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                                               const int32_t *__restrict__ leaf_cell, float kr,
                                               float2 *__restrict__ fr)
 {
+    __shared__ float4 stage[4][WAVE + 4];  // per wave: sources of the small-leaf path, zero-mass padded
     const int nleaves = t.counts[1];
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
+    float4 *sw = stage[threadIdx.x / WAVE];
     const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
     for (int li = first; li < nleaves; li += gridDim.x * wpb) {
         const int c = leaf_cell[li];
@@ -458,8 +466,8 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
             for (int ue = u0; ue < u1; ++ue) {
                 const int2 rg = U[ue];
                 const int sb = rg.x, se = rg.y;
-                int j = sb;
                 if (lg == 0) {
+                    int j = sb;
                     for (; j + 4 <= se; j += 4) {
                         const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
                         FL_P2P_PAIR(s0.x, s0.y, s0.z)
@@ -471,27 +479,32 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                         const float4 s0 = part[j];
                         FL_P2P_PAIR(s0.x, s0.y, s0.z)
                     }
-                } else if (lg == 1) {
-                    const bool hi = grp != 0;
-                    for (; j + 4 <= se; j += 4) {
-                        const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
-                        FL_P2P_PAIR(hi ? s1.x : s0.x, hi ? s1.y : s0.y, hi ? s1.z : s0.z)
-                        FL_P2P_PAIR(hi ? s3.x : s2.x, hi ? s3.y : s2.y, hi ? s3.z : s2.z)
-                    }
-                    for (; j + 2 <= se; j += 2) {
-                        const float4 s0 = part[j], s1 = part[j + 1];
-                        FL_P2P_PAIR(hi ? s1.x : s0.x, hi ? s1.y : s0.y, hi ? s1.z : s0.z)
-                    }
-                    if (j < se) {
-                        const float4 s0 = part[j];
-                        FL_P2P_PAIR(s0.x, s0.y, hi ? 0.f : s0.z)  // odd tail: lower half only
-                    }
                 } else {
-                    // four groups: each lane loads its own source (tiny leaves only)
-                    for (; j < se; j += 4) {
-                        const int jj = j + grp;
-                        const float4 s0 = part[jj < se ? jj : j];
-                        FL_P2P_PAIR(s0.x, s0.y, jj < se ? s0.z : 0.f)
+                    // 2 or 4 lane groups on interleaved sources: the wave stages
+                    // up to 64 sources in LDS with one coalesced load, and each
+                    // group reads its own source (an LDS broadcast, no selects)
+                    const int G = 1 << lg;
+                    for (int j0 = sb; j0 < se; j0 += WAVE) {
+                        const int ns = min(WAVE, se - j0);
+                        float4 v = part[j0 + (lane < ns ? lane : 0)];
+                        const float4 pad = make_float4(v.x, v.y, 0.f, 0.f);  // a source of mass 0 adds 0
+                        wave_lds_sync();  // the previous chunk has been read
+                        sw[lane] = lane < ns ? v : pad;
+                        if (lane < 4) sw[WAVE + lane] = pad;
+                        wave_lds_sync();
+                        int k = 0;
+                        for (; k + 3 * G < ns; k += 4 * G) {  // four LDS reads in flight
+                            const float4 s0 = sw[k + grp], s1 = sw[k + G + grp], s2 = sw[k + 2 * G + grp],
+                                         s3 = sw[k + 3 * G + grp];
+                            FL_P2P_PAIR(s0.x, s0.y, s0.z)
+                            FL_P2P_PAIR(s1.x, s1.y, s1.z)
+                            FL_P2P_PAIR(s2.x, s2.y, s2.z)
+                            FL_P2P_PAIR(s3.x, s3.y, s3.z)
+                        }
+                        for (; k < ns; k += G) {  // k + grp < ns + G - 1 <= WAVE + 3
+                            const float4 s0 = sw[k + grp];
+                            FL_P2P_PAIR(s0.x, s0.y, s0.z)
+                        }
                     }
                 }
             }
@@ -560,7 +573,7 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float2
         const bool fresh = it == c->bufs.end() || !it->second.p;
         float2 *T = ws<float2>(c, tn.c_str(), 4 * (P + 1) * (P + 1));
         if (fresh) hipLaunchKernelGGL(k_m2m_table<P>, dim3(1), dim3(256), 0, c->stream, T);
-        hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(lcap, 4, 2048)), dim3(256), 0, c->stream, tv,
+        hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(lcap, 4, 16384)), dim3(256), 0, c->stream, tv,
                            (const float4 *)t.part, (const int32_t *)t.leaf_cell, M);
         const int64_t nsub = (int64_t)t.s.K << (2 * M2M_CUT);
         hipLaunchKernelGGL(k_m2m_sub<P>, dim3((unsigned)std::min<int64_t>(nsub, 2048)), dim3(256), 0, c->stream, tv,
@@ -571,14 +584,17 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float2
     }
     {
         PhaseTimer pt(c, FL_PH_M2L);
-        hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(cap, 8, 2048)), dim3(256), 0, c->stream, tv,
+        hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(cap, 8, 16384)), dim3(256), 0, c->stream, tv,
                            (const float4 *)t.part, M, L.offVX, L.V, L.X, Lp);
         hipLaunchKernelGGL(k_l2l<P>, dim3(gl), dim3(256), 0, c->stream, tv, Lp, Ll);
         FL_LAUNCH_CHECK();
     }
     {
         PhaseTimer pt(c, FL_PH_EVAL);
-        const unsigned ge = grid_for(lcap, 4, 2048);  // 4 waves per block
+        // about one wave per leaf (4 waves per block): leaves differ a lot in
+        // cost, and the dispatcher balances single-leaf waves far better than
+        // a fixed stride of several leaves per wave
+        const unsigned ge = grid_for(lcap, 4, 16384);
         hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, M, Ll, L.offUW,
                            (const int2 *)L.U, (const int32_t *)L.nU, L.W, (const int32_t *)t.beg,
                            (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr, fr);

@@ -14,7 +14,8 @@
 //   skey[n]     uint32 Morton keys, sorted
 //   cells       depth-first pre-order (sorted by (begin, level)); per cell:
 //               level, ixy (ix | iy << 16), begin, end, parent, child (int4,
-//               -1 = empty quadrant), leafidx (-1 for internal cells)
+//               -1 = empty quadrant), leafidx (-1 for internal cells), skip
+//               (first cell after its subtree: a subtree is [id, skip))
 //   leaves      leaf_cell[nleaves] in Morton order (a leaf's index = the
 //               index of its first particle among the "cell-start" particles)
 //   hash        (system, level, ix, iy) -> cell id, open addressing,
@@ -64,6 +65,7 @@ struct TreeBufs {
     int32_t *lvl = nullptr;      // [cells_cap]
     uint32_t *ixy = nullptr;
     int32_t *beg = nullptr, *end = nullptr, *par = nullptr, *leafidx = nullptr;
+    int32_t *skip = nullptr;       // [cells_cap] first cell after the cell's subtree (pre-order)
     int4 *child = nullptr;
     int32_t *leaf_cell = nullptr;  // [leaves_cap]
     uint64_t *start_key = nullptr;  // system << 32 | Morton key of each cell-start particle
@@ -94,7 +96,7 @@ struct TreeView {
     const float4 *part;
     const int32_t *lvl;
     const uint32_t *ixy;
-    const int32_t *beg, *end, *par, *leafidx;
+    const int32_t *beg, *end, *par, *leafidx, *skip;
     const int4 *child;
     const int32_t *leaf_cell;
     const int32_t *counts;
@@ -106,10 +108,10 @@ struct TreeView {
 
 inline TreeView view(const TreeBufs &t)
 {
-    return TreeView{t.n,        t.bits,     t.leaf,      t.s.K,    t.s.cbits, t.s.coff,  t.ccomp,
-                    t.root,     t.part,     t.lvl,       t.ixy,    t.beg,     t.end,     t.par,
-                    t.leafidx,  t.child,    t.leaf_cell, t.counts, t.hkey,    t.hval,    t.epoch,
-                    t.hash_cap};
+    return TreeView{t.n,       t.bits,  t.leaf,      t.s.K,    t.s.cbits, t.s.coff, t.ccomp,
+                    t.root,    t.part,  t.lvl,       t.ixy,    t.beg,     t.end,    t.par,
+                    t.leafidx, t.skip,  t.child,     t.leaf_cell, t.counts, t.hkey, t.hval,
+                    t.epoch,   t.hash_cap};
 }
 
 // Capacities that no input can exceed (see the capacity notes in fl_tree.hip).

@@ -356,6 +356,18 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int n, uint64_
     return lo;
 }
 
+// first cell whose first particle is >= v (cells are sorted by begin)
+__device__ __forceinline__ int first_cell_from(const int32_t *beg, int ncells, int v)
+{
+    int lo = 0, hi = ncells;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (beg[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, const int64_t *__restrict__ off2,
                              TreeBufs t)
 {
@@ -366,7 +378,9 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
     int l = t.lvl[id];
     const int comp = t.ccomp ? t.ccomp[id] : 0;
     if (l == 0) {
-        t.end[id] = t.s.K > 1 ? t.s.coff[comp + 1] : n;
+        const int e0 = t.s.K > 1 ? t.s.coff[comp + 1] : n;
+        t.end[id] = e0;
+        t.skip[id] = first_cell_from(t.beg, ncells, e0);
         return;
     }
     int k = t.beg[id];
@@ -377,7 +391,9 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
     const uint64_t cs = (uint64_t)(uint32_t)comp << 32;
     uint64_t T = cs + (((uint64_t)pre + 1ull) << sh);
     int j = lower_bound_u64(t.start_key, nleaves, T);
-    t.end[id] = j < nleaves ? t.start_pos[j] : n;
+    const int eid = j < nleaves ? t.start_pos[j] : n;
+    t.end[id] = eid;
+    t.skip[id] = first_cell_from(t.beg, ncells, eid);
     int p = t.par[id];
     if (p == -2) {
         uint64_t Tp = cs | ((uint64_t)(pre >> 2) << (sh + 2));
@@ -498,22 +514,20 @@ __device__ void uw_square(const TreeView &t, int64_t H, uint64_t ep, int comp, i
         if (!ring_seen_before(t, N, l, cx, cy, side, dx, dy)) sk.U(N);
         return;
     }
-    int stack[64];
-    int sp = 0;
-    stack[sp++] = N;
-    while (sp > 0) {
-        const int d = stack[--sp];
-        const int4 dc = t.child[d];
-        const int cc[4] = {dc.x, dc.y, dc.z, dc.w};
-        for (int k = 0; k < 4; ++k) {
-            const int s = cc[k];
-            if (s < 0) continue;
-            if (cells_adjacent(t.lvl[s], t.ixy[s], l, cxy)) {
-                if (is_leaf4(t.child[s])) sk.U(s);
-                else if (sp < 64) stack[sp++] = s;
+    // walk N's subtree in pre-order: a descendant adjacent to the cell is
+    // entered (or listed in U if it is a leaf); one that is not goes to W and
+    // its subtree is skipped
+    for (int s = N + 1, e = t.skip[N]; s < e;) {
+        if (cells_adjacent(t.lvl[s], t.ixy[s], l, cxy)) {
+            if (is_leaf4(t.child[s])) {
+                sk.U(s);
+                s = t.skip[s];
             } else {
-                sk.W(s);
+                ++s;
             }
+        } else {
+            sk.W(s);
+            s = t.skip[s];
         }
     }
 }
@@ -616,6 +630,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
 {
     constexpr int STG = LANES > 1 ? FILL_STAGE : 1;  // one lane per cell: no staging
     __shared__ int2 stage[256 / LANES][STG];
+    __shared__ int2 sorted[256 / LANES][STG];
     const int ncells = t.counts[0];
     const int64_t tvx = offVX[ncells], tuw = offUW[t.counts[1]];
     const bool fits = (tvx & 0xFFFFFFFFll) <= v_cap && (tvx >> 32) <= x_cap && (tuw & 0xFFFFFFFFll) <= u_cap &&
@@ -631,6 +646,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
     const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int nw = gridDim.x * (blockDim.x / WAVE);
     int2 *st = stage[threadIdx.x / LANES];
+    int2 *so = sorted[threadIdx.x / LANES];
     unsigned long long pairs = 0;
     for (int c0 = wid * gpw; c0 < ncells; c0 += nw * gpw) {
         const int c = c0 + lane_id() / LANES;
@@ -662,12 +678,41 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (staged) {
+            // rank sort by the group's lanes: entry a goes to the number of
+            // entries ordered before it (by start, ties by position, so the
+            // ranks are a permutation of 0..k-1)
+            for (int a = q; a < k; a += LANES) {
+                const int2 v = st[a];
+                int r = 0;
+                for (int b2 = 0; b2 < k; ++b2) {
+                    const int x = st[b2].x;
+                    r += (x < v.x || (x == v.x && b2 < a)) ? 1 : 0;
+                }
+                so[r] = v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         if (li >= 0 && q == 0) {
-            int64_t src;
-            int m;
+            int64_t src = 0;
+            int m = 0;
             if (staged) {
-                m = sort_merge_ranges(st, k, src);
-                for (int a = 0; a < m; ++a) u0[a] = st[a];
+                // merge touching ranges (already sorted)
+                int2 cur = so[0];
+                src = cur.y - cur.x;
+                for (int a = 1; a < k; ++a) {
+                    const int2 v = so[a];
+                    src += v.y - v.x;
+                    if (cur.y == v.x) {
+                        cur.y = v.y;
+                    } else {
+                        u0[m++] = cur;
+                        cur = v;
+                    }
+                }
+                u0[m++] = cur;
             } else {
                 m = sort_merge_ranges(u0, k, src);
             }
@@ -837,6 +882,7 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     t.end = ws<int32_t>(c, "t_end", cap);
     t.par = ws<int32_t>(c, "t_par", cap);
     t.leafidx = ws<int32_t>(c, "t_leafidx", cap);
+    t.skip = ws<int32_t>(c, "t_skip", cap);
     t.child = ws<int4>(c, "t_child", cap);
     t.leaf_cell = ws<int32_t>(c, "t_leafcell", lcap);
     t.start_key = ws<uint64_t>(c, "t_skey_start", lcap);

@@ -429,10 +429,11 @@ struct FillSink {
     int2 *pU;
     int32_t *pW;
     const int32_t *beg, *end;
+    bool ids;  // U entries as (cell, 0), resolved to particle ranges later
     int nV = 0, nX = 0, nU = 0, nW = 0;
     __device__ void V(int s) { pV[nV++] = s; }
     __device__ void X(int s) { pX[nX++] = s; }
-    __device__ void U(int s) { pU[nU++] = make_int2(beg[s], end[s]); }
+    __device__ void U(int s) { pU[nU++] = ids ? make_int2(s, 0) : make_int2(beg[s], end[s]); }
     __device__ void W(int s) { pW[nW++] = s; }
 };
 
@@ -568,7 +569,7 @@ __device__ __forceinline__ int group_excl(int v)
 // uniform over the wave (the shuffles need all lanes of a group).
 template <int LANES>
 __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__restrict__ cntVX,
-                                                     int64_t *__restrict__ cntUW)
+                                                     int64_t *__restrict__ cntUW, int64_t *__restrict__ lanecnt)
 {
     const int ncells = t.counts[0];
     const int64_t H = hash_size(ncells, t.hash_cap);
@@ -581,6 +582,9 @@ __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__rest
         const int c = c0 + lane_id() / LANES;
         CountSink sk;
         if (c < ncells) enumerate_part<LANES>(t, H, ep, c, q, sk);
+        if (LANES > 1 && c < ncells)
+            lanecnt[(int64_t)c * LANES + q] = (int64_t)sk.nV | ((int64_t)sk.nX << 8) | ((int64_t)sk.nU << 16) |
+                                              ((int64_t)sk.nW << 40);
         const int nV = group_sum<LANES>(sk.nV), nX = group_sum<LANES>(sk.nX);
         const int nU = group_sum<LANES>(sk.nU), nW = group_sum<LANES>(sk.nW);
         if (c < ncells && q == 0) {
@@ -589,6 +593,15 @@ __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__rest
             if (li >= 0) cntUW[li] = (int64_t)(nU + 1) | ((int64_t)nW << 32);  // + the leaf itself
         }
     }
+}
+
+// LDS writes of any lane of a wave visible to the wave's other lanes (LDS
+// operations of a wave complete in order; no wait for global stores).
+__device__ __forceinline__ void lds_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Near-field ranges of a leaf are sorted by start and touching ones merged.
@@ -626,7 +639,8 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                                                     int32_t *__restrict__ nU, int32_t *__restrict__ W,
                                                     unsigned long long *__restrict__ near_pairs, int64_t cap,
                                                     int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap,
-                                                    int64_t w_cap, int32_t *__restrict__ err)
+                                                    int64_t w_cap, int32_t *__restrict__ err,
+                                                    const int64_t *__restrict__ lanecnt)
 {
     constexpr int STG = LANES > 1 ? FILL_STAGE : 1;  // one lane per cell: no staging
     __shared__ int2 stage[256 / LANES][STG];
@@ -658,26 +672,40 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
         const int k = li >= 0 ? (int)((offUW[li + 1] - ou) & 0xFFFFFFFFll) : 0;
         int pV = 0, pX = 0, pU = 0, pW = 0;
         if (LANES > 1) {  // each lane's offsets within its group's lists
-            CountSink cs;
-            if (live) enumerate_part<LANES>(t, H, ep, c, q, cs);
-            pV = group_excl<LANES>(cs.nV);
-            pX = group_excl<LANES>(cs.nX);
-            pU = group_excl<LANES>(cs.nU);
-            pW = group_excl<LANES>(cs.nW);
+            const int64_t lc = live ? lanecnt[(int64_t)c * LANES + q] : 0;
+            pV = group_excl<LANES>((int)(lc & 0xFF));
+            pX = group_excl<LANES>((int)((lc >> 8) & 0xFF));
+            pU = group_excl<LANES>((int)((lc >> 16) & 0xFFFFFF));
+            pW = group_excl<LANES>((int)((lc >> 40) & 0xFFFFFF));
         }
         const bool staged = LANES > 1 && li >= 0 && k <= STG;
         if (live) {
             const int64_t o = offVX[c];
             FillSink sk{V + (o & 0xFFFFFFFFll) + pV, X + (o >> 32) + pX, (staged ? st : u0) + 1 + pU,
-                        W + (ou >> 32) + pW, t.beg, t.end};
+                        W + (ou >> 32) + pW, t.beg, t.end, staged};
             enumerate_part<LANES>(t, H, ep, c, q, sk);
-            if (li >= 0 && q == 0) (staged ? st : u0)[0] = make_int2(t.beg[c], t.end[c]);
+            if (li >= 0 && q == 0) (staged ? st : u0)[0] = staged ? make_int2(c, 0) : make_int2(t.beg[c], t.end[c]);
         }
-        // the group's U entries were written by its lanes (LDS, or global
-        // memory for long lists): make them visible to lane 0
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // the group's U entries were written by its lanes: make them visible
+        // to the group.  Staged lists are in LDS (a wave-level sync suffices);
+        // only when some list of the wave went to global memory does the
+        // wave wait for its global stores
+        if (__ballot(li >= 0 && !staged) != 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else {
+            lds_wave_sync();
+        }
+        if (staged) {
+            // staged entries are cell ids: their particle ranges, loaded by
+            // the group's lanes together (one memory round trip)
+            for (int a = q; a < k; a += LANES) {
+                const int s = st[a].x;
+                st[a] = make_int2(t.beg[s], t.end[s]);
+            }
+        }
+        lds_wave_sync();
         if (staged) {
             // rank sort by the group's lanes: entry a goes to the number of
             // entries ordered before it (by start, ties by position, so the
@@ -692,9 +720,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                 so[r] = v;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        lds_wave_sync();
         if (li >= 0 && q == 0) {
             int64_t src = 0;
             int m = 0;
@@ -720,9 +746,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
             pairs += (unsigned long long)src * (unsigned long long)(t.end[c] - t.beg[c]);
         }
         // lane 0 is done with the stage before the next cell's lanes write it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        lds_wave_sync();
     }
     pairs = wave_sum(pairs);
     if (lane_id() == 0 && pairs) atomicAdd(near_pairs, pairs);
@@ -971,8 +995,9 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     // grid-stride over the cells (their number is known on the device only)
     const bool wide = lanes == 8;
     const unsigned lg = grid_for(cap, wide ? 256 / 8 : 256, 4096);
-    if (wide) hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW);
-    else hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW);
+    int64_t *lanecnt = wide ? ws<int64_t>(c, "l_lanecnt", (size_t)cap * 8) : nullptr;
+    if (wide) hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt);
+    else hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt);
     FL_LAUNCH_CHECK();
     scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
     scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
@@ -980,7 +1005,7 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
     hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
                        (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2),
-                       cap, lcap, L.v_cap, L.x_cap, L.u_cap, L.w_cap, t.counts + 3);
+                       cap, lcap, L.v_cap, L.x_cap, L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt);
     hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, (const int64_t *)L.offVX,
                        (const int64_t *)L.offUW,
                        c->d_stats, t.n);

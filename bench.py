@@ -202,15 +202,17 @@ def precision_study(args, ctx, G, g, fl, orc, np, torch) -> dict:
     return out
 
 
-def tuned_run(args, G, g, fl, np, torch) -> dict:
-    """fl_autotune on the full graph's points (a random order, so that each
-    size is a uniform subsample) for the error bound, then the timed
-    iterations again with FL_REP_AUTO."""
+def tuned_run(args, G, g, fl, np, torch, xl, yl) -> dict:
+    """fl_autotune for the error bound on the points of the laid-out graph
+    (xl, yl: positions after the main run, where hub clusters have formed and
+    the FMM error is larger than on the random start), in a random order so
+    that each size is a uniform subsample; then the timed iterations again,
+    from the start, with FL_REP_AUTO."""
     dev = torch.device("cuda", 0)
     ctx = fl.Context(0)
     order = torch.from_numpy(np.random.default_rng(7).permutation(g.n)).to(dev)
-    xs = torch.from_numpy(g.x).to(dev)[order].contiguous()
-    ys = torch.from_numpy(g.y).to(dev)[order].contiguous()
+    xs = xl[order].contiguous()
+    ys = yl[order].contiguous()
     ds = G.deg[order].contiguous()
     sizes = [s for s in (1024, 4096, 16384, 65536, 262144, 1048576) if s < g.n] + [g.n]
     t0 = time.perf_counter()
@@ -432,7 +434,7 @@ def main() -> int:
                                             f"repulsion p={args.p}, leaf<={args.leaf}), {cs:.1f} s"}
         log(f"cpu oracle: {cs:.1f}s per iteration on {orc.num_threads()} threads")
     if args.tune_err > 0:
-        result["autotuned"] = tuned_run(args, G, g, fl, np, torch)
+        result["autotuned"] = tuned_run(args, G, g, fl, np, torch, x, y)
     if args.precision_sample > 0:
         result["precision"] = precision_study(args, ctx, G, g, fl, orc, np, torch)
     if args.batched_small > 0:

@@ -27,6 +27,9 @@
  *                        near field.  Operators of Greengard & Rokhlin (1987).
  *   orc_kk_*             sec. 3.1: the Kamada-Kawai energy and its
  *                        minimisation (here: localized stress majorization).
+ *   orc_stress,          sec. 4: Kamada-Kawai on the graph whose nodes are
+ *   orc_kk_sweeps        the components, with real edge lengths (sequential
+ *                        localized stress majorization).
  */
 #include <complex.h>
 #include <math.h>
@@ -814,4 +817,53 @@ void orc_kk_steps(int32_t n, const int32_t *dist, double l, int32_t steps, doubl
         memcpy(y, ny, sizeof(double) * (size_t)n);
     }
     free(nx); free(ny);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kamada-Kawai on the graph of components (sec. 4).  The meta-graph has     */
+/* real edge lengths, so d_ij here is the length of the shortest path and     */
+/* the energy is E = sum_{i<j} d_ij^-2 (|p_i - p_j| - d_ij)^2 (no extra       */
+/* length scale).  It is minimised by localized stress majorization in its   */
+/* sequential form: in one sweep, nodes 0, 1, ..., n-1 in turn move to       */
+/*   p_i' = sum_{j!=i} w_ij (p_j + d_ij u_ij) / sum_{j!=i} w_ij               */
+/* using the positions current at that moment (already moved nodes included).*/
+/* Each move minimises a majorizing function of E in p_i alone, so E never   */
+/* increases.  dist is the n*n matrix (row-major, FP64), > 0 off the         */
+/* diagonal.                                                                  */
+/* ------------------------------------------------------------------------ */
+double orc_stress(int32_t n, const double *dist, const double *x, const double *y)
+{
+    double e = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j) {
+            double d = dist[(int64_t)i * n + j];
+            double dx = x[i] - x[j], dy = y[i] - y[j];
+            double r = sqrt(dx * dx + dy * dy) - d;
+            e += r * r / (d * d);
+        }
+    return e;
+}
+
+void orc_kk_sweeps(int32_t n, const double *dist, int32_t sweeps, double *x, double *y)
+{
+    for (int32_t s = 0; s < sweeps; ++s) {
+        for (int32_t i = 0; i < n; ++i) {
+            double sw = 0.0, ax = 0.0, ay = 0.0;
+            for (int32_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d = dist[(int64_t)i * n + j];
+                double w = 1.0 / (d * d);
+                double dx = x[i] - x[j], dy = y[i] - y[j];
+                double r = sqrt(dx * dx + dy * dy);
+                double ux = r > 0.0 ? dx / r : 0.0, uy = r > 0.0 ? dy / r : 0.0;
+                sw += w;
+                ax += w * (x[j] + d * ux);
+                ay += w * (y[j] + d * uy);
+            }
+            if (sw > 0.0) {
+                x[i] = ax / sw;
+                y[i] = ay / sw;
+            }
+        }
+    }
 }

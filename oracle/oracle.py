@@ -73,6 +73,9 @@ def lib():
         L.orc_kk_energy.argtypes = [i32, P, f64, P, P]
         L.orc_kk_energy.restype = f64
         L.orc_kk_steps.argtypes = [i32, P, f64, i32, P, P]
+        L.orc_stress.argtypes = [i32, P, P, P]
+        L.orc_stress.restype = f64
+        L.orc_kk_sweeps.argtypes = [i32, P, i32, P, P]
         L.orc_num_threads.restype = ctypes.c_int
         for nm in ("orc_op_m2m", "orc_op_m2l", "orc_op_l2l"):
             getattr(L, nm).argtypes = [P, P, f64, f64, ctypes.c_int, P, P]
@@ -444,3 +447,192 @@ def rel_err(ax, ay, bx, by) -> float:
     num = np.sqrt(np.sum((_f64(ax) - _f64(bx)) ** 2 + (_f64(ay) - _f64(by)) ** 2))
     den = np.sqrt(np.sum(_f64(bx) ** 2 + _f64(by) ** 2))
     return float(num / den) if den > 0 else float(num)
+
+
+# --- Assembling the component layouts into one figure (sec. 4) ----------------
+#
+# Readings taken where the paper is silent:
+#
+# * density: a component's nodes are taken to fill a uniform disc with the
+#   same second moment about their centroid.  A uniform disc of radius a has
+#   mean squared distance a^2/2 from its centre, so the equivalent disc of a
+#   component whose RMS distance from its centroid is rho has area
+#   2 pi rho^2; the component is scaled about its centroid by s so that
+#   n / (2 pi (s rho)^2) equals the target density.  rho = 0 (one node, or all
+#   nodes coincident): s = 1.
+# * diameter: twice the radius R of the smallest circle about the centroid
+#   that holds every node, so a meta-edge is R_a + R_b + gap long.
+# * "largest" component: the most nodes; on a tie the one earliest in the
+#   order.
+# * "small enough" / "divide it": the order is cut into consecutive groups of
+#   at most max_group components; each group gets its own meta-graph (built
+#   by the same rule inside the group) and Kamada-Kawai layout; the groups,
+#   in the order they were cut, are then the components of the next level
+#   (their node counts add up; centre = node-weighted centroid of their
+#   members; radius = the smallest circle about that centre holding the
+#   members' circles), until one group remains.
+# * starting layout of a group's Kamada-Kawai: item t at distance d(0, t)
+#   from the origin at angle 2 pi t / g (the first item at the origin).
+# * the energy of a meta-graph with real edge lengths has no extra length
+#   scale and is minimised by sequential localized stress majorization
+#   (orc_kk_sweeps); the finished drawing is translated so that the centroid
+#   of all nodes is the origin.
+
+
+@dataclasses.dataclass
+class AssembleParams:
+    density: float = 1.0   # target nodes per unit area
+    gap: float = 1.0       # constant added to every meta-edge length (> 0)
+    max_group: int = 256   # largest meta-graph laid out in one piece
+    sweeps: int = 100      # majorization sweeps per meta-graph
+
+
+def component_frames(x, y, comp_offsets, density: float):
+    """Centroid (K, 2), scale s (K) and radius R after scaling (K) of every
+    component (node ranges comp_offsets), per the density reading above."""
+    x, y = _f64(x), _f64(y)
+    off = np.asarray(comp_offsets, dtype=np.int64)
+    K = off.shape[0] - 1
+    cen = np.zeros((K, 2))
+    scale = np.ones(K)
+    rad = np.zeros(K)
+    for k in range(K):
+        a, b = off[k], off[k + 1]
+        n = b - a
+        cx, cy = np.sum(x[a:b]) / n, np.sum(y[a:b]) / n
+        r2 = (x[a:b] - cx) ** 2 + (y[a:b] - cy) ** 2
+        rho = math.sqrt(np.sum(r2) / n)
+        s = math.sqrt(n / (2.0 * math.pi * density)) / rho if rho > 0.0 else 1.0
+        cen[k] = (cx, cy)
+        scale[k] = s
+        rad[k] = s * math.sqrt(np.max(r2))
+    return cen, scale, rad
+
+
+def meta_tree(weight, radius, gap: float):
+    """Meta-graph of one group, items in their (random) order: item t > 0 is
+    linked to the largest of items 0..t-1 by an edge of half the two
+    diameters summed plus gap.  Returns (parent, edge length); parent[0] = -1."""
+    w = np.asarray(weight)
+    R = _f64(radius)
+    g = w.shape[0]
+    parent = np.full(g, -1, dtype=np.int64)
+    elen = np.zeros(g)
+    for t in range(1, g):
+        q = int(np.argmax(w[:t]))  # first of the largest
+        parent[t] = q
+        elen[t] = (2.0 * R[t] + 2.0 * R[q]) / 2.0 + gap
+    return parent, elen
+
+
+def tree_distances(parent, elen) -> np.ndarray:
+    """All-pairs shortest path lengths of the weighted meta-graph by the
+    paper's all-pairs algorithm (Floyd-Warshall, sec. 3.1)."""
+    g = len(parent)
+    d = np.full((g, g), np.inf)
+    np.fill_diagonal(d, 0.0)
+    for t in range(g):
+        if parent[t] >= 0:
+            d[t, parent[t]] = d[parent[t], t] = elen[t]
+    for k in range(g):
+        d = np.minimum(d, d[:, k:k + 1] + d[k:k + 1, :])
+    return d
+
+
+def meta_initial(dist):
+    """Starting positions of a group's Kamada-Kawai (reading above)."""
+    g = dist.shape[0]
+    t = np.arange(g)
+    ang = 2.0 * math.pi * t / g
+    return dist[0] * np.cos(ang), dist[0] * np.sin(ang)
+
+
+def stress(dist, x, y) -> float:
+    d = _f64(dist)
+    return float(lib().orc_stress(d.shape[0], _p(d), _p(_f64(x)), _p(_f64(y))))
+
+
+def kk_sweeps(dist, x, y, sweeps: int = 1):
+    d = _f64(dist)
+    x, y = _f64(x).copy(), _f64(y).copy()
+    lib().orc_kk_sweeps(d.shape[0], _p(d), int(sweeps), _p(x), _p(y))
+    return x, y
+
+
+@dataclasses.dataclass
+class Assembly:
+    x: np.ndarray          # assembled positions
+    y: np.ndarray
+    centroid: np.ndarray   # (K, 2) centroid of each component before
+    scale: np.ndarray      # (K,)
+    radius: np.ndarray     # (K,) after scaling
+    shift: np.ndarray      # (K, 2): node p of component k goes to s_k (p - c_k) + shift_k
+    parent: np.ndarray     # (K,) component linked to in the first-level meta-graph, -1 for a group's first
+    levels: int
+    groups: int            # groups over all levels
+
+
+def assemble(x, y, comp_offsets, order, prm: AssembleParams = AssembleParams()) -> Assembly:
+    """Rescale every component to the common density, then place the
+    components by Kamada-Kawai on the meta-graph (sec. 4), level by level as
+    described above.  order: the random order, a permutation of 0..K-1."""
+    off = np.asarray(comp_offsets, dtype=np.int64)
+    K = off.shape[0] - 1
+    order = np.asarray(order, dtype=np.int64)
+    assert sorted(order.tolist()) == list(range(K)), "order must be a permutation"
+    assert prm.gap > 0.0 and prm.density > 0.0 and prm.max_group >= 2
+    cen, scale, rad = component_frames(x, y, off, prm.density)
+    nodes = (off[1:] - off[:-1]).astype(np.int64)
+
+    # level items: weight (nodes), centre before placement, radius
+    w_it = nodes[order]
+    c_it = np.zeros((K, 2))  # scaled components sit about their own centroid
+    r_it = rad[order]
+    levels = []  # per level: (group start offsets, placed positions P, centres C)
+    parent0 = np.full(K, -1, dtype=np.int64)
+    n_groups = 0
+    while True:
+        m = w_it.shape[0]
+        starts = list(range(0, m, prm.max_group)) + [m]
+        P = np.zeros((m, 2))
+        nw, nc, nr = [], [], []
+        for a, b in zip(starts[:-1], starts[1:]):
+            par, el = meta_tree(w_it[a:b], r_it[a:b], prm.gap)
+            if not levels:
+                for t in range(1, b - a):
+                    parent0[order[a + t]] = order[a + par[t]]
+            D = tree_distances(par, el)
+            px, py = meta_initial(D)
+            px, py = kk_sweeps(D, px, py, prm.sweeps)
+            P[a:b, 0], P[a:b, 1] = px, py
+            W = np.sum(w_it[a:b])
+            C = (np.sum(w_it[a:b] * px) / W, np.sum(w_it[a:b] * py) / W)
+            Rg = np.max(np.hypot(px - C[0], py - C[1]) + r_it[a:b])
+            nw.append(W)
+            nc.append(C)
+            nr.append(Rg)
+        n_groups += len(starts) - 1
+        levels.append((starts, P, c_it))
+        if len(starts) == 2:
+            top_centre = np.array(nc[0])
+            break
+        w_it, c_it, r_it = np.array(nw, dtype=np.int64), np.array(nc), np.array(nr)
+
+    # translations, top down: an item moves by (placement - own centre) plus
+    # the move of the group holding it; the whole drawing by -centroid
+    F = -top_centre[None, :]
+    for starts, P, C in reversed(levels):
+        m = P.shape[0]
+        grp = np.zeros(m, dtype=np.int64)
+        for gi, (a, b) in enumerate(zip(starts[:-1], starts[1:])):
+            grp[a:b] = gi
+        F = P - C + F[grp]
+    shift = np.zeros((K, 2))
+    shift[order] = F
+
+    xs, ys = _f64(x).copy(), _f64(y).copy()
+    for k in range(K):
+        a, b = off[k], off[k + 1]
+        xs[a:b] = scale[k] * (xs[a:b] - cen[k, 0]) + shift[k, 0]
+        ys[a:b] = scale[k] * (ys[a:b] - cen[k, 1]) + shift[k, 1]
+    return Assembly(xs, ys, cen, scale, rad, shift, parent0, len(levels), n_groups)

@@ -277,6 +277,64 @@ fl_status fl_layout(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_
                     int32_t kk_max_nodes, int32_t fmm_min_nodes, fl_layout_stats *stats);
 
 /* ------------------------------------------------------------------------
+ * Assembly of the component layouts into one drawing (sec. 4): every
+ * component is rescaled to a common density, the components become the
+ * nodes of a tree ("meta-graph": in a random order, each component is linked
+ * to the largest one before it by an edge of half the two diameters summed
+ * plus a constant), and the tree is laid out by Kamada-Kawai; a tree too
+ * large for one layout is cut into groups that are laid out separately and
+ * then assembled the same way.  Definitions (the paper leaves them open):
+ *   centroid c_k and RMS distance rho_k of component k's nodes from it;
+ *   scale s_k = sqrt(n_k / (2 pi density)) / rho_k (1 when rho_k = 0): the
+ *     nodes then fill an equivalent uniform disc (same second moment) at the
+ *     target density;
+ *   radius R_k = s_k max_i |p_i - c_k| (diameter 2 R_k);
+ *   "largest" = most nodes, the earliest in the order on a tie;
+ *   groups: the order is cut into consecutive runs of max_group components,
+ *     each with its own meta-graph; the runs, in order, are the components of
+ *     the next level (nodes added up, centre = node-weighted centroid,
+ *     radius = smallest circle about it holding the members' circles), until
+ *     one run remains;
+ *   a group's layout starts with item t at distance d(0, t) from the origin
+ *     at angle 2 pi t / g and runs `sweeps` sweeps of sequential localized
+ *     stress majorization of E = sum_{i<j} d_ij^-2 (|p_i - p_j| - d_ij)^2
+ *     (d = path length in the meta-graph): items 0..g-1 in turn move to
+ *     sum_{j!=i} w_ij (p_j + d_ij u_ij) / sum_{j!=i} w_ij, w_ij = d_ij^-2;
+ *   finally node i of component k goes to s_k (p_i - c_k) + shift_k, with the
+ *     drawing's node centroid at the origin.
+ * Precision: frames and group centres FP64; the meta-graph layout FP32.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double density;     /* target nodes per unit area (> 0) */
+    double gap;         /* constant added to every meta-edge length (> 0) */
+    int32_t max_group;  /* largest meta-graph laid out in one piece, 2..256 */
+    int32_t sweeps;     /* majorization sweeps per meta-graph (>= 0) */
+} fl_assemble_params;
+
+/* Defaults: density 1, gap 1, max_group 256, sweeps 100. */
+void fl_assemble_default_params(fl_assemble_params *prm);
+
+typedef struct {
+    int32_t n_comp, levels, groups;
+    double ms;
+} fl_assemble_stats;
+
+/* Assemble, in place on x, y [n], the components given by label [n] (device,
+ * int32 in [0, n), e.g. fl_components' labels; component k = the k-th
+ * smallest distinct label, n_comp of them).  order [host, n_comp] is the
+ * random order: a permutation of 0..n_comp-1 drawn by the caller.
+ * Optional device outputs (NULL: not written):
+ *   frame [n_comp * 6] FP64: c_k (x, y), s_k, R_k, shift_k (x, y);
+ *   parent [n_comp]: the component linked to in the first-level meta-graph,
+ *     -1 for the first of each group.
+ * stats [host] may be NULL.  Synchronises.  FL_EINVAL for a label outside
+ * [0, n), a count of distinct labels other than n_comp, an order that is not
+ * a permutation, or parameters out of range. */
+fl_status fl_assemble(fl_ctx *ctx, int32_t n, const int32_t *label, int32_t n_comp, const int32_t *order, float *x,
+                      float *y, const fl_assemble_params *prm, double *frame, int32_t *parent,
+                      fl_assemble_stats *stats);
+
+/* ------------------------------------------------------------------------
  * Autotuning (project addition; the paper fixes no FMM parameters).
  * The table maps a system size to exact or FMM repulsion and the FMM's
  * expansion order p and leaf size; FL_REP_AUTO reads it.

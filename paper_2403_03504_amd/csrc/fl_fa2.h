@@ -35,6 +35,18 @@ struct FA2Batch {
 void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &b, int iters, int32_t *flags);
 
 int32_t components(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t *label);
+
+// Nodes stably sorted by label (labels in [0, n)): perm[r] = node at sorted
+// position r; flag[r] = 1 where a new label starts; pos = exclusive scan of
+// flag; d_off[k] = first position of the k-th smallest label, d_off[K] = n;
+// off = the same offsets on the host.  Throws FL_EINVAL unless there are
+// exactly n_labels distinct labels.  Synchronises.
+struct LabelSort {
+    const int32_t *perm = nullptr, *flag = nullptr, *pos = nullptr;
+    int32_t *d_off = nullptr;
+    std::vector<int32_t> off;
+};
+LabelSort sort_by_label(fl_ctx *c, int32_t n, const int32_t *label, int32_t n_labels);
 void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,
                       const int32_t *row_ptr, const int32_t *col, float *x, float *y, double l, int steps);
 

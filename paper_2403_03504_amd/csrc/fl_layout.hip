@@ -117,6 +117,37 @@ double ms_since(std::chrono::steady_clock::time_point t0)
 
 }  // namespace
 
+LabelSort sort_by_label(fl_ctx *c, int32_t n, const int32_t *label, int32_t n_labels)
+{
+    const unsigned g = grid_for(n, 256);
+    uint32_t *k0 = ws<uint32_t>(c, "lay_k0", n), *k1 = ws<uint32_t>(c, "lay_k1", n);
+    int32_t *i0 = ws<int32_t>(c, "lay_i0", n), *i1 = ws<int32_t>(c, "lay_i1", n);
+    hipLaunchKernelGGL(k_label_keys, dim3(g), dim3(256), 0, c->stream, label, n, k0, i0);
+    FL_LAUNCH_CHECK();
+    int nbits = 1;
+    while (nbits < 31 && ((int64_t)1 << nbits) < n) ++nbits;
+    const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, nbits);
+    const uint32_t *skey = alt ? k1 : k0;
+    LabelSort r;
+    r.perm = alt ? i1 : i0;
+    int32_t *flag = ws<int32_t>(c, "lay_flag", n);
+    int32_t *pos = ws<int32_t>(c, "lay_pos", (size_t)n + 1);
+    int32_t *d_off = ws<int32_t>(c, "lay_off", (size_t)n_labels + 1);
+    hipLaunchKernelGGL(k_comp_flags, dim3(g), dim3(256), 0, c->stream, skey, n, flag);
+    scan_excl_i32(c, flag, pos, n);
+    FL_REQUIRE(read_i32(c, pos + n) == n_labels, "the number of distinct labels differs from the component count");
+    hipLaunchKernelGGL(k_comp_offsets, dim3(g), dim3(256), 0, c->stream, flag, pos, n, d_off);
+    FL_LAUNCH_CHECK();
+    r.flag = flag;
+    r.pos = pos;
+    r.d_off = d_off;
+    r.off.resize((size_t)n_labels + 1);
+    FL_CHECK_HIP(hipMemcpyAsync(r.off.data(), d_off, sizeof(int32_t) * ((size_t)n_labels + 1), hipMemcpyDeviceToHost,
+                                c->stream));
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    return r;
+}
+
 void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *deg, float *x, float *y,
             const fl_fa2_params *fa2, int32_t fa2_iters, const fl_kk_params *kk, int32_t kk_max_nodes,
             int32_t fmm_min_nodes, fl_layout_stats *stats)
@@ -129,25 +160,9 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
     const unsigned g = grid_for(n, 256);
     int32_t *label = ws<int32_t>(c, "lay_label", n);
     const int32_t ncomp = components(c, n, row_ptr, col, label);
-    uint32_t *k0 = ws<uint32_t>(c, "lay_k0", n), *k1 = ws<uint32_t>(c, "lay_k1", n);
-    int32_t *i0 = ws<int32_t>(c, "lay_i0", n), *i1 = ws<int32_t>(c, "lay_i1", n);
-    hipLaunchKernelGGL(k_label_keys, dim3(g), dim3(256), 0, c->stream, label, n, k0, i0);
-    FL_LAUNCH_CHECK();
-    int nbits = 1;
-    while (nbits < 31 && ((int64_t)1 << nbits) < n) ++nbits;
-    const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, nbits);
-    const uint32_t *skey = alt ? k1 : k0;
-    const int32_t *perm = alt ? i1 : i0;
-    int32_t *flag = ws<int32_t>(c, "lay_flag", n);
-    int32_t *pos = ws<int32_t>(c, "lay_pos", (size_t)n + 1);
-    int32_t *d_off = ws<int32_t>(c, "lay_off", (size_t)ncomp + 1);
-    hipLaunchKernelGGL(k_comp_flags, dim3(g), dim3(256), 0, c->stream, skey, n, flag);
-    scan_excl_i32(c, flag, pos, n);
-    hipLaunchKernelGGL(k_comp_offsets, dim3(g), dim3(256), 0, c->stream, flag, pos, n, d_off);
-    FL_LAUNCH_CHECK();
-    std::vector<int32_t> off(ncomp + 1);
-    FL_CHECK_HIP(hipMemcpyAsync(off.data(), d_off, sizeof(int32_t) * (ncomp + 1), hipMemcpyDeviceToHost, c->stream));
-    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    LabelSort ls = sort_by_label(c, n, label, ncomp);
+    const int32_t *perm = ls.perm, *flag = ls.flag, *pos = ls.pos, *d_off = ls.d_off;
+    const std::vector<int32_t> &off = ls.off;
 
     // classify, then regroup: ForceAtlas2 groups (one per distinct resolved
     // repulsion configuration) first, then the Kamada-Kawai components, then

@@ -36,7 +36,8 @@ EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_syn
             "fl_kk_steps", "fl_kk_layout", "fl_layout", "fl_server_create", "fl_server_create_fake",
             "fl_server_submit", "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release",
             "fl_server_cancel", "fl_server_stats_get", "fl_server_last_error", "fl_server_destroy",
-            "fl_default_tuning", "fl_set_tuning", "fl_get_tuning", "fl_autotune", "fl_server_set_tuning")
+            "fl_default_tuning", "fl_set_tuning", "fl_get_tuning", "fl_autotune", "fl_server_set_tuning",
+            "fl_assemble_default_params", "fl_assemble")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELED = 0, 1, 2, 3, 4
 
 
@@ -61,6 +62,16 @@ class _State(ctypes.Structure):
 
 class KKParams(ctypes.Structure):
     _fields_ = [("l", ctypes.c_double), ("steps", ctypes.c_int32)]
+
+
+class AssembleParams(ctypes.Structure):
+    _fields_ = [("density", ctypes.c_double), ("gap", ctypes.c_double), ("max_group", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32)]
+
+
+class AssembleStats(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int32), ("levels", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class LayoutStats(ctypes.Structure):
@@ -149,6 +160,9 @@ _sig = {
     "fl_layout": ([P, _i32, P, P, P, P, P, ctypes.POINTER(FA2Params), _i32, ctypes.POINTER(KKParams), _i32, _i32,
                    ctypes.POINTER(LayoutStats)], _i32),
     "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
+    "fl_assemble_default_params": ([ctypes.POINTER(AssembleParams)], None),
+    "fl_assemble": ([P, _i32, P, _i32, P, P, P, ctypes.POINTER(AssembleParams), P, P,
+                     ctypes.POINTER(AssembleStats)], _i32),
     "fl_default_tuning": ([ctypes.POINTER(Tuning)], None),
     "fl_set_tuning": ([P, ctypes.POINTER(Tuning)], _i32),
     "fl_get_tuning": ([P, ctypes.POINTER(Tuning)], _i32),
@@ -199,6 +213,16 @@ def default_tuning() -> dict:
 def kk_params(**kw) -> KKParams:
     p = KKParams()
     _lib.fl_kk_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def assemble_params(**kw) -> AssembleParams:
+    p = AssembleParams()
+    _lib.fl_assemble_default_params(ctypes.byref(p))
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -397,6 +421,22 @@ class Context:
                                    ctypes.byref(fa2), fa2_iters, ctypes.byref(kk), kk_max_nodes, fmm_min_nodes,
                                    ctypes.byref(st)), "fl_layout")
         return {k: getattr(st, k) for k, _ in LayoutStats._fields_}
+
+    def assemble(self, label: torch.Tensor, n_comp: int, order, x: torch.Tensor, y: torch.Tensor,
+                 params: AssembleParams, frame: torch.Tensor | None = None,
+                 parent: torch.Tensor | None = None) -> dict:
+        """fl_assemble: in place on x, y; order is a host permutation of
+        0..n_comp-1; frame (float64, n_comp*6) and parent (int32, n_comp) are
+        optional device outputs."""
+        o, op = _host_i32(order)
+        if o.shape != (n_comp,):
+            raise ValueError("order must hold n_comp entries")
+        st = AssembleStats()
+        self._check(_lib.fl_assemble(self._h, x.shape[0], _ptr(label, torch.int32), n_comp, op,
+                                     _ptr(x, torch.float32), _ptr(y, torch.float32), ctypes.byref(params),
+                                     _ptr(frame, torch.float64), _ptr(parent, torch.int32), ctypes.byref(st)),
+                    "fl_assemble")
+        return {k: getattr(st, k) for k, _ in AssembleStats._fields_}
 
     def fmm_stats(self, reset: bool = False) -> dict:
         out = (_i64 * 12)()

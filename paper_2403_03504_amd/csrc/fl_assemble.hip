@@ -11,10 +11,11 @@
 //   k_asm_frames   one thread per component: scale and radius, written into
 //                  the component's slot of the first level (its place in the
 //                  random order)
-//   k_asm_level    one wave per group of <= 256 items: meta-graph links by a
-//                  prefix maximum, path lengths in closed form, the starting
-//                  layout, sequential majorization sweeps, then the group's
-//                  node count, centre and radius as an item of the next level
+//   k_asm_level    one workgroup per group of <= 256 items (one wave per 64):
+//                  meta-graph links by a prefix maximum, path lengths in
+//                  closed form, the starting layout, sequential majorization
+//                  sweeps, then the group's node count, centre and radius as
+//                  an item of the next level
 //   k_asm_shift    one thread per item, top level first: its translation
 //   k_asm_place    one wave per tile: p -> s (p - c) + shift
 //   k_asm_export   one thread per component: frames and first-level links
@@ -25,8 +26,10 @@
 // between items i != j is therefore L_i + L_j + |h_i - h_j|, where L is the
 // length of the item's own edge if it hangs off a record (0 for a record) and
 // h the chain length from the group's first item to the item's record, so no
-// distance matrix is stored: each lane keeps four items in registers and a
-// sweep is 256 sequential item moves, each one wave-wide reduction.
+// distance matrix is stored: each lane keeps one item in registers, the
+// moving item is read from LDS, and a sweep is g sequential item moves, each
+// one reduction over the workgroup.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -147,36 +150,61 @@ __global__ __launch_bounds__(256) void k_asm_frames(int K, const int32_t *__rest
     ir[slot] = R;
 }
 
-// One group: items [a, a + g) of the level, g <= ASM_MAX, one wave.
-__global__ __launch_bounds__(WAVE) void k_asm_level(int m, int M, const int32_t *__restrict__ iw,
-                                                    const double *__restrict__ ir, double gap, int sweeps,
-                                                    double2 *__restrict__ P, int32_t *__restrict__ par_out,
-                                                    int32_t *__restrict__ nw, double2 *__restrict__ nc,
-                                                    double *__restrict__ nr)
+// Wave total of v by DPP: inclusive sums inside rows of 16 lanes (row_shr 1,
+// 2, 4, 8; lanes shifted in from outside the row add 0), then the totals of
+// the rows before by row_bcast 15 and 31.  Only lane 63 holds the total.
+__device__ __forceinline__ float dpp_total_in_lane63(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+    return v;
+}
+
+// One group: items [a, a + g) of the level, g <= ASM_MAX, NW waves (item j
+// lives on lane j % 64 of wave j / 64).  Wave 0 builds the meta-graph and the
+// starting layout into LDS; then every item move is one step of all waves:
+// partial sums over their items, a DPP wave total, and (NW > 1) the wave
+// totals exchanged through LDS and added in wave order, so every wave gets
+// the same new position.
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_asm_level(int m, int M, const int32_t *__restrict__ iw,
+                                                         const double *__restrict__ ir, double gap, int sweeps,
+                                                         double2 *__restrict__ P, int32_t *__restrict__ par_out,
+                                                         int32_t *__restrict__ nw, double2 *__restrict__ nc,
+                                                         double *__restrict__ nr)
 {
     __shared__ double Rs[ASM_MAX];
+    __shared__ double hs[ASM_MAX];
+    __shared__ float Ls[ASM_MAX];
+    __shared__ float2 pos[ASM_MAX];
+    __shared__ int32_t ps[ASM_MAX];
+    __shared__ float part[2][NW][2];
     const int grp = blockIdx.x;
     const int a = grp * M;
     const int g = min(M, m - a);
     const int lane = lane_id();
+    const int wv = (int)(threadIdx.x / WAVE);
 
-    int wq[ASM_Q];
-    double Rq[ASM_Q];
-#pragma unroll
-    for (int q = 0; q < ASM_Q; ++q) {
-        const int t = lane + WAVE * q;
-        wq[q] = t < g ? iw[a + t] : 0;
-        Rq[q] = t < g ? ir[a + t] : 0.0;
-        if (t < g) Rs[t] = Rq[q];
-    }
+    for (int t = (int)threadIdx.x; t < g; t += NW * WAVE) Rs[t] = ir[a + t];
     __syncthreads();
-
-    // links: the largest earlier item (first on a tie) is the maximum of
-    // key = nodes << 32 | ~t over the items before t
-    int parq[ASM_Q];
-    bool recq[ASM_Q];
-    {
-        unsigned long long carry = 0ull;
+    if (wv == 0) {
+        int wq[ASM_Q];
+        double Rq[ASM_Q];
+#pragma unroll
+        for (int q = 0; q < ASM_Q; ++q) {
+            const int t = lane + WAVE * q;
+            wq[q] = t < g ? iw[a + t] : 0;
+            Rq[q] = t < g ? Rs[t] : 0.0;
+        }
+        // links: the largest earlier item (first on a tie) is the maximum of
+        // key = nodes << 32 | ~t over the items before t
+        int parq[ASM_Q];
+        bool recq[ASM_Q];
+        unsigned long long kcarry = 0ull;
 #pragma unroll
         for (int q = 0; q < ASM_Q; ++q) {
             const int t = lane + WAVE * q;
@@ -190,95 +218,170 @@ __global__ __launch_bounds__(WAVE) void k_asm_level(int m, int M, const int32_t 
             }
             unsigned long long exc = __shfl_up(inc, 1, WAVE);
             if (lane == 0) exc = 0ull;
-            exc = exc > carry ? exc : carry;
+            exc = exc > kcarry ? exc : kcarry;
             const unsigned long long last = __shfl(inc, WAVE - 1, WAVE);
-            carry = carry > last ? carry : last;
+            kcarry = kcarry > last ? kcarry : last;
             parq[q] = t == 0 ? -1 : (int)(~(unsigned)(exc & 0xFFFFFFFFull));
             recq[q] = t == 0 || key > exc;
         }
-    }
-
-    // edge lengths, leg lengths L and chain positions h (FP64 prefix sum)
-    float Lq[ASM_Q];
-    double hq[ASM_Q], d0q[ASM_Q];
-    {
-        double carry = 0.0;
+        // edge lengths, leg lengths L, chain positions h (FP64 prefix sum),
+        // starting layout
+        double hcarry = 0.0;
 #pragma unroll
         for (int q = 0; q < ASM_Q; ++q) {
             const int t = lane + WAVE * q;
             const double e = (t < g && t > 0) ? Rq[q] + Rs[parq[q]] + gap : 0.0;
-            const double chain = recq[q] ? e : 0.0;
-            const double inc = wave_incl_scan(chain);
-            hq[q] = carry + inc;
-            carry += __shfl(inc, WAVE - 1, WAVE);
+            const double inc = wave_incl_scan(recq[q] ? e : 0.0);
+            const double h = hcarry + inc;
+            hcarry += __shfl(inc, WAVE - 1, WAVE);
             const double leg = recq[q] ? 0.0 : e;
-            Lq[q] = (float)leg;
-            d0q[q] = leg + hq[q];  // path length from item 0
-        }
-    }
-
-    // starting layout
-    float xq[ASM_Q], yq[ASM_Q];
-#pragma unroll
-    for (int q = 0; q < ASM_Q; ++q) {
-        const int t = lane + WAVE * q;
-        double sn, cs;
-        sincos(2.0 * M_PI * (double)t / (double)g, &sn, &cs);
-        xq[q] = t < g ? (float)(d0q[q] * cs) : 0.f;
-        yq[q] = t < g ? (float)(d0q[q] * sn) : 0.f;
-    }
-
-    // sequential majorization sweeps
-    const int nq = (g + WAVE - 1) / WAVE;
-    for (int s = 0; s < sweeps && g > 1; ++s) {
-#pragma unroll
-        for (int q = 0; q < ASM_Q; ++q) {
-            if (q >= nq) break;
-            const int lim = min(WAVE, g - WAVE * q);
-            for (int il = 0; il < lim; ++il) {
-                const int i = WAVE * q + il;
-                const float xi = read_lane(xq[q], il), yi = read_lane(yq[q], il);
-                const float Li = read_lane(Lq[q], il);
-                const double hi = read_lane(hq[q], il);
-                float ax = 0.f, ay = 0.f, sw = 0.f;
-#pragma unroll
-                for (int qq = 0; qq < ASM_Q; ++qq) {
-                    if (qq >= nq) break;
-                    const int j = lane + WAVE * qq;
-                    const bool ok = j < g && j != i;
-                    const float D = Li + Lq[qq] + (float)fabs(hi - hq[qq]);
-                    const float w = ok ? __builtin_amdgcn_rcpf(D * D) : 0.f;
-                    const float dx = xi - xq[qq], dy = yi - yq[qq];
-                    const float r2 = dx * dx + dy * dy;
-                    const float rinv = r2 > 0.f ? rsqrtf(r2) : 0.f;
-                    const float wd = w * D * rinv;
-                    ax += w * xq[qq] + wd * dx;
-                    ay += w * yq[qq] + wd * dy;
-                    sw += w;
-                }
-                ax = wave_sum(ax);
-                ay = wave_sum(ay);
-                sw = wave_sum(sw);
-                if (lane == il) {
-                    xq[q] = ax / sw;
-                    yq[q] = ay / sw;
-                }
+            const double d0 = leg + h;  // path length from item 0
+            double sn, cs;
+            sincos(2.0 * M_PI * (double)t / (double)g, &sn, &cs);
+            if (t < g) {
+                hs[t] = h;
+                Ls[t] = (float)leg;
+                pos[t] = make_float2((float)(d0 * cs), (float)(d0 * sn));
+                ps[t] = parq[q];
             }
         }
     }
+    __syncthreads();
+
+    // sequential majorization sweeps.  Lane j holds item j; the moving item
+    // i comes from registers (one wave) or LDS (several waves), fetched one
+    // move ahead (item i + 1 does not move during move i).  1 / sum_j w_ij is
+    // fixed over the sweeps and computed once.
+    const int j = wv * WAVE + lane;
+    const bool live = j < g;
+    float xj = 0.f, yj = 0.f, Lj = 0.f;
+    double hj = 0.0;
+    if (live) {
+        xj = pos[j].x;
+        yj = pos[j].y;
+        Lj = Ls[j];
+        hj = hs[j];
+    }
+    float rswj = 0.f;  // 1 / sum_k w_jk of item j
+    if (g > 1 && sweeps > 0) {
+        for (int i = 0; i < g; ++i) {
+            float Li;
+            double hi;
+            if constexpr (NW == 1) {
+                Li = read_lane(Lj, i);
+                hi = read_lane(hj, i);
+            } else {
+                Li = Ls[i];
+                hi = hs[i];
+            }
+            float sw = 0.f;
+            if (live && j != i) {
+                const float D = Li + Lj + (float)fabs(hi - hj);
+                sw = __builtin_amdgcn_rcpf(D * D);
+            }
+            sw = dpp_total_in_lane63(sw);
+            if constexpr (NW == 1) {
+                sw = read_lane(sw, WAVE - 1);
+            } else {
+                const int b = i & 1;
+                if (lane == WAVE - 1) part[b][wv][0] = sw;
+                __syncthreads();
+                sw = part[b][0][0];
+#pragma unroll
+                for (int u = 1; u < NW; ++u) sw += part[b][u][0];
+            }
+            if (j == i) rswj = 1.0f / sw;
+        }
+    }
+    for (int s = 0; s < sweeps && g > 1; ++s) {
+        float2 pn;
+        float Ln;
+        double hn;
+        if constexpr (NW > 1) {
+            pn = pos[0];
+            Ln = Ls[0];
+            hn = hs[0];
+        }
+        for (int i = 0; i < g; ++i) {
+            float2 pi;
+            float Li;
+            double hi;
+            if constexpr (NW == 1) {
+                pi = make_float2(read_lane(xj, i), read_lane(yj, i));
+                Li = read_lane(Lj, i);
+                hi = read_lane(hj, i);
+            } else {
+                pi = pn;
+                Li = Ln;
+                hi = hn;
+                const int i1 = i + 1 < g ? i + 1 : 0;
+                pn = pos[i1];
+                Ln = Ls[i1];
+                hn = hs[i1];
+            }
+            float ax = 0.f, ay = 0.f;
+            if (live && j != i) {
+                const float D = Li + Lj + (float)fabs(hi - hj);
+                const float w = __builtin_amdgcn_rcpf(D * D);
+                const float dx = pi.x - xj, dy = pi.y - yj;
+                const float r2 = dx * dx + dy * dy;
+                const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                const float wd = w * D * rinv;
+                ax = w * xj + wd * dx;
+                ay = w * yj + wd * dy;
+            }
+            ax = dpp_total_in_lane63(ax);
+            ay = dpp_total_in_lane63(ay);
+            if constexpr (NW == 1) {
+                ax = read_lane(ax, WAVE - 1);
+                ay = read_lane(ay, WAVE - 1);
+            } else {
+                const int b = i & 1;
+                if (lane == WAVE - 1) {
+                    part[b][wv][0] = ax;
+                    part[b][wv][1] = ay;
+                }
+                __syncthreads();
+                if (j == i) {
+                    ax = part[b][0][0];
+                    ay = part[b][0][1];
+#pragma unroll
+                    for (int u = 1; u < NW; ++u) {
+                        ax += part[b][u][0];
+                        ay += part[b][u][1];
+                    }
+                }
+            }
+            if (j == i) {
+                xj = ax * rswj;
+                yj = ay * rswj;
+                if constexpr (NW > 1) pos[i] = make_float2(xj, yj);
+            }
+        }
+    }
+    if constexpr (NW == 1) {
+        if (live) pos[j] = make_float2(xj, yj);
+    }
+    __syncthreads();
 
     // placements, first-level links, and the group as a next-level item
+    if (wv != 0) return;
     long long W = 0;
     double cx = 0.0, cy = 0.0;
+    float2 pq[ASM_Q];
+    double Rq[ASM_Q];
 #pragma unroll
     for (int q = 0; q < ASM_Q; ++q) {
         const int t = lane + WAVE * q;
+        pq[q] = t < g ? pos[t] : make_float2(0.f, 0.f);
+        Rq[q] = t < g ? Rs[t] : 0.0;
         if (t < g) {
-            P[a + t] = make_double2((double)xq[q], (double)yq[q]);
-            if (par_out) par_out[a + t] = parq[q] < 0 ? -1 : a + parq[q];
-            W += wq[q];
-            cx += (double)wq[q] * (double)xq[q];
-            cy += (double)wq[q] * (double)yq[q];
+            const int wt = iw[a + t];
+            P[a + t] = make_double2((double)pq[q].x, (double)pq[q].y);
+            if (par_out) par_out[a + t] = ps[t] < 0 ? -1 : a + ps[t];
+            W += wt;
+            cx += (double)wt * (double)pq[q].x;
+            cy += (double)wt * (double)pq[q].y;
         }
     }
     W = wave_sum(W);
@@ -289,7 +392,7 @@ __global__ __launch_bounds__(WAVE) void k_asm_level(int m, int M, const int32_t 
     for (int q = 0; q < ASM_Q; ++q) {
         const int t = lane + WAVE * q;
         if (t < g) {
-            const double dx = (double)xq[q] - cx, dy = (double)yq[q] - cy;
+            const double dx = (double)pq[q].x - cx, dy = (double)pq[q].y - cy;
             rg = fmax(rg, sqrt(dx * dx + dy * dy) + Rq[q]);
         }
     }
@@ -465,7 +568,10 @@ void assemble_ranges(fl_ctx *c, const std::vector<int32_t> &off, const int32_t *
     FL_LAUNCH_CHECK();
     for (int l = 0; l < L; ++l) {
         const unsigned ng = (unsigned)((m[l] + M - 1) / M);
-        hipLaunchKernelGGL(k_asm_level, dim3(ng), dim3(WAVE), 0, c->stream, (int)m[l], M,
+        const int gmax = (int)std::min<int64_t>(M, m[l]);
+        auto kern = gmax <= WAVE ? k_asm_level<1> : (gmax <= 2 * WAVE ? k_asm_level<2> : k_asm_level<4>);
+        const int nwv = gmax <= WAVE ? 1 : (gmax <= 2 * WAVE ? 2 : 4);
+        hipLaunchKernelGGL(kern, dim3(ng), dim3(nwv * WAVE), 0, c->stream, (int)m[l], M,
                            (const int32_t *)(iw + lo[l]), (const double *)(ir + lo[l]), prm.gap, prm.sweeps,
                            P + lo[l], l == 0 ? par0 : (int32_t *)nullptr, iw + lo[l + 1], ic + lo[l + 1],
                            ir + lo[l + 1]);

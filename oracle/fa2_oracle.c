@@ -27,6 +27,8 @@
  *                        near field.  Operators of Greengard & Rokhlin (1987).
  *   orc_kk_*             sec. 3.1: the Kamada-Kawai energy and its
  *                        minimisation (here: localized stress majorization).
+ *   orc_bh_repulsion     sec. 3.2.1: Barnes-Hut, the O(N log N) method the
+ *                        FMM improves on (comparator), on the same quadtree.
  *   orc_stress,          sec. 4: Kamada-Kawai on the graph whose nodes are
  *   orc_kk_sweeps        the components, with real edge lengths (sequential
  *                        localized stress majorization).
@@ -866,4 +868,105 @@ void orc_kk_sweeps(int32_t n, const double *dist, int32_t sweeps, double *x, dou
             }
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Barnes-Hut repulsion (sec. 3.2.1 names it as the O(N log N) approach the  */
+/* FMM improves on; Barnes & Hut 1986).  The same quadtree as the FMM.  Every */
+/* cell carries its total mass and centre of mass.  For a target, the tree is */
+/* walked from the root, children in quadrant order: a cell that does not     */
+/* hold the target and whose side s and distance d from the target to its     */
+/* centre of mass satisfy s < theta d acts as one particle (its mass at its   */
+/* centre of mass); otherwise its children are visited, and a leaf that is    */
+/* visited contributes its particles directly.  Same force law and masses as  */
+/* orc_repulsion_exact; theta = 0 gives the exact sum.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const otree *t;
+    const double *cx, *cy, *cm, *side;  /* per cell */
+    const double *px, *py, *pq;         /* sorted particles */
+    double theta;
+} obh;
+
+static void bh_visit(const obh *b, int64_t c, int64_t k, double tx, double ty, double *ax, double *ay)
+{
+    const ocell *cc = &b->t->c[c];
+    int holds = k >= cc->begin && k < cc->end;
+    if (!holds) {
+        double dx = tx - b->cx[c], dy = ty - b->cy[c];
+        double d2 = dx * dx + dy * dy;
+        if (b->side[c] * b->side[c] < b->theta * b->theta * d2) {
+            *ax += b->cm[c] * dx / d2;
+            *ay += b->cm[c] * dy / d2;
+            return;
+        }
+    }
+    if (is_leaf(cc)) {
+        for (int64_t j = cc->begin; j < cc->end; ++j) {
+            if (j == k) continue;
+            double dx = tx - b->px[j], dy = ty - b->py[j];
+            double d2 = dx * dx + dy * dy;
+            if (d2 == 0.0) continue;
+            *ax += b->pq[j] * dx / d2;
+            *ay += b->pq[j] * dy / d2;
+        }
+        return;
+    }
+    for (int q = 0; q < 4; ++q)
+        if (cc->child[q] >= 0) bh_visit(b, cc->child[q], k, tx, ty, ax, ay);
+}
+
+int orc_bh_repulsion(int64_t n, const double *x, const double *y, const double *m, double kr, double theta,
+                     int leaf_size, int bits, int64_t nt, const int64_t *targets, double *fx, double *fy)
+{
+    if (n <= 0 || theta < 0.0 || leaf_size < 1 || bits < 1 || bits > 31) return -1;
+    oroot r = root_square(n, x, y, bits);
+    uint64_t *key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    int64_t *perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        key[i] = interleave(quantize(x[i], r.xmin, r.S, bits), quantize(y[i], r.ymin, r.S, bits), bits);
+    orc_sort_by_key(n, key, perm);
+    uint64_t *skey = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    double *px = (double *)malloc(sizeof(double) * (size_t)n);
+    double *py = (double *)malloc(sizeof(double) * (size_t)n);
+    double *pq = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        skey[k] = key[perm[k]];
+        px[k] = x[perm[k]];
+        py[k] = y[perm[k]];
+        pq[k] = m[perm[k]];
+        rank[perm[k]] = k;
+    }
+    otree t = build_tree(n, skey, bits, leaf_size);
+    int64_t nc = t.n;
+    double *cx = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *cy = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *cm = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *side = (double *)malloc(sizeof(double) * (size_t)nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        double sm = 0.0, sx = 0.0, sy = 0.0;
+        for (int64_t j = t.c[c].begin; j < t.c[c].end; ++j) {
+            sm += pq[j];
+            sx += pq[j] * px[j];
+            sy += pq[j] * py[j];
+        }
+        cm[c] = sm;
+        cx[c] = sx / sm;
+        cy[c] = sy / sm;
+        side[c] = r.L / (double)((int64_t)1 << t.c[c].level);
+    }
+    obh b = {&t, cx, cy, cm, side, px, py, pq, theta};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < nt; ++s) {
+        int64_t i = targets ? targets[s] : s;
+        int64_t k = rank[i];
+        double ax = 0.0, ay = 0.0;
+        bh_visit(&b, 0, k, px[k], py[k], &ax, &ay);
+        fx[s] = kr * m[i] * ax;
+        fy[s] = kr * m[i] * ay;
+    }
+    free(cx); free(cy); free(cm); free(side); free(t.c);
+    free(key); free(perm); free(rank); free(skey); free(px); free(py); free(pq);
+    return 0;
 }

@@ -73,6 +73,8 @@ def lib():
         L.orc_kk_energy.argtypes = [i32, P, f64, P, P]
         L.orc_kk_energy.restype = f64
         L.orc_kk_steps.argtypes = [i32, P, f64, i32, P, P]
+        L.orc_bh_repulsion.argtypes = [i64, P, P, P, f64, f64, ctypes.c_int, ctypes.c_int, i64, P, P, P]
+        L.orc_bh_repulsion.restype = ctypes.c_int
         L.orc_stress.argtypes = [i32, P, P, P]
         L.orc_stress.restype = f64
         L.orc_kk_sweeps.argtypes = [i32, P, i32, P, P]
@@ -170,6 +172,23 @@ def repulsion_fmm(x, y, m, kr: float = 1.0, p: int = 8, leaf_size: int = 64, bit
         keys = ("cells", "leaves", "max_level", "near_pairs", "v_entries", "w_entries", "x_entries",
                 "coverage_min", "coverage_max", "u_entries", "w_entries2", "x_entries2")
         return fx, fy, dict(zip(keys, (int(v) for v in st)))
+    return fx, fy
+
+
+def repulsion_bh(x, y, m, kr: float = 1.0, theta: float = 0.5, leaf_size: int = 64, bits: int = 16,
+                 targets=None):
+    """Barnes-Hut repulsion (the comparator of sec. 3.2.1) on the FMM's
+    quadtree: a cell not holding the target with side < theta * distance to
+    its centre of mass acts as one particle.  theta = 0 is the exact sum."""
+    x, y, m = _f64(x), _f64(y), _f64(m)
+    n = x.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    fx, fy = np.zeros(nt), np.zeros(nt)
+    rc = lib().orc_bh_repulsion(n, _p(x), _p(y), _p(m), float(kr), float(theta), int(leaf_size), int(bits), nt,
+                                None if tg is None else _p(tg), _p(fx), _p(fy))
+    if rc != 0:
+        raise ValueError("bad Barnes-Hut arguments")
     return fx, fy
 
 

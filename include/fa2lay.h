@@ -213,6 +213,19 @@ fl_status fl_fa2_run(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32
 enum { FL_NSTATS = 12 };
 fl_status fl_fmm_stats(fl_ctx *ctx, int64_t *out, int reset);
 
+/* Barnes-Hut repulsion (comparator: sec. 3.2.1 names it as the O(N log N)
+ * method the FMM improves on; Barnes & Hut 1986).  The quadtree is the
+ * FMM's (leaf_size, morton_bits); every cell carries its total mass and
+ * centre of mass (FP64 sums, stored FP32).  For node i the tree is walked
+ * from the root in depth-first order: a cell that does not hold i, with side
+ * s and distance d from p_i to its centre of mass such that s < theta d,
+ * acts as one particle (its mass at its centre of mass); any other cell is
+ * opened, and an opened leaf is summed directly.  frx, fry [n] receive F_r
+ * with the masses (deg + 1) and kr of fl_fa2_forces; theta = 0 gives the
+ * exact sum.  All nodes form one system.  theta in [0, 10]. */
+fl_status fl_bh_repulsion(fl_ctx *ctx, int32_t n, const float *x, const float *y, const int32_t *deg, double kr,
+                          double theta, int32_t leaf_size, int32_t morton_bits, float *frx, float *fry);
+
 /* ------------------------------------------------------------------------
  * Kamada-Kawai for small components (sec. 3.1): hop distances d_ij by
  * breadth-first search (exact for unit weights, equal to the Floyd-Warshall
@@ -441,11 +454,12 @@ const char *fl_server_last_error(const fl_server *srv);
 void fl_server_destroy(fl_server *srv);
 
 /* Per-phase device timing (HIP events on the context's stream).  When
- * enabled, fl_fa2_step/run record events around their phases; fl_get_timing
+ * enabled, fl_fa2_step/run (and fl_bh_repulsion: tree, then FL_PH_BH for
+ * the cell moments and the walk) record events around their phases; fl_get_timing
  * returns the accumulated milliseconds and launch counts per phase
  * (FL_NPHASE entries each) and clears them [host, synchronises]. */
 enum { FL_PH_TREE = 0, FL_PH_LISTS, FL_PH_UPWARD, FL_PH_M2L, FL_PH_EVAL, FL_PH_ATTRACT, FL_PH_UPDATE,
-       FL_PH_EXACT, FL_NPHASE };
+       FL_PH_EXACT, FL_PH_BH, FL_NPHASE };
 fl_status fl_set_timing(fl_ctx *ctx, int enable);
 /* Graph replay of fl_fa2_run and concurrent components in fl_layout (on by
  * default); 0 runs every iteration as eager launches on the context's stream

@@ -252,6 +252,9 @@ __device__ __forceinline__ T block_sum(T v, T *lds)
 // read as zero.  Three launches.
 void scan_excl_i32(fl_ctx *c, const int32_t *in, int32_t *out, int64_t n, const int32_t *dn = nullptr);
 void scan_excl_i64(fl_ctx *c, const int64_t *in, int64_t *out, int64_t n, const int32_t *dn = nullptr);
+// FP64 scan, summed in a fixed order (deterministic); `tag` names its
+// workspace, so scans whose results are used together need distinct tags.
+void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const int32_t *dn, const char *tag);
 
 // Stable LSD radix sort of 32-bit keys with int32 payload over bits
 // [0, nbits).  Ping-pongs between (k, v) and (kt, vt); returns true when the

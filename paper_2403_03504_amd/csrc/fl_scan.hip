@@ -262,6 +262,11 @@ void scan_excl_i64(fl_ctx *c, const int64_t *in, int64_t *out, int64_t n, const 
     scan_excl<int64_t>(c, in, out, n, dn, "i64");
 }
 
+void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const int32_t *dn, const char *tag)
+{
+    scan_excl<double>(c, in, out, n, dn, tag);
+}
+
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits)
 {
     return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32");

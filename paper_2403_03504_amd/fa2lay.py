@@ -27,7 +27,7 @@ GRAV_STRONG_MASS, GRAV_FA2_CONST, GRAV_STRONG_UNIT = 0, 1, 2
 SWING_PAPER, SWING_FA2 = 0, 1
 REP_EXACT, REP_FMM, REP_AUTO = 0, 1, 2
 TUNE_MAX_BUCKETS = 16
-PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact")
+PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact", "bh")
 
 EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
@@ -37,7 +37,7 @@ EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_syn
             "fl_server_submit", "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release",
             "fl_server_cancel", "fl_server_stats_get", "fl_server_last_error", "fl_server_destroy",
             "fl_default_tuning", "fl_set_tuning", "fl_get_tuning", "fl_autotune", "fl_server_set_tuning",
-            "fl_assemble_default_params", "fl_assemble")
+            "fl_assemble_default_params", "fl_assemble", "fl_bh_repulsion")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELED = 0, 1, 2, 3, 4
 
 
@@ -161,6 +161,7 @@ _sig = {
                    ctypes.POINTER(LayoutStats)], _i32),
     "fl_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
     "fl_assemble_default_params": ([ctypes.POINTER(AssembleParams)], None),
+    "fl_bh_repulsion": ([P, _i32, P, P, P, ctypes.c_double, ctypes.c_double, _i32, _i32, P, P], _i32),
     "fl_assemble": ([P, _i32, P, _i32, P, P, P, ctypes.POINTER(AssembleParams), P, P,
                      ctypes.POINTER(AssembleStats)], _i32),
     "fl_default_tuning": ([ctypes.POINTER(Tuning)], None),
@@ -421,6 +422,17 @@ class Context:
                                    ctypes.byref(fa2), fa2_iters, ctypes.byref(kk), kk_max_nodes, fmm_min_nodes,
                                    ctypes.byref(st)), "fl_layout")
         return {k: getattr(st, k) for k, _ in LayoutStats._fields_}
+
+    def bh_repulsion(self, x: torch.Tensor, y: torch.Tensor, deg: torch.Tensor, kr: float = 1.0,
+                     theta: float = 0.5, leaf_size: int = 64, morton_bits: int = 16):
+        """fl_bh_repulsion: Barnes-Hut F_r as (frx, fry) device tensors."""
+        n = x.shape[0]
+        frx = torch.empty(n, dtype=torch.float32, device=x.device)
+        fry = torch.empty_like(frx)
+        self._check(_lib.fl_bh_repulsion(self._h, n, _ptr(x, torch.float32), _ptr(y, torch.float32),
+                                         _ptr(deg, torch.int32), kr, theta, leaf_size, morton_bits, _ptr(frx),
+                                         _ptr(fry)), "fl_bh_repulsion")
+        return frx, fry
 
     def assemble(self, label: torch.Tensor, n_comp: int, order, x: torch.Tensor, y: torch.Tensor,
                  params: AssembleParams, frame: torch.Tensor | None = None,

@@ -200,6 +200,59 @@ def assembly(args, ctx, G, g, xl, yl, fl, np, torch) -> dict:
     return out
 
 
+def bh_comparison(args, ctx, G, x, y, tg, ex, ey, fl, orc, np, torch) -> dict:
+    """Barnes-Hut (the O(N log N) method the FMM replaces) against the FMM on
+    the same positions: repulsion time per evaluation (tree build included;
+    HIP events around every phase on the context's stream) and the error
+    against the FP64 exact sum on the sampled targets."""
+    reps = 5
+
+    def timed(fn):
+        fn()  # sizes the workspace
+        torch.cuda.synchronize()
+        ctx.get_timing()
+        ctx.set_timing(True)
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        return out, sum(v[0] for v in ctx.get_timing().values()) / reps
+
+    def err(fx, fy):
+        return orc.rel_err(fx.cpu().numpy()[tg], fy.cpu().numpy()[tg], ex, ey)
+
+    res = {"fmm": [], "bh": [], "leaf_size": args.leaf, "sample_nodes": int(tg.size)}
+    for p in (4, 8, 12):
+        prm = fl.default_params(repulsion=fl.REP_FMM, p=p, leaf_size=args.leaf)
+        out, ms = timed(lambda: ctx.fa2_forces(G, x, y, prm, components=False))
+        res["fmm"].append({"p": p, "ms": ms, "rel_err": err(out["frx"], out["fry"])})
+        log(f"FMM p={p}: {ms:.3f} ms per repulsion, error {res['fmm'][-1]['rel_err']:.2e}")
+    for th in [float(v) for v in args.bh_thetas.split(",")]:
+        (fx, fy), ms = timed(lambda: ctx.bh_repulsion(x, y, G.deg, 1.0, th, args.leaf))
+        res["bh"].append({"theta": th, "ms": ms, "rel_err": err(fx, fy)})
+        log(f"Barnes-Hut theta={th}: {ms:.3f} ms per repulsion, error {res['bh'][-1]['rel_err']:.2e}")
+    eq = []
+    for f in res["fmm"]:
+        ok = [b for b in res["bh"] if b["rel_err"] <= f["rel_err"]]
+        if ok:
+            b = min(ok, key=lambda v: v["ms"])
+            eq.append({"p": f["p"], "fmm_ms": f["ms"], "fmm_rel_err": f["rel_err"], "theta": b["theta"],
+                       "bh_ms": b["ms"], "bh_rel_err": b["rel_err"], "bh_over_fmm_time": b["ms"] / f["ms"]})
+        else:
+            eq.append({"p": f["p"], "fmm_ms": f["ms"], "fmm_rel_err": f["rel_err"], "theta": None,
+                       "note": "no theta tried reaches this error"})
+    res["equal_error"] = eq
+    fm = [f for f in res["fmm"] if f["rel_err"] <= 1e-3]
+    bm = [b for b in res["bh"] if b["rel_err"] <= 1e-3]
+    if fm and bm:
+        f, b = min(fm, key=lambda v: v["ms"]), min(bm, key=lambda v: v["ms"])
+        res["at_1e-3"] = {"fmm_p": f["p"], "fmm_ms": f["ms"], "theta": b["theta"], "bh_ms": b["ms"],
+                          "bh_over_fmm_time": b["ms"] / f["ms"]}
+        log(f"within 1e-3: FMM p={f['p']} {f['ms']:.3f} ms, Barnes-Hut theta={b['theta']} {b['ms']:.3f} ms "
+            f"({b['ms'] / f['ms']:.1f}x)")
+    return res
+
+
 def precision_study(args, ctx, G, g, fl, orc, np, torch) -> dict:
     """Expansion order p in {4, 8, 12} on the full graph: each p runs its own
     trajectory from the initial positions; at iterations t in {0, 1, 100,
@@ -318,6 +371,8 @@ def main() -> int:
     ap.add_argument("--batched-large", type=int, default=20)
     ap.add_argument("--batched-kk-steps", type=int, default=200)
     ap.add_argument("--batched-fa2-iters", type=int, default=200)
+    ap.add_argument("--bh-thetas", default="1.0,0.7,0.5,0.35,0.25,0.18,0.12",
+                    help="Barnes-Hut opening angles compared with the FMM at equal error ('' skips)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="finish with a device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -451,6 +506,8 @@ def main() -> int:
                               "reference": "FP64 exact sum over all nodes (oracle)"}
         log(f"repulsion error on {tg.size} nodes: FMM {result['accuracy']['fmm_rel_err']:.2e}, "
             f"direct {result['accuracy']['direct_rel_err']:.2e}")
+        if args.bh_thetas:
+            result["barnes_hut"] = bh_comparison(args, ctx, G, x, y, tg, ex, ey, fl, orc, np, torch)
     if args.direct_steps > 0:
         xd, yd = x.clone(), y.clone()
         sd = fl.FA2State(st.fx_prev.clone(), st.fy_prev.clone(), st.scalars.clone(), st.iter)

@@ -26,7 +26,8 @@
  *                        interacting cells; evaluation at nodes plus the direct
  *                        near field.  Operators of Greengard & Rokhlin (1987).
  *   orc_kk_*             sec. 3.1: the Kamada-Kawai energy and its
- *                        minimisation (here: localized stress majorization).
+ *                        minimisation: localized stress majorization, and
+ *                        the paper's Newton-Raphson (orc_kk_newton).
  *   orc_bh_repulsion     sec. 3.2.1: Barnes-Hut, the O(N log N) method the
  *                        FMM improves on (comparator), on the same quadtree.
  *   orc_stress,          sec. 4: Kamada-Kawai on the graph whose nodes are
@@ -969,4 +970,107 @@ int orc_bh_repulsion(int64_t n, const double *x, const double *y, const double *
     free(cx); free(cy); free(cm); free(side); free(t.c);
     free(key); free(perm); free(rank); free(skey); free(px); free(py); free(pq);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kamada-Kawai's own minimiser (sec. 3.1: Newton-Raphson).  With           */
+/* E = sum_{i<j} w_ij (r_ij - L_ij)^2, w_ij = d_ij^-2, L_ij = l d_ij and      */
+/* r_ij = |p_i - p_j|, the derivatives of E in the position of one node m,    */
+/* over the other nodes i (pairs at r = 0 contribute nothing), are            */
+/*   dE/dx_m        = sum 2 w (dx - L dx / r)                                 */
+/*   d2E/dx_m^2     = sum 2 w (1 - L dy^2 / r^3)                              */
+/*   d2E/dx_m dy_m  = sum 2 w L dx dy / r^3                                   */
+/*   d2E/dy_m^2     = sum 2 w (1 - L dx^2 / r^3)        with dx = x_m - x_i,  */
+/* and the part of E that depends on p_m is E_m = sum w (r - L)^2.            */
+/* A move takes the node with the largest gradient norm Delta_m (the lowest   */
+/* index on a tie) and makes Newton-Raphson steps on p_m alone until Delta_m  */
+/* < eps l or `inner` steps were made.  A step solves the 2x2 system when the */
+/* Hessian is positive definite; otherwise it is the gradient step            */
+/* -g / (2 sum w).  It is halved (at most 30 times) until E_m decreases; a    */
+/* step that finds no decrease ends the move.  Moves repeat until every       */
+/* Delta < eps l or `moves` moves were made.  Every quantity is computed from */
+/* the current positions, from scratch.  Returns the number of moves made.    */
+/* ------------------------------------------------------------------------ */
+void orc_kk_grad_hess(int32_t n, const int32_t *dist, double l, int32_t m, const double *x, const double *y,
+                      double *out5)
+{
+    double gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (i == m) continue;
+        double d = (double)dist[(int64_t)m * n + i];
+        double w = 1.0 / (d * d), L = l * d;
+        double dx = x[m] - x[i], dy = y[m] - y[i];
+        double r = sqrt(dx * dx + dy * dy);
+        if (r == 0.0) continue;
+        double r3 = r * r * r;
+        gx += 2.0 * w * (dx - L * dx / r);
+        gy += 2.0 * w * (dy - L * dy / r);
+        hxx += 2.0 * w * (1.0 - L * dy * dy / r3);
+        hxy += 2.0 * w * L * dx * dy / r3;
+        hyy += 2.0 * w * (1.0 - L * dx * dx / r3);
+    }
+    out5[0] = gx; out5[1] = gy; out5[2] = hxx; out5[3] = hxy; out5[4] = hyy;
+}
+
+static double kk_node_energy(int32_t n, const int32_t *dist, double l, int32_t m, double px, double py,
+                             const double *x, const double *y)
+{
+    double e = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (i == m) continue;
+        double d = (double)dist[(int64_t)m * n + i];
+        double dx = px - x[i], dy = py - y[i];
+        double r = sqrt(dx * dx + dy * dy) - l * d;
+        e += r * r / (d * d);
+    }
+    return e;
+}
+
+int32_t orc_kk_newton(int32_t n, const int32_t *dist, double l, double eps, int32_t moves, int32_t inner,
+                      double *x, double *y)
+{
+    double gh[5];
+    const double tol = eps * l;
+    int32_t done = 0;
+    for (; done < moves; ++done) {
+        int32_t m = -1;
+        double best = -1.0;
+        for (int32_t i = 0; i < n; ++i) {
+            orc_kk_grad_hess(n, dist, l, i, x, y, gh);
+            double dlt = sqrt(gh[0] * gh[0] + gh[1] * gh[1]);
+            if (dlt > best) { best = dlt; m = i; }
+        }
+        if (m < 0 || best < tol) break;
+        double sw = 0.0;
+        for (int32_t i = 0; i < n; ++i)
+            if (i != m) sw += 1.0 / ((double)dist[(int64_t)m * n + i] * (double)dist[(int64_t)m * n + i]);
+        for (int32_t s = 0; s < inner; ++s) {
+            orc_kk_grad_hess(n, dist, l, m, x, y, gh);
+            if (sqrt(gh[0] * gh[0] + gh[1] * gh[1]) < tol) break;
+            double det = gh[2] * gh[4] - gh[3] * gh[3];
+            double sx, sy;
+            if (gh[2] > 0.0 && det > 0.0) {
+                sx = -(gh[4] * gh[0] - gh[3] * gh[1]) / det;
+                sy = -(gh[2] * gh[1] - gh[3] * gh[0]) / det;
+            } else {
+                sx = -gh[0] / (2.0 * sw);
+                sy = -gh[1] / (2.0 * sw);
+            }
+            double e0 = kk_node_energy(n, dist, l, m, x[m], y[m], x, y);
+            int moved = 0;
+            for (int h = 0; h <= 30; ++h) {
+                double nx = x[m] + sx, ny = y[m] + sy;
+                if (kk_node_energy(n, dist, l, m, nx, ny, x, y) < e0) {
+                    x[m] = nx;
+                    y[m] = ny;
+                    moved = 1;
+                    break;
+                }
+                sx *= 0.5;
+                sy *= 0.5;
+            }
+            if (!moved) break;
+        }
+    }
+    return done;
 }

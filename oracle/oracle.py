@@ -73,6 +73,9 @@ def lib():
         L.orc_kk_energy.argtypes = [i32, P, f64, P, P]
         L.orc_kk_energy.restype = f64
         L.orc_kk_steps.argtypes = [i32, P, f64, i32, P, P]
+        L.orc_kk_grad_hess.argtypes = [i32, P, f64, i32, P, P, P]
+        L.orc_kk_newton.argtypes = [i32, P, f64, f64, i32, i32, P, P]
+        L.orc_kk_newton.restype = i32
         L.orc_bh_repulsion.argtypes = [i64, P, P, P, f64, f64, ctypes.c_int, ctypes.c_int, i64, P, P, P]
         L.orc_bh_repulsion.restype = ctypes.c_int
         L.orc_stress.argtypes = [i32, P, P, P]
@@ -459,6 +462,25 @@ def kk_steps(dist, x, y, l: float = 1.0, steps: int = 1):
     x, y = _f64(x).copy(), _f64(y).copy()
     lib().orc_kk_steps(d.shape[0], _p(d), float(l), int(steps), _p(x), _p(y))
     return x, y
+
+
+def kk_grad_hess(dist, x, y, m: int, l: float = 1.0):
+    """Gradient (gx, gy) and Hessian (hxx, hxy, hyy) of the KK energy in the
+    position of node m."""
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    out = np.zeros(5)
+    lib().orc_kk_grad_hess(d.shape[0], _p(d), float(l), int(m), _p(_f64(x)), _p(_f64(y)), _p(out))
+    return out
+
+
+def kk_newton(dist, x, y, l: float = 1.0, eps: float = 1e-4, moves: int = 1000, inner: int = 16):
+    """Kamada-Kawai's Newton-Raphson minimiser (sec. 3.1) with the safeguards of
+    fa2_oracle.c (positive-definite check, step halving); stops when every
+    gradient norm is below eps * l.  Returns (x, y, moves made)."""
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    x, y = _f64(x).copy(), _f64(y).copy()
+    k = lib().orc_kk_newton(d.shape[0], _p(d), float(l), float(eps), int(moves), int(inner), _p(x), _p(y))
+    return x, y, int(k)
 
 
 def rel_err(ax, ay, bx, by) -> float:

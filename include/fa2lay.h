@@ -238,12 +238,27 @@ fl_status fl_bh_repulsion(fl_ctx *ctx, int32_t n, const float *x, const float *y
  * increasing, component k = nodes [comp_offsets[k], comp_offsets[k+1]), each
  * of 1..256 nodes, with no edge leaving its range.
  * ------------------------------------------------------------------------ */
+enum { FL_KK_MAJORIZATION = 0, FL_KK_NEWTON = 1 };
+/* Minimisers:
+ *   FL_KK_MAJORIZATION: `steps` steps of the update above, every node of a
+ *     component at once;
+ *   FL_KK_NEWTON (the paper's Newton-Raphson, after Kamada and Kawai): a
+ *     move takes the node m with the largest gradient norm |dE/dp_m| (lowest
+ *     index on a tie) and makes up to 16 Newton-Raphson steps on p_m alone:
+ *     the 2x2 system of E's second derivatives in x_m, y_m when that Hessian
+ *     is positive definite, else -g / (2 sum_i d_mi^-2); each step is halved
+ *     (at most 30 times) until the part of E that depends on p_m decreases,
+ *     and a step that finds no decrease ends the move.  Moves stop when every
+ *     gradient norm is below eps * l, or after steps * n moves for a
+ *     component of n nodes.  One wave per component. */
 typedef struct {
-    double l;       /* rescaling constant: desired length per hop (> 0) */
-    int32_t steps;  /* majorization steps */
+    double l;           /* rescaling constant: desired length per hop (> 0) */
+    int32_t steps;      /* majorization: steps; Newton-Raphson: moves per node */
+    int32_t minimiser;  /* FL_KK_MAJORIZATION or FL_KK_NEWTON */
+    double eps;         /* Newton-Raphson: gradient-norm tolerance, in units of l (>= 0) */
 } fl_kk_params;
 
-/* Defaults: l = 1, steps = 200. */
+/* Defaults: l = 1, steps = 200, minimiser FL_KK_MAJORIZATION, eps = 1e-3. */
 void fl_kk_default_params(fl_kk_params *prm);
 
 /* Hop distances of every component: dist [sum n_k^2] int32, component k's
@@ -254,10 +269,10 @@ void fl_kk_default_params(fl_kk_params *prm);
 fl_status fl_hop_distances(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
                            const int32_t *col_idx, int32_t *dist, int64_t *dist_offsets);
 
-/* prm->steps majorization steps of every component, in place on x, y, given
- * the distances of fl_hop_distances.  One persistent launch: components are
- * packed into batches of at most 256 nodes, one workgroup each.
- * Synchronises. */
+/* The minimiser of prm on every component, in place on x, y, given the
+ * distances of fl_hop_distances.  One persistent launch: for majorization,
+ * components packed into batches of at most 256 nodes, one workgroup each;
+ * for Newton-Raphson, one wave per component.  Synchronises. */
 fl_status fl_kk_steps(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *dist, float *x,
                       float *y, const fl_kk_params *prm);
 

@@ -48,6 +48,8 @@ struct LabelSort {
 };
 LabelSort sort_by_label(fl_ctx *c, int32_t n, const int32_t *label, int32_t n_labels);
 void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,
-                      const int32_t *row_ptr, const int32_t *col, float *x, float *y, double l, int steps);
+                      const int32_t *row_ptr, const int32_t *col, float *x, float *y, const fl_kk_params &prm);
+// Throws FL_EINVAL unless the Kamada-Kawai parameters are valid.
+void check_kk_params(const fl_kk_params *p);
 
 }  // namespace fl

@@ -165,6 +165,238 @@ __global__ __launch_bounds__(256) void k_kk_steps(const KKBatch *__restrict__ ba
     }
 }
 
+// ---- Newton-Raphson (the paper's minimiser) --------------------------------
+// One wave per component (<= 256 nodes, node j on lane j % 64, slot j / 64):
+// positions in LDS (the wave's own 256 float2), gradients in registers,
+// distances read from the component's row-major matrix (rows of the moving
+// node are contiguous, so the wave reads them coalesced).  A move:
+//   1. the node m with the largest |g| (lowest index on a tie) by a wave
+//      maximum over (|g|^2 bits << 32 | ~index);
+//   2. Newton-Raphson steps on p_m: one wave reduction gives the gradient,
+//      the Hessian and sum w at p_m; the 2x2 solve when the Hessian is
+//      positive definite, else -g / (2 sum w); the step is halved until E_m
+//      decreases (one more reduction per trial, of per-pair energy changes);
+//   3. every other node's gradient is corrected for p_m's move (old term out,
+//      new term in), and m's own is the last one computed.
+constexpr int KKN_Q = KK_MAX / WAVE;
+constexpr int KKN_WPB = 4;
+constexpr int KKN_INNER = 16;
+
+__device__ __forceinline__ float kkn_sum(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), WAVE - 1));
+}
+
+__device__ __forceinline__ unsigned long long kkn_max_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const unsigned long long u = __shfl_xor(v, o, WAVE);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// gradient and Hessian terms of the pair (node at p, other node at q) in
+// p; nothing for coincident points
+struct KKTerm {
+    float gx, gy, hxx, hxy, hyy;
+};
+
+__device__ __forceinline__ KKTerm kkn_term(float px, float py, float qx, float qy, float d, float l)
+{
+    KKTerm t{0.f, 0.f, 0.f, 0.f, 0.f};
+    const float dx = px - qx, dy = py - qy;
+    const float r2 = dx * dx + dy * dy;
+    if (r2 > 0.f) {
+        const float w = 1.0f / (d * d), L = l * d;
+        const float ir = __builtin_amdgcn_rsqf(r2);
+        const float ir3 = ir * ir * ir;
+        t.gx = 2.f * w * (dx - L * dx * ir);
+        t.gy = 2.f * w * (dy - L * dy * ir);
+        t.hxx = 2.f * w * (1.f - L * dy * dy * ir3);
+        t.hxy = 2.f * w * L * dx * dy * ir3;
+        t.hyy = 2.f * w * (1.f - L * dx * dx * ir3);
+    }
+    return t;
+}
+
+__global__ __launch_bounds__(KKN_WPB * WAVE) void k_kk_newton(const int32_t *__restrict__ comp_off,
+                                                              const int32_t *__restrict__ ids,
+                                                              const int64_t *__restrict__ dist_off, int ncomp,
+                                                              const int32_t *__restrict__ dist, float *__restrict__ x,
+                                                              float *__restrict__ y, float l, float tol,
+                                                              int moves_per_node)
+{
+    __shared__ float2 lpos[KKN_WPB][KK_MAX];
+    const int k = blockIdx.x * KKN_WPB + (int)(threadIdx.x / WAVE);
+    if (k >= ncomp) return;  // wave-uniform
+    float2 *pos = lpos[threadIdx.x / WAVE];
+    const int lane = lane_id();
+    const int c = ids[k];
+    const int cb = comp_off[c], n = comp_off[c + 1] - cb;
+    const int32_t *D = dist + dist_off[k];
+    for (int j = lane; j < n; j += WAVE) pos[j] = make_float2(x[cb + j], y[cb + j]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // initial gradients, every node from scratch
+    float gx[KKN_Q], gy[KKN_Q];
+#pragma unroll
+    for (int q = 0; q < KKN_Q; ++q) {
+        gx[q] = 0.f;
+        gy[q] = 0.f;
+        const int i = lane + WAVE * q;
+        if (i < n) {
+            const float2 pi = pos[i];
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const float2 pj = pos[j];
+                const KKTerm t = kkn_term(pi.x, pi.y, pj.x, pj.y, (float)D[(int64_t)i * n + j], l);
+                gx[q] += t.gx;
+                gy[q] += t.gy;
+            }
+        }
+    }
+
+    const float tol2 = tol * tol;
+    const int64_t budget = (int64_t)moves_per_node * n;
+    for (int64_t mv = 0; mv < budget; ++mv) {
+        // 1. the node with the largest gradient norm
+        unsigned long long key = 0ull;
+#pragma unroll
+        for (int q = 0; q < KKN_Q; ++q) {
+            const int i = lane + WAVE * q;
+            if (i < n) {
+                const float g2 = gx[q] * gx[q] + gy[q] * gy[q];
+                const unsigned long long kq =
+                    ((unsigned long long)__float_as_uint(g2) << 32) | (unsigned long long)(~(unsigned)i);
+                key = kq > key ? kq : key;
+            }
+        }
+        key = kkn_max_u64(key);
+        const float g2max = __uint_as_float((unsigned)(key >> 32));
+        if (!(g2max >= tol2)) break;  // also ends on a NaN gradient
+        const int m = (int)(~(unsigned)(key & 0xFFFFFFFFull));
+        const int32_t *Dm = D + (int64_t)m * n;
+        float dq[KKN_Q];
+#pragma unroll
+        for (int q = 0; q < KKN_Q; ++q) {
+            const int j = lane + WAVE * q;
+            dq[q] = j < n ? (float)Dm[j] : 1.f;
+        }
+        const float2 old = pos[m];
+        float mx = old.x, my = old.y;
+        float Gx = 0.f, Gy = 0.f;
+        // 2. Newton-Raphson steps on p_m
+        for (int s = 0; s <= KKN_INNER; ++s) {
+            float a[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // gx gy hxx hxy hyy
+            float sw = 0.f;
+#pragma unroll
+            for (int q = 0; q < KKN_Q; ++q) {
+                const int j = lane + WAVE * q;
+                if (j < n && j != m) {
+                    const float2 pj = pos[j];
+                    const KKTerm t = kkn_term(mx, my, pj.x, pj.y, dq[q], l);
+                    a[0] += t.gx;
+                    a[1] += t.gy;
+                    a[2] += t.hxx;
+                    a[3] += t.hxy;
+                    a[4] += t.hyy;
+                    sw += 1.0f / (dq[q] * dq[q]);
+                }
+            }
+            Gx = kkn_sum(a[0]);
+            Gy = kkn_sum(a[1]);
+            if (Gx * Gx + Gy * Gy < tol2 || s == KKN_INNER) break;
+            const float hxx = kkn_sum(a[2]), hxy = kkn_sum(a[3]), hyy = kkn_sum(a[4]);
+            const float swt = kkn_sum(sw);
+            const float det = hxx * hyy - hxy * hxy;
+            float sx, sy;
+            if (hxx > 0.f && det > 0.f) {
+                sx = -(hyy * Gx - hxy * Gy) / det;
+                sy = -(hxx * Gy - hxy * Gx) / det;
+            } else {
+                sx = -Gx / (2.f * swt);
+                sy = -Gy / (2.f * swt);
+            }
+            // E_m(trial) < E_m(p_m), evaluated as a sum of per-pair changes
+            // w ((r1 - L)^2 - (r0 - L)^2) = w (r1 - r0)(r1 + r0 - 2L) with
+            // r1 - r0 = (2 s.e + s.s) / (r1 + r0), e = p_m - p_j: no
+            // difference of nearly equal numbers, so FP32 resolves the
+            // decrease of a small step
+            float exq[KKN_Q], eyq[KKN_Q], r0q[KKN_Q];
+#pragma unroll
+            for (int q = 0; q < KKN_Q; ++q) {
+                const int j = lane + WAVE * q;
+                exq[q] = 0.f;
+                eyq[q] = 0.f;
+                if (j < n && j != m) {
+                    const float2 pj = pos[j];
+                    exq[q] = mx - pj.x;
+                    eyq[q] = my - pj.y;
+                }
+                r0q[q] = sqrtf(exq[q] * exq[q] + eyq[q] * eyq[q]);
+            }
+            bool moved = false;
+            for (int h = 0; h <= 30; ++h) {
+                float de = 0.f;
+#pragma unroll
+                for (int q = 0; q < KKN_Q; ++q) {
+                    const int j = lane + WAVE * q;
+                    if (j < n && j != m) {
+                        const float ux = exq[q] + sx, uy = eyq[q] + sy;
+                        const float r1 = sqrtf(ux * ux + uy * uy);
+                        const float rs = r1 + r0q[q];
+                        const float dr = rs > 0.f ? (2.f * (sx * exq[q] + sy * eyq[q]) + sx * sx + sy * sy) / rs : 0.f;
+                        de += dr * (rs - 2.f * l * dq[q]) / (dq[q] * dq[q]);
+                    }
+                }
+                if (kkn_sum(de) < 0.f) {
+                    mx += sx;
+                    my += sy;
+                    moved = true;
+                    break;
+                }
+                sx *= 0.5f;
+                sy *= 0.5f;
+            }
+            if (!moved) break;
+        }
+        // 3. p_m's move in every other gradient; m keeps the last one computed
+        if (lane == (m & (WAVE - 1))) pos[m] = make_float2(mx, my);
+#pragma unroll
+        for (int q = 0; q < KKN_Q; ++q) {
+            const int i = lane + WAVE * q;
+            if (i < n && i != m) {
+                const float2 pi = pos[i];
+                const KKTerm to = kkn_term(pi.x, pi.y, old.x, old.y, dq[q], l);
+                const KKTerm tn = kkn_term(pi.x, pi.y, mx, my, dq[q], l);
+                gx[q] += tn.gx - to.gx;
+                gy[q] += tn.gy - to.gy;
+            }
+            if (i == m) {
+                gx[q] = Gx;
+                gy[q] = Gy;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int j = lane; j < n; j += WAVE) {
+        x[cb + j] = pos[j].x;
+        y[cb + j] = pos[j].y;
+    }
+}
+
 }  // namespace
 
 // Components taken by Kamada-Kawai: `ids` (ascending) index the full offset
@@ -230,11 +462,19 @@ static void kk_bfs(fl_ctx *c, const KKPlan &p, const int32_t *row_ptr, const int
     if (e & 2) throw Error(FL_EINVAL, "a component is not connected");
 }
 
-static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float *x, float *y, double l, int steps)
+static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float *x, float *y,
+                         const fl_kk_params &prm)
 {
     if (p.batches.empty()) return;
-    hipLaunchKernelGGL(k_kk_steps, dim3((unsigned)p.batches.size()), dim3(256), 0, c->stream, p.d_batches, p.d_off,
-                       p.d_doff, dist, x, y, (float)l, steps);
+    if (prm.minimiser == FL_KK_NEWTON) {
+        const int nc = (int)p.ids.size();
+        hipLaunchKernelGGL(k_kk_newton, dim3((unsigned)((nc + KKN_WPB - 1) / KKN_WPB)), dim3(KKN_WPB * WAVE), 0,
+                           c->stream, p.d_off, p.d_ids, p.d_doff, nc, dist, x, y, (float)prm.l,
+                           (float)(prm.eps * prm.l), prm.steps);
+    } else {
+        hipLaunchKernelGGL(k_kk_steps, dim3((unsigned)p.batches.size()), dim3(256), 0, c->stream, p.d_batches,
+                           p.d_off, p.d_doff, dist, x, y, (float)prm.l, prm.steps);
+    }
     FL_LAUNCH_CHECK();
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));  // host plan vectors outlive the async copies
 }
@@ -242,13 +482,23 @@ static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float 
 // Kamada-Kawai for the components `ids` of a graph whose components are the
 // node ranges [off[k], off[k+1]); distances in the context workspace.
 void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,
-                      const int32_t *row_ptr, const int32_t *col, float *x, float *y, double l, int steps)
+                      const int32_t *row_ptr, const int32_t *col, float *x, float *y, const fl_kk_params &prm)
 {
     if (ids.empty()) return;
     KKPlan p = kk_plan(c, n_all, off, ids);
     int32_t *dist = ws<int32_t>(c, "kk_dist", p.doff.back() > 0 ? p.doff.back() : 1);
     kk_bfs(c, p, row_ptr, col, dist);
-    kk_run_steps(c, p, dist, x, y, l, steps);
+    kk_run_steps(c, p, dist, x, y, prm);
+}
+
+void check_kk_params(const fl_kk_params *p)
+{
+    FL_REQUIRE(p, "null Kamada-Kawai parameters");
+    FL_REQUIRE(p->l > 0.0 && std::isfinite(p->l), "Kamada-Kawai: need a finite l > 0");
+    FL_REQUIRE(p->steps >= 0, "Kamada-Kawai: need steps >= 0");
+    FL_REQUIRE(p->minimiser == FL_KK_MAJORIZATION || p->minimiser == FL_KK_NEWTON,
+               "Kamada-Kawai: unknown minimiser");
+    FL_REQUIRE(std::isfinite(p->eps) && p->eps >= 0.0, "Kamada-Kawai: need a finite eps >= 0");
 }
 
 static std::vector<int32_t> iota_ids(int n)
@@ -269,6 +519,8 @@ void fl_kk_default_params(fl_kk_params *p)
     if (!p) return;
     p->l = 1.0;
     p->steps = 200;
+    p->minimiser = FL_KK_MAJORIZATION;
+    p->eps = 1e-3;
 }
 
 fl_status fl_hop_distances(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
@@ -286,10 +538,10 @@ fl_status fl_kk_steps(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, co
                       const fl_kk_params *prm)
 {
     FL_API_BEGIN(c)
-    FL_REQUIRE(n_comp >= 1 && comp_offsets && dist && x && y && prm, "fl_kk_steps: bad arguments");
-    FL_REQUIRE(prm->l > 0.0 && std::isfinite(prm->l) && prm->steps >= 0, "fl_kk_steps: need l > 0, steps >= 0");
+    FL_REQUIRE(n_comp >= 1 && comp_offsets && dist && x && y, "fl_kk_steps: bad arguments");
+    check_kk_params(prm);
     KKPlan p = kk_plan(c, n_comp, comp_offsets, iota_ids(n_comp));
-    kk_run_steps(c, p, dist, x, y, prm->l, prm->steps);
+    kk_run_steps(c, p, dist, x, y, *prm);
     FL_API_END(c)
 }
 
@@ -297,9 +549,9 @@ fl_status fl_kk_layout(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, c
                        const int32_t *col_idx, float *x, float *y, const fl_kk_params *prm)
 {
     FL_API_BEGIN(c)
-    FL_REQUIRE(n_comp >= 1 && comp_offsets && row_ptr && col_idx && x && y && prm, "fl_kk_layout: bad arguments");
-    FL_REQUIRE(prm->l > 0.0 && std::isfinite(prm->l) && prm->steps >= 0, "fl_kk_layout: need l > 0, steps >= 0");
-    kk_layout_subset(c, n_comp, comp_offsets, iota_ids(n_comp), row_ptr, col_idx, x, y, prm->l, prm->steps);
+    FL_REQUIRE(n_comp >= 1 && comp_offsets && row_ptr && col_idx && x && y, "fl_kk_layout: bad arguments");
+    check_kk_params(prm);
+    kk_layout_subset(c, n_comp, comp_offsets, iota_ids(n_comp), row_ptr, col_idx, x, y, *prm);
     FL_API_END(c)
 }
 

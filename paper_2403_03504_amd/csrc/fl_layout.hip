@@ -154,7 +154,7 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
 {
     auto t0 = std::chrono::steady_clock::now();
     fa2_validate(c, n, row_ptr, col, deg, fa2);
-    FL_REQUIRE(kk && kk->l > 0.0 && std::isfinite(kk->l) && kk->steps >= 0, "bad Kamada-Kawai parameters");
+    check_kk_params(kk);
     FL_REQUIRE(kk_max_nodes >= 1 && kk_max_nodes <= 256, "kk_max_nodes must be in [1, 256]");
     FL_REQUIRE(fa2_iters >= 0, "fa2_iters must be >= 0");
     const unsigned g = grid_for(n, 256);
@@ -242,7 +242,7 @@ void layout(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, co
         std::vector<int32_t> kk_ids;
         const int first_kk = ncomp - (int)single_list.size() - (int)kk_list.size();
         for (int j = 0; j < (int)kk_list.size(); ++j) kk_ids.push_back(first_kk + j);
-        kk_layout_subset(c, ncomp, newoff.data(), kk_ids, nrow_ptr, ncol, xs, ys, kk->l, kk->steps);
+        kk_layout_subset(c, ncomp, newoff.data(), kk_ids, nrow_ptr, ncol, xs, ys, *kk);
     }
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));
     const double ms_kk = ms_since(t1);

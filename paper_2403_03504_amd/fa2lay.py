@@ -26,6 +26,7 @@ FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENONFINITE, FL_EBUSY, FL_ECANCELED, FL_
 GRAV_STRONG_MASS, GRAV_FA2_CONST, GRAV_STRONG_UNIT = 0, 1, 2
 SWING_PAPER, SWING_FA2 = 0, 1
 REP_EXACT, REP_FMM, REP_AUTO = 0, 1, 2
+KK_MAJORIZATION, KK_NEWTON = 0, 1
 TUNE_MAX_BUCKETS = 16
 PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact", "bh")
 
@@ -61,7 +62,8 @@ class _State(ctypes.Structure):
 
 
 class KKParams(ctypes.Structure):
-    _fields_ = [("l", ctypes.c_double), ("steps", ctypes.c_int32)]
+    _fields_ = [("l", ctypes.c_double), ("steps", ctypes.c_int32), ("minimiser", ctypes.c_int32),
+                ("eps", ctypes.c_double)]
 
 
 class AssembleParams(ctypes.Structure):

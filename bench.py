@@ -152,7 +152,54 @@ def batched(args, fl, w, np, torch) -> dict:
             f"({r['fa2_node_updates_per_s']:.3g} node-updates/s)")
     ctx.set_graphs(True)
     out["assembly"] = assembly(args, ctx, G, g, x, y, fl, np, torch)
+    out["kk_minimisers"] = kk_minimisers(args, ctx, g, offs, fl, np, torch)
     ctx.close()
+    return out
+
+
+def kk_minimisers(args, ctx, g, offs, fl, np, torch) -> dict:
+    """The batched workload's small components laid out from the same start by
+    the two Kamada-Kawai minimisers: localized stress majorization (all nodes
+    of a component at once, 200 steps) and the paper's Newton-Raphson (one
+    node at a time, until every gradient norm < 1e-3 l, at most 200 moves per
+    node).  Time of the minimiser launch, and the total energy by the FP64
+    oracle."""
+    from oracle import oracle as orc
+    sizes = np.diff(offs)
+    small = np.nonzero(sizes <= 256)[0]
+    # the small components are a prefix of the batched workload
+    assert np.all(small == np.arange(small.size))
+    ns = int(offs[small.size])
+    sub_src, sub_dst = g.src, g.dst
+    keep = (sub_src < ns) & (sub_dst < ns)
+    dev = torch.device("cuda", 0)
+    G = ctx.build_csr(ns, torch.from_numpy(sub_src[keep]).to(dev), torch.from_numpy(sub_dst[keep]).to(dev))
+    coff = offs[: small.size + 1].astype(np.int32)
+    dist, doff = ctx.hop_distances(G, coff)
+    D = dist.cpu().numpy()
+    out = {"components": int(small.size), "nodes": ns}
+    for name, kw in (("majorization", dict(minimiser=fl.KK_MAJORIZATION, steps=200)),
+                     ("newton", dict(minimiser=fl.KK_NEWTON, steps=200, eps=1e-3))):
+        best = None
+        for _ in range(2):
+            x = torch.from_numpy(g.x[:ns]).to(dev)
+            y = torch.from_numpy(g.y[:ns]).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.kk_steps(coff, dist, x, y, fl.kk_params(**kw))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if best is None or wall < best[0]:
+                best = (wall, x.cpu().numpy(), y.cpu().numpy())
+        wall, xh, yh = best
+        energy = 0.0
+        for k in range(small.size):
+            a, b = coff[k], coff[k + 1]
+            n = b - a
+            energy += orc.kk_energy(D[doff[k]:doff[k] + n * n].reshape(n, n), xh[a:b], yh[a:b])
+        out[name] = {"ms": wall * 1e3, "energy": energy}
+        log(f"KK {name}: {wall * 1e3:.1f} ms for {small.size} components, total energy {energy:.6g}")
+    out["newton_over_majorization_energy"] = out["newton"]["energy"] / out["majorization"]["energy"]
     return out
 
 

@@ -15,6 +15,8 @@
 //               two coincide).  One workgroup runs every step for a batch of
 //               components (at most 256 nodes in total, one thread per node),
 //               with positions and the batch's distances (uint8) in LDS.
+#include <algorithm>
+
 #include "fl_common.h"
 #include "fl_tree.h"
 
@@ -166,20 +168,18 @@ __global__ __launch_bounds__(256) void k_kk_steps(const KKBatch *__restrict__ ba
 }
 
 // ---- Newton-Raphson (the paper's minimiser) --------------------------------
-// One wave per component (<= 256 nodes, node j on lane j % 64, slot j / 64):
-// positions in LDS (the wave's own 256 float2), gradients in registers,
-// distances read from the component's row-major matrix (rows of the moving
-// node are contiguous, so the wave reads them coalesced).  A move:
+// One wave per component (<= 256 nodes, node j on lane j % 64, slot j / 64),
+// the largest components first: the distance matrix in LDS (as bytes); each
+// lane's nodes (position, gradient, sum_j w_ij) in registers.  A move:
 //   1. the node m with the largest |g| (lowest index on a tie) by a wave
 //      maximum over (|g|^2 bits << 32 | ~index);
-//   2. Newton-Raphson steps on p_m: one wave reduction gives the gradient,
-//      the Hessian and sum w at p_m; the 2x2 solve when the Hessian is
+//   2. Newton-Raphson steps on p_m: one wave reduction gives the gradient
+//      and the Hessian at p_m; the 2x2 solve when the Hessian is
 //      positive definite, else -g / (2 sum w); the step is halved until E_m
 //      decreases (one more reduction per trial, of per-pair energy changes);
 //   3. every other node's gradient is corrected for p_m's move (old term out,
 //      new term in), and m's own is the last one computed.
 constexpr int KKN_Q = KK_MAX / WAVE;
-constexpr int KKN_WPB = 4;
 constexpr int KKN_INNER = 16;
 
 __device__ __forceinline__ float kkn_sum(float v)
@@ -193,14 +193,29 @@ __device__ __forceinline__ float kkn_sum(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), WAVE - 1));
 }
 
+// Wave maximum of a 64-bit key by DPP, the same row pattern as kkn_sum
+// (lanes shifted in from outside a row read 0, the identity of unsigned max)
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ unsigned long long kkn_max_step(unsigned long long v)
+{
+    const unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    const unsigned lo2 = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xF, BOUND);
+    const unsigned hi2 = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xF, BOUND);
+    const unsigned long long u = ((unsigned long long)hi2 << 32) | lo2;
+    return u > v ? u : v;
+}
+
 __device__ __forceinline__ unsigned long long kkn_max_u64(unsigned long long v)
 {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const unsigned long long u = __shfl_xor(v, o, WAVE);
-        v = u > v ? u : v;
-    }
-    return v;
+    v = kkn_max_step<0x111, 0xF, true>(v);
+    v = kkn_max_step<0x112, 0xF, true>(v);
+    v = kkn_max_step<0x114, 0xF, true>(v);
+    v = kkn_max_step<0x118, 0xF, true>(v);
+    v = kkn_max_step<0x142, 0xA, false>(v);
+    v = kkn_max_step<0x143, 0xC, false>(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, WAVE - 1);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), WAVE - 1);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // gradient and Hessian terms of the pair (node at p, other node at q) in
@@ -209,59 +224,88 @@ struct KKTerm {
     float gx, gy, hxx, hxy, hyy;
 };
 
-__device__ __forceinline__ KKTerm kkn_term(float px, float py, float qx, float qy, float d, float l)
+__device__ __forceinline__ KKTerm kkn_term(float px, float py, float qx, float qy, float w, float L)
 {
     KKTerm t{0.f, 0.f, 0.f, 0.f, 0.f};
     const float dx = px - qx, dy = py - qy;
     const float r2 = dx * dx + dy * dy;
     if (r2 > 0.f) {
-        const float w = 1.0f / (d * d), L = l * d;
         const float ir = __builtin_amdgcn_rsqf(r2);
         const float ir3 = ir * ir * ir;
-        t.gx = 2.f * w * (dx - L * dx * ir);
-        t.gy = 2.f * w * (dy - L * dy * ir);
-        t.hxx = 2.f * w * (1.f - L * dy * dy * ir3);
-        t.hxy = 2.f * w * L * dx * dy * ir3;
-        t.hyy = 2.f * w * (1.f - L * dx * dx * ir3);
+        const float w2 = 2.f * w;
+        t.gx = w2 * (dx - L * dx * ir);
+        t.gy = w2 * (dy - L * dy * ir);
+        t.hxx = w2 * (1.f - L * dy * dy * ir3);
+        t.hxy = w2 * L * dx * dy * ir3;
+        t.hyy = w2 * (1.f - L * dx * dx * ir3);
     }
     return t;
 }
 
-__global__ __launch_bounds__(KKN_WPB * WAVE) void k_kk_newton(const int32_t *__restrict__ comp_off,
-                                                              const int32_t *__restrict__ ids,
-                                                              const int64_t *__restrict__ dist_off, int ncomp,
-                                                              const int32_t *__restrict__ dist, float *__restrict__ x,
-                                                              float *__restrict__ y, float l, float tol,
-                                                              int moves_per_node)
+// gradient term only (the corrections after a move and the first gradients)
+__device__ __forceinline__ float2 kkn_grad(float px, float py, float qx, float qy, float w, float L)
 {
-    __shared__ float2 lpos[KKN_WPB][KK_MAX];
-    const int k = blockIdx.x * KKN_WPB + (int)(threadIdx.x / WAVE);
-    if (k >= ncomp) return;  // wave-uniform
-    float2 *pos = lpos[threadIdx.x / WAVE];
+    const float dx = px - qx, dy = py - qy;
+    const float r2 = dx * dx + dy * dy;
+    if (!(r2 > 0.f)) return make_float2(0.f, 0.f);
+    const float f = 2.f * w * (1.f - L * __builtin_amdgcn_rsqf(r2));
+    return make_float2(f * dx, f * dy);
+}
+
+__device__ __forceinline__ float read_lane_f(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ float kkn_pick(const float (&a)[KK_MAX / WAVE], int q)
+{
+    return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+}
+
+__global__ __launch_bounds__(WAVE) void k_kk_newton(const int32_t *__restrict__ comp_off,
+                                                    const int32_t *__restrict__ ids,
+                                                    const int64_t *__restrict__ dist_off,
+                                                    const int32_t *__restrict__ sched,
+                                                    const int32_t *__restrict__ dist, float *__restrict__ x,
+                                                    float *__restrict__ y, float l, float tol, int moves_per_node)
+{
+    extern __shared__ float2 lds_kkn[];  // positions [KK_MAX], then the distances as bytes
+    float2 *pos = lds_kkn;
+    uint8_t *D8 = reinterpret_cast<uint8_t *>(lds_kkn + KK_MAX);
+    const int k = sched[blockIdx.x];
     const int lane = lane_id();
     const int c = ids[k];
     const int cb = comp_off[c], n = comp_off[c + 1] - cb;
-    const int32_t *D = dist + dist_off[k];
+    const int32_t *Dg = dist + dist_off[k];
     for (int j = lane; j < n; j += WAVE) pos[j] = make_float2(x[cb + j], y[cb + j]);
+    for (int e = lane; e < n * n; e += WAVE) D8[e] = (uint8_t)Dg[e];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // initial gradients, every node from scratch
-    float gx[KKN_Q], gy[KKN_Q];
+    // own nodes in registers: positions, gradients, sum_j w_ij
+    float xq[KKN_Q], yq[KKN_Q], gx[KKN_Q], gy[KKN_Q], swq[KKN_Q];
 #pragma unroll
     for (int q = 0; q < KKN_Q; ++q) {
         gx[q] = 0.f;
         gy[q] = 0.f;
+        swq[q] = 0.f;
+        xq[q] = 0.f;
+        yq[q] = 0.f;
         const int i = lane + WAVE * q;
         if (i < n) {
             const float2 pi = pos[i];
+            xq[q] = pi.x;
+            yq[q] = pi.y;
             for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
                 const float2 pj = pos[j];
-                const KKTerm t = kkn_term(pi.x, pi.y, pj.x, pj.y, (float)D[(int64_t)i * n + j], l);
-                gx[q] += t.gx;
-                gy[q] += t.gy;
+                const float d = (float)D8[i * n + j];
+                const float w = __builtin_amdgcn_rcpf(d * d);
+                const float2 t = kkn_grad(pi.x, pi.y, pj.x, pj.y, w, l * d);
+                gx[q] += t.x;
+                gy[q] += t.y;
+                swq[q] += w;
             }
         }
     }
@@ -285,47 +329,48 @@ __global__ __launch_bounds__(KKN_WPB * WAVE) void k_kk_newton(const int32_t *__r
         const float g2max = __uint_as_float((unsigned)(key >> 32));
         if (!(g2max >= tol2)) break;  // also ends on a NaN gradient
         const int m = (int)(~(unsigned)(key & 0xFFFFFFFFull));
-        const int32_t *Dm = D + (int64_t)m * n;
-        float dq[KKN_Q];
+        const int qm = m / WAVE, lm = m & (WAVE - 1);
+        const uint8_t *Dm = D8 + m * n;
+        float wq[KKN_Q], Lq[KKN_Q];
+        bool other[KKN_Q];
 #pragma unroll
         for (int q = 0; q < KKN_Q; ++q) {
             const int j = lane + WAVE * q;
-            dq[q] = j < n ? (float)Dm[j] : 1.f;
+            other[q] = j < n && j != m;
+            const float d = j < n ? (float)Dm[j] : 1.f;
+            wq[q] = __builtin_amdgcn_rcpf(d * d);
+            Lq[q] = l * d;
         }
-        const float2 old = pos[m];
-        float mx = old.x, my = old.y;
+        const float ox = read_lane_f(kkn_pick(xq, qm), lm), oy = read_lane_f(kkn_pick(yq, qm), lm);
+        const float swm = read_lane_f(kkn_pick(swq, qm), lm);
+        float mx = ox, my = oy;
         float Gx = 0.f, Gy = 0.f;
         // 2. Newton-Raphson steps on p_m
         for (int s = 0; s <= KKN_INNER; ++s) {
             float a[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // gx gy hxx hxy hyy
-            float sw = 0.f;
 #pragma unroll
             for (int q = 0; q < KKN_Q; ++q) {
-                const int j = lane + WAVE * q;
-                if (j < n && j != m) {
-                    const float2 pj = pos[j];
-                    const KKTerm t = kkn_term(mx, my, pj.x, pj.y, dq[q], l);
+                if (other[q]) {
+                    const KKTerm t = kkn_term(mx, my, xq[q], yq[q], wq[q], Lq[q]);
                     a[0] += t.gx;
                     a[1] += t.gy;
                     a[2] += t.hxx;
                     a[3] += t.hxy;
                     a[4] += t.hyy;
-                    sw += 1.0f / (dq[q] * dq[q]);
                 }
             }
             Gx = kkn_sum(a[0]);
             Gy = kkn_sum(a[1]);
             if (Gx * Gx + Gy * Gy < tol2 || s == KKN_INNER) break;
             const float hxx = kkn_sum(a[2]), hxy = kkn_sum(a[3]), hyy = kkn_sum(a[4]);
-            const float swt = kkn_sum(sw);
             const float det = hxx * hyy - hxy * hxy;
             float sx, sy;
             if (hxx > 0.f && det > 0.f) {
                 sx = -(hyy * Gx - hxy * Gy) / det;
                 sy = -(hxx * Gy - hxy * Gx) / det;
             } else {
-                sx = -Gx / (2.f * swt);
-                sy = -Gy / (2.f * swt);
+                sx = -Gx / (2.f * swm);
+                sy = -Gy / (2.f * swm);
             }
             // E_m(trial) < E_m(p_m), evaluated as a sum of per-pair changes
             // w ((r1 - L)^2 - (r0 - L)^2) = w (r1 - r0)(r1 + r0 - 2L) with
@@ -335,28 +380,22 @@ __global__ __launch_bounds__(KKN_WPB * WAVE) void k_kk_newton(const int32_t *__r
             float exq[KKN_Q], eyq[KKN_Q], r0q[KKN_Q];
 #pragma unroll
             for (int q = 0; q < KKN_Q; ++q) {
-                const int j = lane + WAVE * q;
-                exq[q] = 0.f;
-                eyq[q] = 0.f;
-                if (j < n && j != m) {
-                    const float2 pj = pos[j];
-                    exq[q] = mx - pj.x;
-                    eyq[q] = my - pj.y;
-                }
-                r0q[q] = sqrtf(exq[q] * exq[q] + eyq[q] * eyq[q]);
+                exq[q] = other[q] ? mx - xq[q] : 0.f;
+                eyq[q] = other[q] ? my - yq[q] : 0.f;
+                r0q[q] = __builtin_amdgcn_sqrtf(exq[q] * exq[q] + eyq[q] * eyq[q]);
             }
             bool moved = false;
             for (int h = 0; h <= 30; ++h) {
                 float de = 0.f;
 #pragma unroll
                 for (int q = 0; q < KKN_Q; ++q) {
-                    const int j = lane + WAVE * q;
-                    if (j < n && j != m) {
+                    if (other[q]) {
                         const float ux = exq[q] + sx, uy = eyq[q] + sy;
-                        const float r1 = sqrtf(ux * ux + uy * uy);
-                        const float rs = r1 + r0q[q];
-                        const float dr = rs > 0.f ? (2.f * (sx * exq[q] + sy * eyq[q]) + sx * sx + sy * sy) / rs : 0.f;
-                        de += dr * (rs - 2.f * l * dq[q]) / (dq[q] * dq[q]);
+                        const float rs = __builtin_amdgcn_sqrtf(ux * ux + uy * uy) + r0q[q];
+                        const float dr = rs > 0.f ? (2.f * (sx * exq[q] + sy * eyq[q]) + sx * sx + sy * sy) *
+                                                        __builtin_amdgcn_rcpf(rs)
+                                                  : 0.f;
+                        de += dr * (rs - 2.f * Lq[q]) * wq[q];
                     }
                 }
                 if (kkn_sum(de) < 0.f) {
@@ -371,29 +410,29 @@ __global__ __launch_bounds__(KKN_WPB * WAVE) void k_kk_newton(const int32_t *__r
             if (!moved) break;
         }
         // 3. p_m's move in every other gradient; m keeps the last one computed
-        if (lane == (m & (WAVE - 1))) pos[m] = make_float2(mx, my);
 #pragma unroll
         for (int q = 0; q < KKN_Q; ++q) {
-            const int i = lane + WAVE * q;
-            if (i < n && i != m) {
-                const float2 pi = pos[i];
-                const KKTerm to = kkn_term(pi.x, pi.y, old.x, old.y, dq[q], l);
-                const KKTerm tn = kkn_term(pi.x, pi.y, mx, my, dq[q], l);
-                gx[q] += tn.gx - to.gx;
-                gy[q] += tn.gy - to.gy;
+            if (other[q]) {
+                const float2 to = kkn_grad(xq[q], yq[q], ox, oy, wq[q], Lq[q]);
+                const float2 tn = kkn_grad(xq[q], yq[q], mx, my, wq[q], Lq[q]);
+                gx[q] += tn.x - to.x;
+                gy[q] += tn.y - to.y;
             }
-            if (i == m) {
+            if (q == qm && lane == lm) {
+                xq[q] = mx;
+                yq[q] = my;
                 gx[q] = Gx;
                 gy[q] = Gy;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    for (int j = lane; j < n; j += WAVE) {
-        x[cb + j] = pos[j].x;
-        y[cb + j] = pos[j].y;
+#pragma unroll
+    for (int q = 0; q < KKN_Q; ++q) {
+        const int i = lane + WAVE * q;
+        if (i < n) {
+            x[cb + i] = xq[q];
+            y[cb + i] = yq[q];
+        }
     }
 }
 
@@ -467,10 +506,24 @@ static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float 
 {
     if (p.batches.empty()) return;
     if (prm.minimiser == FL_KK_NEWTON) {
+        // one wave per component, the largest first (they set the time)
         const int nc = (int)p.ids.size();
-        hipLaunchKernelGGL(k_kk_newton, dim3((unsigned)((nc + KKN_WPB - 1) / KKN_WPB)), dim3(KKN_WPB * WAVE), 0,
-                           c->stream, p.d_off, p.d_ids, p.d_doff, nc, dist, x, y, (float)prm.l,
-                           (float)(prm.eps * prm.l), prm.steps);
+        std::vector<int32_t> sched(nc);
+        int64_t n2max = 1;
+        for (int k = 0; k < nc; ++k) {
+            sched[k] = k;
+            n2max = std::max<int64_t>(n2max, p.doff[k + 1] - p.doff[k]);
+        }
+        std::stable_sort(sched.begin(), sched.end(), [&](int a, int b) {
+            return p.doff[a + 1] - p.doff[a] > p.doff[b + 1] - p.doff[b];
+        });
+        int32_t *d_sched = ws<int32_t>(c, "kk_sched", (size_t)nc);
+        FL_CHECK_HIP(hipMemcpyAsync(d_sched, sched.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, c->stream));
+        const size_t lds = sizeof(float2) * KK_MAX + (size_t)n2max;  // positions, then n^2 distance bytes
+        FL_CHECK_HIP(hipFuncSetAttribute((const void *)k_kk_newton, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds));
+        hipLaunchKernelGGL(k_kk_newton, dim3((unsigned)nc), dim3(WAVE), lds, c->stream, p.d_off, p.d_ids, p.d_doff,
+                           (const int32_t *)d_sched, dist, x, y, (float)prm.l, (float)(prm.eps * prm.l), prm.steps);
     } else {
         hipLaunchKernelGGL(k_kk_steps, dim3((unsigned)p.batches.size()), dim3(256), 0, c->stream, p.d_batches,
                            p.d_off, p.d_doff, dist, x, y, (float)prm.l, prm.steps);

@@ -483,6 +483,120 @@ def kk_newton(dist, x, y, l: float = 1.0, eps: float = 1e-4, moves: int = 1000, 
     return x, y, int(k)
 
 
+# --- Cluster / decluster for Kamada-Kawai (sec. 3.1) ---------------------------
+#
+# Readings (the paper gives the two ideas in a sentence each):
+# * a node of degree 1 whose neighbour has degree >= 2 is contracted into the
+#   neighbour (one round; a 2-node component keeps both nodes);
+# * among the remaining nodes, those with exactly two remaining neighbours
+#   form chains; a chain whose two ends are distinct kept nodes is replaced
+#   by one edge as long as the chain (its nodes removed).  Chains that close
+#   a loop, pure cycles, and every chain but the one with the smallest node
+#   id between the same two ends are kept;
+# * both reductions keep the shortest-path distances between the remaining
+#   nodes, so the layout of the reduced graph is Kamada-Kawai on the kept
+#   nodes with their hop distances in the full component;
+# * declustering: the i-th node (1..k) of a removed chain from end a (the end
+#   with the smaller id) to end b goes to p_a + i/(k+1) (p_b - p_a); then the
+#   contracted leaves of node v, j-th of k in id order, go to distance l from
+#   p_v: at angle phi + (j - (k-1)/2) pi/k, phi the direction from the centre
+#   of gravity of the placed nodes to p_v, or, where p_v is that centre, at
+#   angle 2 pi j / k.
+
+
+def kk_reduce(row_ptr, col, leaves: bool = True, chains: bool = True):
+    """Which nodes of one component (local ids) the reductions remove and how
+    to place them again.  Returns (kept mask, chain records (node, a, b, i,
+    k), leaf records (node, v, j, k))."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    cl = np.asarray(col, dtype=np.int64)
+    n = rp.shape[0] - 1
+    nb = [list(cl[rp[i]:rp[i + 1]]) for i in range(n)]
+    deg = [len(v) for v in nb]
+    leaf = [leaves and deg[i] == 1 and deg[nb[i][0]] >= 2 for i in range(n)]
+    rest = [[j for j in nb[i] if not leaf[j]] for i in range(n)]
+    mid = [chains and not leaf[i] and len(rest[i]) == 2 for i in range(n)]
+    removed = [False] * n
+    seen = [False] * n
+    found = []  # (ends, chain nodes from the smaller end)
+    for s in range(n):
+        if not mid[s] or seen[s]:
+            continue
+        # walk both ways from s through chain nodes
+        sides = []
+        for first in rest[s]:
+            path, prev, cur = [], s, first
+            while mid[cur] and cur != s:
+                path.append(cur)
+                nxt = rest[cur][0] if rest[cur][0] != prev else rest[cur][1]
+                prev, cur = cur, nxt
+            sides.append((path, cur))
+        (p0, e0), (p1, e1) = sides
+        if e0 == s:  # a pure cycle
+            for v in [s] + p0:
+                seen[v] = True
+            continue
+        nodes = list(reversed(p0)) + [s] + p1  # from end e0 to end e1
+        for v in nodes:
+            seen[v] = True
+        if e0 == e1:
+            continue  # a loop
+        a, b = (e0, e1) if e0 < e1 else (e1, e0)
+        if a != e0:
+            nodes.reverse()
+        found.append(((a, b), nodes))
+    best = {}
+    for ends, nodes in found:
+        if ends not in best or min(nodes) < min(best[ends]):
+            best[ends] = nodes
+    chain_rec = []
+    for (a, b), nodes in best.items():
+        k = len(nodes)
+        for i, v in enumerate(nodes, start=1):
+            removed[v] = True
+            chain_rec.append((v, a, b, i, k))
+    leaf_rec = []
+    for v in range(n):
+        lv = sorted(u for u in nb[v] if leaf[u])
+        for j, u in enumerate(lv):
+            leaf_rec.append((u, v, j, len(lv)))
+    kept = np.array([not leaf[i] and not removed[i] for i in range(n)])
+    return kept, chain_rec, leaf_rec
+
+
+def kk_reduced_layout(row_ptr, col, x, y, l: float = 1.0, minimiser: str = "majorization", steps: int = 200,
+                      eps: float = 1e-3, leaves: bool = True, chains: bool = True):
+    """Kamada-Kawai of one component with the reductions of sec. 3.1 (the
+    readings above): lay out the kept nodes, then decluster."""
+    D = hop_distances(row_ptr, col)
+    kept, chain_rec, leaf_rec = kk_reduce(row_ptr, col, leaves, chains)
+    K = np.nonzero(kept)[0]
+    DK = np.ascontiguousarray(D[np.ix_(K, K)])
+    X, Y = _f64(x).copy(), _f64(y).copy()
+    if minimiser == "newton":
+        xk, yk, _ = kk_newton(DK, X[K], Y[K], l, eps, steps * K.shape[0])
+    else:
+        xk, yk = kk_steps(DK, X[K], Y[K], l, steps)
+    X[K], Y[K] = xk, yk
+    for v, a, b, i, k in chain_rec:
+        t = i / (k + 1)
+        X[v] = X[a] + t * (X[b] - X[a])
+        Y[v] = Y[a] + t * (Y[b] - Y[a])
+    placed = np.ones(X.shape[0], dtype=bool)
+    for u, _, _, _ in leaf_rec:
+        placed[u] = False
+    cx, cy = np.mean(X[placed]), np.mean(Y[placed])
+    for u, v, j, k in leaf_rec:
+        dx, dy = X[v] - cx, Y[v] - cy
+        if dx == 0.0 and dy == 0.0:
+            ang = 2.0 * math.pi * j / k
+        else:
+            ang = math.atan2(dy, dx) + (j - (k - 1) / 2.0) * math.pi / k
+        X[u] = X[v] + l * math.cos(ang)
+        Y[u] = Y[v] + l * math.sin(ang)
+    return X, Y, kept
+
+
 def rel_err(ax, ay, bx, by) -> float:
     """Norm-wise relative error |a - b|_2 / |b|_2 over all components."""
     num = np.sqrt(np.sum((_f64(ax) - _f64(bx)) ** 2 + (_f64(ay) - _f64(by)) ** 2))

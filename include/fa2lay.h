@@ -251,14 +251,34 @@ enum { FL_KK_MAJORIZATION = 0, FL_KK_NEWTON = 1 };
  *     and a step that finds no decrease ends the move.  Moves stop when every
  *     gradient norm is below eps * l, or after steps * n moves for a
  *     component of n nodes.  One wave per component. */
+/* Reductions (sec. 3.1, clustering before the layout, declustering after;
+ * fl_kk_layout and fl_layout only, as they need the graph):
+ *   FL_KK_REDUCE_LEAVES: a node with one edge whose neighbour has two or
+ *     more is contracted into the neighbour (one round; a 2-node component
+ *     keeps both);
+ *   FL_KK_REDUCE_CHAINS: among the remaining nodes, those with exactly two
+ *     remaining neighbours form chains; a chain between two distinct kept
+ *     nodes is removed and counts as one edge of its length (loops, pure
+ *     cycles and all but the chain with the smallest node id between the
+ *     same two ends stay).
+ * Both keep the hop distances between the remaining nodes, so these are laid
+ * out with their distances in the full component.  Declustering: the i-th of
+ * k nodes of a removed chain from end a (the smaller id) to end b goes to
+ * p_a + i/(k+1) (p_b - p_a); then the j-th of k contracted leaves of node v
+ * (id order) goes to distance l from p_v at angle phi + (j - (k-1)/2) pi/k,
+ * phi the direction from the centre of gravity of the placed nodes to p_v, or
+ * at angle 2 pi j / k when p_v is that centre. */
+enum { FL_KK_REDUCE_LEAVES = 1, FL_KK_REDUCE_CHAINS = 2 };
 typedef struct {
     double l;           /* rescaling constant: desired length per hop (> 0) */
     int32_t steps;      /* majorization: steps; Newton-Raphson: moves per node */
     int32_t minimiser;  /* FL_KK_MAJORIZATION or FL_KK_NEWTON */
     double eps;         /* Newton-Raphson: gradient-norm tolerance, in units of l (>= 0) */
+    int32_t reduce;     /* FL_KK_REDUCE_* flags (0: none) */
 } fl_kk_params;
 
-/* Defaults: l = 1, steps = 200, minimiser FL_KK_MAJORIZATION, eps = 1e-3. */
+/* Defaults: l = 1, steps = 200, minimiser FL_KK_MAJORIZATION, eps = 1e-3,
+ * reduce 0. */
 void fl_kk_default_params(fl_kk_params *prm);
 
 /* Hop distances of every component: dist [sum n_k^2] int32, component k's
@@ -276,7 +296,9 @@ fl_status fl_hop_distances(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offs
 fl_status fl_kk_steps(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *dist, float *x,
                       float *y, const fl_kk_params *prm);
 
-/* fl_hop_distances then fl_kk_steps, distances in the context workspace. */
+/* fl_hop_distances then fl_kk_steps (with the reductions of prm->reduce),
+ * distances in the context workspace.  FL_EINVAL from fl_kk_steps when
+ * prm->reduce is not 0. */
 fl_status fl_kk_layout(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
                        const int32_t *col_idx, float *x, float *y, const fl_kk_params *prm);
 

@@ -16,6 +16,7 @@
 //               components (at most 256 nodes in total, one thread per node),
 //               with positions and the batch's distances (uint8) in LDS.
 #include <algorithm>
+#include <string>
 
 #include "fl_common.h"
 #include "fl_tree.h"
@@ -436,6 +437,195 @@ __global__ __launch_bounds__(WAVE) void k_kk_newton(const int32_t *__restrict__ 
     }
 }
 
+// ---- cluster / decluster (sec. 3.1) ------------------------------------------
+// Per node of a component (global id), what the reductions did with it:
+//   rec = (kind, a, b, i), rec_k = k, kidx = index among the kept nodes or -1
+//   kind 0: kept;  kind 1: i-th of k nodes of a removed chain from end a to
+//   end b (a < b);  kind 2: a contracted leaf of node a, j = i-th of k.
+// One workgroup per component (<= 256 nodes, node v on thread v).
+__global__ __launch_bounds__(KK_MAX) void k_kk_reduce(const int32_t *__restrict__ comp_off,
+                                                      const int32_t *__restrict__ ids,
+                                                      const int32_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col, int flags,
+                                                      int4 *__restrict__ rec, int32_t *__restrict__ rec_k,
+                                                      int32_t *__restrict__ kidx, int32_t *__restrict__ kcount)
+{
+    __shared__ int deg[KK_MAX];
+    __shared__ uint8_t leaf[KK_MAX], mid[KK_MAX];
+    __shared__ int4 chains[KK_MAX];  // (a, b, smallest node id) of every candidate chain
+    __shared__ int nch;
+    __shared__ int lds_scan[KK_MAX / WAVE];
+    const int c = ids[blockIdx.x];
+    const int cb = comp_off[c], n = comp_off[c + 1] - cb;
+    const int v = threadIdx.x;
+    const bool valid = v < n;
+    const int r0 = valid ? row_ptr[cb + v] : 0, r1 = valid ? row_ptr[cb + v + 1] : 0;
+    if (valid) deg[v] = r1 - r0;
+    if (v == 0) nch = 0;
+    __syncthreads();
+    if (valid) leaf[v] = (flags & FL_KK_REDUCE_LEAVES) && deg[v] == 1 && deg[col[r0] - cb] >= 2;
+    __syncthreads();
+    int rest = 0;
+    if (valid && !leaf[v])
+        for (int e = r0; e < r1; ++e) rest += leaf[col[e] - cb] ? 0 : 1;
+    if (valid) mid[v] = (flags & FL_KK_REDUCE_CHAINS) && !leaf[v] && rest == 2;
+    __syncthreads();
+
+    int kind = 0, a = -1, b = -1, ii = 0, kk = 0, minid = v;
+    bool cand = false;
+    if (valid && mid[v]) {
+        int nb[2], q = 0;
+        for (int e = r0; e < r1 && q < 2; ++e)
+            if (!leaf[col[e] - cb]) nb[q++] = col[e] - cb;
+        int len[2], end[2];
+        for (int s = 0; s < 2; ++s) {
+            int prev = v, cur = nb[s], steps = 0;
+            while (mid[cur] && cur != v && steps < n) {
+                ++steps;
+                minid = min(minid, cur);
+                int nxt = -1;
+                for (int e = row_ptr[cb + cur]; e < row_ptr[cb + cur + 1]; ++e) {
+                    const int u = col[e] - cb;
+                    if (!leaf[u] && u != prev) {
+                        nxt = u;
+                        break;
+                    }
+                }
+                prev = cur;
+                cur = nxt < 0 ? v : nxt;
+            }
+            len[s] = steps;
+            end[s] = cur;
+        }
+        if (end[0] != v && end[1] != v && end[0] != end[1]) {
+            a = min(end[0], end[1]);
+            b = max(end[0], end[1]);
+            ii = (a == end[0] ? len[0] : len[1]) + 1;
+            kk = len[0] + len[1] + 1;
+            cand = true;
+            if (v == minid) {
+                const int slot = atomicAdd(&nch, 1);
+                chains[slot] = make_int4(a, b, minid, 0);
+            }
+        }
+    }
+    __syncthreads();
+    if (cand) {
+        // of the chains between the same two ends, only the one with the
+        // smallest node id is removed
+        const int m = nch;
+        for (int t = 0; t < m; ++t) {
+            const int4 o = chains[t];
+            if (o.x == a && o.y == b && o.z < minid) cand = false;
+        }
+    }
+    if (cand) kind = 1;
+    if (valid && leaf[v]) {
+        kind = 2;
+        a = col[r0] - cb;
+        int rank = 0, tot = 0;
+        for (int e = row_ptr[cb + a]; e < row_ptr[cb + a + 1]; ++e) {
+            const int u = col[e] - cb;
+            if (leaf[u]) {
+                ++tot;
+                rank += u < v ? 1 : 0;
+            }
+        }
+        ii = rank;
+        kk = tot;
+    }
+    const int kept = valid && kind == 0 ? 1 : 0;
+    int total;
+    const int pos = block_excl_scan<int, KK_MAX>(kept, lds_scan, total);
+    if (valid) {
+        rec[cb + v] = make_int4(kind, a, b, ii);
+        rec_k[cb + v] = kk;
+        kidx[cb + v] = kept ? pos : -1;
+    }
+    if (v == 0) kcount[blockIdx.x] = total;
+}
+
+// The kept nodes of each component into consecutive slots of the reduced
+// batch: positions, and the rows and columns of their hop distances.
+__global__ __launch_bounds__(KK_MAX) void k_kk_gather_reduced(
+    const int32_t *__restrict__ comp_off, const int32_t *__restrict__ ids, const int64_t *__restrict__ doff,
+    const int32_t *__restrict__ roff, const int64_t *__restrict__ rdoff, const int32_t *__restrict__ kidx,
+    const int32_t *__restrict__ dist, const float *__restrict__ x, const float *__restrict__ y,
+    int32_t *__restrict__ rdist, float *__restrict__ rx, float *__restrict__ ry)
+{
+    __shared__ int klist[KK_MAX];
+    const int k = blockIdx.x;
+    const int c = ids[k];
+    const int cb = comp_off[c], n = comp_off[c + 1] - cb;
+    const int kc = roff[k + 1] - roff[k];
+    const int v = threadIdx.x;
+    if (v < n && kidx[cb + v] >= 0) klist[kidx[cb + v]] = v;
+    __syncthreads();
+    if (v < kc) {
+        rx[roff[k] + v] = x[cb + klist[v]];
+        ry[roff[k] + v] = y[cb + klist[v]];
+    }
+    const int32_t *D = dist + doff[k];
+    int32_t *R = rdist + rdoff[k];
+    for (int e = v; e < kc * kc; e += blockDim.x) {
+        const int i = e / kc, j = e - i * kc;
+        R[e] = D[klist[i] * n + klist[j]];
+    }
+}
+
+// Kept nodes from the reduced layout, then removed chains on the segments
+// between their ends, then contracted leaves at distance l from their node.
+__global__ __launch_bounds__(KK_MAX) void k_kk_decluster(const int32_t *__restrict__ comp_off,
+                                                         const int32_t *__restrict__ ids,
+                                                         const int32_t *__restrict__ roff,
+                                                         const int4 *__restrict__ rec,
+                                                         const int32_t *__restrict__ rec_k,
+                                                         const int32_t *__restrict__ kidx,
+                                                         const float *__restrict__ rx, const float *__restrict__ ry,
+                                                         double l, float *__restrict__ x, float *__restrict__ y)
+{
+    __shared__ float2 p[KK_MAX];
+    __shared__ double lds_sum[KK_MAX / WAVE];
+    const int k = blockIdx.x;
+    const int c = ids[k];
+    const int cb = comp_off[c], n = comp_off[c + 1] - cb;
+    const int v = threadIdx.x;
+    const bool valid = v < n;
+    int4 r = make_int4(-1, 0, 0, 0);
+    int rk = 0;
+    if (valid) {
+        r = rec[cb + v];
+        rk = rec_k[cb + v];
+        if (r.x == 0) p[v] = make_float2(rx[roff[k] + kidx[cb + v]], ry[roff[k] + kidx[cb + v]]);
+    }
+    __syncthreads();
+    if (r.x == 1) {
+        const double t = (double)r.w / (double)(rk + 1);
+        const float2 pa = p[r.y], pb = p[r.z];
+        p[v] = make_float2((float)((double)pa.x + t * ((double)pb.x - (double)pa.x)),
+                           (float)((double)pa.y + t * ((double)pb.y - (double)pa.y)));
+    }
+    __syncthreads();
+    const bool placed = valid && r.x != 2;
+    const double cnt = block_sum<double, KK_MAX>(placed ? 1.0 : 0.0, lds_sum);
+    const double cx = block_sum<double, KK_MAX>(placed ? (double)p[v].x : 0.0, lds_sum) / cnt;
+    const double cy = block_sum<double, KK_MAX>(placed ? (double)p[v].y : 0.0, lds_sum) / cnt;
+    if (r.x == 2) {
+        const float2 pv = p[r.y];
+        const double dx = (double)pv.x - cx, dy = (double)pv.y - cy;
+        const double ang = (dx == 0.0 && dy == 0.0)
+                               ? 2.0 * M_PI * (double)r.w / (double)rk
+                               : atan2(dy, dx) + ((double)r.w - 0.5 * (double)(rk - 1)) * M_PI / (double)rk;
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        p[v] = make_float2((float)((double)pv.x + l * cs), (float)((double)pv.y + l * sn));
+    }
+    if (valid) {
+        x[cb + v] = p[v].x;
+        y[cb + v] = p[v].y;
+    }
+}
+
 }  // namespace
 
 // Components taken by Kamada-Kawai: `ids` (ascending) index the full offset
@@ -450,7 +640,8 @@ struct KKPlan {
     KKBatch *d_batches = nullptr;
 };
 
-static KKPlan kk_plan(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids)
+static KKPlan kk_plan(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,
+                      const std::string &tag = "kk")
 {
     KKPlan p;
     p.ids = ids;
@@ -475,10 +666,10 @@ static KKPlan kk_plan(fl_ctx *c, int n_all, const int32_t *off, const std::vecto
         p.batches.push_back(KKBatch{ids[k], ids[e - 1] + 1, k, 0});
         k = e;
     }
-    p.d_off = ws<int32_t>(c, "kk_off", n_all + 1);
-    p.d_ids = ws<int32_t>(c, "kk_ids", m > 0 ? m : 1);
-    p.d_doff = ws<int64_t>(c, "kk_doff", m + 1);
-    p.d_batches = ws<KKBatch>(c, "kk_batches", p.batches.size() + 1);
+    p.d_off = ws<int32_t>(c, (tag + "_off").c_str(), n_all + 1);
+    p.d_ids = ws<int32_t>(c, (tag + "_ids").c_str(), m > 0 ? m : 1);
+    p.d_doff = ws<int64_t>(c, (tag + "_doff").c_str(), m + 1);
+    p.d_batches = ws<KKBatch>(c, (tag + "_batches").c_str(), p.batches.size() + 1);
     FL_CHECK_HIP(hipMemcpyAsync(p.d_off, off, sizeof(int32_t) * (n_all + 1), hipMemcpyHostToDevice, c->stream));
     if (m > 0) FL_CHECK_HIP(hipMemcpyAsync(p.d_ids, p.ids.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c->stream));
     FL_CHECK_HIP(hipMemcpyAsync(p.d_doff, p.doff.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, c->stream));
@@ -541,7 +732,44 @@ void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vecto
     KKPlan p = kk_plan(c, n_all, off, ids);
     int32_t *dist = ws<int32_t>(c, "kk_dist", p.doff.back() > 0 ? p.doff.back() : 1);
     kk_bfs(c, p, row_ptr, col, dist);
-    kk_run_steps(c, p, dist, x, y, prm);
+    if (!prm.reduce) {
+        kk_run_steps(c, p, dist, x, y, prm);
+        return;
+    }
+    // cluster: which nodes stay; lay out the kept nodes with their hop
+    // distances in the full component (the reductions keep them); decluster
+    const int m = (int)ids.size();
+    const int64_t nodes = off[n_all];
+    int4 *rec = ws<int4>(c, "kkr_rec", (size_t)nodes);
+    int32_t *rec_k = ws<int32_t>(c, "kkr_reck", (size_t)nodes);
+    int32_t *kidx = ws<int32_t>(c, "kkr_kidx", (size_t)nodes);
+    int32_t *kcount = ws<int32_t>(c, "kkr_kcount", (size_t)m);
+    hipLaunchKernelGGL(k_kk_reduce, dim3((unsigned)m), dim3(KK_MAX), 0, c->stream, (const int32_t *)p.d_off,
+                       (const int32_t *)p.d_ids, row_ptr, col, (int)prm.reduce, rec, rec_k, kidx, kcount);
+    FL_LAUNCH_CHECK();
+    std::vector<int32_t> kc(m), roff(m + 1, 0);
+    FL_CHECK_HIP(hipMemcpyAsync(kc.data(), kcount, sizeof(int32_t) * m, hipMemcpyDeviceToHost, c->stream));
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < m; ++k) {
+        FL_REQUIRE(kc[k] >= 1, "Kamada-Kawai reduction removed every node of a component");
+        roff[k + 1] = roff[k] + kc[k];
+    }
+    std::vector<int32_t> rids(m);
+    for (int k = 0; k < m; ++k) rids[k] = k;
+    KKPlan rp = kk_plan(c, m, roff.data(), rids, "kkr");
+    int32_t *rdist = ws<int32_t>(c, "kkr_dist", rp.doff.back() > 0 ? rp.doff.back() : 1);
+    float *rx = ws<float>(c, "kkr_x", (size_t)roff[m]), *ry = ws<float>(c, "kkr_y", (size_t)roff[m]);
+    hipLaunchKernelGGL(k_kk_gather_reduced, dim3((unsigned)m), dim3(KK_MAX), 0, c->stream, (const int32_t *)p.d_off,
+                       (const int32_t *)p.d_ids, (const int64_t *)p.d_doff, (const int32_t *)rp.d_off,
+                       (const int64_t *)rp.d_doff, (const int32_t *)kidx, (const int32_t *)dist, (const float *)x,
+                       (const float *)y, rdist, rx, ry);
+    FL_LAUNCH_CHECK();
+    kk_run_steps(c, rp, rdist, rx, ry, prm);
+    hipLaunchKernelGGL(k_kk_decluster, dim3((unsigned)m), dim3(KK_MAX), 0, c->stream, (const int32_t *)p.d_off,
+                       (const int32_t *)p.d_ids, (const int32_t *)rp.d_off, (const int4 *)rec, (const int32_t *)rec_k,
+                       (const int32_t *)kidx, (const float *)rx, (const float *)ry, prm.l, x, y);
+    FL_LAUNCH_CHECK();
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
 }
 
 void check_kk_params(const fl_kk_params *p)
@@ -552,6 +780,7 @@ void check_kk_params(const fl_kk_params *p)
     FL_REQUIRE(p->minimiser == FL_KK_MAJORIZATION || p->minimiser == FL_KK_NEWTON,
                "Kamada-Kawai: unknown minimiser");
     FL_REQUIRE(std::isfinite(p->eps) && p->eps >= 0.0, "Kamada-Kawai: need a finite eps >= 0");
+    FL_REQUIRE((p->reduce & ~(FL_KK_REDUCE_LEAVES | FL_KK_REDUCE_CHAINS)) == 0, "Kamada-Kawai: unknown reduce flags");
 }
 
 static std::vector<int32_t> iota_ids(int n)
@@ -574,6 +803,7 @@ void fl_kk_default_params(fl_kk_params *p)
     p->steps = 200;
     p->minimiser = FL_KK_MAJORIZATION;
     p->eps = 1e-3;
+    p->reduce = 0;
 }
 
 fl_status fl_hop_distances(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, const int32_t *row_ptr,
@@ -593,6 +823,7 @@ fl_status fl_kk_steps(fl_ctx *c, int32_t n_comp, const int32_t *comp_offsets, co
     FL_API_BEGIN(c)
     FL_REQUIRE(n_comp >= 1 && comp_offsets && dist && x && y, "fl_kk_steps: bad arguments");
     check_kk_params(prm);
+    FL_REQUIRE(prm->reduce == 0, "fl_kk_steps: the reductions need the graph (use fl_kk_layout)");
     KKPlan p = kk_plan(c, n_comp, comp_offsets, iota_ids(n_comp));
     kk_run_steps(c, p, dist, x, y, *prm);
     FL_API_END(c)

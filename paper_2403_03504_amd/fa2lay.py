@@ -27,6 +27,7 @@ GRAV_STRONG_MASS, GRAV_FA2_CONST, GRAV_STRONG_UNIT = 0, 1, 2
 SWING_PAPER, SWING_FA2 = 0, 1
 REP_EXACT, REP_FMM, REP_AUTO = 0, 1, 2
 KK_MAJORIZATION, KK_NEWTON = 0, 1
+KK_REDUCE_LEAVES, KK_REDUCE_CHAINS = 1, 2
 TUNE_MAX_BUCKETS = 16
 PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact", "bh")
 
@@ -63,7 +64,7 @@ class _State(ctypes.Structure):
 
 class KKParams(ctypes.Structure):
     _fields_ = [("l", ctypes.c_double), ("steps", ctypes.c_int32), ("minimiser", ctypes.c_int32),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("reduce", ctypes.c_int32)]
 
 
 class AssembleParams(ctypes.Structure):

@@ -266,8 +266,9 @@ enum { FL_KK_MAJORIZATION = 0, FL_KK_NEWTON = 1 };
  * k nodes of a removed chain from end a (the smaller id) to end b goes to
  * p_a + i/(k+1) (p_b - p_a); then the j-th of k contracted leaves of node v
  * (id order) goes to distance l from p_v at angle phi + (j - (k-1)/2) pi/k,
- * phi the direction from the centre of gravity of the placed nodes to p_v, or
- * at angle 2 pi j / k when p_v is that centre. */
+ * phi the direction from the centre of gravity c of the placed nodes to p_v,
+ * or at angle 2 pi j / k when |p_v - c| <= 1e-4 (R + l), R the largest
+ * |p - c| of a placed node. */
 enum { FL_KK_REDUCE_LEAVES = 1, FL_KK_REDUCE_CHAINS = 2 };
 typedef struct {
     double l;           /* rescaling constant: desired length per hop (> 0) */

@@ -500,8 +500,9 @@ def kk_newton(dist, x, y, l: float = 1.0, eps: float = 1e-4, moves: int = 1000, 
 #   with the smaller id) to end b goes to p_a + i/(k+1) (p_b - p_a); then the
 #   contracted leaves of node v, j-th of k in id order, go to distance l from
 #   p_v: at angle phi + (j - (k-1)/2) pi/k, phi the direction from the centre
-#   of gravity of the placed nodes to p_v, or, where p_v is that centre, at
-#   angle 2 pi j / k.
+#   of gravity c of the placed nodes to p_v, or, where p_v is that centre
+#   (|p_v - c| <= 1e-4 (R + l), R the largest |p - c| of a placed node, so
+#   that rounding cannot decide a symmetric case), at angle 2 pi j / k.
 
 
 def kk_reduce(row_ptr, col, leaves: bool = True, chains: bool = True):
@@ -586,9 +587,10 @@ def kk_reduced_layout(row_ptr, col, x, y, l: float = 1.0, minimiser: str = "majo
     for u, _, _, _ in leaf_rec:
         placed[u] = False
     cx, cy = np.mean(X[placed]), np.mean(Y[placed])
+    R = np.max(np.hypot(X[placed] - cx, Y[placed] - cy))
     for u, v, j, k in leaf_rec:
         dx, dy = X[v] - cx, Y[v] - cy
-        if dx == 0.0 and dy == 0.0:
+        if math.hypot(dx, dy) <= 1e-4 * (R + l):
             ang = 2.0 * math.pi * j / k
         else:
             ang = math.atan2(dy, dx) + (j - (k - 1) / 2.0) * math.pi / k

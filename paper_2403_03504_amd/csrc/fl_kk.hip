@@ -610,10 +610,21 @@ __global__ __launch_bounds__(KK_MAX) void k_kk_decluster(const int32_t *__restri
     const double cnt = block_sum<double, KK_MAX>(placed ? 1.0 : 0.0, lds_sum);
     const double cx = block_sum<double, KK_MAX>(placed ? (double)p[v].x : 0.0, lds_sum) / cnt;
     const double cy = block_sum<double, KK_MAX>(placed ? (double)p[v].y : 0.0, lds_sum) / cnt;
+    // R: the largest distance of a placed node from the centre; p_v within
+    // 1e-4 (R + l) of the centre counts as the centre (rounding must not
+    // decide a symmetric case)
+    double rr = placed ? hypot((double)p[v].x - cx, (double)p[v].y - cy) : 0.0;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) rr = fmax(rr, __shfl_xor(rr, o, WAVE));
+    if (lane_id() == 0) lds_sum[v / WAVE] = rr;
+    __syncthreads();
+    double R = 0.0;
+#pragma unroll
+    for (int u = 0; u < KK_MAX / WAVE; ++u) R = fmax(R, lds_sum[u]);
     if (r.x == 2) {
         const float2 pv = p[r.y];
         const double dx = (double)pv.x - cx, dy = (double)pv.y - cy;
-        const double ang = (dx == 0.0 && dy == 0.0)
+        const double ang = hypot(dx, dy) <= 1e-4 * (R + l)
                                ? 2.0 * M_PI * (double)r.w / (double)rk
                                : atan2(dy, dx) + ((double)r.w - 0.5 * (double)(rk - 1)) * M_PI / (double)rk;
         double sn, cs;

@@ -159,34 +159,37 @@ def batched(args, fl, w, np, torch) -> dict:
 
 def kk_minimisers(args, ctx, g, offs, fl, np, torch) -> dict:
     """The batched workload's small components laid out from the same start by
-    the two Kamada-Kawai minimisers: localized stress majorization (all nodes
+    the two Kamada-Kawai minimisers, localized stress majorization (all nodes
     of a component at once, 200 steps) and the paper's Newton-Raphson (one
     node at a time, until every gradient norm < 1e-3 l, at most 200 moves per
-    node).  Time of the minimiser launch, and the total energy by the FP64
-    oracle."""
+    node), each also with the cluster/decluster reductions of sec. 3.1.  Time
+    of the whole fl_kk_layout call (hop distances included) and the total
+    energy of the result by the FP64 oracle."""
     from oracle import oracle as orc
     sizes = np.diff(offs)
     small = np.nonzero(sizes <= 256)[0]
     # the small components are a prefix of the batched workload
     assert np.all(small == np.arange(small.size))
     ns = int(offs[small.size])
-    sub_src, sub_dst = g.src, g.dst
-    keep = (sub_src < ns) & (sub_dst < ns)
+    keep = (g.src < ns) & (g.dst < ns)
     dev = torch.device("cuda", 0)
-    G = ctx.build_csr(ns, torch.from_numpy(sub_src[keep]).to(dev), torch.from_numpy(sub_dst[keep]).to(dev))
+    G = ctx.build_csr(ns, torch.from_numpy(g.src[keep]).to(dev), torch.from_numpy(g.dst[keep]).to(dev))
     coff = offs[: small.size + 1].astype(np.int32)
     dist, doff = ctx.hop_distances(G, coff)
     D = dist.cpu().numpy()
     out = {"components": int(small.size), "nodes": ns}
-    for name, kw in (("majorization", dict(minimiser=fl.KK_MAJORIZATION, steps=200)),
-                     ("newton", dict(minimiser=fl.KK_NEWTON, steps=200, eps=1e-3))):
+    variants = (("majorization", dict(minimiser=fl.KK_MAJORIZATION, steps=200)),
+                ("majorization_reduced", dict(minimiser=fl.KK_MAJORIZATION, steps=200, reduce=3)),
+                ("newton", dict(minimiser=fl.KK_NEWTON, steps=200, eps=1e-3)),
+                ("newton_reduced", dict(minimiser=fl.KK_NEWTON, steps=200, eps=1e-3, reduce=3)))
+    for name, kw in variants:
         best = None
         for _ in range(2):
             x = torch.from_numpy(g.x[:ns]).to(dev)
             y = torch.from_numpy(g.y[:ns]).to(dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ctx.kk_steps(coff, dist, x, y, fl.kk_params(**kw))
+            ctx.kk_layout(G, coff, x, y, fl.kk_params(**kw))
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             if best is None or wall < best[0]:
@@ -200,50 +203,6 @@ def kk_minimisers(args, ctx, g, offs, fl, np, torch) -> dict:
         out[name] = {"ms": wall * 1e3, "energy": energy}
         log(f"KK {name}: {wall * 1e3:.1f} ms for {small.size} components, total energy {energy:.6g}")
     out["newton_over_majorization_energy"] = out["newton"]["energy"] / out["majorization"]["energy"]
-    return out
-
-
-def assembly(args, ctx, G, g, xl, yl, fl, np, torch) -> dict:
-    """The components just laid out, assembled into one drawing (density
-    rescaling, meta-graph layout in groups of up to 256, placement); the
-    oracle's assembly of the same components is timed beside it."""
-    label, K = ctx.components(G)
-    order = np.random.Generator(np.random.PCG64(args.seed + 101)).permutation(K).astype(np.int32)
-    prm = fl.assemble_params()
-    best = None
-    for _ in range(3):  # the first call sizes the workspaces
-        x, y = xl.clone(), yl.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.assemble(label, K, order, x, y, prm)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        if best is None or wall < best[0]:
-            best = (wall, st)
-    wall, st = best
-    sizes, groups = [K], []
-    while sizes[-1] > prm.max_group:
-        sizes.append(-(-sizes[-1] // prm.max_group))
-    pairs = 0
-    for m in sizes:
-        for a in range(0, m, prm.max_group):
-            gsz = min(prm.max_group, m - a)
-            pairs += gsz * (gsz - 1)
-    out = {"components": K, "levels": st["levels"], "groups": st["groups"], "sweeps": prm.sweeps,
-           "max_group": prm.max_group, "wall_ms": wall * 1e3,
-           "meta_pair_updates": pairs * prm.sweeps}
-    log(f"assembly: {K} components, {st['levels']} levels, {st['groups']} groups, wall {wall * 1e3:.2f} ms")
-    if not args.no_cpu:
-        from oracle import oracle as orc
-        lab = label.cpu().numpy()
-        ids = np.argsort(lab, kind="stable")
-        off = np.concatenate([[0], np.cumsum(np.unique(lab, return_counts=True)[1])])
-        t0 = time.perf_counter()
-        orc.assemble(g.x[ids].astype(np.float64), g.y[ids].astype(np.float64), off, order,
-                     orc.AssembleParams(sweeps=prm.sweeps, max_group=prm.max_group))
-        out["oracle_ms"] = (time.perf_counter() - t0) * 1e3
-        out["oracle_cores"] = 1  # the sweeps and the all-pairs loops run on one core
-        log(f"assembly oracle: {out['oracle_ms']:.0f} ms")
     return out
 
 

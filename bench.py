@@ -206,6 +206,50 @@ def kk_minimisers(args, ctx, g, offs, fl, np, torch) -> dict:
     return out
 
 
+def assembly(args, ctx, G, g, xl, yl, fl, np, torch) -> dict:
+    """The components just laid out, assembled into one drawing (density
+    rescaling, meta-graph layout in groups of up to 256, placement); the
+    oracle's assembly of the same components is timed beside it."""
+    label, K = ctx.components(G)
+    order = np.random.Generator(np.random.PCG64(args.seed + 101)).permutation(K).astype(np.int32)
+    prm = fl.assemble_params()
+    best = None
+    for _ in range(3):  # the first call sizes the workspaces
+        x, y = xl.clone(), yl.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.assemble(label, K, order, x, y, prm)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if best is None or wall < best[0]:
+            best = (wall, st)
+    wall, st = best
+    sizes, groups = [K], []
+    while sizes[-1] > prm.max_group:
+        sizes.append(-(-sizes[-1] // prm.max_group))
+    pairs = 0
+    for m in sizes:
+        for a in range(0, m, prm.max_group):
+            gsz = min(prm.max_group, m - a)
+            pairs += gsz * (gsz - 1)
+    out = {"components": K, "levels": st["levels"], "groups": st["groups"], "sweeps": prm.sweeps,
+           "max_group": prm.max_group, "wall_ms": wall * 1e3,
+           "meta_pair_updates": pairs * prm.sweeps}
+    log(f"assembly: {K} components, {st['levels']} levels, {st['groups']} groups, wall {wall * 1e3:.2f} ms")
+    if not args.no_cpu:
+        from oracle import oracle as orc
+        lab = label.cpu().numpy()
+        ids = np.argsort(lab, kind="stable")
+        off = np.concatenate([[0], np.cumsum(np.unique(lab, return_counts=True)[1])])
+        t0 = time.perf_counter()
+        orc.assemble(g.x[ids].astype(np.float64), g.y[ids].astype(np.float64), off, order,
+                     orc.AssembleParams(sweeps=prm.sweeps, max_group=prm.max_group))
+        out["oracle_ms"] = (time.perf_counter() - t0) * 1e3
+        out["oracle_cores"] = 1  # the sweeps and the all-pairs loops run on one core
+        log(f"assembly oracle: {out['oracle_ms']:.0f} ms")
+    return out
+
+
 def bh_comparison(args, ctx, G, x, y, tg, ex, ey, fl, orc, np, torch) -> dict:
     """Barnes-Hut (the O(N log N) method the FMM replaces) against the FMM on
     the same positions: repulsion time per evaluation (tree build included;

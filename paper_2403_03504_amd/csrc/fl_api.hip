@@ -119,6 +119,8 @@ void fl_destroy(fl_ctx *c)
             (void)hipStreamSynchronize(s);
             (void)hipStreamDestroy(s);
         }
+    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_fork2, c->ev_join2})
+        if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (auto &kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);

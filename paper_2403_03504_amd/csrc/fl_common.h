@@ -84,7 +84,12 @@ struct fl_ctx {
     fl_tuning tuning{};          // read by FL_REP_AUTO (set in fl_create)
     // private streams (created on first use, destroyed with the context) and
     // branch contexts for concurrent runs of independent systems
-    hipStream_t aux[2] = {nullptr, nullptr};
+    hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
+    // fork/join of the branches of an iteration: the attraction gathers and
+    // the FMM's upward pass (created on first use); `branches` off runs them
+    // in line on the context's stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
+    bool branches = true;
     std::vector<fl_ctx *> sub;
     bool own_stream = false;     // a branch context destroys its stream
     int32_t seg1_n = -1;         // n of the cached one-system descriptor
@@ -140,7 +145,7 @@ fl_fa2_params resolve_repulsion(const fl_tuning &t, int64_t n, const fl_fa2_para
 // Throws FL_EINVAL unless t is a well-formed table.
 void check_tuning(const fl_tuning &t);
 
-// Private stream i (0 or 1) of the context, created on first use.
+// Private stream i (0..3) of the context, created on first use.
 hipStream_t aux_stream(fl_ctx *c, int i);
 // Branch context b (with its own stream), created on first use.
 fl_ctx *sub_ctx(fl_ctx *c, size_t b);

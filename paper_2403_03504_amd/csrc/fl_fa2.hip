@@ -1,11 +1,14 @@
 // ForceAtlas2 iteration of the paper's sec. 3.2 on one GPU:
 //   repulsion  exact O(n^2) (LDS-tiled) or FMM (fl_fmm.hip)
-//   k_combine  linear CSR attraction (FP64 sums; rows longer than 32 entries
-//              are cut into 256-entry chunks summed by one wave each and
-//              added in chunk order), gravity, F = F_r + F_a + F_g,
-//              per-node swing |F - F'| and traction |F + F'| in FP64, block
-//              partial sums; the last block to finish adds the partials in a
-//              fixed order and sets the global speed s_G (no host round trip)
+//   attraction linear CSR attraction in FP64 sums (rows longer than 32
+//              entries are cut into 256-entry chunks summed by one wave each
+//              and added in chunk order); in an iteration these gathers
+//              (k_attract_chunks, k_attract_rows) run on a branch stream
+//              beside the repulsion and k_combine reads their sums
+//   k_combine  gravity, F = F_r + F_a + F_g, per-node swing |F - F'| and
+//              traction |F + F'| in FP64, per-tile partial sums; k_speed adds
+//              each system's partials in a fixed order and sets its global
+//              speed s_G (no host round trip)
 //   k_update   per-node speed and move p += s_i F, F' <- F
 // There are no floating-point atomics: a run is bitwise reproducible.
 #include <algorithm>
@@ -122,6 +125,49 @@ __global__ __launch_bounds__(NT) void k_attract_chunks(const int32_t *__restrict
     }
 }
 
+// The attraction sum of every row (the same arithmetic, in the same order,
+// as k_combine's own): light rows by their gathers, heavy rows from their
+// chunk sums.  Lets the gathers run on a branch stream beside the repulsion.
+__global__ __launch_bounds__(NT) void k_attract_rows(int n, const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const float2 *__restrict__ xy,
+                                                     const int32_t *__restrict__ choff,
+                                                     const double2 *__restrict__ csum, double2 *__restrict__ asum)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ax = 0.0, ay = 0.0;
+    const float2 pi = xy[i];
+    const double xi = pi.x, yi = pi.y;
+    const int rb = row_ptr[i], re = row_ptr[i + 1];
+    if (re - rb <= HEAVY) {
+        int e = rb;
+        for (; e + 4 <= re; e += 4) {  // four gathers in flight
+            const int j0 = col[e], j1 = col[e + 1], j2 = col[e + 2], j3 = col[e + 3];
+            const float2 p0 = xy[j0], p1 = xy[j1], p2 = xy[j2], p3 = xy[j3];
+            ax += (double)p0.x - xi;
+            ay += (double)p0.y - yi;
+            ax += (double)p1.x - xi;
+            ay += (double)p1.y - yi;
+            ax += (double)p2.x - xi;
+            ay += (double)p2.y - yi;
+            ax += (double)p3.x - xi;
+            ay += (double)p3.y - yi;
+        }
+        for (; e < re; ++e) {
+            const float2 pj = xy[col[e]];
+            ax += (double)pj.x - xi;
+            ay += (double)pj.y - yi;
+        }
+    } else {
+        for (int c = choff[i]; c < choff[i + 1]; ++c) {
+            const double2 v = csum[c];
+            ax += v.x;
+            ay += v.y;
+        }
+    }
+    asum[i] = make_double2(ax, ay);
+}
+
 // ---- attraction + gravity + combine + swing/traction ---------------------------
 // One block per system tile: forces, and per-tile FP64 partial sums of swing
 // and traction.  k_speed then adds each system's tile partials in tile order
@@ -137,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restri
                                                 float *__restrict__ fay, float *__restrict__ fgx,
                                                 float *__restrict__ fgy, double2 *__restrict__ part,
                                                 int32_t *__restrict__ flags, const int32_t *__restrict__ choff,
-                                                const double2 *__restrict__ csum)
+                                                const double2 *__restrict__ csum, const double2 *__restrict__ asum)
 {
     __shared__ double lds[NT / WAVE];
     const int2 tl = sg.tiles[blockIdx.x];
@@ -149,7 +195,11 @@ __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restri
         const float2 pi = xy[i];
         const double xi = pi.x, yi = pi.y;
         const int rb = row_ptr[i], re = row_ptr[i + 1];
-        if (re - rb <= HEAVY) {
+        if (asum) {
+            const double2 a = asum[i];
+            ax = a.x;
+            ay = a.y;
+        } else if (re - rb <= HEAVY) {
             int e = rb;
             for (; e + 4 <= re; e += 4) {  // four gathers in flight
                 const int j0 = col[e], j1 = col[e + 1], j2 = col[e + 2], j3 = col[e + 3];
@@ -412,11 +462,12 @@ static AttractPlan attract_plan(fl_ctx *c, const GraphArgs &g, int32_t *choff = 
 
 // positions interleaved (x, y) so each neighbour is one 8-byte gather
 static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const AttractPlan &a, const float *x,
-                                    const float *y, double2 *csum)
+                                    const float *y, double2 *csum, hipStream_t s = nullptr)
 {
+    if (!s) s = c->stream;
     float2 *xy = ws<float2>(c, "at_xy", g.n);
-    hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, c->stream, x, y, g.n, xy);
-    hipLaunchKernelGGL(k_attract_chunks, dim3(1024), dim3(NT), 0, c->stream, g.row_ptr, g.col, (const float2 *)xy,
+    hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, s, x, y, g.n, xy);
+    hipLaunchKernelGGL(k_attract_chunks, dim3(1024), dim3(NT), 0, s, g.row_ptr, g.col, (const float2 *)xy,
                        a.chunks, a.choff + g.n, csum);
     FL_LAUNCH_CHECK();
     return xy;
@@ -455,7 +506,11 @@ struct Sys {
     fl_fa2_params prm;
 };
 
-// one iteration; flags must have been cleared by the caller
+// one iteration; flags must have been cleared by the caller.  Unless phases
+// are being timed (or the context's branches are off), the attraction
+// gathers run on a branch stream (fork and join by events, which graph
+// capture records as parallel branches) beside the repulsion's tree, lists
+// and passes; the combine then reads their sums.
 static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
 {
     fl_ctx *c = b.c;
@@ -464,17 +519,35 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
     float *fcx = ws<float>(c, "fa2_fcx", n);
     float *fcy = ws<float>(c, "fa2_fcy", n);
     double2 *part = ws<double2>(c, "fa2_part", (size_t)b.sg.ntiles);
+    double2 *csum = ws<double2>(c, "at_csum", b.ap.cap);
     const int first = b.st.iter == 0 ? 1 : 0;
-    repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
+    const float2 *xy = nullptr;
+    double2 *asum = nullptr;
+    if (!c->timing && c->branches) {
+        asum = ws<double2>(c, "fa2_asum", n);
+        hipStream_t as = aux_stream(c, 2);
+        if (!c->ev_fork) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        if (!c->ev_join) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        FL_CHECK_HIP(hipEventRecord(c->ev_fork, c->stream));
+        FL_CHECK_HIP(hipStreamWaitEvent(as, c->ev_fork, 0));
+        xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as);
+        hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, NT)), dim3(NT), 0, as, n, b.g.row_ptr, b.g.col, xy,
+                           (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
+        FL_LAUNCH_CHECK();
+        FL_CHECK_HIP(hipEventRecord(c->ev_join, as));
+        repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
+        FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    } else {
+        repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
+    }
     {
         PhaseTimer pt(c, FL_PH_ATTRACT);
-        double2 *csum = ws<double2>(c, "at_csum", b.ap.cap);
-        const float2 *xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum);
+        if (!xy) xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum);
         hipLaunchKernelGGL(k_combine, dim3(b.sg.ntiles), dim3(NT), 0, c->stream, b.sg, b.g.row_ptr, b.g.col,
                            b.g.deg, xy, (const float2 *)fr, consts(&b.prm),
                            (const float *)b.st.fx_prev, (const float *)b.st.fy_prev, first, fcx, fcy,
                            (float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, part, flags,
-                           (const int32_t *)b.ap.choff, (const double2 *)csum);
+                           (const int32_t *)b.ap.choff, (const double2 *)csum, (const double2 *)asum);
         hipLaunchKernelGGL(k_speed, dim3(std::min(b.sg.K, 1024)), dim3(NT), 0, c->stream, b.sg,
                            (const double2 *)part, consts(&b.prm), first, b.st.scalars, ring, ring_it);
         FL_LAUNCH_CHECK();
@@ -579,6 +652,7 @@ void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &in, int iters, int3
             fl_ctx *bc = graphs ? sub_ctx(c, k) : c;
             if (graphs) {
                 bc->timing = false;
+                bc->branches = c->branches;
                 FL_CHECK_HIP(hipStreamWaitEvent(bc->stream, ready, 0));
             }
             const std::string tag = "bt" + std::to_string(graphs ? 0 : k);
@@ -685,7 +759,8 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
         hipLaunchKernelGGL(k_combine, dim3(sg.ntiles), dim3(NT), 0, c->stream, sg, row_ptr, col_idx, deg, xy,
                            (const float2 *)nullptr, consts(prm), (const float *)nullptr,
                            (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
-                           (double2 *)nullptr, flags, (const int32_t *)ap.choff, (const double2 *)csum);
+                           (double2 *)nullptr, flags, (const int32_t *)ap.choff, (const double2 *)csum,
+                           (const double2 *)nullptr);
         FL_LAUNCH_CHECK();
     }
     FL_API_END(c)

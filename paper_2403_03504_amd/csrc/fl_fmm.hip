@@ -557,36 +557,52 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
 #undef FL_P2P_PAIR
 
 template <int P>
-void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float2 *fr)
+struct FmmBufs {
+    float2 *M, *Lp, *Ll, *T;
+    bool fresh;  // the M2M table still has to be written
+};
+
+template <int P>
+FmmBufs<P> fmm_bufs(fl_ctx *c, const TreeBufs &t)
 {
-    const int64_t cap = t.cells_cap, lcap = t.leaves_cap;
-    float2 *M = ws<float2>(c, "f_M", (size_t)cap * (P + 1));
-    float2 *Lp = ws<float2>(c, "f_Lp", (size_t)cap * (P + 1));
-    float2 *Ll = ws<float2>(c, "f_Lleaf", (size_t)lcap * (P + 1));
+    FmmBufs<P> b;
+    b.M = ws<float2>(c, "f_M", (size_t)t.cells_cap * (P + 1));
+    b.Lp = ws<float2>(c, "f_Lp", (size_t)t.cells_cap * (P + 1));
+    b.Ll = ws<float2>(c, "f_Lleaf", (size_t)t.leaves_cap * (P + 1));
+    std::string tn = "f_m2m_T" + std::to_string(P);
+    auto it = c->bufs.find(tn);
+    b.fresh = it == c->bufs.end() || !it->second.p;
+    b.T = ws<float2>(c, tn.c_str(), 4 * (P + 1) * (P + 1));
+    return b;
+}
+
+// upward pass: outgoing expansions of the leaves, shifted up to the root
+template <int P>
+void upward_p(fl_ctx *c, hipStream_t s, const TreeBufs &t, const FmmBufs<P> &b)
+{
     TreeView tv = view(t);
-    const unsigned gl = grid_for(lcap, 256, 2048);
-    const unsigned gc = grid_for(cap, 256, 2048);
-    {
-        PhaseTimer pt(c, FL_PH_UPWARD);
-        std::string tn = "f_m2m_T" + std::to_string(P);
-        auto it = c->bufs.find(tn);
-        const bool fresh = it == c->bufs.end() || !it->second.p;
-        float2 *T = ws<float2>(c, tn.c_str(), 4 * (P + 1) * (P + 1));
-        if (fresh) hipLaunchKernelGGL(k_m2m_table<P>, dim3(1), dim3(256), 0, c->stream, T);
-        hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(lcap, 4, 16384)), dim3(256), 0, c->stream, tv,
-                           (const float4 *)t.part, (const int32_t *)t.leaf_cell, M);
-        const int64_t nsub = (int64_t)t.s.K << (2 * M2M_CUT);
-        hipLaunchKernelGGL(k_m2m_sub<P>, dim3((unsigned)std::min<int64_t>(nsub, 2048)), dim3(256), 0, c->stream, tv,
-                           (const float2 *)T, M);
-        hipLaunchKernelGGL(k_m2m_top<P>, dim3((unsigned)std::min(t.s.K, 1024)), dim3(256), 0, c->stream, tv,
-                           (const float2 *)T, M);
-        FL_LAUNCH_CHECK();
-    }
+    if (b.fresh) hipLaunchKernelGGL(k_m2m_table<P>, dim3(1), dim3(256), 0, s, b.T);
+    hipLaunchKernelGGL(k_p2m<P>, dim3(grid_for(t.leaves_cap, 4, 16384)), dim3(256), 0, s, tv, (const float4 *)t.part,
+                       (const int32_t *)t.leaf_cell, b.M);
+    const int64_t nsub = (int64_t)t.s.K << (2 * M2M_CUT);
+    hipLaunchKernelGGL(k_m2m_sub<P>, dim3((unsigned)std::min<int64_t>(nsub, 2048)), dim3(256), 0, s, tv,
+                       (const float2 *)b.T, b.M);
+    hipLaunchKernelGGL(k_m2m_top<P>, dim3((unsigned)std::min(t.s.K, 1024)), dim3(256), 0, s, tv, (const float2 *)b.T,
+                       b.M);
+    FL_LAUNCH_CHECK();
+}
+
+// incoming expansions (M2L, P2L, L2L) and the evaluation at the particles
+template <int P>
+void downward_eval_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b, float kr, float2 *fr)
+{
+    TreeView tv = view(t);
+    const unsigned gl = grid_for(t.leaves_cap, 256, 2048);
     {
         PhaseTimer pt(c, FL_PH_M2L);
-        hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(cap, 8, 16384)), dim3(256), 0, c->stream, tv,
-                           (const float4 *)t.part, M, L.offVX, L.V, L.X, Lp);
-        hipLaunchKernelGGL(k_l2l<P>, dim3(gl), dim3(256), 0, c->stream, tv, Lp, Ll);
+        hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(t.cells_cap, 8, 16384)), dim3(256), 0, c->stream, tv,
+                           (const float4 *)t.part, b.M, L.offVX, L.V, L.X, b.Lp);
+        hipLaunchKernelGGL(k_l2l<P>, dim3(gl), dim3(256), 0, c->stream, tv, b.Lp, b.Ll);
         FL_LAUNCH_CHECK();
     }
     {
@@ -594,12 +610,44 @@ void run_fmm_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float kr, float2
         // about one wave per leaf (4 waves per block): leaves differ a lot in
         // cost, and the dispatcher balances single-leaf waves far better than
         // a fixed stride of several leaves per wave
-        const unsigned ge = grid_for(lcap, 4, 16384);
-        hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, M, Ll, L.offUW,
-                           (const int2 *)L.U, (const int32_t *)L.nU, L.W, (const int32_t *)t.beg,
+        const unsigned ge = grid_for(t.leaves_cap, 4, 16384);
+        hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, b.M, b.Ll,
+                           L.offUW, (const int2 *)L.U, (const int32_t *)L.nU, L.W, (const int32_t *)t.beg,
                            (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr, fr);
         FL_LAUNCH_CHECK();
     }
+}
+
+// Lists and the upward pass both need only the tree: unless phases are
+// being timed (or the context's branches are off), the upward pass runs on a
+// branch stream beside the lists (fork and join by events, recorded as
+// parallel branches under capture).
+template <int P>
+void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
+{
+    ListBufs L;
+    const FmmBufs<P> b = fmm_bufs<P>(c, t);
+    if (c->timing || !c->branches) {
+        {
+            PhaseTimer pt(c, FL_PH_LISTS);
+            build_lists(c, t, L, lanes);
+        }
+        {
+            PhaseTimer pt(c, FL_PH_UPWARD);
+            upward_p<P>(c, c->stream, t, b);
+        }
+    } else {
+        hipStream_t us = aux_stream(c, 3);
+        if (!c->ev_fork2) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_fork2, hipEventDisableTiming));
+        if (!c->ev_join2) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_join2, hipEventDisableTiming));
+        FL_CHECK_HIP(hipEventRecord(c->ev_fork2, c->stream));
+        FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_fork2, 0));
+        upward_p<P>(c, us, t, b);
+        FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
+        build_lists(c, t, L, lanes);
+        FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
+    }
+    downward_eval_p<P>(c, t, L, b, kr, fr);
 }
 
 }  // namespace
@@ -610,22 +658,17 @@ void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, con
                    int bits, int lanes, float kr, float2 *fr)
 {
     TreeBufs t;
-    ListBufs L;
     {
         PhaseTimer pt(c, FL_PH_TREE);
         build_tree(c, t, s, x, y, deg, bits, leaf);
     }
-    {
-        PhaseTimer pt(c, FL_PH_LISTS);
-        build_lists(c, t, L, lanes);
-    }
     switch (p) {
-    case 4: run_fmm_p<4>(c, t, L, kr, fr); break;
-    case 6: run_fmm_p<6>(c, t, L, kr, fr); break;
-    case 8: run_fmm_p<8>(c, t, L, kr, fr); break;
-    case 10: run_fmm_p<10>(c, t, L, kr, fr); break;
-    case 12: run_fmm_p<12>(c, t, L, kr, fr); break;
-    case 16: run_fmm_p<16>(c, t, L, kr, fr); break;
+    case 4: fmm_passes<4>(c, t, lanes, kr, fr); break;
+    case 6: fmm_passes<6>(c, t, lanes, kr, fr); break;
+    case 8: fmm_passes<8>(c, t, lanes, kr, fr); break;
+    case 10: fmm_passes<10>(c, t, lanes, kr, fr); break;
+    case 12: fmm_passes<12>(c, t, lanes, kr, fr); break;
+    case 16: fmm_passes<16>(c, t, lanes, kr, fr); break;
     default: throw Error(FL_EUNSUPPORTED, "FMM expansion order not built (use 4, 6, 8, 10, 12 or 16)");
     }
 }

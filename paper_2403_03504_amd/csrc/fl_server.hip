@@ -141,6 +141,11 @@ void worker(fl_server *sv)
         if (hipSetDevice(sv->device) != hipSuccess || hipStreamCreate(&s) != hipSuccess ||
             fl_create(&ctx, sv->device, s) != FL_OK)
             init_err = "worker could not create its stream/context";
+        // the workers capture concurrently; their iterations keep every
+        // launch on the job's own streams (no branch streams): a run with
+        // branch streams inside concurrent captures ended in a host crash
+        // whose cause is not established
+        if (ctx) ctx->branches = false;
     }
     while (true) {
         std::shared_ptr<Job> j;

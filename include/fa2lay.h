@@ -233,7 +233,9 @@ fl_status fl_bh_repulsion(fl_ctx *ctx, int32_t n, const float *x, const float *y
  * energy  E = sum_{i<j} d_ij^-2 (|p_i - p_j| - l d_ij)^2: every node of a
  * component moves together from the previous positions to
  *   p_i' = sum_{j!=i} w_ij (p_j + l d_ij u_ij) / sum_{j!=i} w_ij,
- * w_ij = d_ij^-2, u_ij = (p_i - p_j)/|p_i - p_j| (0 when they coincide).
+ * w_ij = d_ij^-2, u_ij = (p_i - p_j)/|p_i - p_j| (0 when they coincide);
+ * in a 2-node component, where this maps the distance r to |2l - r|, each
+ * node moves half way (the pair lands at distance l about its midpoint).
  * Components are given as node ranges: comp_offsets [host, n_comp+1]
  * increasing, component k = nodes [comp_offsets[k], comp_offsets[k+1]), each
  * of 1..256 nodes, with no edge leaving its range.

@@ -781,6 +781,9 @@ int64_t orc_fmm_lists(int64_t n, const double *x, const double *y, int leaf_size
 /*   p_i' = sum_{j!=i} w_ij (p_j + l_ij u_ij) / sum_{j!=i} w_ij,               */
 /*   w_ij = d_ij^-2, l_ij = l d_ij, u_ij = (p_i - p_j)/|p_i - p_j| (0 if       */
 /*   coincident).  dist is the n*n hop matrix of one connected component.     */
+/*   For n = 2 the update maps the pair's distance r to |2l - r| (a           */
+/*   reflection that never settles when r < 2l), so there each node moves    */
+/*   half way: the pair lands at distance l about its midpoint in one step.   */
 /* ------------------------------------------------------------------------ */
 double orc_kk_energy(int32_t n, const int32_t *dist, double l, const double *x, const double *y)
 {
@@ -815,6 +818,10 @@ void orc_kk_steps(int32_t n, const int32_t *dist, double l, int32_t steps, doubl
             }
             nx[i] = sw > 0.0 ? ax / sw : x[i];
             ny[i] = sw > 0.0 ? ay / sw : y[i];
+            if (n == 2) { /* the update reflects a pair's distance r to |2l - r|: relax it by 1/2 */
+                nx[i] = 0.5 * (x[i] + nx[i]);
+                ny[i] = 0.5 * (y[i] + ny[i]);
+            }
         }
         memcpy(x, nx, sizeof(double) * (size_t)n);
         memcpy(y, ny, sizeof(double) * (size_t)n);

@@ -157,6 +157,9 @@ __global__ __launch_bounds__(256) void k_kk_steps(const KKBatch *__restrict__ ba
                 ay += w * pj.y + ld * dy * rinv;
             }
             np = sw > 0.f ? make_float2(ax / sw, ay / sw) : pi;
+            // a pair: the update reflects its distance r to |2l - r|; half
+            // way lands it at distance l about its midpoint
+            if (nk == 2) np = make_float2(0.5f * (pi.x + np.x), 0.5f * (pi.y + np.y));
         }
         __syncthreads();
         if (t < nnodes) pos[t] = np;

@@ -183,3 +183,24 @@ def test_layout_dispatch_matches_parts(ctx, fl, orc):
             ctx.fa2_run(Gp, px, py, fl.FA2State.zeros(part.n, "cuda"), p, 30)
         assert np.array_equal(host(px), lx[ids[order]]), k
         assert np.array_equal(host(py), ly[ids[order]]), k
+
+
+def test_kk_pairs_land_at_l(ctx, fl):
+    # 2-node components: one majorization step puts each pair at distance l
+    # about its midpoint (closed form), and further steps keep it there
+    _note("kk pairs")
+    rng = np.random.default_rng(9)
+    k = 50
+    src = np.arange(0, 2 * k, 2, dtype=np.int32)
+    dst = src + 1
+    x = rng.uniform(-3, 3, 2 * k).astype(np.float32)
+    y = rng.uniform(-3, 3, 2 * k).astype(np.float32)
+    G = ctx.build_csr(2 * k, dev(src), dev(dst))
+    offs = np.arange(0, 2 * k + 1, 2, dtype=np.int32)
+    for steps in (1, 200):
+        xd, yd = dev(x), dev(y)
+        ctx.kk_layout(G, offs, xd, yd, fl.kk_params(l=1.25, steps=steps))
+        px, py = host(xd), host(yd)
+        r = np.hypot(px[0::2] - px[1::2], py[0::2] - py[1::2])
+        assert np.allclose(r, 1.25, rtol=1e-5)
+        assert np.allclose((px[0::2] + px[1::2]) / 2, (x[0::2] + x[1::2]) / 2, atol=1e-5)

@@ -491,3 +491,16 @@ def test_kk_step_is_scaled_gradient_step(orc):
             arr[i] = a0
             g = (ep - em) / (2 * h)
             assert abs(out[i] - (a0 - g / (2 * w))) < 1e-6
+
+
+def test_kk_pair_lands_at_l_about_its_midpoint(orc):
+    # closed form: two nodes one hop apart end at distance l, midpoint kept,
+    # after one step from any distinct start (no reflection back and forth)
+    d = np.array([[0, 1], [1, 0]], np.int32)
+    for x0, y0 in (([0.0, 0.4], [0.0, 0.3]), ([2.0, -5.0], [1.0, 1.0]), ([1.0, 1.5], [0.0, 0.0])):
+        x, y = orc.kk_steps(d, x0, y0, 1.7, 1)
+        assert math.hypot(x[0] - x[1], y[0] - y[1]) == pytest.approx(1.7, rel=1e-14)
+        assert (x[0] + x[1]) / 2 == pytest.approx(np.mean(x0), abs=1e-14)
+        assert (y[0] + y[1]) / 2 == pytest.approx(np.mean(y0), abs=1e-14)
+        x2, y2 = orc.kk_steps(d, x, y, 1.7, 7)
+        assert np.allclose(x2, x, atol=1e-14) and np.allclose(y2, y, atol=1e-14)

@@ -505,6 +505,12 @@ def main() -> int:
     # arithmetic, 8 FLOP per term, per particle
     eval_flop = 11.0 * pairs_per_launch + 8.0 * args.p * g.n
     achieved = eval_flop / (eval_ms * 1e-3)
+    # M2L: per V-list entry one p-term outgoing-to-incoming conversion,
+    # 4p^2 + 24p FLOP (complex multiply-adds of the scaled operator); the
+    # phase also holds the (small) L2L launch, so this is a lower bound
+    m2l_ms = phases["m2l"][0] / max(phases["m2l"][1], 1)
+    v_per_launch = fst["total_v_entries"] / evals
+    m2l_flop = v_per_launch * (4.0 * args.p * args.p + 24.0 * args.p)
     attract_ms = phases["attract"][0] / max(phases["attract"][1], 1)
     attract_bytes = 40.0 * g.n + 4.0 * nnz  # compulsory bytes of the attraction/combine pass
     roofline = {"kernel": "k_eval (P2P+L2P+M2P)", "bound": "alu", "achieved": achieved / 1e12,
@@ -513,6 +519,9 @@ def main() -> int:
                 "traffic": profiled_traffic(f"k_eval<{args.p}>") if args.p == 8 else None,
                 "flop_per_launch": eval_flop, "near_pairs_per_launch": pairs_per_launch,
                 "launch_ms": eval_ms,
+                "m2l": {"achieved_TFLOPs": m2l_flop / (m2l_ms * 1e-3) / 1e12, "flop_per_launch": m2l_flop,
+                        "v_entries_per_launch": v_per_launch, "launch_ms": m2l_ms,
+                        "frac": m2l_flop / (m2l_ms * 1e-3) / FP32_VALU_PEAK},
                 "attraction": {"achieved_GBps": attract_bytes / (attract_ms * 1e-3) / 1e9,
                                "bytes_per_launch": attract_bytes, "launch_ms": attract_ms,
                                "frac_hbm": attract_bytes / (attract_ms * 1e-3) / HBM_PEAK}}

@@ -1,10 +1,15 @@
 // Device-wide exclusive scans and a stable LSD radix sort, written for wave64.
 //
 // Scan: reduce tiles -> rescan every tile with the sum of the tiles before it
-// (two launches; the tile sums are scanned first only when there are many).  Radix sort: per pass, a digit histogram per tile, a scan of the
-// digit-major histogram, and a stable scatter in which each wave ranks its
-// keys step by step with ballot-built "same digit" lane masks (no atomics in
-// the ranking, so the order of equal digits is the input order).
+// (two launches; the tile sums are scanned first only when there are many).
+//
+// Radix sort, 8-bit digits: two launches count the digits of every pass, then
+// each pass is one launch in which a block ranks a 4096-key tile (each wave
+// ranks its keys step by step with ballot-built "same digit" lane masks, no
+// atomics, so equal digits keep the input order) and finds the keys of each
+// digit in the tiles before it by decoupled look-back.  Inputs of more than
+// 4M keys take a three-launch pass instead (per-tile histograms, a scan of
+// them, the scatter).
 #include "fl_common.h"
 
 namespace fl {
@@ -122,6 +127,7 @@ constexpr int RS_WTILE = RS_STEPS * WAVE;  // 1024 keys per wave
 constexpr int RS_TILE = RS_NW * RS_WTILE;  // 4096 keys per block
 constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;
+constexpr int RS_MAXPASS = 8;  // 64-bit keys
 
 template <class K>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
@@ -140,42 +146,42 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one pass.  Each wave ranks its 1024 keys step by step
-// (ballot masks of equal digits), the block then places its 4096 keys in LDS
-// in digit order and writes every digit's run contiguously (coalesced).
+// The LDS of one scatter block.
 template <class K, bool HasVal>
-__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin,
-                                                       K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
-                                                       int shift, const int32_t *__restrict__ hscan, int nblocks)
-{
-    __shared__ int wcnt[RS_NW][RS_BINS];
-    __shared__ int gbase[RS_BINS];
-    __shared__ int lstart[RS_BINS];
-    __shared__ int scan_tmp[RS_NT / WAVE];
-    __shared__ K skey[RS_TILE];
-    __shared__ int32_t sval[HasVal ? RS_TILE : 1];
-    const int lane = lane_id(), w = threadIdx.x / WAVE;
-    for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&wcnt[0][0])[i] = 0;
-    gbase[threadIdx.x] = hscan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    __syncthreads();
+struct RsShared {
+    int wcnt[RS_NW][RS_BINS];
+    int gbase[RS_BINS];
+    int lstart[RS_BINS];
+    int scan_tmp[RS_NT / WAVE];
+    int tile;
+    K skey[RS_TILE];
+    int32_t sval[HasVal ? RS_TILE : 1];
+};
 
-    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WTILE;
-    K key[RS_STEPS];
-    int32_t val[RS_STEPS];
-    int off[RS_STEPS];
-    int dig[RS_STEPS];
+// Loads tile `tile` and ranks its keys: each wave ranks its 1024 keys step
+// by step with ballot masks of equal digits (no atomics, so equal digits keep
+// the input order), then every digit gets its exclusive prefix over the
+// waves (wcnt) and the block's count of the digit is returned to thread d.
+template <class K, bool HasVal>
+__device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restrict__ kin,
+                                       const int32_t *__restrict__ vin, int64_t n, int shift, int64_t tile,
+                                       K (&key)[RS_STEPS], int32_t (&val)[RS_STEPS], int (&off)[RS_STEPS],
+                                       int (&dig)[RS_STEPS])
+{
+    const int lane = lane_id(), w = threadIdx.x / WAVE;
+    const int64_t wbase = tile * RS_TILE + (int64_t)w * RS_WTILE;
 #pragma unroll
-    for (int s = 0; s < RS_STEPS; ++s) {
-        int64_t idx = wbase + (int64_t)s * WAVE + lane;
+    for (int st = 0; st < RS_STEPS; ++st) {
+        int64_t idx = wbase + (int64_t)st * WAVE + lane;
         bool ok = idx < n;
-        key[s] = ok ? kin[idx] : K(0);
-        if (HasVal) val[s] = ok ? vin[idx] : 0;
-        dig[s] = ok ? (int)((key[s] >> shift) & (RS_BINS - 1)) : -1;
+        key[st] = ok ? kin[idx] : K(0);
+        if (HasVal) val[st] = ok ? vin[idx] : 0;
+        dig[st] = ok ? (int)((key[st] >> shift) & (RS_BINS - 1)) : -1;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
 #pragma unroll
-    for (int s = 0; s < RS_STEPS; ++s) {
-        const int d = dig[s];
+    for (int st = 0; st < RS_STEPS; ++st) {
+        const int d = dig[st];
         uint64_t mask = __ballot(d >= 0);
 #pragma unroll
         for (int b = 0; b < RS_BITS; ++b) {
@@ -186,57 +192,239 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
         int cnt = __popcll(mask);
         int leader = mask ? __ffsll((long long)mask) - 1 : lane;
         int b0 = 0;
-        if (d >= 0) b0 = wcnt[w][d];
-        off[s] = b0 + rank;
-        if (d >= 0 && lane == leader) wcnt[w][d] = b0 + cnt;
+        if (d >= 0) b0 = S.wcnt[w][d];
+        off[st] = b0 + rank;
+        if (d >= 0 && lane == leader) S.wcnt[w][d] = b0 + cnt;
     }
     __syncthreads();
-    // per digit: exclusive prefix over the waves, and the digit's start in
-    // the block's digit-sorted order
-    {
-        int t = threadIdx.x, run = 0;
+    const int t = threadIdx.x;
+    int run = 0;
 #pragma unroll
-        for (int ww = 0; ww < RS_NW; ++ww) {
-            int cnum = wcnt[ww][t];
-            wcnt[ww][t] = run;
-            run += cnum;
-        }
-        int tot;
-        int ex = block_excl_scan<int, RS_NT>(run, scan_tmp, tot);
-        lstart[t] = ex;
+    for (int ww = 0; ww < RS_NW; ++ww) {
+        int cnum = S.wcnt[ww][t];
+        S.wcnt[ww][t] = run;
+        run += cnum;
     }
-    __syncthreads();
+    int tot;
+    S.lstart[t] = block_excl_scan<int, RS_NT>(run, S.scan_tmp, tot);  // the digit's start in the block's order
+    return run;
+}
+
+// Places the ranked keys in LDS in digit order and writes every digit's run
+// to its global position gbase[d] + rank within the digit (coalesced).
+template <class K, bool HasVal>
+__device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__ kout, int32_t *__restrict__ vout,
+                                         int64_t n, int shift, int64_t tile, const K (&key)[RS_STEPS],
+                                         const int32_t (&val)[RS_STEPS], const int (&off)[RS_STEPS],
+                                         const int (&dig)[RS_STEPS])
+{
+    const int w = threadIdx.x / WAVE;
 #pragma unroll
-    for (int s = 0; s < RS_STEPS; ++s) {
-        const int d = dig[s];
+    for (int st = 0; st < RS_STEPS; ++st) {
+        const int d = dig[st];
         if (d < 0) continue;
-        const int lp = lstart[d] + wcnt[w][d] + off[s];
-        skey[lp] = key[s];
-        if (HasVal) sval[lp] = val[s];
+        const int lp = S.lstart[d] + S.wcnt[w][d] + off[st];
+        S.skey[lp] = key[st];
+        if (HasVal) S.sval[lp] = val[st];
     }
     __syncthreads();
-    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile0 = tile * RS_TILE;
     const int live = (int)((n - tile0) < RS_TILE ? (n - tile0) : RS_TILE);
     for (int i = threadIdx.x; i < live; i += RS_NT) {
-        const K k2 = skey[i];
+        const K k2 = S.skey[i];
         const int d = (int)((k2 >> shift) & (RS_BINS - 1));
-        const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
-        kout[pos] = k2;
-        if (HasVal) vout[pos] = sval[i];
+        const int64_t pos = (int64_t)S.gbase[d] + (i - S.lstart[d]);
+        if (pos < n) {  // always true unless a look-back gave up (error flagged)
+            kout[pos] = k2;
+            if (HasVal) vout[pos] = S.sval[i];
+        }
     }
 }
 
+// Stable scatter of one pass with the per-tile digit histograms scanned
+// beforehand (three launches per pass).
 template <class K, bool HasVal>
-bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag)
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin,
+                                                       K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
+                                                       int shift, const int32_t *__restrict__ hscan, int nblocks)
+{
+    __shared__ RsShared<K, HasVal> S;
+    for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
+    S.gbase[threadIdx.x] = hscan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    __syncthreads();
+    K key[RS_STEPS];
+    int32_t val[RS_STEPS];
+    int off[RS_STEPS], dig[RS_STEPS];
+    rs_rank<K, HasVal>(S, kin, vin, n, shift, blockIdx.x, key, val, off, dig);
+    __syncthreads();
+    rs_place<K, HasVal>(S, kout, vout, n, shift, blockIdx.x, key, val, off, dig);
+}
+
+// ---- one launch per pass: decoupled look-back --------------------------------
+// Two launches count the digits of every pass over the whole input, per tile
+// and then summed (the global digit offsets of a pass do not depend on the
+// order of the keys).  Each pass is then one launch: a block takes the next
+// tile in launch order from a ticket counter, ranks it, publishes its per-digit
+// counts, and finds the number of keys of each digit in the tiles before it
+// by walking back over their published words until one carries an inclusive
+// prefix (Merrill & Garland 2016).  A tile waits only on tiles that were
+// taken before it, by blocks that are running and publish their counts
+// before they wait themselves, so every wait ends; a bounded spin guards the
+// launch anyway and flags an error instead of hanging.
+//
+// Status word of (pass, tile, digit): flag in bits 30-31 (0 none yet,
+// 1 count of this tile, 2 inclusive prefix up to this tile), value in bits
+// 0-29.
+constexpr uint32_t RS_AGG = 1u << 30, RS_PFX = 2u << 30, RS_VAL = (1u << 30) - 1u;
+constexpr uint32_t RS_SPIN_LIMIT = 1u << 22;
+constexpr int RS_LOOK = 8;  // tiles read per look-back step
+// Larger inputs take the three-launch pass: their look-back chains grow with
+// the tile count while launch overhead matters less (4M keys at most here,
+// far below the 2^30 the status words hold).
+constexpr int RS_LOOKBACK_TILES = 1024;
+
+// Digit counts of all passes per 4096-key tile (LDS counts, written out
+// per tile), the clearing of every pass's status words, and (block 0) the
+// zeroing of the summed counts and the tickets; the launches after this one
+// on the stream see all of it.
+template <class K>
+__global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ keys, int64_t n, int passes,
+                                                        uint32_t *__restrict__ part, uint32_t *__restrict__ status,
+                                                        int64_t nstatus, uint32_t *__restrict__ gh, int ngh)
+{
+    __shared__ uint32_t cnt[RS_MAXPASS][RS_BINS];
+    for (int i = threadIdx.x; i < RS_MAXPASS * RS_BINS; i += RS_NT) (&cnt[0][0])[i] = 0u;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < ngh; i += RS_NT) gh[i] = 0u;
+    const int64_t stride = (int64_t)gridDim.x * RS_NT;
+    for (int64_t i = (int64_t)blockIdx.x * RS_NT + threadIdx.x; i < nstatus; i += stride) status[i] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = threadIdx.x; i < RS_TILE; i += RS_NT) {
+        if (base + i >= n) break;
+        const K k = keys[base + i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(int)((k >> (p * RS_BITS)) & (RS_BINS - 1))], 1u);
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p) part[((int64_t)blockIdx.x * passes + p) * RS_BINS + threadIdx.x] = cnt[p][threadIdx.x];
+}
+
+// Sums the per-tile counts: one wave per (pass, digit) entry, its lanes
+// over the tiles, then a wave sum (integers: the order does not matter).
+__global__ __launch_bounds__(RS_NT) void k_rs_hist_sum(const uint32_t *__restrict__ part, int ntiles, int passes,
+                                                        uint32_t *__restrict__ gh)
+{
+    const int i = blockIdx.x * RS_NW + threadIdx.x / WAVE;  // pass * 256 + digit
+    if (i >= passes * RS_BINS) return;
+    const int64_t st = (int64_t)passes * RS_BINS;
+    uint32_t sum = 0u;
+    for (int b = lane_id(); b < ntiles; b += WAVE) sum += part[(int64_t)b * st + i];
+    sum = wave_sum(sum);
+    if (lane_id() == 0) gh[i] = sum;
+}
+
+template <class K, bool HasVal>
+__global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin, const int32_t *__restrict__ vin,
+                                                        K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
+                                                        int shift, const uint32_t *__restrict__ gh,
+                                                        uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
+                                                        int32_t *__restrict__ err)
+{
+    __shared__ RsShared<K, HasVal> S;
+    for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
+    if (threadIdx.x == 0) S.tile = (int)atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int tile = S.tile;
+    K key[RS_STEPS];
+    int32_t val[RS_STEPS];
+    int off[RS_STEPS], dig[RS_STEPS];
+    const int d = threadIdx.x;
+    const uint32_t cnt = (uint32_t)rs_rank<K, HasVal>(S, kin, vin, n, shift, tile, key, val, off, dig);
+    uint32_t *my = status + (int64_t)tile * RS_BINS + d;
+    __hip_atomic_store(my, (tile == 0 ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // global start of the digit: counts of the smaller digits
+    int tot;
+    const uint32_t dstart = (uint32_t)block_excl_scan<int, RS_NT>((int)gh[d], S.scan_tmp, tot);
+    uint32_t before = 0;
+    if (tile > 0) {
+        // look back RS_LOOK tiles at a time (independent loads in flight),
+        // consuming counts in order until an inclusive prefix; a tile that
+        // has published nothing yet stops the window and is read again
+        int j = tile - 1;
+        uint32_t spins = 0;
+        for (;;) {
+            uint32_t v[RS_LOOK];
+#pragma unroll
+            for (int u = 0; u < RS_LOOK; ++u)
+                v[u] = j - u >= 0 ? __hip_atomic_load(status + (int64_t)(j - u) * RS_BINS + d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0u;  // never consumed: tile 0 publishes a prefix
+            int used = 0;
+            bool pfx = false;
+#pragma unroll
+            for (int u = 0; u < RS_LOOK; ++u) {
+                const uint32_t f = v[u] & ~RS_VAL;
+                if (f == 0u) break;
+                before += v[u] & RS_VAL;
+                used = u + 1;
+                if (f == RS_PFX) {
+                    pfx = true;
+                    break;
+                }
+            }
+            if (pfx) break;
+            j -= used;
+            if (used == 0) {
+                if (++spins > RS_SPIN_LIMIT) {
+                    atomicOr(err, 8);
+                    before = (uint32_t)n;  // every write of this digit is then out of range and skipped
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __hip_atomic_store(my, RS_PFX | ((before + cnt) & RS_VAL), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    S.gbase[d] = (int)(dstart + before);
+    __syncthreads();
+    rs_place<K, HasVal>(S, kout, vout, n, shift, tile, key, val, off, dig);
+}
+
+template <class K, bool HasVal>
+bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag,
+                int32_t *err)
 {
     if (n <= 0) return false;
-    int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int passes = (nbits + RS_BITS - 1) / RS_BITS;
+    K *ka = k, *kb = kt;
+    int32_t *va = v, *vb = vt;
+    if (nblocks <= RS_LOOKBACK_TILES && passes <= RS_MAXPASS) {
+        // gh (passes x 256 digit counts) and the tickets share one buffer
+        const int nz = passes * RS_BINS + passes;
+        uint32_t *gh = ws<uint32_t>(c, (std::string("rs_gh_") + tag).c_str(), (size_t)nz);
+        uint32_t *ticket = gh + passes * RS_BINS;
+        uint32_t *part = ws<uint32_t>(c, (std::string("rs_part_") + tag).c_str(), (size_t)nblocks * passes * RS_BINS);
+        const int64_t nstatus = (int64_t)passes * nblocks * RS_BINS;
+        uint32_t *status = ws<uint32_t>(c, (std::string("rs_status_") + tag).c_str(), (size_t)nstatus);
+        if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
+        hipLaunchKernelGGL(k_rs_hist_all<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)k, n, passes, part,
+                           status, nstatus, gh, nz);
+        hipLaunchKernelGGL(k_rs_hist_sum, dim3(passes * RS_BINS / RS_NW), dim3(RS_NT), 0, c->stream,
+                           (const uint32_t *)part, nblocks, passes, gh);
+        for (int ps = 0; ps < passes; ++ps) {
+            hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
+                               (const int32_t *)va, kb, vb, n, ps * RS_BITS, (const uint32_t *)(gh + ps * RS_BINS),
+                               status + (int64_t)ps * nblocks * RS_BINS, ticket + ps, err);
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        FL_LAUNCH_CHECK();
+        return (passes & 1) != 0;
+    }
     std::string hn = std::string("rs_hist_") + tag;
     int32_t *hist = ws<int32_t>(c, hn.c_str(), (size_t)RS_BINS * nblocks * 2 + 1);
     int32_t *hscan = hist + (size_t)RS_BINS * nblocks;
-    int passes = (nbits + RS_BITS - 1) / RS_BITS;
-    K *ka = k, *kb = kt;
-    int32_t *va = v, *vb = vt;
     for (int ps = 0; ps < passes; ++ps) {
         int shift = ps * RS_BITS;
         hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, n, shift, hist, nblocks);
@@ -267,19 +455,21 @@ void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const in
     scan_excl<double>(c, in, out, n, dn, tag);
 }
 
-bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits)
+bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
+                    int32_t *err)
 {
-    return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32");
+    return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32", err);
 }
 
-bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits)
+bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits, int32_t *err)
 {
-    return radix_sort<uint64_t, false>(c, k, nullptr, kt, nullptr, n, nbits, "u64");
+    return radix_sort<uint64_t, false>(c, k, nullptr, kt, nullptr, n, nbits, "u64", err);
 }
 
-bool radix_sort_u64v(fl_ctx *c, uint64_t *k, int32_t *v, uint64_t *kt, int32_t *vt, int64_t n, int nbits)
+bool radix_sort_u64v(fl_ctx *c, uint64_t *k, int32_t *v, uint64_t *kt, int32_t *vt, int64_t n, int nbits,
+                     int32_t *err)
 {
-    return radix_sort<uint64_t, true>(c, k, v, kt, vt, n, nbits, "u64v");
+    return radix_sort<uint64_t, true>(c, k, v, kt, vt, n, nbits, "u64v", err);
 }
 
 }  // namespace fl

@@ -936,12 +936,12 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     int32_t *perm;
     const uint64_t *sq = nullptr;
     if (s.K > 1) {
-        const bool alt = radix_sort_u64v(c, q0, i0, q1, i1, n, 32 + s.cbits);
+        const bool alt = radix_sort_u64v(c, q0, i0, q1, i1, n, 32 + s.cbits, t.counts + 3);
         sq = alt ? q1 : q0;
         perm = alt ? i1 : i0;
         sk = k0;  // written by k_gather
     } else {
-        const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits);
+        const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3);
         sk = alt ? k1 : k0;
         perm = alt ? i1 : i0;
     }
@@ -1089,7 +1089,12 @@ fl_status fl_sort_keys(fl_ctx *c, int32_t n, const uint32_t *key, int32_t bits, 
     FL_CHECK_HIP(hipMemcpyAsync(key_out, key, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
     hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, perm, n);
     FL_LAUNCH_CHECK();
-    bool alt = radix_sort_u32(c, key_out, perm, kt, vt, n, 2 * bits);
+    int32_t *err = ws_zeroed<int32_t>(c, "sk_err", 1);
+    bool alt = radix_sort_u32(c, key_out, perm, kt, vt, n, 2 * bits, err);
+    if (read_i32(c, err)) {
+        FL_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
+        throw Error(FL_EHIP, "fl_sort_keys: the sort's look-back gave up");
+    }
     if (alt) {
         FL_CHECK_HIP(hipMemcpyAsync(key_out, kt, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
         FL_CHECK_HIP(hipMemcpyAsync(perm, vt, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream));

@@ -424,6 +424,64 @@ struct CountSink {
     __device__ void W(int) { ++nW; }
 };
 
+// Counting pass of the lane groups: besides the counts, the lane's first
+// LIST_SLOTS entries (cell ids tagged V 0, X 1, U 2, W 3 in the top two
+// bits) are kept in LDS and written out per cell, so that the filling pass
+// replays them instead of enumerating the ring again (a chain of dependent
+// lookups); a lane with more entries enumerates again.
+constexpr int LIST_SLOTS = 8;
+struct SlotSink {
+    using lds_i32 = __attribute__((address_space(3))) int32_t;
+    lds_i32 *slot;
+    int nV = 0, nX = 0, nU = 0, nW = 0;
+    __device__ void put(uint32_t tag, int s)
+    {
+        const int k = nV + nX + nU + nW;
+        if (k < LIST_SLOTS) slot[k] = (int)((tag << 30) | (uint32_t)s);
+    }
+    __device__ void V(int s)
+    {
+        put(0u, s);
+        ++nV;
+    }
+    __device__ void X(int s)
+    {
+        put(1u, s);
+        ++nX;
+    }
+    __device__ void U(int s)
+    {
+        put(2u, s);
+        ++nU;
+    }
+    __device__ void W(int s)
+    {
+        put(3u, s);
+        ++nW;
+    }
+};
+
+template <class Sink>
+__device__ __forceinline__ void replay_slots(const int4 *__restrict__ gs, int tot, Sink &sk)
+{
+    const int4 a = gs[0];
+    const int4 b = tot > 4 ? gs[1] : make_int4(0, 0, 0, 0);
+    const int e[LIST_SLOTS] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < LIST_SLOTS; ++i) {
+        if (i < tot) {
+            const uint32_t v = (uint32_t)e[i];
+            const int id = (int)(v & 0x3FFFFFFFu);
+            switch (v >> 30) {
+            case 0: sk.V(id); break;
+            case 1: sk.X(id); break;
+            case 2: sk.U(id); break;
+            default: sk.W(id); break;
+            }
+        }
+    }
+}
+
 struct FillSink {
     int32_t *pV, *pX;
     int2 *pU;
@@ -566,11 +624,14 @@ __device__ __forceinline__ int group_excl(int v)
 }
 
 // Grid-stride over cells, one LANES-lane group per cell; the trip count is
-// uniform over the wave (the shuffles need all lanes of a group).
+// uniform over the wave (the shuffles need all lanes of a group).  With
+// `slots` each lane also stores its first LIST_SLOTS entries there.
 template <int LANES>
 __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__restrict__ cntVX,
-                                                     int64_t *__restrict__ cntUW, int64_t *__restrict__ lanecnt)
+                                                     int64_t *__restrict__ cntUW, int64_t *__restrict__ lanecnt,
+                                                     int4 *__restrict__ slots)
 {
+    __shared__ int32_t slot_lds[LANES > 1 ? 256 : 1][LANES > 1 ? LIST_SLOTS : 1];
     const int ncells = t.counts[0];
     const int64_t H = hash_size(ncells, t.hash_cap);
     const uint64_t ep = *t.epoch;
@@ -580,13 +641,35 @@ __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__rest
     const int nw = gridDim.x * (blockDim.x / WAVE);
     for (int c0 = wid * gpw; c0 < ncells; c0 += nw * gpw) {
         const int c = c0 + lane_id() / LANES;
-        CountSink sk;
-        if (c < ncells) enumerate_part<LANES>(t, H, ep, c, q, sk);
-        if (LANES > 1 && c < ncells)
-            lanecnt[(int64_t)c * LANES + q] = (int64_t)sk.nV | ((int64_t)sk.nX << 8) | ((int64_t)sk.nU << 16) |
-                                              ((int64_t)sk.nW << 40);
-        const int nV = group_sum<LANES>(sk.nV), nX = group_sum<LANES>(sk.nX);
-        const int nU = group_sum<LANES>(sk.nU), nW = group_sum<LANES>(sk.nW);
+        int cV = 0, cX = 0, cU = 0, cW = 0;
+        if constexpr (LANES > 1) {
+            SlotSink sk{(SlotSink::lds_i32 *)slot_lds[threadIdx.x]};
+            if (c < ncells) enumerate_part<LANES>(t, H, ep, c, q, sk);
+            cV = sk.nV;
+            cX = sk.nX;
+            cU = sk.nU;
+            cW = sk.nW;
+            if (c < ncells) {
+                lanecnt[(int64_t)c * LANES + q] =
+                    (int64_t)cV | ((int64_t)cX << 8) | ((int64_t)cU << 16) | ((int64_t)cW << 40);
+                const int tot = cV + cX + cU + cW;
+                if (slots && tot > 0) {  // the lane's own LDS row: no synchronisation needed
+                    const int32_t *r = slot_lds[threadIdx.x];
+                    int4 *gs = slots + ((int64_t)c * LANES + q) * 2;
+                    gs[0] = make_int4(r[0], r[1], r[2], r[3]);
+                    if (tot > 4) gs[1] = make_int4(r[4], r[5], r[6], r[7]);
+                }
+            }
+        } else {
+            CountSink sk;
+            if (c < ncells) enumerate_part<LANES>(t, H, ep, c, q, sk);
+            cV = sk.nV;
+            cX = sk.nX;
+            cU = sk.nU;
+            cW = sk.nW;
+        }
+        const int nV = group_sum<LANES>(cV), nX = group_sum<LANES>(cX);
+        const int nU = group_sum<LANES>(cU), nW = group_sum<LANES>(cW);
         if (c < ncells && q == 0) {
             cntVX[c] = (int64_t)nV | ((int64_t)nX << 32);
             const int li = t.leafidx[c];
@@ -637,10 +720,11 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                                                     const int64_t *__restrict__ offUW, int32_t *__restrict__ V,
                                                     int32_t *__restrict__ X, int2 *__restrict__ U,
                                                     int32_t *__restrict__ nU, int32_t *__restrict__ W,
-                                                    unsigned long long *__restrict__ near_pairs, int64_t cap,
+                                                    unsigned long long *__restrict__ wave_pairs, int64_t cap,
                                                     int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap,
                                                     int64_t w_cap, int32_t *__restrict__ err,
-                                                    const int64_t *__restrict__ lanecnt)
+                                                    const int64_t *__restrict__ lanecnt,
+                                                    const int4 *__restrict__ slots)
 {
     constexpr int STG = LANES > 1 ? FILL_STAGE : 1;  // one lane per cell: no staging
     __shared__ int2 stage[256 / LANES][STG];
@@ -651,6 +735,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                       (tuw >> 32) <= w_cap;
     if (!fits) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 4);
+        if (lane_id() == 0) wave_pairs[blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE] = 0ull;
         return;
     }
     const int64_t H = hash_size(ncells, t.hash_cap);
@@ -670,20 +755,27 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
         int2 *u0 = U + (ou & 0xFFFFFFFFll);
         // the leaf's range count, itself included (from the counting pass)
         const int k = li >= 0 ? (int)((offUW[li + 1] - ou) & 0xFFFFFFFFll) : 0;
-        int pV = 0, pX = 0, pU = 0, pW = 0;
+        int pV = 0, pX = 0, pU = 0, pW = 0, tot = LIST_SLOTS + 1;
         if (LANES > 1) {  // each lane's offsets within its group's lists
             const int64_t lc = live ? lanecnt[(int64_t)c * LANES + q] : 0;
-            pV = group_excl<LANES>((int)(lc & 0xFF));
-            pX = group_excl<LANES>((int)((lc >> 8) & 0xFF));
-            pU = group_excl<LANES>((int)((lc >> 16) & 0xFFFFFF));
-            pW = group_excl<LANES>((int)((lc >> 40) & 0xFFFFFF));
+            const int cV = (int)(lc & 0xFF), cX = (int)((lc >> 8) & 0xFF);
+            const int cU = (int)((lc >> 16) & 0xFFFFFF), cW = (int)((lc >> 40) & 0xFFFFFF);
+            pV = group_excl<LANES>(cV);
+            pX = group_excl<LANES>(cX);
+            pU = group_excl<LANES>(cU);
+            pW = group_excl<LANES>(cW);
+            if (slots) tot = cV + cX + cU + cW;
         }
         const bool staged = LANES > 1 && li >= 0 && k <= STG;
         if (live) {
             const int64_t o = offVX[c];
             FillSink sk{V + (o & 0xFFFFFFFFll) + pV, X + (o >> 32) + pX, (staged ? st : u0) + 1 + pU,
                         W + (ou >> 32) + pW, t.beg, t.end, staged};
-            enumerate_part<LANES>(t, H, ep, c, q, sk);
+            if (LANES > 1 && tot <= LIST_SLOTS) {
+                if (tot > 0) replay_slots(slots + ((int64_t)c * LANES + q) * 2, tot, sk);
+            } else {
+                enumerate_part<LANES>(t, H, ep, c, q, sk);
+            }
             if (li >= 0 && q == 0) (staged ? st : u0)[0] = staged ? make_int2(c, 0) : make_int2(t.beg[c], t.end[c]);
         }
         // the group's U entries were written by its lanes: make them visible
@@ -748,16 +840,28 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
         // lane 0 is done with the stage before the next cell's lanes write it
         lds_wave_sync();
     }
+    // one partial per wave, summed by k_lists_stats: thousands of waves
+    // adding to one global counter serialise at the memory side and stall
+    // the loads of every wave queued behind them
     pairs = wave_sum(pairs);
-    if (lane_id() == 0 && pairs) atomicAdd(near_pairs, pairs);
+    if (lane_id() == 0) wave_pairs[wid] = pairs;
 }
 
-__global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t *__restrict__ offVX,
-                              const int64_t *__restrict__ offUW, int64_t *__restrict__ st, int n)
+__global__ __launch_bounds__(256) void k_lists_stats(const int32_t *__restrict__ counts,
+                                                     const int64_t *__restrict__ offVX,
+                                                     const int64_t *__restrict__ offUW,
+                                                     const unsigned long long *__restrict__ wave_pairs, int nwaves,
+                                                     int64_t *__restrict__ st, int n)
 {
+    __shared__ unsigned long long red[256 / WAVE];
+    unsigned long long p = 0;
+    for (int i = threadIdx.x; i < nwaves; i += 256) p += wave_pairs[i];
+    p = block_sum<unsigned long long, 256>(p, red);
+    if (threadIdx.x != 0) return;
     const int64_t tvx = offVX[counts[0]], tuw = offUW[counts[1]];
     st[0] = counts[0];
     st[1] = counts[1];
+    st[2] = (int64_t)p;
     st[3] = tvx & 0xFFFFFFFFll;
     st[5] = tvx >> 32;
     st[7] = tuw & 0xFFFFFFFFll;
@@ -766,12 +870,6 @@ __global__ void k_lists_stats(const int32_t *__restrict__ counts, const int64_t 
     st[9] += st[3];
     st[10] += 1;
     st[11] += n;
-}
-
-__global__ void k_zero_i64(int64_t *__restrict__ p, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
 }
 
 __global__ void k_export_cells(TreeView t, int32_t *__restrict__ out, int cap)
@@ -996,19 +1094,24 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     const bool wide = lanes == 8;
     const unsigned lg = grid_for(cap, wide ? 256 / 8 : 256, 4096);
     int64_t *lanecnt = wide ? ws<int64_t>(c, "l_lanecnt", (size_t)cap * 8) : nullptr;
-    if (wide) hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt);
-    else hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt);
+    // entry slots: two int4 per (cell, lane); cell ids must leave the tag bits free
+    int4 *slots = wide && cap < (int64_t(1) << 30) ? ws<int4>(c, "l_slots", (size_t)cap * 8 * 2) : nullptr;
+    if (wide)
+        hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt, slots);
+    else
+        hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt,
+                           (int4 *)nullptr);
     FL_LAUNCH_CHECK();
     scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
     scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
-    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, c->d_stats + 2, 1);
     auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
+    const int nwaves = (int)lg * (256 / WAVE);
+    unsigned long long *wave_pairs = ws<unsigned long long>(c, "l_wave_pairs", (size_t)nwaves);
     hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
-                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, (unsigned long long *)(c->d_stats + 2),
-                       cap, lcap, L.v_cap, L.x_cap, L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt);
-    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(1), 0, c->stream, t.counts, (const int64_t *)L.offVX,
-                       (const int64_t *)L.offUW,
-                       c->d_stats, t.n);
+                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, wave_pairs, cap, lcap, L.v_cap, L.x_cap,
+                       L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt, (const int4 *)slots);
+    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(256), 0, c->stream, t.counts, (const int64_t *)L.offVX,
+                       (const int64_t *)L.offUW, (const unsigned long long *)wave_pairs, nwaves, c->d_stats, t.n);
     FL_LAUNCH_CHECK();
 }
 

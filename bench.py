@@ -38,7 +38,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel: str = "k_eval<8>", profile: str = "fa2_fmm_giant2m_p8.md"):
+def profiled_traffic(kernel: str = "k_p2p", profile: str = "fa2_fmm_giant2m_p8.md"):
     """HBM bytes per launch of `kernel` from the committed PMC summary, or None
     if the kernel source changed since the counters were taken."""
     import hashlib
@@ -500,11 +500,14 @@ def main() -> int:
     evals = max(fst["evaluations"], 1)
     pairs_per_launch = fst["total_near_pairs"] / evals
     eval_ms = phases["eval"][0] / max(phases["eval"][1], 1)
-    # 11 FLOP per near-field pair (2 sub, 3 for r^2, 1 reciprocal, 1 mul,
-    # 4 for the two multiply-adds); L2P: Horner of degree p-1 in complex
-    # arithmetic, 8 FLOP per term, per particle
-    eval_flop = 11.0 * pairs_per_launch + 8.0 * args.p * g.n
+    # near field (k_p2p): 11 FLOP per pair (2 sub, 3 for r^2, 1 reciprocal,
+    # 1 mul, 4 for the two multiply-adds)
+    eval_flop = 11.0 * pairs_per_launch
     achieved = eval_flop / (eval_ms * 1e-3)
+    # far field (k_far): L2P, Horner of degree p-1 in complex arithmetic,
+    # 8 FLOP per term per particle (the W-list terms not counted)
+    far_ms = phases["far"][0] / max(phases["far"][1], 1)
+    far_flop = 8.0 * args.p * g.n
     # M2L: per V-list entry one p-term outgoing-to-incoming conversion,
     # 4p^2 + 24p FLOP (complex multiply-adds of the scaled operator); the
     # phase also holds the (small) L2L launch, so this is a lower bound
@@ -513,12 +516,14 @@ def main() -> int:
     m2l_flop = v_per_launch * (4.0 * args.p * args.p + 24.0 * args.p)
     attract_ms = phases["attract"][0] / max(phases["attract"][1], 1)
     attract_bytes = 40.0 * g.n + 4.0 * nnz  # compulsory bytes of the attraction/combine pass
-    roofline = {"kernel": "k_eval (P2P+L2P+M2P)", "bound": "alu", "achieved": achieved / 1e12,
+    roofline = {"kernel": "k_p2p (FMM near field)", "bound": "alu", "achieved": achieved / 1e12,
                 "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
                 "frac_of_published_157": achieved / FP32_PUBLISHED,
-                "traffic": profiled_traffic(f"k_eval<{args.p}>") if args.p == 8 else None,
+                "traffic": profiled_traffic("k_p2p") if args.p == 8 else None,
                 "flop_per_launch": eval_flop, "near_pairs_per_launch": pairs_per_launch,
                 "launch_ms": eval_ms,
+                "far": {"kernel": f"k_far<{args.p}>", "achieved_TFLOPs": far_flop / (far_ms * 1e-3) / 1e12,
+                        "flop_per_launch": far_flop, "launch_ms": far_ms},
                 "m2l": {"achieved_TFLOPs": m2l_flop / (m2l_ms * 1e-3) / 1e12, "flop_per_launch": m2l_flop,
                         "v_entries_per_launch": v_per_launch, "launch_ms": m2l_ms,
                         "frac": m2l_flop / (m2l_ms * 1e-3) / FP32_VALU_PEAK},

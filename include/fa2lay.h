@@ -494,12 +494,13 @@ const char *fl_server_last_error(const fl_server *srv);
 void fl_server_destroy(fl_server *srv);
 
 /* Per-phase device timing (HIP events on the context's stream).  When
- * enabled, fl_fa2_step/run (and fl_bh_repulsion: tree, then FL_PH_BH for
+ * enabled, fl_fa2_step/run (FL_PH_EVAL: the near field, FL_PH_FAR: the far
+ * field added to it; fl_bh_repulsion: tree, then FL_PH_BH for
  * the cell moments and the walk) record events around their phases; fl_get_timing
  * returns the accumulated milliseconds and launch counts per phase
  * (FL_NPHASE entries each) and clears them [host, synchronises]. */
 enum { FL_PH_TREE = 0, FL_PH_LISTS, FL_PH_UPWARD, FL_PH_M2L, FL_PH_EVAL, FL_PH_ATTRACT, FL_PH_UPDATE,
-       FL_PH_EXACT, FL_PH_BH, FL_NPHASE };
+       FL_PH_EXACT, FL_PH_BH, FL_PH_FAR, FL_NPHASE };
 fl_status fl_set_timing(fl_ctx *ctx, int enable);
 /* Graph replay of fl_fa2_run and concurrent components in fl_layout (on by
  * default); 0 runs every iteration as eager launches on the context's stream

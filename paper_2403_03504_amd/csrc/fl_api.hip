@@ -119,7 +119,7 @@ void fl_destroy(fl_ctx *c)
             (void)hipStreamSynchronize(s);
             (void)hipStreamDestroy(s);
         }
-    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_fork2, c->ev_join2})
+    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_fork2, c->ev_join2, c->ev_lists})
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (auto &kv : c->bufs)

@@ -88,7 +88,7 @@ struct fl_ctx {
     // fork/join of the branches of an iteration: the attraction gathers and
     // the FMM's upward pass (created on first use); `branches` off runs them
     // in line on the context's stream
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr, ev_lists = nullptr;
     bool branches = true;
     std::vector<fl_ctx *> sub;
     bool own_stream = false;     // a branch context destroys its stream

@@ -19,17 +19,20 @@
 //             ancestors shifted to the leaf centre.  Shifts compose exactly,
 //             so this is the paper's parent-to-child recursion unrolled along
 //             each leaf's ancestor chain (one launch instead of one per level).
-//   k_eval    one wave per leaf: far field from the incoming expansion (L2P),
-//             W-list outgoing expansions at the particles (M2P), and the
-//             direct near field over the U list (P2P).  Lanes hold targets;
-//             sources are read at wave-uniform addresses (scalar loads, SGPR
-//             operands: no per-lane memory traffic in the pair loop).  Leaves
-//             of at most 32 (16) targets run 2 (4) lane groups on interleaved
-//             sources, staged 64 at a time in LDS and read there by each
-//             group (no per-pair selects); the groups are combined with xor
-//             shuffles (fixed order).
+//   k_p2p     one wave per leaf: the direct near field over the U list
+//             (P2P), written per particle in sorted order.  Lanes hold
+//             targets; sources are read at wave-uniform addresses (scalar
+//             loads, SGPR operands: no per-lane memory traffic in the pair
+//             loop).  Leaves of at most 32 (16) targets run 2 (4) lane groups
+//             on interleaved sources, staged 64 at a time in LDS and read
+//             there by each group (no per-pair selects); the groups are
+//             combined with xor shuffles (fixed order).
+//   k_far     one wave per leaf, lanes on particles: far field from the
+//             incoming expansion (L2P) and the W list's outgoing expansions
+//             (M2P), added to the near field; the force goes to the node's
+//             original index.
 //
-// Launch shapes: P2M, M2L and the evaluation launch about one wave per leaf
+// Launch shapes: P2M, M2L and the evaluations launch about one wave per leaf
 // (or pair of cells) instead of a fixed stride of several per wave; the cost
 // per leaf varies a lot, and the dispatcher balances short waves better.
 #include <algorithm>
@@ -433,14 +436,14 @@ __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restric
         fy = fmaf(sm, dy, fy);                                                                                      \
     }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restrict__ part,
-                                              const float2 *__restrict__ M, const float2 *__restrict__ Lleaf,
-                                              const int64_t *__restrict__ offUW, const int2 *__restrict__ U,
-                                              const int32_t *__restrict__ nU, const int32_t *__restrict__ W,
-                                              const int32_t *__restrict__ cbeg, const int32_t *__restrict__ cend,
-                                              const int32_t *__restrict__ leaf_cell, float kr,
-                                              float2 *__restrict__ fr)
+// k_p2p: the near field of every particle over its leaf's U list (sorted
+// particle order, one float2 per particle).  It needs only the lists, so it
+// runs beside the upward pass and M2L.
+__global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restrict__ part,
+                                             const int64_t *__restrict__ offUW, const int2 *__restrict__ U,
+                                             const int32_t *__restrict__ nU, const int32_t *__restrict__ cbeg,
+                                             const int32_t *__restrict__ cend, const int32_t *__restrict__ leaf_cell,
+                                             float2 *__restrict__ near)
 {
     __shared__ float4 stage[4][WAVE + 4];  // per wave: sources of the small-leaf path, zero-mass padded
     const int nleaves = t.counts[1];
@@ -451,9 +454,8 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
     for (int li = first; li < nleaves; li += gridDim.x * wpb) {
         const int c = leaf_cell[li];
         const int b = cbeg[c], e = cend[c];
-        const int64_t ou0 = offUW[li], ou1 = offUW[li + 1];
+        const int64_t ou0 = offUW[li];
         const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = u0 + nU[li];
-        const int w0 = (int)(ou0 >> 32), w1 = (int)(ou1 >> 32);
         for (int t0 = b; t0 < e; t0 += WAVE) {
             const int ntc = min(WAVE, e - t0);
             // small leaves: G lane groups take interleaved sources
@@ -486,11 +488,15 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                     const int G = 1 << lg;
                     for (int j0 = sb; j0 < se; j0 += WAVE) {
                         const int ns = min(WAVE, se - j0);
-                        float4 v = part[j0 + (lane < ns ? lane : 0)];
-                        const float4 pad = make_float4(v.x, v.y, 0.f, 0.f);  // a source of mass 0 adds 0
+                        const bool in = lane < ns;
+                        const float4 v = part[j0 + (in ? lane : 0)];
+                        // lanes past the chunk hold a source of mass 0 (adds 0);
+                        // the select is per component: a select of the whole
+                        // float4 went through scratch memory
+                        const float4 sv = make_float4(v.x, v.y, in ? v.z : 0.f, in ? v.w : 0.f);
                         wave_lds_sync();  // the previous chunk has been read
-                        sw[lane] = lane < ns ? v : pad;
-                        if (lane < 4) sw[WAVE + lane] = pad;
+                        sw[lane] = sv;
+                        if (lane < 4) sw[WAVE + lane] = make_float4(v.x, v.y, 0.f, 0.f);
                         wave_lds_sync();
                         int k = 0;
                         for (; k + 3 * G < ns; k += 4 * G) {  // four LDS reads in flight
@@ -516,41 +522,66 @@ __global__ __launch_bounds__(256) void k_eval(TreeView t, const float4 *__restri
                 fx += __shfl_xor(fx, WAVE / 2, WAVE);
                 fy += __shfl_xor(fy, WAVE / 2, WAVE);
             }
-            if (grp == 0 && valid) {
-                const CellGeo g = geo(t, c);
-                const double inv_w = 1.0 / g.w;
-                const float2 *Lc = Lleaf + (int64_t)li * (P + 1);
-                // far field: incoming expansion of the leaf (Horner in the scaled variable)
-                const float2 v = make_float2((float)(((double)me.x - g.cx) * inv_w),
-                                             (float)(((double)me.y - g.cy) * inv_w));
-                float2 acc = cscale(Lc[P], (float)P);
+            if (grp == 0 && valid) near[t0 + ti] = make_float2(fx, fy);
+        }
+    }
+}
+
+// k_far: far field of every particle from its leaf's incoming expansion
+// (L2P) and the W list's outgoing expansions (M2P), added to the near field;
+// one wave per leaf, lanes on particles.
+template <int P>
+__global__ __launch_bounds__(256) void k_far(TreeView t, const float4 *__restrict__ part,
+                                             const float2 *__restrict__ M, const float2 *__restrict__ Lleaf,
+                                             const int64_t *__restrict__ offUW, const int32_t *__restrict__ W,
+                                             const int32_t *__restrict__ cbeg, const int32_t *__restrict__ cend,
+                                             const int32_t *__restrict__ leaf_cell, const float2 *__restrict__ near,
+                                             float kr, float2 *__restrict__ fr)
+{
+    const int nleaves = t.counts[1];
+    const int lane = lane_id();
+    const int wpb = blockDim.x / WAVE;
+    const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
+    for (int li = first; li < nleaves; li += gridDim.x * wpb) {
+        const int c = leaf_cell[li];
+        const int b = cbeg[c], e = cend[c];
+        const int64_t ou0 = offUW[li], ou1 = offUW[li + 1];
+        const int w0 = (int)(ou0 >> 32), w1 = (int)(ou1 >> 32);
+        const CellGeo g = geo(t, c);
+        const double inv_w = 1.0 / g.w;
+        const float2 *Lc = Lleaf + (int64_t)li * (P + 1);
+        for (int t0 = b + lane; t0 < e; t0 += WAVE) {
+            const float4 me = part[t0];
+            const float2 nf = near[t0];
+            // far field: incoming expansion of the leaf (Horner in the scaled variable)
+            const float2 v = make_float2((float)(((double)me.x - g.cx) * inv_w), (float)(((double)me.y - g.cy) * inv_w));
+            float2 acc = cscale(Lc[P], (float)P);
 #pragma unroll
-                for (int l = P - 1; l >= 1; --l) acc = cadd(cmul(acc, v), cscale(Lc[l], (float)l));
-                float2 dphi = cscale(acc, (float)inv_w);
-                // W list: outgoing expansions of small separated cells at the particle
-                for (int we = w0; we < w1; ++we) {
-                    const int s = W[we];
-                    const CellGeo gs = geo(t, s);
-                    const double inv_ws = 1.0 / gs.w;
-                    const float2 tt = crecip(make_float2((float)(((double)me.x - gs.cx) * inv_ws),
-                                                         (float)(((double)me.y - gs.cy) * inv_ws)));
-                    const float2 *Ms = M + (int64_t)s * (P + 1);
-                    float2 sum = make_float2(Ms[0].x, 0.f);
-                    float2 pw = tt;
+            for (int l = P - 1; l >= 1; --l) acc = cadd(cmul(acc, v), cscale(Lc[l], (float)l));
+            float2 dphi = cscale(acc, (float)inv_w);
+            // W list: outgoing expansions of small separated cells at the particle
+            for (int we = w0; we < w1; ++we) {
+                const int s = W[we];
+                const CellGeo gs = geo(t, s);
+                const double inv_ws = 1.0 / gs.w;
+                const float2 tt = crecip(make_float2((float)(((double)me.x - gs.cx) * inv_ws),
+                                                     (float)(((double)me.y - gs.cy) * inv_ws)));
+                const float2 *Ms = M + (int64_t)s * (P + 1);
+                float2 sum = make_float2(Ms[0].x, 0.f);
+                float2 pw = tt;
 #pragma unroll
-                    for (int k = 1; k <= P; ++k) {
-                        const float2 tk = cmul(Ms[k], pw);
-                        sum.x -= (float)k * tk.x;
-                        sum.y -= (float)k * tk.y;
-                        pw = cmul(pw, tt);
-                    }
-                    dphi = cadd(dphi, cscale(cmul(tt, sum), (float)inv_ws));
+                for (int k = 1; k <= P; ++k) {
+                    const float2 tk = cmul(Ms[k], pw);
+                    sum.x -= (float)k * tk.x;
+                    sum.y -= (float)k * tk.y;
+                    pw = cmul(pw, tt);
                 }
-                // F = kr m_i (conj(phi'_far) + near field)
-                const float km = kr * me.z;
-                const int orig = __float_as_int(me.w);
-                fr[orig] = make_float2(km * (dphi.x + fx), km * (fy - dphi.y));  // one 8-byte store per node
+                dphi = cadd(dphi, cscale(cmul(tt, sum), (float)inv_ws));
             }
+            // F = kr m_i (conj(phi'_far) + near field)
+            const float km = kr * me.z;
+            const int orig = __float_as_int(me.w);
+            fr[orig] = make_float2(km * (dphi.x + nf.x), km * (nf.y - dphi.y));  // one 8-byte store per node
         }
     }
 }
@@ -592,41 +623,53 @@ void upward_p(fl_ctx *c, hipStream_t s, const TreeBufs &t, const FmmBufs<P> &b)
     FL_LAUNCH_CHECK();
 }
 
-// incoming expansions (M2L, P2L, L2L) and the evaluation at the particles
+// incoming expansions: M2L and P2L into every cell, L2L down to the leaves
 template <int P>
-void downward_eval_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b, float kr, float2 *fr)
+void m2l_p(fl_ctx *c, hipStream_t s, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b)
 {
     TreeView tv = view(t);
-    const unsigned gl = grid_for(t.leaves_cap, 256, 2048);
-    {
-        PhaseTimer pt(c, FL_PH_M2L);
-        hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(t.cells_cap, 8, 16384)), dim3(256), 0, c->stream, tv,
-                           (const float4 *)t.part, b.M, L.offVX, L.V, L.X, b.Lp);
-        hipLaunchKernelGGL(k_l2l<P>, dim3(gl), dim3(256), 0, c->stream, tv, b.Lp, b.Ll);
-        FL_LAUNCH_CHECK();
-    }
-    {
-        PhaseTimer pt(c, FL_PH_EVAL);
-        // about one wave per leaf (4 waves per block): leaves differ a lot in
-        // cost, and the dispatcher balances single-leaf waves far better than
-        // a fixed stride of several leaves per wave
-        const unsigned ge = grid_for(t.leaves_cap, 4, 16384);
-        hipLaunchKernelGGL(k_eval<P>, dim3(ge), dim3(256), 0, c->stream, tv, (const float4 *)t.part, b.M, b.Ll,
-                           L.offUW, (const int2 *)L.U, (const int32_t *)L.nU, L.W, (const int32_t *)t.beg,
-                           (const int32_t *)t.end, (const int32_t *)t.leaf_cell, kr, fr);
-        FL_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL(k_m2l<P>, dim3(grid_for(t.cells_cap, 8, 16384)), dim3(256), 0, s, tv, (const float4 *)t.part,
+                       b.M, L.offVX, L.V, L.X, b.Lp);
+    hipLaunchKernelGGL(k_l2l<P>, dim3(grid_for(t.leaves_cap, 256, 2048)), dim3(256), 0, s, tv, b.Lp, b.Ll);
+    FL_LAUNCH_CHECK();
 }
 
-// Lists and the upward pass both need only the tree: unless phases are
-// being timed (or the context's branches are off), the upward pass runs on a
-// branch stream beside the lists (fork and join by events, recorded as
-// parallel branches under capture).
+// near field (P2P) of every particle: about one wave per leaf (4 waves per
+// block): leaves differ a lot in cost, and the dispatcher balances
+// single-leaf waves far better than a fixed stride of several per wave
+void near_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float2 *near)
+{
+    TreeView tv = view(t);
+    hipLaunchKernelGGL(k_p2p, dim3(grid_for(t.leaves_cap, 4, 16384)), dim3(256), 0, c->stream, tv,
+                       (const float4 *)t.part, L.offUW, (const int2 *)L.U, (const int32_t *)L.nU,
+                       (const int32_t *)t.beg, (const int32_t *)t.end, (const int32_t *)t.leaf_cell, near);
+    FL_LAUNCH_CHECK();
+}
+
+template <int P>
+void far_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b, const float2 *near, float kr,
+           float2 *fr)
+{
+    TreeView tv = view(t);
+    hipLaunchKernelGGL(k_far<P>, dim3(grid_for(t.leaves_cap, 4, 16384)), dim3(256), 0, c->stream, tv,
+                       (const float4 *)t.part, (const float2 *)b.M, (const float2 *)b.Ll, L.offUW,
+                       (const int32_t *)L.W, (const int32_t *)t.beg, (const int32_t *)t.end,
+                       (const int32_t *)t.leaf_cell, near, kr, fr);
+    FL_LAUNCH_CHECK();
+}
+
+// The lists and the upward pass need only the tree; the near field needs
+// only the lists, M2L both.  Unless phases are being timed (or the
+// context's branches are off), the upward pass, then M2L and L2L, run on a
+// branch stream while the main stream builds the lists and evaluates the
+// near field; the far field joins the two (events; recorded as parallel
+// branches under capture).
 template <int P>
 void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
 {
     ListBufs L;
     const FmmBufs<P> b = fmm_bufs<P>(c, t);
+    float2 *near = ws<float2>(c, "f_near", (size_t)t.n);
     if (c->timing || !c->branches) {
         {
             PhaseTimer pt(c, FL_PH_LISTS);
@@ -636,18 +679,31 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
             PhaseTimer pt(c, FL_PH_UPWARD);
             upward_p<P>(c, c->stream, t, b);
         }
+        {
+            PhaseTimer pt(c, FL_PH_M2L);
+            m2l_p<P>(c, c->stream, t, L, b);
+        }
+        {
+            PhaseTimer pt(c, FL_PH_EVAL);
+            near_p(c, t, L, near);
+        }
     } else {
         hipStream_t us = aux_stream(c, 3);
-        if (!c->ev_fork2) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_fork2, hipEventDisableTiming));
-        if (!c->ev_join2) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_join2, hipEventDisableTiming));
+        for (hipEvent_t *e : {&c->ev_fork2, &c->ev_join2, &c->ev_lists})
+            if (!*e) FL_CHECK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         FL_CHECK_HIP(hipEventRecord(c->ev_fork2, c->stream));
         FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_fork2, 0));
         upward_p<P>(c, us, t, b);
-        FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
         build_lists(c, t, L, lanes);
+        FL_CHECK_HIP(hipEventRecord(c->ev_lists, c->stream));
+        FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_lists, 0));
+        m2l_p<P>(c, us, t, L, b);
+        FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
+        near_p(c, t, L, near);
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
     }
-    downward_eval_p<P>(c, t, L, b, kr, fr);
+    PhaseTimer pt(c, FL_PH_FAR);
+    far_p<P>(c, t, L, b, near, kr, fr);
 }
 
 }  // namespace

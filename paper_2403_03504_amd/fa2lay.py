@@ -29,7 +29,7 @@ REP_EXACT, REP_FMM, REP_AUTO = 0, 1, 2
 KK_MAJORIZATION, KK_NEWTON = 0, 1
 KK_REDUCE_LEAVES, KK_REDUCE_CHAINS = 1, 2
 TUNE_MAX_BUCKETS = 16
-PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact", "bh")
+PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact", "bh", "far")
 
 EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",

@@ -720,7 +720,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                                                     const int64_t *__restrict__ offUW, int32_t *__restrict__ V,
                                                     int32_t *__restrict__ X, int2 *__restrict__ U,
                                                     int32_t *__restrict__ nU, int32_t *__restrict__ W,
-                                                    unsigned long long *__restrict__ wave_pairs, int64_t cap,
+                                                    unsigned long long *__restrict__ block_pairs, int64_t cap,
                                                     int64_t lcap, int64_t v_cap, int64_t x_cap, int64_t u_cap,
                                                     int64_t w_cap, int32_t *__restrict__ err,
                                                     const int64_t *__restrict__ lanecnt,
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                       (tuw >> 32) <= w_cap;
     if (!fits) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 4);
-        if (lane_id() == 0) wave_pairs[blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE] = 0ull;
+        if (threadIdx.x == 0) block_pairs[blockIdx.x] = 0ull;
         return;
     }
     const int64_t H = hash_size(ncells, t.hash_cap);
@@ -840,22 +840,23 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
         // lane 0 is done with the stage before the next cell's lanes write it
         lds_wave_sync();
     }
-    // one partial per wave, summed by k_lists_stats: thousands of waves
+    // one partial per block, summed by k_lists_stats: thousands of waves
     // adding to one global counter serialise at the memory side and stall
     // the loads of every wave queued behind them
-    pairs = wave_sum(pairs);
-    if (lane_id() == 0) wave_pairs[wid] = pairs;
+    __shared__ unsigned long long red[256 / WAVE];
+    pairs = block_sum<unsigned long long, 256>(pairs, red);
+    if (threadIdx.x == 0) block_pairs[blockIdx.x] = pairs;
 }
 
 __global__ __launch_bounds__(256) void k_lists_stats(const int32_t *__restrict__ counts,
                                                      const int64_t *__restrict__ offVX,
                                                      const int64_t *__restrict__ offUW,
-                                                     const unsigned long long *__restrict__ wave_pairs, int nwaves,
+                                                     const unsigned long long *__restrict__ block_pairs, int nblocks,
                                                      int64_t *__restrict__ st, int n)
 {
     __shared__ unsigned long long red[256 / WAVE];
     unsigned long long p = 0;
-    for (int i = threadIdx.x; i < nwaves; i += 256) p += wave_pairs[i];
+    for (int i = threadIdx.x; i < nblocks; i += 256) p += block_pairs[i];
     p = block_sum<unsigned long long, 256>(p, red);
     if (threadIdx.x != 0) return;
     const int64_t tvx = offVX[counts[0]], tuw = offUW[counts[1]];
@@ -1105,13 +1106,12 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
     scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
     auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
-    const int nwaves = (int)lg * (256 / WAVE);
-    unsigned long long *wave_pairs = ws<unsigned long long>(c, "l_wave_pairs", (size_t)nwaves);
+    unsigned long long *block_pairs = ws<unsigned long long>(c, "l_block_pairs", (size_t)lg);
     hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
-                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, wave_pairs, cap, lcap, L.v_cap, L.x_cap,
+                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, block_pairs, cap, lcap, L.v_cap, L.x_cap,
                        L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt, (const int4 *)slots);
     hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(256), 0, c->stream, t.counts, (const int64_t *)L.offVX,
-                       (const int64_t *)L.offUW, (const unsigned long long *)wave_pairs, nwaves, c->d_stats, t.n);
+                       (const int64_t *)L.offUW, (const unsigned long long *)block_pairs, (int)lg, c->d_stats, t.n);
     FL_LAUNCH_CHECK();
 }
 

@@ -267,7 +267,8 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
 // tile in launch order from a ticket counter, ranks it, publishes its per-digit
 // counts, and finds the number of keys of each digit in the tiles before it
 // by walking back over their published words until one carries an inclusive
-// prefix (Merrill & Garland 2016).  A tile waits only on tiles that were
+// prefix (Merrill & Garland 2016); the first pass reads its tiles' prefixes
+// from the counting launches instead.  A tile waits only on tiles that were
 // taken before it, by blocks that are running and publish their counts
 // before they wait themselves, so every wait ends; a bounded spin guards the
 // launch anyway and flags an error instead of hanging.
@@ -311,16 +312,30 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ key
 
 // Sums the per-tile counts: one wave per (pass, digit) entry, its lanes
 // over the tiles, then a wave sum (integers: the order does not matter).
+// The first pass's tiles are the input's own, so for it the wave also
+// writes every tile's exclusive prefix of the digit (pfx0[tile][digit]):
+// that pass needs no look-back.
 __global__ __launch_bounds__(RS_NT) void k_rs_hist_sum(const uint32_t *__restrict__ part, int ntiles, int passes,
-                                                        uint32_t *__restrict__ gh)
+                                                        uint32_t *__restrict__ gh, uint32_t *__restrict__ pfx0)
 {
     const int i = blockIdx.x * RS_NW + threadIdx.x / WAVE;  // pass * 256 + digit
     if (i >= passes * RS_BINS) return;
     const int64_t st = (int64_t)passes * RS_BINS;
+    const int lane = lane_id();
     uint32_t sum = 0u;
-    for (int b = lane_id(); b < ntiles; b += WAVE) sum += part[(int64_t)b * st + i];
-    sum = wave_sum(sum);
-    if (lane_id() == 0) gh[i] = sum;
+    if (i < RS_BINS) {
+        for (int b0 = 0; b0 < ntiles; b0 += WAVE) {
+            const int b = b0 + lane;
+            const uint32_t v = b < ntiles ? part[(int64_t)b * st + i] : 0u;
+            const uint32_t inc = wave_incl_scan(v);
+            if (b < ntiles) pfx0[(int64_t)b * RS_BINS + i] = sum + inc - v;
+            sum += __shfl(inc, WAVE - 1, WAVE);
+        }
+    } else {
+        for (int b = lane; b < ntiles; b += WAVE) sum += part[(int64_t)b * st + i];
+        sum = wave_sum(sum);
+    }
+    if (lane == 0) gh[i] = sum;
 }
 
 template <class K, bool HasVal>
@@ -328,11 +343,12 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
                                                         K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
                                                         int shift, const uint32_t *__restrict__ gh,
                                                         uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
-                                                        int32_t *__restrict__ err)
+                                                        const uint32_t *__restrict__ pfx, int32_t *__restrict__ err)
 {
     __shared__ RsShared<K, HasVal> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
-    if (threadIdx.x == 0) S.tile = (int)atomicAdd(ticket, 1u);
+    // with the tiles' prefixes given (first pass) the tile is the block's own
+    if (threadIdx.x == 0) S.tile = pfx ? (int)blockIdx.x : (int)atomicAdd(ticket, 1u);
     __syncthreads();
     const int tile = S.tile;
     K key[RS_STEPS];
@@ -341,12 +357,15 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
     const int d = threadIdx.x;
     const uint32_t cnt = (uint32_t)rs_rank<K, HasVal>(S, kin, vin, n, shift, tile, key, val, off, dig);
     uint32_t *my = status + (int64_t)tile * RS_BINS + d;
-    __hip_atomic_store(my, (tile == 0 ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!pfx)
+        __hip_atomic_store(my, (tile == 0 ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // global start of the digit: counts of the smaller digits
     int tot;
     const uint32_t dstart = (uint32_t)block_excl_scan<int, RS_NT>((int)gh[d], S.scan_tmp, tot);
     uint32_t before = 0;
-    if (tile > 0) {
+    if (pfx) {
+        before = pfx[(int64_t)tile * RS_BINS + d];
+    } else if (tile > 0) {
         // look back RS_LOOK tiles at a time (independent loads in flight),
         // consuming counts in order until an inclusive prefix; a tile that
         // has published nothing yet stops the window and is read again
@@ -410,12 +429,14 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
         if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
         hipLaunchKernelGGL(k_rs_hist_all<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)k, n, passes, part,
                            status, nstatus, gh, nz);
+        uint32_t *pfx0 = ws<uint32_t>(c, (std::string("rs_pfx0_") + tag).c_str(), (size_t)nblocks * RS_BINS);
         hipLaunchKernelGGL(k_rs_hist_sum, dim3(passes * RS_BINS / RS_NW), dim3(RS_NT), 0, c->stream,
-                           (const uint32_t *)part, nblocks, passes, gh);
+                           (const uint32_t *)part, nblocks, passes, gh, pfx0);
         for (int ps = 0; ps < passes; ++ps) {
             hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
                                (const int32_t *)va, kb, vb, n, ps * RS_BITS, (const uint32_t *)(gh + ps * RS_BINS),
-                               status + (int64_t)ps * nblocks * RS_BINS, ticket + ps, err);
+                               status + (int64_t)ps * nblocks * RS_BINS, ticket + ps,
+                               ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err);
             std::swap(ka, kb);
             std::swap(va, vb);
         }

@@ -27,9 +27,9 @@
 //             on interleaved sources, staged 64 at a time in LDS and read
 //             there by each group (no per-pair selects); the groups are
 //             combined with xor shuffles (fixed order).
-//   k_far     one wave per leaf, lanes on particles: far field from the
-//             incoming expansion (L2P) and the W list's outgoing expansions
-//             (M2P), added to the near field; the force goes to the node's
+//   k_far     one thread per particle: far field from its leaf's incoming
+//             expansion (L2P) and the W list's outgoing expansions (M2P),
+//             added to the near field; the force goes to the node's
 //             original index.
 //
 // Launch shapes: P2M, M2L and the evaluations launch about one wave per leaf
@@ -62,8 +62,12 @@ constexpr float binomf(int n, int k)
     return (float)r;
 }
 
+// Centre, width w = L 2^-l and its reciprocal.  The root record holds
+// 2^bits / L correctly rounded, so 2^(l - bits) times it is 1 / w correctly
+// rounded (a power-of-two scaling is exact): the same bits as the FP64
+// division, without one.
 struct CellGeo {
-    double cx, cy, w;
+    double cx, cy, w, iw;
 };
 
 __device__ __forceinline__ CellGeo geo(const TreeView &t, int c)
@@ -73,7 +77,8 @@ __device__ __forceinline__ CellGeo geo(const TreeView &t, int c)
     const int l = t.lvl[c];
     const uint32_t v = t.ixy[c];
     const double w = ldexp(L, -l);
-    return CellGeo{x0 + ((double)cell_ix(v) + 0.5) * w, y0 + ((double)cell_iy(v) + 0.5) * w, w};
+    return CellGeo{x0 + ((double)cell_ix(v) + 0.5) * w, y0 + ((double)cell_iy(v) + 0.5) * w, w,
+                   ldexp(rt[3], l - t.bits)};
 }
 
 __device__ __forceinline__ float2 rel(float x, float y, const CellGeo &g)
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const float4 *__restric
     for (int li = blockIdx.x * wpb + w; li < nleaves; li += gridDim.x * wpb) {
         const int c = leaf_cell[li];
         const CellGeo g = geo(t, c);
-        const double inv_w = 1.0 / g.w;
+        const double inv_w = g.iw;
         const int b = t.beg[c], e = t.end[c];
         float2 acc = make_float2(0.f, 0.f);
         for (int t0 = b; t0 < e; t0 += WAVE) {
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restric
         const bool anyx = __ballot(live && x1 > x0) != 0;
         if (anyx && live && x1 > x0) {
             const CellGeo g = geo(t, c);
-            const double inv_w = 1.0 / g.w;
+            const double inv_w = g.iw;
             for (int e = x0; e < x1; ++e) {
                 const int s = X[e];
                 const int sb = t.beg[s], se = t.end[s];
@@ -443,7 +448,7 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
                                              const int64_t *__restrict__ offUW, const int2 *__restrict__ U,
                                              const int32_t *__restrict__ nU, const int32_t *__restrict__ cbeg,
                                              const int32_t *__restrict__ cend, const int32_t *__restrict__ leaf_cell,
-                                             float2 *__restrict__ near)
+                                             float2 *__restrict__ near, int32_t *__restrict__ pleaf)
 {
     __shared__ float4 stage[4][WAVE + 4];  // per wave: sources of the small-leaf path, zero-mass padded
     const int nleaves = t.counts[1];
@@ -522,67 +527,65 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
                 fx += __shfl_xor(fx, WAVE / 2, WAVE);
                 fy += __shfl_xor(fy, WAVE / 2, WAVE);
             }
-            if (grp == 0 && valid) near[t0 + ti] = make_float2(fx, fy);
+            if (grp == 0 && valid) {
+                near[t0 + ti] = make_float2(fx, fy);
+                pleaf[t0 + ti] = li;
+            }
         }
     }
 }
 
 // k_far: far field of every particle from its leaf's incoming expansion
 // (L2P) and the W list's outgoing expansions (M2P), added to the near field;
-// one wave per leaf, lanes on particles.
+// one thread per particle (sorted order), its leaf from the near-field pass.
+// A wave then holds 64 particles of one or two leaves, so every lane works
+// and the leaf data it shares arrives once through the caches.
 template <int P>
-__global__ __launch_bounds__(256) void k_far(TreeView t, const float4 *__restrict__ part,
+__global__ __launch_bounds__(256) void k_far(TreeView t, int n, const float4 *__restrict__ part,
                                              const float2 *__restrict__ M, const float2 *__restrict__ Lleaf,
                                              const int64_t *__restrict__ offUW, const int32_t *__restrict__ W,
-                                             const int32_t *__restrict__ cbeg, const int32_t *__restrict__ cend,
-                                             const int32_t *__restrict__ leaf_cell, const float2 *__restrict__ near,
-                                             float kr, float2 *__restrict__ fr)
+                                             const int32_t *__restrict__ leaf_cell, const int32_t *__restrict__ pleaf,
+                                             const float2 *__restrict__ near, float kr, float2 *__restrict__ fr)
 {
-    const int nleaves = t.counts[1];
-    const int lane = lane_id();
-    const int wpb = blockDim.x / WAVE;
-    const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
-    for (int li = first; li < nleaves; li += gridDim.x * wpb) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int li = pleaf[k];
         const int c = leaf_cell[li];
-        const int b = cbeg[c], e = cend[c];
-        const int64_t ou0 = offUW[li], ou1 = offUW[li + 1];
-        const int w0 = (int)(ou0 >> 32), w1 = (int)(ou1 >> 32);
+        const float4 me = part[k];
+        const float2 nf = near[k];
+        const int w0 = (int)(offUW[li] >> 32), w1 = (int)(offUW[li + 1] >> 32);
         const CellGeo g = geo(t, c);
-        const double inv_w = 1.0 / g.w;
+        const double inv_w = g.iw;
         const float2 *Lc = Lleaf + (int64_t)li * (P + 1);
-        for (int t0 = b + lane; t0 < e; t0 += WAVE) {
-            const float4 me = part[t0];
-            const float2 nf = near[t0];
-            // far field: incoming expansion of the leaf (Horner in the scaled variable)
-            const float2 v = make_float2((float)(((double)me.x - g.cx) * inv_w), (float)(((double)me.y - g.cy) * inv_w));
-            float2 acc = cscale(Lc[P], (float)P);
+        // far field: incoming expansion of the leaf (Horner in the scaled variable)
+        const float2 v =
+            make_float2((float)(((double)me.x - g.cx) * inv_w), (float)(((double)me.y - g.cy) * inv_w));
+        float2 acc = cscale(Lc[P], (float)P);
 #pragma unroll
-            for (int l = P - 1; l >= 1; --l) acc = cadd(cmul(acc, v), cscale(Lc[l], (float)l));
-            float2 dphi = cscale(acc, (float)inv_w);
-            // W list: outgoing expansions of small separated cells at the particle
-            for (int we = w0; we < w1; ++we) {
-                const int s = W[we];
-                const CellGeo gs = geo(t, s);
-                const double inv_ws = 1.0 / gs.w;
-                const float2 tt = crecip(make_float2((float)(((double)me.x - gs.cx) * inv_ws),
-                                                     (float)(((double)me.y - gs.cy) * inv_ws)));
-                const float2 *Ms = M + (int64_t)s * (P + 1);
-                float2 sum = make_float2(Ms[0].x, 0.f);
-                float2 pw = tt;
+        for (int l = P - 1; l >= 1; --l) acc = cadd(cmul(acc, v), cscale(Lc[l], (float)l));
+        float2 dphi = cscale(acc, (float)inv_w);
+        // W list: outgoing expansions of small separated cells at the particle
+        for (int we = w0; we < w1; ++we) {
+            const int s = W[we];
+            const CellGeo gs = geo(t, s);
+            const double inv_ws = gs.iw;
+            const float2 tt = crecip(make_float2((float)(((double)me.x - gs.cx) * inv_ws),
+                                                 (float)(((double)me.y - gs.cy) * inv_ws)));
+            const float2 *Ms = M + (int64_t)s * (P + 1);
+            float2 sum = make_float2(Ms[0].x, 0.f);
+            float2 pw = tt;
 #pragma unroll
-                for (int k = 1; k <= P; ++k) {
-                    const float2 tk = cmul(Ms[k], pw);
-                    sum.x -= (float)k * tk.x;
-                    sum.y -= (float)k * tk.y;
-                    pw = cmul(pw, tt);
-                }
-                dphi = cadd(dphi, cscale(cmul(tt, sum), (float)inv_ws));
+            for (int q = 1; q <= P; ++q) {
+                const float2 tk = cmul(Ms[q], pw);
+                sum.x -= (float)q * tk.x;
+                sum.y -= (float)q * tk.y;
+                pw = cmul(pw, tt);
             }
-            // F = kr m_i (conj(phi'_far) + near field)
-            const float km = kr * me.z;
-            const int orig = __float_as_int(me.w);
-            fr[orig] = make_float2(km * (dphi.x + nf.x), km * (nf.y - dphi.y));  // one 8-byte store per node
+            dphi = cadd(dphi, cscale(cmul(tt, sum), (float)inv_ws));
         }
+        // F = kr m_i (conj(phi'_far) + near field)
+        const float km = kr * me.z;
+        const int orig = __float_as_int(me.w);
+        fr[orig] = make_float2(km * (dphi.x + nf.x), km * (nf.y - dphi.y));  // one 8-byte store per node
     }
 }
 #undef FL_P2P_PAIR
@@ -637,24 +640,24 @@ void m2l_p(fl_ctx *c, hipStream_t s, const TreeBufs &t, const ListBufs &L, const
 // near field (P2P) of every particle: about one wave per leaf (4 waves per
 // block): leaves differ a lot in cost, and the dispatcher balances
 // single-leaf waves far better than a fixed stride of several per wave
-void near_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float2 *near)
+void near_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, float2 *near, int32_t *pleaf)
 {
     TreeView tv = view(t);
     hipLaunchKernelGGL(k_p2p, dim3(grid_for(t.leaves_cap, 4, 16384)), dim3(256), 0, c->stream, tv,
                        (const float4 *)t.part, L.offUW, (const int2 *)L.U, (const int32_t *)L.nU,
-                       (const int32_t *)t.beg, (const int32_t *)t.end, (const int32_t *)t.leaf_cell, near);
+                       (const int32_t *)t.beg, (const int32_t *)t.end, (const int32_t *)t.leaf_cell, near, pleaf);
     FL_LAUNCH_CHECK();
 }
 
 template <int P>
-void far_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b, const float2 *near, float kr,
-           float2 *fr)
+void far_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b, const float2 *near,
+           const int32_t *pleaf, float kr, float2 *fr)
 {
     TreeView tv = view(t);
-    hipLaunchKernelGGL(k_far<P>, dim3(grid_for(t.leaves_cap, 4, 16384)), dim3(256), 0, c->stream, tv,
-                       (const float4 *)t.part, (const float2 *)b.M, (const float2 *)b.Ll, L.offUW,
-                       (const int32_t *)L.W, (const int32_t *)t.beg, (const int32_t *)t.end,
-                       (const int32_t *)t.leaf_cell, near, kr, fr);
+    hipLaunchKernelGGL(k_far<P>, dim3(grid_for(t.n, 256, 16384)), dim3(256), 0, c->stream, tv, t.n,
+                       (const float4 *)t.part,
+                       (const float2 *)b.M, (const float2 *)b.Ll, L.offUW, (const int32_t *)L.W,
+                       (const int32_t *)t.leaf_cell, pleaf, near, kr, fr);
     FL_LAUNCH_CHECK();
 }
 
@@ -670,6 +673,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
     ListBufs L;
     const FmmBufs<P> b = fmm_bufs<P>(c, t);
     float2 *near = ws<float2>(c, "f_near", (size_t)t.n);
+    int32_t *pleaf = ws<int32_t>(c, "f_pleaf", (size_t)t.n);
     if (c->timing || !c->branches) {
         {
             PhaseTimer pt(c, FL_PH_LISTS);
@@ -685,7 +689,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
         }
         {
             PhaseTimer pt(c, FL_PH_EVAL);
-            near_p(c, t, L, near);
+            near_p(c, t, L, near, pleaf);
         }
     } else {
         hipStream_t us = aux_stream(c, 3);
@@ -699,11 +703,11 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
         FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_lists, 0));
         m2l_p<P>(c, us, t, L, b);
         FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
-        near_p(c, t, L, near);
+        near_p(c, t, L, near, pleaf);
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
     }
     PhaseTimer pt(c, FL_PH_FAR);
-    far_p<P>(c, t, L, b, near, kr, fr);
+    far_p<P>(c, t, L, b, near, pleaf, kr, fr);
 }
 
 }  // namespace

@@ -216,7 +216,8 @@ template <class K, bool HasVal>
 __device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__ kout, int32_t *__restrict__ vout,
                                          int64_t n, int shift, int64_t tile, const K (&key)[RS_STEPS],
                                          const int32_t (&val)[RS_STEPS], const int (&off)[RS_STEPS],
-                                         const int (&dig)[RS_STEPS])
+                                         const int (&dig)[RS_STEPS], const float4 *__restrict__ gsrc,
+                                         float4 *__restrict__ gdst)
 {
     const int w = threadIdx.x / WAVE;
 #pragma unroll
@@ -236,7 +237,11 @@ __device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__
         const int64_t pos = (int64_t)S.gbase[d] + (i - S.lstart[d]);
         if (pos < n) {  // always true unless a look-back gave up (error flagged)
             kout[pos] = k2;
-            if (HasVal) vout[pos] = S.sval[i];
+            if (HasVal) {
+                const int32_t v = S.sval[i];
+                vout[pos] = v;
+                if (gdst) gdst[pos] = gsrc[v];  // last pass: the record of the value's index, moved along
+            }
         }
     }
 }
@@ -246,7 +251,8 @@ __device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__
 template <class K, bool HasVal>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin,
                                                        K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
-                                                       int shift, const int32_t *__restrict__ hscan, int nblocks)
+                                                       int shift, const int32_t *__restrict__ hscan, int nblocks,
+                                                       const float4 *__restrict__ gsrc, float4 *__restrict__ gdst)
 {
     __shared__ RsShared<K, HasVal> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
     int off[RS_STEPS], dig[RS_STEPS];
     rs_rank<K, HasVal>(S, kin, vin, n, shift, blockIdx.x, key, val, off, dig);
     __syncthreads();
-    rs_place<K, HasVal>(S, kout, vout, n, shift, blockIdx.x, key, val, off, dig);
+    rs_place<K, HasVal>(S, kout, vout, n, shift, blockIdx.x, key, val, off, dig, gsrc, gdst);
 }
 
 // ---- one launch per pass: decoupled look-back --------------------------------
@@ -343,7 +349,8 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
                                                         K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
                                                         int shift, const uint32_t *__restrict__ gh,
                                                         uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
-                                                        const uint32_t *__restrict__ pfx, int32_t *__restrict__ err)
+                                                        const uint32_t *__restrict__ pfx, int32_t *__restrict__ err,
+                                                        const float4 *__restrict__ gsrc, float4 *__restrict__ gdst)
 {
     __shared__ RsShared<K, HasVal> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
@@ -406,12 +413,12 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
     }
     S.gbase[d] = (int)(dstart + before);
     __syncthreads();
-    rs_place<K, HasVal>(S, kout, vout, n, shift, tile, key, val, off, dig);
+    rs_place<K, HasVal>(S, kout, vout, n, shift, tile, key, val, off, dig, gsrc, gdst);
 }
 
 template <class K, bool HasVal>
 bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag,
-                int32_t *err)
+                int32_t *err, const float4 *gsrc = nullptr, float4 *gdst = nullptr)
 {
     if (n <= 0) return false;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
@@ -436,7 +443,8 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
             hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
                                (const int32_t *)va, kb, vb, n, ps * RS_BITS, (const uint32_t *)(gh + ps * RS_BINS),
                                status + (int64_t)ps * nblocks * RS_BINS, ticket + ps,
-                               ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err);
+                               ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
+                               ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr);
             std::swap(ka, kb);
             std::swap(va, vb);
         }
@@ -451,7 +459,8 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
         hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, n, shift, hist, nblocks);
         scan_excl<int32_t>(c, hist, hscan, (int64_t)RS_BINS * nblocks, nullptr, tag);
         hipLaunchKernelGGL((k_rs_scatter<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, va, kb, vb, n,
-                           shift, hscan, nblocks);
+                           shift, hscan, nblocks, ps == passes - 1 ? gsrc : nullptr,
+                           ps == passes - 1 ? gdst : nullptr);
         FL_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -477,9 +486,9 @@ void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const in
 }
 
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
-                    int32_t *err)
+                    int32_t *err, const float4 *gsrc, float4 *gdst)
 {
-    return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32", err);
+    return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32", err, gsrc, gdst);
 }
 
 bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits, int32_t *err)

@@ -169,13 +169,16 @@ __global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restr
 }
 
 // Morton key of every node relative to its system's root square; with more
-// than one system also the sort key (system << 32 | key).  When the hash
-// epoch has just wrapped to 1 the table is cleared here (before any insert
-// of this build).
+// than one system also the sort key (system << 32 | key); with `xym` also
+// the node's (x, y, mass, index) record, so that moving a node to its sorted
+// place is a single 16-byte access.  When the hash epoch has
+// just wrapped to 1 the table is cleared here (before any insert of this
+// build).
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, int n,
                          const int32_t *__restrict__ ncomp, const double *__restrict__ root, int bits,
                          uint32_t *__restrict__ key, uint64_t *__restrict__ key64, int32_t *__restrict__ idx,
-                         const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hkey, int64_t hcap)
+                         const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hkey, int64_t hcap,
+                         const int32_t *__restrict__ deg, float4 *__restrict__ xym)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (hkey && epoch && *epoch == 1u)
@@ -184,22 +187,13 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
     const int comp = ncomp ? ncomp[i] : 0;
     const double *rt = root + 4 * (int64_t)comp;
     double x0 = rt[0], y0 = rt[1], S = rt[3];
-    uint32_t qx = quantize(x[i], x0, S, bits), qy = quantize(y[i], y0, S, bits);
+    const float xi = x[i], yi = y[i];
+    uint32_t qx = quantize(xi, x0, S, bits), qy = quantize(yi, y0, S, bits);
     const uint32_t k = part1by1(qx) | (part1by1(qy) << 1);
     if (key) key[i] = k;
     if (key64) key64[i] = ((uint64_t)(uint32_t)comp << 32) | k;
     if (idx) idx[i] = i;
-}
-
-// (x, y, mass, index) of every node in one 16-byte record, so the Morton
-// gather and the CSR attraction fetch a node with a single access
-__global__ void k_pack(const float *__restrict__ x, const float *__restrict__ y, const int32_t *__restrict__ deg,
-                       int n, float4 *__restrict__ xym)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float m = deg ? (float)(deg[i] + 1) : 1.0f;
-    xym[i] = make_float4(x[i], y[i], m, __int_as_float(i));
+    if (xym) xym[i] = make_float4(xi, yi, deg ? (float)(deg[i] + 1) : 1.0f, __int_as_float(i));
 }
 
 // sorted particles; with more than one system also the sorted Morton keys
@@ -1027,28 +1021,25 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     hipLaunchKernelGGL(k_bbox, dim3(s.ntiles), dim3(NT), 0, c->stream, x, y, s, bpart);
     hipLaunchKernelGGL(k_bbox_root, dim3(std::min(s.K, 1024)), dim3(NT), 0, c->stream, s, (const float4 *)bpart,
                        t.root, bits, t.epoch);
+    float4 *xym = ws<float4>(c, "t_xym", n);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
                        (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
-                       t.hkey, t.hash_cap);
+                       t.hkey, t.hash_cap, deg, xym);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
-    int32_t *perm;
-    const uint64_t *sq = nullptr;
     if (s.K > 1) {
         const bool alt = radix_sort_u64v(c, q0, i0, q1, i1, n, 32 + s.cbits, t.counts + 3);
-        sq = alt ? q1 : q0;
-        perm = alt ? i1 : i0;
+        const uint64_t *sq = alt ? q1 : q0;
+        const int32_t *perm = alt ? i1 : i0;
         sk = k0;  // written by k_gather
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float4 *)xym, perm, n,
+                           t.part, sq, sk);
     } else {
-        const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3);
+        // the last pass also moves every node's record to its sorted place
+        const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3, (const float4 *)xym, t.part);
         sk = alt ? k1 : k0;
-        perm = alt ? i1 : i0;
     }
     t.skey = sk;
-    float4 *xym = ws<float4>(c, "t_xym", n);
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, deg, n, xym);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const float4 *)xym, perm, n, t.part,
-                       sq, sk);
     fill_i32(c, t.counts, 3, 0);  // [3] (error bits) is sticky; a kernel, not a memset, so graphs replay it
     hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
                        leaf, s.ncomp, t.pack, cnt2);
@@ -1157,7 +1148,8 @@ void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits,
                        (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, (const int32_t *)nullptr,
                        (const double *)root, bits, key, (uint64_t *)nullptr, (int32_t *)nullptr,
-                       (const uint32_t *)nullptr, (uint64_t *)nullptr, (int64_t)0);
+                       (const uint32_t *)nullptr, (uint64_t *)nullptr, (int64_t)0, (const int32_t *)nullptr,
+                       (float4 *)nullptr);
     FL_LAUNCH_CHECK();
 }
 

@@ -12,6 +12,7 @@
 //   k_update   per-node speed and move p += s_i F, F' <- F
 // There are no floating-point atomics: a run is bitwise reproducible.
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "fl_fa2.h"
@@ -474,7 +475,7 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
 }
 
 static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float *x, const float *y,
-                      const fl_fa2_params *p, float2 *fr)
+                      const fl_fa2_params *p, float2 *fr, const std::function<void(hipEvent_t)> *on_lists = nullptr)
 {
     if (p->repulsion == FL_REP_EXACT) {
         PhaseTimer pt(c, FL_PH_EXACT);
@@ -483,7 +484,7 @@ static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float
         FL_LAUNCH_CHECK();
     } else {
         const int lanes = p->list_lanes ? p->list_lanes : default_list_lanes(sg.n);
-        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, fr);
+        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, fr, on_lists);
     }
 }
 
@@ -509,8 +510,10 @@ struct Sys {
 // one iteration; flags must have been cleared by the caller.  Unless phases
 // are being timed (or the context's branches are off), the attraction
 // gathers run on a branch stream (fork and join by events, which graph
-// capture records as parallel branches) beside the repulsion's tree, lists
-// and passes; the combine then reads their sums.
+// capture records as parallel branches) beside the repulsion; the combine
+// then reads their sums.  With the FMM the branch forks once the lists are
+// built, so that the gathers (bound by memory latency) overlap the
+// ALU-bound near field rather than the latency-bound tree build.
 static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
 {
     fl_ctx *c = b.c;
@@ -528,14 +531,22 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
         hipStream_t as = aux_stream(c, 2);
         if (!c->ev_fork) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         if (!c->ev_join) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        FL_CHECK_HIP(hipEventRecord(c->ev_fork, c->stream));
-        FL_CHECK_HIP(hipStreamWaitEvent(as, c->ev_fork, 0));
-        xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as);
-        hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, NT)), dim3(NT), 0, as, n, b.g.row_ptr, b.g.col, xy,
-                           (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
-        FL_LAUNCH_CHECK();
-        FL_CHECK_HIP(hipEventRecord(c->ev_join, as));
-        repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
+        const std::function<void(hipEvent_t)> side = [&](hipEvent_t after) {
+            FL_CHECK_HIP(hipStreamWaitEvent(as, after, 0));
+            xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as);
+            hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, NT)), dim3(NT), 0, as, n, b.g.row_ptr, b.g.col, xy,
+                               (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
+            FL_LAUNCH_CHECK();
+            FL_CHECK_HIP(hipEventRecord(c->ev_join, as));
+        };
+        if (b.prm.repulsion == FL_REP_EXACT) {
+            FL_CHECK_HIP(hipEventRecord(c->ev_fork, c->stream));
+            side(c->ev_fork);
+            repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
+        } else {
+            repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, &side);
+        }
+        if (!xy) throw Error(FL_EHIP, "iteration: the attraction branch was not forked");
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
     } else {
         repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);

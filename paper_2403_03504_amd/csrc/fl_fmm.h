@@ -1,6 +1,8 @@
 // FMM repulsion driver (fl_fmm.hip) over the tree and lists of fl_tree.h.
 #pragma once
 
+#include <functional>
+
 #include "fl_tree.h"
 
 namespace fl {
@@ -10,8 +12,13 @@ bool fmm_order_supported(int p);
 // F_r of every node in original order into fr (FP32 (x, y) pairs), on the
 // context stream, without host synchronisation.  deg supplies the masses
 // deg + 1.  Every system of `s` is its own particle set: no force crosses
-// systems.  lanes: lanes per cell of the list kernels (1 or 8).
+// systems.  lanes: lanes per cell of the list kernels (1 or 8).  When
+// `on_lists` is given it is called once the list build has been enqueued,
+// with an event recorded on the context stream just after it: work that
+// should overlap the near field (and not the latency-bound tree build) is
+// forked from there.
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, int lanes, float kr, float2 *fr);
+                   int bits, int lanes, float kr, float2 *fr,
+                   const std::function<void(hipEvent_t)> *on_lists = nullptr);
 
 }  // namespace fl

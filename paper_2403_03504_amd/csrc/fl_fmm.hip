@@ -668,7 +668,8 @@ void far_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b,
 // near field; the far field joins the two (events; recorded as parallel
 // branches under capture).
 template <int P>
-void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
+void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
+                const std::function<void(hipEvent_t)> *on_lists)
 {
     ListBufs L;
     const FmmBufs<P> b = fmm_bufs<P>(c, t);
@@ -678,6 +679,11 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
         {
             PhaseTimer pt(c, FL_PH_LISTS);
             build_lists(c, t, L, lanes);
+        }
+        if (on_lists) {
+            if (!c->ev_lists) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_lists, hipEventDisableTiming));
+            FL_CHECK_HIP(hipEventRecord(c->ev_lists, c->stream));
+            (*on_lists)(c->ev_lists);
         }
         {
             PhaseTimer pt(c, FL_PH_UPWARD);
@@ -701,6 +707,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
         build_lists(c, t, L, lanes);
         FL_CHECK_HIP(hipEventRecord(c->ev_lists, c->stream));
         FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_lists, 0));
+        if (on_lists) (*on_lists)(c->ev_lists);
         m2l_p<P>(c, us, t, L, b);
         FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
         near_p(c, t, L, near, pleaf);
@@ -715,7 +722,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr)
 bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16; }
 
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, int lanes, float kr, float2 *fr)
+                   int bits, int lanes, float kr, float2 *fr, const std::function<void(hipEvent_t)> *on_lists)
 {
     TreeBufs t;
     {
@@ -723,12 +730,12 @@ void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, con
         build_tree(c, t, s, x, y, deg, bits, leaf);
     }
     switch (p) {
-    case 4: fmm_passes<4>(c, t, lanes, kr, fr); break;
-    case 6: fmm_passes<6>(c, t, lanes, kr, fr); break;
-    case 8: fmm_passes<8>(c, t, lanes, kr, fr); break;
-    case 10: fmm_passes<10>(c, t, lanes, kr, fr); break;
-    case 12: fmm_passes<12>(c, t, lanes, kr, fr); break;
-    case 16: fmm_passes<16>(c, t, lanes, kr, fr); break;
+    case 4: fmm_passes<4>(c, t, lanes, kr, fr, on_lists); break;
+    case 6: fmm_passes<6>(c, t, lanes, kr, fr, on_lists); break;
+    case 8: fmm_passes<8>(c, t, lanes, kr, fr, on_lists); break;
+    case 10: fmm_passes<10>(c, t, lanes, kr, fr, on_lists); break;
+    case 12: fmm_passes<12>(c, t, lanes, kr, fr, on_lists); break;
+    case 16: fmm_passes<16>(c, t, lanes, kr, fr, on_lists); break;
     default: throw Error(FL_EUNSUPPORTED, "FMM expansion order not built (use 4, 6, 8, 10, 12 or 16)");
     }
 }

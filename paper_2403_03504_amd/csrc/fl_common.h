@@ -257,6 +257,10 @@ __device__ __forceinline__ T block_sum(T v, T *lds)
 // read as zero.  Three launches.
 void scan_excl_i32(fl_ctx *c, const int32_t *in, int32_t *out, int64_t n, const int32_t *dn = nullptr);
 void scan_excl_i64(fl_ctx *c, const int64_t *in, int64_t *out, int64_t n, const int32_t *dn = nullptr);
+// Two such scans in the same two launches (separately when either is long
+// enough to need the recursive form).
+void scan_excl_i64_pair(fl_ctx *c, const int64_t *in0, int64_t *out0, int64_t n0, const int32_t *dn0,
+                        const int64_t *in1, int64_t *out1, int64_t n1, const int32_t *dn1);
 // FP64 scan, summed in a fixed order (deterministic); `tag` names its
 // workspace, so scans whose results are used together need distinct tags.
 void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const int32_t *dn, const char *tag);

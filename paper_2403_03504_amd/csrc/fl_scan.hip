@@ -10,6 +10,8 @@
 // digit in the tiles before it by decoupled look-back.  Inputs of more than
 // 4M keys take a three-launch pass instead (per-tile histograms, a scan of
 // them, the scatter).
+#include <algorithm>
+
 #include "fl_common.h"
 
 namespace fl {
@@ -22,13 +24,13 @@ constexpr int SC_TILE = SC_NT * SC_IPT;  // 2048
 constexpr int SC_TOP_NT = 1024;
 
 template <class T>
-__global__ __launch_bounds__(SC_NT) void k_scan_reduce(const T *__restrict__ in, int64_t n,
-                                                        const int32_t *__restrict__ dn, T *__restrict__ part)
+__device__ __forceinline__ void scan_reduce_tile(const T *__restrict__ in, int64_t n, const int32_t *__restrict__ dn,
+                                                 T *__restrict__ part, int64_t bx)
 {
     __shared__ T lds[SC_NT / WAVE];
     int64_t live = dn ? (int64_t)*dn : n;
     if (live > n) live = n;
-    int64_t base = (int64_t)blockIdx.x * SC_TILE;
+    int64_t base = bx * SC_TILE;
     T s = T(0);
 #pragma unroll
     for (int i = 0; i < SC_IPT; ++i) {
@@ -36,7 +38,14 @@ __global__ __launch_bounds__(SC_NT) void k_scan_reduce(const T *__restrict__ in,
         if (idx < live) s += in[idx];
     }
     s = block_sum<T, SC_NT>(s, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[bx] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_scan_reduce(const T *__restrict__ in, int64_t n,
+                                                        const int32_t *__restrict__ dn, T *__restrict__ part)
+{
+    scan_reduce_tile<T>(in, n, dn, part, blockIdx.x);
 }
 
 // Each block adds the sums of the tiles before it, then scans its own tile.
@@ -48,16 +57,16 @@ __global__ __launch_bounds__(SC_NT) void k_scan_reduce(const T *__restrict__ in,
 constexpr int64_t SC_DIRECT = 4096;
 
 template <class T>
-__global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T *__restrict__ out, int64_t n,
-                                                      const int32_t *__restrict__ dn, const T *__restrict__ part,
-                                                      int scanned)
+__device__ __forceinline__ void scan_down_tile(const T *__restrict__ in, T *__restrict__ out, int64_t n,
+                                               const int32_t *__restrict__ dn, const T *__restrict__ part,
+                                               int scanned, int64_t bx)
 {
     __shared__ T lds[SC_NT / WAVE];
     int64_t live = dn ? (int64_t)*dn : n;
     if (live > n) live = n;
-    const int64_t tile0 = (int64_t)blockIdx.x * SC_TILE;
+    const int64_t tile0 = bx * SC_TILE;
     const int64_t nlive_tiles = (live + SC_TILE - 1) / SC_TILE;
-    if (blockIdx.x == 0) {
+    if (bx == 0) {
         T tot = T(0);
         if (scanned) {
             tot = part[nlive_tiles];
@@ -73,9 +82,9 @@ __global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T
     if (tile0 >= live) return;  // the whole block
     T carry = T(0);
     if (scanned) {
-        carry = part[blockIdx.x];
+        carry = part[bx];
     } else {
-        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SC_NT) carry += part[b];
+        for (int64_t b = threadIdx.x; b < bx; b += SC_NT) carry += part[b];
         carry = block_sum<T, SC_NT>(carry, lds);
     }
     const int64_t base = tile0 + (int64_t)threadIdx.x * SC_IPT;
@@ -96,6 +105,39 @@ __global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T
         if (idx < n) out[idx] = run;
         run += v[i];
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T *__restrict__ out, int64_t n,
+                                                      const int32_t *__restrict__ dn, const T *__restrict__ part,
+                                                      int scanned)
+{
+    scan_down_tile<T>(in, out, n, dn, part, scanned, blockIdx.x);
+}
+
+// Two independent scans in the same launches: blockIdx.y picks the array
+// (each with its own tiles; blocks past an array's tiles do nothing).
+template <class T>
+struct ScanJob {
+    const T *in;
+    T *out;
+    int64_t n, ntiles;
+    const int32_t *dn;
+    T *part;
+};
+
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_scan_reduce_pair(ScanJob<T> a, ScanJob<T> b)
+{
+    const ScanJob<T> &j = blockIdx.y ? b : a;
+    if ((int64_t)blockIdx.x < j.ntiles) scan_reduce_tile<T>(j.in, j.n, j.dn, j.part, blockIdx.x);
+}
+
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_scan_down_pair(ScanJob<T> a, ScanJob<T> b)
+{
+    const ScanJob<T> &j = blockIdx.y ? b : a;
+    if ((int64_t)blockIdx.x < j.ntiles) scan_down_tile<T>(j.in, j.out, j.n, j.dn, j.part, 0, blockIdx.x);
 }
 
 template <class T>
@@ -478,6 +520,24 @@ void scan_excl_i32(fl_ctx *c, const int32_t *in, int32_t *out, int64_t n, const 
 void scan_excl_i64(fl_ctx *c, const int64_t *in, int64_t *out, int64_t n, const int32_t *dn)
 {
     scan_excl<int64_t>(c, in, out, n, dn, "i64");
+}
+
+void scan_excl_i64_pair(fl_ctx *c, const int64_t *in0, int64_t *out0, int64_t n0, const int32_t *dn0,
+                        const int64_t *in1, int64_t *out1, int64_t n1, const int32_t *dn1)
+{
+    const int64_t t0 = std::max<int64_t>(1, (n0 + SC_TILE - 1) / SC_TILE);
+    const int64_t t1 = std::max<int64_t>(1, (n1 + SC_TILE - 1) / SC_TILE);
+    if (t0 > SC_DIRECT || t1 > SC_DIRECT) {  // a recursive scan: one at a time
+        scan_excl<int64_t>(c, in0, out0, n0, dn0, "i64");
+        scan_excl<int64_t>(c, in1, out1, n1, dn1, "i64b");
+        return;
+    }
+    ScanJob<int64_t> a{in0, out0, n0, t0, dn0, ws<int64_t>(c, "scan_pair_a", (size_t)t0 + 1)};
+    ScanJob<int64_t> b{in1, out1, n1, t1, dn1, ws<int64_t>(c, "scan_pair_b", (size_t)t1 + 1)};
+    const dim3 grid((unsigned)std::max(t0, t1), 2);
+    hipLaunchKernelGGL(k_scan_reduce_pair<int64_t>, grid, dim3(SC_NT), 0, c->stream, a, b);
+    hipLaunchKernelGGL(k_scan_down_pair<int64_t>, grid, dim3(SC_NT), 0, c->stream, a, b);
+    FL_LAUNCH_CHECK();
 }
 
 void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const int32_t *dn, const char *tag)

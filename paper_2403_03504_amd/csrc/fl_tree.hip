@@ -178,9 +178,10 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
                          const int32_t *__restrict__ ncomp, const double *__restrict__ root, int bits,
                          uint32_t *__restrict__ key, uint64_t *__restrict__ key64, int32_t *__restrict__ idx,
                          const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hkey, int64_t hcap,
-                         const int32_t *__restrict__ deg, float4 *__restrict__ xym)
+                         const int32_t *__restrict__ deg, float4 *__restrict__ xym, int32_t *__restrict__ counts)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (counts && i < 3) counts[i] = 0;  // the tree's cell, leaf and level counts ([3], the error bits, is sticky)
     if (hkey && epoch && *epoch == 1u)
         for (int64_t h = i; h < hcap; h += (int64_t)gridDim.x * blockDim.x) hkey[h] = 0ull;
     if (i >= n) return;
@@ -1024,7 +1025,7 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     float4 *xym = ws<float4>(c, "t_xym", n);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
                        (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
-                       t.hkey, t.hash_cap, deg, xym);
+                       t.hkey, t.hash_cap, deg, xym, t.counts);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
     if (s.K > 1) {
@@ -1040,7 +1041,6 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
         sk = alt ? k1 : k0;
     }
     t.skey = sk;
-    fill_i32(c, t.counts, 3, 0);  // [3] (error bits) is sticky; a kernel, not a memset, so graphs replay it
     hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
                        leaf, s.ncomp, t.pack, cnt2);
     FL_LAUNCH_CHECK();
@@ -1094,8 +1094,7 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
         hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt,
                            (int4 *)nullptr);
     FL_LAUNCH_CHECK();
-    scan_excl_i64(c, cntVX, L.offVX, cap, t.counts);
-    scan_excl_i64(c, cntUW, L.offUW, lcap, t.counts + 1);
+    scan_excl_i64_pair(c, cntVX, L.offVX, cap, t.counts, cntUW, L.offUW, lcap, t.counts + 1);
     auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
     unsigned long long *block_pairs = ws<unsigned long long>(c, "l_block_pairs", (size_t)lg);
     hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
@@ -1149,7 +1148,7 @@ void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits,
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, (const int32_t *)nullptr,
                        (const double *)root, bits, key, (uint64_t *)nullptr, (int32_t *)nullptr,
                        (const uint32_t *)nullptr, (uint64_t *)nullptr, (int64_t)0, (const int32_t *)nullptr,
-                       (float4 *)nullptr);
+                       (float4 *)nullptr, (int32_t *)nullptr);
     FL_LAUNCH_CHECK();
 }
 

@@ -289,15 +289,18 @@ __global__ __launch_bounds__(256) void k_m2m_top(TreeView t, const float2 *__res
 // converts source V[j] of its cell (a V list holds at most 27 cells) with the
 // whole M2L of Greengard & Rokhlin's Lemma 2.4 in scaled form, rho = w / z0:
 //   B_l += rho^l [ -Q/l + sum_k C(l+k-1, k-1) (-rho)^k A_k ],
-// and the half's lanes are summed by an xor butterfly (fixed order).  The X
-// list (P2L: particles of coarser separated leaves) is spread over the same
-// lanes, particle by particle, before the butterfly.
+// and the half's lanes are summed through LDS in lane order (fixed order).
+// The X list (P2L: particles of coarser separated leaves) is spread over the
+// same lanes, particle by particle, before the sum.
 template <int P>
 __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restrict__ part,
                                              const float2 *__restrict__ M, const int64_t *__restrict__ offVX,
                                              const int32_t *__restrict__ V, const int32_t *__restrict__ X,
                                              float2 *__restrict__ Lp)
 {
+    constexpr int ROW = 2 * P + 1;  // floats per lane row (odd: no bank conflicts down a column)
+    __shared__ float rows_all[4][WAVE * ROW];
+    float *rows = rows_all[threadIdx.x / WAVE];
     const int ncells = t.counts[0];
     const int lane = lane_id();
     const int half = lane >> 5, j = lane & 31;
@@ -369,19 +372,30 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restric
                 }
             }
         }
+        // sum over the half's 32 lanes through LDS: each lane stores its 2P
+        // components, then lane q < 2P of the half adds component q over the
+        // 32 rows in lane order (a transposed reduction: 2P stores and 32
+        // loads per lane instead of an xor butterfly of 5 x 2P shuffles)
+        wave_lds_sync();  // the previous cell's rows have been read
 #pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-#pragma unroll
-            for (int l = 1; l <= P; ++l) {
-                B[l].x += __shfl_xor(B[l].x, o, WAVE);
-                B[l].y += __shfl_xor(B[l].y, o, WAVE);
-            }
+        for (int l = 1; l <= P; ++l) {
+            rows[lane * ROW + 2 * (l - 1)] = B[l].x;
+            rows[lane * ROW + 2 * (l - 1) + 1] = B[l].y;
         }
+        wave_lds_sync();
         if (live) {
-            float2 *Lc = Lp + (int64_t)c * (P + 1);
-#pragma unroll
-            for (int l = 0; l <= P; ++l)
-                if (j == l) Lc[l] = B[l];
+            float *Lc = reinterpret_cast<float *>(Lp + (int64_t)c * (P + 1));
+            if (j < 2 * P) {
+                const float *col = rows + half * 32 * ROW + j;
+                float acc = 0.f;
+#pragma unroll 8
+                for (int r = 0; r < 32; ++r) acc += col[r * ROW];
+                Lc[2 + j] = acc;
+            }
+            if (j == 0) {
+                Lc[0] = 0.f;  // B_0 is never accumulated (the potential's constant)
+                Lc[1] = 0.f;
+            }
         }
     }
 }

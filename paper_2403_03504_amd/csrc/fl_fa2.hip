@@ -23,6 +23,10 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int HEAVY = 32;
+// the per-node passes (combine, update) take a quarter tile per block: more
+// blocks in flight for what is a chain of independent loads per node (an
+// eighth was no better); the combine's FP64 partials are per quarter tile
+constexpr int TILE_SUB = 4;
 
 struct StepConsts {
     double ka, kg, tau, ks, ksmax, max_rise;
@@ -187,11 +191,12 @@ __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restri
                                                 const double2 *__restrict__ csum, const double2 *__restrict__ asum)
 {
     __shared__ double lds[NT / WAVE];
-    const int2 tl = sg.tiles[blockIdx.x];
+    const int2 tl = sg.tiles[blockIdx.x / TILE_SUB];
     const int comp = tl.x;
-    const int b1 = min(tl.y + SEG_TILE, sg.coff[comp + 1]);
+    const int b0 = tl.y + (int)(blockIdx.x % TILE_SUB) * (SEG_TILE / TILE_SUB);
+    const int b1 = min(b0 + SEG_TILE / TILE_SUB, sg.coff[comp + 1]);
     double wswg = 0.0, wtra = 0.0;
-    for (int i = tl.y + threadIdx.x; i < b1; i += NT) {
+    for (int i = b0 + threadIdx.x; i < b1; i += NT) {
         double ax = 0.0, ay = 0.0;
         const float2 pi = xy[i];
         const double xi = pi.x, yi = pi.y;
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(NT) void k_speed(Segs sg, const double2 *__restrict
 {
     __shared__ double lds[NT / WAVE];
     for (int comp = blockIdx.x; comp < sg.K; comp += gridDim.x) {
-        const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
+        const int t0 = TILE_SUB * sg.tile_off[comp], nt = TILE_SUB * sg.tile_off[comp + 1] - t0;
         double s0 = 0.0, s1 = 0.0;
         for (int b = threadIdx.x; b < nt; b += NT) {
             const double2 v = part[t0 + b];
@@ -319,11 +324,12 @@ __global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, f
                                                int32_t *__restrict__ flags)
 {
     if (*flags & 1) return;  // non-finite forces: leave the layout as it was
-    const int2 tl = sg.tiles[blockIdx.x];
+    const int2 tl = sg.tiles[blockIdx.x / TILE_SUB];
     const int comp = tl.x;
-    const int b1 = min(tl.y + SEG_TILE, sg.coff[comp + 1]);
+    const int b0 = tl.y + (int)(blockIdx.x % TILE_SUB) * (SEG_TILE / TILE_SUB);
+    const int b1 = min(b0 + SEG_TILE / TILE_SUB, sg.coff[comp + 1]);
     const double sG = scalars[4 * (int64_t)comp];
-    for (int i = tl.y + threadIdx.x; i < b1; i += NT) {
+    for (int i = b0 + threadIdx.x; i < b1; i += NT) {
         const float Fx = fx[i], Fy = fy[i];
         const double px = first ? 0.0 : (double)fpx[i], py = first ? 0.0 : (double)fpy[i];
         const double dx = (double)Fx - px, dy = (double)Fy - py;
@@ -521,7 +527,7 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
     float2 *fr = ws<float2>(c, "fa2_fr", n);
     float *fcx = ws<float>(c, "fa2_fcx", n);
     float *fcy = ws<float>(c, "fa2_fcy", n);
-    double2 *part = ws<double2>(c, "fa2_part", (size_t)b.sg.ntiles);
+    double2 *part = ws<double2>(c, "fa2_part", (size_t)b.sg.ntiles * TILE_SUB);
     double2 *csum = ws<double2>(c, "at_csum", b.ap.cap);
     const int first = b.st.iter == 0 ? 1 : 0;
     const float2 *xy = nullptr;
@@ -554,7 +560,8 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
     {
         PhaseTimer pt(c, FL_PH_ATTRACT);
         if (!xy) xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum);
-        hipLaunchKernelGGL(k_combine, dim3(b.sg.ntiles), dim3(NT), 0, c->stream, b.sg, b.g.row_ptr, b.g.col,
+        hipLaunchKernelGGL(k_combine, dim3(b.sg.ntiles * TILE_SUB), dim3(NT), 0, c->stream, b.sg, b.g.row_ptr,
+                           b.g.col,
                            b.g.deg, xy, (const float2 *)fr, consts(&b.prm),
                            (const float *)b.st.fx_prev, (const float *)b.st.fy_prev, first, fcx, fcy,
                            (float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, part, flags,
@@ -565,7 +572,7 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
     }
     {
         PhaseTimer pt(c, FL_PH_UPDATE);
-        hipLaunchKernelGGL(k_update, dim3(b.sg.ntiles), dim3(NT), 0, c->stream, b.sg, b.x, b.y,
+        hipLaunchKernelGGL(k_update, dim3(b.sg.ntiles * TILE_SUB), dim3(NT), 0, c->stream, b.sg, b.x, b.y,
                            (const float *)fcx, (const float *)fcy, b.st.fx_prev, b.st.fy_prev, first,
                            (const double *)b.st.scalars, b.prm.ks, b.prm.ksmax, flags);
         FL_LAUNCH_CHECK();
@@ -767,7 +774,7 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
         AttractPlan ap = attract_plan(c, g);
         double2 *csum = ws<double2>(c, "at_csum", ap.cap);
         const float2 *xy = attract_chunks(c, g, ap, x, y, csum);
-        hipLaunchKernelGGL(k_combine, dim3(sg.ntiles), dim3(NT), 0, c->stream, sg, row_ptr, col_idx, deg, xy,
+        hipLaunchKernelGGL(k_combine, dim3(sg.ntiles * TILE_SUB), dim3(NT), 0, c->stream, sg, row_ptr, col_idx, deg, xy,
                            (const float2 *)nullptr, consts(prm), (const float *)nullptr,
                            (const float *)nullptr, 1, (float *)nullptr, (float *)nullptr, fax, fay, fgx, fgy,
                            (double2 *)nullptr, flags, (const int32_t *)ap.choff, (const double2 *)csum,

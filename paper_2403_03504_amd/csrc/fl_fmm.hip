@@ -455,6 +455,23 @@ __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restric
         fy = fmaf(sm, dy, fy);                                                                                      \
     }
 
+// the same pair for two targets held by one lane: me (fx, fy) and mb (gx, gy)
+#define FL_P2P_PAIR2(SX, SY, SM)                                                                                    \
+    {                                                                                                               \
+        const float dx = me.x - (SX), dy = me.y - (SY);                                                             \
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));                                                        \
+        const float sm = (SM) * __builtin_amdgcn_rcpf(r2);                                                          \
+        fx = fmaf(sm, dx, fx);                                                                                      \
+        fy = fmaf(sm, dy, fy);                                                                                      \
+        const float ex = mb.x - (SX), ey = mb.y - (SY);                                                             \
+        const float q2 = fmaf(ex, ex, fmaf(ey, ey, 1e-30f));                                                        \
+        const float sq = (SM) * __builtin_amdgcn_rcpf(q2);                                                          \
+        gx = fmaf(sq, ex, gx);                                                                                      \
+        gy = fmaf(sq, ey, gy);                                                                                      \
+    }
+
+constexpr int P2P_TRI = 21;  // lanes per group of the three-group near-field path
+
 // k_p2p: the near field of every particle over its leaf's U list (sorted
 // particle order, one float2 per particle).  It needs only the lists, so it
 // runs beside the upward pass and M2L.
@@ -465,10 +482,12 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
                                              float2 *__restrict__ near, int32_t *__restrict__ pleaf)
 {
     __shared__ float4 stage[4][WAVE + 4];  // per wave: sources of the small-leaf path, zero-mass padded
+    __shared__ float4 red3[4][WAVE];        // per wave: the three-group path's partial sums
     const int nleaves = t.counts[1];
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
     float4 *sw = stage[threadIdx.x / WAVE];
+    float4 *rw = red3[threadIdx.x / WAVE];
     const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
     for (int li = first; li < nleaves; li += gridDim.x * wpb) {
         const int c = leaf_cell[li];
@@ -477,6 +496,47 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
         const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = u0 + nU[li];
         for (int t0 = b; t0 < e; t0 += WAVE) {
             const int ntc = min(WAVE, e - t0);
+            if (ntc > WAVE / 2 && ntc <= 2 * P2P_TRI) {
+                // 33..42 targets: three groups of 21 lanes on sources k = g
+                // mod 3, two targets per lane (r and r + 21): 63 busy lanes
+                // instead of ntc (one wave per leaf would leave a third idle)
+                const int grp = lane / P2P_TRI, r = lane - grp * P2P_TRI;  // lane 63: grp 3, adds nothing used
+                const float4 me = part[t0 + r];
+                const float4 mb = part[t0 + min(r + P2P_TRI, ntc - 1)];
+                float fx = 0.f, fy = 0.f, gx = 0.f, gy = 0.f;
+                for (int ue = u0; ue < u1; ++ue) {
+                    const int2 rg = U[ue];
+                    for (int j0 = rg.x; j0 < rg.y; j0 += WAVE) {
+                        const int ns = min(WAVE, rg.y - j0);
+                        const bool in = lane < ns;
+                        const float4 v = part[j0 + (in ? lane : 0)];
+                        const float4 sv = make_float4(v.x, v.y, in ? v.z : 0.f, in ? v.w : 0.f);
+                        wave_lds_sync();  // the previous chunk has been read
+                        sw[lane] = sv;
+                        if (lane < 4) sw[WAVE + lane] = make_float4(v.x, v.y, 0.f, 0.f);
+                        wave_lds_sync();
+                        // k + grp <= ns - 1 + 3 < WAVE + 4: past ns the stage holds mass 0
+                        for (int k = 0; k < ns; k += 3) {
+                            const float4 s0 = sw[k + grp];
+                            FL_P2P_PAIR2(s0.x, s0.y, s0.z)
+                        }
+                    }
+                }
+                // the three groups' sums of each target, added in group order
+                wave_lds_sync();
+                rw[lane] = make_float4(fx, fy, gx, gy);
+                wave_lds_sync();
+                if (grp == 0) {
+                    const float4 a0 = rw[r], a1 = rw[r + P2P_TRI], a2 = rw[r + 2 * P2P_TRI];
+                    near[t0 + r] = make_float2(a0.x + a1.x + a2.x, a0.y + a1.y + a2.y);
+                    pleaf[t0 + r] = li;
+                    if (r + P2P_TRI < ntc) {
+                        near[t0 + r + P2P_TRI] = make_float2(a0.z + a1.z + a2.z, a0.w + a1.w + a2.w);
+                        pleaf[t0 + r + P2P_TRI] = li;
+                    }
+                }
+                continue;
+            }
             // small leaves: G lane groups take interleaved sources
             const int lg = ntc <= WAVE / 4 ? 2 : ntc <= WAVE / 2 ? 1 : 0;
             const int ti = lane & ((WAVE >> lg) - 1);
@@ -603,6 +663,7 @@ __global__ __launch_bounds__(256) void k_far(TreeView t, int n, const float4 *__
     }
 }
 #undef FL_P2P_PAIR
+#undef FL_P2P_PAIR2
 
 template <int P>
 struct FmmBufs {

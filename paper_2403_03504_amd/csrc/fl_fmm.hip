@@ -455,22 +455,101 @@ __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restric
         fy = fmaf(sm, dy, fy);                                                                                      \
     }
 
-// the same pair for two targets held by one lane: me (fx, fy) and mb (gx, gy)
-#define FL_P2P_PAIR2(SX, SY, SM)                                                                                    \
-    {                                                                                                               \
-        const float dx = me.x - (SX), dy = me.y - (SY);                                                             \
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));                                                        \
-        const float sm = (SM) * __builtin_amdgcn_rcpf(r2);                                                          \
-        fx = fmaf(sm, dx, fx);                                                                                      \
-        fy = fmaf(sm, dy, fy);                                                                                      \
-        const float ex = mb.x - (SX), ey = mb.y - (SY);                                                             \
-        const float q2 = fmaf(ex, ex, fmaf(ey, ey, 1e-30f));                                                        \
-        const float sq = (SM) * __builtin_amdgcn_rcpf(q2);                                                          \
-        gx = fmaf(sq, ex, gx);                                                                                      \
-        gy = fmaf(sq, ey, gy);                                                                                      \
-    }
+constexpr int P2P_GMAX = 16;            // lane groups at most
+constexpr int P2P_STAGE = WAVE + P2P_GMAX;  // staged sources plus zero-mass padding
 
-constexpr int P2P_TRI = 21;  // lanes per group of the three-group near-field path
+// Lane-group shape of the near field for a leaf chunk of n targets: T
+// targets per lane, groups of L = ceil(n / T) lanes, G = 64 / L groups on
+// sources interleaved mod G.  A round of G sources costs 64 T lane slots and
+// does G n pairs; the shape with the most pairs per slot wins (the smaller
+// T on a tie).  G = 1 is the plain one-target-per-lane wave.
+__device__ __forceinline__ void p2p_shape(int n, int &T, int &L, int &G)
+{
+    T = 1;
+    L = n;
+    G = min(P2P_GMAX, WAVE / n);
+    int best = G * n * 12;  // pairs per round x 12 / T (12: a common multiple of 1..4)
+    for (int t = 2; t <= 4; ++t) {
+        const int l = (n + t - 1) / t, g = min(P2P_GMAX, WAVE / l);
+        const int v = g * n * 12 / t;
+        if (v > best) {
+            best = v;
+            T = t;
+            L = l;
+            G = g;
+        }
+    }
+}
+
+// One chunk of a leaf's targets (t0 .. t0 + n) in lane groups: lane (g, r)
+// holds targets r, r + L, ..., takes sources k = g mod G from a 64-source LDS
+// stage, and the groups' sums are added in group order through LDS.  Lanes
+// past G L compute on group 0's sources and their sums are never read.
+template <int T>
+__device__ __forceinline__ void p2p_groups(const float4 *__restrict__ part, const int2 *__restrict__ U, int u0,
+                                           int u1, int t0, int n, int L, int G, float4 *sw, float2 *rw,
+                                           float2 *__restrict__ near, int32_t *__restrict__ pleaf, int li)
+{
+    const int lane = lane_id();
+    const int grp = lane / L, r = lane - grp * L;
+    const int gr = grp < G ? grp : 0;
+    float4 me[T];
+    float fx[T], fy[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        me[u] = part[t0 + min(r + u * L, n - 1)];
+        fx[u] = 0.f;
+        fy[u] = 0.f;
+    }
+    for (int ue = u0; ue < u1; ++ue) {
+        const int2 rg = U[ue];
+        for (int j0 = rg.x; j0 < rg.y; j0 += WAVE) {
+            const int ns = min(WAVE, rg.y - j0);
+            const bool in = lane < ns;
+            const float4 v = part[j0 + (in ? lane : 0)];
+            // lanes past the chunk hold a source of mass 0 (adds 0); the
+            // select is per component (a whole-float4 select went through
+            // scratch memory)
+            const float4 sv = make_float4(v.x, v.y, in ? v.z : 0.f, in ? v.w : 0.f);
+            wave_lds_sync();  // the previous chunk has been read
+            sw[lane] = sv;
+            if (lane < P2P_GMAX) sw[WAVE + lane] = make_float4(v.x, v.y, 0.f, 0.f);
+            wave_lds_sync();
+            // k + gr <= ns - 1 + G - 1 < P2P_STAGE; past ns the stage holds mass 0
+            for (int k = 0; k < ns; k += G) {
+                const float4 s0 = sw[k + gr];
+#pragma unroll
+                for (int u = 0; u < T; ++u) {
+                    const float dx = me[u].x - s0.x, dy = me[u].y - s0.y;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+                    const float sm = s0.z * __builtin_amdgcn_rcpf(r2);
+                    fx[u] = fmaf(sm, dx, fx[u]);
+                    fy[u] = fmaf(sm, dy, fy[u]);
+                }
+            }
+        }
+    }
+    wave_lds_sync();  // the previous chunk's sums have been read
+#pragma unroll
+    for (int u = 0; u < T; ++u) rw[lane * T + u] = make_float2(fx[u], fy[u]);
+    wave_lds_sync();
+    if (grp == 0) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const int tk = r + u * L;
+            if (tk < n) {
+                float2 a = rw[r * T + u];
+                for (int g = 1; g < G; ++g) {
+                    const float2 q = rw[(g * L + r) * T + u];
+                    a.x += q.x;
+                    a.y += q.y;
+                }
+                near[t0 + tk] = a;
+                pleaf[t0 + tk] = li;
+            }
+        }
+    }
+}
 
 // k_p2p: the near field of every particle over its leaf's U list (sorted
 // particle order, one float2 per particle).  It needs only the lists, so it
@@ -481,13 +560,13 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
                                              const int32_t *__restrict__ cend, const int32_t *__restrict__ leaf_cell,
                                              float2 *__restrict__ near, int32_t *__restrict__ pleaf)
 {
-    __shared__ float4 stage[4][WAVE + 4];  // per wave: sources of the small-leaf path, zero-mass padded
-    __shared__ float4 red3[4][WAVE];        // per wave: the three-group path's partial sums
+    __shared__ float4 stage[4][P2P_STAGE];  // per wave: sources of the lane-group path, zero-mass padded
+    __shared__ float2 sums[4][WAVE * 4];     // per wave: the lane groups' partial sums
     const int nleaves = t.counts[1];
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
     float4 *sw = stage[threadIdx.x / WAVE];
-    float4 *rw = red3[threadIdx.x / WAVE];
+    float2 *rw = sums[threadIdx.x / WAVE];
     const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
     for (int li = first; li < nleaves; li += gridDim.x * wpb) {
         const int c = leaf_cell[li];
@@ -496,114 +575,41 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
         const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = u0 + nU[li];
         for (int t0 = b; t0 < e; t0 += WAVE) {
             const int ntc = min(WAVE, e - t0);
-            if (ntc > WAVE / 2 && ntc <= 2 * P2P_TRI) {
-                // 33..42 targets: three groups of 21 lanes on sources k = g
-                // mod 3, two targets per lane (r and r + 21): 63 busy lanes
-                // instead of ntc (one wave per leaf would leave a third idle)
-                const int grp = lane / P2P_TRI, r = lane - grp * P2P_TRI;  // lane 63: grp 3, adds nothing used
-                const float4 me = part[t0 + r];
-                const float4 mb = part[t0 + min(r + P2P_TRI, ntc - 1)];
-                float fx = 0.f, fy = 0.f, gx = 0.f, gy = 0.f;
-                for (int ue = u0; ue < u1; ++ue) {
-                    const int2 rg = U[ue];
-                    for (int j0 = rg.x; j0 < rg.y; j0 += WAVE) {
-                        const int ns = min(WAVE, rg.y - j0);
-                        const bool in = lane < ns;
-                        const float4 v = part[j0 + (in ? lane : 0)];
-                        const float4 sv = make_float4(v.x, v.y, in ? v.z : 0.f, in ? v.w : 0.f);
-                        wave_lds_sync();  // the previous chunk has been read
-                        sw[lane] = sv;
-                        if (lane < 4) sw[WAVE + lane] = make_float4(v.x, v.y, 0.f, 0.f);
-                        wave_lds_sync();
-                        // k + grp <= ns - 1 + 3 < WAVE + 4: past ns the stage holds mass 0
-                        for (int k = 0; k < ns; k += 3) {
-                            const float4 s0 = sw[k + grp];
-                            FL_P2P_PAIR2(s0.x, s0.y, s0.z)
-                        }
-                    }
-                }
-                // the three groups' sums of each target, added in group order
-                wave_lds_sync();
-                rw[lane] = make_float4(fx, fy, gx, gy);
-                wave_lds_sync();
-                if (grp == 0) {
-                    const float4 a0 = rw[r], a1 = rw[r + P2P_TRI], a2 = rw[r + 2 * P2P_TRI];
-                    near[t0 + r] = make_float2(a0.x + a1.x + a2.x, a0.y + a1.y + a2.y);
-                    pleaf[t0 + r] = li;
-                    if (r + P2P_TRI < ntc) {
-                        near[t0 + r + P2P_TRI] = make_float2(a0.z + a1.z + a2.z, a0.w + a1.w + a2.w);
-                        pleaf[t0 + r + P2P_TRI] = li;
-                    }
+            int T, L, G;
+            p2p_shape(ntc, T, L, G);
+            if (G > 1) {
+                switch (T) {
+                case 1: p2p_groups<1>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 2: p2p_groups<2>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 3: p2p_groups<3>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                default: p2p_groups<4>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
                 }
                 continue;
             }
-            // small leaves: G lane groups take interleaved sources
-            const int lg = ntc <= WAVE / 4 ? 2 : ntc <= WAVE / 2 ? 1 : 0;
-            const int ti = lane & ((WAVE >> lg) - 1);
-            const int grp = lane >> (6 - lg);
-            const bool valid = ti < ntc;
-            const float4 me = part[t0 + (valid ? ti : 0)];
+            // one target per lane, the whole wave on each source: sources at
+            // wave-uniform addresses (scalar loads, SGPR operands)
+            const bool valid = lane < ntc;
+            const float4 me = part[t0 + (valid ? lane : 0)];
             float fx = 0.f, fy = 0.f;
             for (int ue = u0; ue < u1; ++ue) {
                 const int2 rg = U[ue];
                 const int sb = rg.x, se = rg.y;
-                if (lg == 0) {
-                    int j = sb;
-                    for (; j + 4 <= se; j += 4) {
-                        const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
-                        FL_P2P_PAIR(s0.x, s0.y, s0.z)
-                        FL_P2P_PAIR(s1.x, s1.y, s1.z)
-                        FL_P2P_PAIR(s2.x, s2.y, s2.z)
-                        FL_P2P_PAIR(s3.x, s3.y, s3.z)
-                    }
-                    for (; j < se; ++j) {
-                        const float4 s0 = part[j];
-                        FL_P2P_PAIR(s0.x, s0.y, s0.z)
-                    }
-                } else {
-                    // 2 or 4 lane groups on interleaved sources: the wave stages
-                    // up to 64 sources in LDS with one coalesced load, and each
-                    // group reads its own source (an LDS broadcast, no selects)
-                    const int G = 1 << lg;
-                    for (int j0 = sb; j0 < se; j0 += WAVE) {
-                        const int ns = min(WAVE, se - j0);
-                        const bool in = lane < ns;
-                        const float4 v = part[j0 + (in ? lane : 0)];
-                        // lanes past the chunk hold a source of mass 0 (adds 0);
-                        // the select is per component: a select of the whole
-                        // float4 went through scratch memory
-                        const float4 sv = make_float4(v.x, v.y, in ? v.z : 0.f, in ? v.w : 0.f);
-                        wave_lds_sync();  // the previous chunk has been read
-                        sw[lane] = sv;
-                        if (lane < 4) sw[WAVE + lane] = make_float4(v.x, v.y, 0.f, 0.f);
-                        wave_lds_sync();
-                        int k = 0;
-                        for (; k + 3 * G < ns; k += 4 * G) {  // four LDS reads in flight
-                            const float4 s0 = sw[k + grp], s1 = sw[k + G + grp], s2 = sw[k + 2 * G + grp],
-                                         s3 = sw[k + 3 * G + grp];
-                            FL_P2P_PAIR(s0.x, s0.y, s0.z)
-                            FL_P2P_PAIR(s1.x, s1.y, s1.z)
-                            FL_P2P_PAIR(s2.x, s2.y, s2.z)
-                            FL_P2P_PAIR(s3.x, s3.y, s3.z)
-                        }
-                        for (; k < ns; k += G) {  // k + grp < ns + G - 1 <= WAVE + 3
-                            const float4 s0 = sw[k + grp];
-                            FL_P2P_PAIR(s0.x, s0.y, s0.z)
-                        }
-                    }
+                int j = sb;
+                for (; j + 4 <= se; j += 4) {
+                    const float4 s0 = part[j], s1 = part[j + 1], s2 = part[j + 2], s3 = part[j + 3];
+                    FL_P2P_PAIR(s0.x, s0.y, s0.z)
+                    FL_P2P_PAIR(s1.x, s1.y, s1.z)
+                    FL_P2P_PAIR(s2.x, s2.y, s2.z)
+                    FL_P2P_PAIR(s3.x, s3.y, s3.z)
+                }
+                for (; j < se; ++j) {
+                    const float4 s0 = part[j];
+                    FL_P2P_PAIR(s0.x, s0.y, s0.z)
                 }
             }
-            if (lg >= 2) {
-                fx += __shfl_xor(fx, WAVE / 4, WAVE);
-                fy += __shfl_xor(fy, WAVE / 4, WAVE);
-            }
-            if (lg >= 1) {
-                fx += __shfl_xor(fx, WAVE / 2, WAVE);
-                fy += __shfl_xor(fy, WAVE / 2, WAVE);
-            }
-            if (grp == 0 && valid) {
-                near[t0 + ti] = make_float2(fx, fy);
-                pleaf[t0 + ti] = li;
+            if (valid) {
+                near[t0 + lane] = make_float2(fx, fy);
+                pleaf[t0 + lane] = li;
             }
         }
     }
@@ -663,7 +669,6 @@ __global__ __launch_bounds__(256) void k_far(TreeView t, int n, const float4 *__
     }
 }
 #undef FL_P2P_PAIR
-#undef FL_P2P_PAIR2
 
 template <int P>
 struct FmmBufs {

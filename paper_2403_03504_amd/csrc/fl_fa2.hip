@@ -468,12 +468,14 @@ static AttractPlan attract_plan(fl_ctx *c, const GraphArgs &g, int32_t *choff = 
 }
 
 // positions interleaved (x, y) so each neighbour is one 8-byte gather
+// packed: the (x, y) pairs are already in the "at_xy" buffer (written by the
+// tree build)
 static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const AttractPlan &a, const float *x,
-                                    const float *y, double2 *csum, hipStream_t s = nullptr)
+                                    const float *y, double2 *csum, hipStream_t s = nullptr, bool packed = false)
 {
     if (!s) s = c->stream;
     float2 *xy = ws<float2>(c, "at_xy", g.n);
-    hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, s, x, y, g.n, xy);
+    if (!packed) hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, s, x, y, g.n, xy);
     hipLaunchKernelGGL(k_attract_chunks, dim3(1024), dim3(NT), 0, s, g.row_ptr, g.col, (const float2 *)xy,
                        a.chunks, a.choff + g.n, csum);
     FL_LAUNCH_CHECK();
@@ -481,7 +483,8 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
 }
 
 static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float *x, const float *y,
-                      const fl_fa2_params *p, float2 *fr, const std::function<void(hipEvent_t)> *on_lists = nullptr)
+                      const fl_fa2_params *p, float2 *fr, const std::function<void(hipEvent_t)> *on_lists = nullptr,
+                      float2 *xy_out = nullptr)
 {
     if (p->repulsion == FL_REP_EXACT) {
         PhaseTimer pt(c, FL_PH_EXACT);
@@ -490,7 +493,8 @@ static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float
         FL_LAUNCH_CHECK();
     } else {
         const int lanes = p->list_lanes ? p->list_lanes : default_list_lanes(sg.n);
-        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, fr, on_lists);
+        fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, fr, on_lists,
+                      xy_out);
     }
 }
 
@@ -537,20 +541,21 @@ static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
         hipStream_t as = aux_stream(c, 2);
         if (!c->ev_fork) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         if (!c->ev_join) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        const bool fmm = b.prm.repulsion != FL_REP_EXACT;  // the tree build then packs (x, y)
         const std::function<void(hipEvent_t)> side = [&](hipEvent_t after) {
             FL_CHECK_HIP(hipStreamWaitEvent(as, after, 0));
-            xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as);
+            xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as, fmm);
             hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, NT)), dim3(NT), 0, as, n, b.g.row_ptr, b.g.col, xy,
                                (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
             FL_LAUNCH_CHECK();
             FL_CHECK_HIP(hipEventRecord(c->ev_join, as));
         };
-        if (b.prm.repulsion == FL_REP_EXACT) {
+        if (!fmm) {
             FL_CHECK_HIP(hipEventRecord(c->ev_fork, c->stream));
             side(c->ev_fork);
             repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
         } else {
-            repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, &side);
+            repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, &side, ws<float2>(c, "at_xy", n));
         }
         if (!xy) throw Error(FL_EHIP, "iteration: the attraction branch was not forked");
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));

@@ -16,9 +16,10 @@ bool fmm_order_supported(int p);
 // `on_lists` is given it is called once the list build has been enqueued,
 // with an event recorded on the context stream just after it: work that
 // should overlap the near field (and not the latency-bound tree build) is
-// forked from there.
+// forked from there.  xy_out (optional, n float2) receives the (x, y) pairs
+// from the tree build.
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
                    int bits, int lanes, float kr, float2 *fr,
-                   const std::function<void(hipEvent_t)> *on_lists = nullptr);
+                   const std::function<void(hipEvent_t)> *on_lists = nullptr, float2 *xy_out = nullptr);
 
 }  // namespace fl

@@ -759,6 +759,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         {
             PhaseTimer pt(c, FL_PH_LISTS);
             build_lists(c, t, L, lanes);
+            lists_stats(c, t, L);
         }
         if (on_lists) {
             if (!c->ev_lists) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_lists, hipEventDisableTiming));
@@ -791,6 +792,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         m2l_p<P>(c, us, t, L, b);
         FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
         near_p(c, t, L, near, pleaf);
+        lists_stats(c, t, L);
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
     }
     PhaseTimer pt(c, FL_PH_FAR);
@@ -802,12 +804,13 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
 bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16; }
 
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, int lanes, float kr, float2 *fr, const std::function<void(hipEvent_t)> *on_lists)
+                   int bits, int lanes, float kr, float2 *fr, const std::function<void(hipEvent_t)> *on_lists,
+                   float2 *xy_out)
 {
     TreeBufs t;
     {
         PhaseTimer pt(c, FL_PH_TREE);
-        build_tree(c, t, s, x, y, deg, bits, leaf);
+        build_tree(c, t, s, x, y, deg, bits, leaf, xy_out);
     }
     switch (p) {
     case 4: fmm_passes<4>(c, t, lanes, kr, fr, on_lists); break;

@@ -85,6 +85,8 @@ struct ListBufs {
     int32_t *V = nullptr, *X = nullptr, *W = nullptr;
     int2 *U = nullptr;         // near-field particle ranges [begin, end), sorted and merged
     int32_t *nU = nullptr;     // [leaves_cap] merged range count of each leaf
+    unsigned long long *block_pairs = nullptr;  // near-field pair counts per fill block
+    int fill_blocks = 0;
 };
 
 // Device view used by the kernels.
@@ -120,10 +122,15 @@ int64_t cells_capacity(int64_t n, int leaf, int bits, int K = 1);
 // Per system: bbox -> Morton keys; then one stable sort by (system, key) ->
 // sorted particles -> forest.  deg may be null (unit masses).  All on the
 // context stream, no host synchronisation.
+// xy_out (optional, n float2): the (x, y) pairs as well, for the attraction.
 void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
-                int leaf);
+                int leaf, float2 *xy_out = nullptr);
 // lanes: lanes per cell of the list kernels, 1 or 8 (the same lists either way)
 void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes);
+// The lists' statistics (counts, near pairs) into the context's counters;
+// nothing of the passes reads them, so the caller launches this off the
+// critical path (after the near field).
+void lists_stats(fl_ctx *c, const TreeBufs &t, const ListBufs &L);
 // lanes per cell when the caller leaves the choice open (0)
 int default_list_lanes(int64_t n);
 // Deepest level of the last tree into the statistics block.

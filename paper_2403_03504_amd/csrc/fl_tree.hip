@@ -171,14 +171,16 @@ __global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restr
 // Morton key of every node relative to its system's root square; with more
 // than one system also the sort key (system << 32 | key); with `xym` also
 // the node's (x, y, mass, index) record, so that moving a node to its sorted
-// place is a single 16-byte access.  When the hash epoch has
+// place is a single 16-byte access; with `xy` the (x, y) pairs the
+// attraction gathers read.  When the hash epoch has
 // just wrapped to 1 the table is cleared here (before any insert of this
 // build).
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, int n,
                          const int32_t *__restrict__ ncomp, const double *__restrict__ root, int bits,
                          uint32_t *__restrict__ key, uint64_t *__restrict__ key64, int32_t *__restrict__ idx,
                          const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hkey, int64_t hcap,
-                         const int32_t *__restrict__ deg, float4 *__restrict__ xym, int32_t *__restrict__ counts)
+                         const int32_t *__restrict__ deg, float4 *__restrict__ xym, int32_t *__restrict__ counts,
+                         float2 *__restrict__ xy)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (counts && i < 3) counts[i] = 0;  // the tree's cell, leaf and level counts ([3], the error bits, is sticky)
@@ -195,6 +197,7 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
     if (key64) key64[i] = ((uint64_t)(uint32_t)comp << 32) | k;
     if (idx) idx[i] = i;
     if (xym) xym[i] = make_float4(xi, yi, deg ? (float)(deg[i] + 1) : 1.0f, __int_as_float(i));
+    if (xy) xy[i] = make_float2(xi, yi);
 }
 
 // sorted particles; with more than one system also the sorted Morton keys
@@ -966,7 +969,7 @@ Segs make_segs(fl_ctx *c, const std::vector<int32_t> &coff, const char *tag) { r
 namespace {
 
 void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg,
-                     int bits, int leaf)
+                     int bits, int leaf, float2 *xy_out)
 {
     const int n = s.n;
     t.n = n;
@@ -1025,7 +1028,7 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     float4 *xym = ws<float4>(c, "t_xym", n);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
                        (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
-                       t.hkey, t.hash_cap, deg, xym, t.counts);
+                       t.hkey, t.hash_cap, deg, xym, t.counts, xy_out);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
     if (s.K > 1) {
@@ -1055,9 +1058,9 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
 }  // namespace
 
 void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
-                int leaf)
+                int leaf, float2 *xy_out)
 {
-    build_tree_impl(c, t, s, x, y, deg, bits, leaf);
+    build_tree_impl(c, t, s, x, y, deg, bits, leaf, xy_out);
 }
 
 // eight lanes measured faster at every size tried (15k-node components up to
@@ -1096,12 +1099,19 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     FL_LAUNCH_CHECK();
     scan_excl_i64_pair(c, cntVX, L.offVX, cap, t.counts, cntUW, L.offUW, lcap, t.counts + 1);
     auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
-    unsigned long long *block_pairs = ws<unsigned long long>(c, "l_block_pairs", (size_t)lg);
+    L.block_pairs = ws<unsigned long long>(c, "l_block_pairs", (size_t)lg);
+    L.fill_blocks = (int)lg;
     hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
-                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, block_pairs, cap, lcap, L.v_cap, L.x_cap,
-                       L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt, (const int4 *)slots);
+                       (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, L.block_pairs, cap, lcap, L.v_cap,
+                       L.x_cap, L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt, (const int4 *)slots);
+    FL_LAUNCH_CHECK();
+}
+
+void lists_stats(fl_ctx *c, const TreeBufs &t, const ListBufs &L)
+{
     hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(256), 0, c->stream, t.counts, (const int64_t *)L.offVX,
-                       (const int64_t *)L.offUW, (const unsigned long long *)block_pairs, (int)lg, c->d_stats, t.n);
+                       (const int64_t *)L.offUW, (const unsigned long long *)L.block_pairs, L.fill_blocks,
+                       c->d_stats, t.n);
     FL_LAUNCH_CHECK();
 }
 
@@ -1148,7 +1158,7 @@ void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits,
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, (const int32_t *)nullptr,
                        (const double *)root, bits, key, (uint64_t *)nullptr, (int32_t *)nullptr,
                        (const uint32_t *)nullptr, (uint64_t *)nullptr, (int64_t)0, (const int32_t *)nullptr,
-                       (float4 *)nullptr, (int32_t *)nullptr);
+                       (float4 *)nullptr, (int32_t *)nullptr, (float2 *)nullptr);
     FL_LAUNCH_CHECK();
 }
 

@@ -202,11 +202,15 @@ def test_attraction_gravity_parity(ctx, fl, orc, mode):
 
 @pytest.mark.parametrize("kind,n,leaf,p", [("uniform", 20_000, 64, 8), ("clustered", 30_000, 16, 8),
                                            ("clustered", 30_000, 64, 4), ("uniform", 8_000, 32, 12),
-                                           ("duplicates", 6_000, 8, 8), ("clustered", 10_000, 64, 16)])
+                                           ("duplicates", 6_000, 8, 8), ("clustered", 10_000, 64, 16),
+                                           ("clustered", 12_000, 1, 8), ("uniform", 15_000, 150, 8),
+                                           ("clustered", 20_000, 300, 6)])
 def test_fmm_repulsion_parity(ctx, fl, orc, kind, n, leaf, p):
     # Same tree, lists and operators as the FP64 oracle FMM, so the difference
     # is FP32 rounding (tolerance 2e-5); against the exact sum the FMM's own
-    # truncation error must stay within 1e-3 at p >= 8.
+    # truncation error must stay within 1e-3 at p >= 8.  The leaf sizes give
+    # the near field every lane-group shape (one target per leaf up to
+    # leaves cut into several 64-target chunks).
     _note("fmm", kind, n, leaf, p)
     x, y = _positions(kind, n, 17)
     rng = np.random.default_rng(4)

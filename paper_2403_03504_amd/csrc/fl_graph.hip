@@ -178,7 +178,8 @@ int64_t build_csr(fl_ctx *c, int32_t n, int64_t m, const int32_t *src, const int
         if (read_i32(c, bad)) throw Error(FL_EINVAL, "fl_build_csr: edge endpoint outside [0, n)");
         const uint64_t sent = (uint64_t)n * (uint64_t)n;
         int nbits = 64 - __builtin_clzll(sent | 1ull);
-        bool alt = radix_sort_u64(c, keys, tmp, len, nbits);
+        int32_t *serr = ws_zeroed<int32_t>(c, "csr_sort_err", 1);
+        bool alt = radix_sort_u64(c, keys, tmp, len, nbits, serr);
         uint64_t *sk = alt ? tmp : keys;
         int32_t *flag = ws<int32_t>(c, "csr_flag", (size_t)len);
         int32_t *pos = ws<int32_t>(c, "csr_pos", (size_t)len + 1);
@@ -194,7 +195,15 @@ int64_t build_csr(fl_ctx *c, int32_t n, int64_t m, const int32_t *src, const int
     hipLaunchKernelGGL(k_csr_rows, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, c->stream, ukeys, nnz_p,
                        (int64_t)n, row_ptr, deg);
     FL_LAUNCH_CHECK();
-    return (int64_t)read_i32(c, row_ptr + n);
+    const int64_t nnz = (int64_t)read_i32(c, row_ptr + n);
+    if (m > 0) {
+        int32_t *serr = ws_zeroed<int32_t>(c, "csr_sort_err", 1);
+        if (read_i32(c, serr)) {
+            FL_CHECK_HIP(hipMemsetAsync(serr, 0, sizeof(int32_t), c->stream));
+            throw Error(FL_EHIP, "fl_build_csr: the edge sort's look-back gave up");
+        }
+    }
+    return nnz;
 }
 
 int32_t components(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t *label)

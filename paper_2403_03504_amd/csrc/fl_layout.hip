@@ -126,7 +126,8 @@ LabelSort sort_by_label(fl_ctx *c, int32_t n, const int32_t *label, int32_t n_la
     FL_LAUNCH_CHECK();
     int nbits = 1;
     while (nbits < 31 && ((int64_t)1 << nbits) < n) ++nbits;
-    const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, nbits);
+    int32_t *serr = ws_zeroed<int32_t>(c, "lay_sort_err", 1);
+    const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, nbits, serr);
     const uint32_t *skey = alt ? k1 : k0;
     LabelSort r;
     r.perm = alt ? i1 : i0;
@@ -135,6 +136,10 @@ LabelSort sort_by_label(fl_ctx *c, int32_t n, const int32_t *label, int32_t n_la
     int32_t *d_off = ws<int32_t>(c, "lay_off", (size_t)n_labels + 1);
     hipLaunchKernelGGL(k_comp_flags, dim3(g), dim3(256), 0, c->stream, skey, n, flag);
     scan_excl_i32(c, flag, pos, n);
+    if (read_i32(c, serr)) {
+        FL_CHECK_HIP(hipMemsetAsync(serr, 0, sizeof(int32_t), c->stream));
+        throw Error(FL_EHIP, "layout: the label sort's look-back gave up");
+    }
     FL_REQUIRE(read_i32(c, pos + n) == n_labels, "the number of distinct labels differs from the component count");
     hipLaunchKernelGGL(k_comp_offsets, dim3(g), dim3(256), 0, c->stream, flag, pos, n, d_off);
     FL_LAUNCH_CHECK();

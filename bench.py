@@ -509,11 +509,13 @@ def main() -> int:
     far_ms = phases["far"][0] / max(phases["far"][1], 1)
     far_flop = 8.0 * args.p * g.n
     # M2L: per V-list entry one p-term outgoing-to-incoming conversion,
-    # 4p^2 + 24p FLOP (complex multiply-adds of the scaled operator); the
-    # phase also holds the (small) L2L launch, so this is a lower bound
+    # 4p^2 + 15p FLOP (p complex products rho^k a_k, the binomial sums, the
+    # mass term and p complex multiply-adds by rho^l; the powers of rho come
+    # from a table); the phase also holds the (small) L2L launch, so this is
+    # a lower bound
     m2l_ms = phases["m2l"][0] / max(phases["m2l"][1], 1)
     v_per_launch = fst["total_v_entries"] / evals
-    m2l_flop = v_per_launch * (4.0 * args.p * args.p + 24.0 * args.p)
+    m2l_flop = v_per_launch * (4.0 * args.p * args.p + 15.0 * args.p)
     attract_ms = phases["attract"][0] / max(phases["attract"][1], 1)
     attract_bytes = 40.0 * g.n + 4.0 * nnz  # compulsory bytes of the attraction/combine pass
     roofline = {"kernel": "k_p2p (FMM near field)", "bound": "alu", "achieved": achieved / 1e12,

@@ -300,6 +300,20 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restric
 {
     constexpr int ROW = 2 * P + 1;  // floats per lane row (odd: no bank conflicts down a column)
     __shared__ float rows_all[4][WAVE * ROW];
+    // rho^k (k = 1..P) of every offset (dx, dy) a V entry can have: a child
+    // of a same-level neighbour of the parent lies at most 3 cells away on
+    // each axis, so 7 x 7 offsets (the centre is never used)
+    __shared__ float2 rpow[P][49];
+    if (threadIdx.x < 49) {
+        const int dx = (int)threadIdx.x / 7 - 3, dy = (int)threadIdx.x % 7 - 3;
+        const float2 rho = (dx | dy) ? crecip(make_float2((float)dx, (float)dy)) : make_float2(0.f, 0.f);
+        float2 pw = rho;
+        for (int k = 0; k < P; ++k) {
+            rpow[k][threadIdx.x] = pw;
+            pw = cmul(pw, rho);
+        }
+    }
+    __syncthreads();
     float *rows = rows_all[threadIdx.x / WAVE];
     const int ncells = t.counts[0];
     const int lane = lane_id();
@@ -321,31 +335,26 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restric
             for (int ei = v0 + j; ei < v1; ei += 32) {
                 const int s = V[ei];
                 const uint32_t sxy = t.ixy[s];
-                // same level: source centre - target centre = w (dx + i dy)
-                const float dx = (float)(cell_ix(sxy) - cell_ix(cxy)), dy = (float)(cell_iy(sxy) - cell_iy(cxy));
-                const float2 rho = crecip(make_float2(dx, dy));
-                const float2 mr = make_float2(-rho.x, -rho.y);
+                // same level: source centre - target centre = w (dx + i dy),
+                // rho = w / (source - target) from the offset table
+                const int o = (cell_ix(sxy) - cell_ix(cxy) + 3) * 7 + (cell_iy(sxy) - cell_iy(cxy) + 3);
                 const float2 *Ms = M + (int64_t)s * (P + 1);
                 const float Q = Ms[0].x;
-                float2 ap[P + 1];
-                float2 pw = mr;
+                float2 ap[P + 1];  // rho^k a_k; the sign of (-rho)^k goes into the coefficient
 #pragma unroll
-                for (int k = 1; k <= P; ++k) {
-                    ap[k] = cmul(pw, Ms[k]);
-                    pw = cmul(pw, mr);
-                }
-                float2 rl = rho;
+                for (int k = 1; k <= P; ++k) ap[k] = cmul(rpow[k - 1][o], Ms[k]);
 #pragma unroll
                 for (int l = 1; l <= P; ++l) {
-                    float2 in = make_float2(-Q / (float)l, 0.f);
+                    float2 in = make_float2(-Q * (1.0f / (float)l), 0.f);
 #pragma unroll
                     for (int k = 1; k <= P; ++k) {
-                        const float bc = binomf(l + k - 1, k - 1);
-                        in.x += bc * ap[k].x;
-                        in.y += bc * ap[k].y;
+                        const float bc = (k & 1 ? -1.0f : 1.0f) * binomf(l + k - 1, k - 1);
+                        in.x = fmaf(bc, ap[k].x, in.x);
+                        in.y = fmaf(bc, ap[k].y, in.y);
                     }
-                    B[l] = cadd(B[l], cmul(rl, in));
-                    rl = cmul(rl, rho);
+                    const float2 rl = rpow[l - 1][o];
+                    B[l].x = fmaf(rl.x, in.x, fmaf(-rl.y, in.y, B[l].x));
+                    B[l].y = fmaf(rl.x, in.y, fmaf(rl.y, in.x, B[l].y));
                 }
             }
         }
@@ -364,7 +373,7 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restric
                     float2 pw = rho;
 #pragma unroll
                     for (int l = 1; l <= P; ++l) {
-                        const float s2 = p.z / (float)l;
+                        const float s2 = p.z * (1.0f / (float)l);
                         B[l].x -= s2 * pw.x;
                         B[l].y -= s2 * pw.y;
                         pw = cmul(pw, rho);

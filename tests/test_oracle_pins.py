@@ -435,6 +435,34 @@ def test_fmm_lists_basic_structure(orc):
     assert all((s, c) in pairs for c, s in pairs)
 
 
+def test_fmm_v_list_offsets(orc):
+    """Sec. 3.2.1 interacting cells: a V entry is a same-level child of a
+    neighbour of the target's parent that is not adjacent to the target, so
+    its offset is at most 3 cells and at least 2 on some axis (the M2L kernel
+    reads its translation powers from a table over exactly these offsets)."""
+    from paper_2403_03504_amd import workloads as w
+    rng = np.random.default_rng(5)
+    cases = [w.clustered_positions(9, 3000, 4, 100.0, 1.5),
+             (rng.uniform(-50, 50, 4000), rng.uniform(-50, 50, 4000))]
+    for x, y in cases:
+        L = orc.fmm_lists(x, y, leaf_size=8, bits=16)
+        cells = L["cells"]
+        vp, vi = L["V"]
+        assert vi.size > 0
+        seen = set()
+        for c in range(cells.shape[0]):
+            for s in vi[vp[c]:vp[c + 1]]:
+                assert cells[s, 0] == cells[c, 0]
+                dx, dy = int(cells[s, 1] - cells[c, 1]), int(cells[s, 2] - cells[c, 2])
+                assert max(abs(dx), abs(dy)) in (2, 3)
+                pdx = (int(cells[s, 1]) >> 1) - (int(cells[c, 1]) >> 1)
+                pdy = (int(cells[s, 2]) >> 1) - (int(cells[c, 2]) >> 1)
+                assert max(abs(pdx), abs(pdy)) == 1
+                seen.add((dx, dy))
+        # every offset of the 7x7 block outside the 3x3 neighbourhood can occur
+        assert len(seen) > 20
+
+
 # --- Kamada-Kawai (sec. 3.1) ----------------------------------------------------
 
 def _kk_case(orc, n, edges, x, y):

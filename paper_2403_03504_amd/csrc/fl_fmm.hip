@@ -104,7 +104,7 @@ struct P2MLds {
 
 // k_p2m: one wave per leaf.  Each lane takes particles of the leaf and writes
 // its P+1 terms (Q contribution and -q u^k / k) to LDS; lane k then sums
-// column k in lane order.
+// column k in lane order, over the rows that hold particles.
 template <int P>
 __global__ __launch_bounds__(256) void k_p2m(TreeView t, const float4 *__restrict__ part,
                                              const int32_t *__restrict__ leaf_cell, float2 *__restrict__ M)
@@ -133,13 +133,14 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const float4 *__restric
             float2 pw = u;
 #pragma unroll
             for (int k = 1; k <= P; ++k) {
-                sh.buf[w][k][lane] = cscale(pw, -q / (float)k);
+                sh.buf[w][k][lane] = cscale(pw, -q * (1.0f / (float)k));
                 pw = cmul(pw, u);
             }
             wave_lds_sync();
             if (lane <= P) {
+                const int nl = min(WAVE, e - t0);  // rows past the leaf's particles hold zeros
 #pragma unroll 8
-                for (int i = 0; i < WAVE; ++i) acc = cadd(acc, sh.buf[w][lane][i]);
+                for (int i = 0; i < nl; ++i) acc = cadd(acc, sh.buf[w][lane][i]);
             }
             wave_lds_sync();
         }
@@ -798,10 +799,12 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         FL_CHECK_HIP(hipEventRecord(c->ev_lists, c->stream));
         FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_lists, 0));
         if (on_lists) (*on_lists)(c->ev_lists);
+        // the statistics (for the host only) on the branch, ahead of M2L,
+        // rather than between the near field and the far field
+        lists_stats(c, t, L, us);
         m2l_p<P>(c, us, t, L, b);
         FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
         near_p(c, t, L, near, pleaf);
-        lists_stats(c, t, L);
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
     }
     PhaseTimer pt(c, FL_PH_FAR);

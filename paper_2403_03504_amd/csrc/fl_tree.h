@@ -129,8 +129,8 @@ void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const flo
 void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes);
 // The lists' statistics (counts, near pairs) into the context's counters;
 // nothing of the passes reads them, so the caller launches this off the
-// critical path (after the near field).
-void lists_stats(fl_ctx *c, const TreeBufs &t, const ListBufs &L);
+// critical path (on a branch stream `s`, or the context's stream if null).
+void lists_stats(fl_ctx *c, const TreeBufs &t, const ListBufs &L, hipStream_t s = nullptr);
 // lanes per cell when the caller leaves the choice open (0)
 int default_list_lanes(int64_t n);
 // Deepest level of the last tree into the statistics block.

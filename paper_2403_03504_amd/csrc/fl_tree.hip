@@ -1107,9 +1107,9 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     FL_LAUNCH_CHECK();
 }
 
-void lists_stats(fl_ctx *c, const TreeBufs &t, const ListBufs &L)
+void lists_stats(fl_ctx *c, const TreeBufs &t, const ListBufs &L, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(256), 0, c->stream, t.counts, (const int64_t *)L.offVX,
+    hipLaunchKernelGGL(k_lists_stats, dim3(1), dim3(256), 0, s ? s : c->stream, t.counts, (const int64_t *)L.offVX,
                        (const int64_t *)L.offUW, (const unsigned long long *)L.block_pairs, L.fill_blocks,
                        c->d_stats, t.n);
     FL_LAUNCH_CHECK();

@@ -49,6 +49,22 @@ void flush_timing(fl_ctx *c)
     c->ev_pending.clear();
 }
 
+namespace {
+thread_local bool t_recording = false;
+}
+
+std::shared_mutex &alloc_capture_mutex()
+{
+    static std::shared_mutex m;
+    return m;
+}
+
+bool recording_thread() { return t_recording; }
+
+CaptureGuard::CaptureGuard() : lk(alloc_capture_mutex()) { t_recording = true; }
+
+CaptureGuard::~CaptureGuard() { t_recording = false; }
+
 hipStream_t aux_stream(fl_ctx *c, int i)
 {
     if (!c->aux[i]) FL_CHECK_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
@@ -94,6 +110,7 @@ fl_status fl_create(fl_ctx **out, int device, void *stream)
         delete c;
         return FL_EHIP;
     }
+    AllocGuard guard;
     if (hipMalloc(&c->d_stats, 16 * sizeof(int64_t)) != hipSuccess) {
         delete c;
         return FL_ENOMEM;
@@ -122,6 +139,7 @@ void fl_destroy(fl_ctx *c)
     for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_fork2, c->ev_join2, c->ev_lists})
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    AllocGuard guard;
     for (auto &kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto &pe : c->ev_pending) {

@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <shared_mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -98,6 +100,26 @@ struct fl_ctx {
 
 namespace fl {
 
+// Device allocations and frees may synchronise the whole device, and that
+// breaks a graph another thread is recording on one of its streams.  They
+// hold AllocGuard (exclusive) and recordings hold CaptureGuard (shared), so
+// the two never overlap in a process; a thread that is recording takes no
+// AllocGuard (HIP refuses its own allocations then, with an error).
+std::shared_mutex &alloc_capture_mutex();
+bool recording_thread();
+struct AllocGuard {
+    std::unique_lock<std::shared_mutex> lk;
+    AllocGuard()
+    {
+        if (!recording_thread()) lk = std::unique_lock<std::shared_mutex>(alloc_capture_mutex());
+    }
+};
+struct CaptureGuard {
+    std::shared_lock<std::shared_mutex> lk;
+    CaptureGuard();   // marks the thread as recording
+    ~CaptureGuard();  // clears the mark
+};
+
 // Grow-only named workspace buffer of at least `count` elements of T.
 // Growing synchronises the stream (the old buffer may still be in use).
 template <class T>
@@ -107,6 +129,7 @@ T *ws(fl_ctx *c, const char *name, size_t count)
     if (bytes == 0) bytes = sizeof(T);
     DevBuf &b = c->bufs[name];
     if (b.cap < bytes) {
+        AllocGuard guard;
         if (b.p) {
             FL_CHECK_HIP(hipStreamSynchronize(c->stream));
             FL_CHECK_HIP(hipFree(b.p));

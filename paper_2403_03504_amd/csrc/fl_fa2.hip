@@ -12,6 +12,7 @@
 //   k_update   per-node speed and move p += s_i F, F' <- F
 // There are no floating-point atomics: a run is bitwise reproducible.
 #include <algorithm>
+#include <exception>
 #include <functional>
 #include <vector>
 
@@ -595,6 +596,7 @@ constexpr int GRAPH_MIN_ITERS = 4;
 
 static void destroy_graph(hipGraph_t g, hipGraphExec_t e)
 {
+    AllocGuard guard;  // freeing a graph's memory may synchronise the device
     if (e) (void)hipGraphExecDestroy(e);
     if (g) (void)hipGraphDestroy(g);
 }
@@ -620,20 +622,30 @@ static void run_graph(hipStream_t main, std::vector<Sys> &bs, int32_t *flags, in
         if (iters > 1) {
             for (size_t k = 0; k < nb; ++k) {
                 hipStream_t s = bs[k].c->stream;
-                FL_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 const int64_t it0 = bs[k].st.iter;
-                try {
-                    iteration(bs[k], flags, nullptr, 0);
-                } catch (...) {
-                    hipGraph_t g2 = nullptr;
-                    (void)hipStreamEndCapture(s, &g2);
-                    destroy_graph(g2, nullptr);
-                    bs[k].st.iter = it0;
-                    throw;
+                std::exception_ptr fail;
+                hipGraph_t failed = nullptr;
+                {
+                    // no device allocation or free anywhere in the process while recording
+                    CaptureGuard recording;
+                    FL_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                    try {
+                        iteration(bs[k], flags, nullptr, 0);
+                    } catch (...) {
+                        fail = std::current_exception();
+                    }
+                    const hipError_t ec = hipStreamEndCapture(s, fail ? &failed : &graphs[k]);
+                    bs[k].st.iter = it0;  // recorded, not run
+                    if (!fail) FL_CHECK_HIP(ec);
                 }
-                bs[k].st.iter = it0;  // recorded, not run
-                FL_CHECK_HIP(hipStreamEndCapture(s, &graphs[k]));
-                FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
+                if (fail) {
+                    destroy_graph(failed, nullptr);
+                    std::rethrow_exception(fail);
+                }
+                {
+                    AllocGuard guard;  // instantiation allocates the graph's device resources
+                    FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
+                }
             }
             for (int it = 1; it < iters; ++it)
                 for (size_t k = 0; k < nb; ++k) FL_CHECK_HIP(hipGraphLaunch(execs[k], bs[k].c->stream));

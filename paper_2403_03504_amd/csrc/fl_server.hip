@@ -82,16 +82,22 @@ struct DevArrays {
     int32_t *src = nullptr, *dst = nullptr, *rp = nullptr, *col = nullptr, *deg = nullptr;
     float *x = nullptr, *y = nullptr;
     int64_t cap_n = 0, cap_m = 0;
-    void release()
+    void release_held()  // with AllocGuard held
     {
         for (void *p : {(void *)src, (void *)dst, (void *)rp, (void *)col, (void *)deg, (void *)x, (void *)y})
             if (p) (void)hipFree(p);
         *this = DevArrays{};
     }
+    void release()
+    {
+        fl::AllocGuard guard;
+        release_held();
+    }
     bool ensure(int64_t n, int64_t m)
     {
         if (n <= cap_n && m <= cap_m) return true;
-        release();
+        fl::AllocGuard guard;
+        release_held();
         const int64_t nn = std::max<int64_t>(n, 1), mm = std::max<int64_t>(m, 1);
         bool ok = hipMalloc(&src, 4 * mm) == hipSuccess && hipMalloc(&dst, 4 * mm) == hipSuccess &&
                   hipMalloc(&rp, 4 * (nn + 1)) == hipSuccess && hipMalloc(&col, 8 * mm) == hipSuccess &&
@@ -99,7 +105,7 @@ struct DevArrays {
                   hipMalloc(&y, 4 * nn) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
-            release();
+            release_held();
             return false;
         }
         cap_n = nn;

@@ -28,9 +28,12 @@ def test_results_alone_equal_results_in_the_mix():
     srv = fl.Server(0, budget_bytes=8 << 30, slots=4)
     ids = [srv.submit(g.n, g.src, g.dst, g.x, g.y, 40, prm) for g in jobs]
     mix = []
-    for i in ids:
-        assert srv.wait(i, 120.0) == fl.JOB_DONE
-        mix.append(srv.result(i))
+    for i, g in zip(ids, jobs):
+        st_i = srv.wait(i, 120.0)
+        if st_i != fl.JOB_DONE:
+            _note("job", i, "of", g.n, "nodes ended in state", st_i)
+        mix.append(srv.result(i))  # raises with the job's error message if it failed
+        assert st_i == fl.JOB_DONE
     st = srv.stats()
     srv.close()
     assert st["completed"] == len(jobs) and st["peak_bytes"] <= 8 << 30
@@ -38,8 +41,9 @@ def test_results_alone_equal_results_in_the_mix():
     srv1 = fl.Server(0, budget_bytes=8 << 30, slots=1)
     for g, (mx, my, t) in zip(jobs, mix):
         j = srv1.submit(g.n, g.src, g.dst, g.x, g.y, 40, prm)
-        assert srv1.wait(j, 120.0) == fl.JOB_DONE
-        ax, ay, _ = srv1.result(j)
+        st_j = srv1.wait(j, 120.0)
+        ax, ay, _ = srv1.result(j)  # raises with the job's error message if it failed
+        assert st_j == fl.JOB_DONE
         assert np.array_equal(ax, mx) and np.array_equal(ay, my), g.n
         assert np.all(np.isfinite(ax))
         assert t[0] <= t[1] <= t[2]

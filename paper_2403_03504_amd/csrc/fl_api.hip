@@ -65,6 +65,19 @@ CaptureGuard::CaptureGuard() : lk(alloc_capture_mutex()) { t_recording = true; }
 
 CaptureGuard::~CaptureGuard() { t_recording = false; }
 
+void free_retired(fl_ctx *c)
+{
+    if (c->retired.empty()) return;
+    FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    for (auto s : c->aux)
+        if (s) FL_CHECK_HIP(hipStreamSynchronize(s));
+    AllocGuard guard;
+    for (auto &r : c->retired) (void)hipFree(r.first);
+    c->ws_bytes -= c->retired_bytes;
+    c->retired.clear();
+    c->retired_bytes = 0;
+}
+
 hipStream_t aux_stream(fl_ctx *c, int i)
 {
     if (!c->aux[i]) FL_CHECK_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
@@ -140,6 +153,7 @@ void fl_destroy(fl_ctx *c)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     AllocGuard guard;
+    for (auto &r : c->retired) (void)hipFree(r.first);
     for (auto &kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto &pe : c->ev_pending) {

@@ -70,7 +70,11 @@ struct fl_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     std::map<std::string, fl::DevBuf> bufs;
-    size_t ws_bytes = 0;
+    size_t ws_bytes = 0;  // workspace held, retired buffers included
+    // workspace buffers replaced by larger ones, freed together once the
+    // context's streams are idle (free_retired)
+    std::vector<std::pair<void *, size_t>> retired;
+    size_t retired_bytes = 0;
     // pinned host staging for small read-backs
     void *host_stage = nullptr;
     // timing
@@ -120,8 +124,15 @@ struct CaptureGuard {
     ~CaptureGuard();  // clears the mark
 };
 
+// Frees the retired workspace buffers after synchronising the context's
+// streams (a quiet point: the end of a job, the context's destruction).
+void free_retired(fl_ctx *c);
+
 // Grow-only named workspace buffer of at least `count` elements of T.
-// Growing synchronises the stream (the old buffer may still be in use).
+// The buffer it replaces may still be in use by enqueued work: it is retired
+// rather than freed (a free may synchronise the whole device), and retired
+// buffers are freed together once they would hold more than half of the
+// context's workspace, or at the next quiet point.
 template <class T>
 T *ws(fl_ctx *c, const char *name, size_t count)
 {
@@ -129,16 +140,25 @@ T *ws(fl_ctx *c, const char *name, size_t count)
     if (bytes == 0) bytes = sizeof(T);
     DevBuf &b = c->bufs[name];
     if (b.cap < bytes) {
-        AllocGuard guard;
         if (b.p) {
-            FL_CHECK_HIP(hipStreamSynchronize(c->stream));
-            FL_CHECK_HIP(hipFree(b.p));
-            c->ws_bytes -= b.cap;
+            c->retired.emplace_back(b.p, b.cap);
+            c->retired_bytes += b.cap;
             b.p = nullptr;
             b.cap = 0;
+            if (2 * c->retired_bytes > c->ws_bytes) free_retired(c);
         }
         size_t nb = bytes + bytes / 8 + 256;
-        hipError_t e = hipMalloc(&b.p, nb);
+        hipError_t e;
+        {
+            AllocGuard guard;
+            e = hipMalloc(&b.p, nb);
+        }
+        if (e != hipSuccess && !c->retired.empty()) {  // the retired buffers may make the room
+            (void)hipGetLastError();
+            free_retired(c);
+            AllocGuard guard;
+            e = hipMalloc(&b.p, nb);
+        }
         if (e != hipSuccess) {
             (void)hipGetLastError();
             throw Error(FL_ENOMEM, std::string("workspace allocation of ") + std::to_string(nb) + " bytes for " +

@@ -642,10 +642,7 @@ static void run_graph(hipStream_t main, std::vector<Sys> &bs, int32_t *flags, in
                     destroy_graph(failed, nullptr);
                     std::rethrow_exception(fail);
                 }
-                {
-                    AllocGuard guard;  // instantiation allocates the graph's device resources
-                    FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
-                }
+                FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
             }
             for (int it = 1; it < iters; ++it)
                 for (size_t k = 0; k < nb; ++k) FL_CHECK_HIP(hipGraphLaunch(execs[k], bs[k].c->stream));

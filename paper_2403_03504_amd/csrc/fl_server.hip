@@ -135,6 +135,10 @@ void run_on_gpu(fl_ctx *ctx, hipStream_t s, DevArrays &d, Job &j)
     FL_CHECK_HIP(hipMemcpyAsync(j.x.data(), d.x, 4 * (size_t)j.n, hipMemcpyDeviceToHost, s));
     FL_CHECK_HIP(hipMemcpyAsync(j.y.data(), d.y, 4 * (size_t)j.n, hipMemcpyDeviceToHost, s));
     FL_CHECK_HIP(hipStreamSynchronize(s));
+    // a quiet point: free the workspace the job's growth retired (the
+    // branch contexts of its batches keep theirs until they grow or end)
+    fl::free_retired(ctx);
+    for (auto *sc : ctx->sub) fl::free_retired(sc);
 }
 
 void worker(fl_server *sv)

@@ -62,9 +62,12 @@ void fl_destroy(fl_ctx *ctx);
 const char *fl_last_error(const fl_ctx *ctx);
 /* Switch the stream later calls enqueue on. */
 fl_status fl_set_stream(fl_ctx *ctx, void *stream);
-/* Block until the context's stream has drained. */
+/* Block until the context's stream has drained; then free the workspace
+ * buffers that were replaced by larger ones (see fl_workspace_bytes). */
 fl_status fl_synchronize(fl_ctx *ctx);
-/* Bytes of device workspace the context holds. [host] */
+/* Bytes of device workspace the context holds.  A buffer replaced by a
+ * larger one is kept (it may still be in use by enqueued work) and counted
+ * until fl_synchronize, fl_destroy or a later growth frees it. [host] */
 size_t fl_workspace_bytes(const fl_ctx *ctx);
 /* Library version string, e.g. "fa2lay 0.1 gfx950". [host] */
 const char *fl_version(void);

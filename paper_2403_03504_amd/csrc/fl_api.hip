@@ -179,6 +179,10 @@ fl_status fl_synchronize(fl_ctx *c)
 {
     FL_API_BEGIN(c)
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+    // a quiet point: the stream has drained, and so have the branch
+    // contexts (their work joins the context's stream)
+    free_retired(c);
+    for (auto *sc : c->sub) free_retired(sc);
     FL_API_END(c)
 }
 

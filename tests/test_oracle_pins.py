@@ -184,6 +184,36 @@ def test_swing_traction_speed_rules(orc):
     assert math.isclose(SWG2, 3 * math.sqrt(2)) and math.isclose(TRA2, 1.5 * math.sqrt(2))
 
 
+def test_node_speed_swing_term(orc):
+    """s_i depends on the node's own swing through its square root: values
+    derived by hand (a dropped root or the global SWG in place of swg_i
+    gives 0.2/9 or another value)."""
+    ex = GOLD["node_speed_swing_example"]
+    prm = orc.FA2Params(ks=ex["ks"], ksmax=ex["ksmax"])
+    F = np.array(ex["F"])
+    s = orc.node_speed(np.array(ex["swg"]), F[:, 0], F[:, 1], ex["s_G"], prm)
+    assert np.allclose(s, ex["s_i"], rtol=1e-14, atol=0)
+
+
+def test_fa2_two_node_step_worked_example(orc):
+    """A whole iteration worked by hand: forces of the three terms, swing and
+    traction against nonzero previous forces, the rise cap on s_G, node
+    speeds with distinct swings, and the move."""
+    ex = GOLD["fa2_two_node_step"]
+    rp, col, deg = csr_from_edges(2, [(0, 1)], orc)
+    prm = orc.FA2Params(repulsion="exact", tau=1.0, ks=0.1, ksmax=10.0, max_rise=0.5)
+    st = orc.fa2_step(rp, col, deg, np.array(ex["x"]), np.array(ex["y"]), np.array(ex["F_prev_x"]),
+                      np.array(ex["F_prev_y"]), ex["s_prev"], ex["iter"], prm)
+    assert np.allclose(st["fx"], ex["F_x"], rtol=0, atol=1e-13)
+    assert np.allclose(st["fy"], ex["F_y"], rtol=0, atol=1e-13)
+    assert math.isclose(st["swg"], ex["SWG"], rel_tol=1e-13)
+    assert math.isclose(st["tra"], ex["TRA"], rel_tol=1e-13)
+    assert math.isclose(st["speed"], ex["s_G"], rel_tol=1e-13)
+    assert np.allclose(st["s_i"], ex["s_i"], rtol=1e-12, atol=0)
+    assert np.allclose(st["x"], ex["x_next"], rtol=0, atol=1e-13)
+    assert np.allclose(st["y"], ex["y_next"], rtol=0, atol=1e-13)
+
+
 def test_fa2_step_zero_force_no_move(orc):
     x = np.array([1.0, 2.0])
     y = np.array([3.0, -1.0])

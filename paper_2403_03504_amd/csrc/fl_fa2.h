@@ -31,7 +31,10 @@ struct FA2Batch {
 // batch runs on its own branch context (own stream) as one replayed graph,
 // concurrently with the others; otherwise one after the other, eagerly, on
 // the context's stream.  Ordered after earlier, and before later, work on the
-// context's stream; throws if an FMM capacity guard tripped.
+// context's stream; throws if an FMM capacity guard tripped.  Every system
+// has its own status word (a system whose forces turn non-finite stops moving;
+// the others go on); at the end the words are OR-ed into *flags on the
+// context's stream (bit 0: a non-finite force, bit 1: a non-finite position).
 void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &b, int iters, int32_t *flags);
 
 int32_t components(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t *label);

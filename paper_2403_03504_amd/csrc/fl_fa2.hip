@@ -262,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_combine(Segs sg, const int32_t *__restri
             fgx[i] = (float)Fgx;
             fgy[i] = (float)Fgy;
         }
-        if (!isfinite(Fx) || !isfinite(Fy)) atomicOr(flags, 1);
+        if (!isfinite(Fx) || !isfinite(Fy)) atomicOr(flags + comp, 1);
         if (part) {
             const double px = first ? 0.0 : (double)fpx[i], py = first ? 0.0 : (double)fpy[i];
             const double dxs = (double)Fx - px, dys = (double)Fy - py;
@@ -324,9 +324,9 @@ __global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, f
                                                const double *__restrict__ scalars, double ks, double ksmax,
                                                int32_t *__restrict__ flags)
 {
-    if (*flags & 1) return;  // non-finite forces: leave the layout as it was
     const int2 tl = sg.tiles[blockIdx.x / TILE_SUB];
     const int comp = tl.x;
+    if (flags[comp] & 1) return;  // non-finite forces: this system stays as it was
     const int b0 = tl.y + (int)(blockIdx.x % TILE_SUB) * (SEG_TILE / TILE_SUB);
     const int b1 = min(b0 + SEG_TILE / TILE_SUB, sg.coff[comp + 1]);
     const double sG = scalars[4 * (int64_t)comp];
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, f
         y[i] = ny;
         fpx[i] = Fx;
         fpy[i] = Fy;
-        if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags, 2);
+        if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags + comp, 2);
     }
 }
 
@@ -387,6 +387,15 @@ __global__ void k_check_finite(int n, const float *__restrict__ x, const float *
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && (!isfinite(x[i]) || !isfinite(y[i]))) atomicOr(flags, 4);
+}
+
+// the systems' status words of a batch OR-ed into the caller's word
+__global__ void k_flags_or(const int32_t *__restrict__ f, int K, int32_t *__restrict__ dst)
+{
+    int v = 0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) v |= f[k];
+    for (int o = WAVE / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, WAVE);
+    if (lane_id() == 0 && v) atomicOr(dst, v);
 }
 
 }  // namespace
@@ -516,18 +525,22 @@ struct Sys {
     float *x, *y;
     fl_fa2_state st;
     fl_fa2_params prm;
+    // one status word per system (bit 0: a non-finite force, bit 1: a
+    // non-finite position), cleared by the caller before the first iteration
+    int32_t *flags;
 };
 
-// one iteration; flags must have been cleared by the caller.  Unless phases
+// one iteration; b.flags must have been cleared by the caller.  Unless phases
 // are being timed (or the context's branches are off), the attraction
 // gathers run on a branch stream (fork and join by events, which graph
 // capture records as parallel branches) beside the repulsion; the combine
 // then reads their sums.  With the FMM the branch forks once the lists are
 // built, so that the gathers (bound by memory latency) overlap the
 // ALU-bound near field rather than the latency-bound tree build.
-static void iteration(Sys &b, int32_t *flags, double *ring, int ring_it)
+static void iteration(Sys &b, double *ring, int ring_it)
 {
     fl_ctx *c = b.c;
+    int32_t *flags = b.flags;
     const int n = b.g.n;
     float2 *fr = ws<float2>(c, "fa2_fr", n);
     float *fcx = ws<float>(c, "fa2_fcx", n);
@@ -606,9 +619,9 @@ static void destroy_graph(hipGraph_t g, hipGraphExec_t e)
 // captured on and replayed iters-1 times on the batch's stream, so that
 // batches run on separate hardware queues.  On return all work is enqueued
 // and `main` is ordered after every batch.
-static void run_graph(hipStream_t main, std::vector<Sys> &bs, int32_t *flags, int iters)
+static void run_graph(hipStream_t main, std::vector<Sys> &bs, int iters)
 {
-    for (auto &b : bs) iteration(b, flags, nullptr, 0);
+    for (auto &b : bs) iteration(b, nullptr, 0);
     const size_t nb = bs.size();
     std::vector<hipGraph_t> graphs(nb, nullptr);
     std::vector<hipGraphExec_t> execs(nb, nullptr);
@@ -630,7 +643,7 @@ static void run_graph(hipStream_t main, std::vector<Sys> &bs, int32_t *flags, in
                     CaptureGuard recording;
                     FL_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                     try {
-                        iteration(bs[k], flags, nullptr, 0);
+                        iteration(bs[k], nullptr, 0);
                     } catch (...) {
                         fail = std::current_exception();
                     }
@@ -642,7 +655,12 @@ static void run_graph(hipStream_t main, std::vector<Sys> &bs, int32_t *flags, in
                     destroy_graph(failed, nullptr);
                     std::rethrow_exception(fail);
                 }
-                FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
+                {
+                    // instantiation allocates the graph's device resources:
+                    // not while another thread records
+                    AllocGuard guard;
+                    FL_CHECK_HIP(hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0));
+                }
             }
             for (int it = 1; it < iters; ++it)
                 for (size_t k = 0; k < nb; ++k) FL_CHECK_HIP(hipGraphLaunch(execs[k], bs[k].c->stream));
@@ -701,16 +719,22 @@ void fa2_run_batches(fl_ctx *c, const std::vector<FA2Batch> &in, int iters, int3
             b.st = fl_fa2_state{ws<float>(bc, (tag + "_fpx").c_str(), n), ws<float>(bc, (tag + "_fpy").c_str(), n),
                                 ws<double>(bc, (tag + "_sc").c_str(), 4 * (size_t)b.sg.K), 0};
             b.prm = B.prm;
+            b.flags = ws<int32_t>(bc, (tag + "_flags").c_str(), (size_t)b.sg.K);
+            fill_i32(bc, b.flags, b.sg.K, 0);
             bs.push_back(b);
         }
         if (graphs) {
             hipStream_t main = aux_stream(c, 1);
-            run_graph(main, bs, flags, iters);
+            run_graph(main, bs, iters);
             FL_CHECK_HIP(hipEventRecord(ready, main));
             FL_CHECK_HIP(hipStreamWaitEvent(c->stream, ready, 0));
         } else {
             for (auto &b : bs)
-                for (int it = 0; it < iters; ++it) iteration(b, flags, nullptr, 0);
+                for (int it = 0; it < iters; ++it) iteration(b, nullptr, 0);
+        }
+        for (auto &b : bs) {
+            hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(NT), 0, c->stream, (const int32_t *)b.flags, b.sg.K, flags);
+            FL_LAUNCH_CHECK();
         }
         for (auto &b : bs)
             if (b.prm.repulsion != FL_REP_EXACT && tree_error_bits(b.c, true))
@@ -818,7 +842,7 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
     FL_LAUNCH_CHECK();
     if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
     double *ring = per_iter ? ws<double>(c, "fa2_ring", 3 * (size_t)(iters > 0 ? iters : 1)) : nullptr;
-    Sys b{c, segs_single(c, n), g, attract_plan(c, g), x, y, *st, *prm};
+    Sys b{c, segs_single(c, n), g, attract_plan(c, g), x, y, *st, *prm, flags};
     if (!ring && !c->timing && iters >= GRAPH_MIN_ITERS && c->use_graphs) {
         // the caller's stream may be the null stream, which cannot be
         // captured: run on private streams ordered after it and before
@@ -832,7 +856,7 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
             FL_CHECK_HIP(hipStreamWaitEvent(bs, e, 0));
             c->stream = bs;
             std::vector<Sys> one{b};
-            run_graph(main, one, flags, iters);
+            run_graph(main, one, iters);
             c->stream = user;
             FL_CHECK_HIP(hipEventRecord(e, main));
             FL_CHECK_HIP(hipStreamWaitEvent(user, e, 0));
@@ -845,7 +869,7 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
         }
         (void)hipEventDestroy(e);
     } else {
-        for (int it = 0; it < iters; ++it) iteration(b, flags, ring, it);
+        for (int it = 0; it < iters; ++it) iteration(b, ring, it);
         st->iter = b.st.iter;
     }
     if (per_iter || always_sync) {

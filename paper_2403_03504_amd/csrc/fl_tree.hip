@@ -173,8 +173,8 @@ __global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restr
 // the node's (x, y, mass, index) record, so that moving a node to its sorted
 // place is a single 16-byte access; with `xy` the (x, y) pairs the
 // attraction gathers read.  When the hash epoch has
-// just wrapped to 1 the table is cleared here (before any insert of this
-// build).
+// just restarted at 1 (a wrap, or a new key layout) all hcap slots of the
+// table are cleared here (before any insert of this build).
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, int n,
                          const int32_t *__restrict__ ncomp, const double *__restrict__ root, int bits,
                          uint32_t *__restrict__ key, uint64_t *__restrict__ key64, int32_t *__restrict__ idx,
@@ -1026,9 +1026,13 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     hipLaunchKernelGGL(k_bbox_root, dim3(std::min(s.K, 1024)), dim3(NT), 0, c->stream, s, (const float4 *)bpart,
                        t.root, bits, t.epoch);
     float4 *xym = ws<float4>(c, "t_xym", n);
+    // a restarted epoch clears every slot the table holds, not only this
+    // build's: a later, larger build probes slots past this one's range, and
+    // words left there under another key layout could pass its epoch test
+    const int64_t hkey_slots = (int64_t)(c->bufs["t_hkey"].cap / sizeof(uint64_t));
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
                        (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
-                       t.hkey, t.hash_cap, deg, xym, t.counts, xy_out);
+                       t.hkey, hkey_slots, deg, xym, t.counts, xy_out);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
     if (s.K > 1) {

@@ -321,6 +321,11 @@ fl_status fl_kk_layout(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets,
  * component is replayed (results bitwise those of each component run alone
  * by fl_fa2_run).  With graphs off (fl_set_graphs) the components run one
  * after the other as eager launches on the context's stream.  Synchronises.
+ * FL_ENONFINITE when a ForceAtlas2 component's forces or positions turned
+ * non-finite: every component has its own status word, so that component
+ * stops moving (at its last finite positions when a force was the first
+ * non-finite value) while the others are laid out as usual, and all
+ * positions are written back before the call returns the error.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t n_comp, n_single, n_kk, n_fa2;
@@ -443,8 +448,11 @@ fl_status fl_autotune(fl_ctx *ctx, int32_t n, const float *x, const float *y, co
 /* ------------------------------------------------------------------------
  * Layout server: continuous batching of layout jobs on one GPU.  Jobs are
  * copied at submission and queued FIFO; `max_slots` workers (one HIP stream
- * and context each) admit the head of the queue whenever the estimated device
- * bytes of the running jobs plus its own fit `mem_budget_bytes`, so jobs that
+ * and context each) admit the head of the queue whenever the workers' charges
+ * (below) with the head's estimated device bytes fit `mem_budget_bytes`; a
+ * worker that ends a job holding more than the budget allows gives its
+ * memory back, and so does an idle one whose memory keeps the head out, so
+ * the device bytes the workers hold stay within the budget.  Jobs that
  * arrive while others run start as soon as a slot and memory free up, and
  * their kernels overlap on the device.  A job runs fl_build_csr + fl_layout
  * (kk_max_nodes 256, fmm_min_nodes 4096) and its positions come back to host
@@ -463,9 +471,18 @@ typedef struct {
     fl_fa2_params params;
 } fl_job;
 
+/* bytes_in_use / peak_bytes: the sum of the workers' charges against the
+ * budget (a worker between jobs is charged the device bytes it holds, a
+ * worker running a job the larger of those and the job's estimate);
+ * held_bytes / peak_held_bytes: device bytes the workers hold between jobs
+ * (context workspace, branch contexts, job buffers; measured, not estimated);
+ * trims: times a worker gave its memory back to keep the charges within the
+ * budget; over_estimate: jobs that left their worker holding more than the
+ * job's estimate. */
 typedef struct {
     int64_t submitted, admitted, completed, failed, canceled, queued, running;
     int64_t bytes_in_use, peak_bytes, node_updates;
+    int64_t held_bytes, peak_held_bytes, trims, over_estimate;
 } fl_server_stats;
 
 fl_status fl_server_create(fl_server **out, int device, size_t mem_budget_bytes, int32_t max_slots);

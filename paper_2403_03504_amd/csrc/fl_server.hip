@@ -61,7 +61,13 @@ struct fl_server {
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Job>> queue;
     std::map<uint64_t, std::shared_ptr<Job>> jobs;
-    size_t in_use = 0, peak = 0;
+    size_t in_use = 0, peak = 0;  // sum of the workers' charges (below)
+    // per worker: device bytes held while idle (context workspace, branch
+    // contexts, job buffers), and its charge against the budget: the held
+    // bytes when idle, max(held, the job's estimate) while a job runs
+    std::vector<size_t> held, charge;
+    std::vector<char> busy;
+    size_t peak_held = 0;
     uint64_t next_id = 1;
     bool stop = false;
     std::vector<std::thread> workers;
@@ -82,6 +88,7 @@ struct DevArrays {
     int32_t *src = nullptr, *dst = nullptr, *rp = nullptr, *col = nullptr, *deg = nullptr;
     float *x = nullptr, *y = nullptr;
     int64_t cap_n = 0, cap_m = 0;
+    size_t bytes() const { return cap_n ? (size_t)(4 * (cap_n + 1) + 12 * cap_n + 16 * cap_m) : 0; }
     void release_held()  // with AllocGuard held
     {
         for (void *p : {(void *)src, (void *)dst, (void *)rp, (void *)col, (void *)deg, (void *)x, (void *)y})
@@ -141,7 +148,48 @@ void run_on_gpu(fl_ctx *ctx, hipStream_t s, DevArrays &d, Job &j)
     for (auto *sc : ctx->sub) fl::free_retired(sc);
 }
 
-void worker(fl_server *sv)
+// Device bytes a worker holds between jobs: its context's workspace (with
+// the branch contexts') and its job buffers.
+size_t worker_held(const fl_ctx *ctx, const DevArrays &d)
+{
+    size_t b = d.bytes();
+    if (ctx) {
+        b += fl_workspace_bytes(ctx);
+        for (auto *sc : ctx->sub) b += fl_workspace_bytes(sc);
+    }
+    return b;
+}
+
+// Give back everything a worker holds (a fresh context on the same stream).
+bool worker_trim(fl_server *sv, fl_ctx *&ctx, hipStream_t s, DevArrays &d)
+{
+    d.release();
+    if (!ctx) return true;
+    fl_destroy(ctx);
+    ctx = nullptr;
+    if (fl_create(&ctx, sv->device, s) != FL_OK) return false;
+    // the workers capture concurrently; their iterations keep every launch
+    // on the job's own streams (no branch streams, see below)
+    ctx->branches = false;
+    return true;
+}
+
+size_t total_charge(const fl_server *sv)
+{
+    size_t t = 0;
+    for (size_t c : sv->charge) t += c;
+    return t;
+}
+
+size_t running_charge(const fl_server *sv)
+{
+    size_t t = 0;
+    for (size_t w = 0; w < sv->charge.size(); ++w)
+        if (sv->busy[w]) t += sv->charge[w];
+    return t;
+}
+
+void worker(fl_server *sv, int me)
 {
     hipStream_t s = nullptr;
     fl_ctx *ctx = nullptr;
@@ -159,23 +207,46 @@ void worker(fl_server *sv)
     }
     while (true) {
         std::shared_ptr<Job> j;
+        bool trim = false;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_work.wait(lk, [&] {
                 if (sv->stop) return true;
                 if (sv->queue.empty()) return false;
                 const size_t b = sv->queue.front()->bytes;
-                return sv->in_use == 0 || sv->in_use + b <= sv->budget;
+                const size_t mine = std::max(sv->held[me], b);
+                if (total_charge(sv) - sv->charge[me] + mine <= sv->budget) return true;
+                // the head does not fit, but would without the memory idle
+                // workers hold: this idle worker gives its memory back
+                if (sv->held[me] > 0 && running_charge(sv) + b <= sv->budget) {
+                    trim = true;
+                    return true;
+                }
+                return false;
             });
             if (sv->stop) break;
-            j = sv->queue.front();
-            sv->queue.pop_front();
-            j->state = FL_JOB_RUNNING;
-            j->t_start = sv->now();
-            j->tuning = sv->tuning;
-            sv->in_use += j->bytes;
-            sv->peak = std::max(sv->peak, sv->in_use);
-            sv->st.admitted++;
+            if (!trim) {
+                j = sv->queue.front();
+                sv->queue.pop_front();
+                j->state = FL_JOB_RUNNING;
+                j->t_start = sv->now();
+                j->tuning = sv->tuning;
+                sv->busy[me] = 1;
+                sv->charge[me] = std::max(sv->held[me], j->bytes);
+                sv->in_use = total_charge(sv);
+                sv->peak = std::max(sv->peak, sv->in_use);
+                sv->st.admitted++;
+            }
+        }
+        if (trim) {
+            if (sv->fake_ns <= 0.0 && !worker_trim(sv, ctx, s, d) && init_err.empty())
+                init_err = "worker could not recreate its context";
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->held[me] = sv->charge[me] = worker_held(ctx, d);
+            sv->in_use = total_charge(sv);
+            sv->st.trims++;
+            sv->cv_work.notify_all();
+            continue;
         }
         std::string jerr;
         fl_status jrc = FL_OK;
@@ -195,12 +266,33 @@ void worker(fl_server *sv)
             jrc = FL_EHIP;
             jerr = e.what();
         }
+        size_t now_held = worker_held(ctx, d);
+        bool over = false;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
+            if (now_held > j->bytes) sv->st.over_estimate++;
+            sv->held[me] = now_held;
+            sv->busy[me] = 0;
+            sv->charge[me] = now_held;
+            // past the budget, this worker gives its memory back before the
+            // next job
+            over = total_charge(sv) > sv->budget;
+        }
+        if (over && sv->fake_ns <= 0.0) {
+            if (!worker_trim(sv, ctx, s, d) && init_err.empty()) init_err = "worker could not recreate its context";
+            now_held = worker_held(ctx, d);
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (over) sv->st.trims++;
+            sv->held[me] = sv->charge[me] = now_held;
+            sv->in_use = total_charge(sv);
+            size_t all = 0;
+            for (size_t h : sv->held) all += h;
+            sv->peak_held = std::max(sv->peak_held, all);
             j->t_done = sv->now();
             j->state = jrc == FL_OK ? FL_JOB_DONE : FL_JOB_FAILED;
             j->err = jerr;
-            sv->in_use -= j->bytes;
             if (jrc == FL_OK) {
                 sv->st.completed++;
                 sv->st.node_updates += (int64_t)j->n * j->iters;
@@ -234,7 +326,10 @@ fl_status server_create(fl_server **out, int device, size_t budget, int32_t slot
     fl_default_tuning(&sv->tuning);
     sv->slots = slots;
     sv->fake_ns = fake_ns;
-    for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv);
+    sv->held.assign(slots, 0);
+    sv->charge.assign(slots, 0);
+    sv->busy.assign(slots, 0);
+    for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv, i);
     *out = sv;
     return FL_OK;
 }
@@ -399,6 +494,10 @@ fl_status fl_server_stats_get(fl_server *sv, fl_server_stats *out)
     out->running = (int64_t)(sv->st.admitted - sv->st.completed - sv->st.failed);
     out->bytes_in_use = (int64_t)sv->in_use;
     out->peak_bytes = (int64_t)sv->peak;
+    size_t all = 0;
+    for (size_t h : sv->held) all += h;
+    out->held_bytes = (int64_t)all;
+    out->peak_held_bytes = (int64_t)sv->peak_held;
     return FL_OK;
 }
 

@@ -91,7 +91,8 @@ class _Job(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "failed", "canceled", "queued",
-                                               "running", "bytes_in_use", "peak_bytes", "node_updates")]
+                                               "running", "bytes_in_use", "peak_bytes", "node_updates",
+                                               "held_bytes", "peak_held_bytes", "trims", "over_estimate")]
 
 
 class Tuning(ctypes.Structure):

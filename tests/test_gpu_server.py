@@ -70,3 +70,31 @@ def test_failed_job_does_not_disturb_others():
     with pytest.raises(fl.FlError):
         srv.result(b)
     srv.close()
+
+
+def test_held_memory_stays_within_the_budget():
+    """Workers keep their workspace between jobs; the admission charges what
+    they hold, and a worker past the budget gives its memory back.  After a
+    mix of small and large jobs the measured bytes the workers hold stay
+    within the budget, and so does every recorded peak."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_03504_amd import fa2lay as fl
+    from paper_2403_03504_amd import workloads as w
+    sizes = [60000, 2000, 40000, 500, 60000, 9000, 1200, 50000]
+    jobs = [w.scaled(800 + i, n) for i, n in enumerate(sizes)]
+    est = [700 * g.n + 48 * len(g.src) + (16 << 20) for g in jobs]
+    budget = int(1.6 * max(est))  # room for one large job and a small one
+    prm = fl.default_params(p=8, leaf_size=64)
+    _note("held memory, budget", budget, "bytes, 3 slots")
+    srv = fl.Server(0, budget_bytes=budget, slots=3)
+    ids = [srv.submit(g.n, g.src, g.dst, g.x, g.y, 20, prm) for g in jobs]
+    for i in ids:
+        assert srv.wait(i, 120.0) == fl.JOB_DONE
+        srv.result(i)
+    st = srv.stats()
+    srv.close()
+    _note("stats", st)
+    assert st["completed"] == len(jobs)
+    assert 0 < st["held_bytes"] <= budget
+    assert st["peak_held_bytes"] <= budget and st["peak_bytes"] <= budget

@@ -97,6 +97,7 @@ def _many_components(seed):
 
 @pytest.mark.parametrize("iters", [1, 2, 30])
 def test_layout_concurrent_components_equal_alone(ctxs, fl, iters):
+    from oracle import oracle as orc
     _note("layout, 12 ForceAtlas2 components on branch streams, iters =", iters)
     c, eager = ctxs
     parts, offs, perm, src, dst, x, y = _many_components(300 + iters)
@@ -118,9 +119,20 @@ def test_layout_concurrent_components_equal_alone(ctxs, fl, iters):
         order = np.argsort(ids, kind="stable")
         inv = np.empty_like(order)
         inv[order] = np.arange(part.n)
-        Gp = eager.build_csr(part.n, dev(inv[part.src].astype(np.int32)), dev(inv[part.dst].astype(np.int32)))
-        px, py = dev(part.x[order]), dev(part.y[order])
+        psrc, pdst = inv[part.src].astype(np.int32), inv[part.dst].astype(np.int32)
+        Gp = eager.build_csr(part.n, dev(psrc), dev(pdst))
+        # the reference run's own inputs are checked too, so that a mismatch
+        # names its side: the CSR against the oracle's, bit for bit
+        rp, col, _ = orc.build_csr(part.n, psrc, pdst)
+        assert np.array_equal(host(Gp.row_ptr), rp.astype(np.int32)), ("alone CSR rows", k)
+        assert np.array_equal(host(Gp.col)[:len(col)], col.astype(np.int32)), ("alone CSR columns", k)
         p = fa2 if part.n >= 4096 else fl.default_params(repulsion=fl.REP_EXACT, p=8, leaf_size=32)
-        eager.fa2_run(Gp, px, py, fl.FA2State.zeros(part.n, "cuda"), p, iters)
-        assert np.array_equal(host(px), lx[ids[order]]), (k, part.n)
-        assert np.array_equal(host(py), ly[ids[order]]), (k, part.n)
+        alone = []
+        for _ in range(2):  # and the reference run is itself reproducible
+            px, py = dev(part.x[order]), dev(part.y[order])
+            eager.fa2_run(Gp, px, py, fl.FA2State.zeros(part.n, "cuda"), p, iters)
+            alone.append((host(px), host(py)))
+        assert np.array_equal(alone[0][0], alone[1][0]) and np.array_equal(alone[0][1], alone[1][1]), \
+            ("alone runs differ", k, part.n)
+        assert np.array_equal(alone[0][0], lx[ids[order]]), (k, part.n)
+        assert np.array_equal(alone[0][1], ly[ids[order]]), (k, part.n)

@@ -2,10 +2,13 @@
 launch configuration bench.py times (FMM p = 8, leaf <= 64).
 
 Integer work (CSR, Morton keys, tree) is compared in full against the oracle;
-forces on a sampled node subset, each computed by the oracle as the exact FP64
-sum over all 2M sources.  Gate: relative repulsion error <= 1e-3 (FMM) and
-<= 1e-5 (exact-direct), also after 60 iterations, when hubs have pulled their
-neighbours into dense clusters.
+forces on a sampled node subset (1,500 uniform draws plus the 20 heaviest
+hubs), each computed by the oracle as the exact FP64 sum over all 2M sources.
+Gates: relative repulsion error <= 1e-3 (FMM) and <= 1e-5 (exact-direct)
+norm-wise; per node (against max(|F_i|, median |F|)) the FMM within 1e-4 of
+the oracle's own FP64 FMM and within 1e-3 (99th percentile) and 1e-2 (worst)
+of the exact sum, the exact-direct within 1e-4; also after 60 iterations,
+when hubs have pulled their neighbours into dense clusters.
 """
 import sys
 
@@ -59,7 +62,7 @@ def test_fullsize_morton_and_tree_bit_exact(big, orc):
 
 
 @pytest.mark.parametrize("iters", [0, 60])
-def test_fullsize_repulsion_sampled(big, orc, iters):
+def test_fullsize_repulsion_sampled(big, orc, node_err, iters):
     fl, ctx, g, G = big
     _note("2M repulsion after", iters, "iterations")
     x, y = torch.from_numpy(g.x).cuda(), torch.from_numpy(g.y).cuda()
@@ -72,16 +75,29 @@ def test_fullsize_repulsion_sampled(big, orc, iters):
     xs, ys = x.cpu().numpy(), y.cpu().numpy()
     m = G.deg.cpu().numpy() + 1.0
     rng = np.random.default_rng(99 + iters)
-    tg = np.sort(rng.choice(g.n, 1500, replace=False))
+    # a uniform sample holds no hub in expectation (500 of 2M nodes), yet the
+    # hubs carry the largest forces: the 20 heaviest nodes join the sample
+    hubs = np.argsort(-m, kind="stable")[:20]
+    tg = np.unique(np.concatenate([rng.choice(g.n, 1500, replace=False), hubs]))
     ex, ey = orc.repulsion_exact(xs, ys, m, targets=tg)
-    e_fmm = orc.rel_err(fmm["frx"].cpu().numpy()[tg], fmm["fry"].cpu().numpy()[tg], ex, ey)
-    e_dir = orc.rel_err(dirr["frx"].cpu().numpy()[tg], dirr["fry"].cpu().numpy()[tg], ex, ey)
+    fx, fy = fmm["frx"].cpu().numpy()[tg], fmm["fry"].cpu().numpy()[tg]
+    dx, dy = dirr["frx"].cpu().numpy()[tg], dirr["fry"].cpu().numpy()[tg]
+    e_fmm = orc.rel_err(fx, fy, ex, ey)
+    e_dir = orc.rel_err(dx, dy, ex, ey)
     st = ctx.fmm_stats()
     _note("  fmm err", e_fmm, "direct err", e_dir, "cells", st["cells"], "max level", st["max_level"],
           "W/X entries", st["w_entries"])
     assert e_fmm <= 1e-3
     assert e_dir <= 1e-5
-    # per-node errors (reported, not gated: repulsion nearly cancels near the centre)
-    fn = np.hypot(ex, ey)
-    rel = np.hypot(fmm["frx"].cpu().numpy()[tg] - ex, fmm["fry"].cpu().numpy()[tg] - ey) / np.maximum(fn, 1e-300)
-    _note("  per-node rel err p50/p99/max", np.percentile(rel, 50), np.percentile(rel, 99), rel.max())
+    # per node, against max(|F_i|, median |F|) over the sample: the oracle's
+    # own FMM (same tree, lists and operators, FP64) within FP32 rounding,
+    # the exact sum within 1e-3 at the 99th percentile and 1e-2 at worst
+    ox, oy = orc.repulsion_fmm(xs, ys, m, 1.0, 8, 64, 16)
+    n_orc = node_err(fx, fy, ox[tg], oy[tg])
+    n_fmm, n_dir = node_err(fx, fy, ex, ey), node_err(dx, dy, ex, ey)
+    is_hub = np.isin(tg, hubs)
+    _note("  per-node fmm p50/p99/max", np.percentile(n_fmm, 50), np.percentile(n_fmm, 99), n_fmm.max(),
+          "hubs max", n_fmm[is_hub].max(), "direct max", n_dir.max(), "vs oracle fmm max", n_orc.max())
+    assert n_orc.max() <= 1e-4
+    assert np.percentile(n_fmm, 99) <= 1e-3 and n_fmm.max() <= 1e-2
+    assert n_dir.max() <= 1e-4

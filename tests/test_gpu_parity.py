@@ -172,9 +172,10 @@ def _graph_case(name):
     raise ValueError(name)
 
 
-def test_exact_repulsion_parity(ctx, fl, orc):
+def test_exact_repulsion_parity(ctx, fl, orc, node_err):
     # FP32 pair terms with per-tile FP32 sums and FP64 accumulation: the
-    # norm-wise error is a few ulp of the largest terms, far below 1e-5
+    # norm-wise error is a few ulp of the largest terms, far below 1e-5; per
+    # node (against max(|F_i|, median |F|)) below 1e-4
     _note("exact repulsion plain_2k")
     g = _graph_case("plain_2k")
     G = gpu_graph(ctx, g)
@@ -182,7 +183,11 @@ def test_exact_repulsion_parity(ctx, fl, orc):
     out = ctx.fa2_forces(G, dev(g.x), dev(g.y), prm)
     rp, col, deg = orc.build_csr(g.n, g.src, g.dst)
     fx, fy = orc.repulsion_exact(g.x, g.y, orc.masses(deg))
-    assert orc.rel_err(host(out["frx"]), host(out["fry"]), fx, fy) < 1e-5
+    gx, gy = host(out["frx"]), host(out["fry"])
+    ne = node_err(gx, gy, fx, fy)
+    _note("  norm-wise", orc.rel_err(gx, gy, fx, fy), "per node p99/max", np.percentile(ne, 99), ne.max())
+    assert orc.rel_err(gx, gy, fx, fy) < 1e-5
+    assert ne.max() < 1e-4
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
@@ -205,11 +210,17 @@ def test_attraction_gravity_parity(ctx, fl, orc, mode):
                                            ("duplicates", 6_000, 8, 8), ("clustered", 10_000, 64, 16),
                                            ("clustered", 12_000, 1, 8), ("uniform", 15_000, 150, 8),
                                            ("clustered", 20_000, 300, 6)])
-def test_fmm_repulsion_parity(ctx, fl, orc, kind, n, leaf, p):
+def test_fmm_repulsion_parity(ctx, fl, orc, node_err, kind, n, leaf, p):
     # Same tree, lists and operators as the FP64 oracle FMM, so the difference
-    # is FP32 rounding (tolerance 2e-5); against the exact sum the FMM's own
-    # truncation error must stay within 1e-3 at p >= 8.  The leaf sizes give
-    # the near field every lane-group shape (one target per leaf up to
+    # is FP32 rounding: norm-wise 2e-5, and per node (against max(|F_i|,
+    # median |F|)) 1e-4 -- a list entry missing or wrong on either side moves
+    # the nodes it touches by O(1).  Against the exact sum the GPU's error is
+    # the oracle FMM's own truncation error plus that rounding, at every p; at
+    # p >= 8 it is within 1e-3 norm-wise and, per node, 1e-3 at the 99th
+    # percentile and 1e-2 at worst (GR87's worst case for one well-separated
+    # pair of cells: source radius w/sqrt(2) at centre distance >= 2w, so
+    # c = 1.83 and (1/c)^8 = 7.9e-3 of that pair's force).  The leaf sizes
+    # give the near field every lane-group shape (one target per leaf up to
     # leaves cut into several 64-target chunks).
     _note("fmm", kind, n, leaf, p)
     x, y = _positions(kind, n, 17)
@@ -224,10 +235,18 @@ def test_fmm_repulsion_parity(ctx, fl, orc, kind, n, leaf, p):
     ex, ey = orc.repulsion_exact(x, y, m)
     e_orc = orc.rel_err(gx, gy, ox, oy)
     e_exact = orc.rel_err(gx, gy, ex, ey)
-    _note("  err vs oracle fmm", e_orc, "vs exact", e_exact, "oracle vs exact", orc.rel_err(ox, oy, ex, ey))
+    e_oe = orc.rel_err(ox, oy, ex, ey)
+    n_orc = node_err(gx, gy, ox, oy)
+    n_exact = node_err(gx, gy, ex, ey)
+    _note("  err vs oracle fmm", e_orc, "vs exact", e_exact, "oracle vs exact", e_oe)
+    _note("  per node vs oracle fmm p99/max", np.percentile(n_orc, 99), n_orc.max(),
+          "vs exact p99/max", np.percentile(n_exact, 99), n_exact.max())
     assert e_orc < 2e-5
+    assert n_orc.max() < 1e-4
+    assert e_exact <= e_oe + 2e-5
     if p >= 8:
         assert e_exact < 1e-3
+        assert np.percentile(n_exact, 99) <= 1e-3 and n_exact.max() <= 1e-2
     st = ctx.fmm_stats()
     assert st["cells"] > 0 and st["leaves"] > 0
 
@@ -243,16 +262,30 @@ def test_fmm_single_leaf_equals_exact(ctx, fl, orc):
     assert orc.rel_err(host(out["frx"]), host(out["fry"]), ex, ey) < 1e-6
 
 
-@pytest.mark.parametrize("rep", ["exact", "fmm"])
-def test_fa2_step_parity(ctx, fl, orc, rep):
+# step-size and force-model variants: the defaults, ForceAtlas2's own
+# mass-weighted swing with halved traction, and non-default constants (a
+# small rise cap that binds, a large ks with a tight ksmax cap) with the
+# other gravity forms
+STEP_VARIANTS = {
+    "default": {},
+    "swing_fa2": dict(swing_mode=1),
+    "constants": dict(swing_mode=1, tau=0.7, ks=0.35, ksmax=0.05, max_rise=0.1, gravity_mode=1, kg=0.4),
+    "unit_gravity": dict(tau=2.5, ks=0.02, ksmax=50.0, max_rise=2.0, gravity_mode=2, kr=1.7, ka=0.6),
+}
+
+
+@pytest.mark.parametrize("rep,variant", [("exact", "default"), ("fmm", "default"), ("exact", "swing_fa2"),
+                                         ("fmm", "constants"), ("exact", "unit_gravity")])
+def test_fa2_step_parity(ctx, fl, orc, node_err, rep, variant):
     """One iteration from identical state: forces, swing/traction, speed and
     the move.  The update is checked given the GPU's own FP32 forces, so the
     comparison isolates the step logic (FP64 on both sides)."""
-    _note("fa2 step", rep)
+    _note("fa2 step", rep, variant)
     g = _graph_case("hubs_20k")
     G = gpu_graph(ctx, g)
-    prm = fl.default_params(repulsion=fl.REP_EXACT if rep == "exact" else fl.REP_FMM, p=12, leaf_size=32)
-    oprm = orc.FA2Params(repulsion="exact")
+    kw = STEP_VARIANTS[variant]
+    prm = fl.default_params(repulsion=fl.REP_EXACT if rep == "exact" else fl.REP_FMM, p=12, leaf_size=32, **kw)
+    oprm = orc.FA2Params(repulsion="exact", **kw)
     rp, col, deg = orc.build_csr(g.n, g.src, g.dst)
     x, y = dev(g.x), dev(g.y)
     st = fl.FA2State.zeros(g.n, "cuda")
@@ -264,8 +297,10 @@ def test_fa2_step_parity(ctx, fl, orc, rep):
         F_x, F_y = host(st.fx_prev), host(st.fy_prev)
         ref = orc.fa2_step(rp, col, deg, xs, ys, fpx, fpy, s_prev, it, oprm)
         e = orc.rel_err(F_x, F_y, ref["fx"], ref["fy"])
-        _note("  it", it, "force err", e)
+        ne = node_err(F_x, F_y, ref["fx"], ref["fy"])
+        _note("  it", it, "force err", e, "per node p99/max", np.percentile(ne, 99), ne.max())
         assert e < (1e-5 if rep == "exact" else 1e-4)
+        assert ne.max() < (1e-4 if rep == "exact" else 1e-3)
         given = orc.fa2_step(rp, col, deg, xs, ys, fpx, fpy, s_prev, it, oprm, given_forces=(F_x, F_y))
         assert abs(swg - given["swg"]) <= 1e-9 * given["swg"]
         assert abs(tra - given["tra"]) <= 1e-9 * given["tra"]
@@ -276,6 +311,41 @@ def test_fa2_step_parity(ctx, fl, orc, rep):
         # continue both sides from the GPU state (the iteration is chaotic)
         xs, ys = gx.astype(np.float64), gy.astype(np.float64)
         fpx, fpy, s_prev = F_x.astype(np.float64), F_y.astype(np.float64), sp
+
+
+def test_plain_2k_run_gate(ctx, fl, orc, node_err):
+    """The 2,000-node exact-repulsion workload run for 100 iterations (graph
+    replay between the checkpoints); at t = 0, 1, 50 and 99 one step from the
+    GPU's own state is compared with the FP64 oracle's step from the same
+    state: total force norm-wise within 1e-5 and per node within 1e-4,
+    swing, traction and s_G within 1e-9, positions within 1e-6 (1 + |p|)."""
+    g = _graph_case("plain_2k")
+    G = gpu_graph(ctx, g)
+    prm = fl.default_params(repulsion=fl.REP_EXACT)
+    oprm = orc.FA2Params(repulsion="exact")
+    rp, col, deg = orc.build_csr(g.n, g.src, g.dst)
+    x, y = dev(g.x), dev(g.y)
+    st = fl.FA2State.zeros(g.n, "cuda")
+    for t in (0, 1, 50, 99):
+        if t > st.iter:
+            ctx.fa2_run(G, x, y, st, prm, t - st.iter)
+        _note("plain_2k gate, t =", t)
+        xs, ys = host(x).astype(np.float64), host(y).astype(np.float64)
+        fpx, fpy = host(st.fx_prev).astype(np.float64), host(st.fy_prev).astype(np.float64)
+        s_prev = float(host(st.scalars)[0])
+        swg, tra, sp = ctx.fa2_step(G, x, y, st, prm)
+        F_x, F_y = host(st.fx_prev), host(st.fy_prev)
+        ref = orc.fa2_step(rp, col, deg, xs, ys, fpx, fpy, s_prev, t, oprm)
+        e = orc.rel_err(F_x, F_y, ref["fx"], ref["fy"])
+        ne = node_err(F_x, F_y, ref["fx"], ref["fy"])
+        _note("  force err", e, "per node p99/max", np.percentile(ne, 99), ne.max())
+        assert e < 1e-5 and ne.max() < 1e-4
+        given = orc.fa2_step(rp, col, deg, xs, ys, fpx, fpy, s_prev, t, oprm, given_forces=(F_x, F_y))
+        for a, b in ((swg, given["swg"]), (tra, given["tra"]), (sp, given["speed"])):
+            assert abs(a - b) <= 1e-9 * abs(b)
+        gx, gy = host(x), host(y)
+        assert np.all(np.abs(gx - given["x"]) <= 1e-6 * (1 + np.abs(given["x"])))
+        assert np.all(np.abs(gy - given["y"]) <= 1e-6 * (1 + np.abs(given["y"])))
 
 
 def test_run_is_deterministic(ctx, fl):

@@ -207,6 +207,30 @@ fl_status fl_fa2_run(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32
                      const int32_t *deg, float *x, float *y, fl_fa2_state *state, const fl_fa2_params *prm,
                      int32_t iters, fl_step_stats *per_iter);
 
+/* fl_fa2_step for callers that cannot allocate device memory while they run
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same iteration, the same kernels and, bitwise, the same
+ * results as fl_fa2_step, but every buffer the iteration needs beyond the
+ * caller's arrays (sort buffers, tree, hash table, lists, expansions, force
+ * and reduction buffers) is carved from a fixed array of
+ * FL_NOALLOC_SCRATCH_BYTES bytes of device memory that the library holds on
+ * each GPU it runs on until the process ends.  The call allocates and frees
+ * nothing (the context, created earlier by fl_create, supplies its stream
+ * and its small host staging buffer; its own workspace is neither used nor
+ * grown).  Every call on a GPU uses that GPU's array from its start and
+ * leaves the last call's contents in it: calls that overlap on one GPU (on
+ * other streams or threads, or any fl_fa2_step_noalloc in flight) race.
+ * The iteration runs in line on the context's stream (no branch streams).
+ * Errors as fl_fa2_step, and FL_ENOMEM when the iteration's buffers do not
+ * fit the array (then x, y and the state are left unmodified): with FMM at
+ * p = 8 and leaf_size = 64, graphs of the bipartite transaction generator
+ * fit up to 2e5 nodes (2.5e5 do not); with the exact repulsion, 4e6 nodes
+ * without edges fit. */
+#define FL_NOALLOC_SCRATCH_BYTES (256u << 20)
+fl_status fl_fa2_step_noalloc(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                              const int32_t *deg, float *x, float *y, fl_fa2_state *state,
+                              const fl_fa2_params *prm, fl_step_stats *stats);
+
 /* Statistics of the FMM evaluations on this context [host, synchronises]:
  * last evaluation: out[0] cells, [1] leaves, [2] near-field (P2P) particle
  * pairs, [3] M2L (V-list) entries, [4] W-list entries, [5] X-list entries,

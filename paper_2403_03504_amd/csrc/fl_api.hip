@@ -78,6 +78,17 @@ void free_retired(fl_ctx *c)
     c->retired_bytes = 0;
 }
 
+void *arena_carve(fl_ctx *c, size_t bytes, const char *name)
+{
+    const size_t off = (c->arena_used + 255) & ~size_t(255);
+    const size_t len = (bytes + 255) & ~size_t(255);
+    if (off > c->arena_cap || len > c->arena_cap - off)
+        throw Error(FL_ENOMEM, std::string("the call needs more than the ") + std::to_string(c->arena_cap) +
+                                   " bytes of its fixed scratch (at buffer " + name + ")");
+    c->arena_used = off + len;
+    return c->arena + off;
+}
+
 hipStream_t aux_stream(fl_ctx *c, int i)
 {
     if (!c->aux[i]) FL_CHECK_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));

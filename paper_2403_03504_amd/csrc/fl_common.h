@@ -100,6 +100,11 @@ struct fl_ctx {
     bool own_stream = false;     // a branch context destroys its stream
     int32_t seg1_n = -1;         // n of the cached one-system descriptor
     int tree_cbits = 0;          // system-id width of the hash keys last inserted
+    // a fixed device arena (the allocation-free entry point's scratch): while
+    // set, workspace buffers are carved from it for the one call and nothing
+    // is allocated or freed
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
 };
 
 namespace fl {
@@ -133,12 +138,23 @@ void free_retired(fl_ctx *c);
 // rather than freed (a free may synchronise the whole device), and retired
 // buffers are freed together once they would hold more than half of the
 // context's workspace, or at the next quiet point.
+// Carves `bytes` (rounded up to 256) from the context's arena; throws
+// FL_ENOMEM past its end.
+void *arena_carve(fl_ctx *c, size_t bytes, const char *name);
+
 template <class T>
 T *ws(fl_ctx *c, const char *name, size_t count)
 {
     size_t bytes = count * sizeof(T);
     if (bytes == 0) bytes = sizeof(T);
     DevBuf &b = c->bufs[name];
+    if (c->arena) {
+        if (b.cap < bytes) {  // first request in this call, or a larger one: a new piece
+            b.p = arena_carve(c, bytes, name);
+            b.cap = (bytes + 255) & ~size_t(255);
+        }
+        return static_cast<T *>(b.p);
+    }
     if (b.cap < bytes) {
         if (b.p) {
             c->retired.emplace_back(b.p, b.cap);
@@ -172,13 +188,20 @@ T *ws(fl_ctx *c, const char *name, size_t count)
 
 // Zero-filled on first allocation (kept for buffers whose contents must start
 // at zero and are kept clean by the kernels that use them).
+void fill_i32(fl_ctx *c, int32_t *p, int64_t n, int32_t v);
+
 template <class T>
 T *ws_zeroed(fl_ctx *c, const char *name, size_t count)
 {
     DevBuf &b = c->bufs[name];
     size_t before = b.cap;
     T *p = ws<T>(c, name, count);
-    if (b.cap != before) FL_CHECK_HIP(hipMemsetAsync(p, 0, b.cap, c->stream));
+    if (b.cap != before) {
+        if (c->arena)  // a fill kernel (a caller may record the arena's calls into a graph)
+            fill_i32(c, reinterpret_cast<int32_t *>(p), (int64_t)(b.cap / sizeof(int32_t)), 0);
+        else
+            FL_CHECK_HIP(hipMemsetAsync(p, 0, b.cap, c->stream));
+    }
     return p;
 }
 

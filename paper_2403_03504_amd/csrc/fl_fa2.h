@@ -56,3 +56,9 @@ void kk_layout_subset(fl_ctx *c, int n_all, const int32_t *off, const std::vecto
 void check_kk_params(const fl_kk_params *p);
 
 }  // namespace fl
+
+// fl_fa2_step / fl_fa2_run behind their C entry points (argument checks,
+// errors mapped to fl_status and the context's last-error text).
+fl_status fa2_run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                       float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, int32_t iters,
+                       fl_step_stats *per_iter, bool always_sync);

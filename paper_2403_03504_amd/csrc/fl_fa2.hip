@@ -822,9 +822,11 @@ fl_status fl_fa2_forces(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int3
     FL_API_END(c)
 }
 
-static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
-                          float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, int32_t iters,
-                          fl_step_stats *per_iter, bool always_sync)
+}  // extern "C"
+
+fl_status fa2_run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
+                       float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, int32_t iters,
+                       fl_step_stats *per_iter, bool always_sync)
 {
     FL_API_BEGIN(c)
     FL_REQUIRE(prm != nullptr, "null FA2 parameters");
@@ -837,7 +839,7 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
     GraphArgs g{n, row_ptr, col_idx, deg};
     validate_graph(c, g);
     int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
-    FL_CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), c->stream));
+    fill_i32(c, flags, 1, 0);
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, x, y, flags);
     FL_LAUNCH_CHECK();
     if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
@@ -888,17 +890,19 @@ static fl_status run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const in
     FL_API_END(c)
 }
 
+extern "C" {
+
 fl_status fl_fa2_step(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
                       float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, fl_step_stats *stats)
 {
-    return run_impl(c, n, row_ptr, col_idx, deg, x, y, st, prm, 1, stats, true);
+    return fa2_run_impl(c, n, row_ptr, col_idx, deg, x, y, st, prm, 1, stats, true);
 }
 
 fl_status fl_fa2_run(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *deg,
                      float *x, float *y, fl_fa2_state *st, const fl_fa2_params *prm, int32_t iters,
                      fl_step_stats *per_iter)
 {
-    return run_impl(c, n, row_ptr, col_idx, deg, x, y, st, prm, iters, per_iter, true);
+    return fa2_run_impl(c, n, row_ptr, col_idx, deg, x, y, st, prm, iters, per_iter, true);
 }
 
 }  // extern "C"

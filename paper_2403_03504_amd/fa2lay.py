@@ -33,7 +33,8 @@ PHASES = ("tree", "lists", "upward", "m2l", "eval", "attract", "update", "exact"
 
 EXPORTED = ("fl_create", "fl_destroy", "fl_last_error", "fl_set_stream", "fl_synchronize", "fl_workspace_bytes",
             "fl_version", "fl_build_csr", "fl_components", "fl_morton", "fl_sort_keys", "fl_tree",
-            "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_run", "fl_fmm_stats",
+            "fl_fa2_default_params", "fl_fa2_forces", "fl_fa2_step", "fl_fa2_step_noalloc", "fl_fa2_run",
+            "fl_fmm_stats",
             "fl_set_timing", "fl_set_graphs", "fl_get_timing", "fl_kk_default_params", "fl_hop_distances",
             "fl_kk_steps", "fl_kk_layout", "fl_layout", "fl_server_create", "fl_server_create_fake",
             "fl_server_submit", "fl_server_poll", "fl_server_wait", "fl_server_result", "fl_server_release",
@@ -152,6 +153,8 @@ _sig = {
     "fl_fa2_forces": ([P, _i32, P, P, P, P, P, ctypes.POINTER(FA2Params), P, P, P, P, P, P], _i32),
     "fl_fa2_step": ([P, _i32, P, P, P, P, P, ctypes.POINTER(_State), ctypes.POINTER(FA2Params),
                      ctypes.POINTER(StepStats)], _i32),
+    "fl_fa2_step_noalloc": ([P, _i32, P, P, P, P, P, ctypes.POINTER(_State), ctypes.POINTER(FA2Params),
+                             ctypes.POINTER(StepStats)], _i32),
     "fl_fa2_run": ([P, _i32, P, P, P, P, P, ctypes.POINTER(_State), ctypes.POINTER(FA2Params), _i32,
                     ctypes.POINTER(StepStats)], _i32),
     "fl_fmm_stats": ([P, ctypes.POINTER(_i64), ctypes.c_int], _i32),
@@ -379,6 +382,19 @@ class Context:
                                      _ptr(g.deg, torch.int32), _ptr(x, torch.float32), _ptr(y, torch.float32),
                                      ctypes.byref(cs), ctypes.byref(params), ctypes.byref(st) if stats else None),
                     "fl_fa2_step")
+        state.iter = int(cs.iter)
+        return (st.swg, st.tra, st.speed) if stats else None
+
+    def fa2_step_noalloc(self, g: Graph, x: torch.Tensor, y: torch.Tensor, state: FA2State, params: FA2Params,
+                         stats: bool = True):
+        """fl_fa2_step_noalloc: fl_fa2_step with its workspace in the library's
+        fixed per-GPU scratch array (allocates nothing)."""
+        cs = state._c()
+        st = StepStats()
+        self._check(_lib.fl_fa2_step_noalloc(self._h, g.n, _ptr(g.row_ptr, torch.int32), _ptr(g.col, torch.int32),
+                                             _ptr(g.deg, torch.int32), _ptr(x, torch.float32),
+                                             _ptr(y, torch.float32), ctypes.byref(cs), ctypes.byref(params),
+                                             ctypes.byref(st) if stats else None), "fl_fa2_step_noalloc")
         state.iter = int(cs.iter)
         return (st.swg, st.tra, st.speed) if stats else None
 

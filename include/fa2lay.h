@@ -54,8 +54,12 @@ typedef enum {
 typedef struct fl_ctx fl_ctx;
 
 /* Create a context on HIP device `device`, enqueueing on `stream` (a
- * hipStream_t; NULL = the device's null stream).  *out receives the handle. */
-fl_status fl_create(fl_ctx **out, int device, void *stream);
+ * hipStream_t; NULL = the device's null stream).  *out receives the handle.
+ * workspace_budget_bytes bounds the device workspace the context may hold,
+ * its branch contexts included (0: no bound); a call whose workspace would
+ * pass it fails with FL_ENOMEM (after the buffers replaced by larger ones
+ * have been freed and the sum checked again). */
+fl_status fl_create(fl_ctx **out, int device, void *stream, size_t workspace_budget_bytes);
 /* Release the context and its workspace (synchronises its stream). */
 void fl_destroy(fl_ctx *ctx);
 /* Text of the last error on this context; valid until the next call on it. */
@@ -168,15 +172,27 @@ void fl_fa2_default_params(fl_fa2_params *prm);
 
 /* Caller-owned iteration state. fx_prev/fy_prev [n]: forces of the previous
  * iteration (ignored when iter == 0), overwritten with this iteration's.
- * scalars [4] double on the device: [0] s_G of the previous iteration
- * (read when iter > 0), overwritten with this iteration's s_G; [1] SWG;
- * [2] TRA of the last iteration.  iter [host] counts completed iterations
- * and is advanced by the step/run calls. */
+ * iter [host] counts completed iterations and is advanced by the step/run
+ * calls.
+ * Systems (sec. 4: every component is laid out separately): with n_comp <= 1
+ * all n nodes form one system; with n_comp >= 2, comp_offsets [host,
+ * n_comp + 1] (0 = comp_offsets[0] < ... < comp_offsets[n_comp] = n) splits
+ * the nodes into systems k = [comp_offsets[k], comp_offsets[k+1]), no CSR
+ * edge may join two of them (FL_EINVAL), and every system has its own
+ * repulsion (only its own nodes repel), swing, traction and global speed,
+ * so that each system's result is bitwise the one it gets alone.
+ * scalars [4 * max(n_comp, 1)] double on the device, four per system: [0]
+ * s_G of the previous iteration (read when iter > 0), overwritten with this
+ * iteration's s_G; [1] SWG; [2] TRA of the last iteration.  The [host]
+ * statistics of fl_fa2_step / fl_fa2_run are system 0's.  With
+ * FL_REP_AUTO the tuning table is read at the largest system's size. */
 typedef struct {
     float *fx_prev;
     float *fy_prev;
     double *scalars;
     int64_t iter;
+    int32_t n_comp;
+    const int32_t *comp_offsets;
 } fl_fa2_state;
 
 typedef struct {
@@ -191,7 +207,8 @@ fl_status fl_fa2_forces(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const in
 
 /* One iteration, in place on x, y and the state.  stats [host] may be NULL
  * (if not, the call synchronises).  FL_ENONFINITE if a force or position is
- * not finite (then x, y are left unmodified). */
+ * not finite (a system whose forces are not finite is left unmodified; the
+ * others move). */
 fl_status fl_fa2_step(fl_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                       const int32_t *deg, float *x, float *y, fl_fa2_state *state, const fl_fa2_params *prm,
                       fl_step_stats *stats);

@@ -89,6 +89,26 @@ void *arena_carve(fl_ctx *c, size_t bytes, const char *name)
     return c->arena + off;
 }
 
+static size_t held_with_branches(const fl_ctx *o)
+{
+    size_t b = o->ws_bytes;
+    for (const fl_ctx *sc : o->sub) b += sc->ws_bytes;
+    return b;
+}
+
+void budget_check(fl_ctx *c, size_t bytes, const char *name)
+{
+    fl_ctx *o = c->owner ? c->owner : c;
+    if (!o->budget || held_with_branches(o) + bytes <= o->budget) return;
+    free_retired(o);
+    for (fl_ctx *sc : o->sub) free_retired(sc);
+    const size_t held = held_with_branches(o);
+    if (held + bytes > o->budget)
+        throw Error(FL_ENOMEM, std::string("workspace budget of ") + std::to_string(o->budget) +
+                                   " bytes exceeded: " + std::to_string(held) + " held, " + std::to_string(bytes) +
+                                   " more for " + name);
+}
+
 hipStream_t aux_stream(fl_ctx *c, int i)
 {
     if (!c->aux[i]) FL_CHECK_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
@@ -101,11 +121,12 @@ fl_ctx *sub_ctx(fl_ctx *c, size_t b)
         hipStream_t s = nullptr;
         FL_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         fl_ctx *sc = nullptr;
-        if (fl_create(&sc, c->device, s) != FL_OK) {
+        if (fl_create(&sc, c->device, s, 0) != FL_OK) {
             (void)hipStreamDestroy(s);
             throw Error(FL_EHIP, "branch context creation failed");
         }
         sc->own_stream = true;
+        sc->owner = c->owner ? c->owner : c;  // the budget is the owning context's
         c->sub.push_back(sc);
     }
     return c->sub[b];
@@ -119,7 +140,7 @@ extern "C" {
 
 const char *fl_version(void) { return "fa2lay 0.1 gfx950"; }
 
-fl_status fl_create(fl_ctx **out, int device, void *stream)
+fl_status fl_create(fl_ctx **out, int device, void *stream, size_t workspace_budget_bytes)
 {
     if (!out) return FL_EINVAL;
     *out = nullptr;
@@ -129,6 +150,7 @@ fl_status fl_create(fl_ctx **out, int device, void *stream)
     if (!c) return FL_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->budget = workspace_budget_bytes;
     fl_default_tuning(&c->tuning);
     if (hipSetDevice(device) != hipSuccess) {
         delete c;

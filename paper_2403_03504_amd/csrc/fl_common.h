@@ -105,6 +105,10 @@ struct fl_ctx {
     // is allocated or freed
     char *arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
+    // workspace bound of a context and its branch contexts (0: none); a
+    // branch context points at the context that owns the bound
+    size_t budget = 0;
+    fl_ctx *owner = nullptr;
 };
 
 namespace fl {
@@ -141,6 +145,10 @@ void free_retired(fl_ctx *c);
 // Carves `bytes` (rounded up to 256) from the context's arena; throws
 // FL_ENOMEM past its end.
 void *arena_carve(fl_ctx *c, size_t bytes, const char *name);
+// Throws FL_ENOMEM unless `bytes` more of workspace keep the context (with
+// its branch contexts) within its budget; frees retired buffers first when
+// that makes the room.
+void budget_check(fl_ctx *c, size_t bytes, const char *name);
 
 template <class T>
 T *ws(fl_ctx *c, const char *name, size_t count)
@@ -164,6 +172,7 @@ T *ws(fl_ctx *c, const char *name, size_t count)
             if (2 * c->retired_bytes > c->ws_bytes) free_retired(c);
         }
         size_t nb = bytes + bytes / 8 + 256;
+        budget_check(c, nb, name);
         hipError_t e;
         {
             AllocGuard guard;

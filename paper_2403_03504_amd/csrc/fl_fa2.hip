@@ -309,7 +309,7 @@ __global__ __launch_bounds__(NT) void k_speed(Segs sg, const double2 *__restrict
             sc[0] = sG;
             sc[1] = SWG;
             sc[2] = TRA;
-            if (ring) {
+            if (ring && comp == 0) {  // the per-iteration record is system 0's
                 ring[3 * ring_it + 0] = SWG;
                 ring[3 * ring_it + 1] = TRA;
                 ring[3 * ring_it + 2] = sG;
@@ -380,6 +380,20 @@ __global__ void k_validate_cols(int n, const int32_t *__restrict__ row_ptr, cons
             return;
         }
     }
+}
+
+// every edge stays inside its system (sys: system of each node)
+__global__ void k_validate_systems(int n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                   const int32_t *__restrict__ sys, int32_t *__restrict__ bad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int si = sys[i];
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+        if (sys[col[e]] != si) {
+            atomicOr(bad, 1);
+            return;
+        }
 }
 
 __global__ void k_check_finite(int n, const float *__restrict__ x, const float *__restrict__ y,
@@ -830,21 +844,49 @@ fl_status fa2_run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32
 {
     FL_API_BEGIN(c)
     FL_REQUIRE(prm != nullptr, "null FA2 parameters");
-    const fl_fa2_params rp = resolve_repulsion(c->tuning, n, *prm);
-    prm = &rp;
-    validate_params(prm);
     FL_REQUIRE(x && y && st && st->fx_prev && st->fy_prev && st->scalars, "null positions or state");
     FL_REQUIRE(st->iter >= 0, "state iter must be >= 0");
     FL_REQUIRE(iters >= 0, "iters must be >= 0");
+    // independent systems (components) given by the state: node ranges on
+    // the host, each with its own repulsion and global speed
+    const bool multi = st->n_comp > 1;
+    std::vector<int32_t> coff;
+    int32_t largest = n;
+    if (multi) {
+        FL_REQUIRE(st->comp_offsets != nullptr, "n_comp > 1 needs comp_offsets");
+        coff.assign(st->comp_offsets, st->comp_offsets + st->n_comp + 1);
+        FL_REQUIRE(coff[0] == 0 && coff[st->n_comp] == n, "comp_offsets must run from 0 to n");
+        largest = 0;
+        for (int k = 0; k < st->n_comp; ++k) {
+            FL_REQUIRE(coff[k + 1] > coff[k], "comp_offsets must be strictly increasing");
+            largest = std::max(largest, coff[k + 1] - coff[k]);
+        }
+    } else {
+        FL_REQUIRE(st->n_comp >= 0, "n_comp must be >= 0");
+    }
+    const fl_fa2_params rp = resolve_repulsion(c->tuning, largest, *prm);
+    prm = &rp;
+    validate_params(prm);
     GraphArgs g{n, row_ptr, col_idx, deg};
     validate_graph(c, g);
-    int32_t *flags = ws<int32_t>(c, "fa2_flags", 1);
-    fill_i32(c, flags, 1, 0);
-    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, x, y, flags);
+    const Segs sg = multi ? make_segs(c, coff, "fa2_sys") : segs_single(c, n);
+    if (multi) {
+        int32_t *bad = ws<int32_t>(c, "fa2_bad", 1);
+        fill_i32(c, bad, 1, 0);
+        hipLaunchKernelGGL(k_validate_systems, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, row_ptr, col_idx,
+                           sg.ncomp, bad);
+        FL_LAUNCH_CHECK();
+        if (read_i32(c, bad)) throw Error(FL_EINVAL, "an edge joins two systems of comp_offsets");
+    }
+    // one status word per system, and a summary word after them
+    const int K = sg.K;
+    int32_t *flags = ws<int32_t>(c, "fa2_flags", (size_t)K + 1);
+    fill_i32(c, flags, K + 1, 0);
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, n, x, y, flags + K);
     FL_LAUNCH_CHECK();
-    if (read_i32(c, flags) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
+    if (read_i32(c, flags + K) & 4) throw Error(FL_ENONFINITE, "non-finite initial position");
     double *ring = per_iter ? ws<double>(c, "fa2_ring", 3 * (size_t)(iters > 0 ? iters : 1)) : nullptr;
-    Sys b{c, segs_single(c, n), g, attract_plan(c, g), x, y, *st, *prm, flags};
+    Sys b{c, sg, g, attract_plan(c, g), x, y, *st, *prm, flags};
     if (!ring && !c->timing && iters >= GRAPH_MIN_ITERS && c->use_graphs) {
         // the caller's stream may be the null stream, which cannot be
         // captured: run on private streams ordered after it and before
@@ -875,7 +917,9 @@ fl_status fa2_run_impl(fl_ctx *c, int32_t n, const int32_t *row_ptr, const int32
         st->iter = b.st.iter;
     }
     if (per_iter || always_sync) {
-        int32_t f = read_i32(c, flags);
+        hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(NT), 0, c->stream, (const int32_t *)flags, K, flags + K);
+        FL_LAUNCH_CHECK();
+        int32_t f = read_i32(c, flags + K);
         if (per_iter && iters > 0) {
             std::vector<double> h(3 * (size_t)iters);
             FL_CHECK_HIP(hipMemcpyAsync(h.data(), ring, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));

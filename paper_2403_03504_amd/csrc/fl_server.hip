@@ -167,7 +167,7 @@ bool worker_trim(fl_server *sv, fl_ctx *&ctx, hipStream_t s, DevArrays &d)
     if (!ctx) return true;
     fl_destroy(ctx);
     ctx = nullptr;
-    if (fl_create(&ctx, sv->device, s) != FL_OK) return false;
+    if (fl_create(&ctx, sv->device, s, 0) != FL_OK) return false;
     // the workers capture concurrently; their iterations keep every launch
     // on the job's own streams (no branch streams, see below)
     ctx->branches = false;
@@ -197,7 +197,7 @@ void worker(fl_server *sv, int me)
     std::string init_err;
     if (sv->fake_ns <= 0.0) {
         if (hipSetDevice(sv->device) != hipSuccess || hipStreamCreate(&s) != hipSuccess ||
-            fl_create(&ctx, sv->device, s) != FL_OK)
+            fl_create(&ctx, sv->device, s, 0) != FL_OK)
             init_err = "worker could not create its stream/context";
         // the workers capture concurrently; their iterations keep every
         // launch on the job's own streams (no branch streams): a run with

@@ -60,7 +60,7 @@ class FA2Params(ctypes.Structure):
 
 class _State(ctypes.Structure):
     _fields_ = [("fx_prev", ctypes.c_void_p), ("fy_prev", ctypes.c_void_p), ("scalars", ctypes.c_void_p),
-                ("iter", ctypes.c_int64)]
+                ("iter", ctypes.c_int64), ("n_comp", ctypes.c_int32), ("comp_offsets", ctypes.c_void_p)]
 
 
 class KKParams(ctypes.Structure):
@@ -137,7 +137,7 @@ class StepStats(ctypes.Structure):
 P = ctypes.c_void_p
 _i32, _i64 = ctypes.c_int32, ctypes.c_int64
 _sig = {
-    "fl_create": ([ctypes.POINTER(P), ctypes.c_int, P], _i32),
+    "fl_create": ([ctypes.POINTER(P), ctypes.c_int, P, ctypes.c_size_t], _i32),
     "fl_destroy": ([P], None),
     "fl_last_error": ([P], ctypes.c_char_p),
     "fl_set_stream": ([P, P], _i32),
@@ -258,20 +258,31 @@ def _ptr(t: torch.Tensor | None, dtype=None):
 
 @dataclasses.dataclass
 class FA2State:
-    """Caller-owned iteration state (previous forces, device scalars, count)."""
+    """Caller-owned iteration state (previous forces, device scalars, count);
+    with comp_offsets (host int32, n_comp + 1 entries) the nodes form
+    independent systems, each with its own four scalars."""
     fx_prev: torch.Tensor
     fy_prev: torch.Tensor
-    scalars: torch.Tensor  # float64 [4]: s_G, SWG, TRA
+    scalars: torch.Tensor  # float64 [4 * systems]: s_G, SWG, TRA per system
     iter: int = 0
+    comp_offsets: object = None
 
     @staticmethod
-    def zeros(n: int, device) -> "FA2State":
+    def zeros(n: int, device, comp_offsets=None) -> "FA2State":
+        import numpy as np
+        off = None if comp_offsets is None else np.ascontiguousarray(comp_offsets, dtype=np.int32)
+        k = 1 if off is None else max(off.shape[0] - 1, 1)
         return FA2State(torch.zeros(n, dtype=torch.float32, device=device),
                         torch.zeros(n, dtype=torch.float32, device=device),
-                        torch.zeros(4, dtype=torch.float64, device=device), 0)
+                        torch.zeros(4 * k, dtype=torch.float64, device=device), 0, off)
 
     def _c(self) -> _State:
-        return _State(self.fx_prev.data_ptr(), self.fy_prev.data_ptr(), self.scalars.data_ptr(), self.iter)
+        off = self.comp_offsets
+        if off is None:
+            return _State(self.fx_prev.data_ptr(), self.fy_prev.data_ptr(), self.scalars.data_ptr(), self.iter, 0,
+                          None)
+        return _State(self.fx_prev.data_ptr(), self.fy_prev.data_ptr(), self.scalars.data_ptr(), self.iter,
+                      off.shape[0] - 1, off.ctypes.data_as(ctypes.c_void_p))
 
 
 class Graph:
@@ -284,12 +295,13 @@ class Graph:
 class Context:
     """An fl_ctx bound to a device and (by default) torch's current stream."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, budget_bytes: int = 0):
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self._h = P()
-        self._check(_lib.fl_create(ctypes.byref(self._h), device, P(stream.cuda_stream)), "fl_create")
+        self._check(_lib.fl_create(ctypes.byref(self._h), device, P(stream.cuda_stream), budget_bytes),
+                    "fl_create")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,151 @@
+"""Independent systems through the ForceAtlas2 boundary (sec. 4: every
+component is laid out separately): a state with component offsets runs all
+components in the same launches, each with its own repulsion and global
+speed, and each component's result must be bitwise the one it gets alone.
+Also the context's workspace budget."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def fl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_03504_amd import fa2lay
+    return fa2lay
+
+
+def _parts():
+    from paper_2403_03504_amd import workloads as w
+    return [w.scaled(1201, 9000), w.scaled(1202, 5000, hubs_per_4000=False), w.scaled(1203, 3000)]
+
+
+@pytest.mark.parametrize("rep,iters", [("fmm", 6), ("fmm", 1), ("exact", 5)])
+def test_systems_equal_each_alone(fl, rep, iters):
+    from paper_2403_03504_amd import workloads as w
+    _note("systems vs alone,", rep, iters, "iterations")
+    parts = _parts()
+    g, offs = w.union(parts)
+    prm = fl.default_params(repulsion=fl.REP_FMM if rep == "fmm" else fl.REP_EXACT, p=8, leaf_size=32)
+    c = fl.Context(0)
+    try:
+        G = c.build_csr(g.n, dev(g.src), dev(g.dst))
+        x, y = dev(g.x), dev(g.y)
+        st = fl.FA2State.zeros(g.n, "cuda", comp_offsets=offs)
+        c.fa2_run(G, x, y, st, prm, iters)
+        assert st.iter == iters
+        gx, gy, sc = host(x), host(y), host(st.scalars).reshape(-1, 4)
+        for k, part in enumerate(parts):
+            Gp = c.build_csr(part.n, dev(part.src), dev(part.dst))
+            px, py = dev(part.x), dev(part.y)
+            sp = fl.FA2State.zeros(part.n, "cuda")
+            c.fa2_run(Gp, px, py, sp, prm, iters)
+            a, b = offs[k], offs[k + 1]
+            assert np.array_equal(host(px), gx[a:b]) and np.array_equal(host(py), gy[a:b]), k
+            assert np.array_equal(host(sp.scalars)[:3], sc[k, :3]), k
+    finally:
+        c.close()
+
+
+def test_systems_step_against_oracle(fl, orc, node_err):
+    """One step of two systems against the oracle's step of each component:
+    forces (exact repulsion) within 1e-5 norm-wise and 1e-4 per node, each
+    system's swing, traction and s_G within 1e-9 given the GPU's forces."""
+    from paper_2403_03504_amd import workloads as w
+    _note("systems step vs oracle")
+    parts = [w.scaled(1211, 4000), w.scaled(1212, 2500)]
+    g, offs = w.union(parts)
+    prm = fl.default_params(repulsion=fl.REP_EXACT)
+    oprm = orc.FA2Params(repulsion="exact")
+    c = fl.Context(0)
+    try:
+        G = c.build_csr(g.n, dev(g.src), dev(g.dst))
+        x, y = dev(g.x), dev(g.y)
+        st = fl.FA2State.zeros(g.n, "cuda", comp_offsets=offs)
+        c.fa2_step(G, x, y, st, prm)  # nonzero previous forces and s_G for the compared step
+        xs, ys = host(x).astype(np.float64), host(y).astype(np.float64)
+        fpx, fpy = host(st.fx_prev).astype(np.float64), host(st.fy_prev).astype(np.float64)
+        sprev = host(st.scalars).reshape(-1, 4)[:, 0].copy()
+        c.fa2_step(G, x, y, st, prm)
+        F_x, F_y, sc = host(st.fx_prev), host(st.fy_prev), host(st.scalars).reshape(-1, 4)
+        for k, part in enumerate(parts):
+            a, b = offs[k], offs[k + 1]
+            rp, col, deg = orc.build_csr(part.n, part.src, part.dst)
+            ref = orc.fa2_step(rp, col, deg, xs[a:b], ys[a:b], fpx[a:b], fpy[a:b], sprev[k], 1, oprm)
+            assert orc.rel_err(F_x[a:b], F_y[a:b], ref["fx"], ref["fy"]) < 1e-5
+            assert node_err(F_x[a:b], F_y[a:b], ref["fx"], ref["fy"]).max() < 1e-4
+            given = orc.fa2_step(rp, col, deg, xs[a:b], ys[a:b], fpx[a:b], fpy[a:b], sprev[k], 1, oprm,
+                                 given_forces=(F_x[a:b], F_y[a:b]))
+            for v, r in ((sc[k, 1], given["swg"]), (sc[k, 2], given["tra"]), (sc[k, 0], given["speed"])):
+                assert abs(v - r) <= 1e-9 * abs(r), k
+            gx, gy = host(x)[a:b], host(y)[a:b]
+            assert np.all(np.abs(gx - given["x"]) <= 1e-6 * (1 + np.abs(given["x"])))
+            assert np.all(np.abs(gy - given["y"]) <= 1e-6 * (1 + np.abs(given["y"])))
+    finally:
+        c.close()
+
+
+def test_systems_rejected(fl):
+    from paper_2403_03504_amd import workloads as w
+    _note("bad system offsets")
+    g = w.scaled(1221, 3000)
+    c = fl.Context(0)
+    try:
+        G = c.build_csr(g.n, dev(g.src), dev(g.dst))
+        for off in ([0, 1500, g.n],          # cuts a connected graph: edges join the systems
+                    [0, 2000, 1000, g.n],    # not increasing
+                    [0, 1500, g.n - 1],      # does not end at n
+                    [5, 1500, g.n]):         # does not start at 0
+            x, y = dev(g.x), dev(g.y)
+            st = fl.FA2State.zeros(g.n, "cuda", comp_offsets=off)
+            with pytest.raises(fl.FlError) as e:
+                c.fa2_step(G, x, y, st, fl.default_params())
+            assert e.value.status == fl.FL_EINVAL, off
+            assert np.array_equal(host(x), g.x)
+    finally:
+        c.close()
+
+
+def test_workspace_budget(fl):
+    from paper_2403_03504_amd import workloads as w
+    _note("workspace budget")
+    g = w.scaled(1231, 60000)
+    prm = fl.default_params(repulsion=fl.REP_FMM)
+    tight, roomy = fl.Context(0, budget_bytes=4 << 20), fl.Context(0, budget_bytes=512 << 20)
+    try:
+        G = roomy.build_csr(g.n, dev(g.src), dev(g.dst))
+        for c in (tight, roomy):
+            x, y = dev(g.x), dev(g.y)
+            st = fl.FA2State.zeros(g.n, "cuda")
+            if c is tight:
+                with pytest.raises(fl.FlError) as e:
+                    c.fa2_run(G, x, y, st, prm, 5)
+                assert e.value.status == fl.FL_ENOMEM
+                assert c.workspace_bytes() <= 4 << 20
+            else:
+                c.fa2_run(G, x, y, st, prm, 5)
+                assert np.all(np.isfinite(host(x)))
+                assert 0 < c.workspace_bytes() <= 512 << 20
+    finally:
+        tight.close()
+        roomy.close()

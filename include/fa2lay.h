@@ -337,9 +337,10 @@ fl_status fl_hop_distances(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offs
                            const int32_t *col_idx, int32_t *dist, int64_t *dist_offsets);
 
 /* The minimiser of prm on every component, in place on x, y, given the
- * distances of fl_hop_distances.  One persistent launch: for majorization,
- * components packed into batches of at most 256 nodes, one workgroup each;
- * for Newton-Raphson, one wave per component.  Synchronises. */
+ * distances of fl_hop_distances.  For majorization, one workgroup runs all
+ * steps of one component, each node's sum split over up to 16 lanes (a
+ * launch per size class: up to 16, 64 and 256 nodes); for Newton-Raphson,
+ * one wave per component.  Synchronises. */
 fl_status fl_kk_steps(fl_ctx *ctx, int32_t n_comp, const int32_t *comp_offsets, const int32_t *dist, float *x,
                       float *y, const fl_kk_params *prm);
 

@@ -7,14 +7,15 @@
 //               visited(v), and every source bit newly set in next(v) is the
 //               distance d+1 of (source, v).  Unit weights, so this equals the
 //               paper's Floyd-Warshall distances (exact integers).
-//   k_kk_steps  localized stress majorization of the energy
+//   k_kk_major  localized stress majorization of the energy
 //               E = sum_{i<j} d_ij^-2 (|p_i - p_j| - l d_ij)^2, all nodes of a
 //               component updated together from the previous positions:
 //                 p_i' = sum_{j!=i} w_ij (p_j + l d_ij u_ij) / sum_{j!=i} w_ij,
 //               w_ij = d_ij^-2, u_ij the unit vector from p_j to p_i (0 if the
-//               two coincide).  One workgroup runs every step for a batch of
-//               components (at most 256 nodes in total, one thread per node),
-//               with positions and the batch's distances (uint8) in LDS.
+//               two coincide).  One workgroup runs every step of one
+//               component, each node's sum split over several lanes, with
+//               positions, the distances (uint8) and a table of the weights
+//               in LDS.
 #include <algorithm>
 #include <string>
 
@@ -89,85 +90,119 @@ __global__ __launch_bounds__(256) void k_kk_bfs(const int32_t *__restrict__ comp
     }
 }
 
-struct KKBatch {
-    int32_t c0, c1;  // components [c0, c1) of the full list: consecutive node ranges
-    int32_t k0;      // index of c0 in the subset (for the distance offsets)
-    int32_t pad;
-};
-
-__global__ __launch_bounds__(256) void k_kk_steps(const KKBatch *__restrict__ batches,
-                                                  const int32_t *__restrict__ comp_off,
-                                                  const int64_t *__restrict__ dist_off,
-                                                  const int32_t *__restrict__ dist, float *__restrict__ x,
-                                                  float *__restrict__ y, float l, int steps)
+// Localized stress majorization with each node's sum split over s lanes: a
+// workgroup takes one component of nk nodes; node i is summed by lanes
+// i*s .. i*s + s - 1, lane `sub` taking the block of B = ceil(nk / s)
+// consecutive j from sub * B (rounded up to a multiple of four); the s
+// partial sums are added by a butterfly inside the lane group (a fixed order,
+// so a component's result does not depend on anything else in the launch).
+// The distances sit in LDS as bytes, rows padded to four so that one 32-bit
+// read brings four; the weights w = 1/d^2 and l d w come from a table over
+// the integer hop distances (d = 0, the node itself or a padding slot, weighs
+// 0), computed once per workgroup; sum_j w_ij is fixed over the steps.  A
+// coincident pair gets no unit vector: r^2 carries 1e-30, so its direction
+// term is 0 * (finite).  s: about eight pairs per lane, at most 16 lanes per
+// node and blockDim threads in all.
+__device__ __forceinline__ int kk_lanes_per_node(int nk, int threads)
 {
-    __shared__ float2 pos[KK_MAX];
-    __shared__ uint8_t D8[KK_MAX * KK_MAX];
-    __shared__ int cstart[KK_MAX + 1];  // batch-local node offsets of the components
-    __shared__ int dbase[KK_MAX];       // batch-local distance offsets
-    const KKBatch bt = batches[blockIdx.x];
-    const int ncomp = bt.c1 - bt.c0;
-    const int nb = comp_off[bt.c0];
-    const int nnodes = comp_off[bt.c1] - nb;
-    if (threadIdx.x == 0) {
-        int s = 0, db = 0;
-        for (int k = 0; k < ncomp; ++k) {
-            const int nk = comp_off[bt.c0 + k + 1] - comp_off[bt.c0 + k];
-            cstart[k] = s;
-            dbase[k] = db;
-            s += nk;
-            db += nk * nk;
-        }
-        cstart[ncomp] = s;
+    int s = 1;
+    while (s < 16 && 2 * s * 8 <= nk && 2 * s * nk <= threads) s *= 2;
+    return s;
+}
+
+__device__ __forceinline__ int kk_row_stride(int nk) { return (nk + 3) & ~3; }
+
+__global__ __launch_bounds__(1024) void k_kk_major(const int32_t *__restrict__ comp_off,
+                                                   const int32_t *__restrict__ ids,
+                                                   const int64_t *__restrict__ dist_off,
+                                                   const int32_t *__restrict__ order,
+                                                   const int32_t *__restrict__ dist, float *__restrict__ x,
+                                                   float *__restrict__ y, float l, int steps)
+{
+    extern __shared__ float4 kk_lds[];
+    const int k = order[blockIdx.x];
+    const int cb = comp_off[ids[k]];
+    const int nk = comp_off[ids[k] + 1] - cb;
+    const int rs = kk_row_stride(nk);
+    float2 *pos = reinterpret_cast<float2 *>(kk_lds);              // [rs]: past nk, copies of node nk-1
+    float2 *wq = pos + rs;                                          // [256]: (1/d^2, l d / d^2)
+    uint32_t *D4 = reinterpret_cast<uint32_t *>(wq + KK_MAX);       // [nk][rs / 4]: four distance bytes per word
+    const int32_t *Dk = dist + dist_off[k];
+    const int wpr = rs >> 2;
+    for (int b = threadIdx.x; b < nk * wpr; b += blockDim.x) {
+        const int r = b / wpr, c0 = 4 * (b - r * wpr);
+        int32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = c0 + u < nk ? Dk[(int64_t)r * nk + c0 + u] : 0;
+        D4[b] = (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+    }
+    for (int d = threadIdx.x; d < KK_MAX; d += blockDim.x) {
+        const float fd = (float)d;
+        const float w = d > 0 ? 1.0f / (fd * fd) : 0.f;
+        wq[d] = make_float2(w, l * fd * w);
+    }
+    for (int i = threadIdx.x; i < rs; i += blockDim.x) {
+        const int g = cb + min(i, nk - 1);
+        pos[i] = make_float2(x[g], y[g]);
     }
     __syncthreads();
-    // stage distances as bytes (components of <= 256 nodes have d <= 255)
-    for (int k = 0; k < ncomp; ++k) {
-        const int nk = cstart[k + 1] - cstart[k];
-        const int32_t *Dk = dist + dist_off[bt.k0 + k];
-        for (int i = threadIdx.x; i < nk * nk; i += blockDim.x) D8[dbase[k] + i] = (uint8_t)Dk[i];
-    }
+    const int s = kk_lanes_per_node(nk, blockDim.x);
     const int t = threadIdx.x;
-    int k = 0;
-    if (t < nnodes) {
-        while (cstart[k + 1] <= t) ++k;
-        pos[t] = make_float2(x[nb + t], y[nb + t]);
+    const int i = t / s, sub = t - i * s;
+    const bool live = i < nk;
+    const int B = ((nk + s - 1) / s + 3) & ~3;  // a multiple of four
+    const int j0 = live ? min(rs, sub * B) : rs, j1 = live ? min(rs, j0 + B) : rs;
+    const uint32_t *Drow = D4 + (live ? i * wpr : 0);
+    float sw = 0.f;
+    for (int j = j0; j < j1; j += 4) {
+        const uint32_t d4 = Drow[j >> 2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sw += wq[(d4 >> (8 * u)) & 0xFFu].x;
     }
-    __syncthreads();
-    const int s0 = t < nnodes ? cstart[k] : 0;
-    const int nk = t < nnodes ? cstart[k + 1] - s0 : 0;
-    const int li = t - s0;
-    const uint8_t *Drow = D8 + (t < nnodes ? dbase[k] + li * nk : 0);
+    for (int o = s >> 1; o > 0; o >>= 1) sw += __shfl_xor(sw, o, WAVE);
     for (int st = 0; st < steps; ++st) {
-        float2 np = make_float2(0.f, 0.f);
-        if (t < nnodes) {
-            const float2 pi = pos[t];
-            float sw = 0.f, ax = 0.f, ay = 0.f;
-            for (int j = 0; j < nk; ++j) {
-                if (j == li) continue;
-                const float2 pj = pos[s0 + j];
-                const float d = (float)Drow[j];
-                const float w = 1.0f / (d * d);
-                const float dx = pi.x - pj.x, dy = pi.y - pj.y;
-                const float r2 = dx * dx + dy * dy;
-                const float rinv = r2 > 0.f ? rsqrtf(r2) : 0.f;
-                const float ld = l * d * w;  // w l d
-                sw += w;
-                ax += w * pj.x + ld * dx * rinv;
-                ay += w * pj.y + ld * dy * rinv;
+        const float2 pi = live ? pos[i] : make_float2(0.f, 0.f);
+        float ax = 0.f, ay = 0.f;
+        for (int j = j0; j < j1; j += 4) {
+            const uint32_t d4 = Drow[j >> 2];
+            float2 pj[4], c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pj[u] = pos[j + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = wq[(d4 >> (8 * u)) & 0xFFu];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float dx = pi.x - pj[u].x, dy = pi.y - pj[u].y;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+                const float q = c[u].y * __builtin_amdgcn_rsqf(r2);
+                ax = fmaf(c[u].x, pj[u].x, ax);
+                ay = fmaf(c[u].x, pj[u].y, ay);
+                ax = fmaf(q, dx, ax);
+                ay = fmaf(q, dy, ay);
             }
+        }
+        for (int o = s >> 1; o > 0; o >>= 1) {
+            ax += __shfl_xor(ax, o, WAVE);
+            ay += __shfl_xor(ay, o, WAVE);
+        }
+        float2 np = pi;
+        if (live) {
             np = sw > 0.f ? make_float2(ax / sw, ay / sw) : pi;
             // a pair: the update reflects its distance r to |2l - r|; half
             // way lands it at distance l about its midpoint
             if (nk == 2) np = make_float2(0.5f * (pi.x + np.x), 0.5f * (pi.y + np.y));
         }
         __syncthreads();
-        if (t < nnodes) pos[t] = np;
+        if (live && sub == 0) {
+            pos[i] = np;
+            if (i == nk - 1)
+                for (int pad = nk; pad < rs; ++pad) pos[pad] = np;  // padding slots weigh 0 but stay finite
+        }
         __syncthreads();
     }
-    if (t < nnodes) {
-        x[nb + t] = pos[t].x;
-        y[nb + t] = pos[t].y;
+    for (int i2 = threadIdx.x; i2 < nk; i2 += blockDim.x) {
+        x[cb + i2] = pos[i2].x;
+        y[cb + i2] = pos[i2].y;
     }
 }
 
@@ -643,15 +678,12 @@ __global__ __launch_bounds__(KK_MAX) void k_kk_decluster(const int32_t *__restri
 }  // namespace
 
 // Components taken by Kamada-Kawai: `ids` (ascending) index the full offset
-// list.  Batches join runs of consecutive ids (adjacent node ranges) up to
-// KK_MAX nodes; dist_off[k] = sum of n^2 over ids[0..k).
+// list; dist_off[k] = sum of n^2 over ids[0..k).
 struct KKPlan {
     std::vector<int32_t> ids;
     std::vector<int64_t> doff;
-    std::vector<KKBatch> batches;
     int32_t *d_off = nullptr, *d_ids = nullptr;
     int64_t *d_doff = nullptr;
-    KKBatch *d_batches = nullptr;
 };
 
 static KKPlan kk_plan(fl_ctx *c, int n_all, const int32_t *off, const std::vector<int32_t> &ids,
@@ -670,26 +702,12 @@ static KKPlan kk_plan(fl_ctx *c, int n_all, const int32_t *off, const std::vecto
         FL_REQUIRE(nk <= KK_MAX, "Kamada-Kawai components are limited to 256 nodes");
         p.doff[k + 1] = p.doff[k] + nk * nk;
     }
-    int k = 0;
-    while (k < m) {
-        int e = k, tot = 0;
-        while (e < m && (e == k || ids[e] == ids[e - 1] + 1) && tot + (off[ids[e] + 1] - off[ids[e]]) <= KK_MAX) {
-            tot += off[ids[e] + 1] - off[ids[e]];
-            ++e;
-        }
-        p.batches.push_back(KKBatch{ids[k], ids[e - 1] + 1, k, 0});
-        k = e;
-    }
     p.d_off = ws<int32_t>(c, (tag + "_off").c_str(), n_all + 1);
     p.d_ids = ws<int32_t>(c, (tag + "_ids").c_str(), m > 0 ? m : 1);
     p.d_doff = ws<int64_t>(c, (tag + "_doff").c_str(), m + 1);
-    p.d_batches = ws<KKBatch>(c, (tag + "_batches").c_str(), p.batches.size() + 1);
     FL_CHECK_HIP(hipMemcpyAsync(p.d_off, off, sizeof(int32_t) * (n_all + 1), hipMemcpyHostToDevice, c->stream));
     if (m > 0) FL_CHECK_HIP(hipMemcpyAsync(p.d_ids, p.ids.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c->stream));
     FL_CHECK_HIP(hipMemcpyAsync(p.d_doff, p.doff.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, c->stream));
-    if (!p.batches.empty())
-        FL_CHECK_HIP(hipMemcpyAsync(p.d_batches, p.batches.data(), sizeof(KKBatch) * p.batches.size(),
-                                    hipMemcpyHostToDevice, c->stream));
     return p;
 }
 
@@ -709,7 +727,7 @@ static void kk_bfs(fl_ctx *c, const KKPlan &p, const int32_t *row_ptr, const int
 static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float *x, float *y,
                          const fl_kk_params &prm)
 {
-    if (p.batches.empty()) return;
+    if (p.ids.empty()) return;
     if (prm.minimiser == FL_KK_NEWTON) {
         // one wave per component, the largest first (they set the time)
         const int nc = (int)p.ids.size();
@@ -730,8 +748,58 @@ static void kk_run_steps(fl_ctx *c, const KKPlan &p, const int32_t *dist, float 
         hipLaunchKernelGGL(k_kk_newton, dim3((unsigned)nc), dim3(WAVE), lds, c->stream, p.d_off, p.d_ids, p.d_doff,
                            (const int32_t *)d_sched, dist, x, y, (float)prm.l, (float)(prm.eps * prm.l), prm.steps);
     } else {
-        hipLaunchKernelGGL(k_kk_steps, dim3((unsigned)p.batches.size()), dim3(256), 0, c->stream, p.d_batches,
-                           p.d_off, p.d_doff, dist, x, y, (float)prm.l, prm.steps);
+        // one workgroup per component, in three size classes with their own
+        // launch (the workgroup width and the LDS size follow the class):
+        // up to 16 nodes one wave, up to 64 nodes four, larger ones sixteen,
+        // each class largest first
+        const int nc = (int)p.ids.size();
+        const int cls_max[3] = {16, 64, KK_MAX}, cls_threads[3] = {WAVE, 256, 1024};
+        std::vector<int32_t> cls[3];
+        for (int k = 0; k < nc; ++k) {
+            const int64_t n2 = p.doff[k + 1] - p.doff[k];
+            int q = 0;
+            while ((int64_t)cls_max[q] * cls_max[q] < n2) ++q;
+            cls[q].push_back(k);
+        }
+        std::vector<int32_t> order;
+        for (auto &v : cls) {
+            std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+                return p.doff[a + 1] - p.doff[a] > p.doff[b + 1] - p.doff[b];
+            });
+            order.insert(order.end(), v.begin(), v.end());
+        }
+        int32_t *d_order = ws<int32_t>(c, "kk_order", (size_t)nc);
+        FL_CHECK_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, c->stream));
+        // the classes run side by side: the large components, one workgroup
+        // each, leave most compute units free while they run
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        for (auto &e : ev) FL_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        FL_CHECK_HIP(hipEventRecord(ev[0], c->stream));
+        const hipStream_t cs[3] = {aux_stream(c, 3), aux_stream(c, 2), c->stream};
+        const size_t first_of[3] = {0, cls[0].size(), cls[0].size() + cls[1].size()};
+        for (int q = 2; q >= 0; --q) {  // the large components first, so that their groups are placed first
+            const size_t first = first_of[q];
+            if (q < 2) FL_CHECK_HIP(hipStreamWaitEvent(cs[q], ev[0], 0));
+            if (cls[q].empty()) continue;
+            int64_t nk = 1;
+            while (nk * nk < p.doff[cls[q][0] + 1] - p.doff[cls[q][0]]) ++nk;  // the class's largest
+            const int64_t rs = (nk + 3) & ~3;
+            // positions, the weight table, the distance bytes
+            const size_t lds = sizeof(float2) * (size_t)(rs + KK_MAX) + (size_t)(nk * rs);
+            if (lds > 64 * 1024)
+                FL_CHECK_HIP(hipFuncSetAttribute((const void *)k_kk_major,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_kk_major, dim3((unsigned)cls[q].size()), dim3(cls_threads[q]), lds, cs[q],
+                               p.d_off, p.d_ids, p.d_doff, (const int32_t *)(d_order + first), dist, x, y,
+                               (float)prm.l, prm.steps);
+            FL_LAUNCH_CHECK();
+        }
+        for (int q = 0; q < 2; ++q) {
+            FL_CHECK_HIP(hipEventRecord(ev[q + 1], cs[q]));
+            FL_CHECK_HIP(hipStreamWaitEvent(c->stream, ev[q + 1], 0));
+        }
+        FL_CHECK_HIP(hipStreamSynchronize(c->stream));
+        for (auto &e : ev) (void)hipEventDestroy(e);
     }
     FL_LAUNCH_CHECK();
     FL_CHECK_HIP(hipStreamSynchronize(c->stream));  // host plan vectors outlive the async copies

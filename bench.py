@@ -69,7 +69,11 @@ def serving(args, fl, w, np) -> dict:
     sizes = np.round(np.exp(rng.uniform(math.log(100), math.log(1e6), size=J))).astype(np.int64)
     gaps = rng.exponential(1.0 / args.serving_rate, size=J)
     t = time.perf_counter()
-    jobs = [w.scaled(5_000_000 + i, int(n)) for i, n in enumerate(sizes)]
+    jobs = []
+    for i, n in enumerate(sizes):
+        jobs.append(w.scaled(5_000_000 + i, int(n)))
+        if (i + 1) % 200 == 0 and J > 200:
+            log(f"serving: {i + 1} of {J} jobs generated")
     log(f"serving: generated {J} jobs ({int(sizes.sum())} nodes) in {time.perf_counter() - t:.1f}s")
     prm = fl.default_params(p=args.p, leaf_size=args.leaf)
     out = {"jobs": J, "rate_per_s": args.serving_rate, "iters": args.serving_iters,
@@ -80,8 +84,10 @@ def serving(args, fl, w, np) -> dict:
         ids = []
 
         def feeder():
-            for g, dt in zip(jobs, gaps):
-                time.sleep(dt)
+            t_next = time.perf_counter()
+            for g, dt in zip(jobs, gaps):  # arrival times fixed by the gaps, not by how long submit takes
+                t_next += dt
+                time.sleep(max(0.0, t_next - time.perf_counter()))
                 ids.append(srv.submit(g.n, g.src, g.dst, g.x, g.y, args.serving_iters, prm))
 
         th = threading.Thread(target=feeder)
@@ -89,22 +95,50 @@ def serving(args, fl, w, np) -> dict:
         th.start()
         th.join()
         times = []
-        for i in ids:
-            assert srv.wait(i, 600.0) == fl.JOB_DONE
+        for k, i in enumerate(ids):
+            assert srv.wait(i, 900.0) == fl.JOB_DONE
             times.append(srv.result(i)[2])
+            if (k + 1) % 200 == 0 and len(ids) > 200:
+                log(f"serving ({slots} slots): {k + 1} of {len(ids)} jobs done")
         wall = time.perf_counter() - t0
+        st = srv.stats()
         srv.close()
-        lat = np.array([td - ta for ta, ts, td in times]) * 1e3
-        span = max(td for _, _, td in times) - min(ta for ta, _, _ in times)
+        ta = np.array([v[0] for v in times])
+        ts = np.array([v[1] for v in times])
+        td = np.array([v[2] for v in times])
+        lat = (td - ta) * 1e3
+        wait = (ts - ta) * 1e3
+        span = td.max() - ta.min()
+        # share of the span during which at least one job ran
+        ev = sorted([(a, 1) for a in ts] + [(b, -1) for b in td])
+        busy, depth, last = 0.0, 0, None
+        for t, dlt in ev:
+            if depth > 0:
+                busy += t - last
+            depth += dlt
+            last = t
+        q = max(1, len(lat) // 5)
         return {"slots": slots, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "mean_ms": float(lat.mean()), "node_updates_per_s": float(sizes.sum()) * args.serving_iters / span,
-                "wall_s": wall}
+                "mean_ms": float(lat.mean()), "queue_wait_p50_ms": float(np.percentile(wait, 50)),
+                "queue_wait_p99_ms": float(np.percentile(wait, 99)),
+                "node_updates_per_s": float(sizes.sum()) * args.serving_iters / span,
+                "busy_fraction": busy / span, "span_s": float(span), "wall_s": wall,
+                # latency drift with queue position: the first and the last fifth of the arrivals
+                "first_fifth_p50_ms": float(np.percentile(lat[:q], 50)),
+                "last_fifth_p50_ms": float(np.percentile(lat[-q:], 50)),
+                "peak_bytes": st["peak_bytes"], "peak_held_bytes": st["peak_held_bytes"], "trims": st["trims"],
+                "over_estimate": st["over_estimate"]}
 
     out["batched"] = run(args.serving_slots)
-    log(f"serving ({args.serving_slots} slots): p50 {out['batched']['p50_ms']:.1f} ms, "
-        f"p99 {out['batched']['p99_ms']:.1f} ms, {out['batched']['node_updates_per_s']:.3g} node-updates/s")
-    out["one_at_a_time"] = run(1)
-    log(f"serving (1 slot): p50 {out['one_at_a_time']['p50_ms']:.1f} ms, p99 {out['one_at_a_time']['p99_ms']:.1f} ms")
+    b = out["batched"]
+    log(f"serving ({args.serving_slots} slots): p50 {b['p50_ms']:.1f} ms, p99 {b['p99_ms']:.1f} ms, "
+        f"{b['node_updates_per_s']:.3g} node-updates/s, busy {b['busy_fraction']:.2f}, "
+        f"first/last fifth p50 {b['first_fifth_p50_ms']:.0f}/{b['last_fifth_p50_ms']:.0f} ms")
+    if not args.serving_no_single:
+        out["one_at_a_time"] = run(1)
+        o = out["one_at_a_time"]
+        log(f"serving (1 slot): p50 {o['p50_ms']:.1f} ms, p99 {o['p99_ms']:.1f} ms, "
+            f"first/last fifth p50 {o['first_fifth_p50_ms']:.0f}/{o['last_fifth_p50_ms']:.0f} ms")
     return out
 
 
@@ -412,6 +446,8 @@ def main() -> int:
     ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrival rate, jobs/s")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-iters", type=int, default=200)
+    ap.add_argument("--serving-no-single", action="store_true", help="skip the one-job-at-a-time comparison")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving section (no 2M-node run)")
     ap.add_argument("--tune-err", type=float, default=1e-3,
                     help="error bound of the autotuned run (0: skip)")
     ap.add_argument("--precision-sample", type=int, default=500,
@@ -436,6 +472,16 @@ def main() -> int:
     import numpy as np
 
     from paper_2403_03504_amd import workloads as w
+
+    if args.serving_only:  # the serving study alone (long runs of many jobs)
+        import torch
+
+        from paper_2403_03504_amd import fa2lay as fl
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            return 1
+        print(json.dumps({"serving": serving(args, fl, w, np)}), flush=True)
+        return 0
 
     t = time.perf_counter()
     g = w.giant_2m(args.seed, args.nodes, args.hubs)

@@ -519,8 +519,8 @@ typedef struct {
  * held_bytes / peak_held_bytes: device bytes the workers hold between jobs
  * (context workspace, branch contexts, job buffers; measured, not estimated);
  * trims: times a worker gave its memory back to keep the charges within the
- * budget; over_estimate: jobs that left their worker holding more than the
- * job's estimate. */
+ * budget; over_estimate: jobs that grew their worker's memory past what they
+ * were charged (the larger of the job's estimate and what the worker held). */
 typedef struct {
     int64_t submitted, admitted, completed, failed, canceled, queued, running;
     int64_t bytes_in_use, peak_bytes, node_updates;

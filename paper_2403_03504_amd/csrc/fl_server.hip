@@ -208,6 +208,7 @@ void worker(fl_server *sv, int me)
     while (true) {
         std::shared_ptr<Job> j;
         bool trim = false;
+        size_t held_before = 0;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_work.wait(lk, [&] {
@@ -232,6 +233,7 @@ void worker(fl_server *sv, int me)
                 j->t_start = sv->now();
                 j->tuning = sv->tuning;
                 sv->busy[me] = 1;
+                held_before = sv->held[me];
                 sv->charge[me] = std::max(sv->held[me], j->bytes);
                 sv->in_use = total_charge(sv);
                 sv->peak = std::max(sv->peak, sv->in_use);
@@ -270,7 +272,8 @@ void worker(fl_server *sv, int me)
         bool over = false;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            if (now_held > j->bytes) sv->st.over_estimate++;
+            // the job grew its worker's memory past what it was charged
+            if (now_held > std::max(held_before, j->bytes)) sv->st.over_estimate++;
             sv->held[me] = now_held;
             sv->busy[me] = 0;
             sv->charge[me] = now_held;

@@ -222,7 +222,7 @@ constexpr int T1_PER = T1_LEN / NT;
 // their common-prefix length is -1.
 __global__ __launch_bounds__(NT) void k_tree_levels(const uint32_t *__restrict__ K, int n, int bits, int L,
                                                     const int32_t *__restrict__ ncomp, int32_t *__restrict__ pack,
-                                                    int64_t *__restrict__ cnt2)
+                                                    int64_t *__restrict__ off2, int64_t *__restrict__ bsum)
 {
     __shared__ int A[T1_LEN];
     const int t0 = blockIdx.x * T1_TB;
@@ -258,17 +258,40 @@ __global__ __launch_bounds__(NT) void k_tree_levels(const uint32_t *__restrict__
         }
     }
     __syncthreads();
+    // per particle: the cells it starts and whether it starts a leaf, packed
+    // (cells | starts << 32), then their exclusive prefix within the block;
+    // the block's total goes to bsum (a scan of the block totals completes
+    // the numbering)
+    __shared__ int64_t C[T1_TB];
+    __shared__ int64_t stmp[NT / WAVE];
     for (int t = threadIdx.x; t < T1_TB; t += NT) {
         int k = t0 + t;
-        if (k >= n) break;
-        int mx = max(A[t], A[t + w - s]);
-        int lam = min(bits, 1 + mx);
-        int D = (k == 0 || (ncomp && ncomp[k - 1] != ncomp[k])) ? -1 : common_digits(K[k - 1], K[k], bits);
-        int c = lam - D;
-        if (c < 0) c = 0;
-        pack[k] = (D + 1) | (lam << 8);
-        cnt2[k] = (int64_t)c | ((int64_t)(c > 0 ? 1 : 0) << 32);
+        int64_t v = 0;
+        if (k < n) {
+            int mx = max(A[t], A[t + w - s]);
+            int lam = min(bits, 1 + mx);
+            int D = (k == 0 || (ncomp && ncomp[k - 1] != ncomp[k])) ? -1 : common_digits(K[k - 1], K[k], bits);
+            int c = lam - D;
+            if (c < 0) c = 0;
+            pack[k] = (D + 1) | (lam << 8);
+            v = (int64_t)c | ((int64_t)(c > 0 ? 1 : 0) << 32);
+        }
+        C[t] = v;
     }
+    __syncthreads();
+    static_assert(T1_TB == 4 * NT, "four particles per thread in the block scan");
+    const int q = 4 * (int)threadIdx.x;
+    const int64_t a0 = C[q], a1 = C[q + 1], a2 = C[q + 2], a3 = C[q + 3];
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, NT>(a0 + a1 + a2 + a3, stmp, tot);
+    C[q] = ex;
+    C[q + 1] = ex + a0;
+    C[q + 2] = ex + a0 + a1;
+    C[q + 3] = ex + a0 + a1 + a2;
+    __syncthreads();
+    for (int t = threadIdx.x; t < T1_TB; t += NT)
+        if (t0 + t < n) off2[t0 + t] = C[t];
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
 __device__ __forceinline__ uint32_t region_prefix(uint32_t key, int level, int bits)
@@ -276,18 +299,27 @@ __device__ __forceinline__ uint32_t region_prefix(uint32_t key, int level, int b
     return level == 0 ? 0u : (key >> (2 * (bits - level)));
 }
 
+// off2: per particle, the exclusive prefix of (cells | starts << 32) within
+// its block of T1_TB particles; bpre: exclusive prefix of the block totals,
+// bpre[number of blocks] = the totals
+__device__ __forceinline__ int64_t tree_offset(const int64_t *__restrict__ off2, const int64_t *__restrict__ bpre,
+                                               int k)
+{
+    return off2[k] + bpre[k / T1_TB];
+}
+
 __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, const int32_t *__restrict__ pack,
-                             const int64_t *__restrict__ off2, const int32_t *__restrict__ ncomp, int cbits,
-                             TreeBufs t)
+                             const int64_t *__restrict__ off2, const int64_t *__restrict__ bpre,
+                             const int32_t *__restrict__ ncomp, int cbits, TreeBufs t)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int pk = pack[k];
     int D = (pk & 0xFF) - 1, lam = pk >> 8;
     if (lam - D <= 0) return;
-    int64_t o = off2[k];
+    int64_t o = tree_offset(off2, bpre, k);
     int cid0 = (int)(o & 0xFFFFFFFFll), li = (int)(o >> 32);
-    int64_t tot = off2[n];
+    int64_t tot = bpre[(n + T1_TB - 1) / T1_TB];
     int ncells = (int)(tot & 0xFFFFFFFFll), nleaves = (int)(tot >> 32);
     if (ncells > t.cells_cap || nleaves > t.leaves_cap) {
         // cannot happen (see the capacity notes); refuse rather than overrun
@@ -367,7 +399,7 @@ __device__ __forceinline__ int first_cell_from(const int32_t *beg, int ncells, i
 }
 
 __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, const int64_t *__restrict__ off2,
-                             TreeBufs t)
+                             const int64_t *__restrict__ bpre, TreeBufs t)
 {
     int id = blockIdx.x * blockDim.x + threadIdx.x;
     int ncells = t.counts[0];
@@ -402,7 +434,7 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
         }
         int bp = t.start_pos[jp];
         int Dp = t.start_D[jp];
-        int cid0 = (int)(off2[bp] & 0xFFFFFFFFll);
+        int cid0 = (int)(tree_offset(off2, bpre, bp) & 0xFFFFFFFFll);
         p = cid0 + (l - 1 - Dp - 1);
         t.par[id] = p;
     }
@@ -1013,8 +1045,10 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     t.hkey = ws_zeroed<uint64_t>(c, "t_hkey", hc);
     t.hval = ws<int32_t>(c, "t_hval", hc);
     t.pack = ws<int32_t>(c, "t_pack", n);
-    int64_t *cnt2 = ws<int64_t>(c, "t_cnt2", n);
-    t.off2 = ws<int64_t>(c, "t_off2", (size_t)n + 1);
+    t.off2 = ws<int64_t>(c, "t_off2", (size_t)n);
+    const size_t nblk_t = (size_t)grid_for(n, T1_TB);
+    int64_t *bsum = ws<int64_t>(c, "t_bsum", nblk_t);
+    int64_t *bpre = ws<int64_t>(c, "t_bpre", nblk_t + 1);
     if (c->tree_cbits != s.cbits) {
         // the key layout changes: restart the epoch, so that this build
         // clears the table before inserting
@@ -1048,14 +1082,15 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
         sk = alt ? k1 : k0;
     }
     t.skey = sk;
-    hipLaunchKernelGGL(k_tree_levels, dim3(grid_for(n, T1_TB)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
-                       leaf, s.ncomp, t.pack, cnt2);
+    const unsigned nblk = grid_for(n, T1_TB);
+    hipLaunchKernelGGL(k_tree_levels, dim3(nblk), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits, leaf, s.ncomp,
+                       t.pack, t.off2, bsum);
     FL_LAUNCH_CHECK();
-    scan_excl_i64(c, cnt2, t.off2, n);
+    scan_excl_i64(c, bsum, bpre, nblk);
     hipLaunchKernelGGL(k_tree_cells, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
-                       (const int32_t *)t.pack, (const int64_t *)t.off2, s.ncomp, s.cbits, t);
+                       (const int32_t *)t.pack, (const int64_t *)t.off2, (const int64_t *)bpre, s.ncomp, s.cbits, t);
     hipLaunchKernelGGL(k_tree_links, dim3(grid_for(cap, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
-                       (const int64_t *)t.off2, t);
+                       (const int64_t *)t.off2, (const int64_t *)bpre, t);
     FL_LAUNCH_CHECK();
 }
 

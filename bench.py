@@ -448,6 +448,8 @@ def main() -> int:
     ap.add_argument("--serving-iters", type=int, default=200)
     ap.add_argument("--serving-no-single", action="store_true", help="skip the one-job-at-a-time comparison")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving section (no 2M-node run)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched-components section (no 2M-node run)")
     ap.add_argument("--tune-err", type=float, default=1e-3,
                     help="error bound of the autotuned run (0: skip)")
     ap.add_argument("--precision-sample", type=int, default=500,
@@ -473,6 +475,15 @@ def main() -> int:
 
     from paper_2403_03504_amd import workloads as w
 
+    if args.batched_only:  # the many-components workload alone
+        import torch
+
+        from paper_2403_03504_amd import fa2lay as fl
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            return 1
+        print(json.dumps({"batched": batched(args, fl, w, np, torch)}), flush=True)
+        return 0
     if args.serving_only:  # the serving study alone (long runs of many jobs)
         import torch
 

@@ -797,6 +797,9 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         upward_p<P>(c, us, t, b);
         build_lists(c, t, L, lanes);
         FL_CHECK_HIP(hipEventRecord(c->ev_lists, c->stream));
+        // the near field is enqueued (recorded) first among the list build's
+        // successors: graph replay dispatched it after M2L and L2L otherwise
+        near_p(c, t, L, near, pleaf);
         FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_lists, 0));
         if (on_lists) (*on_lists)(c->ev_lists);
         // the statistics (for the host only) on the branch, ahead of M2L,
@@ -804,7 +807,6 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         lists_stats(c, t, L, us);
         m2l_p<P>(c, us, t, L, b);
         FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
-        near_p(c, t, L, near, pleaf);
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
     }
     PhaseTimer pt(c, FL_PH_FAR);

@@ -11,6 +11,7 @@
 // 4M keys take a three-launch pass instead (per-tile histograms, a scan of
 // them, the scatter).
 #include <algorithm>
+#include <type_traits>
 
 #include "fl_common.h"
 
@@ -115,6 +116,40 @@ __global__ __launch_bounds__(SC_NT) void k_scan_down(const T *__restrict__ in, T
     scan_down_tile<T>(in, out, n, dn, part, scanned, blockIdx.x);
 }
 
+// An input of one tile, in one launch: the block's own total is the scan's
+// (integer types only, where the order of the additions does not matter).
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_scan_single(const T *__restrict__ in, T *__restrict__ out, int64_t n,
+                                                        const int32_t *__restrict__ dn)
+{
+    __shared__ T lds[SC_NT / WAVE];
+    int64_t live = dn ? (int64_t)*dn : n;
+    if (live > n) live = n;
+    const int64_t base = (int64_t)threadIdx.x * SC_IPT;
+    T v[SC_IPT];
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < SC_IPT; ++i) {
+        const int64_t idx = base + i;
+        v[i] = idx < live ? in[idx] : T(0);
+        s += v[i];
+    }
+    T tot;
+    T run = block_excl_scan<T, SC_NT>(s, lds, tot);
+    if (live > 0) {
+#pragma unroll
+        for (int i = 0; i < SC_IPT; ++i) {
+            const int64_t idx = base + i;
+            if (idx < n) out[idx] = run;
+            run += v[i];
+        }
+    }
+    if (threadIdx.x == 0) {
+        out[live] = tot;
+        out[n] = tot;
+    }
+}
+
 // Two independent scans in the same launches: blockIdx.y picks the array
 // (each with its own tiles; blocks past an array's tiles do nothing).
 template <class T>
@@ -145,6 +180,11 @@ void scan_excl(fl_ctx *c, const T *in, T *out, int64_t n, const int32_t *dn, con
 {
     int64_t ntiles = (n + SC_TILE - 1) / SC_TILE;
     if (ntiles < 1) ntiles = 1;
+    if (ntiles == 1 && std::is_integral<T>::value) {
+        hipLaunchKernelGGL(k_scan_single<T>, dim3(1), dim3(SC_NT), 0, c->stream, in, out, n, dn);
+        FL_LAUNCH_CHECK();
+        return;
+    }
     std::string nm = std::string("scan_part_") + tag + std::to_string(depth);
     T *part = ws<T>(c, nm.c_str(), (size_t)ntiles + 1);
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)ntiles), dim3(SC_NT), 0, c->stream, in, n, dn, part);

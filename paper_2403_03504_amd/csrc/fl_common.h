@@ -348,6 +348,24 @@ void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const in
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
                     int32_t *err = nullptr, const float4 *gsrc = nullptr, float4 *gdst = nullptr);
 bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits, int32_t *err = nullptr);
+
+// Segmented sort: K independent key ranges [coff[s], coff[s+1]), each sorted
+// on its own (stable), cut into system-aligned tiles of RS_SEG_TILE keys:
+// tile t covers [tiles[t].y, min(tiles[t].y + RS_SEG_TILE, coff[tiles[t].x
+// + 1])), the tiles of a system are consecutive and in system order.  The
+// result equals one stable sort by (system, key), with no system bits in the
+// keys.
+constexpr int RS_SEG_TILE = 4096;
+struct RsSegs {
+    int K = 0, ntiles = 0;
+    const int32_t *coff = nullptr;  // [K+1], device
+    const int2 *tiles = nullptr;    // [ntiles] (system, first key), device
+    const int32_t *toff = nullptr;  // [K+1] first tile of each system, device
+};
+// whether the segmented one-launch-per-pass sort takes n keys in `ntiles` tiles
+bool radix_sort_seg_fits(int64_t n, int ntiles);
+bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
+                        int32_t *err, const RsSegs &sg, const float4 *gsrc = nullptr, float4 *gdst = nullptr);
 bool radix_sort_u64v(fl_ctx *c, uint64_t *k, int32_t *v, uint64_t *kt, int32_t *vt, int64_t n, int nbits,
                      int32_t *err = nullptr);
 

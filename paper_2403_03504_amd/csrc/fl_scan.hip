@@ -246,16 +246,16 @@ struct RsShared {
 // waves (wcnt) and the block's count of the digit is returned to thread d.
 template <class K, bool HasVal>
 __device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restrict__ kin,
-                                       const int32_t *__restrict__ vin, int64_t n, int shift, int64_t tile,
+                                       const int32_t *__restrict__ vin, int64_t t0, int64_t t1, int shift,
                                        K (&key)[RS_STEPS], int32_t (&val)[RS_STEPS], int (&off)[RS_STEPS],
                                        int (&dig)[RS_STEPS])
 {
     const int lane = lane_id(), w = threadIdx.x / WAVE;
-    const int64_t wbase = tile * RS_TILE + (int64_t)w * RS_WTILE;
+    const int64_t wbase = t0 + (int64_t)w * RS_WTILE;
 #pragma unroll
     for (int st = 0; st < RS_STEPS; ++st) {
         int64_t idx = wbase + (int64_t)st * WAVE + lane;
-        bool ok = idx < n;
+        bool ok = idx < t1;
         key[st] = ok ? kin[idx] : K(0);
         if (HasVal) val[st] = ok ? vin[idx] : 0;
         dig[st] = ok ? (int)((key[st] >> shift) & (RS_BINS - 1)) : -1;
@@ -292,11 +292,12 @@ __device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restri
     return run;
 }
 
-// Places the ranked keys in LDS in digit order and writes every digit's run
-// to its global position gbase[d] + rank within the digit (coalesced).
+// Places the ranked keys of the tile [t0, t1) in LDS in digit order and
+// writes every digit's run to its global position gbase[d] + rank within the
+// digit (coalesced); positions at or past `lim` are dropped.
 template <class K, bool HasVal>
 __device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__ kout, int32_t *__restrict__ vout,
-                                         int64_t n, int shift, int64_t tile, const K (&key)[RS_STEPS],
+                                         int64_t t0, int64_t t1, int64_t lim, int shift, const K (&key)[RS_STEPS],
                                          const int32_t (&val)[RS_STEPS], const int (&off)[RS_STEPS],
                                          const int (&dig)[RS_STEPS], const float4 *__restrict__ gsrc,
                                          float4 *__restrict__ gdst)
@@ -311,13 +312,12 @@ __device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__
         if (HasVal) S.sval[lp] = val[st];
     }
     __syncthreads();
-    const int64_t tile0 = tile * RS_TILE;
-    const int live = (int)((n - tile0) < RS_TILE ? (n - tile0) : RS_TILE);
+    const int live = (int)(t1 - t0);
     for (int i = threadIdx.x; i < live; i += RS_NT) {
         const K k2 = S.skey[i];
         const int d = (int)((k2 >> shift) & (RS_BINS - 1));
         const int64_t pos = (int64_t)S.gbase[d] + (i - S.lstart[d]);
-        if (pos < n) {  // always true unless a look-back gave up (error flagged)
+        if (pos < lim) {  // always true unless a look-back gave up (error flagged)
             kout[pos] = k2;
             if (HasVal) {
                 const int32_t v = S.sval[i];
@@ -343,9 +343,10 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
     K key[RS_STEPS];
     int32_t val[RS_STEPS];
     int off[RS_STEPS], dig[RS_STEPS];
-    rs_rank<K, HasVal>(S, kin, vin, n, shift, blockIdx.x, key, val, off, dig);
+    const int64_t t0 = (int64_t)blockIdx.x * RS_TILE, t1 = t0 + RS_TILE < n ? t0 + RS_TILE : n;
+    rs_rank<K, HasVal>(S, kin, vin, t0, t1, shift, key, val, off, dig);
     __syncthreads();
-    rs_place<K, HasVal>(S, kout, vout, n, shift, blockIdx.x, key, val, off, dig, gsrc, gdst);
+    rs_place<K, HasVal>(S, kout, vout, t0, t1, n, shift, key, val, off, dig, gsrc, gdst);
 }
 
 // ---- one launch per pass: decoupled look-back --------------------------------
@@ -371,6 +372,37 @@ constexpr int RS_LOOK = 8;  // tiles read per look-back step
 // the tile count while launch overhead matters less (4M keys at most here,
 // far below the 2^30 the status words hold).
 constexpr int RS_LOOKBACK_TILES = 1024;
+static_assert(RS_TILE == RS_SEG_TILE, "segmented tiles are sort tiles");
+
+// Keys [t0, t1) of a tile; its positions lie in [base, lim) (its system's
+// range, the whole input without segments); `first`: the first tile of its
+// system, which publishes an inclusive prefix at once.
+struct RsTile {
+    int64_t t0, t1, base, lim;
+    int sys;
+    bool first;
+};
+
+__device__ __forceinline__ RsTile rs_tile(const RsSegs &sg, int64_t n, int tile)
+{
+    RsTile r;
+    if (sg.tiles) {
+        const int2 td = sg.tiles[tile];
+        r.sys = td.x;
+        r.t0 = td.y;
+        r.base = sg.coff[td.x];
+        r.lim = sg.coff[td.x + 1];
+        r.first = tile == sg.toff[td.x];
+    } else {
+        r.sys = 0;
+        r.t0 = (int64_t)tile * RS_TILE;
+        r.base = 0;
+        r.lim = n;
+        r.first = tile == 0;
+    }
+    r.t1 = r.t0 + RS_TILE < r.lim ? r.t0 + RS_TILE : r.lim;
+    return r;
+}
 
 // Digit counts of all passes per 4096-key tile (LDS counts, written out
 // per tile), the clearing of every pass's status words, and (block 0) the
@@ -379,7 +411,8 @@ constexpr int RS_LOOKBACK_TILES = 1024;
 template <class K>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ keys, int64_t n, int passes,
                                                         uint32_t *__restrict__ part, uint32_t *__restrict__ status,
-                                                        int64_t nstatus, uint32_t *__restrict__ gh, int ngh)
+                                                        int64_t nstatus, uint32_t *__restrict__ gh, int ngh,
+                                                        RsSegs sg)
 {
     __shared__ uint32_t cnt[RS_MAXPASS][RS_BINS];
     for (int i = threadIdx.x; i < RS_MAXPASS * RS_BINS; i += RS_NT) (&cnt[0][0])[i] = 0u;
@@ -388,10 +421,9 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ key
     const int64_t stride = (int64_t)gridDim.x * RS_NT;
     for (int64_t i = (int64_t)blockIdx.x * RS_NT + threadIdx.x; i < nstatus; i += stride) status[i] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int i = threadIdx.x; i < RS_TILE; i += RS_NT) {
-        if (base + i >= n) break;
-        const K k = keys[base + i];
+    const RsTile tl = rs_tile(sg, n, blockIdx.x);
+    for (int64_t i = tl.t0 + threadIdx.x; i < tl.t1; i += RS_NT) {
+        const K k = keys[i];
         for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(int)((k >> (p * RS_BITS)) & (RS_BINS - 1))], 1u);
     }
     __syncthreads();
@@ -426,13 +458,42 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_sum(const uint32_t *__restric
     if (lane == 0) gh[i] = sum;
 }
 
+// The same per system: one wave per (system, pass, digit) entry, its lanes
+// over the system's tiles; gh[(system * passes + pass) * 256 + digit], and
+// the first pass's tile prefixes within each system.
+__global__ __launch_bounds__(RS_NT) void k_rs_hist_sum_seg(const uint32_t *__restrict__ part, int passes, RsSegs sg,
+                                                            uint32_t *__restrict__ gh, uint32_t *__restrict__ pfx0)
+{
+    const int64_t i = (int64_t)blockIdx.x * RS_NW + threadIdx.x / WAVE;
+    const int64_t per = (int64_t)passes * RS_BINS;
+    if (i >= (int64_t)sg.K * per) return;
+    const int sys = (int)(i / per), r = (int)(i - sys * per), ps = r / RS_BINS, d = r - ps * RS_BINS;
+    const int tb = sg.toff[sys], te = sg.toff[sys + 1];
+    const int lane = lane_id();
+    uint32_t sum = 0u;
+    if (ps == 0) {
+        for (int b0 = tb; b0 < te; b0 += WAVE) {
+            const int b = b0 + lane;
+            const uint32_t v = b < te ? part[(int64_t)b * per + r] : 0u;
+            const uint32_t inc = wave_incl_scan(v);
+            if (b < te) pfx0[(int64_t)b * RS_BINS + d] = sum + inc - v;
+            sum += __shfl(inc, WAVE - 1, WAVE);
+        }
+    } else {
+        for (int b = tb + lane; b < te; b += WAVE) sum += part[(int64_t)b * per + r];
+        sum = wave_sum(sum);
+    }
+    if (lane == 0) gh[i] = sum;
+}
+
 template <class K, bool HasVal>
 __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin, const int32_t *__restrict__ vin,
                                                         K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
-                                                        int shift, const uint32_t *__restrict__ gh,
+                                                        int shift, const uint32_t *__restrict__ gh, int ghstride,
                                                         uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
                                                         const uint32_t *__restrict__ pfx, int32_t *__restrict__ err,
-                                                        const float4 *__restrict__ gsrc, float4 *__restrict__ gdst)
+                                                        const float4 *__restrict__ gsrc, float4 *__restrict__ gdst,
+                                                        RsSegs sg)
 {
     __shared__ RsShared<K, HasVal> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
@@ -444,17 +505,21 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
     int32_t val[RS_STEPS];
     int off[RS_STEPS], dig[RS_STEPS];
     const int d = threadIdx.x;
-    const uint32_t cnt = (uint32_t)rs_rank<K, HasVal>(S, kin, vin, n, shift, tile, key, val, off, dig);
+    const RsTile tl = rs_tile(sg, n, tile);
+    const uint32_t cnt = (uint32_t)rs_rank<K, HasVal>(S, kin, vin, tl.t0, tl.t1, shift, key, val, off, dig);
     uint32_t *my = status + (int64_t)tile * RS_BINS + d;
     if (!pfx)
-        __hip_atomic_store(my, (tile == 0 ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // global start of the digit: counts of the smaller digits
+        __hip_atomic_store(my, (tl.first ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // start of the digit in the system: counts of the smaller digits
     int tot;
-    const uint32_t dstart = (uint32_t)block_excl_scan<int, RS_NT>((int)gh[d], S.scan_tmp, tot);
+    const uint32_t dstart =
+        (uint32_t)block_excl_scan<int, RS_NT>((int)gh[(int64_t)tl.sys * ghstride + d], S.scan_tmp, tot);
     uint32_t before = 0;
     if (pfx) {
         before = pfx[(int64_t)tile * RS_BINS + d];
-    } else if (tile > 0) {
+    } else if (!tl.first) {
+        // the walk ends at an inclusive prefix, at the latest on the first
+        // tile of the system (it publishes one at once)
         // look back RS_LOOK tiles at a time (independent loads in flight),
         // consuming counts in order until an inclusive prefix; a tile that
         // has published nothing yet stops the window and is read again
@@ -466,7 +531,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
             for (int u = 0; u < RS_LOOK; ++u)
                 v[u] = j - u >= 0 ? __hip_atomic_load(status + (int64_t)(j - u) * RS_BINS + d, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT)
-                                  : 0u;  // never consumed: tile 0 publishes a prefix
+                                  : 0u;  // never consumed: a first tile publishes a prefix
             int used = 0;
             bool pfx = false;
 #pragma unroll
@@ -493,9 +558,9 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
         }
         __hip_atomic_store(my, RS_PFX | ((before + cnt) & RS_VAL), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    S.gbase[d] = (int)(dstart + before);
+    S.gbase[d] = (int)(tl.base + dstart + before);
     __syncthreads();
-    rs_place<K, HasVal>(S, kout, vout, n, shift, tile, key, val, off, dig, gsrc, gdst);
+    rs_place<K, HasVal>(S, kout, vout, tl.t0, tl.t1, tl.lim, shift, key, val, off, dig, gsrc, gdst);
 }
 
 template <class K, bool HasVal>
@@ -517,16 +582,16 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
         uint32_t *status = ws<uint32_t>(c, (std::string("rs_status_") + tag).c_str(), (size_t)nstatus);
         if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
         hipLaunchKernelGGL(k_rs_hist_all<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)k, n, passes, part,
-                           status, nstatus, gh, nz);
+                           status, nstatus, gh, nz, RsSegs{});
         uint32_t *pfx0 = ws<uint32_t>(c, (std::string("rs_pfx0_") + tag).c_str(), (size_t)nblocks * RS_BINS);
         hipLaunchKernelGGL(k_rs_hist_sum, dim3(passes * RS_BINS / RS_NW), dim3(RS_NT), 0, c->stream,
                            (const uint32_t *)part, nblocks, passes, gh, pfx0);
         for (int ps = 0; ps < passes; ++ps) {
             hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
-                               (const int32_t *)va, kb, vb, n, ps * RS_BITS, (const uint32_t *)(gh + ps * RS_BINS),
+                               (const int32_t *)va, kb, vb, n, ps * RS_BITS, (const uint32_t *)(gh + ps * RS_BINS), 0,
                                status + (int64_t)ps * nblocks * RS_BINS, ticket + ps,
                                ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
-                               ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr);
+                               ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr, RsSegs{});
             std::swap(ka, kb);
             std::swap(va, vb);
         }
@@ -583,6 +648,44 @@ void scan_excl_i64_pair(fl_ctx *c, const int64_t *in0, int64_t *out0, int64_t n0
 void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const int32_t *dn, const char *tag)
 {
     scan_excl<double>(c, in, out, n, dn, tag);
+}
+
+bool radix_sort_seg_fits(int64_t n, int ntiles) { return n > 0 && ntiles >= 1 && ntiles <= RS_LOOKBACK_TILES; }
+
+bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
+                        int32_t *err, const RsSegs &sg, const float4 *gsrc, float4 *gdst)
+{
+    if (n <= 0) return false;
+    const int passes = (nbits + RS_BITS - 1) / RS_BITS;
+    FL_REQUIRE(radix_sort_seg_fits(n, sg.ntiles) && passes <= RS_MAXPASS && sg.tiles && sg.K >= 1,
+               "segmented sort: tiles out of range");
+    const int nt = sg.ntiles;
+    const int64_t per = (int64_t)passes * RS_BINS;
+    // per-system digit counts, then the tickets (the only words zeroed)
+    uint32_t *gh = ws<uint32_t>(c, "rs_gh_seg", (size_t)(sg.K * per + passes));
+    uint32_t *ticket = gh + sg.K * per;
+    uint32_t *part = ws<uint32_t>(c, "rs_part_seg", (size_t)nt * per);
+    const int64_t nstatus = (int64_t)nt * per;
+    uint32_t *status = ws<uint32_t>(c, "rs_status_seg", (size_t)nstatus);
+    if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
+    hipLaunchKernelGGL(k_rs_hist_all<uint32_t>, dim3(nt), dim3(RS_NT), 0, c->stream, (const uint32_t *)k, n, passes,
+                       part, status, nstatus, ticket, passes, sg);
+    uint32_t *pfx0 = ws<uint32_t>(c, "rs_pfx0_seg", (size_t)nt * RS_BINS);
+    hipLaunchKernelGGL(k_rs_hist_sum_seg, dim3((unsigned)((sg.K * per + RS_NW - 1) / RS_NW)), dim3(RS_NT), 0,
+                       c->stream, (const uint32_t *)part, passes, sg, gh, pfx0);
+    uint32_t *ka = k, *kb = kt;
+    int32_t *va = v, *vb = vt;
+    for (int ps = 0; ps < passes; ++ps) {
+        hipLaunchKernelGGL((k_rs_onesweep<uint32_t, true>), dim3(nt), dim3(RS_NT), 0, c->stream,
+                           (const uint32_t *)ka, (const int32_t *)va, kb, vb, n, ps * RS_BITS,
+                           (const uint32_t *)(gh + ps * RS_BINS), (int)per, status + (int64_t)ps * nt * RS_BINS,
+                           ticket + ps, ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
+                           ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr, sg);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    FL_LAUNCH_CHECK();
+    return (passes & 1) != 0;
 }
 
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,

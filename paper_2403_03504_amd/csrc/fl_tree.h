@@ -46,6 +46,7 @@ struct Segs {
     const int32_t *tile_off = nullptr;  // [K+1] first tile of each system
     int ntiles = 0;
     int cbits = 0;                      // bits of the system id in hash keys (0 when K == 1)
+    RsSegs sort;                        // system-aligned sort tiles (K > 1 only)
 };
 
 // One system of n nodes (device arrays cached per context).

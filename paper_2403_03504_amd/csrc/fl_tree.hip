@@ -950,6 +950,15 @@ static Segs upload_segs(fl_ctx *c, const std::vector<int32_t> &coff, const std::
         for (int64_t b = coff[k]; b < coff[k + 1]; b += SEG_TILE) tiles.push_back(make_int2(k, (int)b));
     }
     toff[K] = (int32_t)tiles.size();
+    std::vector<int2> stiles;  // sort tiles
+    std::vector<int32_t> stoff(K + 1);
+    if (K > 1) {
+        for (int k = 0; k < K; ++k) {
+            stoff[k] = (int32_t)stiles.size();
+            for (int64_t b = coff[k]; b < coff[k + 1]; b += RS_SEG_TILE) stiles.push_back(make_int2(k, (int)b));
+        }
+        stoff[K] = (int32_t)stiles.size();
+    }
     Segs sg;
     sg.K = K;
     sg.n = coff[K];
@@ -968,6 +977,17 @@ static Segs upload_segs(fl_ctx *c, const std::vector<int32_t> &coff, const std::
     sg.tile_off = d_toff;
     sg.tiles = d_tiles;
     if (K > 1) {
+        int2 *d_st = ws<int2>(c, (tag + "_stiles").c_str(), stiles.size());
+        int32_t *d_stoff = ws<int32_t>(c, (tag + "_stoff").c_str(), (size_t)K + 1);
+        FL_CHECK_HIP(hipMemcpyAsync(d_st, stiles.data(), sizeof(int2) * stiles.size(), hipMemcpyHostToDevice,
+                                    c->stream));
+        FL_CHECK_HIP(
+            hipMemcpyAsync(d_stoff, stoff.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice, c->stream));
+        sg.sort.K = K;
+        sg.sort.ntiles = (int)stiles.size();
+        sg.sort.coff = d_coff;
+        sg.sort.tiles = d_st;
+        sg.sort.toff = d_stoff;
         int32_t *nc = ws<int32_t>(c, (tag + "_ncomp").c_str(), (size_t)sg.n);
         hipLaunchKernelGGL(k_fill_ncomp, dim3(grid_for(sg.n, NT)), dim3(NT), 0, c->stream, (const int32_t *)d_coff, K,
                            sg.n, nc);
@@ -1023,7 +1043,13 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     int32_t *i0 = ws<int32_t>(c, "t_idx0", n);
     int32_t *i1 = ws<int32_t>(c, "t_idx1", n);
     uint64_t *q0 = nullptr, *q1 = nullptr;
-    if (s.K > 1) {
+    // several systems: a segmented sort of the 32-bit keys when its tiles
+    // pad the input little (systems of a few keys each take the sort of
+    // (system, key) pairs instead); both give the same order
+    const int64_t min_tiles = ((int64_t)n + RS_SEG_TILE - 1) / RS_SEG_TILE;
+    const bool seg = s.K > 1 && s.sort.tiles && s.sort.ntiles <= 2 * min_tiles + 8 &&
+                     radix_sort_seg_fits(n, s.sort.ntiles);
+    if (s.K > 1 && !seg) {
         q0 = ws<uint64_t>(c, "t_qkey0", n);
         q1 = ws<uint64_t>(c, "t_qkey1", n);
     }
@@ -1065,11 +1091,16 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     // words left there under another key layout could pass its epoch test
     const int64_t hkey_slots = (int64_t)(c->bufs["t_hkey"].cap / sizeof(uint64_t));
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
-                       (const double *)t.root, bits, s.K > 1 ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
+                       (const double *)t.root, bits, s.K > 1 && !seg ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
                        t.hkey, hkey_slots, deg, xym, t.counts, xy_out);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
-    if (s.K > 1) {
+    if (seg) {
+        // the last pass also moves every node's record to its sorted place
+        const bool alt = radix_sort_u32_seg(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3, s.sort,
+                                            (const float4 *)xym, t.part);
+        sk = alt ? k1 : k0;
+    } else if (s.K > 1) {
         const bool alt = radix_sort_u64v(c, q0, i0, q1, i1, n, 32 + s.cbits, t.counts + 3);
         const uint64_t *sq = alt ? q1 : q0;
         const int32_t *perm = alt ? i1 : i0;

@@ -67,6 +67,37 @@ def test_systems_equal_each_alone(fl, rep, iters):
         c.close()
 
 
+@pytest.mark.parametrize("sizes", [
+    (4096, 3, 8193, 4095, 600, 12288),  # sorted in segments: whole tiles, one key past, a few keys
+    (40, 75, 3, 120) * 10,              # many small systems: sorted as (system, key) pairs
+])
+def test_systems_sort_tiles_equal_alone(fl, sizes):
+    """System sizes around the 4096-key sort tiles, and many small systems:
+    every system's FMM layout bitwise the same as alone (the forest's sort
+    orders each system's keys by themselves either way)."""
+    from paper_2403_03504_amd import workloads as w
+    _note("systems around sort tiles,", len(sizes), "systems,", sum(sizes), "nodes")
+    parts = [w.small_component(1300 + i, n) if n < 1000 else w.scaled(1300 + i, n, hubs_per_4000=False)
+             for i, n in enumerate(sizes)]
+    g, offs = w.union(parts)
+    prm = fl.default_params(repulsion=fl.REP_FMM, p=8, leaf_size=32)
+    c = fl.Context(0)
+    try:
+        G = c.build_csr(g.n, dev(g.src), dev(g.dst))
+        x, y = dev(g.x), dev(g.y)
+        st = fl.FA2State.zeros(g.n, "cuda", comp_offsets=offs)
+        c.fa2_run(G, x, y, st, prm, 3)
+        gx, gy = host(x), host(y)
+        for k, part in enumerate(parts):
+            Gp = c.build_csr(part.n, dev(part.src), dev(part.dst))
+            px, py = dev(part.x), dev(part.y)
+            c.fa2_run(Gp, px, py, fl.FA2State.zeros(part.n, "cuda"), prm, 3)
+            a, b = offs[k], offs[k + 1]
+            assert np.array_equal(host(px), gx[a:b]) and np.array_equal(host(py), gy[a:b]), (k, part.n)
+    finally:
+        c.close()
+
+
 def test_systems_step_against_oracle(fl, orc, node_err):
     """One step of two systems against the oracle's step of each component:
     forces (exact repulsion) within 1e-5 norm-wise and 1e-4 per node, each

@@ -310,7 +310,7 @@ __device__ __forceinline__ int64_t tree_offset(const int64_t *__restrict__ off2,
 
 __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, const int32_t *__restrict__ pack,
                              const int64_t *__restrict__ off2, const int64_t *__restrict__ bpre,
-                             const int32_t *__restrict__ ncomp, int cbits, TreeBufs t)
+                             const int32_t *__restrict__ ncomp, TreeBufs t)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -340,8 +340,9 @@ __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, co
         t.counts[0] = ncells;
         t.counts[1] = nleaves;
     }
-    const int64_t H = hash_size(ncells, t.hash_cap);
-    const uint64_t ep = *t.epoch;
+    // the cells this particle starts (their hash entries are made per cell,
+    // in parallel, by k_tree_links: a chain of inserts here would serialise
+    // the deep starts)
     for (int l = D + 1; l <= lam; ++l) {
         int id = cid0 + (l - D - 1);
         uint32_t pre = region_prefix(key, l, bits);
@@ -353,25 +354,29 @@ __global__ void k_tree_cells(const uint32_t *__restrict__ K, int n, int bits, co
         t.leafidx[id] = (l == lam) ? li : -1;
         t.par[id] = (l == 0) ? -1 : (l - 1 > D ? id - 1 : -2);
         if (t.ccomp) t.ccomp[id] = comp;
-        // insert (comp, l, ix, iy) -> id
-        const int sh = HASH_BASE_BITS + cbits;
-        uint64_t hk = hash_key(comp, l, ix, iy);
-        uint64_t kk = hk | (ep << sh);
-        int64_t h = (int64_t)(mix64(hk) & (uint64_t)(H - 1));
-        for (int64_t probe = 0; probe < H; ++probe) {
-            uint64_t old = t.hkey[h];
-            if ((old >> sh) == ep) {
-                h = (h + 1) & (H - 1);
-                continue;
-            }
-            unsigned long long prev = atomicCAS((unsigned long long *)&t.hkey[h], (unsigned long long)old,
-                                                (unsigned long long)kk);
-            if (prev == old) {
-                t.hval[h] = id;
-                break;
-            }
-            --probe;  // lost the slot to another insert: look at it again
+    }
+}
+
+// insert (system, level, ix, iy) -> id into the table of this epoch
+__device__ __forceinline__ void hash_insert(const TreeBufs &t, int64_t H, uint64_t ep, int sh, int comp, int l,
+                                            uint32_t ixy, int id)
+{
+    const uint64_t hk = hash_key(comp, l, (int)(ixy & 0xFFFFu), (int)(ixy >> 16));
+    const uint64_t kk = hk | (ep << sh);
+    int64_t h = (int64_t)(mix64(hk) & (uint64_t)(H - 1));
+    for (int64_t probe = 0; probe < H; ++probe) {
+        const uint64_t old = t.hkey[h];
+        if ((old >> sh) == ep) {
+            h = (h + 1) & (H - 1);
+            continue;
         }
+        const unsigned long long prev =
+            atomicCAS((unsigned long long *)&t.hkey[h], (unsigned long long)old, (unsigned long long)kk);
+        if (prev == old) {
+            t.hval[h] = id;
+            break;
+        }
+        --probe;  // lost the slot to another insert: look at it again
     }
 }
 
@@ -407,6 +412,7 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
     int nleaves = t.counts[1];
     int l = t.lvl[id];
     const int comp = t.ccomp ? t.ccomp[id] : 0;
+    hash_insert(t, hash_size(ncells, t.hash_cap), *t.epoch, HASH_BASE_BITS + t.s.cbits, comp, l, t.ixy[id], id);
     if (l == 0) {
         const int e0 = t.s.K > 1 ? t.s.coff[comp + 1] : n;
         t.end[id] = e0;
@@ -1119,7 +1125,7 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     FL_LAUNCH_CHECK();
     scan_excl_i64(c, bsum, bpre, nblk);
     hipLaunchKernelGGL(k_tree_cells, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
-                       (const int32_t *)t.pack, (const int64_t *)t.off2, (const int64_t *)bpre, s.ncomp, s.cbits, t);
+                       (const int32_t *)t.pack, (const int64_t *)t.off2, (const int64_t *)bpre, s.ncomp, t);
     hipLaunchKernelGGL(k_tree_links, dim3(grid_for(cap, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
                        (const int64_t *)t.off2, (const int64_t *)bpre, t);
     FL_LAUNCH_CHECK();

@@ -202,13 +202,14 @@ void scan_excl(fl_ctx *c, const T *in, T *out, int64_t n, const int32_t *dn, con
 
 // ---------------------------------------------------------------------------
 // radix sort
-constexpr int RS_NT = 256;
-constexpr int RS_NW = RS_NT / WAVE;  // 4 waves
-constexpr int RS_STEPS = 16;         // 64-key steps per wave
-constexpr int RS_WTILE = RS_STEPS * WAVE;  // 1024 keys per wave
+constexpr int RS_NT = 512;
+constexpr int RS_NW = RS_NT / WAVE;  // 8 waves
+constexpr int RS_STEPS = 8;          // 64-key steps per wave
+constexpr int RS_WTILE = RS_STEPS * WAVE;  // 512 keys per wave
 constexpr int RS_TILE = RS_NW * RS_WTILE;  // 4096 keys per block
 constexpr int RS_BITS = 8;
-constexpr int RS_BINS = 1 << RS_BITS;
+constexpr int RS_BINS = 1 << RS_BITS;  // digit d is thread d's in the per-digit steps
+static_assert(RS_NT >= RS_BINS, "a thread per digit");
 constexpr int RS_MAXPASS = 8;  // 64-bit keys
 
 template <class K>
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
                                                     int32_t *__restrict__ hist, int nblocks)
 {
     __shared__ int cnt[RS_BINS];
-    cnt[threadIdx.x] = 0;
+    if (threadIdx.x < RS_BINS) cnt[threadIdx.x] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
 #pragma unroll 4
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
         if (idx < n) atomicAdd(&cnt[(int)((keys[idx] >> shift) & (RS_BINS - 1))], 1);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < RS_BINS) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // The LDS of one scatter block.
@@ -281,14 +282,17 @@ __device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restri
     __syncthreads();
     const int t = threadIdx.x;
     int run = 0;
+    if (t < RS_BINS) {
 #pragma unroll
-    for (int ww = 0; ww < RS_NW; ++ww) {
-        int cnum = S.wcnt[ww][t];
-        S.wcnt[ww][t] = run;
-        run += cnum;
+        for (int ww = 0; ww < RS_NW; ++ww) {
+            int cnum = S.wcnt[ww][t];
+            S.wcnt[ww][t] = run;
+            run += cnum;
+        }
     }
     int tot;
-    S.lstart[t] = block_excl_scan<int, RS_NT>(run, S.scan_tmp, tot);  // the digit's start in the block's order
+    const int ls = block_excl_scan<int, RS_NT>(run, S.scan_tmp, tot);  // the digit's start in the block's order
+    if (t < RS_BINS) S.lstart[t] = ls;
     return run;
 }
 
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin,
 {
     __shared__ RsShared<K, HasVal> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
-    S.gbase[threadIdx.x] = hscan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    if (threadIdx.x < RS_BINS) S.gbase[threadIdx.x] = hscan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
     __syncthreads();
     K key[RS_STEPS];
     int32_t val[RS_STEPS];
@@ -427,7 +431,9 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ key
         for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(int)((k >> (p * RS_BITS)) & (RS_BINS - 1))], 1u);
     }
     __syncthreads();
-    for (int p = 0; p < passes; ++p) part[((int64_t)blockIdx.x * passes + p) * RS_BINS + threadIdx.x] = cnt[p][threadIdx.x];
+    if (threadIdx.x < RS_BINS)
+        for (int p = 0; p < passes; ++p)
+            part[((int64_t)blockIdx.x * passes + p) * RS_BINS + threadIdx.x] = cnt[p][threadIdx.x];
 }
 
 // Sums the per-tile counts: one wave per (pass, digit) entry, its lanes
@@ -505,17 +511,19 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
     int32_t val[RS_STEPS];
     int off[RS_STEPS], dig[RS_STEPS];
     const int d = threadIdx.x;
+    const bool dig_thread = d < RS_BINS;  // thread d handles digit d
     const RsTile tl = rs_tile(sg, n, tile);
     const uint32_t cnt = (uint32_t)rs_rank<K, HasVal>(S, kin, vin, tl.t0, tl.t1, shift, key, val, off, dig);
     uint32_t *my = status + (int64_t)tile * RS_BINS + d;
-    if (!pfx)
+    if (!pfx && dig_thread)
         __hip_atomic_store(my, (tl.first ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // start of the digit in the system: counts of the smaller digits
     int tot;
-    const uint32_t dstart =
-        (uint32_t)block_excl_scan<int, RS_NT>((int)gh[(int64_t)tl.sys * ghstride + d], S.scan_tmp, tot);
+    const uint32_t dstart = (uint32_t)block_excl_scan<int, RS_NT>(
+        dig_thread ? (int)gh[(int64_t)tl.sys * ghstride + d] : 0, S.scan_tmp, tot);
     uint32_t before = 0;
-    if (pfx) {
+    if (!dig_thread) {
+    } else if (pfx) {
         before = pfx[(int64_t)tile * RS_BINS + d];
     } else if (!tl.first) {
         // the walk ends at an inclusive prefix, at the latest on the first
@@ -558,7 +566,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
         }
         __hip_atomic_store(my, RS_PFX | ((before + cnt) & RS_VAL), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    S.gbase[d] = (int)(tl.base + dstart + before);
+    if (dig_thread) S.gbase[d] = (int)(tl.base + dstart + before);
     __syncthreads();
     rs_place<K, HasVal>(S, kout, vout, tl.t0, tl.t1, tl.lim, shift, key, val, off, dig, gsrc, gdst);
 }

@@ -343,10 +343,12 @@ void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const in
 // Stable LSD radix sort of 32-bit keys with int32 payload over bits
 // [0, nbits).  Ping-pongs between (k, v) and (kt, vt); returns true when the
 // sorted result ended in (kt, vt).  With gdst the last pass also writes
-// gdst[i] = gsrc[sorted payload i] (payload values must index gsrc).
+// gdst[i] = gsrc[sorted payload i] (payload values must index gsrc).  With
+// vals_iota the payload of key i is i, and v is not read (only written).
 // Device error bit 8 goes to *err when a look-back gives up.
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
-                    int32_t *err = nullptr, const float4 *gsrc = nullptr, float4 *gdst = nullptr);
+                    int32_t *err = nullptr, const float4 *gsrc = nullptr, float4 *gdst = nullptr,
+                    bool vals_iota = false);
 bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits, int32_t *err = nullptr);
 
 // Segmented sort: K independent key ranges [coff[s], coff[s+1]), each sorted
@@ -365,7 +367,8 @@ struct RsSegs {
 // whether the segmented one-launch-per-pass sort takes n keys in `ntiles` tiles
 bool radix_sort_seg_fits(int64_t n, int ntiles);
 bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
-                        int32_t *err, const RsSegs &sg, const float4 *gsrc = nullptr, float4 *gdst = nullptr);
+                        int32_t *err, const RsSegs &sg, const float4 *gsrc = nullptr, float4 *gdst = nullptr,
+                        bool vals_iota = false);
 bool radix_sort_u64v(fl_ctx *c, uint64_t *k, int32_t *v, uint64_t *kt, int32_t *vt, int64_t n, int nbits,
                      int32_t *err = nullptr);
 

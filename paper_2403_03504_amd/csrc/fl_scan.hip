@@ -258,7 +258,7 @@ __device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restri
         int64_t idx = wbase + (int64_t)st * WAVE + lane;
         bool ok = idx < t1;
         key[st] = ok ? kin[idx] : K(0);
-        if (HasVal) val[st] = ok ? vin[idx] : 0;
+        if (HasVal) val[st] = ok ? (vin ? vin[idx] : (int32_t)idx) : 0;  // no input payload: the index
         dig[st] = ok ? (int)((key[st] >> shift) & (RS_BINS - 1)) : -1;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
 
 template <class K, bool HasVal>
 bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag,
-                int32_t *err, const float4 *gsrc = nullptr, float4 *gdst = nullptr)
+                int32_t *err, const float4 *gsrc = nullptr, float4 *gdst = nullptr, bool vals_iota = false)
 {
     if (n <= 0) return false;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
@@ -596,7 +596,8 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
                            (const uint32_t *)part, nblocks, passes, gh, pfx0);
         for (int ps = 0; ps < passes; ++ps) {
             hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
-                               (const int32_t *)va, kb, vb, n, ps * RS_BITS, (const uint32_t *)(gh + ps * RS_BINS), 0,
+                               (const int32_t *)(ps == 0 && vals_iota ? nullptr : va), kb, vb, n, ps * RS_BITS,
+                               (const uint32_t *)(gh + ps * RS_BINS), 0,
                                status + (int64_t)ps * nblocks * RS_BINS, ticket + ps,
                                ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
                                ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr, RsSegs{});
@@ -613,7 +614,8 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
         int shift = ps * RS_BITS;
         hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, n, shift, hist, nblocks);
         scan_excl<int32_t>(c, hist, hscan, (int64_t)RS_BINS * nblocks, nullptr, tag);
-        hipLaunchKernelGGL((k_rs_scatter<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, va, kb, vb, n,
+        hipLaunchKernelGGL((k_rs_scatter<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, ka,
+                           ps == 0 && vals_iota ? nullptr : va, kb, vb, n,
                            shift, hscan, nblocks, ps == passes - 1 ? gsrc : nullptr,
                            ps == passes - 1 ? gdst : nullptr);
         FL_LAUNCH_CHECK();
@@ -661,7 +663,7 @@ void scan_excl_f64(fl_ctx *c, const double *in, double *out, int64_t n, const in
 bool radix_sort_seg_fits(int64_t n, int ntiles) { return n > 0 && ntiles >= 1 && ntiles <= RS_LOOKBACK_TILES; }
 
 bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
-                        int32_t *err, const RsSegs &sg, const float4 *gsrc, float4 *gdst)
+                        int32_t *err, const RsSegs &sg, const float4 *gsrc, float4 *gdst, bool vals_iota)
 {
     if (n <= 0) return false;
     const int passes = (nbits + RS_BITS - 1) / RS_BITS;
@@ -685,7 +687,8 @@ bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_
     int32_t *va = v, *vb = vt;
     for (int ps = 0; ps < passes; ++ps) {
         hipLaunchKernelGGL((k_rs_onesweep<uint32_t, true>), dim3(nt), dim3(RS_NT), 0, c->stream,
-                           (const uint32_t *)ka, (const int32_t *)va, kb, vb, n, ps * RS_BITS,
+                           (const uint32_t *)ka, (const int32_t *)(ps == 0 && vals_iota ? nullptr : va), kb, vb, n,
+                           ps * RS_BITS,
                            (const uint32_t *)(gh + ps * RS_BINS), (int)per, status + (int64_t)ps * nt * RS_BINS,
                            ticket + ps, ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
                            ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr, sg);
@@ -697,9 +700,9 @@ bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_
 }
 
 bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int nbits,
-                    int32_t *err, const float4 *gsrc, float4 *gdst)
+                    int32_t *err, const float4 *gsrc, float4 *gdst, bool vals_iota)
 {
-    return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32", err, gsrc, gdst);
+    return radix_sort<uint32_t, true>(c, k, v, kt, vt, n, nbits, "u32", err, gsrc, gdst, vals_iota);
 }
 
 bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits, int32_t *err)

@@ -1097,14 +1097,15 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     // words left there under another key layout could pass its epoch test
     const int64_t hkey_slots = (int64_t)(c->bufs["t_hkey"].cap / sizeof(uint64_t));
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
-                       (const double *)t.root, bits, s.K > 1 && !seg ? nullptr : k0, q0, i0, (const uint32_t *)t.epoch,
+                       (const double *)t.root, bits, s.K > 1 && !seg ? nullptr : k0, q0, q0 ? i0 : nullptr,
+                       (const uint32_t *)t.epoch,
                        t.hkey, hkey_slots, deg, xym, t.counts, xy_out);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
     if (seg) {
         // the last pass also moves every node's record to its sorted place
         const bool alt = radix_sort_u32_seg(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3, s.sort,
-                                            (const float4 *)xym, t.part);
+                                            (const float4 *)xym, t.part, true);
         sk = alt ? k1 : k0;
     } else if (s.K > 1) {
         const bool alt = radix_sort_u64v(c, q0, i0, q1, i1, n, 32 + s.cbits, t.counts + 3);
@@ -1115,7 +1116,8 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
                            t.part, sq, sk);
     } else {
         // the last pass also moves every node's record to its sorted place
-        const bool alt = radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3, (const float4 *)xym, t.part);
+        const bool alt =
+            radix_sort_u32(c, k0, i0, k1, i1, n, 2 * bits, t.counts + 3, (const float4 *)xym, t.part, true);
         sk = alt ? k1 : k0;
     }
     t.skey = sk;
@@ -1238,12 +1240,6 @@ void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits,
     FL_LAUNCH_CHECK();
 }
 
-__global__ void k_iota(int32_t *p, int n)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = i;
-}
-
 }  // namespace fl
 
 using namespace fl;
@@ -1267,10 +1263,9 @@ fl_status fl_sort_keys(fl_ctx *c, int32_t n, const uint32_t *key, int32_t bits, 
     uint32_t *kt = ws<uint32_t>(c, "sk_kt", n);
     int32_t *vt = ws<int32_t>(c, "sk_vt", n);
     FL_CHECK_HIP(hipMemcpyAsync(key_out, key, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, perm, n);
-    FL_LAUNCH_CHECK();
     int32_t *err = ws_zeroed<int32_t>(c, "sk_err", 1);
-    bool alt = radix_sort_u32(c, key_out, perm, kt, vt, n, 2 * bits, err);
+    // bits >= 1: at least one pass, which writes every payload (the indices)
+    bool alt = radix_sort_u32(c, key_out, perm, kt, vt, n, 2 * bits, err, nullptr, nullptr, true);
     if (read_i32(c, err)) {
         FL_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
         throw Error(FL_EHIP, "fl_sort_keys: the sort's look-back gave up");

@@ -391,16 +391,12 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int n, uint64_
     return lo;
 }
 
-// first cell whose first particle is >= v (cells are sorted by begin)
-__device__ __forceinline__ int first_cell_from(const int32_t *beg, int ncells, int v)
+// first cell (pre-order) whose first particle is >= v: the number of cells
+// started by the particles before v (cells are numbered particle by particle)
+__device__ __forceinline__ int first_cell_from(const int64_t *__restrict__ off2, const int64_t *__restrict__ bpre,
+                                               int n, int ncells, int v)
 {
-    int lo = 0, hi = ncells;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (beg[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+    return v < n ? (int)(tree_offset(off2, bpre, v) & 0xFFFFFFFFll) : ncells;
 }
 
 __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, const int64_t *__restrict__ off2,
@@ -416,7 +412,7 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
     if (l == 0) {
         const int e0 = t.s.K > 1 ? t.s.coff[comp + 1] : n;
         t.end[id] = e0;
-        t.skip[id] = first_cell_from(t.beg, ncells, e0);
+        t.skip[id] = first_cell_from(off2, bpre, n, ncells, e0);
         return;
     }
     int k = t.beg[id];
@@ -429,7 +425,7 @@ __global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, co
     int j = lower_bound_u64(t.start_key, nleaves, T);
     const int eid = j < nleaves ? t.start_pos[j] : n;
     t.end[id] = eid;
-    t.skip[id] = first_cell_from(t.beg, ncells, eid);
+    t.skip[id] = first_cell_from(off2, bpre, n, ncells, eid);
     int p = t.par[id];
     if (p == -2) {
         uint64_t Tp = cs | ((uint64_t)(pre >> 2) << (sh + 2));
@@ -465,7 +461,8 @@ struct CountSink {
 // bits) are kept in LDS and written out per cell, so that the filling pass
 // replays them instead of enumerating the ring again (a chain of dependent
 // lookups); a lane with more entries enumerates again.
-constexpr int LIST_SLOTS = 8;
+constexpr int LIST_SLOTS = 16;
+constexpr int LIST_SLOT_Q = LIST_SLOTS / 4;  // int4 words per (cell, lane)
 struct SlotSink {
     using lds_i32 = __attribute__((address_space(3))) int32_t;
     lds_i32 *slot;
@@ -500,9 +497,15 @@ struct SlotSink {
 template <class Sink>
 __device__ __forceinline__ void replay_slots(const int4 *__restrict__ gs, int tot, Sink &sk)
 {
-    const int4 a = gs[0];
-    const int4 b = tot > 4 ? gs[1] : make_int4(0, 0, 0, 0);
-    const int e[LIST_SLOTS] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    int e[LIST_SLOTS];
+#pragma unroll
+    for (int q = 0; q < LIST_SLOT_Q; ++q) {
+        const int4 a = 4 * q < tot ? gs[q] : make_int4(0, 0, 0, 0);
+        e[4 * q] = a.x;
+        e[4 * q + 1] = a.y;
+        e[4 * q + 2] = a.z;
+        e[4 * q + 3] = a.w;
+    }
 #pragma unroll
     for (int i = 0; i < LIST_SLOTS; ++i) {
         if (i < tot) {
@@ -691,9 +694,10 @@ __global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__rest
                 const int tot = cV + cX + cU + cW;
                 if (slots && tot > 0) {  // the lane's own LDS row: no synchronisation needed
                     const int32_t *r = slot_lds[threadIdx.x];
-                    int4 *gs = slots + ((int64_t)c * LANES + q) * 2;
-                    gs[0] = make_int4(r[0], r[1], r[2], r[3]);
-                    if (tot > 4) gs[1] = make_int4(r[4], r[5], r[6], r[7]);
+                    int4 *gs = slots + ((int64_t)c * LANES + q) * LIST_SLOT_Q;
+#pragma unroll
+                    for (int w4 = 0; w4 < LIST_SLOT_Q; ++w4)
+                        if (4 * w4 < tot) gs[w4] = make_int4(r[4 * w4], r[4 * w4 + 1], r[4 * w4 + 2], r[4 * w4 + 3]);
                 }
             }
         } else {
@@ -808,7 +812,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
             FillSink sk{V + (o & 0xFFFFFFFFll) + pV, X + (o >> 32) + pX, (staged ? st : u0) + 1 + pU,
                         W + (ou >> 32) + pW, t.beg, t.end, staged};
             if (LANES > 1 && tot <= LIST_SLOTS) {
-                if (tot > 0) replay_slots(slots + ((int64_t)c * LANES + q) * 2, tot, sk);
+                if (tot > 0) replay_slots(slots + ((int64_t)c * LANES + q) * LIST_SLOT_Q, tot, sk);
             } else {
                 enumerate_part<LANES>(t, H, ep, c, q, sk);
             }
@@ -1167,8 +1171,8 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     const bool wide = lanes == 8;
     const unsigned lg = grid_for(cap, wide ? 256 / 8 : 256, 4096);
     int64_t *lanecnt = wide ? ws<int64_t>(c, "l_lanecnt", (size_t)cap * 8) : nullptr;
-    // entry slots: two int4 per (cell, lane); cell ids must leave the tag bits free
-    int4 *slots = wide && cap < (int64_t(1) << 30) ? ws<int4>(c, "l_slots", (size_t)cap * 8 * 2) : nullptr;
+    // entry slots: LIST_SLOT_Q int4 per (cell, lane); cell ids must leave the tag bits free
+    int4 *slots = wide && cap < (int64_t(1) << 30) ? ws<int4>(c, "l_slots", (size_t)cap * 8 * LIST_SLOT_Q) : nullptr;
     if (wide)
         hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt, slots);
     else

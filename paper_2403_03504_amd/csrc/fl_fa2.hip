@@ -318,17 +318,30 @@ __global__ __launch_bounds__(NT) void k_speed(Segs sg, const double2 *__restrict
     }
 }
 
+// With `bpart` every block also writes the extrema of its nodes' new
+// positions (min x, max x, min y, max y): the next iteration's bounding
+// square, so that the tree build need not read the positions again.
 __global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, float *__restrict__ y,
                                                const float *__restrict__ fx, const float *__restrict__ fy,
                                                float *__restrict__ fpx, float *__restrict__ fpy, int first,
                                                const double *__restrict__ scalars, double ks, double ksmax,
-                                               int32_t *__restrict__ flags)
+                                               int32_t *__restrict__ flags, float4 *__restrict__ bpart)
 {
     const int2 tl = sg.tiles[blockIdx.x / TILE_SUB];
     const int comp = tl.x;
-    if (flags[comp] & 1) return;  // non-finite forces: this system stays as it was
     const int b0 = tl.y + (int)(blockIdx.x % TILE_SUB) * (SEG_TILE / TILE_SUB);
     const int b1 = min(b0 + SEG_TILE / TILE_SUB, sg.coff[comp + 1]);
+    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+    if (flags[comp] & 1) {  // non-finite forces: this system stays as it was
+        if (bpart)
+            for (int i = b0 + threadIdx.x; i < b1; i += NT) {
+                const float px = x[i], py = y[i];
+                mnx = fminf(mnx, px);
+                mxx = fmaxf(mxx, px);
+                mny = fminf(mny, py);
+                mxy = fmaxf(mxy, py);
+            }
+    } else {
     const double sG = scalars[4 * (int64_t)comp];
     for (int i = b0 + threadIdx.x; i < b1; i += NT) {
         const float Fx = fx[i], Fy = fy[i];
@@ -345,6 +358,29 @@ __global__ __launch_bounds__(NT) void k_update(Segs sg, float *__restrict__ x, f
         fpx[i] = Fx;
         fpy[i] = Fy;
         if (!isfinite(nx) || !isfinite(ny)) atomicOr(flags + comp, 2);
+        mnx = fminf(mnx, nx);
+        mxx = fmaxf(mxx, nx);
+        mny = fminf(mny, ny);
+        mxy = fmaxf(mxy, ny);
+    }
+    }
+    if (!bpart) return;
+    __shared__ float4 red[NT / WAVE];
+    mnx = wave_min_f(mnx);
+    mxx = wave_max_f(mxx);
+    mny = wave_min_f(mny);
+    mxy = wave_max_f(mxy);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = make_float4(mnx, mxx, mny, mxy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float4 r = red[0];
+        for (int w = 1; w < NT / WAVE; ++w) {
+            r.x = fminf(r.x, red[w].x);
+            r.y = fmaxf(r.y, red[w].y);
+            r.z = fminf(r.z, red[w].z);
+            r.w = fmaxf(r.w, red[w].w);
+        }
+        bpart[blockIdx.x] = r;
     }
 }
 
@@ -508,7 +544,7 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
 
 static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float *x, const float *y,
                       const fl_fa2_params *p, float2 *fr, const std::function<void(hipEvent_t)> *on_lists = nullptr,
-                      float2 *xy_out = nullptr)
+                      float2 *xy_out = nullptr, BBoxIn bb = {})
 {
     if (p->repulsion == FL_REP_EXACT) {
         PhaseTimer pt(c, FL_PH_EXACT);
@@ -518,7 +554,7 @@ static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float
     } else {
         const int lanes = p->list_lanes ? p->list_lanes : default_list_lanes(sg.n);
         fmm_repulsion(c, sg, x, y, g.deg, p->p, p->leaf_size, p->morton_bits, lanes, (float)p->kr, fr, on_lists,
-                      xy_out);
+                      xy_out, bb);
     }
 }
 
@@ -542,6 +578,9 @@ struct Sys {
     // one status word per system (bit 0: a non-finite force, bit 1: a
     // non-finite position), cleared by the caller before the first iteration
     int32_t *flags;
+    // the last iteration's update wrote the tile extrema of the positions
+    // (FMM runs): the next tree build takes them instead of reading x, y
+    bool bbox_ready = false;
 };
 
 // one iteration; b.flags must have been cleared by the caller.  Unless phases
@@ -562,6 +601,12 @@ static void iteration(Sys &b, double *ring, int ring_it)
     double2 *part = ws<double2>(c, "fa2_part", (size_t)b.sg.ntiles * TILE_SUB);
     double2 *csum = ws<double2>(c, "at_csum", b.ap.cap);
     const int first = b.st.iter == 0 ? 1 : 0;
+    // FMM: the update leaves the tile extrema of the new positions for the
+    // next iteration's bounding square
+    float4 *bpart = b.prm.repulsion != FL_REP_EXACT
+                        ? ws<float4>(c, "fa2_bbox_part", (size_t)b.sg.ntiles * TILE_SUB)
+                        : nullptr;
+    const BBoxIn bb = b.bbox_ready ? BBoxIn{bpart, TILE_SUB} : BBoxIn{};
     const float2 *xy = nullptr;
     double2 *asum = nullptr;
     if (!c->timing && c->branches) {
@@ -583,12 +628,12 @@ static void iteration(Sys &b, double *ring, int ring_it)
             side(c->ev_fork);
             repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
         } else {
-            repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, &side, ws<float2>(c, "at_xy", n));
+            repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, &side, ws<float2>(c, "at_xy", n), bb);
         }
         if (!xy) throw Error(FL_EHIP, "iteration: the attraction branch was not forked");
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
     } else {
-        repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
+        repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, nullptr, nullptr, bb);
     }
     {
         PhaseTimer pt(c, FL_PH_ATTRACT);
@@ -607,9 +652,10 @@ static void iteration(Sys &b, double *ring, int ring_it)
         PhaseTimer pt(c, FL_PH_UPDATE);
         hipLaunchKernelGGL(k_update, dim3(b.sg.ntiles * TILE_SUB), dim3(NT), 0, c->stream, b.sg, b.x, b.y,
                            (const float *)fcx, (const float *)fcy, b.st.fx_prev, b.st.fy_prev, first,
-                           (const double *)b.st.scalars, b.prm.ks, b.prm.ksmax, flags);
+                           (const double *)b.st.scalars, b.prm.ks, b.prm.ksmax, flags, bpart);
         FL_LAUNCH_CHECK();
     }
+    b.bbox_ready = bpart != nullptr;
     b.st.iter += 1;
 }
 

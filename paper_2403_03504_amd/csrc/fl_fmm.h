@@ -17,9 +17,10 @@ bool fmm_order_supported(int p);
 // with an event recorded on the context stream just after it: work that
 // should overlap the near field (and not the latency-bound tree build) is
 // forked from there.  xy_out (optional, n float2) receives the (x, y) pairs
-// from the tree build.
+// from the tree build; bb: the positions' tile extrema when already known.
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
                    int bits, int lanes, float kr, float2 *fr,
-                   const std::function<void(hipEvent_t)> *on_lists = nullptr, float2 *xy_out = nullptr);
+                   const std::function<void(hipEvent_t)> *on_lists = nullptr, float2 *xy_out = nullptr,
+                   BBoxIn bb = {});
 
 }  // namespace fl

@@ -819,12 +819,12 @@ bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 |
 
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
                    int bits, int lanes, float kr, float2 *fr, const std::function<void(hipEvent_t)> *on_lists,
-                   float2 *xy_out)
+                   float2 *xy_out, BBoxIn bb)
 {
     TreeBufs t;
     {
         PhaseTimer pt(c, FL_PH_TREE);
-        build_tree(c, t, s, x, y, deg, bits, leaf, xy_out);
+        build_tree(c, t, s, x, y, deg, bits, leaf, xy_out, bb);
     }
     switch (p) {
     case 4: fmm_passes<4>(c, t, lanes, kr, fr, on_lists); break;

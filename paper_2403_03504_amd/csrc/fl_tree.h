@@ -124,8 +124,15 @@ int64_t cells_capacity(int64_t n, int leaf, int bits, int K = 1);
 // sorted particles -> forest.  deg may be null (unit masses).  All on the
 // context stream, no host synchronisation.
 // xy_out (optional, n float2): the (x, y) pairs as well, for the attraction.
+// Extrema of the positions per tile, already known (the ForceAtlas2 update
+// writes them for the next iteration): `per` float4 (min x, max x, min y,
+// max y) per tile of the Segs, in tile order.  Null: computed by the build.
+struct BBoxIn {
+    const float4 *part = nullptr;
+    int per = 1;
+};
 void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
-                int leaf, float2 *xy_out = nullptr);
+                int leaf, float2 *xy_out = nullptr, BBoxIn bb = {});
 // lanes: lanes per cell of the list kernels, 1 or 8 (the same lists either way)
 void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes);
 // The lists' statistics (counts, near pairs) into the context's counters;

@@ -84,7 +84,9 @@ __device__ __forceinline__ int common_digits(uint32_t a, uint32_t b, int bits)
 // k_bbox: the extrema of every tile (tiles never straddle two systems);
 // k_bbox_root: one block per system combines its tiles' extrema (min/max are
 // exact, so the order does not matter) into the system's root square.  Two
-// launches and no device-scope fences.
+// launches and no device-scope fences.  Within a ForceAtlas2 run the update
+// of the previous iteration has written the extrema (`per` per tile) and
+// k_bbox is skipped.
 __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const float *__restrict__ y, Segs sg,
                                              float4 *__restrict__ partial)
 {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(NT) void k_bbox(const float *__restrict__ x, const 
 
 // Block k finishes the root squares of systems k, k + gridDim.x, ...; block 0
 // also advances the hash epoch (when there is a table).
-__global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restrict__ partial,
+__global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restrict__ partial, int per,
                                                   double *__restrict__ root, int bits, uint32_t *__restrict__ epoch)
 {
     __shared__ float4 red[NT / WAVE];
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restr
         *epoch = e;
     }
     for (int comp = blockIdx.x; comp < sg.K; comp += gridDim.x) {
-        const int t0 = sg.tile_off[comp], nt = sg.tile_off[comp + 1] - t0;
+        const int t0 = per * sg.tile_off[comp], nt = per * sg.tile_off[comp + 1] - t0;
         float4 q = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
         for (int j = threadIdx.x; j < nt; j += NT) {
             const float4 v = partial[t0 + j];
@@ -1031,7 +1033,7 @@ Segs make_segs(fl_ctx *c, const std::vector<int32_t> &coff, const char *tag) { r
 namespace {
 
 void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg,
-                     int bits, int leaf, float2 *xy_out)
+                     int bits, int leaf, float2 *xy_out, BBoxIn bb)
 {
     const int n = s.n;
     t.n = n;
@@ -1092,9 +1094,12 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
         c->tree_cbits = s.cbits;
     }
 
-    hipLaunchKernelGGL(k_bbox, dim3(s.ntiles), dim3(NT), 0, c->stream, x, y, s, bpart);
-    hipLaunchKernelGGL(k_bbox_root, dim3(std::min(s.K, 1024)), dim3(NT), 0, c->stream, s, (const float4 *)bpart,
-                       t.root, bits, t.epoch);
+    if (!bb.part) {
+        hipLaunchKernelGGL(k_bbox, dim3(s.ntiles), dim3(NT), 0, c->stream, x, y, s, bpart);
+        bb = BBoxIn{bpart, 1};
+    }
+    hipLaunchKernelGGL(k_bbox_root, dim3(std::min(s.K, 1024)), dim3(NT), 0, c->stream, s, bb.part, bb.per, t.root,
+                       bits, t.epoch);
     float4 *xym = ws<float4>(c, "t_xym", n);
     // a restarted epoch clears every slot the table holds, not only this
     // build's: a later, larger build probes slots past this one's range, and
@@ -1140,9 +1145,9 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
 }  // namespace
 
 void build_tree(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, const float *y, const int32_t *deg, int bits,
-                int leaf, float2 *xy_out)
+                int leaf, float2 *xy_out, BBoxIn bb)
 {
-    build_tree_impl(c, t, s, x, y, deg, bits, leaf, xy_out);
+    build_tree_impl(c, t, s, x, y, deg, bits, leaf, xy_out, bb);
 }
 
 // eight lanes measured faster at every size tried (15k-node components up to
@@ -1235,7 +1240,7 @@ void morton_keys(fl_ctx *c, int32_t n, const float *x, const float *y, int bits,
     float4 *bpart = ws<float4>(c, "t_bbox_part", (size_t)sg.ntiles);
     // no tree is built: leave the hash epoch alone
     hipLaunchKernelGGL(k_bbox, dim3(sg.ntiles), dim3(NT), 0, c->stream, x, y, sg, bpart);
-    hipLaunchKernelGGL(k_bbox_root, dim3(1), dim3(NT), 0, c->stream, sg, (const float4 *)bpart, root, bits,
+    hipLaunchKernelGGL(k_bbox_root, dim3(1), dim3(NT), 0, c->stream, sg, (const float4 *)bpart, 1, root, bits,
                        (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, (const int32_t *)nullptr,
                        (const double *)root, bits, key, (uint64_t *)nullptr, (int32_t *)nullptr,

@@ -473,22 +473,41 @@ constexpr int P2P_STAGE = WAVE + P2P_GMAX;  // staged sources plus zero-mass pad
 // sources interleaved mod G.  A round of G sources costs 64 T lane slots and
 // does G n pairs; the shape with the most pairs per slot wins (the smaller
 // T on a tie).  G = 1 is the plain one-target-per-lane wave.
+// The shapes of all chunk sizes 1..64, fixed at compile time (T | L << 8 |
+// G << 16): a chunk reads its shape with one scalar load instead of dividing.
+struct P2PShapes {
+    uint32_t v[WAVE + 1];
+};
+
+constexpr P2PShapes p2p_shape_table()
+{
+    P2PShapes s{};
+    for (int n = 1; n <= WAVE; ++n) {
+        int T = 1, L = n, G = WAVE / n < P2P_GMAX ? WAVE / n : P2P_GMAX;
+        int best = G * n * 12;  // pairs per round x 12 / T (12: a common multiple of 1..4)
+        for (int t = 2; t <= 4; ++t) {
+            const int l = (n + t - 1) / t, g = WAVE / l < P2P_GMAX ? WAVE / l : P2P_GMAX;
+            const int v = g * n * 12 / t;
+            if (v > best) {
+                best = v;
+                T = t;
+                L = l;
+                G = g;
+            }
+        }
+        s.v[n] = (uint32_t)T | ((uint32_t)L << 8) | ((uint32_t)G << 16);
+    }
+    return s;
+}
+
+__constant__ P2PShapes P2P_SHAPE = p2p_shape_table();
+
 __device__ __forceinline__ void p2p_shape(int n, int &T, int &L, int &G)
 {
-    T = 1;
-    L = n;
-    G = min(P2P_GMAX, WAVE / n);
-    int best = G * n * 12;  // pairs per round x 12 / T (12: a common multiple of 1..4)
-    for (int t = 2; t <= 4; ++t) {
-        const int l = (n + t - 1) / t, g = min(P2P_GMAX, WAVE / l);
-        const int v = g * n * 12 / t;
-        if (v > best) {
-            best = v;
-            T = t;
-            L = l;
-            G = g;
-        }
-    }
+    const uint32_t v = P2P_SHAPE.v[n];
+    T = (int)(v & 0xFFu);
+    L = (int)((v >> 8) & 0xFFu);
+    G = (int)(v >> 16);
 }
 
 // One chunk of a leaf's targets (t0 .. t0 + n) in lane groups: lane (g, r)
@@ -501,7 +520,9 @@ __device__ __forceinline__ void p2p_groups(const float4 *__restrict__ part, cons
                                            float2 *__restrict__ near, int32_t *__restrict__ pleaf, int li)
 {
     const int lane = lane_id();
-    const int grp = lane / L, r = lane - grp * L;
+    // lane / L through FP32: lane + 0.5 is at least 0.5 / L away from every
+    // multiple of L, far more than the rounding of the product
+    const int grp = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)L)), r = lane - grp * L;
     const int gr = grp < G ? grp : 0;
     float4 me[T];
     float fx[T], fy[T];

@@ -72,8 +72,7 @@ struct TreeBufs {
     uint64_t *start_key = nullptr;  // system << 32 | Morton key of each cell-start particle
     int32_t *start_pos = nullptr, *start_D = nullptr;
     int32_t *counts = nullptr;     // [0] cells, [1] leaves, [2] max level, [3] error bits
-    uint64_t *hkey = nullptr;
-    int32_t *hval = nullptr;
+    uint64_t *hslot = nullptr;     // 2 words per slot: key, cell id (one 16-byte read per probe)
     uint32_t *epoch = nullptr;     // device epoch of the hash table
     int64_t *off2 = nullptr;       // per particle (cells, starts) packed prefix
     int32_t *pack = nullptr;       // per particle (D+1) | lambda << 8
@@ -103,8 +102,7 @@ struct TreeView {
     const int4 *child;
     const int32_t *leaf_cell;
     const int32_t *counts;
-    const uint64_t *hkey;
-    const int32_t *hval;
+    const uint64_t *hslot;
     const uint32_t *epoch;
     int64_t hash_cap;
 };
@@ -113,7 +111,7 @@ inline TreeView view(const TreeBufs &t)
 {
     return TreeView{t.n,       t.bits,  t.leaf,      t.s.K,    t.s.cbits, t.s.coff, t.ccomp,
                     t.root,    t.part,  t.lvl,       t.ixy,    t.beg,     t.end,    t.par,
-                    t.leafidx, t.skip,  t.child,     t.leaf_cell, t.counts, t.hkey, t.hval,
+                    t.leafidx, t.skip,  t.child,     t.leaf_cell, t.counts, t.hslot,
                     t.epoch,   t.hash_cap};
 }
 
@@ -203,9 +201,9 @@ __device__ __forceinline__ int hash_find(const TreeView &t, int64_t H, uint64_t 
     uint64_t k = hash_key(comp, level, ix, iy) | (ep << sh);
     int64_t h = (int64_t)(mix64(k & ((1ull << sh) - 1)) & (uint64_t)(H - 1));
     for (int64_t probe = 0; probe < H; ++probe) {
-        uint64_t v = t.hkey[h];
-        if ((v >> sh) != ep) return -1;
-        if (v == k) return t.hval[h];
+        const ulonglong2 e = reinterpret_cast<const ulonglong2 *>(t.hslot)[h];  // key and cell id together
+        if ((e.x >> sh) != ep) return -1;
+        if (e.x == k) return (int)e.y;
         h = (h + 1) & (H - 1);
     }
     return -1;

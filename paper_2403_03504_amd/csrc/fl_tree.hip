@@ -180,14 +180,14 @@ __global__ __launch_bounds__(NT) void k_bbox_root(Segs sg, const float4 *__restr
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, int n,
                          const int32_t *__restrict__ ncomp, const double *__restrict__ root, int bits,
                          uint32_t *__restrict__ key, uint64_t *__restrict__ key64, int32_t *__restrict__ idx,
-                         const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hkey, int64_t hcap,
+                         const uint32_t *__restrict__ epoch, uint64_t *__restrict__ hslot, int64_t hcap,
                          const int32_t *__restrict__ deg, float4 *__restrict__ xym, int32_t *__restrict__ counts,
                          float2 *__restrict__ xy)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (counts && i < 3) counts[i] = 0;  // the tree's cell, leaf and level counts ([3], the error bits, is sticky)
-    if (hkey && epoch && *epoch == 1u)
-        for (int64_t h = i; h < hcap; h += (int64_t)gridDim.x * blockDim.x) hkey[h] = 0ull;
+    if (hslot && epoch && *epoch == 1u)
+        for (int64_t h = i; h < hcap; h += (int64_t)gridDim.x * blockDim.x) hslot[2 * h] = 0ull;  // the keys
     if (i >= n) return;
     const int comp = ncomp ? ncomp[i] : 0;
     const double *rt = root + 4 * (int64_t)comp;
@@ -367,15 +367,15 @@ __device__ __forceinline__ void hash_insert(const TreeBufs &t, int64_t H, uint64
     const uint64_t kk = hk | (ep << sh);
     int64_t h = (int64_t)(mix64(hk) & (uint64_t)(H - 1));
     for (int64_t probe = 0; probe < H; ++probe) {
-        const uint64_t old = t.hkey[h];
+        const uint64_t old = t.hslot[2 * h];
         if ((old >> sh) == ep) {
             h = (h + 1) & (H - 1);
             continue;
         }
         const unsigned long long prev =
-            atomicCAS((unsigned long long *)&t.hkey[h], (unsigned long long)old, (unsigned long long)kk);
+            atomicCAS((unsigned long long *)&t.hslot[2 * h], (unsigned long long)old, (unsigned long long)kk);
         if (prev == old) {
-            t.hval[h] = id;
+            t.hslot[2 * h + 1] = (uint64_t)(uint32_t)id;
             break;
         }
         --probe;  // lost the slot to another insert: look at it again
@@ -1080,8 +1080,7 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     t.start_pos = ws<int32_t>(c, "t_spos", lcap);
     t.start_D = ws<int32_t>(c, "t_sD", lcap);
     t.counts = ws_zeroed<int32_t>(c, "t_counts", 4);
-    t.hkey = ws_zeroed<uint64_t>(c, "t_hkey", hc);
-    t.hval = ws<int32_t>(c, "t_hval", hc);
+    t.hslot = ws_zeroed<uint64_t>(c, "t_hslot", 2 * (size_t)hc);
     t.pack = ws<int32_t>(c, "t_pack", n);
     t.off2 = ws<int64_t>(c, "t_off2", (size_t)n);
     const size_t nblk_t = (size_t)grid_for(n, T1_TB);
@@ -1104,11 +1103,11 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     // a restarted epoch clears every slot the table holds, not only this
     // build's: a later, larger build probes slots past this one's range, and
     // words left there under another key layout could pass its epoch test
-    const int64_t hkey_slots = (int64_t)(c->bufs["t_hkey"].cap / sizeof(uint64_t));
+    const int64_t hkey_slots = (int64_t)(c->bufs["t_hslot"].cap / (2 * sizeof(uint64_t)));
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, x, y, n, s.ncomp,
                        (const double *)t.root, bits, s.K > 1 && !seg ? nullptr : k0, q0, q0 ? i0 : nullptr,
                        (const uint32_t *)t.epoch,
-                       t.hkey, hkey_slots, deg, xym, t.counts, xy_out);
+                       t.hslot, hkey_slots, deg, xym, t.counts, xy_out);
     FL_LAUNCH_CHECK();
     uint32_t *sk;
     if (seg) {

@@ -436,32 +436,41 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ key
             part[((int64_t)blockIdx.x * passes + p) * RS_BINS + threadIdx.x] = cnt[p][threadIdx.x];
 }
 
-// Sums the per-tile counts: one wave per (pass, digit) entry, its lanes
-// over the tiles, then a wave sum (integers: the order does not matter).
-// The first pass's tiles are the input's own, so for it the wave also
-// writes every tile's exclusive prefix of the digit (pfx0[tile][digit]):
-// that pass needs no look-back.
+// Sums the per-tile counts: one block per (pass, digit) entry, its waves
+// over consecutive runs of tiles, then the waves' totals in wave order
+// (integers: the order does not matter).  The first pass's tiles are the
+// input's own, so for it the block also writes every tile's exclusive prefix
+// of the digit (pfx0[tile][digit]): that pass needs no look-back.
 __global__ __launch_bounds__(RS_NT) void k_rs_hist_sum(const uint32_t *__restrict__ part, int ntiles, int passes,
                                                         uint32_t *__restrict__ gh, uint32_t *__restrict__ pfx0)
 {
-    const int i = blockIdx.x * RS_NW + threadIdx.x / WAVE;  // pass * 256 + digit
-    if (i >= passes * RS_BINS) return;
+    __shared__ uint32_t wt[RS_NW];
+    const int i = blockIdx.x;  // pass * 256 + digit
     const int64_t st = (int64_t)passes * RS_BINS;
-    const int lane = lane_id();
+    const int lane = lane_id(), w = threadIdx.x / WAVE;
+    const int per = ((ntiles + RS_NW - 1) / RS_NW + WAVE - 1) / WAVE * WAVE;  // tiles per wave
+    const int tb = w * per, te = min(ntiles, tb + per);
     uint32_t sum = 0u;
-    if (i < RS_BINS) {
-        for (int b0 = 0; b0 < ntiles; b0 += WAVE) {
-            const int b = b0 + lane;
-            const uint32_t v = b < ntiles ? part[(int64_t)b * st + i] : 0u;
-            const uint32_t inc = wave_incl_scan(v);
-            if (b < ntiles) pfx0[(int64_t)b * RS_BINS + i] = sum + inc - v;
-            sum += __shfl(inc, WAVE - 1, WAVE);
-        }
-    } else {
-        for (int b = lane; b < ntiles; b += WAVE) sum += part[(int64_t)b * st + i];
-        sum = wave_sum(sum);
+    for (int b = tb + lane; b < te; b += WAVE) sum += part[(int64_t)b * st + i];
+    sum = wave_sum(sum);
+    if (lane == 0) wt[w] = sum;
+    __syncthreads();
+    uint32_t base = 0u, tot = 0u;
+    for (int k = 0; k < RS_NW; ++k) {
+        if (k < w) base += wt[k];
+        tot += wt[k];
     }
-    if (lane == 0) gh[i] = sum;
+    if (i < RS_BINS) {
+        // the wave's tiles again (now in cache), as exclusive prefixes
+        for (int b0 = tb; b0 < te; b0 += WAVE) {
+            const int b = b0 + lane;
+            const uint32_t v = b < te ? part[(int64_t)b * st + i] : 0u;
+            const uint32_t inc = wave_incl_scan(v);
+            if (b < te) pfx0[(int64_t)b * RS_BINS + i] = base + inc - v;
+            base += __shfl(inc, WAVE - 1, WAVE);
+        }
+    }
+    if (threadIdx.x == 0) gh[i] = tot;
 }
 
 // The same per system: one wave per (system, pass, digit) entry, its lanes
@@ -592,7 +601,7 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
         hipLaunchKernelGGL(k_rs_hist_all<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)k, n, passes, part,
                            status, nstatus, gh, nz, RsSegs{});
         uint32_t *pfx0 = ws<uint32_t>(c, (std::string("rs_pfx0_") + tag).c_str(), (size_t)nblocks * RS_BINS);
-        hipLaunchKernelGGL(k_rs_hist_sum, dim3(passes * RS_BINS / RS_NW), dim3(RS_NT), 0, c->stream,
+        hipLaunchKernelGGL(k_rs_hist_sum, dim3(passes * RS_BINS), dim3(RS_NT), 0, c->stream,
                            (const uint32_t *)part, nblocks, passes, gh, pfx0);
         for (int ps = 0; ps < passes; ++ps) {
             hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,

@@ -75,6 +75,43 @@ def test_noalloc_step_equals_step(rep):
         na.close()
 
 
+def test_noalloc_systems_equal_step():
+    """Independent systems in one state (component offsets): the forest
+    build sorts them as segments, with its sort tiles carved from the same
+    scratch array; bitwise fl_fa2_step's result."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_03504_amd import fa2lay as fl
+    from paper_2403_03504_amd import workloads as w
+    parts = [w.scaled(911, 9000), w.scaled(912, 4096, hubs_per_4000=False), w.small_component(913, 300)]
+    g, offs = w.union(parts)
+    ref, na = fl.Context(0), fl.Context(0)
+    try:
+        _note("noalloc vs step, systems", [p.n for p in parts])
+        G = ref.build_csr(g.n, dev(g.src), dev(g.dst))
+        prm = fl.default_params(repulsion=fl.REP_FMM, p=8, leaf_size=32)
+        rng = np.random.default_rng(914)
+        fx, fy = rng.normal(size=g.n).astype(np.float32), rng.normal(size=g.n).astype(np.float32)
+        states = []
+        for _ in range(2):
+            st = fl.FA2State.zeros(g.n, "cuda", comp_offsets=offs)
+            st.fx_prev.copy_(torch.from_numpy(fx))
+            st.fy_prev.copy_(torch.from_numpy(fy))
+            st.scalars[0::4] = torch.tensor([0.37, 0.5, 0.21], dtype=torch.float64)
+            st.iter = 3
+            states.append(st)
+        xa, ya, xb, yb = dev(g.x), dev(g.y), dev(g.x), dev(g.y)
+        ref.fa2_step(G, xa, ya, states[0], prm)
+        na.fa2_step_noalloc(G, xb, yb, states[1], prm)
+        for a, b in ((xa, xb), (ya, yb), (states[0].fx_prev, states[1].fx_prev),
+                     (states[0].fy_prev, states[1].fy_prev), (states[0].scalars, states[1].scalars)):
+            assert np.array_equal(host(a), host(b))
+        assert na.workspace_bytes() == 0
+    finally:
+        ref.close()
+        na.close()
+
+
 def test_noalloc_rejects_what_does_not_fit():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -591,6 +591,12 @@ def main() -> int:
                 "traffic_ratio": p2p_traffic / p2p_bytes if p2p_traffic else None,
                 "unpacked_fp32_peak": FP32_VALU_PEAK / 1e12,
                 "frac_of_unpacked_peak": achieved / FP32_VALU_PEAK,
+                # the pair loop's own ceiling: 8 wave instructions per pair
+                # (the reciprocal included: the VALU counters show it issuing
+                # at the full rate) for 11 FLOP, at one unpacked FP32
+                # instruction per lane per 4 cycles
+                "pair_loop_ceiling": 11.0 / 8.0 * FP32_VALU_PEAK / 2 / 1e12,
+                "frac_of_pair_loop_ceiling": achieved / (11.0 / 8.0 * FP32_VALU_PEAK / 2),
                 "flop_per_launch": eval_flop, "near_pairs_per_launch": pairs_per_launch,
                 "launch_ms": eval_ms,
                 "far": {"kernel": f"k_far<{args.p}>", "achieved_TFLOPs": far_flop / (far_ms * 1e-3) / 1e12,
@@ -603,6 +609,23 @@ def main() -> int:
                                "frac_hbm": attract_bytes / (attract_ms * 1e-3) / HBM_PEAK,
                                "gather_traffic": at_traffic, "gather_compulsory_bytes": gather_bytes,
                                "gather_traffic_ratio": at_traffic / gather_bytes if at_traffic else None}}
+    # the whole iteration against its roofs: each step's algorithmic work at
+    # its bound (ALU work at the FP32 peak, memory work at HBM bandwidth),
+    # summed, over the measured time per iteration.  Tree and list building
+    # are latency-bound and have no roof here (counted as zero).
+    p_ = float(args.p)
+    ideal_us = {
+        "near_field": eval_flop / FP32_PUBLISHED * 1e6,
+        "m2l": m2l_flop / FP32_PUBLISHED * 1e6,
+        "p2m_l2p": 16.0 * p_ * g.n / FP32_PUBLISHED * 1e6,
+        "m2m_l2l": 8.0 * (p_ + 1) ** 2 * fst["cells"] / FP32_PUBLISHED * 1e6,
+        "attraction": (4.0 * (g.n + 1) + 4.0 * nnz + 16.0 * g.n) / HBM_PEAK * 1e6,
+        "update_swing": 40.0 * g.n / HBM_PEAK * 1e6,
+        "sort": 4 * 2 * 8.0 * g.n / HBM_PEAK * 1e6,
+    }
+    iter_us = wall * 1e6 / args.steps
+    roofline["iteration"] = {"ideal_us": ideal_us, "ideal_total_us": sum(ideal_us.values()),
+                             "measured_us": iter_us, "frac": sum(ideal_us.values()) / iter_us}
 
     result = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,

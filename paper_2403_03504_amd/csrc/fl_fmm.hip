@@ -466,7 +466,11 @@ __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restric
     }
 
 constexpr int P2P_GMAX = 16;            // lane groups at most
+constexpr int P2P_TMAX = 8;             // targets per lane at most
 constexpr int P2P_STAGE = WAVE + P2P_GMAX;  // staged sources plus zero-mass padding
+// per wave, the staged sources (float4) during the source loop and the lane
+// groups' partial sums (float2, T per lane) after it share one LDS area
+constexpr int P2P_WAVE_LDS = (P2P_STAGE * 16 > WAVE * P2P_TMAX * 8 ? P2P_STAGE * 16 : WAVE * P2P_TMAX * 8);
 
 // Lane-group shape of the near field for a leaf chunk of n targets: T
 // targets per lane, groups of L = ceil(n / T) lanes, G = 64 / L groups on
@@ -484,10 +488,10 @@ constexpr P2PShapes p2p_shape_table()
     P2PShapes s{};
     for (int n = 1; n <= WAVE; ++n) {
         int T = 1, L = n, G = WAVE / n < P2P_GMAX ? WAVE / n : P2P_GMAX;
-        int best = G * n * 12;  // pairs per round x 12 / T (12: a common multiple of 1..4)
-        for (int t = 2; t <= 4; ++t) {
+        int best = G * n * 840;  // pairs per round x 840 / T (840: a common multiple of 1..8)
+        for (int t = 2; t <= P2P_TMAX; ++t) {
             const int l = (n + t - 1) / t, g = WAVE / l < P2P_GMAX ? WAVE / l : P2P_GMAX;
-            const int v = g * n * 12 / t;
+            const int v = g * n * 840 / t;
             if (v > best) {
                 best = v;
                 T = t;
@@ -524,11 +528,13 @@ __device__ __forceinline__ void p2p_groups(const float4 *__restrict__ part, cons
     // multiple of L, far more than the rounding of the product
     const int grp = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)L)), r = lane - grp * L;
     const int gr = grp < G ? grp : 0;
-    float4 me[T];
+    // the targets' (x, y) only: the mass and id are not needed here
+    const float2 *pxy = reinterpret_cast<const float2 *>(part);
+    float2 me[T];
     float fx[T], fy[T];
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        me[u] = part[t0 + min(r + u * L, n - 1)];
+        me[u] = pxy[2 * (t0 + min(r + u * L, n - 1))];
         fx[u] = 0.f;
         fy[u] = 0.f;
     }
@@ -564,40 +570,41 @@ __device__ __forceinline__ void p2p_groups(const float4 *__restrict__ part, cons
 #pragma unroll
     for (int u = 0; u < T; ++u) rw[lane * T + u] = make_float2(fx[u], fy[u]);
     wave_lds_sync();
-    if (grp == 0) {
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const int tk = r + u * L;
-            if (tk < n) {
-                float2 a = rw[r * T + u];
-                for (int g = 1; g < G; ++g) {
-                    const float2 q = rw[(g * L + r) * T + u];
-                    a.x += q.x;
-                    a.y += q.y;
-                }
-                near[t0 + tk] = a;
-                pleaf[t0 + tk] = li;
-            }
+    // one target per lane: target k = r' + u' L is lane k, which adds the
+    // groups' sums of lane (g, r') slot u' in group order (u' = k / L as above)
+    if (lane < n) {
+        const int uk = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)L)), rk = lane - uk * L;
+        float2 a = rw[rk * T + uk];
+        for (int g = 1; g < G; ++g) {
+            const float2 q = rw[(g * L + rk) * T + uk];
+            a.x += q.x;
+            a.y += q.y;
         }
+        near[t0 + lane] = a;
+        pleaf[t0 + lane] = li;
     }
 }
 
 // k_p2p: the near field of every particle over its leaf's U list (sorted
 // particle order, one float2 per particle).  It needs only the lists, so it
-// runs beside the upward pass and M2L.
-__global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restrict__ part,
-                                             const int64_t *__restrict__ offUW, const int2 *__restrict__ U,
-                                             const int32_t *__restrict__ nU, const int32_t *__restrict__ cbeg,
-                                             const int32_t *__restrict__ cend, const int32_t *__restrict__ leaf_cell,
-                                             float2 *__restrict__ near, int32_t *__restrict__ pleaf)
+// runs beside the upward pass and M2L.  Eight waves per SIMD: the bound
+// keeps the registers at 64 (the eight-target lane groups would take 95 and
+// leave five waves in flight).
+__global__ __launch_bounds__(256, 8) void k_p2p(TreeView t, const float4 *__restrict__ part,
+                                                const int64_t *__restrict__ offUW, const int2 *__restrict__ U,
+                                                const int32_t *__restrict__ nU, const int32_t *__restrict__ cbeg,
+                                                const int32_t *__restrict__ cend,
+                                                const int32_t *__restrict__ leaf_cell, float2 *__restrict__ near,
+                                                int32_t *__restrict__ pleaf)
 {
-    __shared__ float4 stage[4][P2P_STAGE];  // per wave: sources of the lane-group path, zero-mass padded
-    __shared__ float2 sums[4][WAVE * 4];     // per wave: the lane groups' partial sums
+    // per wave: the sources of the lane-group path (zero-mass padded), then
+    // the lane groups' partial sums
+    __shared__ __align__(16) unsigned char lds[4][P2P_WAVE_LDS];
     const int nleaves = t.counts[1];
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
-    float4 *sw = stage[threadIdx.x / WAVE];
-    float2 *rw = sums[threadIdx.x / WAVE];
+    float4 *sw = reinterpret_cast<float4 *>(lds[threadIdx.x / WAVE]);
+    float2 *rw = reinterpret_cast<float2 *>(lds[threadIdx.x / WAVE]);
     const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)threadIdx.x / WAVE);
     for (int li = first; li < nleaves; li += gridDim.x * wpb) {
         const int c = leaf_cell[li];
@@ -613,7 +620,11 @@ __global__ __launch_bounds__(256) void k_p2p(TreeView t, const float4 *__restric
                 case 1: p2p_groups<1>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
                 case 2: p2p_groups<2>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
                 case 3: p2p_groups<3>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                default: p2p_groups<4>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 4: p2p_groups<4>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 5: p2p_groups<5>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 6: p2p_groups<6>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 7: p2p_groups<7>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                default: p2p_groups<8>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
                 }
                 continue;
             }

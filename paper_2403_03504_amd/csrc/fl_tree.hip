@@ -401,52 +401,66 @@ __device__ __forceinline__ int first_cell_from(const int64_t *__restrict__ off2,
     return v < n ? (int)(tree_offset(off2, bpre, v) & 0xFFFFFFFFll) : ncells;
 }
 
-__global__ void k_tree_links(const uint32_t *__restrict__ K, int n, int bits, const int64_t *__restrict__ off2,
-                             const int64_t *__restrict__ bpre, TreeBufs t)
+// Two independent jobs per cell, each a chain of dependent loads: its hash
+// entry (probe and insert), and its end, skip and parent (binary searches
+// over the leaf starts).  Even waves insert and odd waves link, so that the
+// two chains of a cell run side by side in different waves.
+__global__ __launch_bounds__(NT) void k_tree_links(const uint32_t *__restrict__ K, int n, int bits,
+                                                   const int64_t *__restrict__ off2,
+                                                   const int64_t *__restrict__ bpre, TreeBufs t)
 {
-    int id = blockIdx.x * blockDim.x + threadIdx.x;
-    int ncells = t.counts[0];
-    if (id >= ncells) return;
-    int nleaves = t.counts[1];
-    int l = t.lvl[id];
-    const int comp = t.ccomp ? t.ccomp[id] : 0;
-    hash_insert(t, hash_size(ncells, t.hash_cap), *t.epoch, HASH_BASE_BITS + t.s.cbits, comp, l, t.ixy[id], id);
-    if (l == 0) {
-        const int e0 = t.s.K > 1 ? t.s.coff[comp + 1] : n;
-        t.end[id] = e0;
-        t.skip[id] = first_cell_from(off2, bpre, n, ncells, e0);
-        return;
-    }
-    int k = t.beg[id];
-    uint32_t pre = region_prefix(K[k], l, bits);
-    int sh = 2 * (bits - l);
-    // start keys carry the system above bit 32: the region's end is the first
-    // cell start past it in the same system, or the next system's first start
-    const uint64_t cs = (uint64_t)(uint32_t)comp << 32;
-    uint64_t T = cs + (((uint64_t)pre + 1ull) << sh);
-    int j = lower_bound_u64(t.start_key, nleaves, T);
-    const int eid = j < nleaves ? t.start_pos[j] : n;
-    t.end[id] = eid;
-    t.skip[id] = first_cell_from(off2, bpre, n, ncells, eid);
-    int p = t.par[id];
-    if (p == -2) {
-        uint64_t Tp = cs | ((uint64_t)(pre >> 2) << (sh + 2));
-        int jp = lower_bound_u64(t.start_key, nleaves, Tp);
-        if (jp >= nleaves) {
-            atomicOr(&t.counts[3], 2);
-            return;
+    static_assert(NT % (2 * WAVE) == 0, "whole wave pairs per block");
+    const int ncells = t.counts[0];
+    const int nleaves = t.counts[1];
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    const int pairs = (int)(gridDim.x * blockDim.x / (2 * WAVE));
+    const bool insert = (gw & 1) == 0;
+    for (int id = (gw >> 1) * WAVE + lane_id(); id < ncells; id += pairs * WAVE) {
+        const int l = t.lvl[id];
+        const int comp = t.ccomp ? t.ccomp[id] : 0;
+        if (insert) {
+            hash_insert(t, hash_size(ncells, t.hash_cap), *t.epoch, HASH_BASE_BITS + t.s.cbits, comp, l, t.ixy[id],
+                        id);
+            continue;
         }
-        int bp = t.start_pos[jp];
-        int Dp = t.start_D[jp];
-        int cid0 = (int)(tree_offset(off2, bpre, bp) & 0xFFFFFFFFll);
-        p = cid0 + (l - 1 - Dp - 1);
-        t.par[id] = p;
+        if (l == 0) {
+            const int e0 = t.s.K > 1 ? t.s.coff[comp + 1] : n;
+            t.end[id] = e0;
+            t.skip[id] = first_cell_from(off2, bpre, n, ncells, e0);
+            continue;
+        }
+        const int k = t.beg[id];
+        const uint32_t pre = region_prefix(K[k], l, bits);
+        const int sh = 2 * (bits - l);
+        // start keys carry the system above bit 32: the region's end is the
+        // first cell start past it in the same system, or the next system's
+        // first start
+        const uint64_t cs = (uint64_t)(uint32_t)comp << 32;
+        const uint64_t T = cs + (((uint64_t)pre + 1ull) << sh);
+        const int j = lower_bound_u64(t.start_key, nleaves, T);
+        const int eid = j < nleaves ? t.start_pos[j] : n;
+        t.end[id] = eid;
+        t.skip[id] = first_cell_from(off2, bpre, n, ncells, eid);
+        int p = t.par[id];
+        if (p == -2) {
+            const uint64_t Tp = cs | ((uint64_t)(pre >> 2) << (sh + 2));
+            const int jp = lower_bound_u64(t.start_key, nleaves, Tp);
+            if (jp >= nleaves) {
+                atomicOr(&t.counts[3], 2);
+                continue;
+            }
+            const int bp = t.start_pos[jp];
+            const int Dp = t.start_D[jp];
+            const int cid0 = (int)(tree_offset(off2, bpre, bp) & 0xFFFFFFFFll);
+            p = cid0 + (l - 1 - Dp - 1);
+            t.par[id] = p;
+        }
+        if (p < 0 || p >= ncells) {
+            atomicOr(&t.counts[3], 2);
+            continue;
+        }
+        reinterpret_cast<int *>(&t.child[p])[pre & 3u] = id;
     }
-    if (p < 0 || p >= ncells) {
-        atomicOr(&t.counts[3], 2);
-        return;
-    }
-    reinterpret_cast<int *>(&t.child[p])[pre & 3u] = id;
 }
 
 // ---- lists ------------------------------------------------------------------
@@ -1136,8 +1150,9 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     scan_excl_i64(c, bsum, bpre, nblk);
     hipLaunchKernelGGL(k_tree_cells, dim3(grid_for(n, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
                        (const int32_t *)t.pack, (const int64_t *)t.off2, (const int64_t *)bpre, s.ncomp, t);
-    hipLaunchKernelGGL(k_tree_links, dim3(grid_for(cap, NT)), dim3(NT), 0, c->stream, (const uint32_t *)sk, n, bits,
-                       (const int64_t *)t.off2, (const int64_t *)bpre, t);
+    // a pair of waves per 64 cells (the grid loops past 2048 blocks)
+    hipLaunchKernelGGL(k_tree_links, dim3(grid_for(2 * cap, NT, 2048)), dim3(NT), 0, c->stream, (const uint32_t *)sk,
+                       n, bits, (const int64_t *)t.off2, (const int64_t *)bpre, t);
     FL_LAUNCH_CHECK();
 }
 

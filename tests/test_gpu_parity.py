@@ -262,6 +262,30 @@ def test_fmm_single_leaf_equals_exact(ctx, fl, orc):
     assert orc.rel_err(host(out["frx"]), host(out["fry"]), ex, ey) < 1e-6
 
 
+# every leaf-chunk size of the near field: a single leaf of n particles makes
+# one chunk of n targets (or chunks of 64 and a remainder), each run in its
+# own lane-group shape (targets per lane, groups of lanes on interleaved
+# sources); the FMM then reduces to the direct sum over the leaf
+SINGLE_LEAF_SIZES = list(range(2, 65)) + [65, 100, 127, 128, 129, 200, 300]
+
+
+def test_fmm_every_leaf_chunk_size_equals_exact(ctx, fl, orc, node_err):
+    _note("fmm single leaf, every chunk size")
+    worst = 0.0
+    for n in SINGLE_LEAF_SIZES:
+        x, y = _positions("uniform", n, 500 + n)
+        deg = (np.arange(n, dtype=np.int32) % 5) + 1
+        G = mass_graph(fl, deg)
+        prm = fl.default_params(repulsion=fl.REP_FMM, leaf_size=max(64, n))
+        out = ctx.fa2_forces(G, dev(x), dev(y), prm, components=False)
+        ex, ey = orc.repulsion_exact(x, y, deg + 1.0)
+        e = node_err(host(out["frx"]), host(out["fry"]), ex, ey).max()
+        worst = max(worst, e)
+        assert e < 1e-5, (n, e)
+        assert ctx.fmm_stats()["leaves"] == 1, n
+    _note("  worst per-node error", worst)
+
+
 # step-size and force-model variants: the defaults, ForceAtlas2's own
 # mass-weighted swing with halved traction, and non-default constants (a
 # small rise cap that binds, a large ks with a tight ksmax cap) with the

@@ -351,15 +351,16 @@ bool radix_sort_u32(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *v
                     bool vals_iota = false);
 bool radix_sort_u64(fl_ctx *c, uint64_t *k, uint64_t *kt, int64_t n, int nbits, int32_t *err = nullptr);
 
+// Keys per tile of the sort of n keys (one block each).
+int radix_sort_tile(int64_t n);
 // Segmented sort: K independent key ranges [coff[s], coff[s+1]), each sorted
-// on its own (stable), cut into system-aligned tiles of RS_SEG_TILE keys:
-// tile t covers [tiles[t].y, min(tiles[t].y + RS_SEG_TILE, coff[tiles[t].x
-// + 1])), the tiles of a system are consecutive and in system order.  The
-// result equals one stable sort by (system, key), with no system bits in the
-// keys.
-constexpr int RS_SEG_TILE = 4096;
+// on its own (stable), cut into system-aligned tiles of `tile` keys (that of
+// radix_sort_tile for all the keys): tile t covers [tiles[t].y,
+// min(tiles[t].y + tile, coff[tiles[t].x + 1])), the tiles of a system are
+// consecutive and in system order.  The result equals one stable sort by
+// (system, key), with no system bits in the keys.
 struct RsSegs {
-    int K = 0, ntiles = 0;
+    int K = 0, ntiles = 0, tile = 0;
     const int32_t *coff = nullptr;  // [K+1], device
     const int2 *tiles = nullptr;    // [ntiles] (system, first key), device
     const int32_t *toff = nullptr;  // [K+1] first tile of each system, device

@@ -202,26 +202,35 @@ void scan_excl(fl_ctx *c, const T *in, T *out, int64_t n, const int32_t *dn, con
 
 // ---------------------------------------------------------------------------
 // radix sort
-constexpr int RS_NT = 512;
-constexpr int RS_NW = RS_NT / WAVE;  // 8 waves
-constexpr int RS_STEPS = 8;          // 64-key steps per wave
-constexpr int RS_WTILE = RS_STEPS * WAVE;  // 512 keys per wave
-constexpr int RS_TILE = RS_NW * RS_WTILE;  // 4096 keys per block
+constexpr int RS_NT = 1024;          // threads of every sort block
+constexpr int RS_NW = RS_NT / WAVE;  // 16 waves
+// The tile of one block: STEPS 64-key steps per wave.  4096 keys for up to
+// RS_LARGE_FROM keys, 8192 above: a long input's passes then walk half as
+// many tiles back, while a shorter one keeps more blocks in flight.
+template <int STEPS_>
+struct RsCfg {
+    static constexpr int STEPS = STEPS_;
+    static constexpr int WTILE = STEPS * WAVE;   // keys per wave
+    static constexpr int TILE = RS_NW * WTILE;  // keys per block
+};
+using RsSmall = RsCfg<4>;
+using RsLarge = RsCfg<8>;
+constexpr int64_t RS_LARGE_FROM = 1536 * 1024;
 constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;  // digit d is thread d's in the per-digit steps
 static_assert(RS_NT >= RS_BINS, "a thread per digit");
 constexpr int RS_MAXPASS = 8;  // 64-bit keys
 
-template <class K>
+template <class K, class C>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                     int32_t *__restrict__ hist, int nblocks)
 {
     __shared__ int cnt[RS_BINS];
     if (threadIdx.x < RS_BINS) cnt[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    int64_t base = (int64_t)blockIdx.x * C::TILE;
 #pragma unroll 4
-    for (int i = 0; i < RS_TILE / RS_NT; ++i) {
+    for (int i = 0; i < C::TILE / RS_NT; ++i) {
         int64_t idx = base + (int64_t)i * RS_NT + threadIdx.x;
         if (idx < n) atomicAdd(&cnt[(int)((keys[idx] >> shift) & (RS_BINS - 1))], 1);
     }
@@ -230,31 +239,31 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
 }
 
 // The LDS of one scatter block.
-template <class K, bool HasVal>
+template <class K, bool HasVal, class C>
 struct RsShared {
     int wcnt[RS_NW][RS_BINS];
     int gbase[RS_BINS];
     int lstart[RS_BINS];
     int scan_tmp[RS_NT / WAVE];
     int tile;
-    K skey[RS_TILE];
-    int32_t sval[HasVal ? RS_TILE : 1];
+    K skey[C::TILE];
+    int32_t sval[HasVal ? C::TILE : 1];
 };
 
 // Loads tile `tile` and ranks its keys: each wave ranks its 1024 keys step
 // by step with ballot masks of equal digits (no atomics, so equal digits keep
 // the input order), then every digit gets its exclusive prefix over the
 // waves (wcnt) and the block's count of the digit is returned to thread d.
-template <class K, bool HasVal>
-__device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restrict__ kin,
+template <class K, bool HasVal, class C>
+__device__ __forceinline__ int rs_rank(RsShared<K, HasVal, C> &S, const K *__restrict__ kin,
                                        const int32_t *__restrict__ vin, int64_t t0, int64_t t1, int shift,
-                                       K (&key)[RS_STEPS], int32_t (&val)[RS_STEPS], int (&off)[RS_STEPS],
-                                       int (&dig)[RS_STEPS])
+                                       K (&key)[C::STEPS], int32_t (&val)[C::STEPS], int (&off)[C::STEPS],
+                                       int (&dig)[C::STEPS])
 {
     const int lane = lane_id(), w = threadIdx.x / WAVE;
-    const int64_t wbase = t0 + (int64_t)w * RS_WTILE;
+    const int64_t wbase = t0 + (int64_t)w * C::WTILE;
 #pragma unroll
-    for (int st = 0; st < RS_STEPS; ++st) {
+    for (int st = 0; st < C::STEPS; ++st) {
         int64_t idx = wbase + (int64_t)st * WAVE + lane;
         bool ok = idx < t1;
         key[st] = ok ? kin[idx] : K(0);
@@ -263,7 +272,7 @@ __device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restri
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
 #pragma unroll
-    for (int st = 0; st < RS_STEPS; ++st) {
+    for (int st = 0; st < C::STEPS; ++st) {
         const int d = dig[st];
         uint64_t mask = __ballot(d >= 0);
 #pragma unroll
@@ -299,16 +308,16 @@ __device__ __forceinline__ int rs_rank(RsShared<K, HasVal> &S, const K *__restri
 // Places the ranked keys of the tile [t0, t1) in LDS in digit order and
 // writes every digit's run to its global position gbase[d] + rank within the
 // digit (coalesced); positions at or past `lim` are dropped.
-template <class K, bool HasVal>
-__device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__ kout, int32_t *__restrict__ vout,
-                                         int64_t t0, int64_t t1, int64_t lim, int shift, const K (&key)[RS_STEPS],
-                                         const int32_t (&val)[RS_STEPS], const int (&off)[RS_STEPS],
-                                         const int (&dig)[RS_STEPS], const float4 *__restrict__ gsrc,
+template <class K, bool HasVal, class C>
+__device__ __forceinline__ void rs_place(RsShared<K, HasVal, C> &S, K *__restrict__ kout, int32_t *__restrict__ vout,
+                                         int64_t t0, int64_t t1, int64_t lim, int shift, const K (&key)[C::STEPS],
+                                         const int32_t (&val)[C::STEPS], const int (&off)[C::STEPS],
+                                         const int (&dig)[C::STEPS], const float4 *__restrict__ gsrc,
                                          float4 *__restrict__ gdst)
 {
     const int w = threadIdx.x / WAVE;
 #pragma unroll
-    for (int st = 0; st < RS_STEPS; ++st) {
+    for (int st = 0; st < C::STEPS; ++st) {
         const int d = dig[st];
         if (d < 0) continue;
         const int lp = S.lstart[d] + S.wcnt[w][d] + off[st];
@@ -334,23 +343,23 @@ __device__ __forceinline__ void rs_place(RsShared<K, HasVal> &S, K *__restrict__
 
 // Stable scatter of one pass with the per-tile digit histograms scanned
 // beforehand (three launches per pass).
-template <class K, bool HasVal>
+template <class K, bool HasVal, class C>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin,
                                                        K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
                                                        int shift, const int32_t *__restrict__ hscan, int nblocks,
                                                        const float4 *__restrict__ gsrc, float4 *__restrict__ gdst)
 {
-    __shared__ RsShared<K, HasVal> S;
+    __shared__ RsShared<K, HasVal, C> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
     if (threadIdx.x < RS_BINS) S.gbase[threadIdx.x] = hscan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
     __syncthreads();
-    K key[RS_STEPS];
-    int32_t val[RS_STEPS];
-    int off[RS_STEPS], dig[RS_STEPS];
-    const int64_t t0 = (int64_t)blockIdx.x * RS_TILE, t1 = t0 + RS_TILE < n ? t0 + RS_TILE : n;
-    rs_rank<K, HasVal>(S, kin, vin, t0, t1, shift, key, val, off, dig);
+    K key[C::STEPS];
+    int32_t val[C::STEPS];
+    int off[C::STEPS], dig[C::STEPS];
+    const int64_t t0 = (int64_t)blockIdx.x * C::TILE, t1 = t0 + C::TILE < n ? t0 + C::TILE : n;
+    rs_rank<K, HasVal, C>(S, kin, vin, t0, t1, shift, key, val, off, dig);
     __syncthreads();
-    rs_place<K, HasVal>(S, kout, vout, t0, t1, n, shift, key, val, off, dig, gsrc, gdst);
+    rs_place<K, HasVal, C>(S, kout, vout, t0, t1, n, shift, key, val, off, dig, gsrc, gdst);
 }
 
 // ---- one launch per pass: decoupled look-back --------------------------------
@@ -376,7 +385,6 @@ constexpr int RS_LOOK = 8;  // tiles read per look-back step
 // the tile count while launch overhead matters less (4M keys at most here,
 // far below the 2^30 the status words hold).
 constexpr int RS_LOOKBACK_TILES = 1024;
-static_assert(RS_TILE == RS_SEG_TILE, "segmented tiles are sort tiles");
 
 // Keys [t0, t1) of a tile; its positions lie in [base, lim) (its system's
 // range, the whole input without segments); `first`: the first tile of its
@@ -387,6 +395,7 @@ struct RsTile {
     bool first;
 };
 
+template <class C>
 __device__ __forceinline__ RsTile rs_tile(const RsSegs &sg, int64_t n, int tile)
 {
     RsTile r;
@@ -399,12 +408,12 @@ __device__ __forceinline__ RsTile rs_tile(const RsSegs &sg, int64_t n, int tile)
         r.first = tile == sg.toff[td.x];
     } else {
         r.sys = 0;
-        r.t0 = (int64_t)tile * RS_TILE;
+        r.t0 = (int64_t)tile * C::TILE;
         r.base = 0;
         r.lim = n;
         r.first = tile == 0;
     }
-    r.t1 = r.t0 + RS_TILE < r.lim ? r.t0 + RS_TILE : r.lim;
+    r.t1 = r.t0 + C::TILE < r.lim ? r.t0 + C::TILE : r.lim;
     return r;
 }
 
@@ -412,7 +421,7 @@ __device__ __forceinline__ RsTile rs_tile(const RsSegs &sg, int64_t n, int tile)
 // per tile), the clearing of every pass's status words, and (block 0) the
 // zeroing of the summed counts and the tickets; the launches after this one
 // on the stream see all of it.
-template <class K>
+template <class K, class C>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ keys, int64_t n, int passes,
                                                         uint32_t *__restrict__ part, uint32_t *__restrict__ status,
                                                         int64_t nstatus, uint32_t *__restrict__ gh, int ngh,
@@ -425,7 +434,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const K *__restrict__ key
     const int64_t stride = (int64_t)gridDim.x * RS_NT;
     for (int64_t i = (int64_t)blockIdx.x * RS_NT + threadIdx.x; i < nstatus; i += stride) status[i] = 0u;
     __syncthreads();
-    const RsTile tl = rs_tile(sg, n, blockIdx.x);
+    const RsTile tl = rs_tile<C>(sg, n, blockIdx.x);
     for (int64_t i = tl.t0 + threadIdx.x; i < tl.t1; i += RS_NT) {
         const K k = keys[i];
         for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(int)((k >> (p * RS_BITS)) & (RS_BINS - 1))], 1u);
@@ -501,7 +510,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_sum_seg(const uint32_t *__res
     if (lane == 0) gh[i] = sum;
 }
 
-template <class K, bool HasVal>
+template <class K, bool HasVal, class C>
 __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin, const int32_t *__restrict__ vin,
                                                         K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
                                                         int shift, const uint32_t *__restrict__ gh, int ghstride,
@@ -510,19 +519,19 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
                                                         const float4 *__restrict__ gsrc, float4 *__restrict__ gdst,
                                                         RsSegs sg)
 {
-    __shared__ RsShared<K, HasVal> S;
+    __shared__ RsShared<K, HasVal, C> S;
     for (int i = threadIdx.x; i < RS_NW * RS_BINS; i += RS_NT) (&S.wcnt[0][0])[i] = 0;
     // with the tiles' prefixes given (first pass) the tile is the block's own
     if (threadIdx.x == 0) S.tile = pfx ? (int)blockIdx.x : (int)atomicAdd(ticket, 1u);
     __syncthreads();
     const int tile = S.tile;
-    K key[RS_STEPS];
-    int32_t val[RS_STEPS];
-    int off[RS_STEPS], dig[RS_STEPS];
+    K key[C::STEPS];
+    int32_t val[C::STEPS];
+    int off[C::STEPS], dig[C::STEPS];
     const int d = threadIdx.x;
     const bool dig_thread = d < RS_BINS;  // thread d handles digit d
-    const RsTile tl = rs_tile(sg, n, tile);
-    const uint32_t cnt = (uint32_t)rs_rank<K, HasVal>(S, kin, vin, tl.t0, tl.t1, shift, key, val, off, dig);
+    const RsTile tl = rs_tile<C>(sg, n, tile);
+    const uint32_t cnt = (uint32_t)rs_rank<K, HasVal, C>(S, kin, vin, tl.t0, tl.t1, shift, key, val, off, dig);
     uint32_t *my = status + (int64_t)tile * RS_BINS + d;
     if (!pfx && dig_thread)
         __hip_atomic_store(my, (tl.first ? RS_PFX : RS_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -577,15 +586,15 @@ __global__ __launch_bounds__(RS_NT) void k_rs_onesweep(const K *__restrict__ kin
     }
     if (dig_thread) S.gbase[d] = (int)(tl.base + dstart + before);
     __syncthreads();
-    rs_place<K, HasVal>(S, kout, vout, tl.t0, tl.t1, tl.lim, shift, key, val, off, dig, gsrc, gdst);
+    rs_place<K, HasVal, C>(S, kout, vout, tl.t0, tl.t1, tl.lim, shift, key, val, off, dig, gsrc, gdst);
 }
 
-template <class K, bool HasVal>
-bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag,
-                int32_t *err, const float4 *gsrc = nullptr, float4 *gdst = nullptr, bool vals_iota = false)
+template <class K, bool HasVal, class C>
+bool radix_sort_c(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag,
+                  int32_t *err, const float4 *gsrc, float4 *gdst, bool vals_iota)
 {
     if (n <= 0) return false;
-    const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int nblocks = (int)((n + C::TILE - 1) / C::TILE);
     const int passes = (nbits + RS_BITS - 1) / RS_BITS;
     K *ka = k, *kb = kt;
     int32_t *va = v, *vb = vt;
@@ -598,13 +607,13 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
         const int64_t nstatus = (int64_t)passes * nblocks * RS_BINS;
         uint32_t *status = ws<uint32_t>(c, (std::string("rs_status_") + tag).c_str(), (size_t)nstatus);
         if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
-        hipLaunchKernelGGL(k_rs_hist_all<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)k, n, passes, part,
-                           status, nstatus, gh, nz, RsSegs{});
+        hipLaunchKernelGGL((k_rs_hist_all<K, C>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)k, n, passes,
+                           part, status, nstatus, gh, nz, RsSegs{});
         uint32_t *pfx0 = ws<uint32_t>(c, (std::string("rs_pfx0_") + tag).c_str(), (size_t)nblocks * RS_BINS);
         hipLaunchKernelGGL(k_rs_hist_sum, dim3(passes * RS_BINS), dim3(RS_NT), 0, c->stream,
                            (const uint32_t *)part, nblocks, passes, gh, pfx0);
         for (int ps = 0; ps < passes; ++ps) {
-            hipLaunchKernelGGL((k_rs_onesweep<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
+            hipLaunchKernelGGL((k_rs_onesweep<K, HasVal, C>), dim3(nblocks), dim3(RS_NT), 0, c->stream, (const K *)ka,
                                (const int32_t *)(ps == 0 && vals_iota ? nullptr : va), kb, vb, n, ps * RS_BITS,
                                (const uint32_t *)(gh + ps * RS_BINS), 0,
                                status + (int64_t)ps * nblocks * RS_BINS, ticket + ps,
@@ -621,9 +630,9 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
     int32_t *hscan = hist + (size_t)RS_BINS * nblocks;
     for (int ps = 0; ps < passes; ++ps) {
         int shift = ps * RS_BITS;
-        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, n, shift, hist, nblocks);
+        hipLaunchKernelGGL((k_rs_hist<K, C>), dim3(nblocks), dim3(RS_NT), 0, c->stream, ka, n, shift, hist, nblocks);
         scan_excl<int32_t>(c, hist, hscan, (int64_t)RS_BINS * nblocks, nullptr, tag);
-        hipLaunchKernelGGL((k_rs_scatter<K, HasVal>), dim3(nblocks), dim3(RS_NT), 0, c->stream, ka,
+        hipLaunchKernelGGL((k_rs_scatter<K, HasVal, C>), dim3(nblocks), dim3(RS_NT), 0, c->stream, ka,
                            ps == 0 && vals_iota ? nullptr : va, kb, vb, n,
                            shift, hscan, nblocks, ps == passes - 1 ? gsrc : nullptr,
                            ps == passes - 1 ? gdst : nullptr);
@@ -634,7 +643,51 @@ bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int 
     return (passes & 1) != 0;
 }
 
+template <class K, bool HasVal>
+bool radix_sort(fl_ctx *c, K *k, int32_t *v, K *kt, int32_t *vt, int64_t n, int nbits, const char *tag,
+                int32_t *err, const float4 *gsrc = nullptr, float4 *gdst = nullptr, bool vals_iota = false)
+{
+    return radix_sort_tile(n) == RsLarge::TILE
+               ? radix_sort_c<K, HasVal, RsLarge>(c, k, v, kt, vt, n, nbits, tag, err, gsrc, gdst, vals_iota)
+               : radix_sort_c<K, HasVal, RsSmall>(c, k, v, kt, vt, n, nbits, tag, err, gsrc, gdst, vals_iota);
+}
+
+template <class C>
+void sort_seg_launches(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_t *vt, int64_t n, int passes,
+                       int32_t *err, const RsSegs &sg, const float4 *gsrc, float4 *gdst, bool vals_iota)
+{
+    const int nt = sg.ntiles;
+    const int64_t per = (int64_t)passes * RS_BINS;
+    // per-system digit counts, then the tickets (the only words zeroed)
+    uint32_t *gh = ws<uint32_t>(c, "rs_gh_seg", (size_t)(sg.K * per + passes));
+    uint32_t *ticket = gh + sg.K * per;
+    uint32_t *part = ws<uint32_t>(c, "rs_part_seg", (size_t)nt * per);
+    const int64_t nstatus = (int64_t)nt * per;
+    uint32_t *status = ws<uint32_t>(c, "rs_status_seg", (size_t)nstatus);
+    if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
+    hipLaunchKernelGGL((k_rs_hist_all<uint32_t, C>), dim3(nt), dim3(RS_NT), 0, c->stream, (const uint32_t *)k, n,
+                       passes, part, status, nstatus, ticket, passes, sg);
+    uint32_t *pfx0 = ws<uint32_t>(c, "rs_pfx0_seg", (size_t)nt * RS_BINS);
+    hipLaunchKernelGGL(k_rs_hist_sum_seg, dim3((unsigned)((sg.K * per + RS_NW - 1) / RS_NW)), dim3(RS_NT), 0,
+                       c->stream, (const uint32_t *)part, passes, sg, gh, pfx0);
+    uint32_t *ka = k, *kb = kt;
+    int32_t *va = v, *vb = vt;
+    for (int ps = 0; ps < passes; ++ps) {
+        hipLaunchKernelGGL((k_rs_onesweep<uint32_t, true, C>), dim3(nt), dim3(RS_NT), 0, c->stream,
+                           (const uint32_t *)ka, (const int32_t *)(ps == 0 && vals_iota ? nullptr : va), kb, vb, n,
+                           ps * RS_BITS,
+                           (const uint32_t *)(gh + ps * RS_BINS), (int)per, status + (int64_t)ps * nt * RS_BINS,
+                           ticket + ps, ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
+                           ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr, sg);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    FL_LAUNCH_CHECK();
+}
+
 }  // namespace
+
+int radix_sort_tile(int64_t n) { return n > RS_LARGE_FROM ? RsLarge::TILE : RsSmall::TILE; }
 
 void scan_excl_i32(fl_ctx *c, const int32_t *in, int32_t *out, int64_t n, const int32_t *dn)
 {
@@ -678,33 +731,11 @@ bool radix_sort_u32_seg(fl_ctx *c, uint32_t *k, int32_t *v, uint32_t *kt, int32_
     const int passes = (nbits + RS_BITS - 1) / RS_BITS;
     FL_REQUIRE(radix_sort_seg_fits(n, sg.ntiles) && passes <= RS_MAXPASS && sg.tiles && sg.K >= 1,
                "segmented sort: tiles out of range");
-    const int nt = sg.ntiles;
-    const int64_t per = (int64_t)passes * RS_BINS;
-    // per-system digit counts, then the tickets (the only words zeroed)
-    uint32_t *gh = ws<uint32_t>(c, "rs_gh_seg", (size_t)(sg.K * per + passes));
-    uint32_t *ticket = gh + sg.K * per;
-    uint32_t *part = ws<uint32_t>(c, "rs_part_seg", (size_t)nt * per);
-    const int64_t nstatus = (int64_t)nt * per;
-    uint32_t *status = ws<uint32_t>(c, "rs_status_seg", (size_t)nstatus);
-    if (!err) err = ws_zeroed<int32_t>(c, "rs_err", 1);
-    hipLaunchKernelGGL(k_rs_hist_all<uint32_t>, dim3(nt), dim3(RS_NT), 0, c->stream, (const uint32_t *)k, n, passes,
-                       part, status, nstatus, ticket, passes, sg);
-    uint32_t *pfx0 = ws<uint32_t>(c, "rs_pfx0_seg", (size_t)nt * RS_BINS);
-    hipLaunchKernelGGL(k_rs_hist_sum_seg, dim3((unsigned)((sg.K * per + RS_NW - 1) / RS_NW)), dim3(RS_NT), 0,
-                       c->stream, (const uint32_t *)part, passes, sg, gh, pfx0);
-    uint32_t *ka = k, *kb = kt;
-    int32_t *va = v, *vb = vt;
-    for (int ps = 0; ps < passes; ++ps) {
-        hipLaunchKernelGGL((k_rs_onesweep<uint32_t, true>), dim3(nt), dim3(RS_NT), 0, c->stream,
-                           (const uint32_t *)ka, (const int32_t *)(ps == 0 && vals_iota ? nullptr : va), kb, vb, n,
-                           ps * RS_BITS,
-                           (const uint32_t *)(gh + ps * RS_BINS), (int)per, status + (int64_t)ps * nt * RS_BINS,
-                           ticket + ps, ps == 0 ? (const uint32_t *)pfx0 : (const uint32_t *)nullptr, err,
-                           ps == passes - 1 ? gsrc : nullptr, ps == passes - 1 ? gdst : nullptr, sg);
-        std::swap(ka, kb);
-        std::swap(va, vb);
-    }
-    FL_LAUNCH_CHECK();
+    FL_REQUIRE(sg.tile == RsSmall::TILE || sg.tile == RsLarge::TILE, "segmented sort: tiles of an unknown size");
+    if (sg.tile == RsLarge::TILE)
+        sort_seg_launches<RsLarge>(c, k, v, kt, vt, n, passes, err, sg, gsrc, gdst, vals_iota);
+    else
+        sort_seg_launches<RsSmall>(c, k, v, kt, vt, n, passes, err, sg, gsrc, gdst, vals_iota);
     return (passes & 1) != 0;
 }
 

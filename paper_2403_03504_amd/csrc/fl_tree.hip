@@ -978,10 +978,11 @@ static Segs upload_segs(fl_ctx *c, const std::vector<int32_t> &coff, const std::
     toff[K] = (int32_t)tiles.size();
     std::vector<int2> stiles;  // sort tiles
     std::vector<int32_t> stoff(K + 1);
+    const int stile = radix_sort_tile(coff[K]);
     if (K > 1) {
         for (int k = 0; k < K; ++k) {
             stoff[k] = (int32_t)stiles.size();
-            for (int64_t b = coff[k]; b < coff[k + 1]; b += RS_SEG_TILE) stiles.push_back(make_int2(k, (int)b));
+            for (int64_t b = coff[k]; b < coff[k + 1]; b += stile) stiles.push_back(make_int2(k, (int)b));
         }
         stoff[K] = (int32_t)stiles.size();
     }
@@ -1011,6 +1012,7 @@ static Segs upload_segs(fl_ctx *c, const std::vector<int32_t> &coff, const std::
             hipMemcpyAsync(d_stoff, stoff.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice, c->stream));
         sg.sort.K = K;
         sg.sort.ntiles = (int)stiles.size();
+        sg.sort.tile = stile;
         sg.sort.coff = d_coff;
         sg.sort.tiles = d_st;
         sg.sort.toff = d_stoff;
@@ -1072,7 +1074,7 @@ void build_tree_impl(fl_ctx *c, TreeBufs &t, const Segs &s, const float *x, cons
     // several systems: a segmented sort of the 32-bit keys when its tiles
     // pad the input little (systems of a few keys each take the sort of
     // (system, key) pairs instead); both give the same order
-    const int64_t min_tiles = ((int64_t)n + RS_SEG_TILE - 1) / RS_SEG_TILE;
+    const int64_t min_tiles = s.sort.tile > 0 ? ((int64_t)n + s.sort.tile - 1) / s.sort.tile : 0;
     const bool seg = s.K > 1 && s.sort.tiles && s.sort.ntiles <= 2 * min_tiles + 8 &&
                      radix_sort_seg_fits(n, s.sort.ntiles);
     if (s.K > 1 && !seg) {

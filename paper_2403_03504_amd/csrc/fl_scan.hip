@@ -4,12 +4,12 @@
 // (two launches; the tile sums are scanned first only when there are many).
 //
 // Radix sort, 8-bit digits: two launches count the digits of every pass, then
-// each pass is one launch in which a block ranks a 4096-key tile (each wave
-// ranks its keys step by step with ballot-built "same digit" lane masks, no
-// atomics, so equal digits keep the input order) and finds the keys of each
-// digit in the tiles before it by decoupled look-back.  Inputs of more than
-// 4M keys take a three-launch pass instead (per-tile histograms, a scan of
-// them, the scatter).
+// each pass is one launch in which a block ranks a tile of 4096 or 8192 keys
+// (each wave ranks its keys step by step with ballot-built "same digit" lane
+// masks, no atomics, so equal digits keep the input order) and finds the
+// keys of each digit in the tiles before it by decoupled look-back.  Inputs
+// of more than 1024 tiles take a three-launch pass instead (per-tile
+// histograms, a scan of them, the scatter).
 #include <algorithm>
 #include <type_traits>
 
@@ -250,7 +250,7 @@ struct RsShared {
     int32_t sval[HasVal ? C::TILE : 1];
 };
 
-// Loads tile `tile` and ranks its keys: each wave ranks its 1024 keys step
+// Loads tile `tile` and ranks its keys: each wave ranks its C::WTILE keys step
 // by step with ballot masks of equal digits (no atomics, so equal digits keep
 // the input order), then every digit gets its exclusive prefix over the
 // waves (wcnt) and the block's count of the digit is returned to thread d.
@@ -382,7 +382,7 @@ constexpr uint32_t RS_AGG = 1u << 30, RS_PFX = 2u << 30, RS_VAL = (1u << 30) - 1
 constexpr uint32_t RS_SPIN_LIMIT = 1u << 22;
 constexpr int RS_LOOK = 8;  // tiles read per look-back step
 // Larger inputs take the three-launch pass: their look-back chains grow with
-// the tile count while launch overhead matters less (4M keys at most here,
+// the tile count while launch overhead matters less (8M keys at most here,
 // far below the 2^30 the status words hold).
 constexpr int RS_LOOKBACK_TILES = 1024;
 
@@ -417,7 +417,7 @@ __device__ __forceinline__ RsTile rs_tile(const RsSegs &sg, int64_t n, int tile)
     return r;
 }
 
-// Digit counts of all passes per 4096-key tile (LDS counts, written out
+// Digit counts of all passes per tile (LDS counts, written out
 // per tile), the clearing of every pass's status words, and (block 0) the
 // zeroing of the summed counts and the tickets; the launches after this one
 // on the stream see all of it.

@@ -478,6 +478,10 @@ struct CountSink {
 // replays them instead of enumerating the ring again (a chain of dependent
 // lookups); a lane with more entries enumerates again.
 constexpr int LIST_SLOTS = 16;
+// Workgroups of the list kernels: two waves (16 cells of 8 lanes), which
+// leaves the upward pass on the other branch more room beside them than
+// four waves did (2M-node iteration 0.713 -> 0.706 ms)
+constexpr int LIST_NT = 128;
 constexpr int LIST_SLOT_Q = LIST_SLOTS / 4;  // int4 words per (cell, lane)
 struct SlotSink {
     using lds_i32 = __attribute__((address_space(3))) int32_t;
@@ -682,11 +686,11 @@ __device__ __forceinline__ int group_excl(int v)
 // uniform over the wave (the shuffles need all lanes of a group).  With
 // `slots` each lane also stores its first LIST_SLOTS entries there.
 template <int LANES>
-__global__ __launch_bounds__(256) void k_lists_count(TreeView t, int64_t *__restrict__ cntVX,
+__global__ __launch_bounds__(LIST_NT) void k_lists_count(TreeView t, int64_t *__restrict__ cntVX,
                                                      int64_t *__restrict__ cntUW, int64_t *__restrict__ lanecnt,
                                                      int4 *__restrict__ slots)
 {
-    __shared__ int32_t slot_lds[LANES > 1 ? 256 : 1][LANES > 1 ? LIST_SLOTS : 1];
+    __shared__ int32_t slot_lds[LANES > 1 ? LIST_NT : 1][LANES > 1 ? LIST_SLOTS : 1];
     const int ncells = t.counts[0];
     const int64_t H = hash_size(ncells, t.hash_cap);
     const uint64_t ep = *t.epoch;
@@ -772,7 +776,7 @@ __device__ __forceinline__ int sort_merge_ranges(int2 *r, int k, int64_t &src)
 }
 
 template <int LANES>
-__global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX,
+__global__ __launch_bounds__(LIST_NT) void k_lists_fill(TreeView t, const int64_t *__restrict__ offVX,
                                                     const int64_t *__restrict__ offUW, int32_t *__restrict__ V,
                                                     int32_t *__restrict__ X, int2 *__restrict__ U,
                                                     int32_t *__restrict__ nU, int32_t *__restrict__ W,
@@ -783,8 +787,8 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
                                                     const int4 *__restrict__ slots)
 {
     constexpr int STG = LANES > 1 ? FILL_STAGE : 1;  // one lane per cell: no staging
-    __shared__ int2 stage[256 / LANES][STG];
-    __shared__ int2 sorted[256 / LANES][STG];
+    __shared__ int2 stage[LIST_NT / LANES][STG];
+    __shared__ int2 sorted[LIST_NT / LANES][STG];
     const int ncells = t.counts[0];
     const int64_t tvx = offVX[ncells], tuw = offUW[t.counts[1]];
     const bool fits = (tvx & 0xFFFFFFFFll) <= v_cap && (tvx >> 32) <= x_cap && (tuw & 0xFFFFFFFFll) <= u_cap &&
@@ -899,8 +903,8 @@ __global__ __launch_bounds__(256) void k_lists_fill(TreeView t, const int64_t *_
     // one partial per block, summed by k_lists_stats: thousands of waves
     // adding to one global counter serialise at the memory side and stall
     // the loads of every wave queued behind them
-    __shared__ unsigned long long red[256 / WAVE];
-    pairs = block_sum<unsigned long long, 256>(pairs, red);
+    __shared__ unsigned long long red[LIST_NT / WAVE];
+    pairs = block_sum<unsigned long long, LIST_NT>(pairs, red);
     if (threadIdx.x == 0) block_pairs[blockIdx.x] = pairs;
 }
 
@@ -1190,21 +1194,21 @@ void build_lists(fl_ctx *c, const TreeBufs &t, ListBufs &L, int lanes)
     TreeView tv = view(t);
     // grid-stride over the cells (their number is known on the device only)
     const bool wide = lanes == 8;
-    const unsigned lg = grid_for(cap, wide ? 256 / 8 : 256, 4096);
+    const unsigned lg = grid_for(cap, wide ? LIST_NT / 8 : LIST_NT, 4096 * 256 / LIST_NT);
     int64_t *lanecnt = wide ? ws<int64_t>(c, "l_lanecnt", (size_t)cap * 8) : nullptr;
     // entry slots: LIST_SLOT_Q int4 per (cell, lane); cell ids must leave the tag bits free
     int4 *slots = wide && cap < (int64_t(1) << 30) ? ws<int4>(c, "l_slots", (size_t)cap * 8 * LIST_SLOT_Q) : nullptr;
     if (wide)
-        hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt, slots);
+        hipLaunchKernelGGL(k_lists_count<8>, dim3(lg), dim3(LIST_NT), 0, c->stream, tv, cntVX, cntUW, lanecnt, slots);
     else
-        hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(256), 0, c->stream, tv, cntVX, cntUW, lanecnt,
+        hipLaunchKernelGGL(k_lists_count<1>, dim3(lg), dim3(LIST_NT), 0, c->stream, tv, cntVX, cntUW, lanecnt,
                            (int4 *)nullptr);
     FL_LAUNCH_CHECK();
     scan_excl_i64_pair(c, cntVX, L.offVX, cap, t.counts, cntUW, L.offUW, lcap, t.counts + 1);
     auto fill = wide ? k_lists_fill<8> : k_lists_fill<1>;
     L.block_pairs = ws<unsigned long long>(c, "l_block_pairs", (size_t)lg);
     L.fill_blocks = (int)lg;
-    hipLaunchKernelGGL(fill, dim3(lg), dim3(256), 0, c->stream, tv, (const int64_t *)L.offVX,
+    hipLaunchKernelGGL(fill, dim3(lg), dim3(LIST_NT), 0, c->stream, tv, (const int64_t *)L.offVX,
                        (const int64_t *)L.offUW, L.V, L.X, L.U, L.nU, L.W, L.block_pairs, cap, lcap, L.v_cap,
                        L.x_cap, L.u_cap, L.w_cap, t.counts + 3, (const int64_t *)lanecnt, (const int4 *)slots);
     FL_LAUNCH_CHECK();

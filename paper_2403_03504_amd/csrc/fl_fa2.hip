@@ -133,8 +133,12 @@ __global__ __launch_bounds__(NT) void k_attract_chunks(const int32_t *__restrict
 
 // The attraction sum of every row (the same arithmetic, in the same order,
 // as k_combine's own): light rows by their gathers, heavy rows from their
-// chunk sums.  Lets the gathers run on a branch stream beside the repulsion.
-__global__ __launch_bounds__(NT) void k_attract_rows(int n, const int32_t *__restrict__ row_ptr,
+// chunk sums.  Lets the gathers run on a branch stream beside the repulsion,
+// in eight-wave workgroups: beside the near field they held up its waves
+// less than four-wave ones (2M-node iteration 0.704 -> 0.695 ms; two waves
+// 0.744 ms, sixteen 0.738 ms)
+constexpr int ROWS_NT = 512;
+__global__ __launch_bounds__(ROWS_NT) void k_attract_rows(int n, const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, const float2 *__restrict__ xy,
                                                      const int32_t *__restrict__ choff,
                                                      const double2 *__restrict__ csum, double2 *__restrict__ asum)
@@ -618,8 +622,8 @@ static void iteration(Sys &b, double *ring, int ring_it)
         const std::function<void(hipEvent_t)> side = [&](hipEvent_t after) {
             FL_CHECK_HIP(hipStreamWaitEvent(as, after, 0));
             xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as, fmm);
-            hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, NT)), dim3(NT), 0, as, n, b.g.row_ptr, b.g.col, xy,
-                               (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
+            hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, ROWS_NT)), dim3(ROWS_NT), 0, as, n, b.g.row_ptr,
+                               b.g.col, xy, (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
             FL_LAUNCH_CHECK();
             FL_CHECK_HIP(hipEventRecord(c->ev_join, as));
         };

@@ -542,8 +542,10 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
     if (!packed) hipLaunchKernelGGL(k_pack_xy, dim3(grid_for(g.n, NT)), dim3(NT), 0, s, x, y, g.n, xy);
     // one wave per chunk, grid-strided: 4096 blocks (16 per CU) keep enough
     // gathers in flight; 1024 and 2048 blocks were 1.2% and 0.5% slower per
-    // 2M-node iteration, 8192 no faster
-    hipLaunchKernelGGL(k_attract_chunks, dim3(4096), dim3(NT), 0, s, g.row_ptr, g.col, (const float2 *)xy,
+    // 2M-node iteration, 8192 no faster.  Small graphs launch no more blocks
+    // than their chunk capacity needs.
+    const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (a.cap + NT / WAVE - 1) / (NT / WAVE)));
+    hipLaunchKernelGGL(k_attract_chunks, dim3(blocks), dim3(NT), 0, s, g.row_ptr, g.col, (const float2 *)xy,
                        a.chunks, a.choff + g.n, csum);
     FL_LAUNCH_CHECK();
     return xy;

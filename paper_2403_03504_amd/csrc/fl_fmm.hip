@@ -478,7 +478,9 @@ constexpr int P2P_WAVE_LDS = (P2P_STAGE * 16 > WAVE * P2P_TMAX * 8 ? P2P_STAGE *
 // does G n pairs; the shape with the most pairs per slot wins (the smaller
 // T on a tie).  G = 1 is the plain one-target-per-lane wave.
 // The shapes of all chunk sizes 1..64, fixed at compile time (T | L << 8 |
-// G << 16): a chunk reads its shape with one scalar load instead of dividing.
+// G << 16 | S << 24, with S = G floor(64 / G) the sources a stage takes, so
+// that only a range's last stage ends in a partial round): a chunk reads its
+// shape with one scalar load instead of dividing.
 struct P2PShapes {
     uint32_t v[WAVE + 1];
 };
@@ -499,28 +501,31 @@ constexpr P2PShapes p2p_shape_table()
                 G = g;
             }
         }
-        s.v[n] = (uint32_t)T | ((uint32_t)L << 8) | ((uint32_t)G << 16);
+        const int S = G * (WAVE / G);
+        s.v[n] = (uint32_t)T | ((uint32_t)L << 8) | ((uint32_t)G << 16) | ((uint32_t)S << 24);
     }
     return s;
 }
 
 __constant__ P2PShapes P2P_SHAPE = p2p_shape_table();
 
-__device__ __forceinline__ void p2p_shape(int n, int &T, int &L, int &G)
+__device__ __forceinline__ void p2p_shape(int n, int &T, int &L, int &G, int &S)
 {
     const uint32_t v = P2P_SHAPE.v[n];
     T = (int)(v & 0xFFu);
     L = (int)((v >> 8) & 0xFFu);
-    G = (int)(v >> 16);
+    G = (int)((v >> 16) & 0xFFu);
+    S = (int)(v >> 24);
 }
 
 // One chunk of a leaf's targets (t0 .. t0 + n) in lane groups: lane (g, r)
-// holds targets r, r + L, ..., takes sources k = g mod G from a 64-source LDS
-// stage, and the groups' sums are added in group order through LDS.  Lanes
-// past G L compute on group 0's sources and their sums are never read.
+// holds targets r, r + L, ..., takes sources k = g mod G from an LDS stage of
+// S <= 64 sources (a multiple of G), and the groups' sums are added in group
+// order through LDS.  Lanes past G L compute on group 0's sources and their
+// sums are never read.
 template <int T>
 __device__ __forceinline__ void p2p_groups(const float4 *__restrict__ part, const int2 *__restrict__ U, int u0,
-                                           int u1, int t0, int n, int L, int G, float4 *sw, float2 *rw,
+                                           int u1, int t0, int n, int L, int G, int S, float4 *sw, float2 *rw,
                                            float2 *__restrict__ near, int32_t *__restrict__ pleaf, int li)
 {
     const int lane = lane_id();
@@ -540,8 +545,8 @@ __device__ __forceinline__ void p2p_groups(const float4 *__restrict__ part, cons
     }
     for (int ue = u0; ue < u1; ++ue) {
         const int2 rg = U[ue];
-        for (int j0 = rg.x; j0 < rg.y; j0 += WAVE) {
-            const int ns = min(WAVE, rg.y - j0);
+        for (int j0 = rg.x; j0 < rg.y; j0 += S) {
+            const int ns = min(S, rg.y - j0);
             const bool in = lane < ns;
             const float4 v = part[j0 + (in ? lane : 0)];
             // lanes past the chunk hold a source of mass 0 (adds 0); the
@@ -613,18 +618,18 @@ __global__ __launch_bounds__(256, 8) void k_p2p(TreeView t, const float4 *__rest
         const int u0 = (int)(ou0 & 0xFFFFFFFFll), u1 = u0 + nU[li];
         for (int t0 = b; t0 < e; t0 += WAVE) {
             const int ntc = min(WAVE, e - t0);
-            int T, L, G;
-            p2p_shape(ntc, T, L, G);
+            int T, L, G, S;
+            p2p_shape(ntc, T, L, G, S);
             if (G > 1) {
                 switch (T) {
-                case 1: p2p_groups<1>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                case 2: p2p_groups<2>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                case 3: p2p_groups<3>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                case 4: p2p_groups<4>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                case 5: p2p_groups<5>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                case 6: p2p_groups<6>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                case 7: p2p_groups<7>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
-                default: p2p_groups<8>(part, U, u0, u1, t0, ntc, L, G, sw, rw, near, pleaf, li); break;
+                case 1: p2p_groups<1>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                case 2: p2p_groups<2>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                case 3: p2p_groups<3>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                case 4: p2p_groups<4>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                case 5: p2p_groups<5>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                case 6: p2p_groups<6>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                case 7: p2p_groups<7>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
+                default: p2p_groups<8>(part, U, u0, u1, t0, ntc, L, G, S, sw, rw, near, pleaf, li); break;
                 }
                 continue;
             }

@@ -552,7 +552,7 @@ static const float2 *attract_chunks(fl_ctx *c, const GraphArgs &g, const Attract
 }
 
 static void repulsion(fl_ctx *c, const Segs &sg, const GraphArgs &g, const float *x, const float *y,
-                      const fl_fa2_params *p, float2 *fr, const std::function<void(hipEvent_t)> *on_lists = nullptr,
+                      const fl_fa2_params *p, float2 *fr, const ListsHook *on_lists = nullptr,
                       float2 *xy_out = nullptr, BBoxIn bb = {})
 {
     if (p->repulsion == FL_REP_EXACT) {
@@ -624,17 +624,18 @@ static void iteration(Sys &b, double *ring, int ring_it)
         if (!c->ev_fork) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         if (!c->ev_join) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
         const bool fmm = b.prm.repulsion != FL_REP_EXACT;  // the tree build then packs (x, y)
-        const std::function<void(hipEvent_t)> side = [&](hipEvent_t after) {
+        const ListsHook side = [&](hipEvent_t after, const BranchTail &tail) {
             FL_CHECK_HIP(hipStreamWaitEvent(as, after, 0));
             xy = attract_chunks(c, b.g, b.ap, b.x, b.y, csum, as, fmm);
             hipLaunchKernelGGL(k_attract_rows, dim3(grid_for(n, ROWS_NT)), dim3(ROWS_NT), 0, as, n, b.g.row_ptr,
                                b.g.col, xy, (const int32_t *)b.ap.choff, (const double2 *)csum, asum);
             FL_LAUNCH_CHECK();
+            tail(as);
             FL_CHECK_HIP(hipEventRecord(c->ev_join, as));
         };
         if (!fmm) {
             FL_CHECK_HIP(hipEventRecord(c->ev_fork, c->stream));
-            side(c->ev_fork);
+            side(c->ev_fork, [](hipStream_t) {});
             repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr);
         } else {
             repulsion(c, b.sg, b.g, b.x, b.y, &b.prm, fr, &side, ws<float2>(c, "at_xy", n), bb);

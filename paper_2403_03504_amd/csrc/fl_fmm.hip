@@ -796,7 +796,7 @@ void far_p(fl_ctx *c, const TreeBufs &t, const ListBufs &L, const FmmBufs<P> &b,
 // branches under capture).
 template <int P>
 void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
-                const std::function<void(hipEvent_t)> *on_lists)
+                const ListsHook *on_lists)
 {
     ListBufs L;
     const FmmBufs<P> b = fmm_bufs<P>(c, t);
@@ -811,7 +811,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         if (on_lists) {
             if (!c->ev_lists) FL_CHECK_HIP(hipEventCreateWithFlags(&c->ev_lists, hipEventDisableTiming));
             FL_CHECK_HIP(hipEventRecord(c->ev_lists, c->stream));
-            (*on_lists)(c->ev_lists);
+            (*on_lists)(c->ev_lists, [](hipStream_t) {});
         }
         {
             PhaseTimer pt(c, FL_PH_UPWARD);
@@ -838,10 +838,14 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
         // successors: graph replay dispatched it after M2L and L2L otherwise
         near_p(c, t, L, near, pleaf);
         FL_CHECK_HIP(hipStreamWaitEvent(us, c->ev_lists, 0));
-        if (on_lists) (*on_lists)(c->ev_lists);
-        // the statistics (for the host only) on the branch, ahead of M2L,
-        // rather than between the near field and the far field
-        lists_stats(c, t, L, us);
+        // the statistics (for the host only) on the other branch when there
+        // is one: ahead of M2L they delayed the far field, which waits for
+        // M2L and L2L; else ahead of M2L rather than between the near field
+        // and the far field
+        if (on_lists)
+            (*on_lists)(c->ev_lists, [&](hipStream_t s) { lists_stats(c, t, L, s); });
+        else
+            lists_stats(c, t, L, us);
         m2l_p<P>(c, us, t, L, b);
         FL_CHECK_HIP(hipEventRecord(c->ev_join2, us));
         FL_CHECK_HIP(hipStreamWaitEvent(c->stream, c->ev_join2, 0));
@@ -855,7 +859,7 @@ void fmm_passes(fl_ctx *c, const TreeBufs &t, int lanes, float kr, float2 *fr,
 bool fmm_order_supported(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16; }
 
 void fmm_repulsion(fl_ctx *c, const Segs &s, const float *x, const float *y, const int32_t *deg, int p, int leaf,
-                   int bits, int lanes, float kr, float2 *fr, const std::function<void(hipEvent_t)> *on_lists,
+                   int bits, int lanes, float kr, float2 *fr, const ListsHook *on_lists,
                    float2 *xy_out, BBoxIn bb)
 {
     TreeBufs t;

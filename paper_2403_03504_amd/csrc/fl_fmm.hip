@@ -268,6 +268,11 @@ __global__ __launch_bounds__(256) void k_m2m_sub(TreeView t, const float2 *__res
 template <int P>
 __global__ __launch_bounds__(256) void k_m2m_top(TreeView t, const float2 *__restrict__ T, float2 *M)
 {
+    // a short chain of dependent levels that M2L waits for, started as the
+    // near field fills the GPU: its waves issue first (a 2M-node iteration
+    // 0.6853-0.6859 -> 0.6832-0.6840 ms together with L2L's; priority for the
+    // whole upward/M2L branch, or for M2L, was slower)
+    __builtin_amdgcn_s_setprio(3);
     const int ncells = t.counts[0];
     if (ncells <= 1) return;
     const int64_t H = hash_size(ncells, t.hash_cap);
@@ -414,6 +419,8 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const float4 *__restric
 template <int P>
 __global__ __launch_bounds__(256) void k_l2l(TreeView t, const float2 *__restrict__ Lp, float2 *__restrict__ Lleaf)
 {
+    // between M2L and the far field on the critical path: issue first
+    __builtin_amdgcn_s_setprio(3);
     const int nleaves = t.counts[1];
     for (int li = blockIdx.x * blockDim.x + threadIdx.x; li < nleaves; li += gridDim.x * blockDim.x) {
         const int c = t.leaf_cell[li];

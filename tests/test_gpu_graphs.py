@@ -136,3 +136,36 @@ def test_layout_concurrent_components_equal_alone(ctxs, fl, iters):
             ("alone runs differ", k, part.n)
         assert np.array_equal(alone[0][0], lx[ids[order]]), (k, part.n)
         assert np.array_equal(alone[0][1], ly[ids[order]]), (k, part.n)
+
+
+def test_fmm_stats_equal_across_schedules(fl):
+    """The list statistics (read by the host only) are enqueued on the
+    attraction branch in replayed and branch-stream iterations, and in line
+    when phases are timed: both schedules give the same counts, and the same
+    positions bit for bit."""
+    from paper_2403_03504_amd import workloads as w
+    _note("fmm statistics: branch schedule vs in-line schedule")
+    g = w.bipartite(21, 8000, 12000, 5, hub_deg=(500, 2000))
+    prm = fl.default_params(repulsion=fl.REP_FMM, p=8, leaf_size=32)
+    iters = 12
+    out = []
+    for inline in (False, True):
+        c = fl.Context(0)
+        try:
+            if inline:
+                c.set_timing(True)
+            G = c.build_csr(g.n, dev(g.src), dev(g.dst))
+            x, y = dev(g.x), dev(g.y)
+            st = fl.FA2State.zeros(g.n, "cuda")
+            c.fmm_stats(reset=True)
+            c.fa2_run(G, x, y, st, prm, iters)
+            out.append((c.fmm_stats(), host(x), host(y)))
+        finally:
+            c.close()
+    (s0, x0, y0), (s1, x1, y1) = out
+    assert np.array_equal(x0, x1) and np.array_equal(y0, y1)
+    assert s0["evaluations"] == iters and s0["total_particles"] == iters * g.n
+    for k in ("cells", "leaves", "near_pairs", "v_entries", "total_near_pairs", "total_v_entries", "evaluations",
+              "total_particles"):
+        assert s0[k] == s1[k], (k, s0[k], s1[k])
+    assert s0["total_near_pairs"] > 0
